@@ -1,0 +1,261 @@
+"""CPU oracle: plain FP64 implementation of the immersed-boundary step.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, ``__graft_entry__.smoke()`` and the
+benchmark's ``cpu_baseline`` leg may import this package.  The product path
+(the HIP library and its binding) never imports, links or calls it.
+
+The arithmetic lives in ``oracle.c`` (built by :func:`build`); this module only
+marshals numpy arrays through ctypes.  ``exact.py`` holds exact-rational
+brute-force checks used as pins.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+BC = {"farfield": 0, "extrap": 1, "periodic": 2}
+FLUID, FORCING, G1, G2, G3, SOLID = range(6)
+IREC, DREC = 24, 32
+
+
+def build(openmp=True):
+    """Compile oracle.c (gcc, -O2, no FP contraction, no fast-math)."""
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-D_GNU_SOURCE",
+           "-fPIC", "-shared", "-Wall", "-Wno-unused-function"]
+    if openmp:
+        cmd.append("-fopenmp")
+    cmd += ["-o", _SO + ".tmp", os.path.join(_HERE, "oracle.c"), "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(_SO + ".tmp", _SO)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = ctypes.CDLL(_SO)
+        P = ctypes.c_void_p
+        d, i = ctypes.c_double, ctypes.c_int
+        L.orc_create.restype = P
+        L.orc_create.argtypes = [i, i, i, i, P, P, P, P, i, i, P, P, d, d, d, d, i, i, d, d, i, i, P]
+        L.orc_destroy.argtypes = [P]
+        L.orc_set_pose.argtypes = [P, d]
+        L.orc_classify.argtypes = [P]
+        L.orc_geometry.argtypes = [P]
+        L.orc_bc.argtypes = [P, P]
+        L.orc_fill.argtypes = [P, P, d]
+        L.orc_residual.argtypes = [P, P, P]
+        L.orc_rk3_step.argtypes = [P, P, P, P, d]
+        L.orc_dual_step.argtypes = [P, P, P, P, P, i, d]
+        L.orc_dual_begin.argtypes = [P, P, P, P, i, d]
+        L.orc_dual_iterate.argtypes = [P, P, P, P, P, i, d, i]
+        L.orc_prim_to_state.argtypes = [P, P, P]
+        L.orc_state_to_prim.argtypes = [P, P, P]
+        L.orc_get_class.argtypes = [P, P]
+        L.orc_get_lists.argtypes = [P, P, P, P]
+        L.orc_get_lists.restype = i
+        L.orc_get_records.argtypes = [P, i, P, P]
+        L.orc_get_stats.argtypes = [P, P]
+        L.orc_get_param.argtypes = [P, i]
+        L.orc_get_param.restype = d
+        L.orc_weno5.argtypes = [d] * 5
+        L.orc_weno5.restype = d
+        L.orc_ldfss.argtypes = [i, P, P, P, d, i, d, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def weno5(a, b, c, d, e):
+    return lib().orc_weno5(a, b, c, d, e)
+
+
+def ldfss(ndim, wl, wr, nrm, gamma=1.4, precond=False, uc2=1.0):
+    wl = np.ascontiguousarray(wl, dtype=np.float64)
+    wr = np.ascontiguousarray(wr, dtype=np.float64)
+    n = np.ascontiguousarray(nrm, dtype=np.float64)
+    f = np.zeros(ndim + 2)
+    lib().orc_ldfss(ndim, _p(wl), _p(wr), _p(n), gamma, int(bool(precond)), uc2, _p(f))
+    return f
+
+
+class Oracle:
+    """One solve on the CPU.  State arrays use the halo layout
+    [nv][nk + 2 hz][nj + 6][ni + 6]; see ``new_state``."""
+
+    def __init__(self, case):
+        self.case = case
+        c = case
+        self.ndim, self.ni, self.nj, self.nk = c.ndim, c.ni, c.nj, c.nk
+        self.nv = c.ndim + 2
+        self.hz = 3 if c.ndim == 3 else 0
+        self._keep = []
+
+        def arr(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            self._keep.append(a)
+            return a
+
+        xf, yf = arr(c.xf, np.float64), arr(c.yf, np.float64)
+        zf = arr(c.zf if c.ndim == 3 else [0.0, 1.0], np.float64)
+        bc = arr([BC[b] for b in c.bc], np.int32)
+        vert = arr(c.vert.reshape(-1) if len(c.vert) else np.zeros(1), np.float64)
+        facet = arr(c.facet.reshape(-1) if len(c.facet) else np.zeros(1, np.int32), np.int32)
+        mo = c.motion or {}
+        mpar = arr([mo.get("axis", 0), mo.get("amplitude", 0.0), mo.get("frequency", 0.0),
+                    mo.get("phase", 0.0)], np.float64)
+        self.h = lib().orc_create(
+            c.ndim, c.ni, c.nj, c.nk, _p(xf), _p(yf), _p(zf), _p(bc), len(c.vert), len(c.facet),
+            _p(vert), _p(facet), c.mach, c.reynolds, c.prandtl, c.gamma,
+            0 if c.scheme == "rk3" else 1, 0 if c.ib_family == "linear" else 1, c.dt,
+            c.cfl_tau, c.n_inner, 1 if mo else 0, _p(mpar))
+        self.t = 0.0
+        self.step_index = 0
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_destroy(self.h)
+            self.h = None
+
+    @property
+    def state_shape(self):
+        return (self.nv, self.nk + 2 * self.hz, self.nj + 6, self.ni + 6)
+
+    def new_state(self):
+        return np.zeros(self.state_shape)
+
+    def interior(self, q):
+        h = self.hz
+        return q[:, h:h + self.nk, 3:3 + self.nj, 3:3 + self.ni]
+
+    def param(self, which):
+        return lib().orc_get_param(self.h, {"pinf": 0, "R": 1, "cp": 2, "mu": 3, "k": 4,
+                                            "uc2": 5, "disp": 6}[which])
+
+    def prim_to_state(self, prim):
+        prim = np.ascontiguousarray(prim, dtype=np.float64)
+        q = self.new_state()
+        lib().orc_prim_to_state(self.h, _p(prim), _p(q))
+        return q
+
+    def dual_begin(self, q):
+        """Start a physical dual-time step (history rotation); returns the
+        'first step' flag to pass to dual_iterate."""
+        c = self.case
+        if not hasattr(self, "_qn"):
+            n = self.nv * self.ni * self.nj * self.nk
+            self._qn = np.zeros(n)
+            self._qnm1 = np.zeros(n)
+        first = 1 if self.step_index == 0 else 0
+        self.t += c.dt
+        lib().orc_dual_begin(self.h, _p(q), _p(self._qn), _p(self._qnm1), first, self.t)
+        self.step_index += 1
+        return first
+
+    def dual_iterate(self, q, first, n_iter):
+        wt = q.copy()
+        lib().orc_dual_iterate(self.h, _p(q), _p(wt), _p(self._qn), _p(self._qnm1), first,
+                               self.t, n_iter)
+        return q
+
+    def state_to_prim(self, q):
+        prim = np.zeros((self.nv, self.nk, self.nj, self.ni))
+        lib().orc_state_to_prim(self.h, _p(q), _p(prim))
+        return prim
+
+    def set_pose(self, t):
+        lib().orc_set_pose(self.h, t)
+
+    def classify(self, t=0.0):
+        self.set_pose(t)
+        lib().orc_classify(self.h)
+        lib().orc_geometry(self.h)
+
+    def classes(self):
+        out = np.zeros((self.nk, self.nj, self.ni), dtype=np.uint8)
+        lib().orc_get_class(self.h, _p(out))
+        return out
+
+    def lists(self):
+        counts = np.zeros(5, dtype=np.int32)
+        n = (self.ni * self.nj * self.nk) + 1
+        lf = np.zeros(n, dtype=np.int32)
+        lg = np.zeros(n, dtype=np.int32)
+        lib().orc_get_lists(self.h, _p(lf), _p(lg), _p(counts))
+        return lf[:counts[0]].copy(), lg[:counts[4]].copy(), counts
+
+    def records(self):
+        _, _, counts = self.lists()
+        nrec = int(counts[0] + counts[4])
+        ir = np.zeros((max(nrec, 1), IREC), dtype=np.int32)
+        dr = np.zeros((max(nrec, 1), DREC))
+        lib().orc_get_records(self.h, 0, _p(ir), _p(dr))
+        return ir[:nrec], dr[:nrec]
+
+    def stats(self):
+        s = np.zeros(6, dtype=np.int64)
+        lib().orc_get_stats(self.h, _p(s))
+        return dict(zip(["fallback_pprime", "fallback_probe", "fallback_none",
+                         "stencil_violation", "fresh_cleared", "fresh_violation"], s.tolist()))
+
+    def bc(self, q):
+        lib().orc_bc(self.h, _p(q))
+
+    def fill(self, q, t=0.0):
+        lib().orc_fill(self.h, _p(q), t)
+
+    def residual(self, q):
+        r = np.zeros((self.nv, self.nk, self.nj, self.ni))
+        lib().orc_residual(self.h, _p(q), _p(r))
+        return r
+
+    def run(self, q, nsteps):
+        """Advance nsteps RK3 steps or physical dual-time steps in place."""
+        c = self.case
+        if c.scheme == "rk3":
+            q1, q2 = q.copy(), q.copy()
+            for _ in range(nsteps):
+                lib().orc_rk3_step(self.h, _p(q), _p(q1), _p(q2), self.t)
+                self.t += c.dt
+                self.step_index += 1
+        else:
+            if not hasattr(self, "_qn"):
+                n = self.nv * self.ni * self.nj * self.nk
+                self._qn = np.zeros(n)
+                self._qnm1 = np.zeros(n)
+            wt = q.copy()
+            for _ in range(nsteps):
+                self.t += c.dt
+                lib().orc_dual_step(self.h, _p(q), _p(wt), _p(self._qn), _p(self._qnm1),
+                                    1 if self.step_index == 0 else 0, self.t)
+                self.step_index += 1
+        return q
+
+    def dual_begin(self, q):
+        """Start a physical dual-time step (history rotation); returns the
+        'first step' flag to pass to dual_iterate."""
+        c = self.case
+        if not hasattr(self, "_qn"):
+            n = self.nv * self.ni * self.nj * self.nk
+            self._qn = np.zeros(n)
+            self._qnm1 = np.zeros(n)
+        first = 1 if self.step_index == 0 else 0
+        self.t += c.dt
+        lib().orc_dual_begin(self.h, _p(q), _p(self._qn), _p(self._qnm1), first, self.t)
+        self.step_index += 1
+        return first
+
+    def dual_iterate(self, q, first, n_iter):
+        wt = q.copy()
+        lib().orc_dual_iterate(self.h, _p(q), _p(wt), _p(self._qn), _p(self._qnm1), first,
+                               self.t, n_iter)
+        return q

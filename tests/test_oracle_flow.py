@@ -1,0 +1,480 @@
+"""Pins for the oracle's flow half (WENO5, LDFSS with preconditioning,
+viscous flux, SSP-RK3, dual time, immersed-boundary fill) against closed
+forms, invariants and the paper's printed Rankine-Hugoniot values."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+from workloads.cases import Case
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------- WENO5
+def test_weno5_linear_data_reduces_to_linear_scheme():
+    """Linear data make the three smoothness indicators equal, so the
+    weights are the linear ones (0.1, 0.6, 0.3) and the result is the
+    5th-order linear formula; for linear data that is the exact face value."""
+    for a0, s in [(0.0, 1.0), (3.25, -0.5), (-7.0, 2.0)]:
+        v = [a0 + s * k for k in range(5)]
+        lin = (2 * v[0] - 13 * v[1] + 47 * v[2] + 27 * v[3] - 3 * v[4]) / 60.0
+        got = oracle.weno5(*v)
+        assert abs(got - lin) < 1e-14 * max(1, abs(lin))
+        assert abs(got - (a0 + 2.5 * s)) < 1e-14 * max(1, abs(lin))
+    assert oracle.weno5(*[1.75] * 5) == pytest.approx(1.75, abs=1e-15)
+
+
+def test_weno5_reconstruction_order_smooth():
+    """Face values reconstructed from exact cell averages of a smooth
+    function converge at fifth order (section 2: fifth-order WENO)."""
+    errs = []
+    ns = [40, 80, 160, 320]
+    for n in ns:
+        h = 1.0 / n
+        xf = np.arange(-3, n + 4) * h
+        f = lambda x: np.exp(np.sin(2 * np.pi * x) * 0.3) - x * x
+        F = lambda x: None
+        # cell averages by high-order Gauss quadrature
+        g, gw = np.polynomial.legendre.leggauss(8)
+        avg = np.array([np.sum(gw * f(0.5 * (xf[i] + xf[i + 1]) + 0.5 * h * g)) / 2 for i in range(len(xf) - 1)])
+        e = []
+        for i in range(3, n + 3):
+            left = oracle.weno5(*avg[i - 2:i + 3])
+            e.append(abs(left - f(xf[i + 1])))
+        errs.append(np.mean(e))
+        del F
+    slopes = [math.log(errs[k] / errs[k + 1], 2) for k in range(len(errs) - 1)]
+    assert slopes[-1] > 4.7, (errs, slopes)
+
+
+def test_weno5_no_overshoot_at_step():
+    for jump in [1.0, 100.0, -3.0]:
+        v = [0.0, 0.0, 0.0, jump, jump]
+        r = oracle.weno5(*v)
+        lo, hi = min(0.0, jump), max(0.0, jump)
+        assert lo - 1e-3 * abs(jump) <= r <= hi + 1e-3 * abs(jump)
+        # near-upwind: the left state sits close to the left plateau
+        assert abs(r) < 0.05 * abs(jump)
+
+
+# ----------------------------------------------------------------- LDFSS
+def _phys_flux(ndim, W, n, gamma=1.4):
+    rho, u, p = W[0], np.asarray(W[1:1 + ndim]), W[ndim + 1]
+    U = float(np.dot(u, n))
+    H = gamma / (gamma - 1) * p / rho + 0.5 * float(np.dot(u, u))
+    return np.array([rho * U] + list(rho * u * U + p * np.asarray(n)) + [rho * H * U])
+
+
+def _rand_state(rng, ndim, mach):
+    rho = rng.uniform(0.5, 2.0)
+    p = rng.uniform(0.5, 2.0)
+    a = math.sqrt(1.4 * p / rho)
+    u = rng.normal(size=ndim)
+    u *= mach * a / np.linalg.norm(u)
+    return np.array([rho] + list(u) + [p])
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+@pytest.mark.parametrize("mach", [0.05, 0.5, 0.95, 1.5, 3.0])
+@pytest.mark.parametrize("precond", [False, True])
+def test_ldfss_consistency(ndim, mach, precond):
+    """F(W, W) equals the physical Euler flux, with and without the
+    preconditioned sound speed."""
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        W = _rand_state(rng, ndim, mach)
+        n = rng.normal(size=ndim)
+        n /= np.linalg.norm(n)
+        F = oracle.ldfss(ndim, W, W, n, precond=precond, uc2=1e-4)
+        Fe = _phys_flux(ndim, W, n)
+        scale = np.abs(Fe).max() + W[-1]
+        assert np.abs(F - Fe).max() < 1e-14 * scale
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_ldfss_supersonic_is_pure_upwind(ndim):
+    rng = np.random.default_rng(2)
+    n = np.zeros(ndim)
+    n[0] = 1.0
+    for _ in range(20):
+        WL, WR = _rand_state(rng, ndim, 0.0), _rand_state(rng, ndim, 0.0)
+        aL = math.sqrt(1.4 * WL[-1] / WL[0])
+        aR = math.sqrt(1.4 * WR[-1] / WR[0])
+        WL[1] = 3.0 * max(aL, aR)
+        WR[1] = 3.0 * max(aL, aR)
+        F = oracle.ldfss(ndim, WL, WR, n)
+        assert np.allclose(F, _phys_flux(ndim, WL, n), rtol=1e-14, atol=0)
+        WL[1], WR[1] = -WL[1], -WR[1]
+        F = oracle.ldfss(ndim, WL, WR, n)
+        assert np.allclose(F, _phys_flux(ndim, WR, n), rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_ldfss_contact_discontinuity(ndim):
+    """Low diffusion: a contact (equal u and p, different rho) is carried
+    with the exact upwind mass flux; a stationary one gives zero mass flux."""
+    n = np.zeros(ndim)
+    n[0] = 1.0
+    for U in [0.0, 0.3, -0.4]:
+        WL = np.array([1.0] + [U] + [0.2] * (ndim - 1) + [1.0])
+        WR = np.array([0.125] + [U] + [0.2] * (ndim - 1) + [1.0])
+        F = oracle.ldfss(ndim, WL, WR, n)
+        up = WL if U >= 0 else WR
+        assert abs(F[0] - up[0] * U) <= 1e-15
+        assert abs(F[1] - (up[0] * U * U + 1.0)) <= 1e-14
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_ldfss_eps_one_is_plain_bitwise(ndim):
+    """With the cut-off above the sound speed the preconditioning parameter
+    is 1 and the flux is bit-for-bit plain LDFSS(0)."""
+    rng = np.random.default_rng(3)
+    for _ in range(30):
+        WL, WR = _rand_state(rng, ndim, 0.3), _rand_state(rng, ndim, 0.6)
+        n = rng.normal(size=ndim)
+        n /= np.linalg.norm(n)
+        a = oracle.ldfss(ndim, WL, WR, n, precond=False)
+        b = oracle.ldfss(ndim, WL, WR, n, precond=True, uc2=1e6)
+        assert np.array_equal(a, b)
+
+
+def test_ldfss_preconditioned_dissipation_scales_with_flow_speed():
+    """At low Mach the preconditioned flux's dissipation follows the flow
+    speed: for a velocity jump dU the pressure-flux deviation from the mean
+    is O(rho U dU) with preconditioning and O(rho a dU) without."""
+    M = 0.01
+    p = 1.0 / (1.4 * M * M)
+    dU = 0.01
+    WL = np.array([1.0, 1.0 + dU, 0.0, p])
+    WR = np.array([1.0, 1.0 - dU, 0.0, p])
+    n = np.array([1.0, 0.0])
+    Fp = oracle.ldfss(2, WL, WR, n, precond=True, uc2=1.0)
+    Fn = oracle.ldfss(2, WL, WR, n, precond=False)
+    dev_p = abs(Fp[1] - (1.0 + p))
+    dev_n = abs(Fn[1] - (1.0 + p))
+    assert dev_n > 10 * dev_p
+    assert dev_p < 10 * dU          # O(rho U dU) with U = 1
+    assert dev_n > 0.1 * dU / M     # O(rho a dU) with a = 1/M
+
+
+# ------------------------------------------------------ residual invariants
+def _box(ndim, n, scheme="rk3", stretched=False, mach=0.5, re=100.0, bc="periodic", nz=8):
+    f = w.tanh_center_faces(n, 0.0, 1.0, 1.05) if stretched else w.uniform_faces(n, 0.0, 1.0)
+    zf = w.uniform_faces(nz, 0.0, 1.0) if ndim == 3 else np.array([-0.5, 0.5])
+    axes = [f, f] + ([zf] if ndim == 3 else [])
+    return Case(f"box{ndim}", ndim, f, f.copy(), zf, (bc,) * 6, np.zeros((0, ndim)),
+                np.zeros((0, ndim), np.int32), mach, re, scheme=scheme,
+                dt=w.cases.rk3_dt(mach, re, axes) if scheme == "rk3" else w.cases.dual_dt(axes),
+                n_inner=4)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+@pytest.mark.parametrize("scheme", ["rk3", "dual"])
+@pytest.mark.parametrize("stretched", [False, True])
+@pytest.mark.parametrize("bc", ["periodic", "farfield"])
+def test_freestream_preservation(ndim, scheme, stretched, bc):
+    """A uniform free stream is an exact discrete steady state: R == 0
+    bitwise and the state is unchanged after steps."""
+    c = _box(ndim, 16, scheme, stretched, bc=bc, nz=6)
+    o = oracle.Oracle(c)
+    o.classify()
+    prim = w.freestream_prim(ndim, c.ni, c.nj, c.nk, c.p_inf)
+    q = o.prim_to_state(prim)
+    o.bc(q)
+    r = o.residual(q)
+    assert np.all(r == 0.0)
+    q0 = o.interior(q).copy()
+    o.run(q, 2)
+    assert np.array_equal(o.interior(q), q0)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+@pytest.mark.parametrize("re", [50.0, 1e15])
+def test_conservation_periodic_box(ndim, re):
+    """Conservative finite volumes (section 2): on a periodic box the totals
+    of mass, momentum and energy change only by rounding."""
+    n = 32 if ndim == 2 else 12
+    c = _box(ndim, n, re=re, nz=8)
+    o = oracle.Oracle(c)
+    o.classify()
+    p_inf = c.p_inf
+    prim = w.random_periodic_prim(ndim, c.xf, c.yf, c.zf, p_inf, seed=0)
+    q = o.prim_to_state(prim)
+    dz = np.diff(c.zf) if ndim == 3 else np.array([1.0])
+    vol = dz[:, None, None] * np.diff(c.yf)[None, :, None] * np.diff(c.xf)[None, None, :]
+
+    def totals(q):
+        I = o.interior(q)
+        return [math.fsum((I[v] * vol).ravel()) for v in range(c.ndim + 2)]
+
+    t0 = totals(q)
+    steps = 5
+    o.run(q, steps)
+    t1 = totals(q)
+    I = o.interior(q)
+    for v in range(c.ndim + 2):
+        scale = math.fsum(np.abs(I[v] * vol).ravel())
+        assert abs(t1[v] - t0[v]) <= 10 * steps * np.finfo(float).eps * scale * 3, (v, t0[v], t1[v])
+    # the field actually evolved
+    assert not np.allclose(o.interior(q)[0], prim[0])
+
+
+def test_entropy_wave_semi_discrete_order():
+    """WENO5 order on smooth advection: rho = 1 + 0.2 sin(2 pi x), u and p
+    constant, periodic, exact cell averages; the mass residual converges to
+    the exact cell-averaged -d(rho u)/dx at about fifth order."""
+    errs, ns = [], [32, 64, 128, 256]
+    for n in ns:
+        c = _box(2, n, re=1e15)
+        c.yf = w.uniform_faces(4, 0.0, 4.0 / n)
+        o = oracle.Oracle(c)
+        o.classify()
+        prim = w.entropy_wave_prim(2, c.xf, 4, 1, c.p_inf, amp=0.2, u=1.0)
+        q = o.prim_to_state(prim)
+        o.bc(q)
+        r = o.residual(q)
+        xf = c.xf
+        exact = (0.2 * np.sin(2 * np.pi * xf[1:]) - 0.2 * np.sin(2 * np.pi * xf[:-1])) / np.diff(xf)
+        errs.append(np.mean(np.abs(r[0, 0, 1, :] - exact)))
+    slopes = [math.log(errs[k] / errs[k + 1], 2) for k in range(len(errs) - 1)]
+    assert slopes[-1] > 4.7, (errs, slopes)
+
+
+# ------------------------------------------------------------ RH shocks
+def rh_states(Ms, gamma, rho0, p0):
+    """Normal-shock relations for a shock of Mach Ms into gas at rest."""
+    a0 = math.sqrt(gamma * p0 / rho0)
+    p1 = p0 * (1 + 2 * gamma / (gamma + 1) * (Ms * Ms - 1))
+    rho1 = rho0 * (gamma + 1) * Ms * Ms / ((gamma - 1) * Ms * Ms + 2)
+    Us = Ms * a0
+    u1 = Us * (1 - rho0 / rho1)
+    return rho1, u1, p1, Us
+
+
+def test_rh_relations_reproduce_paper_values():
+    """The closed-form normal-shock relations used below reproduce the
+    post-shock pressure, velocity and shock speed printed for the
+    shock-driven cylinder (section 8.2.6), with T0 = 300 K and R = 287."""
+    g = json.load(open(os.path.join(GOLDEN, "rh_shock_driven_cylinder.json")))["printed"]
+    rho0 = g["p0_Pa"] / (287.0 * 300.0)
+    rho1, u1, p1, Us = rh_states(g["mach_shock"], g["gamma"], rho0, g["p0_Pa"])
+    assert abs(p1 - g["p1_Pa"]) / g["p1_Pa"] < 2e-6
+    assert abs(u1 - g["u1_m_s"]) / g["u1_m_s"] < 2e-6
+    assert abs(Us - g["shock_speed_m_s"]) / g["shock_speed_m_s"] < 2e-6
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+@pytest.mark.parametrize("Ms", [1.5, 3.0])
+def test_moving_normal_shock_with_tangential_velocity(axis, Ms):
+    """A Rankine-Hugoniot jump (with a tangential velocity, i.e. an oblique
+    shock seen in a frame sliding along it) propagates as a single shock at
+    the exact speed: totals change only by the boundary fluxes, the
+    tangential velocity stays constant, and the plateaus keep the RH states
+    away from the shock and the start-up point."""
+    n, nt, M = 200, 4, 0.5
+    gamma = 1.4
+    long_f = w.uniform_faces(n, 0.0, 1.0)
+    short_f = w.uniform_faces(nt, 0.0, nt / n)
+    xf, yf = (long_f, short_f) if axis == 0 else (short_f, long_f)
+    bc = ("extrap", "extrap", "periodic", "periodic") if axis == 0 else ("periodic", "periodic", "extrap", "extrap")
+    p0 = 1.0 / (gamma * M * M)
+    rho1, u1, p1, Us = rh_states(Ms, gamma, 1.0, p0)
+    a1 = math.sqrt(gamma * p1 / rho1)
+    h = 1.0 / n
+    dt = 0.4 * h / (u1 + a1 + 0.7)
+    c = Case("shock", 2, xf, yf, np.array([-0.5, 0.5]), bc + ("periodic", "periodic"),
+             np.zeros((0, 2)), np.zeros((0, 2), np.int32), M, 1e15, dt=dt)
+    o = oracle.Oracle(c)
+    o.classify()
+    x0 = 0.3
+    xc = 0.5 * (long_f[:-1] + long_f[1:])
+    behind = xc < x0
+    prim = np.zeros((4, 1, c.nj, c.ni))
+    vt = 0.7
+    shape = (c.nj, c.ni)
+    line = np.where(behind, 1, 0)
+    L = line[None, :] if axis == 0 else line[:, None]
+    L = np.broadcast_to(L, shape)
+    prim[0, 0] = np.where(L, rho1, 1.0)
+    prim[1 + axis, 0] = np.where(L, u1, 0.0)
+    prim[2 - axis, 0] = vt
+    prim[3, 0] = np.where(L, p1, p0)
+    q = o.prim_to_state(prim)
+    steps = int(0.35 / Us / dt)
+    area = np.diff(c.yf)[:, None] * np.diff(c.xf)[None, :]
+    tot0 = math.fsum((o.interior(q)[0, 0] * area).ravel())
+    o.run(q, steps)
+    t = steps * dt
+    P = o.state_to_prim(q)[:, 0]
+    tot1 = math.fsum((P[0] * area).ravel())
+    # mass: inflow rho1 u1 through the upstream boundary, none downstream
+    width = short_f[-1] - short_f[0]
+    assert abs(tot1 - (tot0 + rho1 * u1 * t * width)) < 1e-12 * tot1
+    # tangential velocity is carried unchanged
+    assert np.abs(P[2 - axis] - vt).max() < 1e-10
+    prof = P[:, 0, :] if axis == 0 else P[:, :, 0]
+    xs = x0 + Us * t
+    xp = x0 + u1 * t                  # start-up entropy error travels with the fluid
+    xa = x0 + (u1 - a1) * t           # start-up acoustic error runs upstream
+    away = (np.abs(xc - xs) > 6 * h) & (np.abs(xc - x0) > 8 * h)
+    quiet = away & (np.abs(xc - xp) > 12 * h) & (np.abs(xc - xa) > 12 * h)
+    exp_rho = np.where(xc < xs, rho1, 1.0)
+    exp_u = np.where(xc < xs, u1, 0.0)
+    exp_p = np.where(xc < xs, p1, p0)
+    # WENO5 + LDFSS leave small post-shock oscillations behind a moving
+    # shock; a wrong flux would split the jump into several waves and miss
+    # the plateaus by O(1)
+    assert np.abs(prof[0][quiet] - exp_rho[quiet]).max() < 1e-2 * rho1
+    assert np.abs(prof[1 + axis][quiet] - exp_u[quiet]).max() < 5e-3 * u1
+    assert np.abs(prof[3][quiet] - exp_p[quiet]).max() < 5e-3 * p1
+    # the jump sits at the exact shock position (half-way crossing of rho)
+    half = 0.5 * (rho1 + 1.0)
+    k = np.nonzero(prof[0] < half)[0][0]
+    xcross = xc[k - 1] + (half - prof[0][k - 1]) / (prof[0][k] - prof[0][k - 1]) * h
+    assert abs(xcross - xs) < 1.0 * h
+    assert quiet.sum() > n // 2
+
+
+# ------------------------------------------------------------- dual time
+def test_dual_time_pseudo_iterations_converge_mach_independently():
+    """The preconditioned point-implicit pseudo-time iteration of one
+    physical step converges (its fixed point is R* = 0), and preconditioning
+    makes the convergence history independent of the Mach number."""
+    hists = []
+    for M in [0.05, 0.005]:
+        c = _box(2, 24, scheme="dual", mach=M, re=200.0)
+        o = oracle.Oracle(c)
+        o.classify()
+        p_inf = c.p_inf
+        prim = w.random_periodic_prim(2, c.xf, c.yf, c.zf, p_inf, seed=3, amp=0.0, u_amp=0.2)
+        prim[3] = p_inf + 0.05 * (prim[1] - 1.0)
+        q = o.prim_to_state(prim)
+        first = o.dual_begin(q)
+        hist = []
+        for it in range(200):
+            before = o.interior(q)[1:3].copy()
+            o.dual_iterate(q, first, 1)
+            hist.append(np.abs(o.interior(q)[1:3] - before).max())
+        hist = np.array(hist)
+        assert np.all(np.isfinite(hist))
+        assert hist[-1] < 2e-2 * hist[0], (M, hist[:3], hist[-3:])
+        assert np.all(hist[100:] < hist[99])
+        hists.append(hist)
+    assert np.allclose(hists[0][::20], hists[1][::20], rtol=0.2)
+
+
+# ------------------------------------------------------------- IB fill
+def _wall_case(family, angle_deg=20.0, n=40, motion=None):
+    f = w.uniform_faces(n, -2.0, 2.0)
+    th = math.radians(angle_deg)
+    t = np.array([math.cos(th), math.sin(th)])
+    nn = np.array([-math.sin(th), math.cos(th)])          # wall normal, into the fluid
+    # big rectangle whose top side passes through the origin along t
+    L, D = 30.0, 20.0
+    v = np.array([-L * t, -L * t - D * nn, L * t - D * nn, L * t])
+    # counter-clockwise with the interior below the top side
+    v = w.snap(v)
+    s = np.array([[0, 1], [1, 2], [2, 3], [3, 0]], dtype=np.int32)
+    c = Case("wall", 2, f, f.copy(), np.array([-0.5, 0.5]), ("farfield",) * 4 + ("periodic",) * 2,
+             v, s, 0.3, 100.0, dt=1e-3, ib_family=family, motion=motion or {})
+    return c, nn, v
+
+
+@pytest.mark.parametrize("family", ["linear", "quadratic"])
+def test_fill_reproduces_linear_wall_profile(family):
+    """A field linear in the wall distance s that satisfies the boundary
+    conditions (u = 0 at the wall, dp/dn = 0, dT/dn = 0) is reproduced
+    exactly at every node the family reconstructs with multilinear probes
+    (ghost image points; both probes of the quadratic family)."""
+    c, nn, v = _wall_case(family)
+    o = oracle.Oracle(c)
+    o.classify()
+    xc = 0.5 * (c.xf[:-1] + c.xf[1:])
+    X, Y = np.meshgrid(xc, xc)
+    a = v[0]
+    tvec = (v[3] - v[0]) / np.linalg.norm(v[3] - v[0])
+    nrm = np.array([-tvec[1], tvec[0]])
+    s = (X - a[0]) * nrm[0] + (Y - a[1]) * nrm[1]
+    p_inf = c.p_inf
+    prim = np.zeros((4, 1, c.nj, c.ni))
+    prim[0] = 1.0
+    prim[1, 0] = 0.8 * s
+    prim[2, 0] = -0.3 * s
+    prim[3] = p_inf
+    q = o.prim_to_state(prim)
+    o.bc(q)
+    o.fill(q)
+    P = o.state_to_prim(q)
+    ir, dr = o.records()
+    nF = o.lists()[2][0]
+    flat = o.classes().ravel()
+    checked = 0
+    for r in range(len(ir)):
+        forcing = r < nF
+        if forcing and family == "linear":
+            continue   # IDW probes do not reproduce linear fields
+        if ir[r, 6]:
+            continue   # probe pushed out of the domain (wall spans the box): counted fallback
+        if family == "linear":
+            used = [cid for cid, ww in zip(ir[r, 7:11], dr[r, 9:13]) if ww != 0.0]
+            if any(flat[cid] != oracle.FLUID for cid in used):
+                continue   # reads an IDW-filled forcing node, itself not exact
+        cell = ir[r, 0]
+        i, j = cell % c.ni, cell // c.ni
+        if min(i, j, c.ni - 1 - i, c.nj - 1 - j) < 6:
+            continue   # near the box edge the wall's probes leave the domain
+        assert abs(P[1, 0, j, i] - 0.8 * s[j, i]) < 1e-12
+        assert abs(P[2, 0, j, i] + 0.3 * s[j, i]) < 1e-12
+        assert abs(P[3, 0, j, i] - p_inf) < 1e-12 * p_inf
+        checked += 1
+    assert checked > 20
+    # pressure and temperature (constant) are exact for the IDW nodes too
+    for r in range(nF):
+        cell = ir[r, 0]
+        i, j = cell % c.ni, cell // c.ni
+        assert abs(P[3, 0, j, i] - p_inf) < 1e-12 * p_inf
+        assert abs(P[0, 0, j, i] - 1.0) < 1e-12
+
+
+def test_fill_moving_wall_dirichlet_velocity():
+    """With a moving body the Dirichlet velocity is the body velocity (eq.4):
+    a field u = U_body + G s is reproduced at ghost image points."""
+    motion = dict(axis=1, amplitude=0.05, frequency=0.5, phase=0.0)
+    c, nn, v = _wall_case("linear", motion=motion)
+    o = oracle.Oracle(c)
+    t = 0.5   # quarter period: displacement 0, acceleration 0
+    o.classify(t)
+    ub = -2 * math.pi * 0.5 * 0.05 * math.sin(2 * math.pi * 0.5 * t)
+    xc = 0.5 * (c.xf[:-1] + c.xf[1:])
+    X, Y = np.meshgrid(xc, xc)
+    a = v[0]
+    tvec = (v[3] - v[0]) / np.linalg.norm(v[3] - v[0])
+    nrm = np.array([-tvec[1], tvec[0]])
+    s = (X - a[0]) * nrm[0] + (Y - a[1]) * nrm[1]
+    prim = np.zeros((4, 1, c.nj, c.ni))
+    prim[0] = 1.0
+    prim[1, 0] = 0.5 * s
+    prim[2, 0] = ub + 0.25 * s
+    prim[3] = c.p_inf
+    q = o.prim_to_state(prim)
+    o.bc(q)
+    o.fill(q, t)
+    P = o.state_to_prim(q)
+    ir, dr = o.records()
+    nF = o.lists()[2][0]
+    flat = o.classes().ravel()
+    for r in range(nF, len(ir)):
+        cell = ir[r, 0]
+        i, j = cell % c.ni, cell // c.ni
+        if ir[r, 6] or min(i, j, c.ni - 1 - i, c.nj - 1 - j) < 6:
+            continue
+        used = [cid for cid, ww in zip(ir[r, 7:11], dr[r, 9:13]) if ww != 0.0]
+        if any(flat[cid] != oracle.FLUID for cid in used):
+            continue
+        assert abs(P[1, 0, j, i] - 0.5 * s[j, i]) < 1e-12
+        assert abs(P[2, 0, j, i] - (ub + 0.25 * s[j, i])) < 1e-12

@@ -1,0 +1,277 @@
+"""Pins for the oracle's immersed-boundary geometry (classification, tagging,
+closest features, local normals, probes) against exact-rational brute force
+and geometric invariants."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import exact
+import workloads as w
+from workloads.cases import Case
+
+
+def _tiny_case(vert, seg, n=32, lo=-1.5, hi=1.5, family="linear"):
+    f = w.uniform_faces(n, lo, hi)
+    return Case("tiny", 2, f, f.copy(), np.array([-0.5, 0.5]), ("farfield",) * 4 + ("periodic",) * 2,
+                vert, seg, 0.3, 40.0, dt=1e-3, ib_family=family)
+
+
+BODIES = {
+    "16-gon": lambda: w.circle_polygon(16, 1.7),
+    "wedge": lambda: w.wedge_polygon(15.0, 2.0, (-1.0, 0.0)),
+    "naca12": lambda: w.naca00_polygon(0.12, 64, -1.0, 2.2),
+    "naca18": lambda: w.naca00_polygon(0.18, 40, -1.1, 2.0),
+}
+
+
+@pytest.mark.parametrize("body", sorted(BODIES))
+@pytest.mark.parametrize("n", [17, 32])
+def test_classification_matches_exact_winding_number(body, n):
+    """Ray parity (section 3.2) equals the exact rational winding number at
+    every node of a tiny grid, and equals the -x ray parity."""
+    v, s = BODIES[body]()
+    c = _tiny_case(v, s, n)
+    o = oracle.Oracle(c)
+    o.classify()
+    inside = o.classes()[0] >= oracle.G1
+    poly = [(exact.fr(x), exact.fr(y)) for x, y in v]
+    xc = 0.5 * (c.xf[:-1] + c.xf[1:])
+    yc = 0.5 * (c.yf[:-1] + c.yf[1:])
+    checked = 0
+    for j in range(n):
+        for i in range(n):
+            p = (exact.fr(xc[i]), exact.fr(yc[j]))
+            if exact.on_boundary(poly, p):
+                continue
+            wn = exact.winding_number(poly, p)
+            assert (wn != 0) == bool(inside[j, i]), (i, j)
+            assert exact.parity_minus_x(poly, p) == int(inside[j, i]), (i, j)
+            checked += 1
+    assert checked > n * n * 0.9
+    assert inside.any() and not inside.all()
+
+
+def test_classification_half_open_rule_on_vertex_rows():
+    """Nodes on the same horizontal line as polygon vertices (the rays pass
+    exactly through vertices) are still classified exactly."""
+    f = w.uniform_faces(16, -2.0, 2.0)
+    yc = 0.5 * (f[:-1] + f[1:])
+    xc = yc.copy()
+    # diamond with vertices exactly on cell-centre rows / columns
+    v = np.array([[xc[8], yc[2]], [xc[13], yc[8]], [xc[8], yc[13]], [xc[3], yc[8]]])
+    s = np.array([[0, 1], [1, 2], [2, 3], [3, 0]], dtype=np.int32)
+    c = Case("diamond", 2, f, f.copy(), np.array([-0.5, 0.5]), ("farfield",) * 4 + ("periodic",) * 2,
+             v, s, 0.3, 40.0, dt=1e-3)
+    o = oracle.Oracle(c)
+    o.classify()
+    inside = o.classes()[0] >= oracle.G1
+    poly = [(exact.fr(x), exact.fr(y)) for x, y in v]
+    for j in range(16):
+        for i in range(16):
+            p = (exact.fr(xc[i]), exact.fr(yc[j]))
+            if exact.on_boundary(poly, p):
+                continue
+            assert (exact.winding_number(poly, p) != 0) == bool(inside[j, i])
+
+
+def _neighbours(cls, j, i):
+    n = cls.shape[0]
+    for dj, di in ((0, 1), (0, -1), (1, 0), (-1, 0)):
+        jj, ii = j + dj, i + di
+        if 0 <= jj < n and 0 <= ii < cls.shape[1]:
+            yield cls[jj, ii]
+
+
+@pytest.mark.parametrize("body", sorted(BODIES))
+def test_tagging_layers(body):
+    """FORCING = fluid with a solid face neighbour; G1..G3 are successive
+    face-neighbour layers into the solid; lists are in raster order."""
+    v, s = BODIES[body]()
+    c = _tiny_case(v, s, 40)
+    o = oracle.Oracle(c)
+    o.classify()
+    cls = o.classes()[0]
+    inside = cls >= oracle.G1
+    for j in range(cls.shape[0]):
+        for i in range(cls.shape[1]):
+            nb = list(_neighbours(cls, j, i))
+            t = cls[j, i]
+            if not inside[j, i]:
+                assert (t == oracle.FORCING) == any(x >= oracle.G1 for x in nb)
+            elif t == oracle.G1:
+                assert any(x == oracle.FORCING for x in nb)
+            elif t == oracle.G2:
+                assert any(x == oracle.G1 for x in nb) and not any(x == oracle.FORCING for x in nb)
+            elif t == oracle.G3:
+                assert any(x == oracle.G2 for x in nb) and not any(x in (oracle.FORCING, oracle.G1) for x in nb)
+            elif t == oracle.SOLID:
+                assert not any(x in (oracle.FORCING, oracle.G1, oracle.G2) for x in nb)
+    lf, lg, cnt = o.lists()
+    flat = cls.ravel()
+    assert np.array_equal(lf, np.nonzero(flat == oracle.FORCING)[0])
+    assert np.array_equal(lg, np.nonzero((flat >= oracle.G1) & (flat <= oracle.G3))[0])
+    assert cnt[4] == cnt[1] + cnt[2] + cnt[3]
+
+
+@pytest.mark.parametrize("body", sorted(BODIES))
+def test_closest_feature_exact(body):
+    """Closest point (section 4.1, eq.1) equals the exact rational minimum over
+    all segments; the feature type matches the exact clamped parameter."""
+    v, s = BODIES[body]()
+    c = _tiny_case(v, s, 40)
+    o = oracle.Oracle(c)
+    o.classify()
+    ir, dr = o.records()
+    xc = 0.5 * (c.xf[:-1] + c.xf[1:])
+    poly = [(exact.fr(x), exact.fr(y)) for x, y in v]
+    for r in range(len(ir)):
+        cell = ir[r, 0]
+        i, j = cell % c.ni, cell // c.ni
+        p = (exact.fr(xc[i]), exact.fr(xc[j]))
+        best = None
+        for k in range(len(s)):
+            d2, t = exact.closest_on_segment(p, poly[s[k, 0]], poly[s[k, 1]])
+            if best is None or d2 < best[0]:
+                best = (d2, t, k)
+        d_exact = float(best[0]) ** 0.5
+        assert abs(dr[r, 25] - d_exact) <= 1e-14 * max(1.0, d_exact)
+        kind = ir[r, 1]
+        exact_kind = 0 if 0 < best[1] < 1 else 1
+        # a tie between a face minimum and a vertex minimum cannot occur for
+        # distinct features, so the kinds must agree
+        assert kind == exact_kind, (r, kind, best)
+
+
+@pytest.mark.parametrize("body", sorted(BODIES))
+def test_pseudo_normal_sign_agrees_with_ray_parity(body):
+    """For closed polygons the sign of (X - C) . n_feature, with n the facet
+    normal or the angle-weighted pseudo-normal of the closest feature, gives
+    inside/outside (Baerentzen-Aanaes); it must agree with the ray parity for
+    every listed node (sections 3.2 vs 4.2)."""
+    v, s = BODIES[body]()
+    c = _tiny_case(v, s, 40)
+    o = oracle.Oracle(c)
+    o.classify()
+    ir, dr = o.records()
+    nF = o.lists()[2][0]
+    xc = 0.5 * (c.xf[:-1] + c.xf[1:])
+    # closest point per node from exact search, normal from the record
+    poly = [(exact.fr(x), exact.fr(y)) for x, y in v]
+    for r in range(len(ir)):
+        cell = ir[r, 0]
+        i, j = cell % c.ni, cell // c.ni
+        p = (exact.fr(xc[i]), exact.fr(xc[j]))
+        best = None
+        for k in range(len(s)):
+            d2, t = exact.closest_on_segment(p, poly[s[k, 0]], poly[s[k, 1]])
+            if best is None or d2 < best[0]:
+                a, b = poly[s[k, 0]], poly[s[k, 1]]
+                best = (d2, (a[0] + t * (b[0] - a[0]), a[1] + t * (b[1] - a[1])))
+        if best[0] == 0:
+            continue
+        dot = float(p[0] - best[1][0]) * dr[r, 0] + float(p[1] - best[1][1]) * dr[r, 1]
+        if r < nF:
+            assert dot > 0, r
+        else:
+            assert dot < 0, r
+
+
+@pytest.mark.parametrize("body", ["wedge", "naca12", "16-gon"])
+def test_boundary_point_on_surface_along_local_normal(body):
+    """P' lies on the body surface and X - P' is parallel to the local normal
+    (section 4.3) unless the counted fallback was taken."""
+    v, s = BODIES[body]()
+    c = _tiny_case(v, s, 40)
+    o = oracle.Oracle(c)
+    o.classify()
+    ir, dr = o.records()
+    xc = 0.5 * (c.xf[:-1] + c.xf[1:])
+    for r in range(len(ir)):
+        cell = ir[r, 0]
+        X = np.array([xc[cell % c.ni], xc[cell // c.ni]])
+        n = dr[r, :2]
+        P = dr[r, 3:5]
+        # distance of P' to the polygon
+        dmin = min(np.linalg.norm(P - _proj(P, v[a], v[b])) for a, b in s)
+        assert dmin < 1e-12
+        if ir[r, 6] & 1:
+            continue
+        d = X - P
+        assert abs(d[0] * n[1] - d[1] * n[0]) < 1e-12
+        assert abs(abs(dr[r, 6]) - np.linalg.norm(d)) < 1e-14
+
+
+def _proj(p, a, b):
+    e = b - a
+    t = np.clip(np.dot(p - a, e) / np.dot(e, e), 0.0, 1.0)
+    return a + t * e
+
+
+@pytest.mark.parametrize("family", ["linear", "quadratic"])
+@pytest.mark.parametrize("body", sorted(BODIES))
+def test_probe_validity_rules(family, body):
+    """Probe corners obey the validity rules (sections 4.5 and 5): IDW probes
+    of forcing nodes weight FLUID corners only; multilinear probes use only
+    FLUID (quadratic forcing) or FLUID/FORCING (ghost) corners; weights sum
+    to one."""
+    v, s = BODIES[body]()
+    c = _tiny_case(v, s, 40, family=family)
+    o = oracle.Oracle(c)
+    o.classify()
+    ir, dr = o.records()
+    nF = o.lists()[2][0]
+    flat = o.classes().ravel()
+    for r in range(len(ir)):
+        forcing = r < nF
+        for probe in range(2 if family == "quadratic" else 1):
+            mode = ir[r, 4 + probe]
+            if mode == 2:
+                continue
+            ids = ir[r, 7 + 8 * probe: 11 + 8 * probe]
+            wt = dr[r, 9 + 8 * probe: 13 + 8 * probe]
+            assert abs(wt.sum() - 1.0) < 1e-14
+            for cid, ww in zip(ids, wt):
+                if ww == 0.0:
+                    continue
+                t = flat[cid]
+                if forcing:
+                    assert t == oracle.FLUID
+                else:
+                    assert t in (oracle.FLUID, oracle.FORCING)
+    st = o.stats()
+    assert st["fallback_none"] == 0
+
+
+@pytest.mark.parametrize("kind", ["cylinder", "wedge", "naca"])
+def test_ghost_layers_cover_stencils(kind):
+    """Three ghost layers (section 5) cover every cell the WENO5 and viscous
+    stencils of FLUID cells read: the oracle counts SOLID reads."""
+    c = w.small_case(kind, 48)
+    o = oracle.Oracle(c)
+    o.classify()
+    nv = c.ndim + 2
+    prim = w.freestream_prim(2, c.ni, c.nj, 1, c.p_inf)
+    q = o.prim_to_state(prim)
+    o.bc(q)
+    o.fill(q)
+    o.residual(q)
+    assert o.stats()["stencil_violation"] == 0
+    assert nv == 4
+
+
+def test_moving_body_fresh_cleared_cells_were_ghosts():
+    """A cell uncovered by a moving body keeps its last ghost-extended state
+    (section 5); with motion below three cells per step it was a ghost."""
+    c = w.small_case("moving-cylinder", 64, steps=6)
+    o = oracle.Oracle(c)
+    prim = w.freestream_prim(2, c.ni, c.nj, 1, c.p_inf)
+    q = o.prim_to_state(prim)
+    o.classify(0.0)
+    # large time steps so the body moves several cells over the run
+    seen = 0
+    for k in range(12):
+        o.classify(0.4 * k)
+        seen = o.stats()["fresh_cleared"]
+    assert seen > 0
+    assert o.stats()["fresh_violation"] == 0
+    del q

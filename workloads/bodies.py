@@ -1,0 +1,77 @@
+"""Synthetic immersed bodies.
+
+2D bodies are closed polygons listed counter-clockwise (interior on the left);
+facets are segments (v[k], v[k+1]).  The 3D body is a triangulated open tube
+whose triangles are counter-clockwise seen from outside.  All vertex
+coordinates are snapped to multiples of 2**-24.
+"""
+import numpy as np
+
+from .grids import snap
+
+
+def _polygon(v):
+    v = snap(np.asarray(v, dtype=np.float64))
+    n = len(v)
+    seg = np.stack([np.arange(n), (np.arange(n) + 1) % n], axis=1).astype(np.int32)
+    return v, seg
+
+
+def circle_polygon(n=256, diameter=1.0, center=(0.0, 0.0)):
+    """Regular n-gon inscribed in the circle, vertices at angles 2 pi k / n."""
+    t = 2.0 * np.pi * np.arange(n) / n
+    r = 0.5 * diameter
+    v = np.stack([center[0] + r * np.cos(t), center[1] + r * np.sin(t)], axis=1)
+    return _polygon(v)
+
+
+def wedge_polygon(half_angle_deg=15.0, length=1.0, apex=(-0.5, 0.0)):
+    """Triangle with its apex pointing upstream (-x) and a vertical base."""
+    t = length * np.tan(np.radians(half_angle_deg))
+    ax, ay = apex
+    v = [[ax, ay], [ax + length, ay - t], [ax + length, ay + t]]
+    return _polygon(v)
+
+
+def naca00_polygon(thickness=0.12, n_vert=1024, x0=0.0, chord=1.0):
+    """Symmetric NACA 4-digit section with a closed, sharp trailing edge
+    (last coefficient -0.1036), cosine-spaced; n_vert unique vertices."""
+    if n_vert % 2:
+        raise ValueError("n_vert must be even")
+    m = n_vert // 2
+    k = np.arange(m + 1)
+    x = 0.5 * (1.0 - np.cos(np.pi * k / m))
+    yt = 5.0 * thickness * (0.2969 * np.sqrt(x) - 0.1260 * x - 0.3516 * x ** 2
+                            + 0.2843 * x ** 3 - 0.1036 * x ** 4)
+    yt[0] = 0.0
+    yt[-1] = 0.0
+    upper = [[x[i], yt[i]] for i in range(m, 0, -1)]    # TE, upper ... (x>0)
+    lower = [[x[i], -yt[i]] for i in range(0, m)]       # LE, lower ...
+    v = np.array(upper + lower, dtype=np.float64)
+    v[:, 0] = x0 + chord * v[:, 0]
+    v[:, 1] = chord * v[:, 1]
+    return _polygon(v)
+
+
+def tube_mesh(radius=0.5, n_theta=512, n_z=64, z_lo=-2.0, z_hi=2.0,
+              center=(0.0, 0.0)):
+    """Open circular tube along z (no caps): (n_z+1)*n_theta vertices and
+    2*n_theta*n_z triangles with outward orientation."""
+    t = 2.0 * np.pi * np.arange(n_theta) / n_theta
+    z = z_lo + (z_hi - z_lo) * np.arange(n_z + 1) / n_z
+    zz, tt = np.meshgrid(z, t, indexing="ij")
+    v = np.stack([center[0] + radius * np.cos(tt), center[1] + radius * np.sin(tt), zz],
+                 axis=-1).reshape(-1, 3)
+    v = snap(v)
+
+    def vid(a, b):
+        return b * n_theta + (a % n_theta)
+
+    tri = []
+    for b in range(n_z):
+        for a in range(n_theta):
+            p00, p10 = vid(a, b), vid(a + 1, b)
+            p11, p01 = vid(a + 1, b + 1), vid(a, b + 1)
+            tri.append((p00, p10, p11))
+            tri.append((p00, p11, p01))
+    return v, np.asarray(tri, dtype=np.int32)

@@ -1,0 +1,185 @@
+"""Case descriptions: grid, body, flow conditions and numerics parameters.
+
+The four fixed workloads mirror the paper's case shapes (circular cylinder,
+supersonic wedge, low-Mach NACA section, transversely oscillating cylinder)
+and ``small_case`` builds scaled-down versions for parity tests.  Time steps
+are fixed per case and computed here once, so every implementation advances
+with the same step.
+"""
+from dataclasses import dataclass, field
+import numpy as np
+
+from .grids import uniform_faces, tanh_center_faces, core_stretched_faces
+from .bodies import circle_polygon, wedge_polygon, naca00_polygon, tube_mesh
+
+BC_NAMES = ("farfield", "extrap", "periodic")
+
+
+@dataclass
+class Case:
+    name: str
+    ndim: int
+    xf: np.ndarray
+    yf: np.ndarray
+    zf: np.ndarray
+    bc: tuple                      # (x-, x+, y-, y+, z-, z+), names from BC_NAMES
+    vert: np.ndarray               # (nvert, ndim) float64
+    facet: np.ndarray              # (nfacet, ndim) int32
+    mach: float
+    reynolds: float
+    prandtl: float = 0.72
+    gamma: float = 1.4
+    scheme: str = "rk3"            # "rk3" | "dual"
+    ib_family: str = "linear"      # "linear" (IDW + image point) | "quadratic"
+    dt: float = 0.0
+    cfl_tau: float = 0.5
+    n_inner: int = 20
+    motion: dict = field(default_factory=dict)   # {} or {axis, amplitude, frequency, phase}
+    steps: int = 1                 # RK3 steps, or physical steps for dual time
+
+    @property
+    def ni(self):
+        return len(self.xf) - 1
+
+    @property
+    def nj(self):
+        return len(self.yf) - 1
+
+    @property
+    def nk(self):
+        return len(self.zf) - 1 if self.ndim == 3 else 1
+
+    @property
+    def ncells(self):
+        return self.ni * self.nj * self.nk
+
+    @property
+    def evals_per_step(self):
+        return 3 if self.scheme == "rk3" else self.n_inner
+
+    @property
+    def p_inf(self):
+        return 1.0 / (self.gamma * self.mach ** 2)
+
+
+def _hmin(axes):
+    return [float(np.min(np.diff(a))) for a in axes]
+
+
+def rk3_dt(mach, reynolds, axes, cfl=None):
+    """Explicit step: CFL / sum_d (|U_inf,d| + a_inf) / h_min,d, capped by the
+    viscous limit Re h_min^2 / 4 (U_inf = 1 along x, a_inf = 1 / M)."""
+    if cfl is None:
+        cfl = 0.4 if mach > 1.0 else 0.5
+    h = _hmin(axes)
+    a = 1.0 / mach
+    s = sum(((1.0 if d == 0 else 0.0) + a) / h[d] for d in range(len(h)))
+    return min(cfl / s, 0.25 * reynolds * min(h) ** 2)
+
+
+def dual_dt(axes):
+    """Physical step of dual time stepping: h_min / U_inf (unit CFL on U_inf)."""
+    return min(_hmin(axes))
+
+
+def _z_dummy():
+    return np.array([-0.5, 0.5])
+
+
+def case_c1(steps=200):
+    f = uniform_faces(128, -8.0, 8.0)
+    v, s = circle_polygon(256, 1.0)
+    return Case("C1-cylinder-M0.3", 2, f, f.copy(), _z_dummy(), ("farfield",) * 4 + ("periodic",) * 2,
+                v, s, 0.3, 40.0, dt=rk3_dt(0.3, 40.0, [f, f]), steps=steps)
+
+
+def case_c2(steps=2000):
+    xf = uniform_faces(1024, -1.0, 3.0)
+    yf = tanh_center_faces(512, -2.0, 2.0, 1.02)
+    v, s = wedge_polygon(15.0, 1.0, (-0.5, 0.0))
+    bc = ("farfield", "extrap", "extrap", "extrap", "periodic", "periodic")
+    return Case("C2-wedge-M2", 2, xf, yf, _z_dummy(), bc, v, s, 2.0, 1.0e4,
+                dt=rk3_dt(2.0, 1.0e4, [xf, yf]), steps=steps)
+
+
+def case_c3(physical_steps=250, n_inner=20):
+    h = 1.0 / 512
+    xf = core_stretched_faces(2048, -20.0, 20.0, -0.5, 1.5, h)
+    yf = core_stretched_faces(1024, -15.0, 15.0, -0.25, 0.25, h)
+    v, s = naca00_polygon(0.12, 1024, 0.0, 1.0)
+    return Case("C3-naca0012-M0.001", 2, xf, yf, _z_dummy(), ("farfield",) * 4 + ("periodic",) * 2,
+                v, s, 0.001, 1000.0, scheme="dual", ib_family="quadratic",
+                dt=dual_dt([xf, yf]), n_inner=n_inner, steps=physical_steps)
+
+
+def case_c4(steps=1000):
+    xf = uniform_faces(384, -8.0, 16.0)
+    yf = uniform_faces(256, -8.0, 8.0)
+    zf = uniform_faces(64, -2.0, 2.0)
+    v, t = tube_mesh(0.5, 512, 64, -2.0, 2.0)
+    bc = ("farfield",) * 4 + ("periodic",) * 2
+    motion = dict(axis=1, amplitude=0.2, frequency=0.2, phase=0.0)
+    return Case("C4-oscillating-tube-M0.2", 3, xf, yf, zf, bc, v, t, 0.2, 185.0,
+                dt=rk3_dt(0.2, 185.0, [xf, yf, zf]), motion=motion, steps=steps)
+
+
+def small_case(kind, n=64, steps=2, **kw):
+    """Scaled-down parity cases: kind in cylinder | wedge | naca | tube |
+    moving-cylinder | box (no body, periodic)."""
+    if kind == "cylinder":
+        f = uniform_faces(n, -4.0, 4.0)
+        v, s = circle_polygon(kw.get("nseg", 64), 1.0)
+        m = kw.get("mach", 0.3)
+        return Case(f"small-cylinder-{n}", 2, f, f.copy(), _z_dummy(),
+                    ("farfield",) * 4 + ("periodic",) * 2, v, s, m, 40.0,
+                    dt=rk3_dt(m, 40.0, [f, f]), steps=steps,
+                    ib_family=kw.get("ib_family", "linear"))
+    if kind == "moving-cylinder":
+        f = uniform_faces(n, -4.0, 4.0)
+        v, s = circle_polygon(kw.get("nseg", 64), 1.0)
+        motion = dict(axis=1, amplitude=0.2, frequency=0.2, phase=0.0)
+        return Case(f"small-moving-cylinder-{n}", 2, f, f.copy(), _z_dummy(),
+                    ("farfield",) * 4 + ("periodic",) * 2, v, s, 0.2, 185.0,
+                    dt=rk3_dt(0.2, 185.0, [f, f]), motion=motion, steps=steps)
+    if kind == "wedge":
+        xf = uniform_faces(2 * n, -1.0, 3.0)
+        yf = tanh_center_faces(n, -2.0, 2.0, 1.02)
+        v, s = wedge_polygon(15.0, 1.0, (-0.5, 0.0))
+        bc = ("farfield", "extrap", "extrap", "extrap", "periodic", "periodic")
+        return Case(f"small-wedge-{2*n}x{n}", 2, xf, yf, _z_dummy(), bc, v, s, 2.0, 1.0e4,
+                    dt=rk3_dt(2.0, 1.0e4, [xf, yf]), steps=steps)
+    if kind == "naca":
+        h = kw.get("h", 1.0 / 32)
+        xf = core_stretched_faces(2 * n, -4.0, 5.0, -0.5, 1.5, h)
+        yf = core_stretched_faces(n, -4.0, 4.0, -0.25, 0.25, h)
+        v, s = naca00_polygon(kw.get("thickness", 0.12), kw.get("nvert", 256), 0.0, 1.0)
+        m = kw.get("mach", 0.001)
+        return Case(f"small-naca-{2*n}x{n}", 2, xf, yf, _z_dummy(), ("farfield",) * 4 + ("periodic",) * 2,
+                    v, s, m, 1000.0, scheme="dual", ib_family="quadratic",
+                    dt=dual_dt([xf, yf]), n_inner=kw.get("n_inner", 4), steps=steps)
+    if kind == "tube":
+        xf = uniform_faces(n, -2.0, 4.0)
+        yf = uniform_faces(n, -3.0, 3.0)
+        zf = uniform_faces(kw.get("nz", 8), -0.5, 0.5)
+        v, t = tube_mesh(0.5, kw.get("ntheta", 64), kw.get("nzt", 4), -0.5, 0.5)
+        bc = ("farfield",) * 4 + ("periodic",) * 2
+        motion = dict(axis=1, amplitude=0.2, frequency=0.2, phase=0.0) if kw.get("moving", True) else {}
+        return Case(f"small-tube-{n}", 3, xf, yf, zf, bc, v, t, 0.2, 185.0,
+                    dt=rk3_dt(0.2, 185.0, [xf, yf, zf]), motion=motion, steps=steps)
+    if kind == "box":
+        ndim = kw.get("ndim", 2)
+        f = uniform_faces(n, 0.0, 1.0)
+        zf = uniform_faces(kw.get("nz", 8), 0.0, 1.0) if ndim == 3 else _z_dummy()
+        m = kw.get("mach", 0.5)
+        empty_v = np.zeros((0, ndim))
+        empty_f = np.zeros((0, ndim), dtype=np.int32)
+        axes = [f, f] + ([zf] if ndim == 3 else [])
+        return Case(f"box-{ndim}d-{n}", ndim, f, f.copy(), zf, ("periodic",) * 6,
+                    empty_v, empty_f, m, kw.get("reynolds", 100.0),
+                    scheme=kw.get("scheme", "rk3"),
+                    dt=kw.get("dt", rk3_dt(m, kw.get("reynolds", 100.0), axes)),
+                    n_inner=kw.get("n_inner", 4), steps=steps)
+    raise ValueError(kind)
+
+
+CASES = {"C1": case_c1, "C2": case_c2, "C3": case_c3, "C4": case_c4}
