@@ -1,0 +1,173 @@
+/*
+ * ibm.h -- C ABI of the MI355X (gfx950) immersed-boundary step library.
+ *
+ * The library advances the compressible Navier-Stokes equations on a
+ * rectilinear cell-centred finite-volume grid with a sharp-interface
+ * immersed body, following Seshadri & De, "A novel sharp interface immersed
+ * boundary framework for viscous flow simulations at arbitrary Mach number
+ * involving complex and moving boundaries" (arXiv 1912.11908):
+ *   - node classification by ray casting with crossing parity (section 3.2),
+ *   - forcing (IB) and three ghost layers (sections 3.2 and 5),
+ *   - closest feature, angle-weighted pseudo-normals and the local-normal
+ *     reconstruction direction (section 4, eqs 1-3),
+ *   - boundary conditions eqs 4-6 and 8 with inverse-distance / image-point
+ *     (compressible) or quadratic (incompressible) reconstruction
+ *     (sections 4.4-4.6 and 5),
+ *   - WENO5 reconstruction, low-diffusion flux splitting with low-Mach
+ *     preconditioning and central viscous fluxes (section 2),
+ *   - explicit SSP-RK3 or preconditioned dual time stepping (section 2).
+ *
+ * Conventions shared by every entry point
+ *   Units: rho_inf = U_inf = T_inf = 1, U_inf along +x, p_inf = 1/(gamma M^2),
+ *     gas constant R = p_inf, mu = 1/Re (constant), conductivity mu c_p / Pr.
+ *   State layout (device, double): [nv][nk + 2*hz][nj + 6][ni + 6], i fastest,
+ *     nv = ndim + 2, three halo cells per side in x and y, hz = 3 in 3D and 0
+ *     in 2D.  For IBM_RK3 the state is conserved (rho, rho u, rho v[, rho w],
+ *     rho E); for IBM_DUAL it is the primitive perturbation
+ *     (p - p_inf, u, v[, w], T - 1).
+ *   Interior arrays (residuals, primitives, classes): [..][nk][nj][ni].
+ *   Classes: IBM_FLUID, IBM_FORCING (fluid cell with a solid face
+ *     neighbour), IBM_G1..IBM_G3 (ghost layers), IBM_SOLID.
+ *   Streams are hipStream_t passed as void*; NULL means the default stream.
+ *   Every device buffer is allocated by the caller and must stay valid while
+ *   work that uses it is in flight; the library never allocates or frees
+ *   device memory.  The workspace handed to ibm_create belongs to the context
+ *   until ibm_destroy.
+ *   Calls enqueue work asynchronously and do not synchronise, except
+ *   ibm_create (uploads the geometry), ibm_status and ibm_read_counts.
+ *   One context is used by one host thread at a time; distinct contexts are
+ *   independent.
+ *   Return codes: IBM_OK (0) or a negative IBM_E* code; ibm_last_error gives
+ *   a message.  Nothing aborts and no C++ exception crosses the ABI.
+ */
+#ifndef IBM_H
+#define IBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IBM_OK 0
+#define IBM_EINVAL (-1)      /* bad argument, shape or descriptor             */
+#define IBM_EGEOM (-2)       /* body out of the lattice range or degenerate   */
+#define IBM_EDEVICE (-3)     /* HIP error (code in ibm_last_error)            */
+#define IBM_ENONFINITE (-4)  /* non-finite or non-positive rho/p in a cell    */
+#define IBM_ENOSPACE (-5)    /* workspace smaller than ibm_workspace_bytes    */
+#define IBM_ECAPACITY (-6)   /* more IB nodes than the workspace can hold     */
+
+enum { IBM_BC_FARFIELD = 0, IBM_BC_EXTRAP = 1, IBM_BC_PERIODIC = 2 };
+enum { IBM_RK3 = 0, IBM_DUAL = 1 };
+enum { IBM_IB_LINEAR = 0, IBM_IB_QUADRATIC = 1 };
+enum { IBM_FP64 = 0, IBM_MIXED = 1 };
+enum { IBM_FLUID = 0, IBM_FORCING = 1, IBM_G1 = 2, IBM_G2 = 3, IBM_G3 = 4, IBM_SOLID = 5 };
+
+/* Case descriptor; all pointers are host pointers, copied by ibm_create. */
+typedef struct ibm_case {
+    int ndim;                 /* 2 or 3                                            */
+    int ni, nj, nk;           /* interior cells per axis (nk = 1 when ndim = 2)    */
+    const double *xf, *yf, *zf; /* face coordinates, ni+1 / nj+1 / nk+1, increasing */
+    int bc[6];                /* x-, x+, y-, y+, z-, z+: IBM_BC_*                   */
+    int nvert, nfacet;        /* body size (0 facets: no body)                     */
+    const double *vert;       /* nvert * ndim coordinates (rest pose)              */
+    const int32_t *facet;     /* 2D: nfacet * 2 vertex ids, counter-clockwise      */
+                              /* polygon; 3D: nfacet * 3 ids, counter-clockwise    */
+                              /* seen from outside                                 */
+    int motion;               /* 0: stationary; 1: translation along one axis      */
+    double motion_par[4];     /* axis, amplitude A, frequency f, phase:            */
+                              /* x_axis(t) = A cos(2 pi f t + phase) (section 8.2.2) */
+    double mach, reynolds, prandtl, gamma;
+    int scheme;               /* IBM_RK3 or IBM_DUAL                               */
+    int ib_family;            /* IBM_IB_LINEAR (IDW + image point) or QUADRATIC    */
+    int precision;            /* IBM_FP64, or IBM_MIXED: FP32 reconstruction and   */
+                              /* fluxes on perturbation variables, FP64 update     */
+    double dt;                /* physical time step                                */
+    double cfl_tau;           /* pseudo-time CFL (dual time)                       */
+    int n_inner;              /* pseudo-iterations per physical step (dual time)   */
+} ibm_case;
+
+typedef struct ibm_ctx ibm_ctx;
+
+/* Device pointers into the context's workspace, for inspection. */
+typedef struct ibm_info {
+    int ndim, ni, nj, nk, nv;
+    long long state_elems;    /* doubles per state array (nv * extended cells)     */
+    long long ncell;          /* interior cells                                    */
+    int cap_nodes;            /* capacity of each IB node list                     */
+    int region[6];            /* IB region box [i0,i1) [j0,j1) [k0,k1)             */
+    uint8_t *cls;             /* class per interior cell                           */
+    int32_t *counts;          /* nF, nG1, nG2, nG3, nG, status, fallbacks x2       */
+    int32_t *list_forcing;    /* cell ids of FORCING nodes, raster order           */
+    int32_t *list_ghost;      /* cell ids of G1..G3 nodes, raster order            */
+    int32_t *rec_int;         /* per record (forcing first, then ghosts):          */
+                              /* IBM_REC_INT int32s                                */
+    double *rec_dbl;          /* per record IBM_REC_DBL doubles                    */
+    double time;              /* current solution time                             */
+} ibm_info;
+
+#define IBM_REC_INT 24
+#define IBM_REC_DBL 32
+
+/* Bytes of device workspace a case needs (host-only; no device work).
+ * Returns IBM_EINVAL for an invalid descriptor. */
+int ibm_workspace_bytes(const ibm_case *c, size_t *bytes);
+
+/* Create a context bound to the current HIP device.  Copies the descriptor's
+ * host arrays, builds facet normals and the pseudo-normals of eqs 2-3 on the
+ * host, and uploads grid and body data into d_workspace (synchronous).
+ * bytes must be at least ibm_workspace_bytes(c). */
+int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out);
+void ibm_destroy(ibm_ctx *ctx);
+
+/* Solution time used by the next ibm_classify / ibm_advance call. */
+int ibm_set_time(ibm_ctx *ctx, double t);
+
+/* a1-a4: pose the body at the context time, classify every cell by ray
+ * parity (section 3.2), tag FORCING and G1-G3, compact the node lists in
+ * raster order, and build per-node reconstruction records: closest feature,
+ * local normal, boundary point P' and probe stencils (section 4). */
+int ibm_classify(ibm_ctx *ctx, void *stream);
+
+/* a5: fill the domain ghost layers and then the immersed-boundary nodes of
+ * d_q at time t (FORCING first, then the ghost layers), eqs 4-6 and 8. */
+int ibm_fill(ibm_ctx *ctx, double *d_q, double t, void *stream);
+
+/* a6-a9: residual R = (1/V) sum_faces (F_inv - F_visc) . S of d_q on FLUID
+ * cells (zero elsewhere), in conserved form, interior layout [nv][nk][nj][ni].
+ * d_q's halo and IB nodes must already be filled (ibm_fill). */
+int ibm_residual(ibm_ctx *ctx, const double *d_q, double *d_r, void *stream);
+
+/* a1-a10: advance nsteps SSP-RK3 steps (IBM_RK3) or physical dual-time steps
+ * of n_inner pseudo-iterations each (IBM_DUAL), in place on d_q.  Moving
+ * bodies are reclassified at the pose of each step's start time. */
+int ibm_advance(ibm_ctx *ctx, double *d_q, int nsteps, void *stream);
+
+/* Primitive (rho, u, v[, w], p) interior array -> state (halo untouched),
+ * and back. */
+int ibm_init_state(ibm_ctx *ctx, const double *d_prim, double *d_q, void *stream);
+int ibm_state_to_prim(ibm_ctx *ctx, const double *d_q, double *d_prim, void *stream);
+
+/* Synchronise the stream and report the sticky device status: IBM_OK,
+ * IBM_ENONFINITE or IBM_ECAPACITY. */
+int ibm_status(ibm_ctx *ctx, void *stream);
+
+/* Copy the counts word array (8 int32) to host memory; synchronises. */
+int ibm_read_counts(ibm_ctx *ctx, int32_t *host_counts, void *stream);
+
+int ibm_info_get(const ibm_ctx *ctx, ibm_info *out);
+const char *ibm_last_error(const ibm_ctx *ctx);
+
+/* Average device time in milliseconds of one launch of the fused
+ * residual-and-update kernel of the given RK3 stage (1..3) or of one dual-time
+ * pseudo-iteration (stage 0), measured with HIP events around nrep launches
+ * on stream.  The state d_q is used as input and scratch stage buffers as
+ * output (d_q is not modified).  Synchronises. */
+int ibm_time_update_kernel(ibm_ctx *ctx, const double *d_q, int stage, int nrep, void *stream,
+                           float *avg_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

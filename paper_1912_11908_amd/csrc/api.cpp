@@ -1,0 +1,861 @@
+// Host side of the C ABI declared in include/ibm.h: descriptor checks,
+// workspace layout, host preprocessing of grid and body (lattice snapping,
+// facet normals, angle-weighted pseudo-normals of eqs 2-3, edge adjacency),
+// and the orchestration of the HIP kernels for classify / fill / residual /
+// advance.  No device memory is allocated here: everything lives in the
+// caller's workspace.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.h"
+
+using namespace ibm;
+
+struct ibm_ctx {
+    int device;
+    Grid g;
+    Body b;
+    Flow f;
+    IB ib;
+    Motion mo;
+    double *q1, *q2, *wtmp, *qn, *qnm1;
+    double t;
+    long long step;
+    int n_inner;
+    bool classified;
+    long long rest_box_lat[6];
+    char err[256];
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+struct Carve {
+    char *base;
+    size_t off;
+    template <typename T> T *take(size_t n)
+    {
+        off = (off + kAlign - 1) / kAlign * kAlign;
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += n * sizeof(T);
+        return p;
+    }
+};
+
+int set_err(ibm_ctx *c, int code, const char *msg)
+{
+    if (c)
+        std::snprintf(c->err, sizeof c->err, "%s", msg);
+    return code;
+}
+
+int check_desc(const ibm_case *c)
+{
+    if (!c || (c->ndim != 2 && c->ndim != 3))
+        return IBM_EINVAL;
+    if (c->ni < 4 || c->nj < 4 || (c->ndim == 3 && c->nk < 4))
+        return IBM_EINVAL;
+    if (c->ndim == 2 && c->nk != 1)
+        return IBM_EINVAL;
+    if (!c->xf || !c->yf || (c->ndim == 3 && !c->zf))
+        return IBM_EINVAL;
+    const double *f[3] = {c->xf, c->yf, c->zf};
+    int n[3] = {c->ni, c->nj, c->nk};
+    for (int d = 0; d < c->ndim; ++d)
+        for (int i = 0; i < n[d]; ++i)
+            if (!(f[d][i + 1] > f[d][i]))
+                return IBM_EINVAL;
+    for (int s = 0; s < 6; ++s)
+        if (c->bc[s] < IBM_BC_FARFIELD || c->bc[s] > IBM_BC_PERIODIC)
+            return IBM_EINVAL;
+    for (int d = 0; d < c->ndim; ++d)
+        if ((c->bc[2 * d] == IBM_BC_PERIODIC) != (c->bc[2 * d + 1] == IBM_BC_PERIODIC))
+            return IBM_EINVAL;
+    if (c->nfacet < 0 || c->nvert < 0 || (c->nfacet > 0 && (!c->vert || !c->facet)))
+        return IBM_EINVAL;
+    for (long long m = 0; m < (long long)c->nfacet * c->ndim; ++m)
+        if (c->facet[m] < 0 || c->facet[m] >= c->nvert)
+            return IBM_EINVAL;
+    if (!(c->mach > 0) || !(c->reynolds > 0) || !(c->prandtl > 0) || !(c->gamma > 1) || !(c->dt > 0))
+        return IBM_EINVAL;
+    if (c->scheme != IBM_RK3 && c->scheme != IBM_DUAL)
+        return IBM_EINVAL;
+    if (c->ib_family != IBM_IB_LINEAR && c->ib_family != IBM_IB_QUADRATIC)
+        return IBM_EINVAL;
+    if (c->precision != IBM_FP64 && c->precision != IBM_MIXED)
+        return IBM_EINVAL;
+    if (c->scheme == IBM_DUAL && (c->n_inner < 1 || !(c->cfl_tau > 0)))
+        return IBM_EINVAL;
+    if (c->motion && (c->motion_par[0] < 0 || c->motion_par[0] >= c->ndim))
+        return IBM_EINVAL;
+    return IBM_OK;
+}
+
+// extended faces: periodic axes take the periodic images of the far end,
+// the others mirror the first / last interior cells
+std::vector<double> ext_faces(const double *f, int n, bool periodic)
+{
+    std::vector<double> e(n + 7);
+    for (int i = 0; i <= n; ++i)
+        e[i + 3] = f[i];
+    for (int k = 1; k <= 3; ++k) {
+        if (periodic) {
+            e[3 - k] = f[0] - (f[n] - f[n - k]);
+            e[n + 3 + k] = f[n] + (f[k] - f[0]);
+        } else {
+            e[3 - k] = 2.0 * f[0] - f[k];
+            e[n + 3 + k] = 2.0 * f[n] - f[n - k];
+        }
+    }
+    return e;
+}
+
+struct HostGeom {
+    int nd, n[3], hz, sx, sy, sz;
+    long long vs, ncell;
+    std::vector<double> xf[3], xc[3], rdx[3], rdxc[3], rdtc[3];
+    std::vector<float> rdx_f[3], rdxc_f[3], rdtc_f[3];
+    std::vector<long long> Xc[3];
+    // body
+    std::vector<long long> V0;
+    std::vector<double> v0;
+    std::vector<int> facet;
+    std::vector<double> fnrm, vnrm, enrm;
+    std::vector<int> edge_of;
+    int nedge;
+    int region[6];
+    int cap, wpr, nblk;
+};
+
+double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+void unit3(double *a)
+{
+    double l = std::sqrt(dot3(a, a));
+    if (l > 0.0) {
+        a[0] /= l;
+        a[1] /= l;
+        a[2] /= l;
+    }
+}
+
+// Facet normals and the pseudo-normals of section 4.2.  2D: a polygon
+// vertex is the planar image of an extruded edge, so it takes eq.3 with both
+// incident segments weighted equally (normalised).  3D: eq.2 weights the
+// incident facet normals by their interior angles at the vertex; eq.3 weights
+// the two facets of an edge equally (pi each), normalised; a boundary edge
+// of an open mesh takes its single facet's normal.
+void body_normals(HostGeom &h, const std::vector<double> &v)
+{
+    int nd = h.nd;
+    int nf = (int)(h.facet.size() / nd), nv = (int)(v.size() / nd);
+    h.fnrm.assign((size_t)std::max(nf, 1) * 3, 0.0);
+    h.vnrm.assign((size_t)std::max(nv, 1) * 3, 0.0);
+    if (nd == 2) {
+        for (int f = 0; f < nf; ++f) {
+            const double *a = &v[2 * h.facet[2 * f]], *b = &v[2 * h.facet[2 * f + 1]];
+            double ex = b[0] - a[0], ey = b[1] - a[1], l = std::sqrt(ex * ex + ey * ey);
+            h.fnrm[3 * f] = ey / l;
+            h.fnrm[3 * f + 1] = -ex / l;
+        }
+        for (int f = 0; f < nf; ++f)
+            for (int e = 0; e < 2; ++e) {
+                int id = h.facet[2 * f + e];
+                h.vnrm[3 * id] += h.fnrm[3 * f];
+                h.vnrm[3 * id + 1] += h.fnrm[3 * f + 1];
+            }
+        for (int m = 0; m < nv; ++m)
+            unit3(&h.vnrm[3 * m]);
+        h.nedge = 0;
+        h.enrm.assign(3, 0.0);
+        h.edge_of.assign(3, 0);
+        return;
+    }
+    for (int f = 0; f < nf; ++f) {
+        const int *t = &h.facet[3 * f];
+        const double *a = &v[3 * t[0]], *b = &v[3 * t[1]], *c = &v[3 * t[2]];
+        double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+        double e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+        double *n = &h.fnrm[3 * f];
+        n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+        n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+        n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        unit3(n);
+        for (int m = 0; m < 3; ++m) {
+            const double *p = &v[3 * t[m]], *q = &v[3 * t[(m + 1) % 3]], *r = &v[3 * t[(m + 2) % 3]];
+            double u[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]};
+            double w[3] = {r[0] - p[0], r[1] - p[1], r[2] - p[2]};
+            double cs = dot3(u, w) / (std::sqrt(dot3(u, u)) * std::sqrt(dot3(w, w)));
+            cs = std::min(1.0, std::max(-1.0, cs));
+            double ang = std::acos(cs);
+            for (int d = 0; d < 3; ++d)
+                h.vnrm[3 * t[m] + d] += ang * n[d];
+        }
+    }
+    for (int m = 0; m < nv; ++m)
+        unit3(&h.vnrm[3 * m]);
+    // edge adjacency: half-edges keyed by (min vertex, max vertex), sorted
+    struct HE {
+        long long a, b;
+        int f, m;
+    };
+    std::vector<HE> he((size_t)3 * nf);
+    for (int f = 0; f < nf; ++f)
+        for (int m = 0; m < 3; ++m) {
+            int p = h.facet[3 * f + m], q = h.facet[3 * f + (m + 1) % 3];
+            he[3 * f + m] = {std::min(p, q), std::max(p, q), f, m};
+        }
+    std::sort(he.begin(), he.end(), [](const HE &x, const HE &y) {
+        if (x.a != y.a) return x.a < y.a;
+        if (x.b != y.b) return x.b < y.b;
+        if (x.f != y.f) return x.f < y.f;
+        return x.m < y.m;
+    });
+    h.edge_of.assign((size_t)std::max(3 * nf, 1), 0);
+    h.enrm.assign((size_t)std::max(3 * nf, 1) * 3, 0.0);
+    int ne = 0;
+    for (size_t s = 0; s < he.size();) {
+        size_t e = s;
+        while (e < he.size() && he[e].a == he[s].a && he[e].b == he[s].b)
+            ++e;
+        for (size_t m = s; m < e; ++m) {
+            h.edge_of[3 * he[m].f + he[m].m] = ne;
+            for (int d = 0; d < 3; ++d)
+                h.enrm[3 * ne + d] += M_PI * h.fnrm[3 * he[m].f + d];
+        }
+        unit3(&h.enrm[3 * ne]);
+        ++ne;
+        s = e;
+    }
+    h.nedge = ne;
+}
+
+int host_geom(const ibm_case *c, HostGeom &h)
+{
+    h.nd = c->ndim;
+    h.n[0] = c->ni;
+    h.n[1] = c->nj;
+    h.n[2] = c->ndim == 3 ? c->nk : 1;
+    h.hz = c->ndim == 3 ? 3 : 0;
+    h.sx = c->ni + 6;
+    h.sy = c->nj + 6;
+    h.sz = h.n[2] + 2 * h.hz;
+    h.vs = (long long)h.sx * h.sy * h.sz;
+    h.ncell = (long long)c->ni * c->nj * h.n[2];
+    const double *fa[3] = {c->xf, c->yf, c->zf};
+    static const double unit_z[2] = {-0.5, 0.5};
+    for (int d = 0; d < 3; ++d) {
+        int n = h.n[d];
+        if (d < c->ndim)
+            h.xf[d] = ext_faces(fa[d], n, c->bc[2 * d] == IBM_BC_PERIODIC);
+        else
+            h.xf[d] = ext_faces(unit_z, 1, false);
+        h.xc[d].resize(n + 6);
+        for (int i = 0; i < n + 6; ++i)
+            h.xc[d][i] = 0.5 * (h.xf[d][i] + h.xf[d][i + 1]);
+        h.rdx[d].resize(n + 6);
+        h.rdxc[d].assign(n + 6, 0.0);
+        h.rdtc[d].assign(n + 6, 0.0);
+        for (int i = 0; i < n + 6; ++i) {
+            h.rdx[d][i] = 1.0 / (h.xf[d][i + 1] - h.xf[d][i]);
+            if (i + 1 < n + 6)
+                h.rdxc[d][i] = 1.0 / (h.xc[d][i + 1] - h.xc[d][i]);
+            if (i >= 1 && i + 1 < n + 6)
+                h.rdtc[d][i] = 1.0 / (h.xc[d][i + 1] - h.xc[d][i - 1]);
+        }
+        h.rdx_f[d].assign(h.rdx[d].begin(), h.rdx[d].end());
+        h.rdxc_f[d].assign(h.rdxc[d].begin(), h.rdxc[d].end());
+        h.rdtc_f[d].assign(h.rdtc[d].begin(), h.rdtc[d].end());
+        h.Xc[d].resize(n);
+        for (int i = 0; i < n; ++i)
+            h.Xc[d][i] = std::llrint(h.xc[d][i + 3] * kLatScale);
+    }
+    // body on the lattice
+    int nv = c->nvert, nf = c->nfacet, nd = c->ndim;
+    h.V0.resize((size_t)std::max(nv, 1) * nd);
+    h.v0.resize((size_t)std::max(nv, 1) * nd);
+    for (long long m = 0; m < (long long)nv * nd; ++m) {
+        double x = c->vert[m];
+        if (!(std::fabs(x) < 1.0e6))
+            return IBM_EGEOM;
+        h.V0[m] = std::llrint(x * kLatScale);
+        h.v0[m] = (double)h.V0[m] / kLatScale;
+    }
+    h.facet.assign(c->facet, c->facet + (size_t)nf * nd);
+    if (nf > 0) {
+        for (int f = 0; f < nf; ++f) {
+            bool same = h.facet[nd * f] == h.facet[nd * f + 1];
+            if (nd == 3)
+                same = same || h.facet[3 * f + 1] == h.facet[3 * f + 2] || h.facet[3 * f] == h.facet[3 * f + 2];
+            if (same)
+                return IBM_EGEOM;
+        }
+        body_normals(h, h.v0);
+    } else {
+        h.fnrm.assign(3, 0.0);
+        h.vnrm.assign(3, 0.0);
+        h.enrm.assign(3, 0.0);
+        h.edge_of.assign(3, 0);
+        h.nedge = 0;
+    }
+    // immersed-boundary region: body box over all poses, 4 cells of margin
+    if (nf == 0) {
+        for (int s = 0; s < 6; ++s)
+            h.region[s] = 0;
+        h.region[5] = h.region[4] = 0;
+    } else {
+        for (int d = 0; d < 3; ++d) {
+            int n = h.n[d];
+            if (d >= nd) {
+                h.region[2 * d] = 0;
+                h.region[2 * d + 1] = 1;
+                continue;
+            }
+            double lo = 1e300, hi = -1e300;
+            for (int m = 0; m < nv; ++m) {
+                lo = std::min(lo, h.v0[(size_t)m * nd + d]);
+                hi = std::max(hi, h.v0[(size_t)m * nd + d]);
+            }
+            if (c->motion && (int)c->motion_par[0] == d) {
+                double a = std::fabs(c->motion_par[1]) + 1e-6;
+                lo -= a;
+                hi += a;
+            }
+            int i0 = 0, i1 = n;
+            while (i0 < n && h.xc[d][i0 + 3] < lo)
+                ++i0;
+            while (i1 > 0 && h.xc[d][i1 + 2] > hi)
+                --i1;
+            i0 = std::max(0, i0 - 4);
+            i1 = std::min(n, i1 + 4);
+            if (i1 <= i0) {
+                i0 = 0;
+                i1 = 0;
+            }
+            h.region[2 * d] = i0;
+            h.region[2 * d + 1] = i1;
+        }
+    }
+    int rw = h.region[1] - h.region[0], rh = h.region[3] - h.region[2], rd = h.region[5] - h.region[4];
+    if (rw <= 0 || rh <= 0 || rd <= 0)
+        rw = rh = rd = 0;
+    h.cap = rw * rh * rd;
+    h.wpr = (rw + 1 + 31) / 32;
+    h.nblk = (h.cap + 255) / 256;
+    return IBM_OK;
+}
+
+struct Layout {
+    double *xc[3], *xf[3], *rdx[3], *rdxc[3], *rdtc[3];
+    float *rdx_f[3], *rdxc_f[3], *rdtc_f[3];
+    long long *Xc[3];
+    long long *V0, *V;
+    double *v;
+    int *facet;
+    double *fnrm, *vnrm, *enrm;
+    int *edge_of;
+    uint8_t *cls, *inside;
+    uint32_t *toggle;
+    int32_t *counts, *blk, *listF, *listG, *rec_i;
+    double *rec_d;
+    double *q1, *q2, *wtmp, *qn, *qnm1;
+};
+
+size_t carve(const ibm_case *c, const HostGeom &h, char *base, Layout &L)
+{
+    Carve cv{base, 0};
+    int nd = c->ndim;
+    for (int d = 0; d < 3; ++d) {
+        int n = h.n[d];
+        L.xc[d] = cv.take<double>(n + 6);
+        L.xf[d] = cv.take<double>(n + 7);
+        L.rdx[d] = cv.take<double>(n + 6);
+        L.rdxc[d] = cv.take<double>(n + 6);
+        L.rdtc[d] = cv.take<double>(n + 6);
+        L.rdx_f[d] = cv.take<float>(n + 6);
+        L.rdxc_f[d] = cv.take<float>(n + 6);
+        L.rdtc_f[d] = cv.take<float>(n + 6);
+        L.Xc[d] = cv.take<long long>(n);
+    }
+    size_t nvx = (size_t)std::max(c->nvert, 1) * nd;
+    size_t nfx = (size_t)std::max(c->nfacet, 1);
+    L.V0 = cv.take<long long>(nvx);
+    L.V = cv.take<long long>(nvx);
+    L.v = cv.take<double>(nvx);
+    L.facet = cv.take<int>(nfx * nd);
+    L.fnrm = cv.take<double>(nfx * 3);
+    L.vnrm = cv.take<double>((size_t)std::max(c->nvert, 1) * 3);
+    L.enrm = cv.take<double>(nfx * 3 * 3);
+    L.edge_of = cv.take<int>(nfx * 3);
+    size_t cap = (size_t)std::max(h.cap, 1);
+    int rows = (h.region[3] - h.region[2]) * (h.region[5] - h.region[4]);
+    L.cls = cv.take<uint8_t>(h.ncell);
+    L.inside = cv.take<uint8_t>(cap);
+    L.toggle = cv.take<uint32_t>((size_t)std::max(rows * h.wpr, 1));
+    L.counts = cv.take<int32_t>(CNT_WORDS);
+    L.blk = cv.take<int32_t>((size_t)2 * std::max(h.nblk, 1));
+    L.listF = cv.take<int32_t>(cap);
+    L.listG = cv.take<int32_t>(cap);
+    L.rec_i = cv.take<int32_t>(cap * kRecI);
+    L.rec_d = cv.take<double>(cap * kRecD);
+    size_t st = (size_t)h.vs * (nd + 2);
+    L.q1 = L.q2 = L.wtmp = L.qn = L.qnm1 = nullptr;
+    if (c->scheme == IBM_RK3) {
+        L.q1 = cv.take<double>(st);
+        L.q2 = cv.take<double>(st);
+    } else {
+        L.wtmp = cv.take<double>(st);
+        L.qn = cv.take<double>((size_t)h.ncell * (nd + 2));
+        L.qnm1 = cv.take<double>((size_t)h.ncell * (nd + 2));
+    }
+    return (cv.off + kAlign - 1) / kAlign * kAlign;
+}
+
+template <typename T> hipError_t up(T *dst, const std::vector<T> &src)
+{
+    if (src.empty())
+        return hipSuccess;
+    return hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+int dev_err(ibm_ctx *c, hipError_t e, const char *where)
+{
+    if (e == hipSuccess)
+        return IBM_OK;
+    if (c)
+        std::snprintf(c->err, sizeof c->err, "%s: %s (%d)", where, hipGetErrorString(e), (int)e);
+    return IBM_EDEVICE;
+}
+
+hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+void motion_kin(const ibm_ctx *c, double t, double &disp, double &vel, double &acc)
+{
+    double w = 2.0 * M_PI * c->mo.freq;
+    disp = c->mo.amp * std::cos(w * t + c->mo.phase);
+    vel = -w * c->mo.amp * std::sin(w * t + c->mo.phase);
+    acc = -w * w * c->mo.amp * std::cos(w * t + c->mo.phase);
+}
+
+int do_classify(ibm_ctx *c, double t, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    if (c->mo.on && c->b.nvert > 0) {
+        double disp, vel, acc;
+        motion_kin(c, t, disp, vel, acc);
+        e = launch_pose(c->g, c->b, std::llrint(disp * kLatScale), c->mo.axis, s);
+        if (e != hipSuccess)
+            return dev_err(c, e, "pose");
+    }
+    if (c->b.nfacet == 0) {
+        c->classified = true;
+        return IBM_OK;
+    }
+    e = launch_classify(c->g, c->b, c->ib, s);
+    if (e != hipSuccess)
+        return dev_err(c, e, "classify");
+    e = launch_records(c->g, c->b, c->f, c->ib, s);
+    if (e != hipSuccess)
+        return dev_err(c, e, "records");
+    c->classified = true;
+    return IBM_OK;
+}
+
+int do_fill(ibm_ctx *c, double *q, double t, hipStream_t s)
+{
+    hipError_t e = launch_domain_bc(c->g, c->f, q, s);
+    if (e != hipSuccess)
+        return dev_err(c, e, "domain bc");
+    if (c->b.nfacet == 0)
+        return IBM_OK;
+    double disp = 0.0, vel = 0.0, acc = 0.0;
+    int axis = -1;
+    if (c->mo.on) {
+        motion_kin(c, t, disp, vel, acc);
+        axis = c->mo.axis;
+    }
+    e = launch_fill(c->g, c->f, c->ib, q, vel, acc, axis, s);
+    return dev_err(c, e, "fill");
+}
+
+}  // namespace
+
+extern "C" {
+
+int ibm_workspace_bytes(const ibm_case *c, size_t *bytes)
+{
+    if (!bytes)
+        return IBM_EINVAL;
+    int rc = check_desc(c);
+    if (rc)
+        return rc;
+    HostGeom h;
+    rc = host_geom(c, h);
+    if (rc)
+        return rc;
+    Layout L;
+    *bytes = carve(c, h, nullptr, L);
+    return IBM_OK;
+}
+
+int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out)
+{
+    if (!out)
+        return IBM_EINVAL;
+    *out = nullptr;
+    int rc = check_desc(c);
+    if (rc)
+        return rc;
+    if (!d_workspace)
+        return IBM_EINVAL;
+    HostGeom h;
+    rc = host_geom(c, h);
+    if (rc)
+        return rc;
+    Layout L;
+    size_t need = carve(c, h, nullptr, L);
+    if (bytes < need)
+        return IBM_ENOSPACE;
+    carve(c, h, static_cast<char *>(d_workspace), L);
+    ibm_ctx *x = new (std::nothrow) ibm_ctx();
+    if (!x)
+        return IBM_EINVAL;
+    std::memset(x->err, 0, sizeof x->err);
+    if (hipGetDevice(&x->device) != hipSuccess)
+        x->device = -1;
+    int nd = c->ndim;
+    Grid &g = x->g;
+    g.ndim = nd;
+    g.ni = c->ni;
+    g.nj = c->nj;
+    g.nk = h.n[2];
+    g.nv = nd + 2;
+    g.hz = h.hz;
+    g.sx = h.sx;
+    g.sy = h.sy;
+    g.sz = h.sz;
+    g.vs = h.vs;
+    g.ncell = h.ncell;
+    for (int s = 0; s < 6; ++s)
+        g.bc[s] = c->bc[s];
+    hipError_t e = hipSuccess;
+    for (int d = 0; d < 3; ++d) {
+        g.xc[d] = L.xc[d];
+        g.xf[d] = L.xf[d];
+        g.rdx[d] = L.rdx[d];
+        g.rdxc[d] = L.rdxc[d];
+        g.rdtc[d] = L.rdtc[d];
+        g.rdx_f[d] = L.rdx_f[d];
+        g.rdxc_f[d] = L.rdxc_f[d];
+        g.rdtc_f[d] = L.rdtc_f[d];
+        g.Xc[d] = L.Xc[d];
+        if (e == hipSuccess) e = up(L.xc[d], h.xc[d]);
+        if (e == hipSuccess) e = up(L.xf[d], h.xf[d]);
+        if (e == hipSuccess) e = up(L.rdx[d], h.rdx[d]);
+        if (e == hipSuccess) e = up(L.rdxc[d], h.rdxc[d]);
+        if (e == hipSuccess) e = up(L.rdtc[d], h.rdtc[d]);
+        if (e == hipSuccess) e = up(L.rdx_f[d], h.rdx_f[d]);
+        if (e == hipSuccess) e = up(L.rdxc_f[d], h.rdxc_f[d]);
+        if (e == hipSuccess) e = up(L.rdtc_f[d], h.rdtc_f[d]);
+        if (e == hipSuccess) e = up(L.Xc[d], h.Xc[d]);
+    }
+    Body &b = x->b;
+    b.nvert = c->nvert;
+    b.nfacet = c->nfacet;
+    b.nedge = h.nedge;
+    b.V0 = L.V0;
+    b.V = L.V;
+    b.v = L.v;
+    b.facet = L.facet;
+    b.fnrm = L.fnrm;
+    b.vnrm = L.vnrm;
+    b.enrm = L.enrm;
+    b.edge_of = L.edge_of;
+    if (e == hipSuccess) e = up(L.V0, h.V0);
+    if (e == hipSuccess) e = up(L.V, h.V0);
+    if (e == hipSuccess) e = up(L.v, h.v0);
+    if (e == hipSuccess && c->nfacet > 0) e = up(L.facet, h.facet);
+    if (e == hipSuccess) e = up(L.fnrm, h.fnrm);
+    if (e == hipSuccess) e = up(L.vnrm, h.vnrm);
+    if (e == hipSuccess && !h.enrm.empty()) e = up(L.enrm, h.enrm);
+    if (e == hipSuccess && !h.edge_of.empty()) e = up(L.edge_of, h.edge_of);
+
+    Flow &f = x->f;
+    f.gamma = c->gamma;
+    f.pinf = 1.0 / (c->gamma * c->mach * c->mach);
+    f.R = f.pinf;
+    f.cp = c->gamma * f.R / (c->gamma - 1.0);
+    f.mu = 1.0 / c->reynolds;
+    f.kc = f.mu * f.cp / c->prandtl;
+    f.pr = c->prandtl;
+    f.Hinf = c->gamma / (c->gamma - 1.0) * f.pinf + 0.5;
+    f.dt = c->dt;
+    f.cfl_tau = c->cfl_tau;
+    f.scheme = c->scheme;
+    f.family = c->ib_family;
+    f.precision = c->precision;
+    {
+        // preconditioning cut-off: U_c^2 = max(U_inf^2, (nu/h)^2, (h/(pi dt))^2)
+        double hmin = 1e300;
+        for (int d = 0; d < nd; ++d)
+            for (int i = 0; i < h.n[d]; ++i)
+                hmin = std::min(hmin, h.xf[d][i + 4] - h.xf[d][i + 3]);
+        double a = 1.0, bb = f.mu / hmin, cc = hmin / (M_PI * c->dt);
+        f.uc2 = std::max(a * a, std::max(bb * bb, cc * cc));
+    }
+    IB &ib = x->ib;
+    for (int s = 0; s < 6; ++s)
+        ib.region[s] = h.region[s];
+    ib.rw = h.region[1] - h.region[0];
+    ib.rh = h.region[3] - h.region[2];
+    ib.rd = h.region[5] - h.region[4];
+    if (h.cap == 0)
+        ib.rw = ib.rh = ib.rd = 0;
+    ib.words_per_row = h.wpr;
+    ib.cap = h.cap;
+    ib.cls = L.cls;
+    ib.inside = L.inside;
+    ib.toggle = L.toggle;
+    ib.counts = L.counts;
+    ib.blk = L.blk;
+    ib.nblk = h.nblk;
+    ib.listF = L.listF;
+    ib.listG = L.listG;
+    ib.rec_i = L.rec_i;
+    ib.rec_d = L.rec_d;
+    if (e == hipSuccess) e = hipMemset(L.cls, IBM_FLUID, (size_t)h.ncell);
+    if (e == hipSuccess) e = hipMemset(L.counts, 0, sizeof(int32_t) * CNT_WORDS);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    x->mo.on = c->motion != 0;
+    x->mo.axis = c->motion ? (int)c->motion_par[0] : 0;
+    x->mo.amp = c->motion_par[1];
+    x->mo.freq = c->motion_par[2];
+    x->mo.phase = c->motion_par[3];
+    x->q1 = L.q1;
+    x->q2 = L.q2;
+    x->wtmp = L.wtmp;
+    x->qn = L.qn;
+    x->qnm1 = L.qnm1;
+    x->t = 0.0;
+    x->step = 0;
+    x->n_inner = c->n_inner;
+    x->classified = false;
+    if (e != hipSuccess) {
+        delete x;
+        return IBM_EDEVICE;
+    }
+    *out = x;
+    return IBM_OK;
+}
+
+void ibm_destroy(ibm_ctx *c) { delete c; }
+
+int ibm_set_time(ibm_ctx *c, double t)
+{
+    if (!c || !std::isfinite(t))
+        return IBM_EINVAL;
+    c->t = t;
+    return IBM_OK;
+}
+
+int ibm_classify(ibm_ctx *c, void *stream)
+{
+    if (!c)
+        return IBM_EINVAL;
+    return do_classify(c, c->t, S(stream));
+}
+
+int ibm_fill(ibm_ctx *c, double *q, double t, void *stream)
+{
+    if (!c || !q)
+        return IBM_EINVAL;
+    if (!c->classified) {
+        int rc = do_classify(c, c->t, S(stream));
+        if (rc)
+            return rc;
+    }
+    return do_fill(c, q, t, S(stream));
+}
+
+int ibm_residual(ibm_ctx *c, const double *q, double *r, void *stream)
+{
+    if (!c || !q || !r)
+        return IBM_EINVAL;
+    if (!c->classified) {
+        int rc = do_classify(c, c->t, S(stream));
+        if (rc)
+            return rc;
+    }
+    return dev_err(c, launch_residual(c->g, c->f, c->ib, q, r, S(stream)), "residual");
+}
+
+int ibm_advance(ibm_ctx *c, double *q, int nsteps, void *stream)
+{
+    if (!c || !q || nsteps < 0)
+        return IBM_EINVAL;
+    hipStream_t s = S(stream);
+    int rc;
+    double dt = c->f.dt;
+    for (int n = 0; n < nsteps; ++n) {
+        if (c->f.scheme == IBM_RK3) {
+            // SSP-RK3 (Shu-Osher); moving bodies are posed at t^n
+            double t = c->t;
+            if (c->mo.on || !c->classified)
+                if ((rc = do_classify(c, t, s)))
+                    return rc;
+            if ((rc = do_fill(c, q, t, s)))
+                return rc;
+            if ((rc = dev_err(c, launch_rk_stage(c->g, c->f, c->ib, q, q, c->q1, 0.0, 1.0, s), "stage 1")))
+                return rc;
+            if ((rc = do_fill(c, c->q1, t + dt, s)))
+                return rc;
+            if ((rc = dev_err(c, launch_rk_stage(c->g, c->f, c->ib, q, c->q1, c->q2, 0.75, 0.25, s), "stage 2")))
+                return rc;
+            if ((rc = do_fill(c, c->q2, t + 0.5 * dt, s)))
+                return rc;
+            if ((rc = dev_err(c, launch_rk_stage(c->g, c->f, c->ib, q, c->q2, q, 1.0 / 3.0, 2.0 / 3.0, s), "stage 3")))
+                return rc;
+            c->t = t + dt;
+        } else {
+            // dual time: BDF1 on the first physical step, BDF2 after; the
+            // body is posed at t^{n+1} and frozen over the pseudo-iterations
+            double tn = c->t + dt;
+            if (c->mo.on || !c->classified)
+                if ((rc = do_classify(c, tn, s)))
+                    return rc;
+            int first = c->step == 0;
+            if ((rc = dev_err(c, launch_dual_begin(c->g, c->f, q, c->qn, c->qnm1, first, s), "dual begin")))
+                return rc;
+            double b0 = first ? 1.0 : 1.5, b2 = first ? 0.0 : 0.5;
+            double *cur = q, *nxt = c->wtmp;
+            for (int it = 0; it < c->n_inner; ++it) {
+                if ((rc = do_fill(c, cur, tn, s)))
+                    return rc;
+                if ((rc = dev_err(c, launch_dual_iter(c->g, c->f, c->ib, cur, nxt, c->qn, c->qnm1, b0, b2, s), "dual iteration")))
+                    return rc;
+                double *tmp = cur;
+                cur = nxt;
+                nxt = tmp;
+            }
+            if (cur != q)
+                if ((rc = dev_err(c, launch_copy_state(c->g, cur, q, s), "copy")))
+                    return rc;
+            c->t = tn;
+        }
+        c->step++;
+    }
+    return IBM_OK;
+}
+
+int ibm_init_state(ibm_ctx *c, const double *prim, double *q, void *stream)
+{
+    if (!c || !prim || !q)
+        return IBM_EINVAL;
+    return dev_err(c, launch_prim_to_state(c->g, c->f, prim, q, S(stream)), "init state");
+}
+
+int ibm_state_to_prim(ibm_ctx *c, const double *q, double *prim, void *stream)
+{
+    if (!c || !prim || !q)
+        return IBM_EINVAL;
+    return dev_err(c, launch_state_to_prim(c->g, c->f, q, prim, S(stream)), "state to prim");
+}
+
+int ibm_read_counts(ibm_ctx *c, int32_t *host_counts, void *stream)
+{
+    if (!c || !host_counts)
+        return IBM_EINVAL;
+    hipError_t e = hipMemcpyAsync(host_counts, c->ib.counts, sizeof(int32_t) * CNT_WORDS,
+                                  hipMemcpyDeviceToHost, S(stream));
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(S(stream));
+    return dev_err(c, e, "read counts");
+}
+
+int ibm_status(ibm_ctx *c, void *stream)
+{
+    if (!c)
+        return IBM_EINVAL;
+    int32_t cnt[CNT_WORDS];
+    int rc = ibm_read_counts(c, cnt, stream);
+    if (rc)
+        return rc;
+    if (cnt[CNT_STATUS] & ST_CAPACITY)
+        return set_err(c, IBM_ECAPACITY, "more immersed-boundary nodes than the workspace holds");
+    if (cnt[CNT_STATUS] & ST_NONFINITE)
+        return set_err(c, IBM_ENONFINITE, "non-finite state or non-positive density in a fluid cell");
+    return IBM_OK;
+}
+
+int ibm_info_get(const ibm_ctx *c, ibm_info *o)
+{
+    if (!c || !o)
+        return IBM_EINVAL;
+    o->ndim = c->g.ndim;
+    o->ni = c->g.ni;
+    o->nj = c->g.nj;
+    o->nk = c->g.nk;
+    o->nv = c->g.nv;
+    o->state_elems = c->g.vs * c->g.nv;
+    o->ncell = c->g.ncell;
+    o->cap_nodes = c->ib.cap;
+    for (int s = 0; s < 6; ++s)
+        o->region[s] = c->ib.region[s];
+    o->cls = c->ib.cls;
+    o->counts = c->ib.counts;
+    o->list_forcing = c->ib.listF;
+    o->list_ghost = c->ib.listG;
+    o->rec_int = c->ib.rec_i;
+    o->rec_dbl = c->ib.rec_d;
+    o->time = c->t;
+    return IBM_OK;
+}
+
+const char *ibm_last_error(const ibm_ctx *c) { return c ? c->err : "null context"; }
+
+int ibm_time_update_kernel(ibm_ctx *c, const double *q, int stage, int nrep, void *stream,
+                           float *avg_ms)
+{
+    if (!c || !q || !avg_ms || nrep < 1)
+        return IBM_EINVAL;
+    hipStream_t s = S(stream);
+    if (!c->classified) {
+        int rc = do_classify(c, c->t, s);
+        if (rc)
+            return rc;
+    }
+    bool rk = c->f.scheme == IBM_RK3;
+    if (rk && (stage < 1 || stage > 3))
+        return IBM_EINVAL;
+    static const double A[4] = {0.0, 0.0, 0.75, 1.0 / 3.0}, B[4] = {0.0, 1.0, 0.25, 2.0 / 3.0};
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess)
+        e = hipEventCreate(&e1);
+    if (e != hipSuccess)
+        return dev_err(c, e, "event create");
+    if (!rk)
+        e = launch_dual_begin(c->g, c->f, q, c->qn, c->qnm1, 1, s);
+    if (e == hipSuccess)
+        e = hipEventRecord(e0, s);
+    for (int r = 0; r < nrep && e == hipSuccess; ++r)
+        e = rk ? launch_rk_stage(c->g, c->f, c->ib, q, q, c->q1, A[stage], B[stage], s)
+               : launch_dual_iter(c->g, c->f, c->ib, q, c->wtmp, c->qn, c->qnm1, 1.0, 0.0, s);
+    if (e == hipSuccess)
+        e = hipEventRecord(e1, s);
+    if (e == hipSuccess)
+        e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_ms = ms / nrep;
+    return dev_err(c, e, "time kernel");
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+// Internal structures shared by the host orchestration (api.cpp) and the
+// HIP kernels (geometry.hip, flow.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ibm.h"
+
+namespace ibm {
+
+constexpr double kLatScale = 16777216.0;  // 2^24: lattice of the exact predicates
+constexpr int kRecI = IBM_REC_INT;
+constexpr int kRecD = IBM_REC_DBL;
+
+// counts[] words on the device
+enum { CNT_F = 0, CNT_G1 = 1, CNT_G2 = 2, CNT_G3 = 3, CNT_G = 4, CNT_STATUS = 5,
+       CNT_FB_PPRIME = 6, CNT_FB_PROBE = 7, CNT_WORDS = 8 };
+enum { ST_NONFINITE = 1, ST_CAPACITY = 2 };
+
+// Grid description in device memory.  Extended per-axis arrays hold the
+// three halo cells on each side: centre index i lives at [i + 3].
+struct Grid {
+    int ndim, ni, nj, nk, nv, hz;
+    int sx, sy, sz;          // extended sizes
+    long long vs;            // doubles per state variable
+    long long ncell;         // interior cells
+    int bc[6];
+    const double *xc[3];     // extended centres (n + 6)
+    const double *xf[3];     // extended faces (n + 7), face f at [f + 3]
+    const double *rdx[3];    // 1 / cell width, extended (n + 6)
+    const double *rdxc[3];   // 1 / (xc[i+1] - xc[i]), index [i + 3]
+    const double *rdtc[3];   // 1 / (xc[i+1] - xc[i-1]), index [i + 3]
+    const float *rdx_f[3], *rdxc_f[3], *rdtc_f[3];
+    const long long *Xc[3];  // lattice centres, interior
+};
+
+struct Body {
+    int nvert, nfacet, nedge;
+    const long long *V0;     // lattice vertices at rest (nvert * ndim)
+    long long *V;            // posed lattice vertices
+    double *v;               // posed vertices (exact V / 2^24)
+    const int *facet;        // nfacet * ndim
+    const double *fnrm;      // nfacet * 3
+    const double *vnrm;      // nvert * 3
+    const double *enrm;      // nedge * 3 (3D)
+    const int *edge_of;      // nfacet * 3 (3D): global edge id per facet edge
+};
+
+struct Flow {
+    double gamma, pinf, R, cp, mu, kc, pr, uc2, Hinf, dt, cfl_tau;
+    int scheme, family, precision;
+};
+
+// Immersed-boundary work area.
+struct IB {
+    int region[6];           // [i0,i1) [j0,j1) [k0,k1)
+    int rw, rh, rd;          // region extents
+    int words_per_row;       // toggle bitmask words per region row
+    int cap;                 // capacity of each list and of the records
+    uint8_t *cls;            // class per interior cell
+    uint8_t *inside;         // inside flag per region cell
+    uint32_t *toggle;        // crossing toggles per region row
+    int32_t *counts;         // CNT_* words
+    int32_t *blk;            // per-block counts for the compaction scan (2 * nblk)
+    int nblk;
+    int32_t *listF, *listG;
+    int32_t *rec_i;          // cap * kRecI
+    double *rec_d;           // cap * kRecD
+};
+
+struct Motion {
+    int on, axis;
+    double amp, freq, phase;
+};
+
+// ------------------------------------------------------------ launchers
+// geometry.hip
+hipError_t launch_pose(const Grid &g, Body &b, long long disp, int axis, hipStream_t s);
+hipError_t launch_classify(const Grid &g, const Body &b, IB &ib, hipStream_t s);
+hipError_t launch_records(const Grid &g, const Body &b, const Flow &f, IB &ib, hipStream_t s);
+
+// flow.hip
+hipError_t launch_domain_bc(const Grid &g, const Flow &f, double *q, hipStream_t s);
+hipError_t launch_fill(const Grid &g, const Flow &f, const IB &ib, double *q, double ub_axis,
+                       double ab_axis, int axis, hipStream_t s);
+hipError_t launch_residual(const Grid &g, const Flow &f, const IB &ib, const double *q, double *r,
+                           hipStream_t s);
+hipError_t launch_rk_stage(const Grid &g, const Flow &f, const IB &ib, const double *qn,
+                           const double *qin, double *qout, double a, double b, hipStream_t s);
+hipError_t launch_dual_iter(const Grid &g, const Flow &f, const IB &ib, const double *w,
+                            double *wout, const double *qn, const double *qnm1, double b0,
+                            double b2, hipStream_t s);
+hipError_t launch_dual_begin(const Grid &g, const Flow &f, const double *w, double *qn,
+                             double *qnm1, int first, hipStream_t s);
+hipError_t launch_prim_to_state(const Grid &g, const Flow &f, const double *prim, double *q,
+                                hipStream_t s);
+hipError_t launch_state_to_prim(const Grid &g, const Flow &f, const double *q, double *prim,
+                                hipStream_t s);
+hipError_t launch_copy_state(const Grid &g, const double *src, double *dst, hipStream_t s);
+
+}  // namespace ibm

@@ -1,0 +1,944 @@
+// Flow kernels for gfx950: domain ghost layers, immersed-boundary fill, and
+// the fused residual + update (WENO5, low-diffusion flux splitting with
+// low-Mach preconditioning, central viscous fluxes; SSP-RK3 or
+// preconditioned dual time stepping) of Seshadri & De, sections 2 and 4.4-5.
+//
+// The residual works on perturbation variables rho' = rho - 1,
+// p' = p - p_inf, T' = T - 1 in a template precision Real (double for the
+// FP64 path, float for the mixed path): the mean pressure's contribution
+// cancels exactly over a closed cell, and the energy residual is split as
+// R_E = H_inf R_rho + R_E' (H_inf the free-stream total enthalpy), so no
+// O(p_inf) quantity is ever rounded to Real.  Conserved updates and the
+// recovery of (rho', p', T') from the state are FP64.
+#include "common.h"
+
+namespace ibm {
+namespace {
+
+constexpr int kBlock = 256;
+
+inline int blocks_for(long long n, int bs) { return (int)((n + bs - 1) / bs); }
+
+template <typename R> __device__ inline R rcp_fast(R x);
+template <> __device__ inline double rcp_fast<double>(double x) { return 1.0 / x; }
+template <> __device__ inline float rcp_fast<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ inline long long sidx(const Grid &g, int i, int j, int k)
+{
+    return ((long long)(k + g.hz) * g.sy + (j + 3)) * g.sx + (i + 3);
+}
+
+// State -> primitive (FP64).  RK3: conserved; dual time: (p', u, v[, w], T').
+struct PrimD {
+    double rho, u[3], p, T;
+};
+
+__device__ inline PrimD load_prim(const Grid &g, const Flow &f, const double *q, long long s)
+{
+    PrimD w;
+    int nd = g.ndim;
+    w.u[0] = w.u[1] = w.u[2] = 0.0;
+    if (f.scheme == IBM_RK3) {
+        w.rho = q[s];
+        double ke = 0.0;
+        for (int d = 0; d < nd; ++d) {
+            w.u[d] = q[s + (1 + d) * g.vs] / w.rho;
+            ke += w.u[d] * w.u[d];
+        }
+        w.p = (f.gamma - 1.0) * (q[s + (nd + 1) * g.vs] - 0.5 * w.rho * ke);
+        w.T = w.p / (w.rho * f.R);
+    } else {
+        w.p = f.pinf + q[s];
+        for (int d = 0; d < nd; ++d)
+            w.u[d] = q[s + (1 + d) * g.vs];
+        w.T = 1.0 + q[s + (nd + 1) * g.vs];
+        w.rho = w.p / (f.R * w.T);
+    }
+    return w;
+}
+
+__device__ inline void store_prim(const Grid &g, const Flow &f, const PrimD &w, double *q,
+                                  long long s)
+{
+    int nd = g.ndim;
+    if (f.scheme == IBM_RK3) {
+        double ke = 0.0;
+        for (int d = 0; d < nd; ++d)
+            ke += w.u[d] * w.u[d];
+        q[s] = w.rho;
+        for (int d = 0; d < nd; ++d)
+            q[s + (1 + d) * g.vs] = w.rho * w.u[d];
+        q[s + (nd + 1) * g.vs] = w.p / (f.gamma - 1.0) + 0.5 * w.rho * ke;
+    } else {
+        q[s] = w.p - f.pinf;
+        for (int d = 0; d < nd; ++d)
+            q[s + (1 + d) * g.vs] = w.u[d];
+        q[s + (nd + 1) * g.vs] = w.T - 1.0;
+    }
+}
+
+// ------------------------------------------------------ domain ghosts
+// Three ghost layers per side: FARFIELD = free stream, EXTRAP = nearest
+// interior cell, PERIODIC = wrap; corner ghosts resolve the later axis
+// first (the x, then y, then z sweep order).
+struct FreeStream {
+    double v[5];
+};
+
+__device__ inline void halo_cell(const Grid &g, long long t, int &i, int &j, int &k)
+{
+    if (g.ndim == 2) {
+        long long band = 3LL * g.sx;
+        k = 0;
+        if (t < 2 * band) {
+            int top = t >= band;
+            long long r = t - top * band;
+            j = (int)(r / g.sx) + (top ? g.nj : -3);
+            i = (int)(r % g.sx) - 3;
+            return;
+        }
+        t -= 2 * band;
+        j = (int)(t / 6);
+        int c = (int)(t % 6);
+        i = c < 3 ? c - 3 : g.ni + (c - 3);
+        return;
+    }
+    long long zb = 3LL * g.sx * g.sy;
+    if (t < 2 * zb) {
+        int top = t >= zb;
+        long long r = t - top * zb;
+        k = (int)(r / ((long long)g.sx * g.sy)) + (top ? g.nk : -3);
+        r %= (long long)g.sx * g.sy;
+        j = (int)(r / g.sx) - 3;
+        i = (int)(r % g.sx) - 3;
+        return;
+    }
+    t -= 2 * zb;
+    long long yb = 6LL * g.sx;
+    if (t < yb * g.nk) {
+        k = (int)(t / yb);
+        long long r = t % yb;
+        int top = r >= 3LL * g.sx;
+        r -= top * 3LL * g.sx;
+        j = (int)(r / g.sx) + (top ? g.nj : -3);
+        i = (int)(r % g.sx) - 3;
+        return;
+    }
+    t -= yb * g.nk;
+    k = (int)(t / (6LL * g.nj));
+    long long r = t % (6LL * g.nj);
+    j = (int)(r / 6);
+    int c = (int)(r % 6);
+    i = c < 3 ? c - 3 : g.ni + (c - 3);
+}
+
+__global__ void bc_kernel(Grid g, FreeStream fs, double *q, long long nhalo)
+{
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nhalo)
+        return;
+    int i, j, k;
+    halo_cell(g, t, i, j, k);
+    int c[3] = {i, j, k}, n[3] = {g.ni, g.nj, g.nk};
+    bool farfield = false;
+    for (int ax = g.ndim - 1; ax >= 0; --ax) {
+        if (c[ax] >= 0 && c[ax] < n[ax])
+            continue;
+        int type = g.bc[2 * ax + (c[ax] < 0 ? 0 : 1)];
+        if (type == IBM_BC_FARFIELD) {
+            farfield = true;
+            break;
+        }
+        if (type == IBM_BC_EXTRAP)
+            c[ax] = c[ax] < 0 ? 0 : n[ax] - 1;
+        else
+            c[ax] = c[ax] < 0 ? c[ax] + n[ax] : c[ax] - n[ax];
+    }
+    long long dst = sidx(g, i, j, k);
+    long long src = sidx(g, c[0], c[1], c[2]);
+    for (int v = 0; v < g.nv; ++v)
+        q[dst + v * g.vs] = farfield ? fs.v[v] : q[src + v * g.vs];
+}
+
+// ------------------------------------------------------------ IB fill
+// Boundary conditions along the local-normal line (section 4.4): velocity
+// Dirichlet = body velocity (eq.4); dp/dn = -rho n . a_body (eqs 5-6);
+// dT/dn = 0 (eq.8).  Linear family: linear profile through the wall value
+// (Dirichlet) or slope (Neumann) and the probe; quadratic family: profile
+// through two probes (sections 4.5-4.6 and 5).  s = 0 at P', s > 0 in the
+// fluid; the node sits at s_X.
+__device__ inline void probe_value(const Grid &g, const Flow &f, const double *q, const int *ids,
+                                   const double *w, double *phi)
+{
+    int nd = g.ndim;
+    for (int v = 0; v < nd + 2; ++v)
+        phi[v] = 0.0;
+    for (int m = 0; m < (1 << nd); ++m) {
+        if (ids[m] < 0 || w[m] == 0.0)
+            continue;
+        int c = ids[m];
+        int i = c % g.ni, j = (c / g.ni) % g.nj, k = c / (g.ni * g.nj);
+        PrimD p = load_prim(g, f, q, sidx(g, i, j, k));
+        phi[0] += w[m] * p.p;
+        for (int d = 0; d < nd; ++d)
+            phi[1 + d] += w[m] * p.u[d];
+        phi[nd + 1] += w[m] * p.T;
+    }
+}
+
+__global__ void fill_kernel(Grid g, Flow f, IB ib, double *q, int which, double ub, double ab,
+                            int axis)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int nF = min(ib.counts[CNT_F], ib.cap);
+    int nG = min(ib.counts[CNT_G], ib.cap - nF);
+    int r = which == 0 ? t : nF + t;
+    if (t >= (which == 0 ? nF : nG))
+        return;
+    int nd = g.ndim;
+    bool quad = f.family == IBM_IB_QUADRATIC;
+    const int *ir = ib.rec_i + (long long)kRecI * r;
+    const double *dr = ib.rec_d + (long long)kRecD * r;
+    double ubv[3] = {0.0, 0.0, 0.0}, abv[3] = {0.0, 0.0, 0.0};
+    if (axis >= 0) {
+        ubv[axis] = ub;
+        abv[axis] = ab;
+    }
+    const double *n = dr;
+    double sx = dr[6], s1 = dr[7], s2 = dr[8];
+    PrimD res;
+    res.u[0] = res.u[1] = res.u[2] = 0.0;
+    if (ir[4] == 2) {
+        res.p = f.pinf;
+        res.T = 1.0;
+        for (int d = 0; d < nd; ++d)
+            res.u[d] = ubv[d];
+    } else {
+        double phi1[5], phi2[5];
+        probe_value(g, f, q, ir + 7, dr + 9, phi1);
+        double rho1 = phi1[0] / (f.R * phi1[nd + 1]);
+        double an = 0.0;
+        for (int d = 0; d < nd; ++d)
+            an += n[d] * abv[d];
+        double gp = -rho1 * an, gT = 0.0;
+        if (!quad || ir[5] == 2) {
+            for (int d = 0; d < nd; ++d)
+                res.u[d] = ubv[d] + (phi1[1 + d] - ubv[d]) * sx / s1;
+            res.p = phi1[0] + gp * (sx - s1);
+            res.T = phi1[nd + 1] + gT * (sx - s1);
+        } else {
+            probe_value(g, f, q, ir + 15, dr + 17, phi2);
+            double L0 = (sx - s1) * (sx - s2) / (s1 * s2);
+            double L1 = sx * (sx - s2) / (s1 * (s1 - s2));
+            double L2 = sx * (sx - s1) / (s2 * (s2 - s1));
+            for (int d = 0; d < nd; ++d)
+                res.u[d] = ubv[d] * L0 + phi1[1 + d] * L1 + phi2[1 + d] * L2;
+            double c2p = (phi2[0] - phi1[0] - gp * (s2 - s1)) / (s2 * s2 - s1 * s1);
+            double c0p = phi1[0] - gp * s1 - c2p * s1 * s1;
+            res.p = c0p + gp * sx + c2p * sx * sx;
+            double c2T = (phi2[nd + 1] - phi1[nd + 1] - gT * (s2 - s1)) / (s2 * s2 - s1 * s1);
+            double c0T = phi1[nd + 1] - gT * s1 - c2T * s1 * s1;
+            res.T = c0T + gT * sx + c2T * sx * sx;
+        }
+    }
+    res.rho = res.p / (f.R * res.T);
+    int c = ir[0];
+    int i = c % g.ni, j = (c / g.ni) % g.nj, k = c / (g.ni * g.nj);
+    store_prim(g, f, res, q, sidx(g, i, j, k));
+}
+
+// ------------------------------------------------ fused residual / update
+template <int DIM> struct TileCfg;
+template <> struct TileCfg<2> {
+    static constexpr int TX = 32, TY = 8, TZ = 1, HZ = 0;
+};
+template <> struct TileCfg<3> {
+    static constexpr int TX = 8, TY = 8, TZ = 4, HZ = 3;
+};
+
+enum { MODE_RESID = 0, MODE_RK3 = 1, MODE_DUAL = 2 };
+
+struct StepArgs {
+    Grid g;
+    Flow f;
+    const uint8_t *cls;
+    int32_t *counts;
+    const double *qin;   // state read by the stencils
+    const double *qn;    // RK3: Q^n (state layout); dual: Q'^n (interior layout)
+    const double *qnm1;  // dual: Q'^{n-1} (interior layout)
+    double *out;         // RK3/dual: next state; residual mode: R (interior)
+    double a, b;         // RK3 stage coefficients / dual b0, b2
+    int ntx, nty, ntz;
+};
+
+// WENO5 (Jiang-Shu, eps 1e-6, linear weights 0.1, 0.6, 0.3) left state at
+// i+1/2 from v(i-2..i+2).  The nonlinear weights are formed with a single
+// reciprocal: omega_k ~ d_k prod_{m != k} (eps + beta_m)^2.
+template <typename R>
+__device__ inline R weno5(R a, R b, R c, R d, R e)
+{
+    const R k13 = R(13.0 / 12.0), q = R(0.25), eps = R(1.0e-6);
+    R t0 = a - R(2) * b + c, u0 = a - R(4) * b + R(3) * c;
+    R t1 = b - R(2) * c + d, u1 = b - d;
+    R t2 = c - R(2) * d + e, u2 = R(3) * c - R(4) * d + e;
+    R s0 = eps + (k13 * t0 * t0 + q * u0 * u0);
+    R s1 = eps + (k13 * t1 * t1 + q * u1 * u1);
+    R s2 = eps + (k13 * t2 * t2 + q * u2 * u2);
+    s0 *= s0;
+    s1 *= s1;
+    s2 *= s2;
+    R a0 = R(0.1) * (s1 * s2), a1 = R(0.6) * (s0 * s2), a2 = R(0.3) * (s0 * s1);
+    R q0 = (R(2) * a - R(7) * b + R(11) * c);
+    R q1 = (-b + R(5) * c + R(2) * d);
+    R q2 = (R(2) * c + R(5) * d - e);
+    return (a0 * q0 + a1 * q1 + a2 * q2) * rcp_fast<R>(R(6) * (a0 + a1 + a2));
+}
+
+template <typename R> struct FlowR {
+    R gamma, gm1inv, pinf, mu, kc, uc2;
+    bool precond;
+};
+
+__device__ inline double sgn1(double m) { return m >= 0.0 ? 1.0 : -1.0; }
+__device__ inline float sgn1(float m) { return m >= 0.0f ? 1.0f : -1.0f; }
+
+// split-pressure coefficient D of Edwards' LDFSS(0) for Mach number m on the
+// left (+) or right (-) side
+template <typename R>
+__device__ inline R dsplit(R m, bool plus, bool &sub)
+{
+    R am = fabs(m);
+    sub = am < R(1);
+    if (!sub)
+        return plus ? (m >= R(0) ? R(1) : R(0)) : (m >= R(0) ? R(0) : R(1));
+    return plus ? R(0.25) * (m + R(1)) * (m + R(1)) * (R(2) - m)
+                : R(0.25) * (m - R(1)) * (m - R(1)) * (R(2) + m);
+}
+
+// D+ + D- - 1 without cancellation when both sides are subsonic
+template <typename R>
+__device__ inline R dsum_minus1(R mL, R mR, R dp, R dm, bool subL, bool subR)
+{
+    if (subL && subR)
+        return R(0.25) * (mL - mR) * (R(3) - (mL * mL + mL * mR + mR * mR));
+    return (dp + dm) - R(1);
+}
+
+// Section 2 inviscid flux, perturbation form; w = (rho', u.., p').  Reading:
+// LDFSS(0) with the Weiss-Smith preconditioned interface sound speed a~ in
+// the mass flux; the pressure split of the preconditioned flux uses the
+// unpreconditioned Mach numbers with its velocity-diffusion part scaled by
+// a~ / a_half.  Momentum flux excludes the constant p_inf; the energy slot
+// holds the H' part (total flux = H_inf * mass flux + this).
+template <typename R, int NV>
+__device__ inline void ldfss_pert(const R *wl, const R *wr, int d, const FlowR<R> &fp, R *fl_out)
+{
+    constexpr int ND = NV - 2;
+    R rl = R(1) + wl[0], rr = R(1) + wr[0];
+    R plp = wl[NV - 1], prp = wr[NV - 1];
+    R pl = fp.pinf + plp, pr = fp.pinf + prp;
+    R UL = wl[1 + d], UR = wr[1 + d];
+    R ql2 = R(0), qr2 = R(0);
+#pragma unroll
+    for (int e = 0; e < ND; ++e) {
+        ql2 += wl[1 + e] * wl[1 + e];
+        qr2 += wr[1 + e] * wr[1 + e];
+    }
+    R al = sqrt(fp.gamma * pl * rcp_fast<R>(rl)), ar = sqrt(fp.gamma * pr * rcp_fast<R>(rr));
+    R ah = R(0.5) * (al + ar);
+    R at = ah, eps = R(1);
+    if (fp.precond) {
+        R ah2 = ah * ah;
+        eps = fmin(R(1), fmax(R(0.5) * ql2 + R(0.5) * qr2, fp.uc2) * rcp_fast<R>(ah2));
+        if (eps < R(1)) {
+            R ub = R(0.5) * (UL + UR);
+            at = R(0.5) * sqrt((R(1) - eps) * (R(1) - eps) * ub * ub + R(4) * eps * ah2);
+        }
+    }
+    R rat = rcp_fast<R>(at);
+    R ML = UL * rat, MR = UR * rat;
+    R apl = R(0.5) * (R(1) + sgn1(ML)), amr = R(0.5) * (R(1) - sgn1(MR));
+    R bl = fabs(ML) < R(1) ? R(-1) : R(0), br = fabs(MR) < R(1) ? R(-1) : R(0);
+    R mpl = R(0.25) * (ML + R(1)) * (ML + R(1)), mmr = R(-0.25) * (MR - R(1)) * (MR - R(1));
+    R cp = apl * (R(1) + bl) * ML - bl * mpl;
+    R cm = amr * (R(1) + br) * MR - br * mmr;
+    R sq = sqrt(R(0.5) * (ML * ML + MR * MR)) - R(1);
+    R mh = R(0.25) * bl * br * sq * sq;
+    R dpp = plp - prp;
+    R ri = rcp_fast<R>(at * at);
+    R mhp = mh * (R(1) - (dpp + fabs(dpp)) * R(0.5) * rcp_fast<R>(rl) * ri);
+    R mhm = mh * (R(1) + (dpp - fabs(dpp)) * R(0.5) * rcp_fast<R>(rr) * ri);
+    R fl = at * rl * (cp - mhp), fr = at * rr * (cm + mhm);
+    R pf;
+    if (eps >= R(1)) {
+        bool sl, sr;
+        R dp = dsplit(ML, true, sl), dm = dsplit(MR, false, sr);
+        pf = dp * plp + dm * prp + fp.pinf * dsum_minus1(ML, MR, dp, dm, sl, sr);
+    } else {
+        R rah = rcp_fast<R>(ah);
+        R mL = UL * rah, mR = UR * rah;
+        bool sl, sr;
+        R eL = dsplit(mL, true, sl), eR = dsplit(mR, false, sr);
+        R pbp = R(0.5) * (plp + prp);
+        pf = pbp + R(0.5) * (eL - eR) * dpp + at * rah * (fp.pinf + pbp) * dsum_minus1(mL, mR, eL, eR, sl, sr);
+    }
+    fl_out[0] = fl + fr;
+#pragma unroll
+    for (int e = 0; e < ND; ++e)
+        fl_out[1 + e] = fl * wl[1 + e] + fr * wr[1 + e] + (e == d ? pf : R(0));
+    R g1 = fp.gamma * fp.gm1inv;
+    R hl = g1 * (plp - fp.pinf * wl[0]) * rcp_fast<R>(rl) + R(0.5) * (ql2 - R(1));
+    R hr = g1 * (prp - fp.pinf * wr[0]) * rcp_fast<R>(rr) + R(0.5) * (qr2 - R(1));
+    fl_out[NV - 1] = fl * hl + fr * hr;
+}
+
+template <int DIM, typename Real, int MODE>
+__global__ __launch_bounds__(kBlock) void step_kernel(StepArgs A)
+{
+    using C = TileCfg<DIM>;
+    constexpr int TX = C::TX, TY = C::TY, TZ = C::TZ, HZ = C::HZ;
+    constexpr int LX = TX + 6, LY = TY + 6, LZ = TZ + 2 * HZ;
+    constexpr int NV = DIM + 2;          // conserved variables
+    constexpr int NS = DIM + 3;          // rho', u.., p', T'
+    constexpr int LCELLS = LX * LY * LZ;
+    constexpr int NF0 = (TX + 1) * TY * TZ;
+    constexpr int NF1 = TX * (TY + 1) * TZ;
+    constexpr int NF2 = DIM == 3 ? TX * TY * (TZ + 1) : 0;
+    constexpr int NFACE = NF0 + NF1 + NF2;
+    __shared__ Real S[NS * LCELLS];
+    __shared__ Real F[NV * NFACE];
+
+    const Grid &g = A.g;
+    const Flow &f = A.f;
+    // tile id, spread so that consecutive tiles share an XCD (8 XCDs, blocks
+    // dispatched round-robin)
+    int nt = A.ntx * A.nty * A.ntz;
+    int b = blockIdx.x;
+    int tile = (nt % 8 == 0) ? (b % 8) * (nt / 8) + b / 8 : b;
+    int tx0 = tile % A.ntx, ty0 = (tile / A.ntx) % A.nty, tz0 = tile / (A.ntx * A.nty);
+    int i0 = tx0 * TX, j0 = ty0 * TY, k0 = tz0 * TZ;
+    int tid = threadIdx.x;
+
+    // 1. load the tile and its 3-cell halo, recovering (rho', u.., p', T')
+    for (int t = tid; t < LCELLS; t += kBlock) {
+        int lx = t % LX, ly = (t / LX) % LY, lz = t / (LX * LY);
+        int i = i0 + lx - 3, j = j0 + ly - 3, k = k0 + lz - HZ;
+        bool ok = i >= -3 && i < g.ni + 3 && j >= -3 && j < g.nj + 3 &&
+                  (DIM == 2 || (k >= -3 && k < g.nk + 3));
+        double v[NS];
+        if (ok) {
+            long long s = sidx(g, i, j, k);
+            if (f.scheme == IBM_RK3) {
+                double rho = A.qin[s];
+                double ke = 0.0;
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) {
+                    v[1 + d] = A.qin[s + (1 + d) * g.vs] / rho;
+                    ke += v[1 + d] * v[1 + d];
+                }
+                double p = (f.gamma - 1.0) * (A.qin[s + (DIM + 1) * g.vs] - 0.5 * rho * ke);
+                v[0] = rho - 1.0;
+                v[DIM + 1] = p - f.pinf;
+                v[DIM + 2] = p / (rho * f.R) - 1.0;
+            } else {
+                double pp = A.qin[s], tp = A.qin[s + (DIM + 1) * g.vs];
+#pragma unroll
+                for (int d = 0; d < DIM; ++d)
+                    v[1 + d] = A.qin[s + (1 + d) * g.vs];
+                v[0] = (pp - f.R * tp) / (f.R * (1.0 + tp));
+                v[DIM + 1] = pp;
+                v[DIM + 2] = tp;
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < NS; ++m)
+                v[m] = 0.0;
+            v[1] = 1.0;
+        }
+#pragma unroll
+        for (int m = 0; m < NS; ++m)
+            S[m * LCELLS + t] = (Real)v[m];
+    }
+    __syncthreads();
+
+    FlowR<Real> fp;
+    fp.gamma = (Real)f.gamma;
+    fp.gm1inv = (Real)(1.0 / (f.gamma - 1.0));
+    fp.pinf = (Real)f.pinf;
+    fp.mu = (Real)f.mu;
+    fp.kc = (Real)f.kc;
+    fp.uc2 = (Real)f.uc2;
+    fp.precond = f.scheme == IBM_DUAL;
+    const int strides[3] = {1, LX, LX * LY};
+    const int ext[3] = {g.ni, g.nj, g.nk};
+    const int org[3] = {i0, j0, k0};
+
+    // 2. face fluxes (all directions in one flat loop)
+    for (int fi = tid; fi < NFACE; fi += kBlock) {
+        int d, fx, fy, fz;
+        if (fi < NF0) {
+            d = 0;
+            fx = fi % (TX + 1);
+            fy = (fi / (TX + 1)) % TY;
+            fz = fi / ((TX + 1) * TY);
+        } else if (fi < NF0 + NF1) {
+            int r = fi - NF0;
+            d = 1;
+            fx = r % TX;
+            fy = (r / TX) % (TY + 1);
+            fz = r / (TX * (TY + 1));
+        } else {
+            int r = fi - NF0 - NF1;
+            d = 2;
+            fx = r % TX;
+            fy = (r / TX) % TY;
+            fz = r / (TX * TY);
+        }
+        // left cell of the face, tile-local
+        int lc[3] = {fx, fy, fz};
+        lc[d] -= 1;
+        int gc[3] = {i0 + lc[0], j0 + lc[1], k0 + lc[2]};
+        // needed only if both sides lie within [-1, n] along d and the
+        // transverse coordinates are interior
+        bool need = gc[d] >= -1 && gc[d] < ext[d];
+        for (int e = 0; e < DIM; ++e)
+            if (e != d && gc[e] >= ext[e])
+                need = false;
+        if (!need)
+            continue;
+        int base = (lc[0] + 3) + (lc[1] + 3) * LX + (DIM == 3 ? (lc[2] + HZ) * LX * LY : 0);
+        int sd = strides[d];
+        Real wl[NV], wr[NV];
+#pragma unroll
+        for (int m = 0; m < NV; ++m) {
+            const Real *s = S + m * LCELLS + base;
+            Real v0 = s[-2 * sd], v1 = s[-sd], v2 = s[0], v3 = s[sd], v4 = s[2 * sd], v5 = s[3 * sd];
+            wl[m] = weno5<Real>(v0, v1, v2, v3, v4);
+            wr[m] = weno5<Real>(v5, v4, v3, v2, v1);
+        }
+        Real flux[NV];
+        ldfss_pert<Real, NV>(wl, wr, d, fp, flux);
+
+        // viscous flux: central differences, face velocity the mean of the
+        // two cells, tangential gradients the mean of both cells' central
+        // differences
+        Real grad[DIM + 1][DIM];  // rows: u_0.., T; columns: derivative axis
+        const Real *SU = S + LCELLS;  // u_0 at var 1
+        const Real *ST = S + (DIM + 2) * LCELLS;
+        Real rdn = (Real)g.rdxc[d][gc[d] + 3];
+        if constexpr (sizeof(Real) == 4)
+            rdn = g.rdxc_f[d][gc[d] + 3];
+#pragma unroll
+        for (int m = 0; m < DIM; ++m)
+            grad[m][d] = (SU[m * LCELLS + base + sd] - SU[m * LCELLS + base]) * rdn;
+        grad[DIM][d] = (ST[base + sd] - ST[base]) * rdn;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) {
+            if (e == d)
+                continue;
+            int se = strides[e];
+            Real rl, rr;
+            if constexpr (sizeof(Real) == 4) {
+                rl = g.rdtc_f[e][gc[e] + 3];
+                rr = rl;
+            } else {
+                rl = (Real)g.rdtc[e][gc[e] + 3];
+                rr = rl;
+            }
+            (void)rr;
+#pragma unroll
+            for (int m = 0; m <= DIM; ++m) {
+                const Real *P = m < DIM ? SU + m * LCELLS : ST;
+                Real gl = (P[base + se] - P[base - se]) * rl;
+                Real gr = (P[base + sd + se] - P[base + sd - se]) * rl;
+                grad[m][e] = Real(0.5) * (gl + gr);
+            }
+        }
+        Real div = Real(0);
+#pragma unroll
+        for (int m = 0; m < DIM; ++m)
+            div += grad[m][m];
+        Real work = Real(0);
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) {
+            Real tau = fp.mu * (grad[m][d] + grad[d][m] - (m == d ? Real(2.0 / 3.0) * div : Real(0)));
+            Real uf = Real(0.5) * (SU[m * LCELLS + base] + SU[m * LCELLS + base + sd]);
+            flux[1 + m] -= tau;
+            work += uf * tau;
+        }
+        flux[NV - 1] -= work + fp.kc * grad[DIM][d];
+#pragma unroll
+        for (int m = 0; m < NV; ++m)
+            F[m * NFACE + fi] = flux[m];
+    }
+    __syncthreads();
+
+    // 3. per-cell residual and update
+    int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
+    int i = i0 + tx, j = j0 + ty, k = k0 + tz;
+    if (i >= g.ni || j >= g.nj || (DIM == 3 && k >= g.nk))
+        return;
+    long long cell = ((long long)k * g.nj + j) * g.ni + i;
+    uint8_t cls = A.cls[cell];
+    long long s = sidx(g, i, j, k);
+    if (MODE != MODE_RESID) {
+        if (cls == IBM_SOLID)
+            return;
+        if (cls != IBM_FLUID) {  // IB nodes carry their filled value
+#pragma unroll
+            for (int m = 0; m < NV; ++m)
+                A.out[s + m * g.vs] = A.qin[s + m * g.vs];
+            return;
+        }
+    } else if (cls != IBM_FLUID) {
+#pragma unroll
+        for (int m = 0; m < NV; ++m)
+            A.out[m * g.ncell + cell] = 0.0;
+        return;
+    }
+    int fl0 = (tz * TY + ty) * (TX + 1) + tx;        // x-face at i - 1/2
+    int fl1 = NF0 + (tz * (TY + 1) + ty) * TX + tx;  // y-face at j - 1/2
+    int fl2 = NF0 + NF1 + (tz * TY + ty) * TX + tx;  // z-face at k - 1/2
+    Real rd[3];
+    if constexpr (sizeof(Real) == 4) {
+        rd[0] = g.rdx_f[0][i + 3];
+        rd[1] = g.rdx_f[1][j + 3];
+        rd[2] = DIM == 3 ? g.rdx_f[2][k + 3] : Real(0);
+    } else {
+        rd[0] = (Real)g.rdx[0][i + 3];
+        rd[1] = (Real)g.rdx[1][j + 3];
+        rd[2] = DIM == 3 ? (Real)g.rdx[2][k + 3] : Real(0);
+    }
+    double R[NV];
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+        const Real *Fm = F + m * NFACE;
+        Real r = (Fm[fl0 + 1] - Fm[fl0]) * rd[0] + (Fm[fl1 + TX] - Fm[fl1]) * rd[1];
+        if (DIM == 3)
+            r += (Fm[fl2 + TX * TY] - Fm[fl2]) * rd[2];
+        R[m] = (double)r;
+    }
+    R[NV - 1] += f.Hinf * R[0];
+
+    if (MODE == MODE_RESID) {
+#pragma unroll
+        for (int m = 0; m < NV; ++m)
+            A.out[m * g.ncell + cell] = R[m];
+        return;
+    }
+    if (MODE == MODE_RK3) {
+        bool bad = false;
+#pragma unroll
+        for (int m = 0; m < NV; ++m) {
+            double qi = A.qin[s + m * g.vs];
+            double qv = A.b * (qi - f.dt * R[m]);
+            if (A.a != 0.0)
+                qv += A.a * A.qn[s + m * g.vs];
+            A.out[s + m * g.vs] = qv;
+            bad |= !isfinite(qv);
+            if (m == 0)
+                bad |= !(qv > 0.0);
+        }
+        if (bad)
+            atomicOr(&A.counts[CNT_STATUS], ST_NONFINITE);
+        return;
+    }
+    // MODE_DUAL: point-implicit preconditioned pseudo-time step, FP64
+    {
+        constexpr int N = NV;
+        double pp = A.qin[s], tp = A.qin[s + (DIM + 1) * g.vs];
+        double u[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+            u[d] = A.qin[s + (1 + d) * g.vs];
+        double p = f.pinf + pp, T = 1.0 + tp;
+        double rho = p / (f.R * T);
+        double rhop = (pp - f.R * tp) / (f.R * T);  // rho - 1
+        double q2 = 0.0;
+        for (int d = 0; d < DIM; ++d)
+            q2 += u[d] * u[d];
+        double a2 = f.gamma * p / rho;
+        double ur2 = fmin(a2, fmax(q2, f.uc2));
+        double eps = ur2 / a2;
+        double nuv = f.mu / rho * fmax(4.0 / 3.0, f.gamma / f.pr);
+        double dxs[3] = {1.0 / g.rdx[0][i + 3], 1.0 / g.rdx[1][j + 3],
+                         DIM == 3 ? 1.0 / g.rdx[2][k + 3] : 1.0};
+        double lam = 0.0;
+        for (int d = 0; d < DIM; ++d) {
+            double ud = u[d];
+            double up = 0.5 * (1.0 + eps) * fabs(ud);
+            double cpr = 0.5 * sqrt((1.0 - eps) * (1.0 - eps) * ud * ud + 4.0 * eps * a2);
+            lam += (up + cpr) / dxs[d] + 2.0 * nuv / (dxs[d] * dxs[d]);
+        }
+        double dtau = f.cfl_tau / lam;
+        double b0 = A.a, b2 = A.b;
+        double cdt = b0 / f.dt, ctau = 1.0 / dtau;
+        double rp = 1.0 / (f.R * T), rT = -rho / T;
+        double th = 1.0 / ur2 + 1.0 / (f.cp * T);
+        // perturbation conserved vector of the current state
+        double Qp[N];
+        Qp[0] = rhop;
+        for (int d = 0; d < DIM; ++d)
+            Qp[1 + d] = rhop * u[d] + (u[d] - (d == 0 ? 1.0 : 0.0));
+        Qp[N - 1] = pp / (f.gamma - 1.0) + 0.5 * (rhop * q2 + q2 - 1.0);
+        double rhs[N];
+        for (int m = 0; m < N; ++m) {
+            double qn = A.qn[m * g.ncell + cell], qm = A.qnm1[m * g.ncell + cell];
+            rhs[m] = -((b0 * (Qp[m] - qn) - b2 * (qn - qm)) / f.dt + R[m]);
+        }
+        // energy row minus H times the mass row: exact row operation that
+        // removes the O(H) terms (H' = c_p T' + (|u|^2 - 1) / 2)
+        double H = f.cp * T + 0.5 * q2;
+        double Hp = f.cp * tp + 0.5 * (q2 - 1.0);
+        {
+            double qn0 = A.qn[cell], qm0 = A.qnm1[cell];
+            double qnE = A.qn[(N - 1) * g.ncell + cell], qmE = A.qnm1[(N - 1) * g.ncell + cell];
+            double bdf0 = b0 * (Qp[0] - qn0) - b2 * (qn0 - qm0);
+            double bdfE = b0 * (Qp[N - 1] - qnE) - b2 * (qnE - qmE);
+            double Rrho = R[0], REp = R[N - 1] - f.Hinf * R[0];
+            rhs[N - 1] = -((bdfE - H * bdf0) / f.dt + (REp - Hp * Rrho));
+        }
+        double M[N][N];
+        for (int r = 0; r < N; ++r)
+            for (int c = 0; c < N; ++c)
+                M[r][c] = 0.0;
+        double cc = ctau + cdt;
+        M[0][0] = th * ctau + rp * cdt;
+        M[0][N - 1] = rT * cc;
+        for (int d = 0; d < DIM; ++d) {
+            M[1 + d][0] = u[d] * (th * ctau + rp * cdt);
+            M[1 + d][1 + d] = rho * cc;
+            M[1 + d][N - 1] = u[d] * rT * cc;
+            M[N - 1][1 + d] = rho * u[d] * cc;
+        }
+        M[N - 1][0] = -cc;
+        M[N - 1][N - 1] = rho * f.cp * cc;
+        (void)H;
+        // Gaussian elimination with partial pivoting
+        for (int c = 0; c < N; ++c) {
+            int piv = c;
+            for (int r = c + 1; r < N; ++r)
+                if (fabs(M[r][c]) > fabs(M[piv][c]))
+                    piv = r;
+            if (piv != c) {
+                for (int m = 0; m < N; ++m) {
+                    double t = M[c][m];
+                    M[c][m] = M[piv][m];
+                    M[piv][m] = t;
+                }
+                double t = rhs[c];
+                rhs[c] = rhs[piv];
+                rhs[piv] = t;
+            }
+            for (int r = c + 1; r < N; ++r) {
+                double fct = M[r][c] / M[c][c];
+                for (int m = c; m < N; ++m)
+                    M[r][m] -= fct * M[c][m];
+                rhs[r] -= fct * rhs[c];
+            }
+        }
+        for (int r = N - 1; r >= 0; --r) {
+            double sum = rhs[r];
+            for (int m = r + 1; m < N; ++m)
+                sum -= M[r][m] * rhs[m];
+            rhs[r] = sum / M[r][r];
+        }
+        bool bad = false;
+        for (int m = 0; m < N; ++m) {
+            double v = A.qin[s + m * g.vs] + rhs[m];
+            A.out[s + m * g.vs] = v;
+            bad |= !isfinite(v);
+        }
+        if (bad)
+            atomicOr(&A.counts[CNT_STATUS], ST_NONFINITE);
+    }
+}
+
+// Q'^{n-1} <- Q'^n (after the first step); Q'^n <- Q(W) - Q_inf
+__global__ void dual_begin_kernel(Grid g, Flow f, const double *w, double *qn, double *qnm1,
+                                  int first)
+{
+    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.ncell)
+        return;
+    int nd = g.ndim, N = g.nv;
+    int i = (int)(c % g.ni), j = (int)((c / g.ni) % g.nj), k = (int)(c / ((long long)g.ni * g.nj));
+    long long s = sidx(g, i, j, k);
+    double pp = w[s], tp = w[s + (nd + 1) * g.vs];
+    double u[3] = {0.0, 0.0, 0.0}, q2 = 0.0;
+    for (int d = 0; d < nd; ++d) {
+        u[d] = w[s + (1 + d) * g.vs];
+        q2 += u[d] * u[d];
+    }
+    double T = 1.0 + tp;
+    double rhop = (pp - f.R * tp) / (f.R * T);
+    double Q[5];
+    Q[0] = rhop;
+    for (int d = 0; d < nd; ++d)
+        Q[1 + d] = rhop * u[d] + (u[d] - (d == 0 ? 1.0 : 0.0));
+    Q[N - 1] = pp / (f.gamma - 1.0) + 0.5 * (rhop * q2 + q2 - 1.0);
+    for (int m = 0; m < N; ++m) {
+        if (!first)
+            qnm1[m * g.ncell + c] = qn[m * g.ncell + c];
+        qn[m * g.ncell + c] = Q[m];
+    }
+}
+
+__global__ void prim_to_state_kernel(Grid g, Flow f, const double *prim, double *q)
+{
+    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.ncell)
+        return;
+    int nd = g.ndim;
+    int i = (int)(c % g.ni), j = (int)((c / g.ni) % g.nj), k = (int)(c / ((long long)g.ni * g.nj));
+    PrimD w;
+    w.u[0] = w.u[1] = w.u[2] = 0.0;
+    w.rho = prim[c];
+    for (int d = 0; d < nd; ++d)
+        w.u[d] = prim[(1 + d) * g.ncell + c];
+    w.p = prim[(nd + 1) * g.ncell + c];
+    w.T = w.p / (w.rho * f.R);
+    store_prim(g, f, w, q, sidx(g, i, j, k));
+}
+
+__global__ void state_to_prim_kernel(Grid g, Flow f, const double *q, double *prim)
+{
+    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.ncell)
+        return;
+    int nd = g.ndim;
+    int i = (int)(c % g.ni), j = (int)((c / g.ni) % g.nj), k = (int)(c / ((long long)g.ni * g.nj));
+    PrimD w = load_prim(g, f, q, sidx(g, i, j, k));
+    prim[c] = w.rho;
+    for (int d = 0; d < nd; ++d)
+        prim[(1 + d) * g.ncell + c] = w.u[d];
+    prim[(nd + 1) * g.ncell + c] = w.p;
+}
+
+__global__ void copy_kernel(const double *src, double *dst, long long n)
+{
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n)
+        dst[t] = src[t];
+}
+
+template <int DIM, typename Real, int MODE>
+hipError_t run_step(const Grid &g, const Flow &f, const IB &ib, const double *qin,
+                    const double *qn, const double *qnm1, double *out, double a, double b,
+                    hipStream_t s)
+{
+    using C = TileCfg<DIM>;
+    StepArgs A;
+    A.g = g;
+    A.f = f;
+    A.cls = ib.cls;
+    A.counts = ib.counts;
+    A.qin = qin;
+    A.qn = qn;
+    A.qnm1 = qnm1;
+    A.out = out;
+    A.a = a;
+    A.b = b;
+    A.ntx = (g.ni + C::TX - 1) / C::TX;
+    A.nty = (g.nj + C::TY - 1) / C::TY;
+    A.ntz = DIM == 3 ? (g.nk + C::TZ - 1) / C::TZ : 1;
+    int nt = A.ntx * A.nty * A.ntz;
+    hipLaunchKernelGGL((step_kernel<DIM, Real, MODE>), dim3(nt), dim3(kBlock), 0, s, A);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t dispatch_step(const Grid &g, const Flow &f, const IB &ib, const double *qin,
+                         const double *qn, const double *qnm1, double *out, double a, double b,
+                         hipStream_t s)
+{
+    bool mixed = f.precision == IBM_MIXED;
+    if (g.ndim == 2)
+        return mixed ? run_step<2, float, MODE>(g, f, ib, qin, qn, qnm1, out, a, b, s)
+                     : run_step<2, double, MODE>(g, f, ib, qin, qn, qnm1, out, a, b, s);
+    return mixed ? run_step<3, float, MODE>(g, f, ib, qin, qn, qnm1, out, a, b, s)
+                 : run_step<3, double, MODE>(g, f, ib, qin, qn, qnm1, out, a, b, s);
+}
+
+}  // namespace
+
+hipError_t launch_domain_bc(const Grid &g, const Flow &f, double *q, hipStream_t s)
+{
+    FreeStream fs;
+    for (int m = 0; m < 5; ++m)
+        fs.v[m] = 0.0;
+    if (f.scheme == IBM_RK3) {
+        fs.v[0] = 1.0;
+        fs.v[1] = 1.0;
+        fs.v[g.nv - 1] = f.pinf / (f.gamma - 1.0) + 0.5;
+    } else {
+        fs.v[1] = 1.0;
+    }
+    long long nhalo = (long long)g.sx * g.sy * g.sz - g.ncell;
+    hipLaunchKernelGGL(bc_kernel, dim3(blocks_for(nhalo, kBlock)), dim3(kBlock), 0, s, g, fs, q,
+                       nhalo);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(const Grid &g, const Flow &f, const IB &ib, double *q, double ub_axis,
+                       double ab_axis, int axis, hipStream_t s)
+{
+    if (ib.cap == 0)
+        return hipSuccess;
+    int nb = blocks_for(ib.cap, 64);
+    hipLaunchKernelGGL(fill_kernel, dim3(nb), dim3(64), 0, s, g, f, ib, q, 0, ub_axis, ab_axis, axis);
+    hipLaunchKernelGGL(fill_kernel, dim3(nb), dim3(64), 0, s, g, f, ib, q, 1, ub_axis, ab_axis, axis);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const Grid &g, const Flow &f, const IB &ib, const double *q, double *r,
+                           hipStream_t s)
+{
+    return dispatch_step<MODE_RESID>(g, f, ib, q, nullptr, nullptr, r, 0.0, 0.0, s);
+}
+
+hipError_t launch_rk_stage(const Grid &g, const Flow &f, const IB &ib, const double *qn,
+                           const double *qin, double *qout, double a, double b, hipStream_t s)
+{
+    return dispatch_step<MODE_RK3>(g, f, ib, qin, qn, nullptr, qout, a, b, s);
+}
+
+hipError_t launch_dual_iter(const Grid &g, const Flow &f, const IB &ib, const double *w,
+                            double *wout, const double *qn, const double *qnm1, double b0,
+                            double b2, hipStream_t s)
+{
+    return dispatch_step<MODE_DUAL>(g, f, ib, w, qn, qnm1, wout, b0, b2, s);
+}
+
+hipError_t launch_dual_begin(const Grid &g, const Flow &f, const double *w, double *qn,
+                             double *qnm1, int first, hipStream_t s)
+{
+    hipLaunchKernelGGL(dual_begin_kernel, dim3(blocks_for(g.ncell, kBlock)), dim3(kBlock), 0, s, g,
+                       f, w, qn, qnm1, first);
+    return hipGetLastError();
+}
+
+hipError_t launch_prim_to_state(const Grid &g, const Flow &f, const double *prim, double *q,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(prim_to_state_kernel, dim3(blocks_for(g.ncell, kBlock)), dim3(kBlock), 0, s,
+                       g, f, prim, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_to_prim(const Grid &g, const Flow &f, const double *q, double *prim,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(state_to_prim_kernel, dim3(blocks_for(g.ncell, kBlock)), dim3(kBlock), 0, s,
+                       g, f, q, prim);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_state(const Grid &g, const double *src, double *dst, hipStream_t s)
+{
+    long long n = g.vs * g.nv;
+    hipLaunchKernelGGL(copy_kernel, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace ibm

@@ -1,0 +1,828 @@
+// Immersed-boundary geometry kernels for gfx950: body pose, ray-parity
+// classification, forcing/ghost tagging, list compaction and the per-node
+// reconstruction records (Seshadri & De, sections 3-4).
+//
+// Built with -ffp-contract=off: every floating-point decision taken here
+// (closest feature, boundary point, probe validity) must be reproducible
+// bit for bit, so no multiply-add is fused behind the source's back.
+#include "common.h"
+
+namespace ibm {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+
+__device__ inline int cell_index(const Grid &g, int i, int j, int k)
+{
+    return (k * g.nj + j) * g.ni + i;
+}
+
+// ------------------------------------------------------------------ pose
+// a1: translate the lattice body by an integer displacement along one axis;
+// the floating coordinates are the exact lattice values.
+__global__ void pose_kernel(int n, int ndim, const long long *V0, long long *V, double *v,
+                            long long disp, int axis)
+{
+    int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n * ndim)
+        return;
+    long long x = V0[m] + ((m % ndim) == axis ? disp : 0);
+    V[m] = x;
+    v[m] = (double)x / kLatScale;
+}
+
+// ---------------------------------------------------------- classification
+__global__ void clear_kernel(uint8_t *inside, int ncell, uint32_t *toggle, int nwords)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < ncell)
+        inside[t] = 0;
+    if (t < nwords)
+        toggle[t] = 0u;
+}
+
+// first index in [lo, hi) with X[idx] >= key (X increasing); hi if none
+__device__ inline int lower_bound_ll(const long long *X, int lo, int hi, long long key)
+{
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (X[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Section 3.2 ray casting, +x rays, exact lattice predicates.  A segment
+// a->b crosses the ray of node p iff (a_y > p_y) != (b_y > p_y) and the
+// crossing lies strictly right of p.  Rows crossed are those with
+// min(a_y, b_y) <= Y_j < max(a_y, b_y); in each, the crossed nodes form a
+// prefix of the row, found by binary search; one bit toggles at its end.
+__global__ void cross2d_kernel(Grid g, Body b, IB ib)
+{
+    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= b.nfacet)
+        return;
+    const long long *A = b.V + 2 * b.facet[2 * f];
+    const long long *B = b.V + 2 * b.facet[2 * f + 1];
+    if (A[1] == B[1])
+        return;  // horizontal: never satisfies the half-open rule
+    long long ylo = A[1] < B[1] ? A[1] : B[1];
+    long long yhi = A[1] < B[1] ? B[1] : A[1];
+    const long long *Y = g.Xc[1];
+    const long long *X = g.Xc[0];
+    int j0 = lower_bound_ll(Y, ib.region[2], ib.region[3], ylo);
+    int j1 = lower_bound_ll(Y, ib.region[2], ib.region[3], yhi);
+    long long dxab = B[0] - A[0], dyab = B[1] - A[1];
+    for (int j = j0; j < j1; ++j) {
+        long long py = Y[j];
+        // crossing strictly right of px <=> orient * sign(dy) > 0, which is
+        // true on a prefix of the row
+        int lo = ib.region[0], hi = ib.region[1];
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            long long o = dxab * (py - A[1]) - dyab * (X[mid] - A[0]);
+            bool right = dyab > 0 ? o > 0 : o < 0;
+            if (right)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        int pos = lo - ib.region[0];
+        int row = j - ib.region[2];
+        atomicXor(&ib.toggle[row * ib.words_per_row + (pos >> 5)], 1u << (pos & 31));
+    }
+}
+
+__device__ inline bool edge_owns(long long dy, long long dz) { return (dz == 0 && dy < 0) || dz > 0; }
+
+// 3D: a triangle counts for node (py, pz) iff the point lies in its (y, z)
+// projection (top-left tie rule; triangles parallel to the ray skipped) and
+// the crossing lies strictly ahead in +x (exact 128-bit arithmetic).
+__global__ void cross3d_kernel(Grid g, Body b, IB ib)
+{
+    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= b.nfacet)
+        return;
+    const int *t = b.facet + 3 * f;
+    const long long *P[3] = {b.V + 3 * t[0], b.V + 3 * t[1], b.V + 3 * t[2]};
+    long long area = (P[1][1] - P[0][1]) * (P[2][2] - P[0][2]) - (P[1][2] - P[0][2]) * (P[2][1] - P[0][1]);
+    if (area == 0)
+        return;
+    if (area < 0) {
+        const long long *tmp = P[1];
+        P[1] = P[2];
+        P[2] = tmp;
+    }
+    long long ylo = P[0][1], yhi = P[0][1], zlo = P[0][2], zhi = P[0][2];
+    for (int m = 1; m < 3; ++m) {
+        ylo = P[m][1] < ylo ? P[m][1] : ylo;
+        yhi = P[m][1] > yhi ? P[m][1] : yhi;
+        zlo = P[m][2] < zlo ? P[m][2] : zlo;
+        zhi = P[m][2] > zhi ? P[m][2] : zhi;
+    }
+    const long long *X = g.Xc[0], *Y = g.Xc[1], *Z = g.Xc[2];
+    int j0 = lower_bound_ll(Y, ib.region[2], ib.region[3], ylo);
+    int j1 = lower_bound_ll(Y, ib.region[2], ib.region[3], yhi + 1);
+    int k0 = lower_bound_ll(Z, ib.region[4], ib.region[5], zlo);
+    int k1 = lower_bound_ll(Z, ib.region[4], ib.region[5], zhi + 1);
+    for (int k = k0; k < k1; ++k)
+        for (int j = j0; j < j1; ++j) {
+            long long py = Y[j], pz = Z[k];
+            long long w[3];
+            bool ok = true;
+            for (int m = 0; m < 3; ++m) {
+                const long long *p = P[m], *q = P[(m + 1) % 3];
+                long long dy = q[1] - p[1], dz = q[2] - p[2];
+                w[m] = dy * (pz - p[2]) - dz * (py - p[1]);
+                if (w[m] < 0 || (w[m] == 0 && !edge_owns(dy, dz)))
+                    ok = false;
+            }
+            if (!ok)
+                continue;
+            // crossing ahead of px <=> sum_m w[m] (x_opp(m) - px) > 0; the
+            // sum decreases with px, so crossed nodes form a row prefix
+            __int128 base = 0, wsum = 0;
+            for (int m = 0; m < 3; ++m) {
+                base += (__int128)w[m] * (__int128)P[(m + 2) % 3][0];
+                wsum += (__int128)w[m];
+            }
+            int lo = ib.region[0], hi = ib.region[1];
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                __int128 s = base - wsum * (__int128)X[mid];
+                if (s > 0)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            int pos = lo - ib.region[0];
+            int row = (k - ib.region[4]) * ib.rh + (j - ib.region[2]);
+            atomicXor(&ib.toggle[row * ib.words_per_row + (pos >> 5)], 1u << (pos & 31));
+        }
+}
+
+// One wavefront per region row: a node is inside iff an odd number of
+// toggles sit at positions above it.  Suffix parity over words with a
+// wavefront ballot, processed from the high end in chunks of 64 words.
+__global__ void parity_kernel(IB ib, int nrows)
+{
+    int lane = threadIdx.x & (kWave - 1);
+    int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (row >= nrows)
+        return;
+    const uint32_t *T = ib.toggle + (long long)row * ib.words_per_row;
+    uint8_t *out = ib.inside + (long long)row * ib.rw;
+    int nw = ib.words_per_row;
+    int carry = 0;
+    for (int top = nw; top > 0; top -= kWave) {
+        int w = top - kWave + lane;  // this lane's word
+        uint32_t word = (w >= 0) ? T[w] : 0u;
+        int pw = __popc(word) & 1;
+        unsigned long long mask = __ballot(pw);
+        // parity of the words strictly above w within this chunk
+        unsigned long long above = lane == kWave - 1 ? 0ull : (mask >> (lane + 1));
+        int suffix = (__popcll(above) + carry) & 1;
+        if (w >= 0) {
+            for (int bit = 0; bit < 32; ++bit) {
+                int pos = 32 * w + bit;
+                if (pos >= ib.rw)
+                    break;
+                unsigned long long higher = (unsigned long long)word >> (bit + 1);
+                out[pos] = (uint8_t)((__popcll(higher) + suffix) & 1);
+            }
+        }
+        carry = (carry + __popcll(mask)) & 1;
+    }
+}
+
+// a3 tagging.  Outside the region every cell is fluid.  FORCING: a fluid
+// cell with an inside face neighbour.  Inside cells take the face-graph
+// distance to the nearest fluid cell: 1, 2, 3 -> G1, G2, G3, more -> SOLID
+// (the BFS layers of successive face neighbours).  Periodic axes wrap;
+// cells beyond other domain boundaries do not exist.
+__device__ inline bool nb_coord(const Grid &g, int axis, int c, int &out)
+{
+    int n = axis == 0 ? g.ni : axis == 1 ? g.nj : g.nk;
+    if (c >= 0 && c < n) {
+        out = c;
+        return true;
+    }
+    if (g.bc[2 * axis] != IBM_BC_PERIODIC)
+        return false;
+    out = ((c % n) + n) % n;
+    return true;
+}
+
+__device__ inline int inside_at(const IB &ib, int i, int j, int k)
+{
+    if (i < ib.region[0] || i >= ib.region[1] || j < ib.region[2] || j >= ib.region[3] ||
+        k < ib.region[4] || k >= ib.region[5])
+        return 0;
+    return ib.inside[((k - ib.region[4]) * ib.rh + (j - ib.region[2])) * ib.rw + (i - ib.region[0])];
+}
+
+__global__ void tag_kernel(Grid g, IB ib)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int n = ib.rw * ib.rh * ib.rd;
+    if (t >= n)
+        return;
+    int li = t % ib.rw, lj = (t / ib.rw) % ib.rh, lk = t / (ib.rw * ib.rh);
+    int i = li + ib.region[0], j = lj + ib.region[2], k = lk + ib.region[4];
+    int nd = g.ndim;
+    uint8_t cls;
+    if (!ib.inside[t]) {
+        cls = IBM_FLUID;
+        for (int d = 0; d < nd; ++d)
+            for (int s = -1; s <= 1; s += 2) {
+                int c[3] = {i, j, k}, o;
+                if (!nb_coord(g, d, c[d] + s, o))
+                    continue;
+                c[d] = o;
+                if (inside_at(ib, c[0], c[1], c[2]))
+                    cls = IBM_FORCING;
+            }
+    } else {
+        int best = 4;
+        int rz = nd == 3 ? 3 : 0;
+        for (int c = -rz; c <= rz; ++c)
+            for (int b2 = -3; b2 <= 3; ++b2)
+                for (int a = -3; a <= 3; ++a) {
+                    int dist = abs(a) + abs(b2) + abs(c);
+                    if (dist == 0 || dist > 3 || dist >= best)
+                        continue;
+                    int ii, jj, kk = k;
+                    if (!nb_coord(g, 0, i + a, ii) || !nb_coord(g, 1, j + b2, jj))
+                        continue;
+                    if (nd == 3 && !nb_coord(g, 2, k + c, kk))
+                        continue;
+                    if (!inside_at(ib, ii, jj, kk))
+                        best = dist;
+                }
+        cls = best == 1 ? IBM_G1 : best == 2 ? IBM_G2 : best == 3 ? IBM_G3 : IBM_SOLID;
+    }
+    ib.cls[cell_index(g, i, j, k)] = cls;
+}
+
+// --------------------------------------------------------- compaction
+__device__ inline int region_cell(const Grid &g, const IB &ib, int t)
+{
+    int li = t % ib.rw, lj = (t / ib.rw) % ib.rh, lk = t / (ib.rw * ib.rh);
+    return cell_index(g, li + ib.region[0], lj + ib.region[2], lk + ib.region[4]);
+}
+
+__global__ void zero_counts_kernel(int32_t *counts)
+{
+    if (threadIdx.x < CNT_WORDS && threadIdx.x != CNT_STATUS)
+        counts[threadIdx.x] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void count_kernel(Grid g, IB ib)
+{
+    __shared__ int sF[kBlock / kWave], sG[kBlock / kWave];
+    int n = ib.rw * ib.rh * ib.rd;
+    int t = blockIdx.x * kBlock + threadIdx.x;
+    uint8_t c = t < n ? ib.cls[region_cell(g, ib, t)] : (uint8_t)IBM_SOLID;
+    bool f = c == IBM_FORCING, gh = c >= IBM_G1 && c <= IBM_G3;
+    unsigned long long bf = __ballot(f), bg = __ballot(gh);
+    unsigned long long b1 = __ballot(c == IBM_G1), b2 = __ballot(c == IBM_G2),
+                       b3 = __ballot(c == IBM_G3);
+    int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    if (lane == 0) {
+        sF[w] = __popcll(bf);
+        sG[w] = __popcll(bg);
+        if (b1) atomicAdd(&ib.counts[CNT_G1], __popcll(b1));
+        if (b2) atomicAdd(&ib.counts[CNT_G2], __popcll(b2));
+        if (b3) atomicAdd(&ib.counts[CNT_G3], __popcll(b3));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int a = 0, b = 0;
+        for (int m = 0; m < kBlock / kWave; ++m) {
+            a += sF[m];
+            b += sG[m];
+        }
+        ib.blk[blockIdx.x] = a;
+        ib.blk[ib.nblk + blockIdx.x] = b;
+    }
+}
+
+// single block: exclusive scan of the per-block counts of both lists
+__global__ __launch_bounds__(1024) void scan_kernel(IB ib)
+{
+    __shared__ int part[2][1024];
+    int nb = ib.nblk;
+    int per = (nb + 1023) / 1024;
+    int t = threadIdx.x;
+    for (int l = 0; l < 2; ++l) {
+        int *a = ib.blk + l * nb;
+        int s = 0;
+        for (int m = 0; m < per; ++m) {
+            int idx = t * per + m;
+            if (idx < nb)
+                s += a[idx];
+        }
+        part[l][t] = s;
+    }
+    __syncthreads();
+    if (t < 2) {
+        int run = 0;
+        for (int m = 0; m < 1024; ++m) {
+            int v = part[t][m];
+            part[t][m] = run;
+            run += v;
+        }
+        ib.counts[t == 0 ? CNT_F : CNT_G] = run;
+        if (run > ib.cap)
+            atomicOr(&ib.counts[CNT_STATUS], ST_CAPACITY);
+    }
+    __syncthreads();
+    for (int l = 0; l < 2; ++l) {
+        int *a = ib.blk + l * nb;
+        int run = part[l][t];
+        for (int m = 0; m < per; ++m) {
+            int idx = t * per + m;
+            if (idx < nb) {
+                int v = a[idx];
+                a[idx] = run;
+                run += v;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void write_lists_kernel(Grid g, IB ib)
+{
+    __shared__ int sF[kBlock / kWave], sG[kBlock / kWave];
+    int n = ib.rw * ib.rh * ib.rd;
+    int t = blockIdx.x * kBlock + threadIdx.x;
+    int cell = t < n ? region_cell(g, ib, t) : 0;
+    uint8_t c = t < n ? ib.cls[cell] : (uint8_t)IBM_SOLID;
+    bool f = c == IBM_FORCING, gh = c >= IBM_G1 && c <= IBM_G3;
+    unsigned long long bf = __ballot(f), bg = __ballot(gh);
+    int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    unsigned long long lower = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+    if (lane == 0) {
+        sF[w] = __popcll(bf);
+        sG[w] = __popcll(bg);
+    }
+    __syncthreads();
+    int offF = ib.blk[blockIdx.x], offG = ib.blk[ib.nblk + blockIdx.x];
+    for (int m = 0; m < w; ++m) {
+        offF += sF[m];
+        offG += sG[m];
+    }
+    if (f) {
+        int pos = offF + __popcll(bf & lower);
+        if (pos < ib.cap)
+            ib.listF[pos] = cell;
+    }
+    if (gh) {
+        int pos = offG + __popcll(bg & lower);
+        if (pos < ib.cap)
+            ib.listG[pos] = cell;
+    }
+}
+
+// ------------------------------------------------------ records (a4)
+struct Closest {
+    int kind, id, facet;
+    double c[3], d2;
+};
+enum { FEAT_FACE = 0, FEAT_VERTEX = 1, FEAT_EDGE = 2 };
+
+__device__ inline double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+__device__ inline void cross3(const double *a, const double *b, double *c)
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Section 4.1: minimum of the squared distance of eq.1 over all facets;
+// the lowest facet id wins exact ties.  2D: clamped segment parameter.
+__device__ Closest closest2d(const Body &b, const double *p)
+{
+    Closest best;
+    best.d2 = __builtin_inf();
+    best.kind = best.id = best.facet = -1;
+    best.c[0] = best.c[1] = best.c[2] = 0.0;
+    for (int f = 0; f < b.nfacet; ++f) {
+        int ia = b.facet[2 * f], ibv = b.facet[2 * f + 1];
+        const double *a = b.v + 2 * ia, *q = b.v + 2 * ibv;
+        double ex = q[0] - a[0], ey = q[1] - a[1];
+        double t = ((p[0] - a[0]) * ex + (p[1] - a[1]) * ey) / (ex * ex + ey * ey);
+        double cx, cy;
+        int kind, id;
+        if (t <= 0.0) {
+            cx = a[0]; cy = a[1]; kind = FEAT_VERTEX; id = ia;
+        } else if (t >= 1.0) {
+            cx = q[0]; cy = q[1]; kind = FEAT_VERTEX; id = ibv;
+        } else {
+            cx = a[0] + t * ex; cy = a[1] + t * ey; kind = FEAT_FACE; id = f;
+        }
+        double dx = p[0] - cx, dy = p[1] - cy, d2 = dx * dx + dy * dy;
+        if (d2 < best.d2) {
+            best.d2 = d2;
+            best.kind = kind;
+            best.id = id;
+            best.facet = f;
+            best.c[0] = cx;
+            best.c[1] = cy;
+        }
+    }
+    return best;
+}
+
+__device__ inline void seg_closest(const double *p, const double *a, const double *q, double &t,
+                                   double *c, double &d2)
+{
+    double e[3] = {q[0] - a[0], q[1] - a[1], q[2] - a[2]};
+    double w[3] = {p[0] - a[0], p[1] - a[1], p[2] - a[2]};
+    t = dot3(w, e) / dot3(e, e);
+    if (t <= 0.0) {
+        t = 0.0;
+        c[0] = a[0]; c[1] = a[1]; c[2] = a[2];
+    } else if (t >= 1.0) {
+        t = 1.0;
+        c[0] = q[0]; c[1] = q[1]; c[2] = q[2];
+    } else {
+        c[0] = a[0] + t * e[0];
+        c[1] = a[1] + t * e[1];
+        c[2] = a[2] + t * e[2];
+    }
+    double dx = p[0] - c[0], dy = p[1] - c[1], dz = p[2] - c[2];
+    d2 = dx * dx + dy * dy + dz * dz;
+}
+
+// 3D: interior stationary point of eq.1 (face region) when feasible,
+// otherwise the best of the three edge minimisers (edge or vertex regions).
+__device__ Closest closest3d(const Body &b, const double *p)
+{
+    Closest best;
+    best.d2 = __builtin_inf();
+    best.kind = best.id = best.facet = -1;
+    best.c[0] = best.c[1] = best.c[2] = 0.0;
+    for (int f = 0; f < b.nfacet; ++f) {
+        const int *tv = b.facet + 3 * f;
+        const double *A = b.v + 3 * tv[0], *B = b.v + 3 * tv[1], *C = b.v + 3 * tv[2];
+        double e0[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+        double e1[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+        double dd[3] = {A[0] - p[0], A[1] - p[1], A[2] - p[2]};
+        double a = dot3(e0, e0), bb = dot3(e0, e1), c = dot3(e1, e1);
+        double d = dot3(e0, dd), e = dot3(e1, dd);
+        double det = a * c - bb * bb;
+        double s = bb * e - c * d, t = bb * d - a * e;
+        Closest cur;
+        cur.kind = cur.id = -1;
+        if (s > 0.0 && t > 0.0 && s + t < det) {
+            s /= det;
+            t /= det;
+            cur.kind = FEAT_FACE;
+            cur.id = f;
+            for (int m = 0; m < 3; ++m)
+                cur.c[m] = A[m] + s * e0[m] + t * e1[m];
+            double dx = p[0] - cur.c[0], dy = p[1] - cur.c[1], dz = p[2] - cur.c[2];
+            cur.d2 = dx * dx + dy * dy + dz * dz;
+        } else {
+            cur.d2 = __builtin_inf();
+            for (int m = 0; m < 3; ++m) {
+                const double *pa = b.v + 3 * tv[m], *pb = b.v + 3 * tv[(m + 1) % 3];
+                double tt, cc[3], d2;
+                seg_closest(p, pa, pb, tt, cc, d2);
+                if (d2 < cur.d2) {
+                    cur.d2 = d2;
+                    cur.c[0] = cc[0]; cur.c[1] = cc[1]; cur.c[2] = cc[2];
+                    if (tt == 0.0) {
+                        cur.kind = FEAT_VERTEX;
+                        cur.id = tv[m];
+                    } else if (tt == 1.0) {
+                        cur.kind = FEAT_VERTEX;
+                        cur.id = tv[(m + 1) % 3];
+                    } else {
+                        cur.kind = FEAT_EDGE;
+                        cur.id = b.edge_of[3 * f + m];
+                    }
+                }
+            }
+        }
+        if (cur.d2 < best.d2) {
+            best = cur;
+            best.facet = f;
+        }
+    }
+    return best;
+}
+
+__device__ double line_hit2d(const Body &b, const double *x, const double *dir, double smax)
+{
+    double best = -1.0;
+    for (int f = 0; f < b.nfacet; ++f) {
+        const double *a = b.v + 2 * b.facet[2 * f], *q = b.v + 2 * b.facet[2 * f + 1];
+        double ex = q[0] - a[0], ey = q[1] - a[1];
+        double den = dir[0] * ey - dir[1] * ex;
+        if (den == 0.0)
+            continue;
+        double ax = a[0] - x[0], ay = a[1] - x[1];
+        double sig = (ax * ey - ay * ex) / den;
+        double tau = (ax * dir[1] - ay * dir[0]) / den;
+        if (tau < 0.0 || tau > 1.0 || sig < 0.0 || sig > smax)
+            continue;
+        if (best < 0.0 || sig < best)
+            best = sig;
+    }
+    return best;
+}
+
+// Moller-Trumbore line/triangle intersection (section 3.2)
+__device__ double line_hit3d(const Body &b, const double *x, const double *dir, double smax)
+{
+    double best = -1.0;
+    for (int f = 0; f < b.nfacet; ++f) {
+        const int *tv = b.facet + 3 * f;
+        const double *A = b.v + 3 * tv[0], *B = b.v + 3 * tv[1], *C = b.v + 3 * tv[2];
+        double e1[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+        double e2[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+        double pv[3];
+        cross3(dir, e2, pv);
+        double det = dot3(e1, pv);
+        if (det == 0.0)
+            continue;
+        double tv_[3] = {x[0] - A[0], x[1] - A[1], x[2] - A[2]};
+        double u = dot3(tv_, pv) / det;
+        if (u < 0.0 || u > 1.0)
+            continue;
+        double qv[3];
+        cross3(tv_, e1, qv);
+        double vv = dot3(dir, qv) / det;
+        if (vv < 0.0 || u + vv > 1.0)
+            continue;
+        double sig = dot3(e2, qv) / det;
+        if (sig < 0.0 || sig > smax)
+            continue;
+        if (best < 0.0 || sig < best)
+            best = sig;
+    }
+    return best;
+}
+
+// enclosing interior cell along one axis: largest i0 with c[i0] <= y and
+// i0 + 1 interior
+__device__ inline bool locate(const double *c, int n, double y, int &i0, double &frac)
+{
+    if (!(y >= c[3]) || !(y < c[n + 2]))
+        return false;
+    int lo = 0, hi = n - 1;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) / 2;
+        if (c[mid + 3] <= y)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    i0 = lo;
+    frac = (y - c[lo + 3]) / (c[lo + 4] - c[lo + 3]);
+    return true;
+}
+
+// Probe stencil set-up: mode 0 multilinear (all corners valid), mode 1
+// inverse-distance 1/r^2 over the valid corners (a corner at r = 0 takes all
+// the weight).  Valid corners: FLUID, plus FORCING for ghost nodes.
+__device__ bool probe_setup(const Grid &g, const uint8_t *cls, const double *y, int mode,
+                            bool allow_forcing, int *ids, double *w)
+{
+    int nd = g.ndim, ncorner = 1 << nd;
+    for (int m = 0; m < 8; ++m) {
+        ids[m] = -1;
+        w[m] = 0.0;
+    }
+    int i0[3] = {0, 0, 0};
+    double fr[3] = {0.0, 0.0, 0.0};
+    if (!locate(g.xc[0], g.ni, y[0], i0[0], fr[0]) || !locate(g.xc[1], g.nj, y[1], i0[1], fr[1]))
+        return false;
+    if (nd == 3 && !locate(g.xc[2], g.nk, y[2], i0[2], fr[2]))
+        return false;
+    int nvalid = 0, zero = -1;
+    for (int m = 0; m < ncorner; ++m) {
+        int bx = m & 1, by = (m >> 1) & 1, bz = (m >> 2) & 1;
+        int c = cell_index(g, i0[0] + bx, i0[1] + by, nd == 3 ? i0[2] + bz : 0);
+        uint8_t t = cls[c];
+        bool valid = t == IBM_FLUID || (allow_forcing && t == IBM_FORCING);
+        ids[m] = c;
+        if (mode == 0) {
+            if (!valid)
+                return false;
+            double wt = 1.0;
+            int bb[3] = {bx, by, bz};
+            for (int d = 0; d < nd; ++d)
+                wt *= bb[d] ? fr[d] : 1.0 - fr[d];
+            w[m] = wt;
+            nvalid++;
+        } else {
+            if (!valid) {
+                w[m] = 0.0;
+                continue;
+            }
+            double cc[3] = {g.xc[0][i0[0] + bx + 3], g.xc[1][i0[1] + by + 3],
+                            nd == 3 ? g.xc[2][i0[2] + bz + 3] : 0.0};
+            double r2 = 0.0;
+            for (int d = 0; d < nd; ++d)
+                r2 += (y[d] - cc[d]) * (y[d] - cc[d]);
+            if (r2 == 0.0 && zero < 0)
+                zero = m;
+            w[m] = r2 > 0.0 ? 1.0 / r2 : 0.0;
+            nvalid++;
+        }
+    }
+    if (nvalid == 0)
+        return false;
+    if (mode == 1) {
+        if (zero >= 0) {
+            for (int m = 0; m < ncorner; ++m)
+                w[m] = m == zero ? 1.0 : 0.0;
+        } else {
+            double s = 0.0;
+            for (int m = 0; m < ncorner; ++m)
+                s += w[m];
+            for (int m = 0; m < ncorner; ++m)
+                w[m] /= s;
+        }
+    }
+    return true;
+}
+
+// Sections 4.1-4.3: closest feature, local normal (face normal or the
+// pseudo-normals of eqs 2-3), boundary point P' where the line through the
+// node parallel to the normal meets the surface, and probes along it.
+__global__ void records_kernel(Grid g, Body b, Flow fl, IB ib)
+{
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    int nF = min(ib.counts[CNT_F], ib.cap);
+    int nG = min(ib.counts[CNT_G], ib.cap - nF);
+    if (r >= nF + nG)
+        return;
+    bool forcing = r < nF;
+    int c = forcing ? ib.listF[r] : ib.listG[r - nF];
+    int nd = g.ndim;
+    int i = c % g.ni, j = (c / g.ni) % g.nj, k = c / (g.ni * g.nj);
+    double X[3] = {g.xc[0][i + 3], g.xc[1][j + 3], nd == 3 ? g.xc[2][k + 3] : 0.0};
+    double h = fmin(g.xf[0][i + 4] - g.xf[0][i + 3], g.xf[1][j + 4] - g.xf[1][j + 3]);
+    if (nd == 3)
+        h = fmin(h, g.xf[2][k + 4] - g.xf[2][k + 3]);
+    Closest cl = nd == 2 ? closest2d(b, X) : closest3d(b, X);
+    const double *src = cl.kind == FEAT_FACE ? b.fnrm + 3 * cl.id
+                        : cl.kind == FEAT_VERTEX ? b.vnrm + 3 * cl.id
+                                                 : b.enrm + 3 * cl.id;
+    double n[3] = {src[0], src[1], src[2]};
+    double P[3] = {cl.c[0], cl.c[1], cl.c[2]};
+    int fb = 0;
+    if (cl.kind != FEAT_FACE) {
+        double dir[3] = {0.0, 0.0, 0.0};
+        for (int d = 0; d < nd; ++d)
+            dir[d] = forcing ? -n[d] : n[d];
+        double sig = nd == 2 ? line_hit2d(b, X, dir, 4.0 * h) : line_hit3d(b, X, dir, 4.0 * h);
+        if (sig >= 0.0) {
+            for (int d = 0; d < nd; ++d)
+                P[d] = X[d] + sig * dir[d];
+        } else {
+            fb |= 1;
+            atomicAdd(&ib.counts[CNT_FB_PPRIME], 1);
+        }
+    }
+    double dist2 = 0.0;
+    for (int d = 0; d < nd; ++d)
+        dist2 += (X[d] - P[d]) * (X[d] - P[d]);
+    double sx = forcing ? sqrt(dist2) : -sqrt(dist2);
+    bool quad = fl.family == IBM_IB_QUADRATIC;
+    int mode = (!quad && forcing) ? 1 : 0;
+    bool allow_forcing = !forcing;
+    double s1 = forcing ? sx + h : fmax(-sx, h);
+    double s2 = s1 + h;
+    int ids1[8], ids2[8];
+    double w1[8], w2[8];
+    bool ok = false;
+    int mode1 = mode, mode2 = mode;
+    for (int attempt = 0; attempt <= 6; ++attempt) {
+        double y1[3] = {0.0, 0.0, 0.0}, y2[3] = {0.0, 0.0, 0.0};
+        for (int d = 0; d < nd; ++d) {
+            y1[d] = P[d] + s1 * n[d];
+            y2[d] = P[d] + s2 * n[d];
+        }
+        bool v1 = probe_setup(g, ib.cls, y1, mode, allow_forcing, ids1, w1);
+        bool v2 = quad ? probe_setup(g, ib.cls, y2, mode, allow_forcing, ids2, w2) : true;
+        if (v1 && v2) {
+            ok = true;
+            break;
+        }
+        if (attempt < 6) {
+            s1 += 0.5 * h;
+            s2 += 0.5 * h;
+        }
+    }
+    if (!ok) {
+        double y1[3] = {0.0, 0.0, 0.0}, y2[3] = {0.0, 0.0, 0.0};
+        for (int d = 0; d < nd; ++d) {
+            y1[d] = P[d] + s1 * n[d];
+            y2[d] = P[d] + s2 * n[d];
+        }
+        fb |= 2;
+        atomicAdd(&ib.counts[CNT_FB_PROBE], 1);
+        mode1 = mode2 = 1;
+        bool v1 = probe_setup(g, ib.cls, y1, 1, allow_forcing, ids1, w1);
+        bool v2 = quad ? probe_setup(g, ib.cls, y2, 1, allow_forcing, ids2, w2) : true;
+        if (!v1)
+            mode1 = 2;
+        if (quad && !v2)
+            mode2 = 2;
+        if (!v1 || (quad && !v2))
+            fb |= 4;
+    }
+    if (!quad) {
+        for (int m = 0; m < 8; ++m) {
+            ids2[m] = -1;
+            w2[m] = 0.0;
+        }
+        mode2 = 3;
+    }
+    int *ir = ib.rec_i + (long long)kRecI * r;
+    double *dr = ib.rec_d + (long long)kRecD * r;
+    ir[0] = c;
+    ir[1] = cl.kind;
+    ir[2] = cl.id;
+    ir[3] = cl.facet;
+    ir[4] = mode1;
+    ir[5] = mode2;
+    ir[6] = fb;
+    for (int m = 0; m < 8; ++m) {
+        ir[7 + m] = ids1[m];
+        ir[15 + m] = ids2[m];
+        dr[9 + m] = w1[m];
+        dr[17 + m] = w2[m];
+    }
+    ir[23] = 0;
+    for (int d = 0; d < 3; ++d) {
+        dr[d] = n[d];
+        dr[3 + d] = P[d];
+    }
+    dr[6] = sx;
+    dr[7] = s1;
+    dr[8] = s2;
+    dr[25] = sqrt(cl.d2);
+    for (int m = 26; m < kRecD; ++m)
+        dr[m] = 0.0;
+}
+
+inline int blocks_for(long long n, int bs) { return (int)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t launch_pose(const Grid &g, Body &b, long long disp, int axis, hipStream_t s)
+{
+    int n = b.nvert * g.ndim;
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(pose_kernel, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, b.nvert,
+                       g.ndim, b.V0, b.V, b.v, disp, axis);
+    return hipGetLastError();
+}
+
+hipError_t launch_classify(const Grid &g, const Body &b, IB &ib, hipStream_t s)
+{
+    int ncell = ib.rw * ib.rh * ib.rd;
+    int nrows = ib.rh * ib.rd;
+    int nwords = nrows * ib.words_per_row;
+    int nmax = ncell > nwords ? ncell : nwords;
+    hipLaunchKernelGGL(zero_counts_kernel, dim3(1), dim3(64), 0, s, ib.counts);
+    if (ncell == 0)
+        return hipGetLastError();
+    hipLaunchKernelGGL(clear_kernel, dim3(blocks_for(nmax, kBlock)), dim3(kBlock), 0, s, ib.inside,
+                       ncell, ib.toggle, nwords);
+    if (b.nfacet > 0) {
+        if (g.ndim == 2)
+            hipLaunchKernelGGL(cross2d_kernel, dim3(blocks_for(b.nfacet, 64)), dim3(64), 0, s, g, b,
+                               ib);
+        else
+            hipLaunchKernelGGL(cross3d_kernel, dim3(blocks_for(b.nfacet, 64)), dim3(64), 0, s, g, b,
+                               ib);
+        hipLaunchKernelGGL(parity_kernel, dim3(blocks_for(nrows, kBlock / kWave)), dim3(kBlock), 0,
+                           s, ib, nrows);
+    }
+    hipLaunchKernelGGL(tag_kernel, dim3(blocks_for(ncell, kBlock)), dim3(kBlock), 0, s, g, ib);
+    hipLaunchKernelGGL(count_kernel, dim3(ib.nblk), dim3(kBlock), 0, s, g, ib);
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, ib);
+    hipLaunchKernelGGL(write_lists_kernel, dim3(ib.nblk), dim3(kBlock), 0, s, g, ib);
+    return hipGetLastError();
+}
+
+hipError_t launch_records(const Grid &g, const Body &b, const Flow &f, IB &ib, hipStream_t s)
+{
+    if (ib.cap == 0 || b.nfacet == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(records_kernel, dim3(blocks_for(ib.cap, 64)), dim3(64), 0, s, g, b, f, ib);
+    return hipGetLastError();
+}
+
+}  // namespace ibm
