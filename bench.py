@@ -1,0 +1,180 @@
+"""Throughput benchmark of the immersed-boundary residual + update step.
+
+Workload: the supersonic wedge -- 15 degree half-angle triangle of length 1,
+M = 2, Re = 1e4, 1024 x 512 rectilinear grid (x uniform on [-1, 3], y tanh
+clustered toward the wedge axis with adjacent-width ratio 1.02), SSP-RK3 with
+the compressible (IDW + image point) immersed-boundary family, free-stream
+start.  A step is one RK3 step: three stages, each a domain-ghost fill, IB
+fill and fused residual + update over every cell, so one step is
+3 * 1024 * 512 cell-updates.
+
+Both precision modes are timed (mixed = FP32 reconstruction and fluxes on
+perturbation variables with FP64 update; fp64); ``value`` is the mixed
+path's whole-job cell-updates/s with the state resident in HBM.  The fused
+stage kernel is timed separately with HIP events on the launch stream for
+the roofline entry; the CPU oracle is timed on a bounded sample of the same
+workload for the cpu_baseline entry.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s (full residual+IBM step) mixed vs FP64; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+
+# Algorithmic work per cell-update of the fused stage kernel (2D, SSP-RK3),
+# counted from the formulas (each +, -, *, /, sqrt one flop):
+#   WENO5 reconstruction 68 flops, 8 per face (4 variables x 2 sides);
+#   LDFSS flux 118; central viscous flux 55  -> 717 per face, 2 faces/cell;
+#   flux differences 31, primitive recovery 11, RK3 update 20.
+FLOPS_PER_CELL_2D_RK3 = 2 * (8 * 68 + 118 + 55) + 31 + 11 + 20
+# HBM bytes per cell-update (algorithmic): stage input state 4 x 8 B read,
+# stage output 4 x 8 B written, class byte; stages 2 and 3 also read Q^n.
+BYTES_PER_CELL_STAGE = {1: 32 + 32 + 1, 2: 32 + 32 + 32 + 1, 3: 32 + 32 + 32 + 1}
+
+
+def _parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--precisions", default="mixed,fp64")
+    return ap.parse_args()
+
+
+def run_gpu(case, prim, precision, steps, warmup, reps):
+    import torch
+    import paper_1912_11908_amd as P
+    s = P.Solver(case, precision, "cuda:0")
+    s.init_prim(prim)
+    s.classify()
+    s.advance(warmup)
+    torch.cuda.synchronize()
+    s.check_status()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    s.advance(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    s.check_status()
+    # fused stage kernel, timed with HIP events around repeated launches
+    stage_ms = {st: s.time_update_kernel(st, reps) for st in (1, 2, 3)}
+    torch.cuda.synchronize()
+    prim_out = s.to_prim().cpu().numpy()
+    return dict(wall=wall, event_ms=ev_ms, stage_ms=stage_ms, prim=prim_out,
+                counts=s.counts().tolist())
+
+
+def cpu_baseline(case, prim, seconds):
+    """The oracle as it stands, on this host's cores, over whole RK3 steps of
+    the same workload until about `seconds` of wall time have passed."""
+    import numpy as np
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    o = oracle.Oracle(case)
+    o.classify()
+    q = o.prim_to_state(prim)
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        o.run(q, 1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 200:
+            break
+    cu = steps * 3 * case.ncells
+    assert np.all(np.isfinite(o.interior(q)))
+    return {"value": cu / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} RK3 steps of the full {case.ni}x{case.nj} wedge grid "
+                      f"({cu:.3g} cell-updates, {el:.1f} s wall, OMP_NUM_THREADS={threads})"}
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import workloads as w
+
+    case = w.case_c2(steps=args.steps)
+    prim = w.freestream_prim(2, case.ni, case.nj, 1, case.p_inf)
+    ncell = case.ncells
+    res = {}
+    for prec in [p for p in args.precisions.split(",") if p]:
+        res[prec] = run_gpu(case, prim, prec, args.steps, args.warmup, args.kernel_reps)
+    head = "mixed" if "mixed" in res else "fp64"
+    r = res[head]
+    cell_updates = args.steps * 3 * ncell
+    value = cell_updates / r["wall"]
+
+    # roofline of the fused stage kernel (average over the three stages)
+    avg_ms = sum(r["stage_ms"].values()) / 3.0
+    bytes_cell = sum(BYTES_PER_CELL_STAGE.values()) / 3.0
+    achieved_gbs = bytes_cell * ncell / (avg_ms * 1e-3) / 1e9
+    achieved_tf = FLOPS_PER_CELL_2D_RK3 * ncell / (avg_ms * 1e-3) / 1e12
+    fpeak = FP32_PEAK_TFLOPS if head == "mixed" else FP64_PEAK_TFLOPS
+    t_alu = FLOPS_PER_CELL_2D_RK3 / (fpeak * 1e12)
+    t_hbm = bytes_cell / (HBM_PEAK_GBS * 1e9)
+    if t_alu >= t_hbm:
+        roof = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": fpeak,
+                "unit": "TFLOP/s", "frac": round(achieved_tf / fpeak, 4)}
+        other = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
+                 "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4)}
+        other = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": fpeak,
+                 "unit": "TFLOP/s", "frac": round(achieved_tf / fpeak, 4)}
+    roof["traffic"] = None
+    roof["kernel"] = "step_kernel<2,%s,RK3>" % ("float" if head == "mixed" else "double")
+    roof["kernel_avg_ms"] = round(avg_ms, 5)
+    roof["per_unit"] = {"flops_per_cell_update": FLOPS_PER_CELL_2D_RK3,
+                        "bytes_per_cell_update": round(bytes_cell, 2), "cells_per_launch": ncell}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": r["wall"] * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "supersonic wedge 1024x512, M=2, Re=1e4, SSP-RK3, IDW/image-point IB",
+                   "cells": ncell, "cell_updates_per_step": 3 * ncell, "precision": head},
+        "roofline": roof, "roofline_other": other,
+    }
+    if "fp64" in res and "mixed" in res:
+        f = res["fp64"]
+        out["fp64"] = {"value": cell_updates / f["wall"], "ms_per_step": f["wall"] * 1e3 / args.steps,
+                       "kernel_avg_ms": round(sum(f["stage_ms"].values()) / 3.0, 5)}
+        out["mixed_speedup_vs_fp64"] = f["wall"] / r["wall"]
+        a, b = res["mixed"]["prim"], f["prim"]
+        errs = [float(np.sqrt(np.sum((a[v] - b[v]) ** 2) / np.sum(b[v] ** 2))) for v in range(4)]
+        out["mixed_vs_fp64_rel_l2"] = {"rho": errs[0], "u": errs[1], "v": errs[2], "p": errs[3]}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case, prim, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

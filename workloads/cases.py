@@ -66,15 +66,21 @@ def _hmin(axes):
     return [float(np.min(np.diff(a))) for a in axes]
 
 
-def rk3_dt(mach, reynolds, axes, cfl=None):
-    """Explicit step: CFL / sum_d (|U_inf,d| + a_inf) / h_min,d, capped by the
-    viscous limit Re h_min^2 / 4 (U_inf = 1 along x, a_inf = 1 / M)."""
+def rk3_dt(mach, reynolds, axes, cfl=None, prandtl=0.72, gamma=1.4):
+    """Explicit step: CFL / sum_d (|U_inf,d| + a_inf) / h_min,d (U_inf = 1
+    along x, a_inf = 1 / M), capped by the explicit diffusion limit
+    0.5 / (4 nu_max sum_d 1 / h_min,d^2) with the thermal diffusivity
+    nu_max = (gamma / Pr) mu / rho_floor; rho_floor = 0.1 for supersonic free
+    streams (deep expansions behind bases), 0.5 otherwise."""
     if cfl is None:
         cfl = 0.4 if mach > 1.0 else 0.5
     h = _hmin(axes)
     a = 1.0 / mach
     s = sum(((1.0 if d == 0 else 0.0) + a) / h[d] for d in range(len(h)))
-    return min(cfl / s, 0.25 * reynolds * min(h) ** 2)
+    rho_floor = 0.1 if mach > 1.0 else 0.5
+    nu = gamma / prandtl / reynolds / rho_floor
+    dt_visc = 0.5 / (4.0 * nu * sum(1.0 / hd ** 2 for hd in h))
+    return min(cfl / s, dt_visc)
 
 
 def dual_dt(axes):
