@@ -750,12 +750,15 @@ static double line_hit3d(const orc *o, const double *x, const double *dir, doubl
 }
 
 /* Enclosing cell of a probe point: per axis the largest centre index i0 with
- * c[i0] <= y among the interior cells, and i0 + 1 interior too. */
-static int locate(const double *c, int n, double y, int *i0, double *frac)
+ * c[i0] <= y < c[i0 + 1].  On a non-periodic axis both cells must be
+ * interior; on a periodic axis the pair may straddle the boundary
+ * (i0 = -1 or i0 + 1 = n, their periodic images), so every point of the
+ * period has an enclosing cell.  Extended centres hold those images. */
+static int locate(const double *c, int n, int periodic, double y, int *i0, double *frac)
 {
-    if (!(y >= c[3]) || !(y < c[n + 2]))
+    int lo = periodic ? -1 : 0, hi = periodic ? n : n - 1; /* c[lo+3] <= y < c[hi+3] */
+    if (!(y >= c[lo + 3]) || !(y < c[hi + 3]))
         return 0;
-    int lo = 0, hi = n - 1; /* c[lo+3] <= y < c[hi+3] */
     while (hi - lo > 1) {
         int mid = (lo + hi) / 2;
         if (c[mid + 3] <= y)
@@ -767,6 +770,8 @@ static int locate(const double *c, int n, double y, int *i0, double *frac)
     *frac = (y - c[lo + 3]) / (c[lo + 4] - c[lo + 3]);
     return 1;
 }
+
+static int wrap(int i, int n) { return ((i % n) + n) % n; }
 
 /* Probe interpolation set-up.  Returns 1 when the probe passes its validity
  * rule; fills corner ids (-1 where unused) and weights.
@@ -784,14 +789,18 @@ static int probe_setup(const orc *o, const double *y, int mode, int allow_forcin
     }
     int i0[3] = {0, 0, 0};
     double fr[3] = {0, 0, 0};
-    if (!locate(o->xc, o->ni, y[0], &i0[0], &fr[0]) || !locate(o->yc, o->nj, y[1], &i0[1], &fr[1]))
+    int per[3] = {o->bc[0] == ORC_BC_PERIODIC, o->bc[2] == ORC_BC_PERIODIC,
+                  o->bc[4] == ORC_BC_PERIODIC};
+    if (!locate(o->xc, o->ni, per[0], y[0], &i0[0], &fr[0]) ||
+        !locate(o->yc, o->nj, per[1], y[1], &i0[1], &fr[1]))
         return 0;
-    if (nd == 3 && !locate(o->zc, o->nk, y[2], &i0[2], &fr[2]))
+    if (nd == 3 && !locate(o->zc, o->nk, per[2], y[2], &i0[2], &fr[2]))
         return 0;
     int nvalid = 0, zero = -1;
     for (int m = 0; m < ncorner; m++) {
         int b[3] = {m & 1, (m >> 1) & 1, (m >> 2) & 1};
-        long c = cidx(o, i0[0] + b[0], i0[1] + b[1], nd == 3 ? i0[2] + b[2] : 0);
+        long c = cidx(o, wrap(i0[0] + b[0], o->ni), wrap(i0[1] + b[1], o->nj),
+                      nd == 3 ? wrap(i0[2] + b[2], o->nk) : 0);
         uint8_t t = o->cls[c];
         int valid = t == ORC_FLUID || (allow_forcing && t == ORC_FORCING);
         ids[m] = (int32_t)c;

@@ -569,13 +569,15 @@ __device__ double line_hit3d(const Body &b, const double *x, const double *dir, 
     return best;
 }
 
-// enclosing interior cell along one axis: largest i0 with c[i0] <= y and
-// i0 + 1 interior
-__device__ inline bool locate(const double *c, int n, double y, int &i0, double &frac)
+// enclosing cell along one axis: largest i0 with c[i0] <= y < c[i0 + 1];
+// interior pairs only, except on a periodic axis where the pair may
+// straddle the boundary (i0 = -1 or i0 + 1 = n, the extended centres being
+// the periodic images)
+__device__ inline bool locate(const double *c, int n, bool periodic, double y, int &i0, double &frac)
 {
-    if (!(y >= c[3]) || !(y < c[n + 2]))
+    int lo = periodic ? -1 : 0, hi = periodic ? n : n - 1;
+    if (!(y >= c[lo + 3]) || !(y < c[hi + 3]))
         return false;
-    int lo = 0, hi = n - 1;
     while (hi - lo > 1) {
         int mid = (lo + hi) / 2;
         if (c[mid + 3] <= y)
@@ -587,6 +589,8 @@ __device__ inline bool locate(const double *c, int n, double y, int &i0, double 
     frac = (y - c[lo + 3]) / (c[lo + 4] - c[lo + 3]);
     return true;
 }
+
+__device__ inline int wrap_idx(int i, int n) { return ((i % n) + n) % n; }
 
 // Probe stencil set-up: mode 0 multilinear (all corners valid), mode 1
 // inverse-distance 1/r^2 over the valid corners (a corner at r = 0 takes all
@@ -601,14 +605,17 @@ __device__ bool probe_setup(const Grid &g, const uint8_t *cls, const double *y, 
     }
     int i0[3] = {0, 0, 0};
     double fr[3] = {0.0, 0.0, 0.0};
-    if (!locate(g.xc[0], g.ni, y[0], i0[0], fr[0]) || !locate(g.xc[1], g.nj, y[1], i0[1], fr[1]))
+    bool per[3] = {g.bc[0] == IBM_BC_PERIODIC, g.bc[2] == IBM_BC_PERIODIC, g.bc[4] == IBM_BC_PERIODIC};
+    if (!locate(g.xc[0], g.ni, per[0], y[0], i0[0], fr[0]) ||
+        !locate(g.xc[1], g.nj, per[1], y[1], i0[1], fr[1]))
         return false;
-    if (nd == 3 && !locate(g.xc[2], g.nk, y[2], i0[2], fr[2]))
+    if (nd == 3 && !locate(g.xc[2], g.nk, per[2], y[2], i0[2], fr[2]))
         return false;
     int nvalid = 0, zero = -1;
     for (int m = 0; m < ncorner; ++m) {
         int bx = m & 1, by = (m >> 1) & 1, bz = (m >> 2) & 1;
-        int c = cell_index(g, i0[0] + bx, i0[1] + by, nd == 3 ? i0[2] + bz : 0);
+        int c = cell_index(g, wrap_idx(i0[0] + bx, g.ni), wrap_idx(i0[1] + by, g.nj),
+                           nd == 3 ? wrap_idx(i0[2] + bz, g.nk) : 0);
         uint8_t t = cls[c];
         bool valid = t == IBM_FLUID || (allow_forcing && t == IBM_FORCING);
         ids[m] = c;

@@ -19,7 +19,25 @@ SMALL = {
     "naca": lambda: w.small_case("naca", 48, steps=2, n_inner=3),
     "moving-cylinder": lambda: w.small_case("moving-cylinder", 64, steps=4),
     "ragged": lambda: w.small_case("cylinder", 61, steps=3),
+    "tube-moving": lambda: w.small_case("tube", 32, steps=3, nz=8, ntheta=64, nzt=4),
+    "tube-static": lambda: w.small_case("tube", 30, steps=2, nz=10, ntheta=48, nzt=5, moving=False),
+    "octahedron": lambda: _octahedron_case(),
 }
+
+
+def _octahedron_case():
+    from workloads.cases import Case, rk3_dt
+    r = 1.1
+    v = w.snap(np.array([[r, 0, 0], [-r, 0, 0], [0, r, 0], [0, -r, 0], [0, 0, r], [0, 0, -r]], float))
+    t = []
+    for a, b in ((0, 2), (2, 1), (1, 3), (3, 0)):
+        t.append([a, b, 4])
+        t.append([b, a, 5])
+    xf = w.uniform_faces(23, -1.37, 1.45)
+    yf = w.uniform_faces(21, -1.41, 1.39)
+    zf = w.uniform_faces(19, -1.33, 1.42)
+    return Case("octahedron", 3, xf, yf, zf, ("farfield",) * 6, v, np.array(t, np.int32), 0.3, 100.0,
+                dt=rk3_dt(0.3, 100.0, [xf, yf, zf]), steps=2)
 
 
 def _classified(kind, precision="fp64"):
@@ -46,7 +64,8 @@ def test_classification_lists_records_exact(kind):
     assert np.abs(dr[:, :26] - odr[:, :26]).max() <= 1e-14
 
 
-@pytest.mark.parametrize("kind", ["cylinder", "cylinder-quad", "wedge", "naca", "ragged"])
+@pytest.mark.parametrize("kind", ["cylinder", "cylinder-quad", "wedge", "naca", "ragged",
+                                  "tube-static", "octahedron"])
 def test_fill_and_residual_fp64(kind):
     case, prim, s, o = _classified(kind)
     s.fill(0.0)
@@ -63,7 +82,8 @@ def test_fill_and_residual_fp64(kind):
     assert np.abs(ro).max() > 0
 
 
-@pytest.mark.parametrize("kind", ["cylinder", "cylinder-quad", "wedge", "ragged", "moving-cylinder"])
+@pytest.mark.parametrize("kind", ["cylinder", "cylinder-quad", "wedge", "ragged", "moving-cylinder",
+                                  "tube-moving", "tube-static", "octahedron"])
 def test_rk3_steps_fp64(kind):
     case, prim, s, o = _classified(kind)
     n = case.steps
@@ -130,7 +150,7 @@ def test_nonfinite_status_reported():
     assert s.status() == -4
 
 
-@pytest.mark.parametrize("kind", ["cylinder", "wedge", "naca"])
+@pytest.mark.parametrize("kind", ["cylinder", "wedge", "naca", "tube-moving"])
 def test_mixed_precision_error(kind):
     """Mixed mode (FP32 reconstruction and fluxes on perturbation variables,
     FP64 update) stays within a stated distance of the FP64 oracle."""

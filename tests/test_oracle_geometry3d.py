@@ -177,3 +177,21 @@ def test_closest_points_3d_against_bruteforce_and_sign_theorem():
         if abs(s) < 1e-12:
             continue
         assert (s > 0) == (r < nF), r
+
+
+def test_probe_stencils_wrap_across_periodic_axis():
+    """A body spanning a periodic axis (the tube) has valid probe stencils at
+    every node; nodes in the last layer take their enclosing pair across the
+    periodic boundary (cells n-1 and 0) rather than falling back."""
+    c = w.small_case("tube", 30, steps=1, nz=10, ntheta=48, nzt=5, moving=False)
+    o = oracle.Oracle(c)
+    o.classify()
+    st = o.stats()
+    assert st["fallback_probe"] == 0 and st["fallback_none"] == 0
+    ir, dr = o.records()
+    top = [r for r in range(len(ir)) if ir[r, 0] // (c.ni * c.nj) == c.nk - 1]
+    assert top
+    for r in top:
+        ks = {int(cid) // (c.ni * c.nj) for cid in ir[r, 7:15] if cid >= 0}
+        assert ks == {c.nk - 1, 0}, ks
+        assert abs(dr[r, 9:17].sum() - 1.0) < 1e-14
