@@ -157,6 +157,13 @@ int ibm_status(ibm_ctx *ctx, void *stream);
 int ibm_read_counts(ibm_ctx *ctx, int32_t *host_counts, void *stream);
 
 int ibm_info_get(const ibm_ctx *ctx, ibm_info *out);
+
+/* Options.  IBM_OPT_GRAPHS (default 1): ibm_advance replays each step of a
+ * stationary-body solve as a captured HIP graph (launched on the caller's
+ * stream) instead of enqueuing its kernels one by one; 0 enqueues eagerly.
+ * Both give bit-identical results. */
+#define IBM_OPT_GRAPHS 1
+int ibm_set_option(ibm_ctx *ctx, int option, int value);
 const char *ibm_last_error(const ibm_ctx *ctx);
 
 /* Average device time in milliseconds of one launch of the fused

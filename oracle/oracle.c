@@ -884,6 +884,7 @@ static void node_geometry(orc *o, int r, long c, int is_forcing)
                 P[d] = X[d] + sig * dir[d];
         } else {
             fb |= 1;
+#pragma omp atomic
             o->stat_fallback_pprime++;
         }
     }
@@ -923,6 +924,7 @@ static void node_geometry(orc *o, int r, long c, int is_forcing)
             y2[d] = P[d] + s2 * n[d];
         }
         fb |= 2;
+#pragma omp atomic
         o->stat_fallback_probe++;
         mode1 = mode2 = 1;
         int v1 = probe_setup(o, y1, 1, allow_forcing, ids1, w1);
@@ -933,6 +935,7 @@ static void node_geometry(orc *o, int r, long c, int is_forcing)
             mode2 = 2;
         if (!v1 || (quad && !v2)) {
             fb |= 4;
+#pragma omp atomic
             o->stat_fallback_none++;
         }
     }
@@ -977,6 +980,8 @@ int orc_geometry(orc *o)
     free(o->drec);
     o->irec = (int32_t *)calloc((size_t)(nrec > 0 ? nrec : 1) * IREC, sizeof(int32_t));
     o->drec = (double *)calloc((size_t)(nrec > 0 ? nrec : 1) * DREC, sizeof(double));
+    /* one node per iteration; each writes only its own record */
+#pragma omp parallel for schedule(dynamic, 16)
     for (int r = 0; r < nrec; r++) {
         int forcing = r < o->nF;
         long c = forcing ? o->listF[r] : o->listG[r - o->nF];

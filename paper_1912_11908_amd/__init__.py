@@ -164,6 +164,10 @@ class Solver:
         _lib.check(self.L.ibm_advance(self.h, self._p(q), int(nsteps), self._s()),
                    "ibm_advance", self.h)
 
+    def set_graphs(self, on):
+        """Replay whole steps as HIP graphs (stationary bodies; default on)."""
+        _lib.check(self.L.ibm_set_option(self.h, 1, 1 if on else 0), "ibm_set_option", self.h)
+
     def status(self):
         return self.L.ibm_status(self.h, self._s())
 

@@ -19,7 +19,7 @@ REC_INT, REC_DBL = 24, 32
 EXPORTS = ["ibm_workspace_bytes", "ibm_create", "ibm_destroy", "ibm_set_time", "ibm_classify",
            "ibm_fill", "ibm_residual", "ibm_advance", "ibm_init_state", "ibm_state_to_prim",
            "ibm_status", "ibm_read_counts", "ibm_info_get", "ibm_last_error",
-           "ibm_time_update_kernel"]
+           "ibm_time_update_kernel", "ibm_set_option"]
 
 
 class IbmCase(ctypes.Structure):
@@ -84,6 +84,7 @@ def load():
     L.ibm_last_error.argtypes = [P]
     L.ibm_last_error.restype = ctypes.c_char_p
     L.ibm_time_update_kernel.argtypes = [P, P, I, I, P, ctypes.POINTER(ctypes.c_float)]
+    L.ibm_set_option.argtypes = [P, I, I]
     for name in EXPORTS:
         if name not in ("ibm_destroy", "ibm_last_error"):
             getattr(L, name).restype = ctypes.c_int

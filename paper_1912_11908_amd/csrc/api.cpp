@@ -27,6 +27,12 @@ struct ibm_ctx {
     long long step;
     int n_inner;
     bool classified;
+    // graph replay of whole steps (stationary bodies)
+    bool use_graphs;
+    hipStream_t cap_stream;
+    hipGraph_t graph;
+    hipGraphExec_t graph_exec;
+    const double *graph_q;
     long long rest_box_lat[6];
     char err[256];
 };
@@ -467,18 +473,14 @@ int do_classify(ibm_ctx *c, double t, hipStream_t s)
 
 int do_fill(ibm_ctx *c, double *q, double t, hipStream_t s)
 {
-    hipError_t e = launch_domain_bc(c->g, c->f, q, s);
-    if (e != hipSuccess)
-        return dev_err(c, e, "domain bc");
-    if (c->b.nfacet == 0)
-        return IBM_OK;
     double disp = 0.0, vel = 0.0, acc = 0.0;
     int axis = -1;
     if (c->mo.on) {
         motion_kin(c, t, disp, vel, acc);
         axis = c->mo.axis;
     }
-    e = launch_fill(c->g, c->f, c->ib, q, vel, acc, axis, s);
+    hipError_t e = c->b.nfacet == 0 ? launch_domain_bc(c->g, c->f, q, s)
+                                    : launch_bc_fill(c->g, c->f, c->ib, q, vel, acc, axis, s);
     return dev_err(c, e, "fill");
 }
 
@@ -644,6 +646,11 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     x->step = 0;
     x->n_inner = c->n_inner;
     x->classified = false;
+    x->use_graphs = true;
+    x->cap_stream = nullptr;
+    x->graph = nullptr;
+    x->graph_exec = nullptr;
+    x->graph_q = nullptr;
     if (e != hipSuccess) {
         delete x;
         return IBM_EDEVICE;
@@ -652,7 +659,38 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     return IBM_OK;
 }
 
-void ibm_destroy(ibm_ctx *c) { delete c; }
+static void drop_graph(ibm_ctx *c)
+{
+    if (c->graph_exec)
+        (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph)
+        (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+    c->graph_q = nullptr;
+}
+
+void ibm_destroy(ibm_ctx *c)
+{
+    if (!c)
+        return;
+    drop_graph(c);
+    if (c->cap_stream)
+        (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+}
+
+int ibm_set_option(ibm_ctx *c, int option, int value)
+{
+    if (!c)
+        return IBM_EINVAL;
+    if (option == IBM_OPT_GRAPHS) {
+        c->use_graphs = value != 0;
+        drop_graph(c);
+        return IBM_OK;
+    }
+    return IBM_EINVAL;
+}
 
 int ibm_set_time(ibm_ctx *c, double t)
 {
@@ -693,6 +731,91 @@ int ibm_residual(ibm_ctx *c, const double *q, double *r, void *stream)
     return dev_err(c, launch_residual(c->g, c->f, c->ib, q, r, S(stream)), "residual");
 }
 
+}  // extern "C"
+
+namespace {
+
+// One SSP-RK3 step (Shu-Osher) starting at time t; a fill at each stage time.
+int enqueue_rk3_step(ibm_ctx *c, double *q, double t, hipStream_t s)
+{
+    int rc;
+    double dt = c->f.dt;
+    if ((rc = do_fill(c, q, t, s)))
+        return rc;
+    if ((rc = dev_err(c, launch_rk_stage(c->g, c->f, c->ib, q, q, c->q1, 0.0, 1.0, s), "stage 1")))
+        return rc;
+    if ((rc = do_fill(c, c->q1, t + dt, s)))
+        return rc;
+    if ((rc = dev_err(c, launch_rk_stage(c->g, c->f, c->ib, q, c->q1, c->q2, 0.75, 0.25, s), "stage 2")))
+        return rc;
+    if ((rc = do_fill(c, c->q2, t + 0.5 * dt, s)))
+        return rc;
+    return dev_err(c, launch_rk_stage(c->g, c->f, c->ib, q, c->q2, q, 1.0 / 3.0, 2.0 / 3.0, s), "stage 3");
+}
+
+// One physical dual-time step ending at tn: history rotation, then n_inner
+// pseudo-iterations ping-ponging between q and the scratch state.
+int enqueue_dual_step(ibm_ctx *c, double *q, double tn, int first, hipStream_t s)
+{
+    int rc;
+    if ((rc = dev_err(c, launch_dual_begin(c->g, c->f, q, c->qn, c->qnm1, first, s), "dual begin")))
+        return rc;
+    double b0 = first ? 1.0 : 1.5, b2 = first ? 0.0 : 0.5;
+    double *cur = q, *nxt = c->wtmp;
+    for (int it = 0; it < c->n_inner; ++it) {
+        if ((rc = do_fill(c, cur, tn, s)))
+            return rc;
+        if ((rc = dev_err(c, launch_dual_iter(c->g, c->f, c->ib, cur, nxt, c->qn, c->qnm1, b0, b2, s),
+                          "dual iteration")))
+            return rc;
+        double *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+    if (cur != q)
+        return dev_err(c, launch_copy_state(c->g, cur, q, s), "copy");
+    return IBM_OK;
+}
+
+// Capture one step of a stationary-body solve into a graph (on a private
+// stream: the caller's stream may be the legacy default stream, which cannot
+// be captured).  Returns false if capture is unavailable; the caller then
+// enqueues eagerly.
+bool build_graph(ibm_ctx *c, double *q)
+{
+    if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        c->cap_stream = nullptr;
+        return false;
+    }
+    drop_graph(c);
+    if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return false;
+    int rc = c->f.scheme == IBM_RK3 ? enqueue_rk3_step(c, q, 0.0, c->cap_stream)
+                                    : enqueue_dual_step(c, q, 0.0, 0, c->cap_stream);
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &gr);
+    if (rc != IBM_OK || e != hipSuccess || !gr) {
+        if (gr)
+            (void)hipGraphDestroy(gr);
+        (void)hipGetLastError();
+        return false;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(gr);
+        (void)hipGetLastError();
+        return false;
+    }
+    c->graph = gr;
+    c->graph_exec = ex;
+    c->graph_q = q;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
 int ibm_advance(ibm_ctx *c, double *q, int nsteps, void *stream)
 {
     if (!c || !q || nsteps < 0)
@@ -701,51 +824,27 @@ int ibm_advance(ibm_ctx *c, double *q, int nsteps, void *stream)
     int rc;
     double dt = c->f.dt;
     for (int n = 0; n < nsteps; ++n) {
-        if (c->f.scheme == IBM_RK3) {
-            // SSP-RK3 (Shu-Osher); moving bodies are posed at t^n
-            double t = c->t;
-            if (c->mo.on || !c->classified)
-                if ((rc = do_classify(c, t, s)))
-                    return rc;
-            if ((rc = do_fill(c, q, t, s)))
+        bool rk = c->f.scheme == IBM_RK3;
+        // moving bodies are posed at t^n (RK3) or t^{n+1} (dual time)
+        double tpose = rk ? c->t : c->t + dt;
+        if (c->mo.on || !c->classified)
+            if ((rc = do_classify(c, tpose, s)))
                 return rc;
-            if ((rc = dev_err(c, launch_rk_stage(c->g, c->f, c->ib, q, q, c->q1, 0.0, 1.0, s), "stage 1")))
+        int first = !rk && c->step == 0;
+        bool graphable = c->use_graphs && !c->mo.on && !first;
+        if (graphable && c->graph_q != q && !build_graph(c, q))
+            graphable = false;
+        if (graphable) {
+            if ((rc = dev_err(c, hipGraphLaunch(c->graph_exec, s), "graph launch")))
                 return rc;
-            if ((rc = do_fill(c, c->q1, t + dt, s)))
+        } else if (rk) {
+            if ((rc = enqueue_rk3_step(c, q, c->t, s)))
                 return rc;
-            if ((rc = dev_err(c, launch_rk_stage(c->g, c->f, c->ib, q, c->q1, c->q2, 0.75, 0.25, s), "stage 2")))
-                return rc;
-            if ((rc = do_fill(c, c->q2, t + 0.5 * dt, s)))
-                return rc;
-            if ((rc = dev_err(c, launch_rk_stage(c->g, c->f, c->ib, q, c->q2, q, 1.0 / 3.0, 2.0 / 3.0, s), "stage 3")))
-                return rc;
-            c->t = t + dt;
         } else {
-            // dual time: BDF1 on the first physical step, BDF2 after; the
-            // body is posed at t^{n+1} and frozen over the pseudo-iterations
-            double tn = c->t + dt;
-            if (c->mo.on || !c->classified)
-                if ((rc = do_classify(c, tn, s)))
-                    return rc;
-            int first = c->step == 0;
-            if ((rc = dev_err(c, launch_dual_begin(c->g, c->f, q, c->qn, c->qnm1, first, s), "dual begin")))
+            if ((rc = enqueue_dual_step(c, q, c->t + dt, first, s)))
                 return rc;
-            double b0 = first ? 1.0 : 1.5, b2 = first ? 0.0 : 0.5;
-            double *cur = q, *nxt = c->wtmp;
-            for (int it = 0; it < c->n_inner; ++it) {
-                if ((rc = do_fill(c, cur, tn, s)))
-                    return rc;
-                if ((rc = dev_err(c, launch_dual_iter(c->g, c->f, c->ib, cur, nxt, c->qn, c->qnm1, b0, b2, s), "dual iteration")))
-                    return rc;
-                double *tmp = cur;
-                cur = nxt;
-                nxt = tmp;
-            }
-            if (cur != q)
-                if ((rc = dev_err(c, launch_copy_state(c->g, cur, q, s), "copy")))
-                    return rc;
-            c->t = tn;
         }
+        c->t += dt;
         c->step++;
     }
     return IBM_OK;

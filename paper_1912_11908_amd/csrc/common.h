@@ -81,8 +81,8 @@ hipError_t launch_records(const Grid &g, const Body &b, const Flow &f, IB &ib, h
 
 // flow.hip
 hipError_t launch_domain_bc(const Grid &g, const Flow &f, double *q, hipStream_t s);
-hipError_t launch_fill(const Grid &g, const Flow &f, const IB &ib, double *q, double ub_axis,
-                       double ab_axis, int axis, hipStream_t s);
+hipError_t launch_bc_fill(const Grid &g, const Flow &f, const IB &ib, double *q, double ub_axis,
+                          double ab_axis, int axis, hipStream_t s);
 hipError_t launch_residual(const Grid &g, const Flow &f, const IB &ib, const double *q, double *r,
                            hipStream_t s);
 hipError_t launch_rk_stage(const Grid &g, const Flow &f, const IB &ib, const double *qn,

@@ -132,11 +132,8 @@ __device__ inline void halo_cell(const Grid &g, long long t, int &i, int &j, int
     i = c < 3 ? c - 3 : g.ni + (c - 3);
 }
 
-__global__ void bc_kernel(Grid g, FreeStream fs, double *q, long long nhalo)
+__device__ inline void bc_cell(const Grid &g, const FreeStream &fs, double *q, long long t)
 {
-    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nhalo)
-        return;
     int i, j, k;
     halo_cell(g, t, i, j, k);
     int c[3] = {i, j, k}, n[3] = {g.ni, g.nj, g.nk};
@@ -158,6 +155,13 @@ __global__ void bc_kernel(Grid g, FreeStream fs, double *q, long long nhalo)
     long long src = sidx(g, c[0], c[1], c[2]);
     for (int v = 0; v < g.nv; ++v)
         q[dst + v * g.vs] = farfield ? fs.v[v] : q[src + v * g.vs];
+}
+
+__global__ void bc_kernel(Grid g, FreeStream fs, double *q, long long nhalo)
+{
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nhalo)
+        bc_cell(g, fs, q, t);
 }
 
 // ------------------------------------------------------------ IB fill
@@ -186,15 +190,9 @@ __device__ inline void probe_value(const Grid &g, const Flow &f, const double *q
     }
 }
 
-__global__ void fill_kernel(Grid g, Flow f, IB ib, double *q, int which, double ub, double ab,
-                            int axis)
+__device__ inline void fill_one(const Grid &g, const Flow &f, const IB &ib, double *q, int r,
+                                double ub, double ab, int axis)
 {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    int nF = min(ib.counts[CNT_F], ib.cap);
-    int nG = min(ib.counts[CNT_G], ib.cap - nF);
-    int r = which == 0 ? t : nF + t;
-    if (t >= (which == 0 ? nF : nG))
-        return;
     int nd = g.ndim;
     bool quad = f.family == IBM_IB_QUADRATIC;
     const int *ir = ib.rec_i + (long long)kRecI * r;
@@ -245,6 +243,35 @@ __global__ void fill_kernel(Grid g, Flow f, IB ib, double *q, int which, double 
     int c = ir[0];
     int i = c % g.ni, j = (c / g.ni) % g.nj, k = c / (g.ni * g.nj);
     store_prim(g, f, res, q, sidx(g, i, j, k));
+}
+
+
+// Domain ghosts (blocks [0, nbb)) and forcing nodes (the remaining blocks,
+// grid-stride) in one launch: the forcing fill reads interior FLUID cells
+// only, the ghost layers never, so the two are independent.
+__global__ void bc_forcing_kernel(Grid g, FreeStream fs, Flow f, IB ib, double *q, long long nhalo,
+                                  int nbb, double ub, double ab, int axis)
+{
+    if ((int)blockIdx.x < nbb) {
+        long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+        if (t < nhalo)
+            bc_cell(g, fs, q, t);
+        return;
+    }
+    int nF = min(ib.counts[CNT_F], ib.cap);
+    int stride = (gridDim.x - nbb) * blockDim.x;
+    for (int r = (blockIdx.x - nbb) * blockDim.x + threadIdx.x; r < nF; r += stride)
+        fill_one(g, f, ib, q, r, ub, ab, axis);
+}
+
+// Ghost layers G1-G3 (they read FLUID and FORCING cells), grid-stride.
+__global__ void ghost_fill_kernel(Grid g, Flow f, IB ib, double *q, double ub, double ab, int axis)
+{
+    int nF = min(ib.counts[CNT_F], ib.cap);
+    int nG = min(ib.counts[CNT_G], ib.cap - nF);
+    int stride = gridDim.x * blockDim.x;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nG; t += stride)
+        fill_one(g, f, ib, q, nF + t, ub, ab, axis);
 }
 
 // ------------------------------------------------ fused residual / update
@@ -330,8 +357,8 @@ __device__ inline R dsum_minus1(R mL, R mR, R dp, R dm, bool subL, bool subR)
 // unpreconditioned Mach numbers with its velocity-diffusion part scaled by
 // a~ / a_half.  Momentum flux excludes the constant p_inf; the energy slot
 // holds the H' part (total flux = H_inf * mass flux + this).
-template <typename R, int NV>
-__device__ inline void ldfss_pert(const R *wl, const R *wr, int d, const FlowR<R> &fp, R *fl_out)
+template <typename R, int NV, int d>
+__device__ inline void ldfss_pert(const R *wl, const R *wr, const FlowR<R> &fp, R *fl_out)
 {
     constexpr int ND = NV - 2;
     R rl = R(1) + wl[0], rr = R(1) + wr[0];
@@ -390,6 +417,102 @@ __device__ inline void ldfss_pert(const R *wl, const R *wr, int d, const FlowR<R
     R hl = g1 * (plp - fp.pinf * wl[0]) * rcp_fast<R>(rl) + R(0.5) * (ql2 - R(1));
     R hr = g1 * (prp - fp.pinf * wr[0]) * rcp_fast<R>(rr) + R(0.5) * (qr2 - R(1));
     fl_out[NV - 1] = fl * hl + fr * hr;
+}
+
+template <typename Real> __device__ inline Real metric(const double *d64, const float *d32, int idx)
+{
+    if constexpr (sizeof(Real) == 4)
+        return d32[idx];
+    else
+        return d64[idx];
+}
+
+// Flux through the face between tile-local cells L (LDS index `base`) and
+// L + e_D: WENO5 face states, LDFSS, minus the central viscous flux.
+// gc: global coordinates of L.
+template <int DIM, int D, typename Real, int LX, int LY, int LCELLS>
+__device__ inline void face_flux(const Real *__restrict__ S, int base, const int *gc, const Grid &g,
+                                 const FlowR<Real> &fp, Real *flux)
+{
+    constexpr int NV = DIM + 2;
+    constexpr int SD = D == 0 ? 1 : (D == 1 ? LX : LX * LY);
+    Real wl[NV], wr[NV];
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+        const Real *s = S + m * LCELLS + base;
+        Real v0 = s[-2 * SD], v1 = s[-SD], v2 = s[0], v3 = s[SD], v4 = s[2 * SD], v5 = s[3 * SD];
+        wl[m] = weno5<Real>(v0, v1, v2, v3, v4);
+        wr[m] = weno5<Real>(v5, v4, v3, v2, v1);
+    }
+    ldfss_pert<Real, NV, D>(wl, wr, fp, flux);
+
+    // viscous flux: tau = mu (grad u + grad u^T - 2/3 div u I), q = -k grad T;
+    // normal derivatives from the two cells, tangential ones the mean of the
+    // two cells' central differences, face velocity the mean of the cells
+    const Real *SU = S + LCELLS;
+    const Real *ST = S + (DIM + 2) * LCELLS;
+    Real rdn = metric<Real>(g.rdxc[D], g.rdxc_f[D], gc[D] + 3);
+    Real dudn[DIM], uf[DIM];
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) {
+        Real uL = SU[m * LCELLS + base], uR = SU[m * LCELLS + base + SD];
+        dudn[m] = (uR - uL) * rdn;
+        uf[m] = Real(0.5) * (uL + uR);
+    }
+    Real dTdn = (ST[base + SD] - ST[base]) * rdn;
+    Real div = dudn[D];
+    Real tau[DIM];
+#pragma unroll
+    for (int e = 0; e < DIM; ++e) {
+        if (e == D)
+            continue;
+        const int SE = e == 0 ? 1 : (e == 1 ? LX : LX * LY);
+        Real rt = metric<Real>(g.rdtc[e], g.rdtc_f[e], gc[e] + 3);
+        const Real *UD = SU + D * LCELLS, *UE = SU + e * LCELLS;
+        Real dUD = Real(0.5) * ((UD[base + SE] - UD[base - SE]) + (UD[base + SD + SE] - UD[base + SD - SE])) * rt;
+        Real dUE = Real(0.5) * ((UE[base + SE] - UE[base - SE]) + (UE[base + SD + SE] - UE[base + SD - SE])) * rt;
+        div += dUE;
+        tau[e] = fp.mu * (dudn[e] + dUD);
+    }
+    tau[D] = fp.mu * (Real(2) * dudn[D] - Real(2.0 / 3.0) * div);
+    Real work = Real(0);
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) {
+        flux[1 + m] -= tau[m];
+        work += uf[m] * tau[m];
+    }
+    flux[NV - 1] -= work + fp.kc * dTdn;
+}
+
+// All faces of direction D in a tile, written to F at offset `off`.
+template <int DIM, int D, typename Real, int TX, int TY, int TZ, int HZ>
+__device__ inline void face_pass(const Real *__restrict__ S, Real *__restrict__ F, int NFACE, int off,
+                                 int i0, int j0, int k0, const Grid &g, const FlowR<Real> &fp, int tid)
+{
+    constexpr int LX = TX + 6, LY = TY + 6, LZ = TZ + 2 * HZ;
+    constexpr int LCELLS = LX * LY * LZ;
+    constexpr int NV = DIM + 2;
+    constexpr int FX = TX + (D == 0), FY = TY + (D == 1), FZ = TZ + (D == 2);
+    constexpr int NF = FX * FY * FZ;
+    for (int fi = tid; fi < NF; fi += kBlock) {
+        int fx = fi % FX, fy = (fi / FX) % FY, fz = fi / (FX * FY);
+        int lc[3] = {fx - (D == 0), fy - (D == 1), fz - (D == 2)};
+        int gc[3] = {i0 + lc[0], j0 + lc[1], k0 + lc[2]};
+        // the face is needed if its left cell lies in [-1, n) along D and
+        // the transverse coordinates are interior
+        bool need = true;
+        if (D == 0) need = gc[0] >= -1 && gc[0] < g.ni && gc[1] < g.nj && (DIM == 2 || gc[2] < g.nk);
+        if (D == 1) need = gc[1] >= -1 && gc[1] < g.nj && gc[0] < g.ni && (DIM == 2 || gc[2] < g.nk);
+        if (D == 2) need = gc[2] >= -1 && gc[2] < g.nk && gc[0] < g.ni && gc[1] < g.nj;
+        if (!need)
+            continue;
+        int base = (lc[0] + 3) + (lc[1] + 3) * LX + (DIM == 3 ? (lc[2] + HZ) * LX * LY : 0);
+        Real flux[NV];
+        face_flux<DIM, D, Real, LX, LY, LCELLS>(S, base, gc, g, fp, flux);
+#pragma unroll
+        for (int m = 0; m < NV; ++m)
+            F[m * NFACE + off + fi] = flux[m];
+    }
 }
 
 template <int DIM, typename Real, int MODE>
@@ -469,108 +592,11 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs A)
     fp.kc = (Real)f.kc;
     fp.uc2 = (Real)f.uc2;
     fp.precond = f.scheme == IBM_DUAL;
-    const int strides[3] = {1, LX, LX * LY};
-    const int ext[3] = {g.ni, g.nj, g.nk};
-    const int org[3] = {i0, j0, k0};
-
-    // 2. face fluxes (all directions in one flat loop)
-    for (int fi = tid; fi < NFACE; fi += kBlock) {
-        int d, fx, fy, fz;
-        if (fi < NF0) {
-            d = 0;
-            fx = fi % (TX + 1);
-            fy = (fi / (TX + 1)) % TY;
-            fz = fi / ((TX + 1) * TY);
-        } else if (fi < NF0 + NF1) {
-            int r = fi - NF0;
-            d = 1;
-            fx = r % TX;
-            fy = (r / TX) % (TY + 1);
-            fz = r / (TX * (TY + 1));
-        } else {
-            int r = fi - NF0 - NF1;
-            d = 2;
-            fx = r % TX;
-            fy = (r / TX) % TY;
-            fz = r / (TX * TY);
-        }
-        // left cell of the face, tile-local
-        int lc[3] = {fx, fy, fz};
-        lc[d] -= 1;
-        int gc[3] = {i0 + lc[0], j0 + lc[1], k0 + lc[2]};
-        // needed only if both sides lie within [-1, n] along d and the
-        // transverse coordinates are interior
-        bool need = gc[d] >= -1 && gc[d] < ext[d];
-        for (int e = 0; e < DIM; ++e)
-            if (e != d && gc[e] >= ext[e])
-                need = false;
-        if (!need)
-            continue;
-        int base = (lc[0] + 3) + (lc[1] + 3) * LX + (DIM == 3 ? (lc[2] + HZ) * LX * LY : 0);
-        int sd = strides[d];
-        Real wl[NV], wr[NV];
-#pragma unroll
-        for (int m = 0; m < NV; ++m) {
-            const Real *s = S + m * LCELLS + base;
-            Real v0 = s[-2 * sd], v1 = s[-sd], v2 = s[0], v3 = s[sd], v4 = s[2 * sd], v5 = s[3 * sd];
-            wl[m] = weno5<Real>(v0, v1, v2, v3, v4);
-            wr[m] = weno5<Real>(v5, v4, v3, v2, v1);
-        }
-        Real flux[NV];
-        ldfss_pert<Real, NV>(wl, wr, d, fp, flux);
-
-        // viscous flux: central differences, face velocity the mean of the
-        // two cells, tangential gradients the mean of both cells' central
-        // differences
-        Real grad[DIM + 1][DIM];  // rows: u_0.., T; columns: derivative axis
-        const Real *SU = S + LCELLS;  // u_0 at var 1
-        const Real *ST = S + (DIM + 2) * LCELLS;
-        Real rdn = (Real)g.rdxc[d][gc[d] + 3];
-        if constexpr (sizeof(Real) == 4)
-            rdn = g.rdxc_f[d][gc[d] + 3];
-#pragma unroll
-        for (int m = 0; m < DIM; ++m)
-            grad[m][d] = (SU[m * LCELLS + base + sd] - SU[m * LCELLS + base]) * rdn;
-        grad[DIM][d] = (ST[base + sd] - ST[base]) * rdn;
-#pragma unroll
-        for (int e = 0; e < DIM; ++e) {
-            if (e == d)
-                continue;
-            int se = strides[e];
-            Real rl, rr;
-            if constexpr (sizeof(Real) == 4) {
-                rl = g.rdtc_f[e][gc[e] + 3];
-                rr = rl;
-            } else {
-                rl = (Real)g.rdtc[e][gc[e] + 3];
-                rr = rl;
-            }
-            (void)rr;
-#pragma unroll
-            for (int m = 0; m <= DIM; ++m) {
-                const Real *P = m < DIM ? SU + m * LCELLS : ST;
-                Real gl = (P[base + se] - P[base - se]) * rl;
-                Real gr = (P[base + sd + se] - P[base + sd - se]) * rl;
-                grad[m][e] = Real(0.5) * (gl + gr);
-            }
-        }
-        Real div = Real(0);
-#pragma unroll
-        for (int m = 0; m < DIM; ++m)
-            div += grad[m][m];
-        Real work = Real(0);
-#pragma unroll
-        for (int m = 0; m < DIM; ++m) {
-            Real tau = fp.mu * (grad[m][d] + grad[d][m] - (m == d ? Real(2.0 / 3.0) * div : Real(0)));
-            Real uf = Real(0.5) * (SU[m * LCELLS + base] + SU[m * LCELLS + base + sd]);
-            flux[1 + m] -= tau;
-            work += uf * tau;
-        }
-        flux[NV - 1] -= work + fp.kc * grad[DIM][d];
-#pragma unroll
-        for (int m = 0; m < NV; ++m)
-            F[m * NFACE + fi] = flux[m];
-    }
+    // 2. face fluxes, one pass per direction (compile-time direction)
+    face_pass<DIM, 0, Real, TX, TY, TZ, HZ>(S, F, NFACE, 0, i0, j0, k0, g, fp, tid);
+    face_pass<DIM, 1, Real, TX, TY, TZ, HZ>(S, F, NFACE, NF0, i0, j0, k0, g, fp, tid);
+    if constexpr (DIM == 3)
+        face_pass<DIM, 2, Real, TX, TY, TZ, HZ>(S, F, NFACE, NF0 + NF1, i0, j0, k0, g, fp, tid);
     __syncthreads();
 
     // 3. per-cell residual and update
@@ -582,9 +608,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs A)
     uint8_t cls = A.cls[cell];
     long long s = sidx(g, i, j, k);
     if (MODE != MODE_RESID) {
-        if (cls == IBM_SOLID)
-            return;
-        if (cls != IBM_FLUID) {  // IB nodes carry their filled value
+        if (cls != IBM_FLUID) {  // IB nodes carry their filled value, solid cells their state
 #pragma unroll
             for (int m = 0; m < NV; ++m)
                 A.out[s + m * g.vs] = A.qin[s + m * g.vs];
@@ -600,15 +624,9 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs A)
     int fl1 = NF0 + (tz * (TY + 1) + ty) * TX + tx;  // y-face at j - 1/2
     int fl2 = NF0 + NF1 + (tz * TY + ty) * TX + tx;  // z-face at k - 1/2
     Real rd[3];
-    if constexpr (sizeof(Real) == 4) {
-        rd[0] = g.rdx_f[0][i + 3];
-        rd[1] = g.rdx_f[1][j + 3];
-        rd[2] = DIM == 3 ? g.rdx_f[2][k + 3] : Real(0);
-    } else {
-        rd[0] = (Real)g.rdx[0][i + 3];
-        rd[1] = (Real)g.rdx[1][j + 3];
-        rd[2] = DIM == 3 ? (Real)g.rdx[2][k + 3] : Real(0);
-    }
+    rd[0] = metric<Real>(g.rdx[0], g.rdx_f[0], i + 3);
+    rd[1] = metric<Real>(g.rdx[1], g.rdx_f[1], j + 3);
+    rd[2] = DIM == 3 ? metric<Real>(g.rdx[2], g.rdx_f[2], k + 3) : Real(0);
     double R[NV];
 #pragma unroll
     for (int m = 0; m < NV; ++m) {
@@ -862,7 +880,7 @@ hipError_t dispatch_step(const Grid &g, const Flow &f, const IB &ib, const doubl
 
 }  // namespace
 
-hipError_t launch_domain_bc(const Grid &g, const Flow &f, double *q, hipStream_t s)
+static FreeStream freestream_of(const Grid &g, const Flow &f)
 {
     FreeStream fs;
     for (int m = 0; m < 5; ++m)
@@ -874,20 +892,30 @@ hipError_t launch_domain_bc(const Grid &g, const Flow &f, double *q, hipStream_t
     } else {
         fs.v[1] = 1.0;
     }
+    return fs;
+}
+
+hipError_t launch_domain_bc(const Grid &g, const Flow &f, double *q, hipStream_t s)
+{
     long long nhalo = (long long)g.sx * g.sy * g.sz - g.ncell;
-    hipLaunchKernelGGL(bc_kernel, dim3(blocks_for(nhalo, kBlock)), dim3(kBlock), 0, s, g, fs, q,
-                       nhalo);
+    hipLaunchKernelGGL(bc_kernel, dim3(blocks_for(nhalo, kBlock)), dim3(kBlock), 0, s, g,
+                       freestream_of(g, f), q, nhalo);
     return hipGetLastError();
 }
 
-hipError_t launch_fill(const Grid &g, const Flow &f, const IB &ib, double *q, double ub_axis,
-                       double ab_axis, int axis, hipStream_t s)
+hipError_t launch_bc_fill(const Grid &g, const Flow &f, const IB &ib, double *q, double ub_axis,
+                          double ab_axis, int axis, hipStream_t s)
 {
     if (ib.cap == 0)
-        return hipSuccess;
-    int nb = blocks_for(ib.cap, 64);
-    hipLaunchKernelGGL(fill_kernel, dim3(nb), dim3(64), 0, s, g, f, ib, q, 0, ub_axis, ab_axis, axis);
-    hipLaunchKernelGGL(fill_kernel, dim3(nb), dim3(64), 0, s, g, f, ib, q, 1, ub_axis, ab_axis, axis);
+        return launch_domain_bc(g, f, q, s);
+    long long nhalo = (long long)g.sx * g.sy * g.sz - g.ncell;
+    int nbb = blocks_for(nhalo, kBlock);
+    int nbf = blocks_for(ib.cap, kBlock);
+    nbf = nbf < 128 ? nbf : 128;
+    hipLaunchKernelGGL(bc_forcing_kernel, dim3(nbb + nbf), dim3(kBlock), 0, s, g, freestream_of(g, f),
+                       f, ib, q, nhalo, nbb, ub_axis, ab_axis, axis);
+    hipLaunchKernelGGL(ghost_fill_kernel, dim3(nbf), dim3(kBlock), 0, s, g, f, ib, q, ub_axis, ab_axis,
+                       axis);
     return hipGetLastError();
 }
 

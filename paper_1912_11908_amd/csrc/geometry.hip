@@ -62,7 +62,9 @@ __device__ inline int lower_bound_ll(const long long *X, int lo, int hi, long lo
 // prefix of the row, found by binary search; one bit toggles at its end.
 __global__ void cross2d_kernel(Grid g, Body b, IB ib)
 {
-    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    // one wavefront per facet, lanes over the crossed rows
+    int f = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    int lane = threadIdx.x & (kWave - 1);
     if (f >= b.nfacet)
         return;
     const long long *A = b.V + 2 * b.facet[2 * f];
@@ -76,7 +78,7 @@ __global__ void cross2d_kernel(Grid g, Body b, IB ib)
     int j0 = lower_bound_ll(Y, ib.region[2], ib.region[3], ylo);
     int j1 = lower_bound_ll(Y, ib.region[2], ib.region[3], yhi);
     long long dxab = B[0] - A[0], dyab = B[1] - A[1];
-    for (int j = j0; j < j1; ++j) {
+    for (int j = j0 + lane; j < j1; j += kWave) {
         long long py = Y[j];
         // crossing strictly right of px <=> orient * sign(dy) > 0, which is
         // true on a prefix of the row
@@ -664,13 +666,19 @@ __device__ bool probe_setup(const Grid &g, const uint8_t *cls, const double *y, 
 // Sections 4.1-4.3: closest feature, local normal (face normal or the
 // pseudo-normals of eqs 2-3), boundary point P' where the line through the
 // node parallel to the normal meets the surface, and probes along it.
+__device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib, int r, int nF);
+
 __global__ void records_kernel(Grid g, Body b, Flow fl, IB ib)
 {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
     int nF = min(ib.counts[CNT_F], ib.cap);
     int nG = min(ib.counts[CNT_G], ib.cap - nF);
-    if (r >= nF + nG)
-        return;
+    int stride = gridDim.x * blockDim.x;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nF + nG; r += stride)
+        node_record(g, b, fl, ib, r, nF);
+}
+
+__device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib, int r, int nF)
+{
     bool forcing = r < nF;
     int c = forcing ? ib.listF[r] : ib.listG[r - nF];
     int nd = g.ndim;
@@ -809,8 +817,8 @@ hipError_t launch_classify(const Grid &g, const Body &b, IB &ib, hipStream_t s)
                        ncell, ib.toggle, nwords);
     if (b.nfacet > 0) {
         if (g.ndim == 2)
-            hipLaunchKernelGGL(cross2d_kernel, dim3(blocks_for(b.nfacet, 64)), dim3(64), 0, s, g, b,
-                               ib);
+            hipLaunchKernelGGL(cross2d_kernel, dim3(blocks_for(b.nfacet, kBlock / kWave)), dim3(kBlock),
+                               0, s, g, b, ib);
         else
             hipLaunchKernelGGL(cross3d_kernel, dim3(blocks_for(b.nfacet, 64)), dim3(64), 0, s, g, b,
                                ib);
@@ -828,7 +836,9 @@ hipError_t launch_records(const Grid &g, const Body &b, const Flow &f, IB &ib, h
 {
     if (ib.cap == 0 || b.nfacet == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(records_kernel, dim3(blocks_for(ib.cap, 64)), dim3(64), 0, s, g, b, f, ib);
+    int nb = blocks_for(ib.cap, 64);
+    nb = nb < 1024 ? nb : 1024;
+    hipLaunchKernelGGL(records_kernel, dim3(nb), dim3(64), 0, s, g, b, f, ib);
     return hipGetLastError();
 }
 

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import workloads as w
-from gpu_common import make_pair, smooth_prim, compare_fields, rel_l2, tol64
+from gpu_common import make_pair, smooth_prim, compare_fields, rel_l2, tol64, resid_tol_abs
 
 pytestmark = pytest.mark.gpu
 
@@ -72,13 +72,19 @@ def test_fill_and_residual_fp64(kind):
     q = o.prim_to_state(prim)
     o.bc(q)
     o.fill(q, 0.0)
-    got = s.state.cpu().numpy()
-    errs = compare_fields(got.reshape(q.shape), q)
+    got = s.state.cpu().numpy().reshape(q.shape)
+    errs = compare_fields(got, q)
+    if case.scheme == "dual":
+        # p' carries O(eps p_inf) absolute rounding on both sides; compare it
+        # against the dynamic pressure (rho U^2 = 1) instead
+        assert np.abs(got[0] - q[0]).max() < tol64(case)
+        errs = errs[1:]
     assert errs.max() < 1e-13, errs
     r = s.residual().cpu().numpy()
     ro = o.residual(q)
-    errs = compare_fields(r, ro)
-    assert errs.max() < tol64(case), errs
+    for v in range(ro.shape[0]):
+        err = np.abs(r[v] - ro[v]).max()
+        assert err <= max(TOL64 * np.abs(ro[v]).max(), resid_tol_abs(case, v)), (v, err)
     assert np.abs(ro).max() > 0
 
 
@@ -165,3 +171,84 @@ def test_mixed_precision_error(kind):
     errs = compare_fields(gp, op)
     print(kind, "mixed rel L2 per primitive", errs)
     assert errs.max() < 1e-4, errs
+
+
+@pytest.mark.parametrize("kind", ["wedge", "naca", "tube-static"])
+def test_graph_replay_matches_eager(kind):
+    """Whole-step HIP graph replay gives bit-identical states to eager
+    launches, replay after replay, with eager work and synchronisations in
+    between."""
+    import torch
+    case = SMALL[kind]()
+    prim = smooth_prim(case)
+    from paper_1912_11908_amd import Solver
+    a = Solver(case, "fp64", "cuda:0")
+    b = Solver(case, "fp64", "cuda:0")
+    b.set_graphs(False)
+    for s in (a, b):
+        s.init_prim(prim)
+        s.classify()
+    for step in range(4):
+        a.advance(1)
+        torch.cuda.synchronize()
+        junk = torch.randn(1000, device="cuda").sum()   # eager work between replays
+        b.advance(1)
+        torch.cuda.synchronize()
+        assert bool((a.state == b.state).all()), (kind, step)
+        del junk
+    a.check_status()
+
+
+def _full_prefix(case, steps, precision="fp64"):
+    prim = w.freestream_prim(case.ndim, case.ni, case.nj, case.nk, case.p_inf)
+    s, o = make_pair(case, prim, precision)
+    s.classify()
+    o.classify()
+    assert np.array_equal(s.classes(), o.classes())
+    s.advance(steps)
+    s.check_status()
+    q = o.prim_to_state(prim)
+    o.run(q, steps)
+    return s, o, q
+
+
+def test_c2_full_size_prefix_fp64():
+    """Wedge at its full 1024x512 size: classification exact, 5 RK3 steps."""
+    case = w.case_c2()
+    s, o, q = _full_prefix(case, 5)
+    errs = compare_fields(s.interior().cpu().numpy(), o.interior(q))
+    assert errs.max() < TOL64, errs
+
+
+def test_c3_full_size_prefix_fp64():
+    """NACA 0012 at M = 0.001 at its full 2048x1024 size: classification
+    exact, one physical dual-time step of 20 pseudo-iterations."""
+    case = w.case_c3()
+    s, o, q = _full_prefix(case, 1)
+    gp = s.to_prim().cpu().numpy()
+    op = o.state_to_prim(q)
+    errs = compare_fields(gp, op)
+    assert errs.max() < tol64(case), errs
+    assert np.abs(gp[3] - op[3]).max() < 1e-6   # p' against rho U^2 = 1
+
+
+def test_c4_full_size_prefix_fp64():
+    """Oscillating tube at its full 384x256x64 size with 65,536 triangles:
+    classification and records exact at the pose of t = 0, one RK3 step
+    (reclassified at the step's pose)."""
+    case = w.case_c4()
+    prim = w.freestream_prim(3, case.ni, case.nj, case.nk, case.p_inf)
+    s, o = make_pair(case, prim)
+    s.classify()
+    o.classify()
+    assert np.array_equal(s.classes(), o.classes())
+    ir, dr = s.records()
+    oir, odr = o.records()
+    assert np.array_equal(ir[:, :23], oir[:, :23])
+    assert np.abs(dr[:, :26] - odr[:, :26]).max() <= 1e-14
+    s.advance(1)
+    s.check_status()
+    q = o.prim_to_state(prim)
+    o.run(q, 1)
+    errs = compare_fields(s.interior().cpu().numpy(), o.interior(q))
+    assert errs.max() < TOL64, errs

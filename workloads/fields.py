@@ -23,10 +23,12 @@ def freestream_prim(ndim, ni, nj, nk, p_ref, velocity=(1.0, 0.0, 0.0), rho=1.0):
 
 
 def random_periodic_prim(ndim, xf, yf, zf, p_ref, seed=0, modes=3, amp=0.05,
-                         u_amp=0.3):
+                         u_amp=0.3, p_amp=None):
     """Smooth periodic random field: a few Fourier modes per variable with
     seeded amplitudes and phases (numpy PCG64).  The box must be periodic in
-    every direction for the field to be smooth across the boundaries."""
+    every direction for the field to be smooth across the boundaries.
+    Relative amplitudes: amp for density, p_amp (default amp) for pressure,
+    u_amp absolute for velocity."""
     rng = np.random.Generator(np.random.PCG64(seed))
     xs = [_centres(xf), _centres(yf)] + ([_centres(zf)] if ndim == 3 else [np.zeros(1)])
     lens = [xf[-1] - xf[0], yf[-1] - yf[0], (zf[-1] - zf[0]) if ndim == 3 else 1.0]
@@ -50,7 +52,7 @@ def random_periodic_prim(ndim, xf, yf, zf, p_ref, seed=0, modes=3, amp=0.05,
     out[0] = 1.0 + amp * smooth()
     for d in range(ndim):
         out[1 + d] = (1.0 if d == 0 else 0.0) + u_amp * smooth()
-    out[nv - 1] = p_ref * (1.0 + amp * smooth())
+    out[nv - 1] = p_ref * (1.0 + (amp if p_amp is None else p_amp) * smooth())
     return out
 
 
