@@ -29,7 +29,8 @@ struct ibm_ctx {
     bool classified;
     // graph replay of whole steps (stationary bodies)
     bool use_graphs;
-    hipStream_t cap_stream;
+    hipStream_t cap_stream, cap_side;
+    hipEvent_t ev_fork, ev_join;
     hipGraph_t graph;
     hipGraphExec_t graph_exec;
     const double *graph_q;
@@ -368,6 +369,8 @@ struct Layout {
     uint32_t *toggle;
     int32_t *counts, *blk, *listF, *listG, *rec_i;
     double *rec_d;
+    int32_t *plan_node, *plan_off, *plan_mode;
+    double *plan_w, *plan_geo;
     double *q1, *q2, *wtmp, *qn, *qnm1;
 };
 
@@ -408,6 +411,11 @@ size_t carve(const ibm_case *c, const HostGeom &h, char *base, Layout &L)
     L.listG = cv.take<int32_t>(cap);
     L.rec_i = cv.take<int32_t>(cap * kRecI);
     L.rec_d = cv.take<double>(cap * kRecD);
+    L.plan_node = cv.take<int32_t>(cap);
+    L.plan_off = cv.take<int32_t>(16 * cap);
+    L.plan_w = cv.take<double>(16 * cap);
+    L.plan_geo = cv.take<double>(6 * cap);
+    L.plan_mode = cv.take<int32_t>(cap);
     size_t st = (size_t)h.vs * (nd + 2);
     L.q1 = L.q2 = L.wtmp = L.qn = L.qnm1 = nullptr;
     if (c->scheme == IBM_RK3) {
@@ -629,6 +637,11 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     ib.listG = L.listG;
     ib.rec_i = L.rec_i;
     ib.rec_d = L.rec_d;
+    ib.plan_node = L.plan_node;
+    ib.plan_off = L.plan_off;
+    ib.plan_w = L.plan_w;
+    ib.plan_geo = L.plan_geo;
+    ib.plan_mode = L.plan_mode;
     if (e == hipSuccess) e = hipMemset(L.cls, IBM_FLUID, (size_t)h.ncell);
     if (e == hipSuccess) e = hipMemset(L.counts, 0, sizeof(int32_t) * CNT_WORDS);
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -648,6 +661,9 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     x->classified = false;
     x->use_graphs = true;
     x->cap_stream = nullptr;
+    x->cap_side = nullptr;
+    x->ev_fork = nullptr;
+    x->ev_join = nullptr;
     x->graph = nullptr;
     x->graph_exec = nullptr;
     x->graph_q = nullptr;
@@ -677,6 +693,12 @@ void ibm_destroy(ibm_ctx *c)
     drop_graph(c);
     if (c->cap_stream)
         (void)hipStreamDestroy(c->cap_stream);
+    if (c->cap_side)
+        (void)hipStreamDestroy(c->cap_side);
+    if (c->ev_fork)
+        (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join)
+        (void)hipEventDestroy(c->ev_join);
     delete c;
 }
 
@@ -735,42 +757,83 @@ int ibm_residual(ibm_ctx *c, const double *q, double *r, void *stream)
 
 namespace {
 
+// Optional fork for one stage: tiles whose stencils read no cell written by
+// the fill run on a side stream concurrently with the fill chain; the tiles
+// near the body or the domain boundary follow the fill on the main stream.
+struct Split {
+    hipStream_t side;
+    hipEvent_t fork, join;
+};
+
+template <typename Launch>
+int enqueue_stage(ibm_ctx *c, double *qin, double t, hipStream_t s, const Split *sp, Launch launch)
+{
+    int rc;
+    if (!sp) {
+        if ((rc = do_fill(c, qin, t, s)))
+            return rc;
+        return dev_err(c, launch(s, 0), "stage");
+    }
+    hipError_t e = hipEventRecord(sp->fork, s);
+    if (e == hipSuccess)
+        e = hipStreamWaitEvent(sp->side, sp->fork, 0);
+    if (e == hipSuccess)
+        e = launch(sp->side, 1);
+    if ((rc = dev_err(c, e, "stage (far tiles)")))
+        return rc;
+    if ((rc = do_fill(c, qin, t, s)))
+        return rc;
+    e = launch(s, 2);
+    if (e == hipSuccess)
+        e = hipEventRecord(sp->join, sp->side);
+    if (e == hipSuccess)
+        e = hipStreamWaitEvent(s, sp->join, 0);
+    return dev_err(c, e, "stage (near tiles)");
+}
+
 // One SSP-RK3 step (Shu-Osher) starting at time t; a fill at each stage time.
-int enqueue_rk3_step(ibm_ctx *c, double *q, double t, hipStream_t s)
+int enqueue_rk3_step(ibm_ctx *c, double *q, double t, hipStream_t s, const Split *sp = nullptr)
 {
     int rc;
     double dt = c->f.dt;
-    if ((rc = do_fill(c, q, t, s)))
+    const Grid &g = c->g;
+    const Flow &f = c->f;
+    const IB &ib = c->ib;
+    double *q1 = c->q1, *q2 = c->q2;
+    if ((rc = enqueue_stage(c, q, t, s, sp, [&](hipStream_t st, int set) {
+             return launch_rk_stage(g, f, ib, q, q, q1, 0.0, 1.0, st, set);
+         })))
         return rc;
-    if ((rc = dev_err(c, launch_rk_stage(c->g, c->f, c->ib, q, q, c->q1, 0.0, 1.0, s), "stage 1")))
+    if ((rc = enqueue_stage(c, q1, t + dt, s, sp, [&](hipStream_t st, int set) {
+             return launch_rk_stage(g, f, ib, q, q1, q2, 0.75, 0.25, st, set);
+         })))
         return rc;
-    if ((rc = do_fill(c, c->q1, t + dt, s)))
-        return rc;
-    if ((rc = dev_err(c, launch_rk_stage(c->g, c->f, c->ib, q, c->q1, c->q2, 0.75, 0.25, s), "stage 2")))
-        return rc;
-    if ((rc = do_fill(c, c->q2, t + 0.5 * dt, s)))
-        return rc;
-    return dev_err(c, launch_rk_stage(c->g, c->f, c->ib, q, c->q2, q, 1.0 / 3.0, 2.0 / 3.0, s), "stage 3");
+    return enqueue_stage(c, q2, t + 0.5 * dt, s, sp, [&](hipStream_t st, int set) {
+        return launch_rk_stage(g, f, ib, q, q2, q, 1.0 / 3.0, 2.0 / 3.0, st, set);
+    });
 }
 
 // One physical dual-time step ending at tn: history rotation, then n_inner
 // pseudo-iterations ping-ponging between q and the scratch state.
-int enqueue_dual_step(ibm_ctx *c, double *q, double tn, int first, hipStream_t s)
+int enqueue_dual_step(ibm_ctx *c, double *q, double tn, int first, hipStream_t s,
+                      const Split *sp = nullptr)
 {
     int rc;
     if ((rc = dev_err(c, launch_dual_begin(c->g, c->f, q, c->qn, c->qnm1, first, s), "dual begin")))
         return rc;
     double b0 = first ? 1.0 : 1.5, b2 = first ? 0.0 : 0.5;
     double *cur = q, *nxt = c->wtmp;
+    const Grid &g = c->g;
+    const Flow &f = c->f;
+    const IB &ib = c->ib;
     for (int it = 0; it < c->n_inner; ++it) {
-        if ((rc = do_fill(c, cur, tn, s)))
+        double *in = cur, *out = nxt;
+        if ((rc = enqueue_stage(c, in, tn, s, sp, [&](hipStream_t st, int set) {
+                 return launch_dual_iter(g, f, ib, in, out, c->qn, c->qnm1, b0, b2, st, set);
+             })))
             return rc;
-        if ((rc = dev_err(c, launch_dual_iter(c->g, c->f, c->ib, cur, nxt, c->qn, c->qnm1, b0, b2, s),
-                          "dual iteration")))
-            return rc;
-        double *tmp = cur;
-        cur = nxt;
-        nxt = tmp;
+        cur = out;
+        nxt = in;
     }
     if (cur != q)
         return dev_err(c, launch_copy_state(c->g, cur, q, s), "copy");
@@ -787,11 +850,25 @@ bool build_graph(ibm_ctx *c, double *q)
         c->cap_stream = nullptr;
         return false;
     }
+    if (!c->cap_side && hipStreamCreateWithFlags(&c->cap_side, hipStreamNonBlocking) != hipSuccess) {
+        c->cap_side = nullptr;
+        return false;
+    }
+    if (!c->ev_fork && hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess) {
+        c->ev_fork = nullptr;
+        return false;
+    }
+    if (!c->ev_join && hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        c->ev_join = nullptr;
+        return false;
+    }
     drop_graph(c);
+    Split sp{c->cap_side, c->ev_fork, c->ev_join};
+    const Split *psp = c->b.nfacet > 0 ? &sp : nullptr;
     if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return false;
-    int rc = c->f.scheme == IBM_RK3 ? enqueue_rk3_step(c, q, 0.0, c->cap_stream)
-                                    : enqueue_dual_step(c, q, 0.0, 0, c->cap_stream);
+    int rc = c->f.scheme == IBM_RK3 ? enqueue_rk3_step(c, q, 0.0, c->cap_stream, psp)
+                                    : enqueue_dual_step(c, q, 0.0, 0, c->cap_stream, psp);
     hipGraph_t gr = nullptr;
     hipError_t e = hipStreamEndCapture(c->cap_stream, &gr);
     if (rc != IBM_OK || e != hipSuccess || !gr) {

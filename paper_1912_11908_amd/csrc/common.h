@@ -66,6 +66,14 @@ struct IB {
     int32_t *listF, *listG;
     int32_t *rec_i;          // cap * kRecI
     double *rec_d;           // cap * kRecD
+    // fill plan (structure of arrays, cap entries each): state offsets of the
+    // node and of its probe corners (unused corners point at the node with
+    // weight 0), weights, line geometry n0 n1 n2 s_X s1 s2, modes
+    int32_t *plan_node;      // cap
+    int32_t *plan_off;       // 16 * cap: probe 1 corners 0..7, probe 2 corners 8..15
+    double *plan_w;          // 16 * cap
+    double *plan_geo;        // 6 * cap
+    int32_t *plan_mode;      // cap: mode1 | mode2 << 4
 };
 
 struct Motion {
@@ -85,11 +93,13 @@ hipError_t launch_bc_fill(const Grid &g, const Flow &f, const IB &ib, double *q,
                           double ab_axis, int axis, hipStream_t s);
 hipError_t launch_residual(const Grid &g, const Flow &f, const IB &ib, const double *q, double *r,
                            hipStream_t s);
+// tile_set: 0 all tiles, 1 tiles whose stencils read no fill output, 2 the others
 hipError_t launch_rk_stage(const Grid &g, const Flow &f, const IB &ib, const double *qn,
-                           const double *qin, double *qout, double a, double b, hipStream_t s);
+                           const double *qin, double *qout, double a, double b, hipStream_t s,
+                           int tile_set = 0);
 hipError_t launch_dual_iter(const Grid &g, const Flow &f, const IB &ib, const double *w,
                             double *wout, const double *qn, const double *qnm1, double b0,
-                            double b2, hipStream_t s);
+                            double b2, hipStream_t s, int tile_set = 0);
 hipError_t launch_dual_begin(const Grid &g, const Flow &f, const double *w, double *qn,
                              double *qnm1, int first, hipStream_t s);
 hipError_t launch_prim_to_state(const Grid &g, const Flow &f, const double *prim, double *q,

@@ -85,54 +85,55 @@ struct FreeStream {
     double v[5];
 };
 
-__device__ inline void halo_cell(const Grid &g, long long t, int &i, int &j, int &k)
+__device__ inline void halo_cell(const Grid &g, int t, int &i, int &j, int &k)
 {
     if (g.ndim == 2) {
-        long long band = 3LL * g.sx;
+        int band = 3 * g.sx;
         k = 0;
         if (t < 2 * band) {
             int top = t >= band;
-            long long r = t - top * band;
-            j = (int)(r / g.sx) + (top ? g.nj : -3);
-            i = (int)(r % g.sx) - 3;
+            int r = t - top * band;
+            j = r / g.sx + (top ? g.nj : -3);
+            i = r % g.sx - 3;
             return;
         }
         t -= 2 * band;
-        j = (int)(t / 6);
-        int c = (int)(t % 6);
+        j = t / 6;
+        int c = t % 6;
         i = c < 3 ? c - 3 : g.ni + (c - 3);
         return;
     }
-    long long zb = 3LL * g.sx * g.sy;
+    int plane = g.sx * g.sy;
+    int zb = 3 * plane;
     if (t < 2 * zb) {
         int top = t >= zb;
-        long long r = t - top * zb;
-        k = (int)(r / ((long long)g.sx * g.sy)) + (top ? g.nk : -3);
-        r %= (long long)g.sx * g.sy;
-        j = (int)(r / g.sx) - 3;
-        i = (int)(r % g.sx) - 3;
+        int r = t - top * zb;
+        k = r / plane + (top ? g.nk : -3);
+        r %= plane;
+        j = r / g.sx - 3;
+        i = r % g.sx - 3;
         return;
     }
     t -= 2 * zb;
-    long long yb = 6LL * g.sx;
+    int yb = 6 * g.sx;
     if (t < yb * g.nk) {
-        k = (int)(t / yb);
-        long long r = t % yb;
-        int top = r >= 3LL * g.sx;
-        r -= top * 3LL * g.sx;
-        j = (int)(r / g.sx) + (top ? g.nj : -3);
-        i = (int)(r % g.sx) - 3;
+        k = t / yb;
+        int r = t % yb;
+        int top = r >= 3 * g.sx;
+        r -= top * 3 * g.sx;
+        j = r / g.sx + (top ? g.nj : -3);
+        i = r % g.sx - 3;
         return;
     }
     t -= yb * g.nk;
-    k = (int)(t / (6LL * g.nj));
-    long long r = t % (6LL * g.nj);
-    j = (int)(r / 6);
-    int c = (int)(r % 6);
+    k = t / (6 * g.nj);
+    int r = t % (6 * g.nj);
+    j = r / 6;
+    int c = r % 6;
     i = c < 3 ? c - 3 : g.ni + (c - 3);
 }
 
-__device__ inline void bc_cell(const Grid &g, const FreeStream &fs, double *q, long long t)
+__device__ inline void bc_cell(const Grid &g, const FreeStream &fs, double *q, int t)
 {
     int i, j, k;
     halo_cell(g, t, i, j, k);
@@ -157,9 +158,9 @@ __device__ inline void bc_cell(const Grid &g, const FreeStream &fs, double *q, l
         q[dst + v * g.vs] = farfield ? fs.v[v] : q[src + v * g.vs];
 }
 
-__global__ void bc_kernel(Grid g, FreeStream fs, double *q, long long nhalo)
+__global__ void bc_kernel(Grid g, FreeStream fs, double *q, int nhalo)
 {
-    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < nhalo)
         bc_cell(g, fs, q, t);
 }
@@ -171,89 +172,142 @@ __global__ void bc_kernel(Grid g, FreeStream fs, double *q, long long nhalo)
 // (Dirichlet) or slope (Neumann) and the probe; quadratic family: profile
 // through two probes (sections 4.5-4.6 and 5).  s = 0 at P', s > 0 in the
 // fluid; the node sits at s_X.
-__device__ inline void probe_value(const Grid &g, const Flow &f, const double *q, const int *ids,
-                                   const double *w, double *phi)
+template <int DIM>
+__device__ inline void load_prim_t(const Grid &g, const Flow &f, const double *q, long long s,
+                                   double &rho, double *u, double &p, double &T)
 {
-    int nd = g.ndim;
-    for (int v = 0; v < nd + 2; ++v)
-        phi[v] = 0.0;
-    for (int m = 0; m < (1 << nd); ++m) {
-        if (ids[m] < 0 || w[m] == 0.0)
-            continue;
-        int c = ids[m];
-        int i = c % g.ni, j = (c / g.ni) % g.nj, k = c / (g.ni * g.nj);
-        PrimD p = load_prim(g, f, q, sidx(g, i, j, k));
-        phi[0] += w[m] * p.p;
-        for (int d = 0; d < nd; ++d)
-            phi[1 + d] += w[m] * p.u[d];
-        phi[nd + 1] += w[m] * p.T;
+    if (f.scheme == IBM_RK3) {
+        rho = q[s];
+        double ke = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            u[d] = q[s + (1 + d) * g.vs] / rho;
+            ke += u[d] * u[d];
+        }
+        p = (f.gamma - 1.0) * (q[s + (DIM + 1) * g.vs] - 0.5 * rho * ke);
+        T = p / (rho * f.R);
+    } else {
+        p = f.pinf + q[s];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+            u[d] = q[s + (1 + d) * g.vs];
+        T = 1.0 + q[s + (DIM + 1) * g.vs];
+        rho = p / (f.R * T);
     }
 }
 
+// value at probe `p` (0 or 1) of record r: weighted sum of (p, u.., T) over
+// the plan's corners (unused corners carry zero weight)
+template <int DIM>
+__device__ inline void plan_probe(const Grid &g, const Flow &f, const IB &ib, const double *q, int r,
+                                  int p, double *phi)
+{
+    constexpr int NC = 1 << DIM;
+#pragma unroll
+    for (int v = 0; v < DIM + 2; ++v)
+        phi[v] = 0.0;
+#pragma unroll
+    for (int m = 0; m < NC; ++m) {
+        int off = ib.plan_off[(8 * p + m) * ib.cap + r];
+        double w = ib.plan_w[(8 * p + m) * ib.cap + r];
+        double rho, u[DIM], pr, T;
+        load_prim_t<DIM>(g, f, q, off, rho, u, pr, T);
+        if (w != 0.0) {
+            phi[0] += w * pr;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d)
+                phi[1 + d] += w * u[d];
+            phi[DIM + 1] += w * T;
+        }
+    }
+}
+
+template <int DIM>
 __device__ inline void fill_one(const Grid &g, const Flow &f, const IB &ib, double *q, int r,
                                 double ub, double ab, int axis)
 {
-    int nd = g.ndim;
+    constexpr int NV = DIM + 2;
+    int cap = ib.cap;
     bool quad = f.family == IBM_IB_QUADRATIC;
-    const int *ir = ib.rec_i + (long long)kRecI * r;
-    const double *dr = ib.rec_d + (long long)kRecD * r;
-    double ubv[3] = {0.0, 0.0, 0.0}, abv[3] = {0.0, 0.0, 0.0};
-    if (axis >= 0) {
-        ubv[axis] = ub;
-        abv[axis] = ab;
+    int node = ib.plan_node[r];
+    int mode = ib.plan_mode[r];
+    int mode1 = mode & 15, mode2 = mode >> 4;
+    double n[DIM], ubv[DIM], abv[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        n[d] = ib.plan_geo[d * cap + r];
+        ubv[d] = d == axis ? ub : 0.0;
+        abv[d] = d == axis ? ab : 0.0;
     }
-    const double *n = dr;
-    double sx = dr[6], s1 = dr[7], s2 = dr[8];
-    PrimD res;
-    res.u[0] = res.u[1] = res.u[2] = 0.0;
-    if (ir[4] == 2) {
-        res.p = f.pinf;
-        res.T = 1.0;
-        for (int d = 0; d < nd; ++d)
-            res.u[d] = ubv[d];
+    double sx = ib.plan_geo[3 * cap + r], s1 = ib.plan_geo[4 * cap + r], s2 = ib.plan_geo[5 * cap + r];
+    double rp, ru[DIM], rT;
+    if (mode1 == 2) {  // no valid probe corner at all: counted fallback
+        rp = f.pinf;
+        rT = 1.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+            ru[d] = ubv[d];
     } else {
-        double phi1[5], phi2[5];
-        probe_value(g, f, q, ir + 7, dr + 9, phi1);
-        double rho1 = phi1[0] / (f.R * phi1[nd + 1]);
+        double phi1[NV];
+        plan_probe<DIM>(g, f, ib, q, r, 0, phi1);
+        double rho1 = phi1[0] / (f.R * phi1[NV - 1]);
         double an = 0.0;
-        for (int d = 0; d < nd; ++d)
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
             an += n[d] * abv[d];
         double gp = -rho1 * an, gT = 0.0;
-        if (!quad || ir[5] == 2) {
-            for (int d = 0; d < nd; ++d)
-                res.u[d] = ubv[d] + (phi1[1 + d] - ubv[d]) * sx / s1;
-            res.p = phi1[0] + gp * (sx - s1);
-            res.T = phi1[nd + 1] + gT * (sx - s1);
+        if (!quad || mode2 == 2) {
+#pragma unroll
+            for (int d = 0; d < DIM; ++d)
+                ru[d] = ubv[d] + (phi1[1 + d] - ubv[d]) * sx / s1;
+            rp = phi1[0] + gp * (sx - s1);
+            rT = phi1[NV - 1] + gT * (sx - s1);
         } else {
-            probe_value(g, f, q, ir + 15, dr + 17, phi2);
+            double phi2[NV];
+            plan_probe<DIM>(g, f, ib, q, r, 1, phi2);
             double L0 = (sx - s1) * (sx - s2) / (s1 * s2);
             double L1 = sx * (sx - s2) / (s1 * (s1 - s2));
             double L2 = sx * (sx - s1) / (s2 * (s2 - s1));
-            for (int d = 0; d < nd; ++d)
-                res.u[d] = ubv[d] * L0 + phi1[1 + d] * L1 + phi2[1 + d] * L2;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d)
+                ru[d] = ubv[d] * L0 + phi1[1 + d] * L1 + phi2[1 + d] * L2;
             double c2p = (phi2[0] - phi1[0] - gp * (s2 - s1)) / (s2 * s2 - s1 * s1);
             double c0p = phi1[0] - gp * s1 - c2p * s1 * s1;
-            res.p = c0p + gp * sx + c2p * sx * sx;
-            double c2T = (phi2[nd + 1] - phi1[nd + 1] - gT * (s2 - s1)) / (s2 * s2 - s1 * s1);
-            double c0T = phi1[nd + 1] - gT * s1 - c2T * s1 * s1;
-            res.T = c0T + gT * sx + c2T * sx * sx;
+            rp = c0p + gp * sx + c2p * sx * sx;
+            double c2T = (phi2[NV - 1] - phi1[NV - 1] - gT * (s2 - s1)) / (s2 * s2 - s1 * s1);
+            double c0T = phi1[NV - 1] - gT * s1 - c2T * s1 * s1;
+            rT = c0T + gT * sx + c2T * sx * sx;
         }
     }
-    res.rho = res.p / (f.R * res.T);
-    int c = ir[0];
-    int i = c % g.ni, j = (c / g.ni) % g.nj, k = c / (g.ni * g.nj);
-    store_prim(g, f, res, q, sidx(g, i, j, k));
+    double rrho = rp / (f.R * rT);
+    if (f.scheme == IBM_RK3) {
+        double ke = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+            ke += ru[d] * ru[d];
+        q[node] = rrho;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+            q[node + (1 + d) * g.vs] = rrho * ru[d];
+        q[node + (DIM + 1) * g.vs] = rp / (f.gamma - 1.0) + 0.5 * rrho * ke;
+    } else {
+        q[node] = rp - f.pinf;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+            q[node + (1 + d) * g.vs] = ru[d];
+        q[node + (DIM + 1) * g.vs] = rT - 1.0;
+    }
 }
-
 
 // Domain ghosts (blocks [0, nbb)) and forcing nodes (the remaining blocks,
 // grid-stride) in one launch: the forcing fill reads interior FLUID cells
 // only, the ghost layers never, so the two are independent.
-__global__ void bc_forcing_kernel(Grid g, FreeStream fs, Flow f, IB ib, double *q, long long nhalo,
-                                  int nbb, double ub, double ab, int axis)
+template <int DIM>
+__global__ void bc_forcing_kernel(Grid g, FreeStream fs, Flow f, IB ib, double *q, int nhalo, int nbb,
+                                  double ub, double ab, int axis)
 {
     if ((int)blockIdx.x < nbb) {
-        long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+        int t = blockIdx.x * blockDim.x + threadIdx.x;
         if (t < nhalo)
             bc_cell(g, fs, q, t);
         return;
@@ -261,17 +315,18 @@ __global__ void bc_forcing_kernel(Grid g, FreeStream fs, Flow f, IB ib, double *
     int nF = min(ib.counts[CNT_F], ib.cap);
     int stride = (gridDim.x - nbb) * blockDim.x;
     for (int r = (blockIdx.x - nbb) * blockDim.x + threadIdx.x; r < nF; r += stride)
-        fill_one(g, f, ib, q, r, ub, ab, axis);
+        fill_one<DIM>(g, f, ib, q, r, ub, ab, axis);
 }
 
 // Ghost layers G1-G3 (they read FLUID and FORCING cells), grid-stride.
+template <int DIM>
 __global__ void ghost_fill_kernel(Grid g, Flow f, IB ib, double *q, double ub, double ab, int axis)
 {
     int nF = min(ib.counts[CNT_F], ib.cap);
     int nG = min(ib.counts[CNT_G], ib.cap - nF);
     int stride = gridDim.x * blockDim.x;
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nG; t += stride)
-        fill_one(g, f, ib, q, nF + t, ub, ab, axis);
+        fill_one<DIM>(g, f, ib, q, nF + t, ub, ab, axis);
 }
 
 // ------------------------------------------------ fused residual / update
@@ -296,6 +351,8 @@ struct StepArgs {
     double *out;         // RK3/dual: next state; residual mode: R (interior)
     double a, b;         // RK3 stage coefficients / dual b0, b2
     int ntx, nty, ntz;
+    int tile_set;        // 0: all tiles; 1: far tiles only; 2: near tiles only
+    int region[6];       // immersed-boundary region (cells)
 };
 
 // WENO5 (Jiang-Shu, eps 1e-6, linear weights 0.1, 0.6, 0.3) left state at
@@ -541,6 +598,19 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs A)
     int tx0 = tile % A.ntx, ty0 = (tile / A.ntx) % A.nty, tz0 = tile / (A.ntx * A.nty);
     int i0 = tx0 * TX, j0 = ty0 * TY, k0 = tz0 * TZ;
     int tid = threadIdx.x;
+    if (A.tile_set != 0) {
+        // a tile is "near" when its stencil footprint (3-cell halo) reaches a
+        // domain ghost cell or the immersed-boundary region: only those read
+        // cells that the fill of this stage writes
+        bool nearb = i0 - 3 < 0 || i0 + TX + 3 > g.ni || j0 - 3 < 0 || j0 + TY + 3 > g.nj ||
+                     (DIM == 3 && (k0 - 3 < 0 || k0 + TZ + 3 > g.nk));
+        bool hits = i0 - 3 < A.region[1] && i0 + TX + 3 > A.region[0] && j0 - 3 < A.region[3] &&
+                    j0 + TY + 3 > A.region[2] &&
+                    (DIM == 2 || (k0 - 3 < A.region[5] && k0 + TZ + 3 > A.region[4]));
+        bool near = nearb || hits;
+        if ((A.tile_set == 1) == near)
+            return;
+    }
 
     // 1. load the tile and its 3-cell halo, recovering (rho', u.., p', T')
     for (int t = tid; t < LCELLS; t += kBlock) {
@@ -843,7 +913,7 @@ __global__ void copy_kernel(const double *src, double *dst, long long n)
 template <int DIM, typename Real, int MODE>
 hipError_t run_step(const Grid &g, const Flow &f, const IB &ib, const double *qin,
                     const double *qn, const double *qnm1, double *out, double a, double b,
-                    hipStream_t s)
+                    hipStream_t s, int tile_set)
 {
     using C = TileCfg<DIM>;
     StepArgs A;
@@ -860,6 +930,9 @@ hipError_t run_step(const Grid &g, const Flow &f, const IB &ib, const double *qi
     A.ntx = (g.ni + C::TX - 1) / C::TX;
     A.nty = (g.nj + C::TY - 1) / C::TY;
     A.ntz = DIM == 3 ? (g.nk + C::TZ - 1) / C::TZ : 1;
+    A.tile_set = tile_set;
+    for (int m = 0; m < 6; ++m)
+        A.region[m] = ib.cap > 0 ? ib.region[m] : 0;
     int nt = A.ntx * A.nty * A.ntz;
     hipLaunchKernelGGL((step_kernel<DIM, Real, MODE>), dim3(nt), dim3(kBlock), 0, s, A);
     return hipGetLastError();
@@ -868,14 +941,14 @@ hipError_t run_step(const Grid &g, const Flow &f, const IB &ib, const double *qi
 template <int MODE>
 hipError_t dispatch_step(const Grid &g, const Flow &f, const IB &ib, const double *qin,
                          const double *qn, const double *qnm1, double *out, double a, double b,
-                         hipStream_t s)
+                         hipStream_t s, int tile_set = 0)
 {
     bool mixed = f.precision == IBM_MIXED;
     if (g.ndim == 2)
-        return mixed ? run_step<2, float, MODE>(g, f, ib, qin, qn, qnm1, out, a, b, s)
-                     : run_step<2, double, MODE>(g, f, ib, qin, qn, qnm1, out, a, b, s);
-    return mixed ? run_step<3, float, MODE>(g, f, ib, qin, qn, qnm1, out, a, b, s)
-                 : run_step<3, double, MODE>(g, f, ib, qin, qn, qnm1, out, a, b, s);
+        return mixed ? run_step<2, float, MODE>(g, f, ib, qin, qn, qnm1, out, a, b, s, tile_set)
+                     : run_step<2, double, MODE>(g, f, ib, qin, qn, qnm1, out, a, b, s, tile_set);
+    return mixed ? run_step<3, float, MODE>(g, f, ib, qin, qn, qnm1, out, a, b, s, tile_set)
+                 : run_step<3, double, MODE>(g, f, ib, qin, qn, qnm1, out, a, b, s, tile_set);
 }
 
 }  // namespace
@@ -897,7 +970,7 @@ static FreeStream freestream_of(const Grid &g, const Flow &f)
 
 hipError_t launch_domain_bc(const Grid &g, const Flow &f, double *q, hipStream_t s)
 {
-    long long nhalo = (long long)g.sx * g.sy * g.sz - g.ncell;
+    int nhalo = (int)((long long)g.sx * g.sy * g.sz - g.ncell);
     hipLaunchKernelGGL(bc_kernel, dim3(blocks_for(nhalo, kBlock)), dim3(kBlock), 0, s, g,
                        freestream_of(g, f), q, nhalo);
     return hipGetLastError();
@@ -908,14 +981,22 @@ hipError_t launch_bc_fill(const Grid &g, const Flow &f, const IB &ib, double *q,
 {
     if (ib.cap == 0)
         return launch_domain_bc(g, f, q, s);
-    long long nhalo = (long long)g.sx * g.sy * g.sz - g.ncell;
+    int nhalo = (int)((long long)g.sx * g.sy * g.sz - g.ncell);
     int nbb = blocks_for(nhalo, kBlock);
     int nbf = blocks_for(ib.cap, kBlock);
-    nbf = nbf < 128 ? nbf : 128;
-    hipLaunchKernelGGL(bc_forcing_kernel, dim3(nbb + nbf), dim3(kBlock), 0, s, g, freestream_of(g, f),
-                       f, ib, q, nhalo, nbb, ub_axis, ab_axis, axis);
-    hipLaunchKernelGGL(ghost_fill_kernel, dim3(nbf), dim3(kBlock), 0, s, g, f, ib, q, ub_axis, ab_axis,
-                       axis);
+    nbf = nbf < 64 ? nbf : 64;
+    FreeStream fs = freestream_of(g, f);
+    if (g.ndim == 2) {
+        hipLaunchKernelGGL(bc_forcing_kernel<2>, dim3(nbb + nbf), dim3(kBlock), 0, s, g, fs, f, ib, q, nhalo,
+                           nbb, ub_axis, ab_axis, axis);
+        hipLaunchKernelGGL(ghost_fill_kernel<2>, dim3(nbf), dim3(kBlock), 0, s, g, f, ib, q, ub_axis,
+                           ab_axis, axis);
+    } else {
+        hipLaunchKernelGGL(bc_forcing_kernel<3>, dim3(nbb + nbf), dim3(kBlock), 0, s, g, fs, f, ib, q, nhalo,
+                           nbb, ub_axis, ab_axis, axis);
+        hipLaunchKernelGGL(ghost_fill_kernel<3>, dim3(nbf), dim3(kBlock), 0, s, g, f, ib, q, ub_axis,
+                           ab_axis, axis);
+    }
     return hipGetLastError();
 }
 
@@ -926,16 +1007,17 @@ hipError_t launch_residual(const Grid &g, const Flow &f, const IB &ib, const dou
 }
 
 hipError_t launch_rk_stage(const Grid &g, const Flow &f, const IB &ib, const double *qn,
-                           const double *qin, double *qout, double a, double b, hipStream_t s)
+                           const double *qin, double *qout, double a, double b, hipStream_t s,
+                           int tile_set)
 {
-    return dispatch_step<MODE_RK3>(g, f, ib, qin, qn, nullptr, qout, a, b, s);
+    return dispatch_step<MODE_RK3>(g, f, ib, qin, qn, nullptr, qout, a, b, s, tile_set);
 }
 
 hipError_t launch_dual_iter(const Grid &g, const Flow &f, const IB &ib, const double *w,
                             double *wout, const double *qn, const double *qnm1, double b0,
-                            double b2, hipStream_t s)
+                            double b2, hipStream_t s, int tile_set)
 {
-    return dispatch_step<MODE_DUAL>(g, f, ib, w, qn, qnm1, wout, b0, b2, s);
+    return dispatch_step<MODE_DUAL>(g, f, ib, w, qn, qnm1, wout, b0, b2, s, tile_set);
 }
 
 hipError_t launch_dual_begin(const Grid &g, const Flow &f, const double *w, double *qn,

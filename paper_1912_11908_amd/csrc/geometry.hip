@@ -788,6 +788,34 @@ __device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib
     dr[25] = sqrt(cl.d2);
     for (int m = 26; m < kRecD; ++m)
         dr[m] = 0.0;
+
+    // fill plan: state offsets instead of cell ids, unused corners aimed at
+    // the node itself with zero weight, so the fill loops are branch-free
+    int cap = ib.cap;
+    long long node_off = ((long long)(k + g.hz) * g.sy + (j + 3)) * g.sx + (i + 3);
+    ib.plan_node[r] = (int)node_off;
+    for (int m = 0; m < 8; ++m) {
+        int ids[2] = {ids1[m], ids2[m]};
+        double ws[2] = {w1[m], w2[m]};
+        for (int p = 0; p < 2; ++p) {
+            int off = (int)node_off;
+            double wt = 0.0;
+            if (ids[p] >= 0 && ws[p] != 0.0) {
+                int cc = ids[p];
+                int ci = cc % g.ni, cj = (cc / g.ni) % g.nj, ck = cc / (g.ni * g.nj);
+                off = (int)(((long long)(ck + g.hz) * g.sy + (cj + 3)) * g.sx + (ci + 3));
+                wt = ws[p];
+            }
+            ib.plan_off[(8 * p + m) * cap + r] = off;
+            ib.plan_w[(8 * p + m) * cap + r] = wt;
+        }
+    }
+    for (int d = 0; d < 3; ++d)
+        ib.plan_geo[d * cap + r] = n[d];
+    ib.plan_geo[3 * cap + r] = sx;
+    ib.plan_geo[4 * cap + r] = s1;
+    ib.plan_geo[5 * cap + r] = s2;
+    ib.plan_mode[r] = mode1 | (mode2 << 4);
 }
 
 inline int blocks_for(long long n, int bs) { return (int)((n + bs - 1) / bs); }
