@@ -130,18 +130,23 @@ int ibm_set_time(ibm_ctx *ctx, double t);
  * local normal, boundary point P' and probe stencils (section 4). */
 int ibm_classify(ibm_ctx *ctx, void *stream);
 
-/* a5: fill the domain ghost layers and then the immersed-boundary nodes of
- * d_q at time t (FORCING first, then the ghost layers), eqs 4-6 and 8. */
+/* a5: fill the immersed-boundary nodes of d_q at time t (FORCING first, then
+ * the ghost layers G1-G3), eqs 4-6 and 8, and then the domain ghost layers
+ * (three per side) as images of the filled interior. */
 int ibm_fill(ibm_ctx *ctx, double *d_q, double t, void *stream);
 
 /* a6-a9: residual R = (1/V) sum_faces (F_inv - F_visc) . S of d_q on FLUID
  * cells (zero elsewhere), in conserved form, interior layout [nv][nk][nj][ni].
- * d_q's halo and IB nodes must already be filled (ibm_fill). */
+ * d_q's IB nodes must already be filled (ibm_fill); its halo is not read:
+ * stencils resolve domain ghost cells from the interior by the rules of the
+ * boundary types. */
 int ibm_residual(ibm_ctx *ctx, const double *d_q, double *d_r, void *stream);
 
 /* a1-a10: advance nsteps SSP-RK3 steps (IBM_RK3) or physical dual-time steps
  * of n_inner pseudo-iterations each (IBM_DUAL), in place on d_q.  Moving
- * bodies are reclassified at the pose of each step's start time. */
+ * bodies are reclassified at the pose of each step's start time.  The
+ * interior (IB nodes included) is advanced; d_q's halo is neither read nor
+ * written (call ibm_fill for a filled halo). */
 int ibm_advance(ibm_ctx *ctx, double *d_q, int nsteps, void *stream);
 
 /* Primitive (rho, u, v[, w], p) interior array -> state (halo untouched),

@@ -1546,14 +1546,16 @@ void orc_rk3_step(orc *o, double *q, double *q1, double *q2, double t)
         orc_geometry(o);
     }
     double dt = o->dt;
-    orc_bc(o, q);
+    /* each stage: IB fill (its probes read interior cells only), then the
+     * domain ghost layers as images of the filled interior */
     orc_fill(o, q, t);
+    orc_bc(o, q);
     rk_stage(o, q, q, q1, 0.0, 1.0);
-    orc_bc(o, q1);
     orc_fill(o, q1, t + dt);
+    orc_bc(o, q1);
     rk_stage(o, q, q1, q2, 0.75, 0.25);
-    orc_bc(o, q2);
     orc_fill(o, q2, t + 0.5 * dt);
+    orc_bc(o, q2);
     rk_stage(o, q, q2, q, 1.0 / 3.0, 2.0 / 3.0);
 }
 
@@ -1640,8 +1642,8 @@ void orc_dual_iterate(orc *o, double *w, double *wtmp, const double *qn, const d
     double b0 = first ? 1.0 : 1.5, b2 = first ? 0.0 : 0.5;
     double *r = (double *)malloc(sizeof(double) * nv * n);
     for (int it = 0; it < n_iter; it++) {
-        orc_bc(o, w);
         orc_fill(o, w, t_new);
+        orc_bc(o, w);
         orc_residual(o, w, r);
         memcpy(wtmp, w, sizeof(double) * nv * vs);
 #pragma omp parallel for schedule(static)

@@ -27,13 +27,16 @@ struct ibm_ctx {
     long long step;
     int n_inner;
     bool classified;
-    // graph replay of whole steps (stationary bodies)
+    // tile lists of the stage launches (device)
+    const int32_t *tiles_far, *tiles_near;
+    int nfar, nnear;
+    // graph replay of whole steps (stationary bodies): slot 0 holds one
+    // step, slot 1 a chunk of kChunk steps
     bool use_graphs;
-    hipStream_t cap_stream, cap_side;
-    hipEvent_t ev_fork, ev_join;
-    hipGraph_t graph;
-    hipGraphExec_t graph_exec;
-    const double *graph_q;
+    hipStream_t cap_stream;
+    hipGraph_t graph[2];
+    hipGraphExec_t graph_exec[2];
+    const double *graph_q[2];
     long long rest_box_lat[6];
     char err[256];
 };
@@ -137,7 +140,45 @@ struct HostGeom {
     int nedge;
     int region[6];
     int cap, wpr, nblk;
+    // tiles of the fused residual/update kernel: those whose stencils never
+    // reach the IB region ("far") and the others ("near"), raster order
+    std::vector<int32_t> tiles_far, tiles_near;
 };
+
+// Does [lo, hi) meet [r0, r1), directly or through a periodic wrap of an
+// axis of n cells?
+bool meets(int lo, int hi, int r0, int r1, int n, bool periodic)
+{
+    if (r1 <= r0)
+        return false;
+    for (int sh = periodic ? -1 : 0; sh <= (periodic ? 1 : 0); ++sh)
+        if (lo + sh * n < r1 && hi + sh * n > r0)
+            return true;
+    return false;
+}
+
+void tile_lists(const ibm_case *c, HostGeom &h)
+{
+    const int *T = h.nd == 2 ? kTile2 : kTile3;
+    int nt[3];
+    for (int d = 0; d < 3; ++d)
+        nt[d] = d < h.nd ? (h.n[d] + T[d] - 1) / T[d] : 1;
+    h.tiles_far.clear();
+    h.tiles_near.clear();
+    for (int tz = 0; tz < nt[2]; ++tz)
+        for (int ty = 0; ty < nt[1]; ++ty)
+            for (int tx = 0; tx < nt[0]; ++tx) {
+                int t0[3] = {tx, ty, tz};
+                bool near = h.cap > 0;
+                for (int d = 0; d < h.nd && near; ++d) {
+                    int lo = t0[d] * T[d] - 3, hi = t0[d] * T[d] + T[d] + 3;
+                    near = meets(lo, hi, h.region[2 * d], h.region[2 * d + 1], h.n[d],
+                                 c->bc[2 * d] == IBM_BC_PERIODIC);
+                }
+                int id = (tz * nt[1] + ty) * nt[0] + tx;
+                (near ? h.tiles_near : h.tiles_far).push_back(id);
+            }
+}
 
 double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 void unit3(double *a)
@@ -353,6 +394,7 @@ int host_geom(const ibm_case *c, HostGeom &h)
     h.cap = rw * rh * rd;
     h.wpr = (rw + 1 + 31) / 32;
     h.nblk = (h.cap + 255) / 256;
+    tile_lists(c, h);
     return IBM_OK;
 }
 
@@ -371,6 +413,7 @@ struct Layout {
     double *rec_d;
     int32_t *plan_node, *plan_off, *plan_mode;
     double *plan_w, *plan_geo;
+    int32_t *tiles;
     double *q1, *q2, *wtmp, *qn, *qnm1;
 };
 
@@ -416,6 +459,7 @@ size_t carve(const ibm_case *c, const HostGeom &h, char *base, Layout &L)
     L.plan_w = cv.take<double>(16 * cap);
     L.plan_geo = cv.take<double>(6 * cap);
     L.plan_mode = cv.take<int32_t>(cap);
+    L.tiles = cv.take<int32_t>(std::max<size_t>(h.tiles_far.size() + h.tiles_near.size(), 1));
     size_t st = (size_t)h.vs * (nd + 2);
     L.q1 = L.q2 = L.wtmp = L.qn = L.qnm1 = nullptr;
     if (c->scheme == IBM_RK3) {
@@ -642,6 +686,8 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     ib.plan_w = L.plan_w;
     ib.plan_geo = L.plan_geo;
     ib.plan_mode = L.plan_mode;
+    if (e == hipSuccess) e = up(L.tiles, h.tiles_far);
+    if (e == hipSuccess) e = up(L.tiles + h.tiles_far.size(), h.tiles_near);
     if (e == hipSuccess) e = hipMemset(L.cls, IBM_FLUID, (size_t)h.ncell);
     if (e == hipSuccess) e = hipMemset(L.counts, 0, sizeof(int32_t) * CNT_WORDS);
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -661,12 +707,15 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     x->classified = false;
     x->use_graphs = true;
     x->cap_stream = nullptr;
-    x->cap_side = nullptr;
-    x->ev_fork = nullptr;
-    x->ev_join = nullptr;
-    x->graph = nullptr;
-    x->graph_exec = nullptr;
-    x->graph_q = nullptr;
+    for (int k = 0; k < 2; ++k) {
+        x->graph[k] = nullptr;
+        x->graph_exec[k] = nullptr;
+        x->graph_q[k] = nullptr;
+    }
+    x->tiles_far = L.tiles;
+    x->nfar = (int)h.tiles_far.size();
+    x->tiles_near = L.tiles + h.tiles_far.size();
+    x->nnear = (int)h.tiles_near.size();
     if (e != hipSuccess) {
         delete x;
         return IBM_EDEVICE;
@@ -677,13 +726,15 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
 
 static void drop_graph(ibm_ctx *c)
 {
-    if (c->graph_exec)
-        (void)hipGraphExecDestroy(c->graph_exec);
-    if (c->graph)
-        (void)hipGraphDestroy(c->graph);
-    c->graph_exec = nullptr;
-    c->graph = nullptr;
-    c->graph_q = nullptr;
+    for (int k = 0; k < 2; ++k) {
+        if (c->graph_exec[k])
+            (void)hipGraphExecDestroy(c->graph_exec[k]);
+        if (c->graph[k])
+            (void)hipGraphDestroy(c->graph[k]);
+        c->graph_exec[k] = nullptr;
+        c->graph[k] = nullptr;
+        c->graph_q[k] = nullptr;
+    }
 }
 
 void ibm_destroy(ibm_ctx *c)
@@ -693,12 +744,6 @@ void ibm_destroy(ibm_ctx *c)
     drop_graph(c);
     if (c->cap_stream)
         (void)hipStreamDestroy(c->cap_stream);
-    if (c->cap_side)
-        (void)hipStreamDestroy(c->cap_side);
-    if (c->ev_fork)
-        (void)hipEventDestroy(c->ev_fork);
-    if (c->ev_join)
-        (void)hipEventDestroy(c->ev_join);
     delete c;
 }
 
@@ -757,42 +802,34 @@ int ibm_residual(ibm_ctx *c, const double *q, double *r, void *stream)
 
 namespace {
 
-// Optional fork for one stage: tiles whose stencils read no cell written by
-// the fill run on a side stream concurrently with the fill chain; the tiles
-// near the body or the domain boundary follow the fill on the main stream.
-struct Split {
-    hipStream_t side;
-    hipEvent_t fork, join;
-};
-
-template <typename Launch>
-int enqueue_stage(ibm_ctx *c, double *qin, double t, hipStream_t s, const Split *sp, Launch launch)
+// One stage: with a body, three launches on the stream -- the FORCING fill
+// with the first half of the far tiles, the ghost-layer fill (it reads the
+// FORCING nodes) with the second half, then the near tiles, whose stencils
+// read the filled nodes.  Without a body every tile runs in one launch.
+template <typename Launch> int enqueue_stage(ibm_ctx *c, double t, hipStream_t s, Launch launch)
 {
-    int rc;
-    if (!sp) {
-        if ((rc = do_fill(c, qin, t, s)))
-            return rc;
-        return dev_err(c, launch(s, 0), "stage");
+    if (c->b.nfacet == 0 || c->ib.cap == 0)
+        return dev_err(c, launch(s, nullptr), "stage");
+    double disp = 0.0, vel = 0.0, acc = 0.0;
+    int axis = -1;
+    if (c->mo.on) {
+        motion_kin(c, t, disp, vel, acc);
+        axis = c->mo.axis;
     }
-    hipError_t e = hipEventRecord(sp->fork, s);
+    int half = c->nfar / 2;
+    StagePart pa{c->tiles_far, half, PART_FILL_FORCING, vel, acc, axis};
+    StagePart pb{c->tiles_far + half, c->nfar - half, PART_FILL_GHOSTS, vel, acc, axis};
+    StagePart pc{c->tiles_near, c->nnear, PART_NO_FILL, vel, acc, axis};
+    hipError_t e = launch(s, &pa);
     if (e == hipSuccess)
-        e = hipStreamWaitEvent(sp->side, sp->fork, 0);
+        e = launch(s, &pb);
     if (e == hipSuccess)
-        e = launch(sp->side, 1);
-    if ((rc = dev_err(c, e, "stage (far tiles)")))
-        return rc;
-    if ((rc = do_fill(c, qin, t, s)))
-        return rc;
-    e = launch(s, 2);
-    if (e == hipSuccess)
-        e = hipEventRecord(sp->join, sp->side);
-    if (e == hipSuccess)
-        e = hipStreamWaitEvent(s, sp->join, 0);
-    return dev_err(c, e, "stage (near tiles)");
+        e = launch(s, &pc);
+    return dev_err(c, e, "stage");
 }
 
 // One SSP-RK3 step (Shu-Osher) starting at time t; a fill at each stage time.
-int enqueue_rk3_step(ibm_ctx *c, double *q, double t, hipStream_t s, const Split *sp = nullptr)
+int enqueue_rk3_step(ibm_ctx *c, double *q, double t, hipStream_t s)
 {
     int rc;
     double dt = c->f.dt;
@@ -800,23 +837,22 @@ int enqueue_rk3_step(ibm_ctx *c, double *q, double t, hipStream_t s, const Split
     const Flow &f = c->f;
     const IB &ib = c->ib;
     double *q1 = c->q1, *q2 = c->q2;
-    if ((rc = enqueue_stage(c, q, t, s, sp, [&](hipStream_t st, int set) {
-             return launch_rk_stage(g, f, ib, q, q, q1, 0.0, 1.0, st, set);
+    if ((rc = enqueue_stage(c, t, s, [&](hipStream_t st, const StagePart *p) {
+             return launch_rk_stage(g, f, ib, q, q, q1, 0.0, 1.0, st, p);
          })))
         return rc;
-    if ((rc = enqueue_stage(c, q1, t + dt, s, sp, [&](hipStream_t st, int set) {
-             return launch_rk_stage(g, f, ib, q, q1, q2, 0.75, 0.25, st, set);
+    if ((rc = enqueue_stage(c, t + dt, s, [&](hipStream_t st, const StagePart *p) {
+             return launch_rk_stage(g, f, ib, q, q1, q2, 0.75, 0.25, st, p);
          })))
         return rc;
-    return enqueue_stage(c, q2, t + 0.5 * dt, s, sp, [&](hipStream_t st, int set) {
-        return launch_rk_stage(g, f, ib, q, q2, q, 1.0 / 3.0, 2.0 / 3.0, st, set);
+    return enqueue_stage(c, t + 0.5 * dt, s, [&](hipStream_t st, const StagePart *p) {
+        return launch_rk_stage(g, f, ib, q, q2, q, 1.0 / 3.0, 2.0 / 3.0, st, p);
     });
 }
 
 // One physical dual-time step ending at tn: history rotation, then n_inner
 // pseudo-iterations ping-ponging between q and the scratch state.
-int enqueue_dual_step(ibm_ctx *c, double *q, double tn, int first, hipStream_t s,
-                      const Split *sp = nullptr)
+int enqueue_dual_step(ibm_ctx *c, double *q, double tn, int first, hipStream_t s)
 {
     int rc;
     if ((rc = dev_err(c, launch_dual_begin(c->g, c->f, q, c->qn, c->qnm1, first, s), "dual begin")))
@@ -828,8 +864,8 @@ int enqueue_dual_step(ibm_ctx *c, double *q, double tn, int first, hipStream_t s
     const IB &ib = c->ib;
     for (int it = 0; it < c->n_inner; ++it) {
         double *in = cur, *out = nxt;
-        if ((rc = enqueue_stage(c, in, tn, s, sp, [&](hipStream_t st, int set) {
-                 return launch_dual_iter(g, f, ib, in, out, c->qn, c->qnm1, b0, b2, st, set);
+        if ((rc = enqueue_stage(c, tn, s, [&](hipStream_t st, const StagePart *p) {
+                 return launch_dual_iter(g, f, ib, in, out, c->qn, c->qnm1, b0, b2, st, p);
              })))
             return rc;
         cur = out;
@@ -840,35 +876,33 @@ int enqueue_dual_step(ibm_ctx *c, double *q, double tn, int first, hipStream_t s
     return IBM_OK;
 }
 
-// Capture one step of a stationary-body solve into a graph (on a private
-// stream: the caller's stream may be the legacy default stream, which cannot
-// be captured).  Returns false if capture is unavailable; the caller then
-// enqueues eagerly.
-bool build_graph(ibm_ctx *c, double *q)
+// Steps per chunk graph: RK3 steps are 9 launches, dual-time steps 3 n_inner + 1.
+int chunk_steps(const ibm_ctx *c) { return c->f.scheme == IBM_RK3 ? 8 : 2; }
+
+// Capture `slot` (0: one step, 1: a chunk of steps) of a stationary-body solve
+// into a graph, on a private stream (the caller's stream may be the legacy
+// default stream, which cannot be captured).  Returns false if capture is
+// unavailable; the caller then enqueues eagerly.
+bool build_graph(ibm_ctx *c, double *q, int slot)
 {
     if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         c->cap_stream = nullptr;
         return false;
     }
-    if (!c->cap_side && hipStreamCreateWithFlags(&c->cap_side, hipStreamNonBlocking) != hipSuccess) {
-        c->cap_side = nullptr;
-        return false;
-    }
-    if (!c->ev_fork && hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess) {
-        c->ev_fork = nullptr;
-        return false;
-    }
-    if (!c->ev_join && hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
-        c->ev_join = nullptr;
-        return false;
-    }
-    drop_graph(c);
-    Split sp{c->cap_side, c->ev_fork, c->ev_join};
-    const Split *psp = c->b.nfacet > 0 ? &sp : nullptr;
+    if (c->graph_exec[slot])
+        (void)hipGraphExecDestroy(c->graph_exec[slot]);
+    if (c->graph[slot])
+        (void)hipGraphDestroy(c->graph[slot]);
+    c->graph_exec[slot] = nullptr;
+    c->graph[slot] = nullptr;
+    c->graph_q[slot] = nullptr;
+    int nsteps = slot == 0 ? 1 : chunk_steps(c);
     if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return false;
-    int rc = c->f.scheme == IBM_RK3 ? enqueue_rk3_step(c, q, 0.0, c->cap_stream, psp)
-                                    : enqueue_dual_step(c, q, 0.0, 0, c->cap_stream, psp);
+    int rc = IBM_OK;
+    for (int n = 0; n < nsteps && rc == IBM_OK; ++n)
+        rc = c->f.scheme == IBM_RK3 ? enqueue_rk3_step(c, q, 0.0, c->cap_stream)
+                                    : enqueue_dual_step(c, q, 0.0, 0, c->cap_stream);
     hipGraph_t gr = nullptr;
     hipError_t e = hipStreamEndCapture(c->cap_stream, &gr);
     if (rc != IBM_OK || e != hipSuccess || !gr) {
@@ -883,9 +917,9 @@ bool build_graph(ibm_ctx *c, double *q)
         (void)hipGetLastError();
         return false;
     }
-    c->graph = gr;
-    c->graph_exec = ex;
-    c->graph_q = q;
+    c->graph[slot] = gr;
+    c->graph_exec[slot] = ex;
+    c->graph_q[slot] = q;
     return true;
 }
 
@@ -900,7 +934,7 @@ int ibm_advance(ibm_ctx *c, double *q, int nsteps, void *stream)
     hipStream_t s = S(stream);
     int rc;
     double dt = c->f.dt;
-    for (int n = 0; n < nsteps; ++n) {
+    for (int n = 0; n < nsteps;) {
         bool rk = c->f.scheme == IBM_RK3;
         // moving bodies are posed at t^n (RK3) or t^{n+1} (dual time)
         double tpose = rk ? c->t : c->t + dt;
@@ -908,21 +942,29 @@ int ibm_advance(ibm_ctx *c, double *q, int nsteps, void *stream)
             if ((rc = do_classify(c, tpose, s)))
                 return rc;
         int first = !rk && c->step == 0;
+        int k = 1;
         bool graphable = c->use_graphs && !c->mo.on && !first;
-        if (graphable && c->graph_q != q && !build_graph(c, q))
-            graphable = false;
         if (graphable) {
-            if ((rc = dev_err(c, hipGraphLaunch(c->graph_exec, s), "graph launch")))
-                return rc;
-        } else if (rk) {
-            if ((rc = enqueue_rk3_step(c, q, c->t, s)))
-                return rc;
-        } else {
-            if ((rc = enqueue_dual_step(c, q, c->t + dt, first, s)))
+            int slot = nsteps - n >= chunk_steps(c) ? 1 : 0;
+            if (c->graph_q[slot] != q && !build_graph(c, q, slot))
+                graphable = false;
+            else {
+                if ((rc = dev_err(c, hipGraphLaunch(c->graph_exec[slot], s), "graph launch")))
+                    return rc;
+                k = slot == 1 ? chunk_steps(c) : 1;
+            }
+        }
+        if (!graphable) {
+            if (rk)
+                rc = enqueue_rk3_step(c, q, c->t, s);
+            else
+                rc = enqueue_dual_step(c, q, c->t + dt, first, s);
+            if (rc)
                 return rc;
         }
-        c->t += dt;
-        c->step++;
+        c->t += k * dt;
+        c->step += k;
+        n += k;
     }
     return IBM_OK;
 }
@@ -1019,8 +1061,10 @@ int ibm_time_update_kernel(ibm_ctx *c, const double *q, int stage, int nrep, voi
     if (e == hipSuccess)
         e = hipEventRecord(e0, s);
     for (int r = 0; r < nrep && e == hipSuccess; ++r)
-        e = rk ? launch_rk_stage(c->g, c->f, c->ib, q, q, c->q1, A[stage], B[stage], s)
-               : launch_dual_iter(c->g, c->f, c->ib, q, c->wtmp, c->qn, c->qnm1, 1.0, 0.0, s);
+        // every tile, no fill part: d_q is only read
+        e = rk ? launch_rk_stage(c->g, c->f, c->ib, q, const_cast<double *>(q), c->q1, A[stage], B[stage], s)
+               : launch_dual_iter(c->g, c->f, c->ib, const_cast<double *>(q), c->wtmp, c->qn, c->qnm1, 1.0,
+                                  0.0, s);
     if (e == hipSuccess)
         e = hipEventRecord(e1, s);
     if (e == hipSuccess)

@@ -76,6 +76,24 @@ struct IB {
     int32_t *plan_mode;      // cap: mode1 | mode2 << 4
 };
 
+// Tiles of the fused residual/update kernel: cells per block along x, y, z.
+constexpr int kTile2[3] = {32, 8, 1};
+constexpr int kTile3[3] = {8, 8, 4};
+
+// One launch of a stage of the fused residual/update kernel: a list of tiles
+// (null: every tile of the grid) and, ahead of the tiles, blocks that fill
+// the immersed-boundary nodes of the stage input (FORCING nodes, or the
+// ghost layers G1-G3 that read them).  Tiles whose stencils reach an IB node
+// must run after both fills.
+enum { PART_NO_FILL = 0, PART_FILL_FORCING = 1, PART_FILL_GHOSTS = 2 };
+struct StagePart {
+    const int32_t *tiles;
+    int ntiles;
+    int fill;
+    double ub, ab;           // body velocity and acceleration along `axis`
+    int axis;                // motion axis, -1 for a stationary body
+};
+
 struct Motion {
     int on, axis;
     double amp, freq, phase;
@@ -93,13 +111,14 @@ hipError_t launch_bc_fill(const Grid &g, const Flow &f, const IB &ib, double *q,
                           double ab_axis, int axis, hipStream_t s);
 hipError_t launch_residual(const Grid &g, const Flow &f, const IB &ib, const double *q, double *r,
                            hipStream_t s);
-// tile_set: 0 all tiles, 1 tiles whose stencils read no fill output, 2 the others
+// part: null runs every tile with no fill; the stencils resolve domain ghost
+// cells on the fly, so the state's halo is never read
 hipError_t launch_rk_stage(const Grid &g, const Flow &f, const IB &ib, const double *qn,
-                           const double *qin, double *qout, double a, double b, hipStream_t s,
-                           int tile_set = 0);
-hipError_t launch_dual_iter(const Grid &g, const Flow &f, const IB &ib, const double *w,
+                           double *qin, double *qout, double a, double b, hipStream_t s,
+                           const StagePart *part = nullptr);
+hipError_t launch_dual_iter(const Grid &g, const Flow &f, const IB &ib, double *w,
                             double *wout, const double *qn, const double *qnm1, double b0,
-                            double b2, hipStream_t s, int tile_set = 0);
+                            double b2, hipStream_t s, const StagePart *part = nullptr);
 hipError_t launch_dual_begin(const Grid &g, const Flow &f, const double *w, double *qn,
                              double *qnm1, int first, hipStream_t s);
 hipError_t launch_prim_to_state(const Grid &g, const Flow &f, const double *prim, double *q,

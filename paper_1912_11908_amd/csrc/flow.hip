@@ -299,22 +299,13 @@ __device__ inline void fill_one(const Grid &g, const Flow &f, const IB &ib, doub
     }
 }
 
-// Domain ghosts (blocks [0, nbb)) and forcing nodes (the remaining blocks,
-// grid-stride) in one launch: the forcing fill reads interior FLUID cells
-// only, the ghost layers never, so the two are independent.
+// FORCING nodes (they read interior FLUID cells only), grid-stride.
 template <int DIM>
-__global__ void bc_forcing_kernel(Grid g, FreeStream fs, Flow f, IB ib, double *q, int nhalo, int nbb,
-                                  double ub, double ab, int axis)
+__global__ void forcing_fill_kernel(Grid g, Flow f, IB ib, double *q, double ub, double ab, int axis)
 {
-    if ((int)blockIdx.x < nbb) {
-        int t = blockIdx.x * blockDim.x + threadIdx.x;
-        if (t < nhalo)
-            bc_cell(g, fs, q, t);
-        return;
-    }
     int nF = min(ib.counts[CNT_F], ib.cap);
-    int stride = (gridDim.x - nbb) * blockDim.x;
-    for (int r = (blockIdx.x - nbb) * blockDim.x + threadIdx.x; r < nF; r += stride)
+    int stride = gridDim.x * blockDim.x;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nF; r += stride)
         fill_one<DIM>(g, f, ib, q, r, ub, ab, axis);
 }
 
@@ -332,10 +323,10 @@ __global__ void ghost_fill_kernel(Grid g, Flow f, IB ib, double *q, double ub, d
 // ------------------------------------------------ fused residual / update
 template <int DIM> struct TileCfg;
 template <> struct TileCfg<2> {
-    static constexpr int TX = 32, TY = 8, TZ = 1, HZ = 0;
+    static constexpr int TX = kTile2[0], TY = kTile2[1], TZ = kTile2[2], HZ = 0;
 };
 template <> struct TileCfg<3> {
-    static constexpr int TX = 8, TY = 8, TZ = 4, HZ = 3;
+    static constexpr int TX = kTile3[0], TY = kTile3[1], TZ = kTile3[2], HZ = 3;
 };
 
 enum { MODE_RESID = 0, MODE_RK3 = 1, MODE_DUAL = 2 };
@@ -345,15 +336,43 @@ struct StepArgs {
     Flow f;
     const uint8_t *cls;
     int32_t *counts;
-    const double *qin;   // state read by the stencils
+    double *qin;         // state read by the stencils (and filled by fill blocks)
     const double *qn;    // RK3: Q^n (state layout); dual: Q'^n (interior layout)
     const double *qnm1;  // dual: Q'^{n-1} (interior layout)
     double *out;         // RK3/dual: next state; residual mode: R (interior)
     double a, b;         // RK3 stage coefficients / dual b0, b2
     int ntx, nty, ntz;
-    int tile_set;        // 0: all tiles; 1: far tiles only; 2: near tiles only
-    int region[6];       // immersed-boundary region (cells)
+    const int32_t *tiles;  // tile ids to run (null: every tile)
+    int ntiles;
+    int nfill;           // leading blocks that fill IB nodes (a multiple of 8)
+    int fill;            // PART_FILL_FORCING or PART_FILL_GHOSTS
+    IB ib;
+    double ub, ab;       // body velocity / acceleration along `axis`
+    int axis;
+    FreeStream fs;       // conserved or perturbation free-stream state
 };
+
+// Domain ghost cell -> source cell, by the rules of the ghost-layer fill:
+// EXTRAP copies the nearest interior cell, PERIODIC wraps; a cell outside
+// a FARFIELD side takes the free stream (returns true).
+template <int DIM> __device__ inline bool ghost_source(const Grid &g, int *c)
+{
+    const int n[3] = {g.ni, g.nj, g.nk};
+    bool ff = false;
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+        if (c[ax] >= 0 && c[ax] < n[ax])
+            continue;
+        int type = g.bc[2 * ax + (c[ax] < 0 ? 0 : 1)];
+        if (type == IBM_BC_FARFIELD)
+            ff = true;
+        else if (type == IBM_BC_EXTRAP)
+            c[ax] = c[ax] < 0 ? 0 : n[ax] - 1;
+        else
+            c[ax] = ((c[ax] % n[ax]) + n[ax]) % n[ax];
+    }
+    return ff;
+}
 
 // WENO5 (Jiang-Shu, eps 1e-6, linear weights 0.1, 0.6, 0.3) left state at
 // i+1/2 from v(i-2..i+2).  The nonlinear weights are formed with a single
@@ -572,7 +591,7 @@ __device__ inline void face_pass(const Real *__restrict__ S, Real *__restrict__ 
     }
 }
 
-template <int DIM, typename Real, int MODE>
+template <int DIM, typename Real, int MODE, bool FUSED>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs A)
 {
     using C = TileCfg<DIM>;
@@ -590,63 +609,76 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs A)
 
     const Grid &g = A.g;
     const Flow &f = A.f;
-    // tile id, spread so that consecutive tiles share an XCD (8 XCDs, blocks
-    // dispatched round-robin)
-    int nt = A.ntx * A.nty * A.ntz;
-    int b = blockIdx.x;
-    int tile = (nt % 8 == 0) ? (b % 8) * (nt / 8) + b / 8 : b;
+    if constexpr (FUSED) {
+        // leading blocks: fill the IB nodes of the stage input (grid-stride);
+        // the tiles of this launch never read those nodes
+        if ((int)blockIdx.x < A.nfill) {
+            int nF = min(A.ib.counts[CNT_F], A.ib.cap);
+            int stride = A.nfill * kBlock;
+            int r0 = blockIdx.x * kBlock + threadIdx.x;
+            if (A.fill == PART_FILL_FORCING) {
+                for (int r = r0; r < nF; r += stride)
+                    fill_one<DIM>(g, f, A.ib, A.qin, r, A.ub, A.ab, A.axis);
+            } else {
+                int nG = min(A.ib.counts[CNT_G], A.ib.cap - nF);
+                for (int r = r0; r < nG; r += stride)
+                    fill_one<DIM>(g, f, A.ib, A.qin, nF + r, A.ub, A.ab, A.axis);
+            }
+            return;
+        }
+    }
+    // tile id: the blocks b with the same b mod 8 (dispatched to the same
+    // XCD) take a contiguous run of the tile list, so neighbouring tiles
+    // share that XCD's L2
+    int nt = A.tiles ? A.ntiles : A.ntx * A.nty * A.ntz;
+    int b = (int)blockIdx.x - (FUSED ? A.nfill : 0);
+    int per = (nt + 7) / 8;
+    int pos = (b % 8) * per + b / 8;
+    if (pos >= nt)
+        return;
+    int tile = A.tiles ? A.tiles[pos] : pos;
     int tx0 = tile % A.ntx, ty0 = (tile / A.ntx) % A.nty, tz0 = tile / (A.ntx * A.nty);
     int i0 = tx0 * TX, j0 = ty0 * TY, k0 = tz0 * TZ;
     int tid = threadIdx.x;
-    if (A.tile_set != 0) {
-        // a tile is "near" when its stencil footprint (3-cell halo) reaches a
-        // domain ghost cell or the immersed-boundary region: only those read
-        // cells that the fill of this stage writes
-        bool nearb = i0 - 3 < 0 || i0 + TX + 3 > g.ni || j0 - 3 < 0 || j0 + TY + 3 > g.nj ||
-                     (DIM == 3 && (k0 - 3 < 0 || k0 + TZ + 3 > g.nk));
-        bool hits = i0 - 3 < A.region[1] && i0 + TX + 3 > A.region[0] && j0 - 3 < A.region[3] &&
-                    j0 + TY + 3 > A.region[2] &&
-                    (DIM == 2 || (k0 - 3 < A.region[5] && k0 + TZ + 3 > A.region[4]));
-        bool near = nearb || hits;
-        if ((A.tile_set == 1) == near)
-            return;
-    }
 
-    // 1. load the tile and its 3-cell halo, recovering (rho', u.., p', T')
+    // 1. load the tile and its 3-cell halo, recovering (rho', u.., p', T');
+    //    domain ghost cells are resolved on the fly
     for (int t = tid; t < LCELLS; t += kBlock) {
         int lx = t % LX, ly = (t / LX) % LY, lz = t / (LX * LY);
-        int i = i0 + lx - 3, j = j0 + ly - 3, k = k0 + lz - HZ;
-        bool ok = i >= -3 && i < g.ni + 3 && j >= -3 && j < g.nj + 3 &&
-                  (DIM == 2 || (k >= -3 && k < g.nk + 3));
-        double v[NS];
-        if (ok) {
-            long long s = sidx(g, i, j, k);
-            if (f.scheme == IBM_RK3) {
-                double rho = A.qin[s];
-                double ke = 0.0;
+        int c[3] = {i0 + lx - 3, j0 + ly - 3, k0 + lz - HZ};
+        double qv[NV];
+        bool ff = ghost_source<DIM>(g, c);
+        if (ff) {
 #pragma unroll
-                for (int d = 0; d < DIM; ++d) {
-                    v[1 + d] = A.qin[s + (1 + d) * g.vs] / rho;
-                    ke += v[1 + d] * v[1 + d];
-                }
-                double p = (f.gamma - 1.0) * (A.qin[s + (DIM + 1) * g.vs] - 0.5 * rho * ke);
-                v[0] = rho - 1.0;
-                v[DIM + 1] = p - f.pinf;
-                v[DIM + 2] = p / (rho * f.R) - 1.0;
-            } else {
-                double pp = A.qin[s], tp = A.qin[s + (DIM + 1) * g.vs];
-#pragma unroll
-                for (int d = 0; d < DIM; ++d)
-                    v[1 + d] = A.qin[s + (1 + d) * g.vs];
-                v[0] = (pp - f.R * tp) / (f.R * (1.0 + tp));
-                v[DIM + 1] = pp;
-                v[DIM + 2] = tp;
-            }
+            for (int m = 0; m < NV; ++m)
+                qv[m] = A.fs.v[m];
         } else {
+            long long s = sidx(g, c[0], c[1], c[2]);
 #pragma unroll
-            for (int m = 0; m < NS; ++m)
-                v[m] = 0.0;
-            v[1] = 1.0;
+            for (int m = 0; m < NV; ++m)
+                qv[m] = A.qin[s + m * g.vs];
+        }
+        double v[NS];
+        if (f.scheme == IBM_RK3) {
+            double rho = qv[0];
+            double ke = 0.0;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                v[1 + d] = qv[1 + d] / rho;
+                ke += v[1 + d] * v[1 + d];
+            }
+            double p = (f.gamma - 1.0) * (qv[DIM + 1] - 0.5 * rho * ke);
+            v[0] = rho - 1.0;
+            v[DIM + 1] = p - f.pinf;
+            v[DIM + 2] = p / (rho * f.R) - 1.0;
+        } else {
+            double pp = qv[0], tp = qv[DIM + 1];
+#pragma unroll
+            for (int d = 0; d < DIM; ++d)
+                v[1 + d] = qv[1 + d];
+            v[0] = (pp - f.R * tp) / (f.R * (1.0 + tp));
+            v[DIM + 1] = pp;
+            v[DIM + 2] = tp;
         }
 #pragma unroll
         for (int m = 0; m < NS; ++m)
@@ -903,17 +935,37 @@ __global__ void state_to_prim_kernel(Grid g, Flow f, const double *q, double *pr
     prim[(nd + 1) * g.ncell + c] = w.p;
 }
 
-__global__ void copy_kernel(const double *src, double *dst, long long n)
+// interior cells of every variable (the halo is left as it is)
+__global__ void copy_kernel(Grid g, const double *src, double *dst)
 {
-    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n)
-        dst[t] = src[t];
+    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.ncell)
+        return;
+    int i = (int)(c % g.ni), j = (int)((c / g.ni) % g.nj), k = (int)(c / ((long long)g.ni * g.nj));
+    long long s = sidx(g, i, j, k);
+    for (int m = 0; m < g.nv; ++m)
+        dst[s + m * g.vs] = src[s + m * g.vs];
+}
+
+FreeStream freestream_of(const Grid &g, const Flow &f)
+{
+    FreeStream fs;
+    for (int m = 0; m < 5; ++m)
+        fs.v[m] = 0.0;
+    if (f.scheme == IBM_RK3) {
+        fs.v[0] = 1.0;
+        fs.v[1] = 1.0;
+        fs.v[g.nv - 1] = f.pinf / (f.gamma - 1.0) + 0.5;
+    } else {
+        fs.v[1] = 1.0;
+    }
+    return fs;
 }
 
 template <int DIM, typename Real, int MODE>
-hipError_t run_step(const Grid &g, const Flow &f, const IB &ib, const double *qin,
-                    const double *qn, const double *qnm1, double *out, double a, double b,
-                    hipStream_t s, int tile_set)
+hipError_t run_step(const Grid &g, const Flow &f, const IB &ib, double *qin, const double *qn,
+                    const double *qnm1, double *out, double a, double b, hipStream_t s,
+                    const StagePart *part)
 {
     using C = TileCfg<DIM>;
     StepArgs A;
@@ -930,43 +982,45 @@ hipError_t run_step(const Grid &g, const Flow &f, const IB &ib, const double *qi
     A.ntx = (g.ni + C::TX - 1) / C::TX;
     A.nty = (g.nj + C::TY - 1) / C::TY;
     A.ntz = DIM == 3 ? (g.nk + C::TZ - 1) / C::TZ : 1;
-    A.tile_set = tile_set;
-    for (int m = 0; m < 6; ++m)
-        A.region[m] = ib.cap > 0 ? ib.region[m] : 0;
-    int nt = A.ntx * A.nty * A.ntz;
-    hipLaunchKernelGGL((step_kernel<DIM, Real, MODE>), dim3(nt), dim3(kBlock), 0, s, A);
+    A.tiles = part ? part->tiles : nullptr;
+    A.ntiles = part ? part->ntiles : 0;
+    A.fill = part ? part->fill : PART_NO_FILL;
+    A.nfill = 0;
+    A.ib = ib;
+    A.ub = part ? part->ub : 0.0;
+    A.ab = part ? part->ab : 0.0;
+    A.axis = part ? part->axis : -1;
+    A.fs = freestream_of(g, f);
+    if (A.fill != PART_NO_FILL && ib.cap > 0) {
+        int nb = blocks_for(ib.cap, kBlock);
+        nb = nb < 64 ? nb : 64;
+        A.nfill = (nb + 7) / 8 * 8;
+    }
+    int nt = A.tiles ? A.ntiles : A.ntx * A.nty * A.ntz;
+    int grid = A.nfill + 8 * ((nt + 7) / 8);
+    if (grid == 0)
+        return hipSuccess;
+    if (A.nfill > 0)
+        hipLaunchKernelGGL((step_kernel<DIM, Real, MODE, true>), dim3(grid), dim3(kBlock), 0, s, A);
+    else
+        hipLaunchKernelGGL((step_kernel<DIM, Real, MODE, false>), dim3(grid), dim3(kBlock), 0, s, A);
     return hipGetLastError();
 }
 
 template <int MODE>
-hipError_t dispatch_step(const Grid &g, const Flow &f, const IB &ib, const double *qin,
-                         const double *qn, const double *qnm1, double *out, double a, double b,
-                         hipStream_t s, int tile_set = 0)
+hipError_t dispatch_step(const Grid &g, const Flow &f, const IB &ib, double *qin, const double *qn,
+                         const double *qnm1, double *out, double a, double b, hipStream_t s,
+                         const StagePart *part = nullptr)
 {
     bool mixed = f.precision == IBM_MIXED;
     if (g.ndim == 2)
-        return mixed ? run_step<2, float, MODE>(g, f, ib, qin, qn, qnm1, out, a, b, s, tile_set)
-                     : run_step<2, double, MODE>(g, f, ib, qin, qn, qnm1, out, a, b, s, tile_set);
-    return mixed ? run_step<3, float, MODE>(g, f, ib, qin, qn, qnm1, out, a, b, s, tile_set)
-                 : run_step<3, double, MODE>(g, f, ib, qin, qn, qnm1, out, a, b, s, tile_set);
+        return mixed ? run_step<2, float, MODE>(g, f, ib, qin, qn, qnm1, out, a, b, s, part)
+                     : run_step<2, double, MODE>(g, f, ib, qin, qn, qnm1, out, a, b, s, part);
+    return mixed ? run_step<3, float, MODE>(g, f, ib, qin, qn, qnm1, out, a, b, s, part)
+                 : run_step<3, double, MODE>(g, f, ib, qin, qn, qnm1, out, a, b, s, part);
 }
 
 }  // namespace
-
-static FreeStream freestream_of(const Grid &g, const Flow &f)
-{
-    FreeStream fs;
-    for (int m = 0; m < 5; ++m)
-        fs.v[m] = 0.0;
-    if (f.scheme == IBM_RK3) {
-        fs.v[0] = 1.0;
-        fs.v[1] = 1.0;
-        fs.v[g.nv - 1] = f.pinf / (f.gamma - 1.0) + 0.5;
-    } else {
-        fs.v[1] = 1.0;
-    }
-    return fs;
-}
 
 hipError_t launch_domain_bc(const Grid &g, const Flow &f, double *q, hipStream_t s)
 {
@@ -976,48 +1030,51 @@ hipError_t launch_domain_bc(const Grid &g, const Flow &f, double *q, hipStream_t
     return hipGetLastError();
 }
 
+// IB nodes (FORCING, then the ghost layers that read them), then the domain
+// ghost layers as images of the filled interior.
 hipError_t launch_bc_fill(const Grid &g, const Flow &f, const IB &ib, double *q, double ub_axis,
                           double ab_axis, int axis, hipStream_t s)
 {
-    if (ib.cap == 0)
-        return launch_domain_bc(g, f, q, s);
-    int nhalo = (int)((long long)g.sx * g.sy * g.sz - g.ncell);
-    int nbb = blocks_for(nhalo, kBlock);
-    int nbf = blocks_for(ib.cap, kBlock);
-    nbf = nbf < 64 ? nbf : 64;
-    FreeStream fs = freestream_of(g, f);
-    if (g.ndim == 2) {
-        hipLaunchKernelGGL(bc_forcing_kernel<2>, dim3(nbb + nbf), dim3(kBlock), 0, s, g, fs, f, ib, q, nhalo,
-                           nbb, ub_axis, ab_axis, axis);
-        hipLaunchKernelGGL(ghost_fill_kernel<2>, dim3(nbf), dim3(kBlock), 0, s, g, f, ib, q, ub_axis,
-                           ab_axis, axis);
-    } else {
-        hipLaunchKernelGGL(bc_forcing_kernel<3>, dim3(nbb + nbf), dim3(kBlock), 0, s, g, fs, f, ib, q, nhalo,
-                           nbb, ub_axis, ab_axis, axis);
-        hipLaunchKernelGGL(ghost_fill_kernel<3>, dim3(nbf), dim3(kBlock), 0, s, g, f, ib, q, ub_axis,
-                           ab_axis, axis);
+    if (ib.cap > 0) {
+        int nbf = blocks_for(ib.cap, kBlock);
+        nbf = nbf < 64 ? nbf : 64;
+        if (g.ndim == 2) {
+            hipLaunchKernelGGL(forcing_fill_kernel<2>, dim3(nbf), dim3(kBlock), 0, s, g, f, ib, q, ub_axis,
+                               ab_axis, axis);
+            hipLaunchKernelGGL(ghost_fill_kernel<2>, dim3(nbf), dim3(kBlock), 0, s, g, f, ib, q, ub_axis,
+                               ab_axis, axis);
+        } else {
+            hipLaunchKernelGGL(forcing_fill_kernel<3>, dim3(nbf), dim3(kBlock), 0, s, g, f, ib, q, ub_axis,
+                               ab_axis, axis);
+            hipLaunchKernelGGL(ghost_fill_kernel<3>, dim3(nbf), dim3(kBlock), 0, s, g, f, ib, q, ub_axis,
+                               ab_axis, axis);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
     }
-    return hipGetLastError();
+    return launch_domain_bc(g, f, q, s);
 }
 
 hipError_t launch_residual(const Grid &g, const Flow &f, const IB &ib, const double *q, double *r,
                            hipStream_t s)
 {
-    return dispatch_step<MODE_RESID>(g, f, ib, q, nullptr, nullptr, r, 0.0, 0.0, s);
+    // no fill part: the kernel only reads q
+    return dispatch_step<MODE_RESID>(g, f, ib, const_cast<double *>(q), nullptr, nullptr, r, 0.0, 0.0,
+                                     s);
 }
 
-hipError_t launch_rk_stage(const Grid &g, const Flow &f, const IB &ib, const double *qn,
-                           const double *qin, double *qout, double a, double b, hipStream_t s,
-                           int tile_set)
+hipError_t launch_rk_stage(const Grid &g, const Flow &f, const IB &ib, const double *qn, double *qin,
+                           double *qout, double a, double b, hipStream_t s, const StagePart *part)
 {
-    return dispatch_step<MODE_RK3>(g, f, ib, qin, qn, nullptr, qout, a, b, s, tile_set);
+    return dispatch_step<MODE_RK3>(g, f, ib, qin, qn, nullptr, qout, a, b, s, part);
 }
 
-hipError_t launch_dual_iter(const Grid &g, const Flow &f, const IB &ib, const double *w,
-                            double *wout, const double *qn, const double *qnm1, double b0,
-                            double b2, hipStream_t s, int tile_set)
+hipError_t launch_dual_iter(const Grid &g, const Flow &f, const IB &ib, double *w, double *wout,
+                            const double *qn, const double *qnm1, double b0, double b2, hipStream_t s,
+                            const StagePart *part)
 {
-    return dispatch_step<MODE_DUAL>(g, f, ib, w, qn, qnm1, wout, b0, b2, s, tile_set);
+    return dispatch_step<MODE_DUAL>(g, f, ib, w, qn, qnm1, wout, b0, b2, s, part);
 }
 
 hipError_t launch_dual_begin(const Grid &g, const Flow &f, const double *w, double *qn,
@@ -1046,8 +1103,7 @@ hipError_t launch_state_to_prim(const Grid &g, const Flow &f, const double *q, d
 
 hipError_t launch_copy_state(const Grid &g, const double *src, double *dst, hipStream_t s)
 {
-    long long n = g.vs * g.nv;
-    hipLaunchKernelGGL(copy_kernel, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, src, dst, n);
+    hipLaunchKernelGGL(copy_kernel, dim3(blocks_for(g.ncell, kBlock)), dim3(kBlock), 0, s, g, src, dst);
     return hipGetLastError();
 }
 

@@ -407,8 +407,8 @@ def test_fill_reproduces_linear_wall_profile(family):
     prim[2, 0] = -0.3 * s
     prim[3] = p_inf
     q = o.prim_to_state(prim)
-    o.bc(q)
     o.fill(q)
+    o.bc(q)
     P = o.state_to_prim(q)
     ir, dr = o.records()
     nF = o.lists()[2][0]
@@ -462,8 +462,8 @@ def test_fill_moving_wall_dirichlet_velocity():
     prim[2, 0] = ub + 0.25 * s
     prim[3] = c.p_inf
     q = o.prim_to_state(prim)
-    o.bc(q)
     o.fill(q, t)
+    o.bc(q)
     P = o.state_to_prim(q)
     ir, dr = o.records()
     nF = o.lists()[2][0]

@@ -252,8 +252,8 @@ def test_ghost_layers_cover_stencils(kind):
     nv = c.ndim + 2
     prim = w.freestream_prim(2, c.ni, c.nj, 1, c.p_inf)
     q = o.prim_to_state(prim)
-    o.bc(q)
     o.fill(q)
+    o.bc(q)
     o.residual(q)
     assert o.stats()["stencil_violation"] == 0
     assert nv == 4
