@@ -77,7 +77,7 @@ struct IB {
 };
 
 // Tiles of the fused residual/update kernel: cells per block along x, y, z.
-constexpr int kTile2[3] = {32, 8, 1};
+constexpr int kTile2[3] = {16, 15, 1};  // 255 x-faces, 256 y-faces: one pass each
 constexpr int kTile3[3] = {8, 8, 4};
 
 // One launch of a stage of the fused residual/update kernel: a list of tiles

@@ -640,49 +640,92 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs A)
     int tx0 = tile % A.ntx, ty0 = (tile / A.ntx) % A.nty, tz0 = tile / (A.ntx * A.nty);
     int i0 = tx0 * TX, j0 = ty0 * TY, k0 = tz0 * TZ;
     int tid = threadIdx.x;
+    constexpr int NCELL = TX * TY * TZ;  // <= kBlock
+    static_assert(NCELL <= kBlock, "one thread per tile cell");
+
+    // own cell of the update, its class and state fetched first so that
+    // their latency overlaps the stencil work
+    int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
+    int i = i0 + tx, j = j0 + ty, k = k0 + tz;
+    bool own = tid < NCELL && i < g.ni && j < g.nj && (DIM == 2 || k < g.nk);
+    long long cell = ((long long)k * g.nj + j) * g.ni + i;
+    long long s_own = sidx(g, i, j, k);
+    uint8_t cls = IBM_SOLID;
+    double qc[NV], qnc[NV];
+#pragma unroll
+    for (int m = 0; m < NV; ++m)
+        qc[m] = qnc[m] = 0.0;
+    if (own) {
+        cls = A.cls[cell];
+        if (MODE != MODE_RESID) {
+#pragma unroll
+            for (int m = 0; m < NV; ++m)
+                qc[m] = A.qin[s_own + m * g.vs];
+        }
+        if (MODE == MODE_RK3 && A.a != 0.0) {
+#pragma unroll
+            for (int m = 0; m < NV; ++m)
+                qnc[m] = A.qn[s_own + m * g.vs];
+        }
+    }
 
     // 1. load the tile and its 3-cell halo, recovering (rho', u.., p', T');
-    //    domain ghost cells are resolved on the fly
-    for (int t = tid; t < LCELLS; t += kBlock) {
-        int lx = t % LX, ly = (t / LX) % LY, lz = t / (LX * LY);
-        int c[3] = {i0 + lx - 3, j0 + ly - 3, k0 + lz - HZ};
-        double qv[NV];
-        bool ff = ghost_source<DIM>(g, c);
-        if (ff) {
+    //    domain ghost cells are resolved on the fly.  Two rounds of loads
+    //    are issued before either is converted.
+    constexpr int NR = (LCELLS + kBlock - 1) / kBlock;
+    constexpr int NB = NR < 2 ? NR : 2;
+    for (int r0 = 0; r0 < NR; r0 += NB) {
+        double qv[NB][NV];
 #pragma unroll
-            for (int m = 0; m < NV; ++m)
-                qv[m] = A.fs.v[m];
-        } else {
-            long long s = sidx(g, c[0], c[1], c[2]);
+        for (int rr = 0; rr < NB; ++rr) {
+            int t = tid + (r0 + rr) * kBlock;
+            if (r0 + rr >= NR || t >= LCELLS)
+                continue;
+            int lx = t % LX, ly = (t / LX) % LY, lz = t / (LX * LY);
+            int c[3] = {i0 + lx - 3, j0 + ly - 3, k0 + lz - HZ};
+            bool ff = ghost_source<DIM>(g, c);
+            if (ff) {
 #pragma unroll
-            for (int m = 0; m < NV; ++m)
-                qv[m] = A.qin[s + m * g.vs];
-        }
-        double v[NS];
-        if (f.scheme == IBM_RK3) {
-            double rho = qv[0];
-            double ke = 0.0;
+                for (int m = 0; m < NV; ++m)
+                    qv[rr][m] = A.fs.v[m];
+            } else {
+                long long s = sidx(g, c[0], c[1], c[2]);
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) {
-                v[1 + d] = qv[1 + d] / rho;
-                ke += v[1 + d] * v[1 + d];
+                for (int m = 0; m < NV; ++m)
+                    qv[rr][m] = A.qin[s + m * g.vs];
             }
-            double p = (f.gamma - 1.0) * (qv[DIM + 1] - 0.5 * rho * ke);
-            v[0] = rho - 1.0;
-            v[DIM + 1] = p - f.pinf;
-            v[DIM + 2] = p / (rho * f.R) - 1.0;
-        } else {
-            double pp = qv[0], tp = qv[DIM + 1];
-#pragma unroll
-            for (int d = 0; d < DIM; ++d)
-                v[1 + d] = qv[1 + d];
-            v[0] = (pp - f.R * tp) / (f.R * (1.0 + tp));
-            v[DIM + 1] = pp;
-            v[DIM + 2] = tp;
         }
 #pragma unroll
-        for (int m = 0; m < NS; ++m)
-            S[m * LCELLS + t] = (Real)v[m];
+        for (int rr = 0; rr < NB; ++rr) {
+            int t = tid + (r0 + rr) * kBlock;
+            if (r0 + rr >= NR || t >= LCELLS)
+                continue;
+            double v[NS];
+            if (f.scheme == IBM_RK3) {
+                double rho = qv[rr][0];
+                double ke = 0.0;
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) {
+                    v[1 + d] = qv[rr][1 + d] / rho;
+                    ke += v[1 + d] * v[1 + d];
+                }
+                double p = (f.gamma - 1.0) * (qv[rr][DIM + 1] - 0.5 * rho * ke);
+                v[0] = rho - 1.0;
+                v[DIM + 1] = p - f.pinf;
+                v[DIM + 2] = p / (rho * f.R) - 1.0;
+            } else {
+                double pp = qv[rr][0], tp = qv[rr][DIM + 1];
+#pragma unroll
+                for (int d = 0; d < DIM; ++d)
+                    v[1 + d] = qv[rr][1 + d];
+                v[0] = (pp - f.R * tp) / (f.R * (1.0 + tp));
+                v[DIM + 1] = pp;
+                v[DIM + 2] = tp;
+            }
+#pragma unroll
+            for (int m = 0; m < NS; ++m)
+                S[m * LCELLS + t] = (Real)v[m];
+        }
     }
     __syncthreads();
 
@@ -702,18 +745,14 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs A)
     __syncthreads();
 
     // 3. per-cell residual and update
-    int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
-    int i = i0 + tx, j = j0 + ty, k = k0 + tz;
-    if (i >= g.ni || j >= g.nj || (DIM == 3 && k >= g.nk))
+    if (!own)
         return;
-    long long cell = ((long long)k * g.nj + j) * g.ni + i;
-    uint8_t cls = A.cls[cell];
-    long long s = sidx(g, i, j, k);
+    long long s = s_own;
     if (MODE != MODE_RESID) {
         if (cls != IBM_FLUID) {  // IB nodes carry their filled value, solid cells their state
 #pragma unroll
             for (int m = 0; m < NV; ++m)
-                A.out[s + m * g.vs] = A.qin[s + m * g.vs];
+                A.out[s + m * g.vs] = qc[m];
             return;
         }
     } else if (cls != IBM_FLUID) {
@@ -750,10 +789,9 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs A)
         bool bad = false;
 #pragma unroll
         for (int m = 0; m < NV; ++m) {
-            double qi = A.qin[s + m * g.vs];
-            double qv = A.b * (qi - f.dt * R[m]);
+            double qv = A.b * (qc[m] - f.dt * R[m]);
             if (A.a != 0.0)
-                qv += A.a * A.qn[s + m * g.vs];
+                qv += A.a * qnc[m];
             A.out[s + m * g.vs] = qv;
             bad |= !isfinite(qv);
             if (m == 0)
@@ -766,11 +804,11 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs A)
     // MODE_DUAL: point-implicit preconditioned pseudo-time step, FP64
     {
         constexpr int N = NV;
-        double pp = A.qin[s], tp = A.qin[s + (DIM + 1) * g.vs];
+        double pp = qc[0], tp = qc[DIM + 1];
         double u[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
-            u[d] = A.qin[s + (1 + d) * g.vs];
+            u[d] = qc[1 + d];
         double p = f.pinf + pp, T = 1.0 + tp;
         double rho = p / (f.R * T);
         double rhop = (pp - f.R * tp) / (f.R * T);  // rho - 1
@@ -865,7 +903,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs A)
         }
         bool bad = false;
         for (int m = 0; m < N; ++m) {
-            double v = A.qin[s + m * g.vs] + rhs[m];
+            double v = qc[m] + rhs[m];
             A.out[s + m * g.vs] = v;
             bad |= !isfinite(v);
         }
