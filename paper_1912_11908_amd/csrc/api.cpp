@@ -27,9 +27,11 @@ struct ibm_ctx {
     long long step;
     int n_inner;
     bool classified;
-    // tile lists of the stage launches (device)
-    const int32_t *tiles_far, *tiles_near;
-    int nfar, nnear;
+    // tile lists of the two stage launches (device): the first holds far
+    // tiles only, the second the near tiles spread over the XCD chunks and
+    // the remaining far tiles, padded with -1
+    const int32_t *tiles1, *tiles2;
+    int ntiles1, ntiles2;
     // graph replay of whole steps (stationary bodies): slot 0 holds one
     // step, slot 1 a chunk of kChunk steps
     bool use_graphs;
@@ -413,6 +415,7 @@ struct Layout {
     double *rec_d;
     int32_t *plan_node, *plan_off, *plan_mode;
     double *plan_w, *plan_geo;
+    int32_t *rmap;
     int32_t *tiles;
     double *q1, *q2, *wtmp, *qn, *qnm1;
 };
@@ -459,7 +462,8 @@ size_t carve(const ibm_case *c, const HostGeom &h, char *base, Layout &L)
     L.plan_w = cv.take<double>(16 * cap);
     L.plan_geo = cv.take<double>(6 * cap);
     L.plan_mode = cv.take<int32_t>(cap);
-    L.tiles = cv.take<int32_t>(std::max<size_t>(h.tiles_far.size() + h.tiles_near.size(), 1));
+    L.rmap = cv.take<int32_t>(cap);
+    L.tiles = cv.take<int32_t>(h.tiles_far.size() + h.tiles_near.size() + 16);
     size_t st = (size_t)h.vs * (nd + 2);
     L.q1 = L.q2 = L.wtmp = L.qn = L.qnm1 = nullptr;
     if (c->scheme == IBM_RK3) {
@@ -686,8 +690,36 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     ib.plan_w = L.plan_w;
     ib.plan_geo = L.plan_geo;
     ib.plan_mode = L.plan_mode;
-    if (e == hipSuccess) e = up(L.tiles, h.tiles_far);
-    if (e == hipSuccess) e = up(L.tiles + h.tiles_far.size(), h.tiles_near);
+    ib.rmap = L.rmap;
+    // first launch: as many far tiles as leave each CU room for two more
+    // resident blocks (the near tiles are latency-bound and run with the
+    // rest in the second launch)
+    std::vector<int32_t> list1, list2;
+    {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, x->device) != hipSuccess)
+            ncu = 0;
+        int occ = stage_blocks_per_cu(g, f);
+        int nfar = (int)h.tiles_far.size(), nnear = (int)h.tiles_near.size();
+        int k = occ > 2 && ncu > 0 ? std::min(nfar, ncu * (occ - 2)) : nfar;
+        list1.assign(h.tiles_far.begin(), h.tiles_far.begin() + k);
+        std::vector<int32_t> chunk[8];
+        int nf2 = nfar - k;
+        size_t per = 0;
+        for (int x = 0; x < 8; ++x) {
+            for (long long m = (long long)x * nnear / 8; m < (long long)(x + 1) * nnear / 8; ++m)
+                chunk[x].push_back(h.tiles_near[m]);
+            for (long long m = (long long)x * nf2 / 8; m < (long long)(x + 1) * nf2 / 8; ++m)
+                chunk[x].push_back(h.tiles_far[k + m]);
+            per = std::max(per, chunk[x].size());
+        }
+        for (int x = 0; x < 8; ++x) {
+            chunk[x].resize(per, -1);
+            list2.insert(list2.end(), chunk[x].begin(), chunk[x].end());
+        }
+    }
+    if (e == hipSuccess) e = up(L.tiles, list1);
+    if (e == hipSuccess) e = up(L.tiles + list1.size(), list2);
     if (e == hipSuccess) e = hipMemset(L.cls, IBM_FLUID, (size_t)h.ncell);
     if (e == hipSuccess) e = hipMemset(L.counts, 0, sizeof(int32_t) * CNT_WORDS);
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -712,10 +744,10 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
         x->graph_exec[k] = nullptr;
         x->graph_q[k] = nullptr;
     }
-    x->tiles_far = L.tiles;
-    x->nfar = (int)h.tiles_far.size();
-    x->tiles_near = L.tiles + h.tiles_far.size();
-    x->nnear = (int)h.tiles_near.size();
+    x->tiles1 = L.tiles;
+    x->ntiles1 = (int)list1.size();
+    x->tiles2 = L.tiles + list1.size();
+    x->ntiles2 = (int)list2.size();
     if (e != hipSuccess) {
         delete x;
         return IBM_EDEVICE;
@@ -802,10 +834,11 @@ int ibm_residual(ibm_ctx *c, const double *q, double *r, void *stream)
 
 namespace {
 
-// One stage: with a body, three launches on the stream -- the FORCING fill
-// with the first half of the far tiles, the ghost-layer fill (it reads the
-// FORCING nodes) with the second half, then the near tiles, whose stencils
-// read the filled nodes.  Without a body every tile runs in one launch.
+// One stage with a body is two launches on the stream: the FORCING fill
+// (it reads FLUID cells only) with the tiles whose stencils never reach the
+// immersed-boundary region, then the remaining tiles, which fill the ghost
+// layers they read from the FORCING values just stored.  Without a body
+// every tile runs in one launch.
 template <typename Launch> int enqueue_stage(ibm_ctx *c, double t, hipStream_t s, Launch launch)
 {
     if (c->b.nfacet == 0 || c->ib.cap == 0)
@@ -816,15 +849,11 @@ template <typename Launch> int enqueue_stage(ibm_ctx *c, double t, hipStream_t s
         motion_kin(c, t, disp, vel, acc);
         axis = c->mo.axis;
     }
-    int half = c->nfar / 2;
-    StagePart pa{c->tiles_far, half, PART_FILL_FORCING, vel, acc, axis};
-    StagePart pb{c->tiles_far + half, c->nfar - half, PART_FILL_GHOSTS, vel, acc, axis};
-    StagePart pc{c->tiles_near, c->nnear, PART_NO_FILL, vel, acc, axis};
-    hipError_t e = launch(s, &pa);
+    StagePart p1{c->tiles1, c->ntiles1, true, false, vel, acc, axis};
+    StagePart p2{c->tiles2, c->ntiles2, false, true, vel, acc, axis};
+    hipError_t e = launch(s, &p1);
     if (e == hipSuccess)
-        e = launch(s, &pb);
-    if (e == hipSuccess)
-        e = launch(s, &pc);
+        e = launch(s, &p2);
     return dev_err(c, e, "stage");
 }
 

@@ -74,22 +74,23 @@ struct IB {
     double *plan_w;          // 16 * cap
     double *plan_geo;        // 6 * cap
     int32_t *plan_mode;      // cap: mode1 | mode2 << 4
+    int32_t *rmap;           // cap: record index per region cell (IB nodes only)
 };
 
 // Tiles of the fused residual/update kernel: cells per block along x, y, z.
 constexpr int kTile2[3] = {16, 15, 1};  // 255 x-faces, 256 y-faces: one pass each
 constexpr int kTile3[3] = {8, 8, 4};
 
-// One launch of a stage of the fused residual/update kernel: a list of tiles
-// (null: every tile of the grid) and, ahead of the tiles, blocks that fill
-// the immersed-boundary nodes of the stage input (FORCING nodes, or the
-// ghost layers G1-G3 that read them).  Tiles whose stencils reach an IB node
-// must run after both fills.
-enum { PART_NO_FILL = 0, PART_FILL_FORCING = 1, PART_FILL_GHOSTS = 2 };
+// One launch of the fused residual/update kernel for a stage: a list of
+// tiles (null: every tile of the grid) and what the launch also fills.  A
+// stage with a body is two launches: the FORCING fill (leading blocks) with
+// the tiles whose stencils never reach the IB region, then the other tiles,
+// which fill the ghost layers G1-G3 they read on the fly.
 struct StagePart {
-    const int32_t *tiles;
+    const int32_t *tiles;    // tile ids, -1 entries are padding
     int ntiles;
-    int fill;
+    bool fill_forcing;       // leading blocks fill the FORCING nodes of qin
+    bool inline_ghosts;      // tiles fill the ghost nodes they read
     double ub, ab;           // body velocity and acceleration along `axis`
     int axis;                // motion axis, -1 for a stationary body
 };
@@ -126,5 +127,7 @@ hipError_t launch_prim_to_state(const Grid &g, const Flow &f, const double *prim
 hipError_t launch_state_to_prim(const Grid &g, const Flow &f, const double *q, double *prim,
                                 hipStream_t s);
 hipError_t launch_copy_state(const Grid &g, const double *src, double *dst, hipStream_t s);
+// resident blocks per CU of the stage kernel for this grid and flow (0 if unknown)
+int stage_blocks_per_cu(const Grid &g, const Flow &f);
 
 }  // namespace ibm

@@ -172,29 +172,34 @@ __global__ void bc_kernel(Grid g, FreeStream fs, double *q, int nhalo)
 // (Dirichlet) or slope (Neumann) and the probe; quadratic family: profile
 // through two probes (sections 4.5-4.6 and 5).  s = 0 at P', s > 0 in the
 // fluid; the node sits at s_X.
+// (rho, u.., p, T) of state values qv (the cell's NV state variables)
 template <int DIM>
-__device__ inline void load_prim_t(const Grid &g, const Flow &f, const double *q, long long s,
-                                   double &rho, double *u, double &p, double &T)
+__device__ inline void prim_of_state(const Flow &f, const double *qv, double &rho, double *u, double &p,
+                                     double &T)
 {
     if (f.scheme == IBM_RK3) {
-        rho = q[s];
+        rho = qv[0];
         double ke = 0.0;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-            u[d] = q[s + (1 + d) * g.vs] / rho;
+            u[d] = qv[1 + d] / rho;
             ke += u[d] * u[d];
         }
-        p = (f.gamma - 1.0) * (q[s + (DIM + 1) * g.vs] - 0.5 * rho * ke);
+        p = (f.gamma - 1.0) * (qv[DIM + 1] - 0.5 * rho * ke);
         T = p / (rho * f.R);
     } else {
-        p = f.pinf + q[s];
+        p = f.pinf + qv[0];
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
-            u[d] = q[s + (1 + d) * g.vs];
-        T = 1.0 + q[s + (DIM + 1) * g.vs];
+            u[d] = qv[1 + d];
+        T = 1.0 + qv[DIM + 1];
         rho = p / (f.R * T);
     }
 }
+
+template <int DIM>
+__device__ void node_fill(const Grid &g, const Flow &f, const IB &ib, const double *q, int r, double ub,
+                          double ab, int axis, double *qs);
 
 // value at probe `p` (0 or 1) of record r: weighted sum of (p, u.., T) over
 // the plan's corners (unused corners carry zero weight)
@@ -203,15 +208,20 @@ __device__ inline void plan_probe(const Grid &g, const Flow &f, const IB &ib, co
                                   int p, double *phi)
 {
     constexpr int NC = 1 << DIM;
+    constexpr int NV = DIM + 2;
 #pragma unroll
-    for (int v = 0; v < DIM + 2; ++v)
+    for (int v = 0; v < NV; ++v)
         phi[v] = 0.0;
 #pragma unroll
     for (int m = 0; m < NC; ++m) {
         int off = ib.plan_off[(8 * p + m) * ib.cap + r];
         double w = ib.plan_w[(8 * p + m) * ib.cap + r];
+        double qv[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            qv[v] = q[off + v * g.vs];
         double rho, u[DIM], pr, T;
-        load_prim_t<DIM>(g, f, q, off, rho, u, pr, T);
+        prim_of_state<DIM>(f, qv, rho, u, pr, T);
         if (w != 0.0) {
             phi[0] += w * pr;
 #pragma unroll
@@ -222,14 +232,15 @@ __device__ inline void plan_probe(const Grid &g, const Flow &f, const IB &ib, co
     }
 }
 
+// State value qs of IB record r (its plan and the node's boundary
+// conditions) from the cells of q.
 template <int DIM>
-__device__ inline void fill_one(const Grid &g, const Flow &f, const IB &ib, double *q, int r,
-                                double ub, double ab, int axis)
+__device__ void node_fill(const Grid &g, const Flow &f, const IB &ib, const double *q, int r, double ub,
+                          double ab, int axis, double *qs)
 {
     constexpr int NV = DIM + 2;
     int cap = ib.cap;
     bool quad = f.family == IBM_IB_QUADRATIC;
-    int node = ib.plan_node[r];
     int mode = ib.plan_mode[r];
     int mode1 = mode & 15, mode2 = mode >> 4;
     double n[DIM], ubv[DIM], abv[DIM];
@@ -285,18 +296,31 @@ __device__ inline void fill_one(const Grid &g, const Flow &f, const IB &ib, doub
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
             ke += ru[d] * ru[d];
-        q[node] = rrho;
+        qs[0] = rrho;
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
-            q[node + (1 + d) * g.vs] = rrho * ru[d];
-        q[node + (DIM + 1) * g.vs] = rp / (f.gamma - 1.0) + 0.5 * rrho * ke;
+            qs[1 + d] = rrho * ru[d];
+        qs[DIM + 1] = rp / (f.gamma - 1.0) + 0.5 * rrho * ke;
     } else {
-        q[node] = rp - f.pinf;
+        qs[0] = rp - f.pinf;
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
-            q[node + (1 + d) * g.vs] = ru[d];
-        q[node + (DIM + 1) * g.vs] = rT - 1.0;
+            qs[1 + d] = ru[d];
+        qs[DIM + 1] = rT - 1.0;
     }
+}
+
+// fill record r of q in place from the values stored in q
+template <int DIM>
+__device__ inline void fill_one(const Grid &g, const Flow &f, const IB &ib, double *q, int r, double ub,
+                                double ab, int axis)
+{
+    double qs[DIM + 2];
+    node_fill<DIM>(g, f, ib, q, r, ub, ab, axis, qs);
+    int node = ib.plan_node[r];
+#pragma unroll
+    for (int v = 0; v < DIM + 2; ++v)
+        q[node + v * g.vs] = qs[v];
 }
 
 // FORCING nodes (they read interior FLUID cells only), grid-stride.
@@ -342,10 +366,9 @@ struct StepArgs {
     double *out;         // RK3/dual: next state; residual mode: R (interior)
     double a, b;         // RK3 stage coefficients / dual b0, b2
     int ntx, nty, ntz;
-    const int32_t *tiles;  // tile ids to run (null: every tile)
+    const int32_t *tiles;  // tile ids to run (null: every tile, in order)
     int ntiles;
-    int nfill;           // leading blocks that fill IB nodes (a multiple of 8)
-    int fill;            // PART_FILL_FORCING or PART_FILL_GHOSTS
+    int nfill;           // leading blocks that fill the FORCING nodes of qin
     IB ib;
     double ub, ab;       // body velocity / acceleration along `axis`
     int axis;
@@ -591,8 +614,8 @@ __device__ inline void face_pass(const Real *__restrict__ S, Real *__restrict__ 
     }
 }
 
-template <int DIM, typename Real, int MODE, bool FUSED>
-__global__ __launch_bounds__(kBlock) void step_kernel(StepArgs A)
+template <int DIM, typename Real, int MODE, bool INLINE_GHOSTS>
+__device__ __forceinline__ void step_body(const StepArgs &A)
 {
     using C = TileCfg<DIM>;
     constexpr int TX = C::TX, TY = C::TY, TZ = C::TZ, HZ = C::HZ;
@@ -609,65 +632,64 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs A)
 
     const Grid &g = A.g;
     const Flow &f = A.f;
-    if constexpr (FUSED) {
-        // leading blocks: fill the IB nodes of the stage input (grid-stride);
-        // the tiles of this launch never read those nodes
+    if constexpr (MODE != MODE_RESID) {
+        // leading blocks: fill the FORCING nodes of the stage input
+        // (grid-stride); the tiles of such a launch never read those nodes
         if ((int)blockIdx.x < A.nfill) {
             int nF = min(A.ib.counts[CNT_F], A.ib.cap);
-            int stride = A.nfill * kBlock;
-            int r0 = blockIdx.x * kBlock + threadIdx.x;
-            if (A.fill == PART_FILL_FORCING) {
-                for (int r = r0; r < nF; r += stride)
-                    fill_one<DIM>(g, f, A.ib, A.qin, r, A.ub, A.ab, A.axis);
-            } else {
-                int nG = min(A.ib.counts[CNT_G], A.ib.cap - nF);
-                for (int r = r0; r < nG; r += stride)
-                    fill_one<DIM>(g, f, A.ib, A.qin, nF + r, A.ub, A.ab, A.axis);
-            }
+            for (int r = blockIdx.x * kBlock + threadIdx.x; r < nF; r += A.nfill * kBlock)
+                fill_one<DIM>(g, f, A.ib, A.qin, r, A.ub, A.ab, A.axis);
             return;
         }
     }
     // tile id: the blocks b with the same b mod 8 (dispatched to the same
     // XCD) take a contiguous run of the tile list, so neighbouring tiles
     // share that XCD's L2
-    int nt = A.tiles ? A.ntiles : A.ntx * A.nty * A.ntz;
-    int b = (int)blockIdx.x - (FUSED ? A.nfill : 0);
+    const int32_t *list = A.tiles;
+    int nt = list ? A.ntiles : A.ntx * A.nty * A.ntz;
+    int b = (int)blockIdx.x - (MODE != MODE_RESID ? A.nfill : 0);
     int per = (nt + 7) / 8;
     int pos = (b % 8) * per + b / 8;
     if (pos >= nt)
         return;
-    int tile = A.tiles ? A.tiles[pos] : pos;
+    int tile = list ? list[pos] : pos;
+    if (tile < 0)  // padding of a tile list
+        return;
     int tx0 = tile % A.ntx, ty0 = (tile / A.ntx) % A.nty, tz0 = tile / (A.ntx * A.nty);
     int i0 = tx0 * TX, j0 = ty0 * TY, k0 = tz0 * TZ;
     int tid = threadIdx.x;
     constexpr int NCELL = TX * TY * TZ;  // <= kBlock
     static_assert(NCELL <= kBlock, "one thread per tile cell");
 
-    // own cell of the update, its class and state fetched first so that
-    // their latency overlaps the stencil work
-    int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
-    int i = i0 + tx, j = j0 + ty, k = k0 + tz;
-    bool own = tid < NCELL && i < g.ni && j < g.nj && (DIM == 2 || k < g.nk);
-    long long cell = ((long long)k * g.nj + j) * g.ni + i;
-    long long s_own = sidx(g, i, j, k);
-    uint8_t cls = IBM_SOLID;
-    double qc[NV], qnc[NV];
+
+    // perturbation primitives of state values qv into LDS cell t
+    auto put = [&](int t, const double *qv) {
+        double v[NS];
+        if (f.scheme == IBM_RK3) {
+            double rho = qv[0];
+            double ke = 0.0;
 #pragma unroll
-    for (int m = 0; m < NV; ++m)
-        qc[m] = qnc[m] = 0.0;
-    if (own) {
-        cls = A.cls[cell];
-        if (MODE != MODE_RESID) {
+            for (int d = 0; d < DIM; ++d) {
+                v[1 + d] = qv[1 + d] / rho;
+                ke += v[1 + d] * v[1 + d];
+            }
+            double p = (f.gamma - 1.0) * (qv[DIM + 1] - 0.5 * rho * ke);
+            v[0] = rho - 1.0;
+            v[DIM + 1] = p - f.pinf;
+            v[DIM + 2] = p / (rho * f.R) - 1.0;
+        } else {
+            double pp = qv[0], tp = qv[DIM + 1];
 #pragma unroll
-            for (int m = 0; m < NV; ++m)
-                qc[m] = A.qin[s_own + m * g.vs];
+            for (int d = 0; d < DIM; ++d)
+                v[1 + d] = qv[1 + d];
+            v[0] = (pp - f.R * tp) / (f.R * (1.0 + tp));
+            v[DIM + 1] = pp;
+            v[DIM + 2] = tp;
         }
-        if (MODE == MODE_RK3 && A.a != 0.0) {
 #pragma unroll
-            for (int m = 0; m < NV; ++m)
-                qnc[m] = A.qn[s_own + m * g.vs];
-        }
-    }
+        for (int m = 0; m < NS; ++m)
+            S[m * LCELLS + t] = (Real)v[m];
+    };
 
     // 1. load the tile and its 3-cell halo, recovering (rho', u.., p', T');
     //    domain ghost cells are resolved on the fly.  Two rounds of loads
@@ -700,31 +722,82 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs A)
             int t = tid + (r0 + rr) * kBlock;
             if (r0 + rr >= NR || t >= LCELLS)
                 continue;
-            double v[NS];
-            if (f.scheme == IBM_RK3) {
-                double rho = qv[rr][0];
-                double ke = 0.0;
+            put(t, qv[rr]);
+        }
+    }
+
+    // 1b. inline ghost fill (tiles whose stencils reach the IB region): the
+    //     ghost nodes G1-G3 among the loaded cells take their filled values,
+    //     computed from the stage input, whose FORCING nodes are already
+    //     filled.  Those nodes are first gathered into a block list so that
+    //     each thread fills at most one per pass; a node inside the tile
+    //     also stores the value as its stage output.
+    if constexpr (INLINE_GHOSTS) {
+        __shared__ int gl_n;
+        __shared__ int gl_t[LCELLS];
+        if (tid == 0)
+            gl_n = 0;
+        __syncthreads();
+        const IB &ib = A.ib;
+        for (int t = tid; t < LCELLS; t += kBlock) {
+            int lx = t % LX, ly = (t / LX) % LY, lz = t / (LX * LY);
+            int c[3] = {i0 + lx - 3, j0 + ly - 3, k0 + lz - HZ};
+            if (ghost_source<DIM>(g, c))
+                continue;
+            int li = c[0] - ib.region[0], lj = c[1] - ib.region[2], lk = c[2] - ib.region[4];
+            if (li < 0 || li >= ib.rw || lj < 0 || lj >= ib.rh || lk < 0 || lk >= ib.rd)
+                continue;
+            uint8_t kc = A.cls[((long long)c[2] * g.nj + c[1]) * g.ni + c[0]];
+            if (kc >= IBM_G1 && kc <= IBM_G3)
+                gl_t[atomicAdd(&gl_n, 1)] = t;
+        }
+        __syncthreads();
+        int n = gl_n;
+        for (int e = tid; e < n; e += kBlock) {
+            int t = gl_t[e];
+            int lx = t % LX, ly = (t / LX) % LY, lz = t / (LX * LY);
+            int c[3] = {i0 + lx - 3, j0 + ly - 3, k0 + lz - HZ};
+            bool inside = lx >= 3 && lx < 3 + TX && ly >= 3 && ly < 3 + TY && lz >= HZ && lz < HZ + TZ &&
+                          c[0] < g.ni && c[1] < g.nj && (DIM == 2 || c[2] < g.nk);
+            ghost_source<DIM>(g, c);
+            int li = c[0] - ib.region[0], lj = c[1] - ib.region[2], lk = c[2] - ib.region[4];
+            int rec = ib.rmap[(lk * ib.rh + lj) * ib.rw + li];
+            long long s = sidx(g, c[0], c[1], c[2]);
+            double qs[NV];
+            if (rec < 0) {  // no record (capacity exceeded, flagged): stored value
 #pragma unroll
-                for (int d = 0; d < DIM; ++d) {
-                    v[1 + d] = qv[rr][1 + d] / rho;
-                    ke += v[1 + d] * v[1 + d];
-                }
-                double p = (f.gamma - 1.0) * (qv[rr][DIM + 1] - 0.5 * rho * ke);
-                v[0] = rho - 1.0;
-                v[DIM + 1] = p - f.pinf;
-                v[DIM + 2] = p / (rho * f.R) - 1.0;
+                for (int m = 0; m < NV; ++m)
+                    qs[m] = A.qin[s + m * g.vs];
             } else {
-                double pp = qv[rr][0], tp = qv[rr][DIM + 1];
-#pragma unroll
-                for (int d = 0; d < DIM; ++d)
-                    v[1 + d] = qv[rr][1 + d];
-                v[0] = (pp - f.R * tp) / (f.R * (1.0 + tp));
-                v[DIM + 1] = pp;
-                v[DIM + 2] = tp;
+                node_fill<DIM>(g, f, ib, A.qin, rec, A.ub, A.ab, A.axis, qs);
+                put(t, qs);
             }
+            if (inside) {
 #pragma unroll
-            for (int m = 0; m < NS; ++m)
-                S[m * LCELLS + t] = (Real)v[m];
+                for (int m = 0; m < NV; ++m)
+                    A.out[s + m * g.vs] = qs[m];
+            }
+        }
+    }
+
+    // own cell of the update: its class and state are fetched before the
+    // stencil work so that their latency overlaps it
+    int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
+    int i = i0 + tx, j = j0 + ty, k = k0 + tz;
+    bool own = tid < NCELL && i < g.ni && j < g.nj && (DIM == 2 || k < g.nk);
+    long long cell = ((long long)k * g.nj + j) * g.ni + i;
+    long long s_own = sidx(g, i, j, k);
+    uint8_t cls = IBM_SOLID;
+    double qc[NV];
+#pragma unroll
+    for (int m = 0; m < NV; ++m)
+        qc[m] = 0.0;
+    if (own) {
+        cls = A.cls[cell];
+        if (MODE != MODE_RESID) {
+#pragma unroll
+            for (int m = 0; m < NV; ++m)
+                qc[m] = A.qin[s_own + m * g.vs];
         }
     }
     __syncthreads();
@@ -750,6 +823,8 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs A)
     long long s = s_own;
     if (MODE != MODE_RESID) {
         if (cls != IBM_FLUID) {  // IB nodes carry their filled value, solid cells their state
+            if (INLINE_GHOSTS && cls >= IBM_G1 && cls <= IBM_G3)
+                return;  // written by the inline ghost fill
 #pragma unroll
             for (int m = 0; m < NV; ++m)
                 A.out[s + m * g.vs] = qc[m];
@@ -791,7 +866,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs A)
         for (int m = 0; m < NV; ++m) {
             double qv = A.b * (qc[m] - f.dt * R[m]);
             if (A.a != 0.0)
-                qv += A.a * qnc[m];
+                qv += A.a * A.qn[s + m * g.vs];
             A.out[s + m * g.vs] = qv;
             bad |= !isfinite(qv);
             if (m == 0)
@@ -912,6 +987,18 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs A)
     }
 }
 
+template <int DIM, typename Real, int MODE>
+__global__ __launch_bounds__(kBlock) void step_kernel(StepArgs A)
+{
+    step_body<DIM, Real, MODE, false>(A);
+}
+
+template <int DIM, typename Real, int MODE>
+__global__ __launch_bounds__(kBlock) void step_ghost_kernel(StepArgs A)
+{
+    step_body<DIM, Real, MODE, true>(A);
+}
+
 // Q'^{n-1} <- Q'^n (after the first step); Q'^n <- Q(W) - Q_inf
 __global__ void dual_begin_kernel(Grid g, Flow f, const double *w, double *qn, double *qnm1,
                                   int first)
@@ -1022,26 +1109,30 @@ hipError_t run_step(const Grid &g, const Flow &f, const IB &ib, double *qin, con
     A.ntz = DIM == 3 ? (g.nk + C::TZ - 1) / C::TZ : 1;
     A.tiles = part ? part->tiles : nullptr;
     A.ntiles = part ? part->ntiles : 0;
-    A.fill = part ? part->fill : PART_NO_FILL;
     A.nfill = 0;
     A.ib = ib;
     A.ub = part ? part->ub : 0.0;
     A.ab = part ? part->ab : 0.0;
     A.axis = part ? part->axis : -1;
     A.fs = freestream_of(g, f);
-    if (A.fill != PART_NO_FILL && ib.cap > 0) {
-        int nb = blocks_for(ib.cap, kBlock);
-        nb = nb < 64 ? nb : 64;
-        A.nfill = (nb + 7) / 8 * 8;
-    }
     int nt = A.tiles ? A.ntiles : A.ntx * A.nty * A.ntz;
-    int grid = A.nfill + 8 * ((nt + 7) / 8);
-    if (grid == 0)
+    if constexpr (MODE != MODE_RESID) {
+        if (part && part->fill_forcing && ib.cap > 0) {
+            int nb = blocks_for(ib.cap, kBlock);
+            nb = nb < 64 ? nb : 64;
+            A.nfill = (nb + 7) / 8 * 8;
+        }
+    }
+    int nblk = A.nfill + 8 * ((nt + 7) / 8);
+    if (nblk == 0)
         return hipSuccess;
-    if (A.nfill > 0)
-        hipLaunchKernelGGL((step_kernel<DIM, Real, MODE, true>), dim3(grid), dim3(kBlock), 0, s, A);
-    else
-        hipLaunchKernelGGL((step_kernel<DIM, Real, MODE, false>), dim3(grid), dim3(kBlock), 0, s, A);
+    if constexpr (MODE != MODE_RESID) {
+        if (part && part->inline_ghosts && ib.cap > 0) {
+            hipLaunchKernelGGL((step_ghost_kernel<DIM, Real, MODE>), dim3(nblk), dim3(kBlock), 0, s, A);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((step_kernel<DIM, Real, MODE>), dim3(nblk), dim3(kBlock), 0, s, A);
     return hipGetLastError();
 }
 
@@ -1137,6 +1228,24 @@ hipError_t launch_state_to_prim(const Grid &g, const Flow &f, const double *q, d
     hipLaunchKernelGGL(state_to_prim_kernel, dim3(blocks_for(g.ncell, kBlock)), dim3(kBlock), 0, s,
                        g, f, q, prim);
     return hipGetLastError();
+}
+
+int stage_blocks_per_cu(const Grid &g, const Flow &f)
+{
+    int n = 0;
+    bool mixed = f.precision == IBM_MIXED, rk = f.scheme == IBM_RK3;
+    hipError_t e;
+    if (g.ndim == 2)
+        e = mixed ? (rk ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<2, float, MODE_RK3>, kBlock, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<2, float, MODE_DUAL>, kBlock, 0))
+                  : (rk ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<2, double, MODE_RK3>, kBlock, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<2, double, MODE_DUAL>, kBlock, 0));
+    else
+        e = mixed ? (rk ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<3, float, MODE_RK3>, kBlock, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<3, float, MODE_DUAL>, kBlock, 0))
+                  : (rk ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<3, double, MODE_RK3>, kBlock, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<3, double, MODE_DUAL>, kBlock, 0));
+    return e == hipSuccess ? n : 0;
 }
 
 hipError_t launch_copy_state(const Grid &g, const double *src, double *dst, hipStream_t s)

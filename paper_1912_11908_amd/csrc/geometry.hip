@@ -377,15 +377,20 @@ __global__ __launch_bounds__(kBlock) void write_lists_kernel(Grid g, IB ib)
         offF += sF[m];
         offG += sG[m];
     }
+    // record index per IB node: forcing records first, then the ghosts
+    // (-1 beyond the capacity, which the scan has flagged)
+    int nF = min(ib.counts[CNT_F], ib.cap);
     if (f) {
         int pos = offF + __popcll(bf & lower);
         if (pos < ib.cap)
             ib.listF[pos] = cell;
+        ib.rmap[t] = pos < ib.cap ? pos : -1;
     }
     if (gh) {
         int pos = offG + __popcll(bg & lower);
         if (pos < ib.cap)
             ib.listG[pos] = cell;
+        ib.rmap[t] = nF + pos < ib.cap ? nF + pos : -1;
     }
 }
 
