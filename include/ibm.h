@@ -149,6 +149,17 @@ int ibm_residual(ibm_ctx *ctx, const double *d_q, double *d_r, void *stream);
  * written (call ibm_fill for a filled halo). */
 int ibm_advance(ibm_ctx *ctx, double *d_q, int nsteps, void *stream);
 
+/* Serving (several independent solves, e.g. under continuous batching):
+ * advance each ctx[m] by nsteps steps on its state d_q[m], as ibm_advance
+ * would, with bit-identical results.  Stationary-body solves that share
+ * ndim, precision and scheme advance together: every stage of one step of
+ * all of them is one launch over all their tiles, so many small solves fill
+ * the GPU as one large one does.  Moving-body solves advance one after
+ * another.  Contexts must be distinct and on the current device;
+ * n <= IBM_BATCH_MAX.  The first call with a new d_q[m] copies that solve's
+ * launch arguments into its workspace (asynchronously, on stream). */
+int ibm_batch_advance(ibm_ctx *const *ctx, double *const *d_q, int n, int nsteps, void *stream);
+
 /* Primitive (rho, u, v[, w], p) interior array -> state (halo untouched),
  * and back. */
 int ibm_init_state(ibm_ctx *ctx, const double *d_prim, double *d_q, void *stream);
@@ -168,6 +179,7 @@ int ibm_info_get(const ibm_ctx *ctx, ibm_info *out);
  * stream) instead of enqueuing its kernels one by one; 0 enqueues eagerly.
  * Both give bit-identical results. */
 #define IBM_OPT_GRAPHS 1
+#define IBM_BATCH_MAX 64
 int ibm_set_option(ibm_ctx *ctx, int option, int value);
 const char *ibm_last_error(const ibm_ctx *ctx);
 

@@ -14,7 +14,9 @@ from . import _lib
 from ._lib import IbmError, FLUID, FORCING, G1, G2, G3, SOLID, REC_INT, REC_DBL
 
 __all__ = ["Solver", "IbmError", "FLUID", "FORCING", "G1", "G2", "G3", "SOLID",
-           "case_struct", "workspace_bytes"]
+           "case_struct", "workspace_bytes", "batch_advance", "BATCH_MAX"]
+
+BATCH_MAX = _lib.BATCH_MAX
 
 
 def _torch():
@@ -222,3 +224,25 @@ class Solver:
         ir = self._view(inf.rec_int, n * REC_INT, np.int32).reshape(n, REC_INT)
         dr = self._view(inf.rec_dbl, n * REC_DBL, np.float64).reshape(n, REC_DBL)
         return ir, dr
+
+
+def batch_advance(solvers, nsteps, stream=None):
+    """Advance several solvers by nsteps steps each through ibm_batch_advance
+    (stationary-body solves of one kind share each stage's launch).  The
+    solvers must be distinct and on one device; at most BATCH_MAX."""
+    solvers = list(solvers)
+    if not solvers:
+        return
+    if len(solvers) > BATCH_MAX:
+        raise ValueError(f"at most {BATCH_MAX} solvers per batch")
+    torch = _torch()
+    L = solvers[0].L
+    n = len(solvers)
+    ctxs = (ctypes.c_void_p * n)(*[s.h.value for s in solvers])
+    qs = (ctypes.c_void_p * n)(*[s.state.data_ptr() for s in solvers])
+    st = stream if stream is not None else torch.cuda.current_stream(solvers[0].device)
+    rc = L.ibm_batch_advance(ctypes.cast(ctxs, ctypes.c_void_p), ctypes.cast(qs, ctypes.c_void_p), n,
+                             int(nsteps), ctypes.c_void_p(st.cuda_stream))
+    if rc != 0:
+        msgs = "; ".join(L.ibm_last_error(s.h).decode(errors="replace") for s in solvers)
+        raise IbmError(rc, "ibm_batch_advance", msgs)

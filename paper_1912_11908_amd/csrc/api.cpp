@@ -15,6 +15,8 @@
 
 using namespace ibm;
 
+constexpr int kSlots = 9;  // 8 stage launches of a step + 1 for kernel timing
+
 struct ibm_ctx {
     int device;
     Grid g;
@@ -39,6 +41,13 @@ struct ibm_ctx {
     hipGraph_t graph[2];
     hipGraphExec_t graph_exec[2];
     const double *graph_q[2];
+    // batched serving: device argument blocks of every stage launch of a
+    // step (RK3: 3 stages x 2 launches; dual time: first / later step x
+    // iteration parity x 2 launches), prepared for the state batch_q
+    void *d_args;
+    int slot_nblk[kSlots];
+    const double *batch_q;
+    std::vector<char> h_args;
     long long rest_box_lat[6];
     char err[256];
 };
@@ -417,6 +426,7 @@ struct Layout {
     double *plan_w, *plan_geo;
     int32_t *rmap;
     int32_t *tiles;
+    char *args;
     double *q1, *q2, *wtmp, *qn, *qnm1;
 };
 
@@ -464,6 +474,7 @@ size_t carve(const ibm_case *c, const HostGeom &h, char *base, Layout &L)
     L.plan_mode = cv.take<int32_t>(cap);
     L.rmap = cv.take<int32_t>(cap);
     L.tiles = cv.take<int32_t>(h.tiles_far.size() + h.tiles_near.size() + 16);
+    L.args = cv.take<char>(kSlots * stage_args_bytes());
     size_t st = (size_t)h.vs * (nd + 2);
     L.q1 = L.q2 = L.wtmp = L.qn = L.qnm1 = nullptr;
     if (c->scheme == IBM_RK3) {
@@ -722,7 +733,7 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     if (e == hipSuccess) e = up(L.tiles + list1.size(), list2);
     if (e == hipSuccess) e = hipMemset(L.cls, IBM_FLUID, (size_t)h.ncell);
     if (e == hipSuccess) e = hipMemset(L.counts, 0, sizeof(int32_t) * CNT_WORDS);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     x->mo.on = c->motion != 0;
     x->mo.axis = c->motion ? (int)c->motion_par[0] : 0;
     x->mo.amp = c->motion_par[1];
@@ -744,6 +755,10 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
         x->graph_exec[k] = nullptr;
         x->graph_q[k] = nullptr;
     }
+    x->d_args = L.args;
+    x->batch_q = nullptr;
+    for (int k = 0; k < kSlots; ++k)
+        x->slot_nblk[k] = 0;
     x->tiles1 = L.tiles;
     x->ntiles1 = (int)list1.size();
     x->tiles2 = L.tiles + list1.size();
@@ -905,6 +920,106 @@ int enqueue_dual_step(ibm_ctx *c, double *q, double tn, int first, hipStream_t s
     return IBM_OK;
 }
 
+// Write the device argument blocks of every stage launch of a step of a
+// stationary-body solve on state q (see ibm_ctx::d_args).
+int prepare_batch(ibm_ctx *c, double *q, hipStream_t s)
+{
+    size_t nb = stage_args_bytes();
+    c->h_args.assign(kSlots * nb, 0);
+    bool body = c->b.nfacet > 0 && c->ib.cap > 0;
+    StagePart p1{c->tiles1, c->ntiles1, true, false, 0.0, 0.0, -1};
+    StagePart p2{c->tiles2, c->ntiles2, false, true, 0.0, 0.0, -1};
+    auto put = [&](int slot, int launch, double *qin, const double *qn, const double *qnm1, double *out,
+                   double a, double b) {
+        const StagePart *part = body ? (launch == 0 ? &p1 : &p2) : nullptr;
+        if (!body && launch == 1) {
+            c->slot_nblk[slot] = 0;
+            return;
+        }
+        c->slot_nblk[slot] = stage_args(c->g, c->f, c->ib, qin, qn, qnm1, out, a, b, part, &c->h_args[slot * nb]);
+    };
+    for (int k = 0; k < kSlots; ++k)
+        c->slot_nblk[k] = 0;
+    if (c->f.scheme == IBM_RK3) {
+        static const double A[3] = {0.0, 0.75, 1.0 / 3.0}, B[3] = {1.0, 0.25, 2.0 / 3.0};
+        double *in[3] = {q, c->q1, c->q2}, *out[3] = {c->q1, c->q2, q};
+        for (int st = 0; st < 3; ++st)
+            for (int l = 0; l < 2; ++l)
+                put(2 * st + l, l, in[st], q, nullptr, out[st], A[st], B[st]);
+    } else {
+        for (int first = 0; first < 2; ++first)
+            for (int par = 0; par < 2; ++par)
+                for (int l = 0; l < 2; ++l) {
+                    double *in = par == 0 ? q : c->wtmp, *out = par == 0 ? c->wtmp : q;
+                    put(4 * first + 2 * par + l, l, in, c->qn, c->qnm1, out, first ? 1.0 : 1.5, first ? 0.0 : 0.5);
+                }
+    }
+    hipError_t e = hipMemcpyAsync(c->d_args, c->h_args.data(), c->h_args.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess)
+        return dev_err(c, e, "batch arguments");
+    c->batch_q = q;
+    return IBM_OK;
+}
+
+// One step of a group of stationary-body solves that share ndim, precision
+// and scheme (their launch arguments prepared by prepare_batch): each stage
+// launch of all of them is one batched launch.  Every stationary advance
+// path (eager, graph replay, batched serving) goes through here, so they
+// run the same kernels on the same arguments.  Time and step counters are
+// left to the caller.
+int enqueue_group_step(ibm_ctx *const *ctx, double *const *q, const std::vector<int> &gp, hipStream_t s)
+{
+    const ibm_ctx *c0 = ctx[gp[0]];
+    int nd = c0->g.ndim, prec = c0->f.precision, scheme = c0->f.scheme;
+    size_t nb = stage_args_bytes();
+    std::vector<const void *> args;
+    std::vector<int> nblk;
+    auto run = [&](auto slot_of) -> int {
+        for (int l = 0; l < 2; ++l) {
+            args.clear();
+            nblk.clear();
+            for (int m : gp) {
+                int slot = slot_of(ctx[m]);
+                if (slot < 0)
+                    continue;
+                args.push_back(static_cast<char *>(ctx[m]->d_args) + (slot + l) * nb);
+                nblk.push_back(ctx[m]->slot_nblk[slot + l]);
+            }
+            hipError_t e = launch_stage_batch(nd, prec, scheme, l == 1, (int)args.size(), args.data(), nblk.data(), s);
+            if (e != hipSuccess)
+                return dev_err(ctx[gp[0]], e, "batched stage");
+        }
+        return IBM_OK;
+    };
+    int rc;
+    if (scheme == IBM_RK3) {
+        for (int st = 0; st < 3; ++st)
+            if ((rc = run([&](const ibm_ctx *) { return 2 * st; })))
+                return rc;
+        return IBM_OK;
+    }
+    int most = 0;
+    for (int m : gp) {
+        ibm_ctx *c = ctx[m];
+        most = std::max(most, c->n_inner);
+        hipError_t e = launch_dual_begin(c->g, c->f, q[m], c->qn, c->qnm1, c->step == 0, s);
+        if (e != hipSuccess)
+            return dev_err(c, e, "dual begin");
+    }
+    for (int it = 0; it < most; ++it)
+        if ((rc = run([&](const ibm_ctx *c) { return it < c->n_inner ? 4 * (c->step == 0) + 2 * (it % 2) : -1; })))
+            return rc;
+    for (int m : gp) {
+        ibm_ctx *c = ctx[m];
+        if (c->n_inner % 2 == 1) {
+            hipError_t e = launch_copy_state(c->g, c->wtmp, q[m], s);
+            if (e != hipSuccess)
+                return dev_err(c, e, "copy");
+        }
+    }
+    return IBM_OK;
+}
+
 // Steps per chunk graph: RK3 steps are 9 launches, dual-time steps 3 n_inner + 1.
 int chunk_steps(const ibm_ctx *c) { return c->f.scheme == IBM_RK3 ? 8 : 2; }
 
@@ -929,9 +1044,11 @@ bool build_graph(ibm_ctx *c, double *q, int slot)
     if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return false;
     int rc = IBM_OK;
+    ibm_ctx *one[1] = {c};
+    double *qs[1] = {q};
+    const std::vector<int> gp{0};
     for (int n = 0; n < nsteps && rc == IBM_OK; ++n)
-        rc = c->f.scheme == IBM_RK3 ? enqueue_rk3_step(c, q, 0.0, c->cap_stream)
-                                    : enqueue_dual_step(c, q, 0.0, 0, c->cap_stream);
+        rc = enqueue_group_step(one, qs, gp, c->cap_stream);
     hipGraph_t gr = nullptr;
     hipError_t e = hipStreamEndCapture(c->cap_stream, &gr);
     if (rc != IBM_OK || e != hipSuccess || !gr) {
@@ -972,6 +1089,9 @@ int ibm_advance(ibm_ctx *c, double *q, int nsteps, void *stream)
                 return rc;
         int first = !rk && c->step == 0;
         int k = 1;
+        // stationary bodies: the shared batched path on prepared arguments
+        if (!c->mo.on && c->batch_q != q && (rc = prepare_batch(c, q, s)))
+            return rc;
         bool graphable = c->use_graphs && !c->mo.on && !first;
         if (graphable) {
             int slot = nsteps - n >= chunk_steps(c) ? 1 : 0;
@@ -984,7 +1104,11 @@ int ibm_advance(ibm_ctx *c, double *q, int nsteps, void *stream)
             }
         }
         if (!graphable) {
-            if (rk)
+            ibm_ctx *one[1] = {c};
+            double *qs[1] = {q};
+            if (!c->mo.on)
+                rc = enqueue_group_step(one, qs, std::vector<int>{0}, s);
+            else if (rk)
                 rc = enqueue_rk3_step(c, q, c->t, s);
             else
                 rc = enqueue_dual_step(c, q, c->t + dt, first, s);
@@ -995,6 +1119,67 @@ int ibm_advance(ibm_ctx *c, double *q, int nsteps, void *stream)
         c->step += k;
         n += k;
     }
+    return IBM_OK;
+}
+
+int ibm_batch_advance(ibm_ctx *const *ctx, double *const *q, int n, int nsteps, void *stream)
+{
+    if (!ctx || !q || n < 0 || n > IBM_BATCH_MAX || nsteps < 0)
+        return IBM_EINVAL;
+    hipStream_t s = S(stream);
+    int dev = -1;
+    for (int m = 0; m < n; ++m) {
+        if (!ctx[m] || !q[m])
+            return IBM_EINVAL;
+        if (m == 0)
+            dev = ctx[m]->device;
+        else if (ctx[m]->device != dev)
+            return set_err(ctx[m], IBM_EINVAL, "batched contexts must share one device");
+        for (int k = 0; k < m; ++k)
+            if (ctx[k] == ctx[m])
+                return set_err(ctx[m], IBM_EINVAL, "a context appears twice in a batch");
+    }
+    // moving bodies are reclassified every step: they advance on their own
+    std::vector<int> batched;
+    for (int m = 0; m < n; ++m) {
+        ibm_ctx *c = ctx[m];
+        int rc;
+        if (c->mo.on) {
+            if ((rc = ibm_advance(c, q[m], nsteps, stream)))
+                return rc;
+            continue;
+        }
+        if (!c->classified && (rc = do_classify(c, c->t, s)))
+            return rc;
+        if (c->batch_q != q[m] && (rc = prepare_batch(c, q[m], s)))
+            return rc;
+        batched.push_back(m);
+    }
+    // groups sharing a kernel: (ndim, precision, scheme)
+    std::vector<std::vector<int>> groups;
+    for (int m : batched) {
+        bool placed = false;
+        for (auto &gp : groups) {
+            const ibm_ctx *a = ctx[gp[0]], *b = ctx[m];
+            if (a->g.ndim == b->g.ndim && a->f.precision == b->f.precision && a->f.scheme == b->f.scheme) {
+                gp.push_back(m);
+                placed = true;
+                break;
+            }
+        }
+        if (!placed)
+            groups.push_back({m});
+    }
+    for (int step = 0; step < nsteps; ++step)
+        for (auto &gp : groups) {
+            int rc = enqueue_group_step(ctx, q, gp, s);
+            if (rc)
+                return rc;
+            for (int m : gp) {
+                ctx[m]->t += ctx[m]->f.dt;
+                ctx[m]->step++;
+            }
+        }
     return IBM_OK;
 }
 
@@ -1085,15 +1270,22 @@ int ibm_time_update_kernel(ibm_ctx *c, const double *q, int stage, int nrep, voi
         e = hipEventCreate(&e1);
     if (e != hipSuccess)
         return dev_err(c, e, "event create");
-    if (!rk)
+    // the kernel of the stage launches (batched form), over every tile with
+    // no fill part: d_q is only read
+    size_t nb = stage_args_bytes();
+    std::vector<char> h(nb);
+    double *qm = const_cast<double *>(q);
+    int nblk = rk ? stage_args(c->g, c->f, c->ib, qm, q, nullptr, c->q1, A[stage], B[stage], nullptr, h.data())
+                  : stage_args(c->g, c->f, c->ib, qm, c->qn, c->qnm1, c->wtmp, 1.0, 0.0, nullptr, h.data());
+    const void *d = static_cast<char *>(c->d_args) + (kSlots - 1) * nb;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(const_cast<void *>(d), h.data(), nb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !rk)
         e = launch_dual_begin(c->g, c->f, q, c->qn, c->qnm1, 1, s);
     if (e == hipSuccess)
         e = hipEventRecord(e0, s);
     for (int r = 0; r < nrep && e == hipSuccess; ++r)
-        // every tile, no fill part: d_q is only read
-        e = rk ? launch_rk_stage(c->g, c->f, c->ib, q, const_cast<double *>(q), c->q1, A[stage], B[stage], s)
-               : launch_dual_iter(c->g, c->f, c->ib, const_cast<double *>(q), c->wtmp, c->qn, c->qnm1, 1.0,
-                                  0.0, s);
+        e = launch_stage_batch(c->g.ndim, c->f.precision, c->f.scheme, false, 1, &d, &nblk, s);
     if (e == hipSuccess)
         e = hipEventRecord(e1, s);
     if (e == hipSuccess)

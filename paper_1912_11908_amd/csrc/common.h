@@ -130,4 +130,17 @@ hipError_t launch_copy_state(const Grid &g, const double *src, double *dst, hipS
 // resident blocks per CU of the stage kernel for this grid and flow (0 if unknown)
 int stage_blocks_per_cu(const Grid &g, const Flow &f);
 
+// Batched stages (several solves per launch): the arguments of one stage
+// launch of a solve are written as stage_args_bytes() opaque bytes to host
+// memory `dst` (to be copied to device memory); the return value is the
+// launch's block count.  launch_stage_batch runs n prepared launches (device
+// argument blocks d_args[m], block counts nblk[m]) of solves that share
+// ndim, precision and scheme as one launch; ghosts selects the second
+// launch of a stage.
+size_t stage_args_bytes();
+int stage_args(const Grid &g, const Flow &f, const IB &ib, double *qin, const double *qn,
+               const double *qnm1, double *out, double a, double b, const StagePart *part, void *dst);
+hipError_t launch_stage_batch(int ndim, int precision, int scheme, bool ghosts, int n, const void *const *d_args,
+                              const int *nblk, hipStream_t s);
+
 }  // namespace ibm

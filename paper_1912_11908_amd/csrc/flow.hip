@@ -10,6 +10,8 @@
 // R_E = H_inf R_rho + R_E' (H_inf the free-stream total enthalpy), so no
 // O(p_inf) quantity is ever rounded to Real.  Conserved updates and the
 // recovery of (rho', p', T') from the state are FP64.
+#include <cstring>
+
 #include "common.h"
 
 namespace ibm {
@@ -615,7 +617,7 @@ __device__ inline void face_pass(const Real *__restrict__ S, Real *__restrict__ 
 }
 
 template <int DIM, typename Real, int MODE, bool INLINE_GHOSTS>
-__device__ __forceinline__ void step_body(const StepArgs &A)
+__device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bid)
 {
     using C = TileCfg<DIM>;
     constexpr int TX = C::TX, TY = C::TY, TZ = C::TZ, HZ = C::HZ;
@@ -635,9 +637,9 @@ __device__ __forceinline__ void step_body(const StepArgs &A)
     if constexpr (MODE != MODE_RESID) {
         // leading blocks: fill the FORCING nodes of the stage input
         // (grid-stride); the tiles of such a launch never read those nodes
-        if ((int)blockIdx.x < A.nfill) {
+        if (bid < A.nfill) {
             int nF = min(A.ib.counts[CNT_F], A.ib.cap);
-            for (int r = blockIdx.x * kBlock + threadIdx.x; r < nF; r += A.nfill * kBlock)
+            for (int r = bid * kBlock + threadIdx.x; r < nF; r += A.nfill * kBlock)
                 fill_one<DIM>(g, f, A.ib, A.qin, r, A.ub, A.ab, A.axis);
             return;
         }
@@ -647,7 +649,7 @@ __device__ __forceinline__ void step_body(const StepArgs &A)
     // share that XCD's L2
     const int32_t *list = A.tiles;
     int nt = list ? A.ntiles : A.ntx * A.nty * A.ntz;
-    int b = (int)blockIdx.x - (MODE != MODE_RESID ? A.nfill : 0);
+    int b = bid - (MODE != MODE_RESID ? A.nfill : 0);
     int per = (nt + 7) / 8;
     int pos = (b % 8) * per + b / 8;
     if (pos >= nt)
@@ -990,16 +992,50 @@ __device__ __forceinline__ void step_body(const StepArgs &A)
 template <int DIM, typename Real, int MODE>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs A)
 {
-    step_body<DIM, Real, MODE, false>(A);
+    step_body<DIM, Real, MODE, false>(A, blockIdx.x);
 }
 
 template <int DIM, typename Real, int MODE>
 __global__ __launch_bounds__(kBlock) void step_ghost_kernel(StepArgs A)
 {
-    step_body<DIM, Real, MODE, true>(A);
+    step_body<DIM, Real, MODE, true>(A, blockIdx.x);
 }
 
-// Q'^{n-1} <- Q'^n (after the first step); Q'^n <- Q(W) - Q_inf
+// Several solves in one launch: the blocks [off[m], off[m + 1]) run the
+// launch described by args[m] (prepared in device memory).
+struct BatchArgs {
+    int n;
+    int off[IBM_BATCH_MAX + 1];
+    const StepArgs *args[IBM_BATCH_MAX];
+};
+
+template <int DIM, typename Real, int MODE, bool GHOSTS>
+__global__ __launch_bounds__(kBlock) void step_batch_kernel(BatchArgs B)
+{
+    int b = blockIdx.x;
+    int lo = 0, hi = B.n - 1;  // the m with off[m] <= b < off[m + 1]
+    while (lo < hi) {
+        int mid = (lo + hi + 1) / 2;
+        if (B.off[mid] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    // the solve, its argument block and its first block are the same for
+    // every lane: keep them in scalar registers, so the argument loads are
+    // scalar too (the arguments are read-only for the whole launch)
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    unsigned long long pa = reinterpret_cast<unsigned long long>(B.args[lo]);
+    unsigned plo = __builtin_amdgcn_readfirstlane((unsigned)pa);
+    unsigned phi = __builtin_amdgcn_readfirstlane((unsigned)(pa >> 32));
+    // constant address space: the block is never written during a launch
+    using ConstArgs = __attribute__((address_space(4))) const StepArgs;
+    const ConstArgs *ap = (const ConstArgs *)(((unsigned long long)phi << 32) | plo);
+    int first = __builtin_amdgcn_readfirstlane(B.off[lo]);
+    step_body<DIM, Real, MODE, GHOSTS>(*(const StepArgs *)ap, b - first);
+}
+
+// Q'^{n-1} <- Q'^n (at the first step Q'^{n-1} <- Q(W) - Q_inf too); Q'^n <- Q(W) - Q_inf
 __global__ void dual_begin_kernel(Grid g, Flow f, const double *w, double *qn, double *qnm1,
                                   int first)
 {
@@ -1022,9 +1058,10 @@ __global__ void dual_begin_kernel(Grid g, Flow f, const double *w, double *qn, d
     for (int d = 0; d < nd; ++d)
         Q[1 + d] = rhop * u[d] + (u[d] - (d == 0 ? 1.0 : 0.0));
     Q[N - 1] = pp / (f.gamma - 1.0) + 0.5 * (rhop * q2 + q2 - 1.0);
+    // the first step (BDF1) weights Q'^{n-1} by zero; it is set to Q'^n so
+    // that the term is an exact zero whatever the workspace held
     for (int m = 0; m < N; ++m) {
-        if (!first)
-            qnm1[m * g.ncell + c] = qn[m * g.ncell + c];
+        qnm1[m * g.ncell + c] = first ? Q[m] : qn[m * g.ncell + c];
         qn[m * g.ncell + c] = Q[m];
     }
 }
@@ -1087,12 +1124,13 @@ FreeStream freestream_of(const Grid &g, const Flow &f)
     return fs;
 }
 
-template <int DIM, typename Real, int MODE>
-hipError_t run_step(const Grid &g, const Flow &f, const IB &ib, double *qin, const double *qn,
-                    const double *qnm1, double *out, double a, double b, hipStream_t s,
-                    const StagePart *part)
+// Arguments of one stage launch, and its block count.
+template <int DIM>
+StepArgs make_args(const Grid &g, const Flow &f, const IB &ib, double *qin, const double *qn,
+                   const double *qnm1, double *out, double a, double b, bool resid, const StagePart *part,
+                   int *nblk)
 {
-    using C = TileCfg<DIM>;
+    const int *T = DIM == 2 ? kTile2 : kTile3;
     StepArgs A;
     A.g = g;
     A.f = f;
@@ -1104,9 +1142,9 @@ hipError_t run_step(const Grid &g, const Flow &f, const IB &ib, double *qin, con
     A.out = out;
     A.a = a;
     A.b = b;
-    A.ntx = (g.ni + C::TX - 1) / C::TX;
-    A.nty = (g.nj + C::TY - 1) / C::TY;
-    A.ntz = DIM == 3 ? (g.nk + C::TZ - 1) / C::TZ : 1;
+    A.ntx = (g.ni + T[0] - 1) / T[0];
+    A.nty = (g.nj + T[1] - 1) / T[1];
+    A.ntz = DIM == 3 ? (g.nk + T[2] - 1) / T[2] : 1;
     A.tiles = part ? part->tiles : nullptr;
     A.ntiles = part ? part->ntiles : 0;
     A.nfill = 0;
@@ -1116,14 +1154,22 @@ hipError_t run_step(const Grid &g, const Flow &f, const IB &ib, double *qin, con
     A.axis = part ? part->axis : -1;
     A.fs = freestream_of(g, f);
     int nt = A.tiles ? A.ntiles : A.ntx * A.nty * A.ntz;
-    if constexpr (MODE != MODE_RESID) {
-        if (part && part->fill_forcing && ib.cap > 0) {
-            int nb = blocks_for(ib.cap, kBlock);
-            nb = nb < 64 ? nb : 64;
-            A.nfill = (nb + 7) / 8 * 8;
-        }
+    if (!resid && part && part->fill_forcing && ib.cap > 0) {
+        int nb = blocks_for(ib.cap, kBlock);
+        nb = nb < 64 ? nb : 64;
+        A.nfill = (nb + 7) / 8 * 8;
     }
-    int nblk = A.nfill + 8 * ((nt + 7) / 8);
+    *nblk = A.nfill + 8 * ((nt + 7) / 8);
+    return A;
+}
+
+template <int DIM, typename Real, int MODE>
+hipError_t run_step(const Grid &g, const Flow &f, const IB &ib, double *qin, const double *qn,
+                    const double *qnm1, double *out, double a, double b, hipStream_t s,
+                    const StagePart *part)
+{
+    int nblk = 0;
+    StepArgs A = make_args<DIM>(g, f, ib, qin, qn, qnm1, out, a, b, MODE == MODE_RESID, part, &nblk);
     if (nblk == 0)
         return hipSuccess;
     if constexpr (MODE != MODE_RESID) {
@@ -1228,6 +1274,55 @@ hipError_t launch_state_to_prim(const Grid &g, const Flow &f, const double *q, d
     hipLaunchKernelGGL(state_to_prim_kernel, dim3(blocks_for(g.ncell, kBlock)), dim3(kBlock), 0, s,
                        g, f, q, prim);
     return hipGetLastError();
+}
+
+size_t stage_args_bytes() { return sizeof(StepArgs); }
+
+int stage_args(const Grid &g, const Flow &f, const IB &ib, double *qin, const double *qn,
+               const double *qnm1, double *out, double a, double b, const StagePart *part, void *dst)
+{
+    int nblk = 0;
+    StepArgs A = g.ndim == 2 ? make_args<2>(g, f, ib, qin, qn, qnm1, out, a, b, false, part, &nblk)
+                             : make_args<3>(g, f, ib, qin, qn, qnm1, out, a, b, false, part, &nblk);
+    std::memcpy(dst, &A, sizeof A);
+    return nblk;
+}
+
+template <int DIM, typename Real, int MODE>
+hipError_t batch_launch(const BatchArgs &B, bool ghosts, hipStream_t s)
+{
+    int nblk = B.off[B.n];
+    if (ghosts)
+        hipLaunchKernelGGL((step_batch_kernel<DIM, Real, MODE, true>), dim3(nblk), dim3(kBlock), 0, s, B);
+    else
+        hipLaunchKernelGGL((step_batch_kernel<DIM, Real, MODE, false>), dim3(nblk), dim3(kBlock), 0, s, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_batch(int ndim, int precision, int scheme, bool ghosts, int n, const void *const *d_args,
+                              const int *nblk, hipStream_t s)
+{
+    BatchArgs B;
+    B.n = 0;
+    B.off[0] = 0;
+    for (int m = 0; m < n && m < IBM_BATCH_MAX; ++m) {
+        if (nblk[m] <= 0)
+            continue;
+        B.args[B.n] = static_cast<const StepArgs *>(d_args[m]);
+        B.off[B.n + 1] = B.off[B.n] + nblk[m];
+        ++B.n;
+    }
+    if (B.n == 0)
+        return hipSuccess;
+    bool mixed = precision == IBM_MIXED, rk = scheme == IBM_RK3;
+    if (ndim == 2) {
+        if (rk)
+            return mixed ? batch_launch<2, float, MODE_RK3>(B, ghosts, s) : batch_launch<2, double, MODE_RK3>(B, ghosts, s);
+        return mixed ? batch_launch<2, float, MODE_DUAL>(B, ghosts, s) : batch_launch<2, double, MODE_DUAL>(B, ghosts, s);
+    }
+    if (rk)
+        return mixed ? batch_launch<3, float, MODE_RK3>(B, ghosts, s) : batch_launch<3, double, MODE_RK3>(B, ghosts, s);
+    return mixed ? batch_launch<3, float, MODE_DUAL>(B, ghosts, s) : batch_launch<3, double, MODE_DUAL>(B, ghosts, s);
 }
 
 int stage_blocks_per_cu(const Grid &g, const Flow &f)

@@ -1,0 +1,102 @@
+"""Batched serving path (ibm_batch_advance): every solve advanced inside a
+mixed batch ends bit-identical to the same solve advanced alone, across
+schemes (RK3 and dual time), precisions, 2D and 3D, a moving body (advanced
+on its own inside the batch) and a solve without a body; one batched solve
+is also checked against the oracle."""
+import numpy as np
+import pytest
+
+import workloads as w
+from gpu_common import make_pair, smooth_prim, compare_fields, tol64
+
+pytestmark = pytest.mark.gpu
+
+MIX = [
+    ("cylinder", "mixed", lambda: w.small_case("cylinder", 64, steps=4)),
+    ("cylinder64", "fp64", lambda: w.small_case("cylinder", 48, steps=4)),
+    ("wedge", "mixed", lambda: w.small_case("wedge", 48, steps=4)),
+    ("naca-dual", "mixed", lambda: w.small_case("naca", 48, steps=2, n_inner=3)),
+    ("naca-dual-even", "mixed", lambda: w.small_case("naca", 40, steps=2, n_inner=4)),
+    ("ragged", "mixed", lambda: w.small_case("cylinder", 61, steps=3)),
+    ("box", "mixed", lambda: w.small_case("box", 32, steps=3)),
+    ("tube-static", "mixed", lambda: w.small_case("tube", 30, steps=2, nz=10, ntheta=48, nzt=5,
+                                                  moving=False)),
+    ("tube-moving", "mixed", lambda: w.small_case("tube", 32, steps=3, nz=8, ntheta=64, nzt=4)),
+]
+
+
+def _solvers():
+    from paper_1912_11908_amd import Solver
+    out = []
+    for name, prec, make in MIX:
+        case = make()
+        prim = smooth_prim(case)
+        s = Solver(case, prec, "cuda:0")
+        s.init_prim(prim)
+        out.append((name, case, prim, s))
+    return out
+
+
+def test_batch_matches_alone():
+    import torch
+    from paper_1912_11908_amd import batch_advance
+    alone = _solvers()
+    batch = _solvers()
+    for _, _, _, s in alone:
+        s.advance(2)
+        s.advance(1)
+    batch_advance([s for _, _, _, s in batch], 2)
+    torch.cuda.synchronize()
+    junk = torch.randn(1000, device="cuda").sum()   # eager work between batched calls
+    batch_advance([s for _, _, _, s in batch], 1)
+    torch.cuda.synchronize()
+    del junk
+    for (name, _, _, a), (_, _, _, b) in zip(alone, batch):
+        a.check_status()
+        b.check_status()
+        ia, ib = a.interior(), b.interior()
+        assert bool((ia == ib).all()), name
+        assert a.info().time == b.info().time, name
+
+
+def test_batch_subsets_and_order():
+    """A solve's result does not depend on which other solves share its
+    batch, nor on their order."""
+    import torch
+    from paper_1912_11908_amd import batch_advance
+    one = _solvers()
+    two = _solvers()
+    batch_advance([s for _, _, _, s in one], 3)
+    rev = [s for _, _, _, s in two][::-1]
+    batch_advance(rev[:4], 2)
+    batch_advance(rev[4:], 2)
+    batch_advance(rev[::2], 1)
+    batch_advance(rev[1::2], 1)
+    torch.cuda.synchronize()
+    for (name, _, _, a), (_, _, _, b) in zip(one, two):
+        assert bool((a.interior() == b.interior()).all()), name
+
+
+def test_batched_solve_matches_oracle():
+    from paper_1912_11908_amd import batch_advance
+    case = w.small_case("cylinder", 64, steps=3)
+    prim = smooth_prim(case)
+    s, o = make_pair(case, prim, "fp64")
+    other = w.small_case("wedge", 48, steps=3)
+    s2, _ = make_pair(other, smooth_prim(other), "fp64")
+    batch_advance([s, s2], case.steps)
+    s.check_status()
+    o.classify()
+    q = o.prim_to_state(prim)
+    o.run(q, case.steps)
+    errs = compare_fields(s.interior().cpu().numpy(), o.interior(q))
+    assert errs.max() < tol64(case), errs
+
+
+def test_batch_rejects_bad_input():
+    from paper_1912_11908_amd import batch_advance, IbmError, BATCH_MAX
+    solvers = _solvers()[:2]
+    with pytest.raises(IbmError):
+        batch_advance([solvers[0][3], solvers[0][3]], 1)
+    with pytest.raises(ValueError):
+        batch_advance([solvers[0][3]] * (BATCH_MAX + 1), 1)

@@ -4,7 +4,9 @@ Grid side uniform in {64, 128, 256, 512} on [-8, 8]^2; body uniform over
 {256-gon cylinder, 15 degree wedge, NACA 00tt with tt ~ U[6, 18] %} (chord
 centred on the origin); Mach log-uniform in [0.01, 2]; Reynolds log-uniform in
 [40, 1000]; exponential inter-arrival gaps.  Solves with M < 0.1 use dual time
-stepping with the quadratic IB family.
+stepping with the quadratic IB family.  Every request costs the same number
+of residual evaluations: `steps` RK3 steps (3 each), or 3 steps / n_inner
+physical dual-time steps of n_inner pseudo-iterations.
 """
 import numpy as np
 
@@ -41,7 +43,7 @@ def request_stream(n=2000, rate=50.0, steps=500, seed=SEED, sides=(64, 128, 256,
             n_inner = 20
             case = Case(f"req{r}", 2, f, f.copy(), np.array([-0.5, 0.5]), tuple(bc), v, s,
                         mach, re, scheme="dual", ib_family="quadratic", dt=dual_dt([f, f]),
-                        n_inner=n_inner, steps=max(1, steps // n_inner))
+                        n_inner=n_inner, steps=max(1, 3 * steps // n_inner))
         else:
             case = Case(f"req{r}", 2, f, f.copy(), np.array([-0.5, 0.5]), tuple(bc), v, s,
                         mach, re, dt=rk3_dt(mach, re, [f, f]), steps=steps)
