@@ -4,9 +4,16 @@ Workload: the supersonic wedge -- 15 degree half-angle triangle of length 1,
 M = 2, Re = 1e4, 1024 x 512 rectilinear grid (x uniform on [-1, 3], y tanh
 clustered toward the wedge axis with adjacent-width ratio 1.02), SSP-RK3 with
 the compressible (IDW + image point) immersed-boundary family, free-stream
-start.  A step is one RK3 step: three stages, each a domain-ghost fill, IB
-fill and fused residual + update over every cell, so one step is
+start.  A step is one RK3 step: three stages, each an IB fill and a fused
+residual + update over every cell (two launches), so one step is
 3 * 1024 * 512 cell-updates.
+
+The serving workload runs after it: the seeded stream of 2000 independent
+2D solves (grid side 64-512, cylinder / wedge / NACA 00tt, M 0.01-2, Re
+40-1000, dual time below M 0.1, mixed precision, 1500 residual evaluations
+each) arriving as a Poisson process of 50 per second, served by the
+continuous-batching server; it reports the p50 / p99 latency from arrival
+to completion and the sustained cell-updates/s.
 
 Both precision modes are timed (mixed = FP32 reconstruction and fluxes on
 perturbation variables with FP64 update; fp64); ``value`` is the mixed
@@ -16,6 +23,7 @@ the roofline entry; the CPU oracle is timed on a bounded sample of the same
 workload for the cpu_baseline entry.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--serving-requests N] [--serving-rate R]
 """
 import argparse
 import json
@@ -30,7 +38,10 @@ if ROOT not in sys.path:
 METRIC = "cell-updates/s (full residual+IBM step) mixed vs FP64; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-FP32_PEAK_TFLOPS = 157.3
+# FP32 vector peak without packed FP32 math (which this build leaves off):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.  The packed peak,
+# 157.3 TFLOP/s, is twice that.
+FP32_PEAK_TFLOPS = 78.6
 
 # Algorithmic work per cell-update of the fused stage kernel (2D, SSP-RK3),
 # counted from the formulas (each +, -, *, /, sqrt one flop):
@@ -43,6 +54,27 @@ FLOPS_PER_CELL_2D_RK3 = 2 * (8 * 68 + 118 + 55) + 31 + 11 + 20
 BYTES_PER_CELL_STAGE = {1: 32 + 32 + 1, 2: 32 + 32 + 32 + 1, 3: 32 + 32 + 32 + 1}
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "step_batch_kernel_wedge_1024x512_hbm_counters.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1912_11908_amd", "csrc", "flow.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the timed kernel from the committed counter
+    summary, or None when the kernel source has changed since the counters
+    were taken (the summary records the source's SHA-256)."""
+    import hashlib
+    try:
+        text = open(COUNTERS).read()
+        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines()
+                  if line.startswith(("traffic_bytes_per_launch: ", "kernel_source_sha256: ")))
+    if fields.get("kernel_source_sha256", "").strip() != sha:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -52,7 +84,27 @@ def _parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--precisions", default="mixed,fp64")
+    ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--serving-rate", type=float, default=50.0)
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="also run one plain device copy of 256 MiB (reference for HBM counters)")
     return ap.parse_args()
+
+
+def serving(n, rate):
+    """The seeded serving stream through the continuous-batching server."""
+    import workloads as w
+    from workloads.serving import request_stream
+    from paper_1912_11908_amd.serving import Server, GpuBackend
+    reqs = request_stream(n=n, rate=rate, steps=500)
+    init = lambda c: w.freestream_prim(c.ndim, c.ni, c.nj, c.nk, c.p_inf)  # noqa: E731
+    backend = GpuBackend("mixed", init=init)
+    st = Server(backend, mem_budget=64 << 30, max_active=128, tick_steps=10).run(reqs)
+    out = st.summary()
+    out.update({"workload": f"{n} seeded 2D solves, Poisson arrivals at {rate:g}/s, grid side "
+                            "64-512, 1500 residual evaluations each, mixed precision",
+                "precision": "mixed", "arrival_span_s": reqs[-1][0] if reqs else 0.0})
+    return out
 
 
 def run_gpu(case, prim, precision, steps, warmup, reps):
@@ -146,9 +198,11 @@ def main():
                 "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4)}
         other = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": fpeak,
                  "unit": "TFLOP/s", "frac": round(achieved_tf / fpeak, 4)}
-    roof["traffic"] = None
-    roof["kernel"] = "step_kernel<2,%s,RK3>" % ("float" if head == "mixed" else "double")
+    # measured HBM bytes per launch (mixed path only: the counters were taken on it)
+    roof["traffic"] = measured_traffic() if head == "mixed" else None
+    roof["kernel"] = "step_batch_kernel<2,%s,RK3>" % ("float" if head == "mixed" else "double")
     roof["kernel_avg_ms"] = round(avg_ms, 5)
+    roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     roof["per_unit"] = {"flops_per_cell_update": FLOPS_PER_CELL_2D_RK3,
                         "bytes_per_cell_update": round(bytes_cell, 2), "cells_per_launch": ncell}
 
@@ -171,6 +225,18 @@ def main():
         a, b = res["mixed"]["prim"], f["prim"]
         errs = [float(np.sqrt(np.sum((a[v] - b[v]) ** 2) / np.sum(b[v] ** 2))) for v in range(4)]
         out["mixed_vs_fp64_rel_l2"] = {"rho": errs[0], "u": errs[1], "v": errs[2], "p": errs[3]}
+    if args.calibration_copy:
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = 2 * src.numel() * 8
+        del src, dst
+    if args.serving_requests > 0:
+        sv = serving(args.serving_requests, args.serving_rate)
+        out["latency_p50_s"] = sv["p50_s"]
+        out["latency_p99_s"] = sv["p99_s"]
+        out["serving"] = sv
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, prim, args.cpu_seconds)
     print(json.dumps(out), flush=True)
