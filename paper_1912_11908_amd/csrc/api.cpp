@@ -154,7 +154,89 @@ struct HostGeom {
     // tiles of the fused residual/update kernel: those whose stencils never
     // reach the IB region ("far") and the others ("near"), raster order
     std::vector<int32_t> tiles_far, tiles_near;
+    // 3D facet bins (rest frame), see Body
+    double bin_o[3], bin_h;
+    int bin_n[3], nbin;
+    std::vector<int32_t> bin_start, bin_facet;
 };
+
+// Uniform bins over the rest-pose body box for the 3D closest-feature and
+// line searches: cubes of side 2 h_min (at least the box over 2^21 bins),
+// one bin of margin; every facet is listed in each bin its bounding box
+// (widened by 1e-9 of a side against rounding) meets.
+void facet_bins(HostGeom &h, const std::vector<double> &v)
+{
+    h.nbin = 0;
+    h.bin_h = 1.0;
+    for (int d = 0; d < 3; ++d) {
+        h.bin_o[d] = 0.0;
+        h.bin_n[d] = 0;
+    }
+    h.bin_start.assign(1, 0);
+    h.bin_facet.clear();
+    int nf = (int)(h.facet.size() / 3);
+    if (h.nd != 3 || nf == 0)
+        return;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (size_t m = 0; m < v.size() / 3; ++m)
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = std::min(lo[d], v[3 * m + d]);
+            hi[d] = std::max(hi[d], v[3 * m + d]);
+        }
+    double hmin = 1e300;
+    for (int d = 0; d < 3; ++d)
+        for (int i = 0; i < h.n[d]; ++i)
+            hmin = std::min(hmin, h.xf[d][i + 4] - h.xf[d][i + 3]);
+    double bs = 2.0 * hmin;
+    for (;;) {
+        long long tot = 1;
+        for (int d = 0; d < 3; ++d)
+            tot *= (long long)std::floor((hi[d] - lo[d]) / bs) + 3;
+        if (tot <= (1LL << 21))
+            break;
+        bs *= 2.0;
+    }
+    h.bin_h = bs;
+    for (int d = 0; d < 3; ++d) {
+        h.bin_o[d] = lo[d] - bs;
+        h.bin_n[d] = (int)std::floor((hi[d] - h.bin_o[d]) / bs) + 2;
+    }
+    h.nbin = h.bin_n[0] * h.bin_n[1] * h.bin_n[2];
+    auto range = [&](int f, int *a, int *b) {
+        for (int d = 0; d < 3; ++d) {
+            double fl = 1e300, fh = -1e300;
+            for (int m = 0; m < 3; ++m) {
+                fl = std::min(fl, v[3 * h.facet[3 * f + m] + d]);
+                fh = std::max(fh, v[3 * h.facet[3 * f + m] + d]);
+            }
+            double slack = 1e-9 * bs;
+            a[d] = std::max(0, (int)std::floor((fl - slack - h.bin_o[d]) / bs));
+            b[d] = std::min(h.bin_n[d] - 1, (int)std::floor((fh + slack - h.bin_o[d]) / bs));
+        }
+    };
+    std::vector<int32_t> cnt(h.nbin + 1, 0);
+    for (int f = 0; f < nf; ++f) {
+        int a[3], b[3];
+        range(f, a, b);
+        for (int kz = a[2]; kz <= b[2]; ++kz)
+            for (int ky = a[1]; ky <= b[1]; ++ky)
+                for (int kx = a[0]; kx <= b[0]; ++kx)
+                    ++cnt[(kz * h.bin_n[1] + ky) * h.bin_n[0] + kx + 1];
+    }
+    for (int k = 0; k < h.nbin; ++k)
+        cnt[k + 1] += cnt[k];
+    h.bin_start = cnt;
+    h.bin_facet.assign(cnt[h.nbin], 0);
+    std::vector<int32_t> fillp(cnt.begin(), cnt.end() - 1);
+    for (int f = 0; f < nf; ++f) {
+        int a[3], b[3];
+        range(f, a, b);
+        for (int kz = a[2]; kz <= b[2]; ++kz)
+            for (int ky = a[1]; ky <= b[1]; ++ky)
+                for (int kx = a[0]; kx <= b[0]; ++kx)
+                    h.bin_facet[fillp[(kz * h.bin_n[1] + ky) * h.bin_n[0] + kx]++] = f;
+    }
+}
 
 // Does [lo, hi) meet [r0, r1), directly or through a periodic wrap of an
 // axis of n cells?
@@ -354,7 +436,9 @@ int host_geom(const ibm_case *c, HostGeom &h)
                 return IBM_EGEOM;
         }
         body_normals(h, h.v0);
+        facet_bins(h, h.v0);
     } else {
+        facet_bins(h, h.v0);
         h.fnrm.assign(3, 0.0);
         h.vnrm.assign(3, 0.0);
         h.enrm.assign(3, 0.0);
@@ -418,6 +502,7 @@ struct Layout {
     int *facet;
     double *fnrm, *vnrm, *enrm;
     int *edge_of;
+    int32_t *bin_start, *bin_facet;
     uint8_t *cls, *inside;
     uint32_t *toggle;
     int32_t *counts, *blk, *listF, *listG, *rec_i;
@@ -456,6 +541,8 @@ size_t carve(const ibm_case *c, const HostGeom &h, char *base, Layout &L)
     L.vnrm = cv.take<double>((size_t)std::max(c->nvert, 1) * 3);
     L.enrm = cv.take<double>(nfx * 3 * 3);
     L.edge_of = cv.take<int>(nfx * 3);
+    L.bin_start = cv.take<int32_t>(h.bin_start.size());
+    L.bin_facet = cv.take<int32_t>(std::max<size_t>(h.bin_facet.size(), 1));
     size_t cap = (size_t)std::max(h.cap, 1);
     int rows = (h.region[3] - h.region[2]) * (h.region[5] - h.region[4]);
     L.cls = cv.take<uint8_t>(h.ncell);
@@ -520,7 +607,10 @@ int do_classify(ibm_ctx *c, double t, hipStream_t s)
     if (c->mo.on && c->b.nvert > 0) {
         double disp, vel, acc;
         motion_kin(c, t, disp, vel, acc);
-        e = launch_pose(c->g, c->b, std::llrint(disp * kLatScale), c->mo.axis, s);
+        long long dl = std::llrint(disp * kLatScale);
+        for (int d = 0; d < 3; ++d)
+            c->b.disp[d] = d == c->mo.axis ? (double)dl / kLatScale : 0.0;
+        e = launch_pose(c->g, c->b, dl, c->mo.axis, s);
         if (e != hipSuccess)
             return dev_err(c, e, "pose");
     }
@@ -644,6 +734,17 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     b.vnrm = L.vnrm;
     b.enrm = L.enrm;
     b.edge_of = L.edge_of;
+    for (int d = 0; d < 3; ++d) {
+        b.bin_o[d] = h.bin_o[d];
+        b.bin_n[d] = h.bin_n[d];
+        b.disp[d] = 0.0;
+    }
+    b.bin_h = h.bin_h;
+    b.nbin = h.nbin;
+    b.bin_start = L.bin_start;
+    b.bin_facet = L.bin_facet;
+    if (e == hipSuccess) e = up(L.bin_start, h.bin_start);
+    if (e == hipSuccess) e = up(L.bin_facet, h.bin_facet);
     if (e == hipSuccess) e = up(L.V0, h.V0);
     if (e == hipSuccess) e = up(L.V, h.V0);
     if (e == hipSuccess) e = up(L.v, h.v0);

@@ -44,6 +44,13 @@ struct Body {
     const double *vnrm;      // nvert * 3
     const double *enrm;      // nedge * 3 (3D)
     const int *edge_of;      // nfacet * 3 (3D): global edge id per facet edge
+    // 3D facet bins in the rest frame (uniform cubes of side bin_h from
+    // bin_o; a facet is listed in every bin its bounding box meets), CSR:
+    // bin_start[nbin + 1], bin_facet; nbin = 0 for brute-force search
+    double bin_o[3], bin_h;
+    int bin_n[3], nbin;
+    const int *bin_start, *bin_facet;
+    double disp[3];          // current displacement of the pose (exact)
 };
 
 struct Flow {

@@ -411,37 +411,78 @@ __device__ inline void cross3(const double *a, const double *b, double *c)
 
 // Section 4.1: minimum of the squared distance of eq.1 over all facets;
 // the lowest facet id wins exact ties.  2D: clamped segment parameter.
-__device__ Closest closest2d(const Body &b, const double *p)
+// Lexicographic minimum of (d2, facet) over the wavefront: every lane
+// returns the winning lane's candidate.
+__device__ inline Closest wave_min(const Closest &c)
+{
+    double d = c.d2;
+    for (int o = kWave / 2; o >= 1; o >>= 1) {
+        double t = __shfl_xor(d, o, kWave);
+        d = t < d ? t : d;
+    }
+    int f = c.d2 == d ? c.facet : 0x7fffffff;
+    for (int o = kWave / 2; o >= 1; o >>= 1) {
+        int t = __shfl_xor(f, o, kWave);
+        f = t < f ? t : f;
+    }
+    unsigned long long m = __ballot(c.d2 == d && c.facet == f);
+    int src = __ffsll((long long)m) - 1;
+    Closest r;
+    r.kind = __shfl(c.kind, src, kWave);
+    r.id = __shfl(c.id, src, kWave);
+    r.facet = __shfl(c.facet, src, kWave);
+    r.d2 = __shfl(c.d2, src, kWave);
+    for (int k = 0; k < 3; ++k)
+        r.c[k] = __shfl(c.c[k], src, kWave);
+    return r;
+}
+
+// smallest non-negative value over the wavefront (-1 if none)
+__device__ inline double wave_min_hit(double sig)
+{
+    double d = sig < 0.0 ? __builtin_inf() : sig;
+    for (int o = kWave / 2; o >= 1; o >>= 1) {
+        double t = __shfl_xor(d, o, kWave);
+        d = t < d ? t : d;
+    }
+    return d == __builtin_inf() ? -1.0 : d;
+}
+
+__device__ inline void keep(Closest &best, const Closest &cur)
+{
+    if (cur.d2 < best.d2 || (cur.d2 == best.d2 && cur.facet < best.facet))
+        best = cur;
+}
+
+// 2D: closest point of each segment (vertex or interior); the minimum over
+// all segments, lowest segment id among equals.  Called by a whole
+// wavefront for one node: lanes split the segments.
+__device__ Closest closest2d(const Body &b, const double *p, int lane)
 {
     Closest best;
     best.d2 = __builtin_inf();
     best.kind = best.id = best.facet = -1;
     best.c[0] = best.c[1] = best.c[2] = 0.0;
-    for (int f = 0; f < b.nfacet; ++f) {
+    for (int f = lane; f < b.nfacet; f += kWave) {
         int ia = b.facet[2 * f], ibv = b.facet[2 * f + 1];
         const double *a = b.v + 2 * ia, *q = b.v + 2 * ibv;
         double ex = q[0] - a[0], ey = q[1] - a[1];
         double t = ((p[0] - a[0]) * ex + (p[1] - a[1]) * ey) / (ex * ex + ey * ey);
-        double cx, cy;
-        int kind, id;
+        Closest cur;
+        cur.c[2] = 0.0;
         if (t <= 0.0) {
-            cx = a[0]; cy = a[1]; kind = FEAT_VERTEX; id = ia;
+            cur.c[0] = a[0]; cur.c[1] = a[1]; cur.kind = FEAT_VERTEX; cur.id = ia;
         } else if (t >= 1.0) {
-            cx = q[0]; cy = q[1]; kind = FEAT_VERTEX; id = ibv;
+            cur.c[0] = q[0]; cur.c[1] = q[1]; cur.kind = FEAT_VERTEX; cur.id = ibv;
         } else {
-            cx = a[0] + t * ex; cy = a[1] + t * ey; kind = FEAT_FACE; id = f;
+            cur.c[0] = a[0] + t * ex; cur.c[1] = a[1] + t * ey; cur.kind = FEAT_FACE; cur.id = f;
         }
-        double dx = p[0] - cx, dy = p[1] - cy, d2 = dx * dx + dy * dy;
-        if (d2 < best.d2) {
-            best.d2 = d2;
-            best.kind = kind;
-            best.id = id;
-            best.facet = f;
-            best.c[0] = cx;
-            best.c[1] = cy;
-        }
+        double dx = p[0] - cur.c[0], dy = p[1] - cur.c[1];
+        cur.d2 = dx * dx + dy * dy;
+        cur.facet = f;
+        keep(best, cur);
     }
-    return best;
+    return wave_min(best);
 }
 
 __device__ inline void seg_closest(const double *p, const double *a, const double *q, double &t,
@@ -467,67 +508,115 @@ __device__ inline void seg_closest(const double *p, const double *a, const doubl
 
 // 3D: interior stationary point of eq.1 (face region) when feasible,
 // otherwise the best of the three edge minimisers (edge or vertex regions).
-__device__ Closest closest3d(const Body &b, const double *p)
+__device__ inline Closest facet_closest(const Body &b, const double *p, int f)
+{
+    const int *tv = b.facet + 3 * f;
+    const double *A = b.v + 3 * tv[0], *B = b.v + 3 * tv[1], *C = b.v + 3 * tv[2];
+    double e0[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+    double e1[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+    double dd[3] = {A[0] - p[0], A[1] - p[1], A[2] - p[2]};
+    double a = dot3(e0, e0), bb = dot3(e0, e1), c = dot3(e1, e1);
+    double d = dot3(e0, dd), e = dot3(e1, dd);
+    double det = a * c - bb * bb;
+    double s = bb * e - c * d, t = bb * d - a * e;
+    Closest cur;
+    cur.kind = cur.id = -1;
+    cur.facet = f;
+    if (s > 0.0 && t > 0.0 && s + t < det) {
+        s /= det;
+        t /= det;
+        cur.kind = FEAT_FACE;
+        cur.id = f;
+        for (int m = 0; m < 3; ++m)
+            cur.c[m] = A[m] + s * e0[m] + t * e1[m];
+        double dx = p[0] - cur.c[0], dy = p[1] - cur.c[1], dz = p[2] - cur.c[2];
+        cur.d2 = dx * dx + dy * dy + dz * dz;
+    } else {
+        cur.d2 = __builtin_inf();
+        for (int m = 0; m < 3; ++m) {
+            const double *pa = b.v + 3 * tv[m], *pb = b.v + 3 * tv[(m + 1) % 3];
+            double tt, cc[3], d2;
+            seg_closest(p, pa, pb, tt, cc, d2);
+            if (d2 < cur.d2) {
+                cur.d2 = d2;
+                cur.c[0] = cc[0]; cur.c[1] = cc[1]; cur.c[2] = cc[2];
+                if (tt == 0.0) {
+                    cur.kind = FEAT_VERTEX;
+                    cur.id = tv[m];
+                } else if (tt == 1.0) {
+                    cur.kind = FEAT_VERTEX;
+                    cur.id = tv[(m + 1) % 3];
+                } else {
+                    cur.kind = FEAT_EDGE;
+                    cur.id = b.edge_of[3 * f + m];
+                }
+            }
+        }
+    }
+    return cur;
+}
+
+// bin index of rest-frame coordinate y along axis d (may lie outside the grid)
+__device__ inline int bin_of(const Body &b, int d, double y) { return (int)floor((y - b.bin_o[d]) / b.bin_h); }
+
+// The brute-force minimum over all facets, smallest squared distance first
+// and the lowest facet id among equals.  With bins, cubic shells of bins
+// around the node are searched outwards: after the shells up to K every
+// facet closer than (K - 1) bin sides has been examined (one side of slack
+// for the rounding of the node's own bin), so the search stops there with
+// the same result as the brute force.
+// Called by a whole wavefront for one node: lanes split the facets of
+// each bin, and the shells end on the wavefront's minimum.
+__device__ Closest closest3d(const Body &b, const double *p, int lane)
 {
     Closest best;
     best.d2 = __builtin_inf();
     best.kind = best.id = best.facet = -1;
     best.c[0] = best.c[1] = best.c[2] = 0.0;
-    for (int f = 0; f < b.nfacet; ++f) {
-        const int *tv = b.facet + 3 * f;
-        const double *A = b.v + 3 * tv[0], *B = b.v + 3 * tv[1], *C = b.v + 3 * tv[2];
-        double e0[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
-        double e1[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
-        double dd[3] = {A[0] - p[0], A[1] - p[1], A[2] - p[2]};
-        double a = dot3(e0, e0), bb = dot3(e0, e1), c = dot3(e1, e1);
-        double d = dot3(e0, dd), e = dot3(e1, dd);
-        double det = a * c - bb * bb;
-        double s = bb * e - c * d, t = bb * d - a * e;
-        Closest cur;
-        cur.kind = cur.id = -1;
-        if (s > 0.0 && t > 0.0 && s + t < det) {
-            s /= det;
-            t /= det;
-            cur.kind = FEAT_FACE;
-            cur.id = f;
-            for (int m = 0; m < 3; ++m)
-                cur.c[m] = A[m] + s * e0[m] + t * e1[m];
-            double dx = p[0] - cur.c[0], dy = p[1] - cur.c[1], dz = p[2] - cur.c[2];
-            cur.d2 = dx * dx + dy * dy + dz * dz;
-        } else {
-            cur.d2 = __builtin_inf();
-            for (int m = 0; m < 3; ++m) {
-                const double *pa = b.v + 3 * tv[m], *pb = b.v + 3 * tv[(m + 1) % 3];
-                double tt, cc[3], d2;
-                seg_closest(p, pa, pb, tt, cc, d2);
-                if (d2 < cur.d2) {
-                    cur.d2 = d2;
-                    cur.c[0] = cc[0]; cur.c[1] = cc[1]; cur.c[2] = cc[2];
-                    if (tt == 0.0) {
-                        cur.kind = FEAT_VERTEX;
-                        cur.id = tv[m];
-                    } else if (tt == 1.0) {
-                        cur.kind = FEAT_VERTEX;
-                        cur.id = tv[(m + 1) % 3];
-                    } else {
-                        cur.kind = FEAT_EDGE;
-                        cur.id = b.edge_of[3 * f + m];
-                    }
+    if (b.nbin == 0) {
+        for (int f = lane; f < b.nfacet; f += kWave)
+            keep(best, facet_closest(b, p, f));
+        return wave_min(best);
+    }
+    int ic[3], far = 0;
+    for (int d = 0; d < 3; ++d) {
+        ic[d] = bin_of(b, d, p[d] - b.disp[d]);
+        far = max(far, max(ic[d], b.bin_n[d] - 1 - ic[d]));
+    }
+    for (int K = 0; K <= far; ++K) {
+        for (int dz = -K; dz <= K; ++dz) {
+            int kz = ic[2] + dz;
+            if (kz < 0 || kz >= b.bin_n[2])
+                continue;
+            for (int dy = -K; dy <= K; ++dy) {
+                int ky = ic[1] + dy;
+                if (ky < 0 || ky >= b.bin_n[1])
+                    continue;
+                bool edge = abs(dz) == K || abs(dy) == K;
+                for (int dx = -K; dx <= K; dx += (edge || K == 0) ? 1 : 2 * K) {
+                    int kx = ic[0] + dx;
+                    if (kx < 0 || kx >= b.bin_n[0])
+                        continue;
+                    int bin = (kz * b.bin_n[1] + ky) * b.bin_n[0] + kx;
+                    for (int m = b.bin_start[bin] + lane; m < b.bin_start[bin + 1]; m += kWave)
+                        keep(best, facet_closest(b, p, b.bin_facet[m]));
                 }
             }
         }
-        if (cur.d2 < best.d2) {
-            best = cur;
-            best.facet = f;
+        double reach = (K - 1) * b.bin_h;
+        if (K >= 1) {
+            best = wave_min(best);
+            if (best.d2 < reach * reach * (1.0 - 1e-9))
+                break;
         }
     }
-    return best;
+    return wave_min(best);
 }
 
-__device__ double line_hit2d(const Body &b, const double *x, const double *dir, double smax)
+__device__ double line_hit2d(const Body &b, const double *x, const double *dir, double smax, int lane)
 {
     double best = -1.0;
-    for (int f = 0; f < b.nfacet; ++f) {
+    for (int f = lane; f < b.nfacet; f += kWave) {
         const double *a = b.v + 2 * b.facet[2 * f], *q = b.v + 2 * b.facet[2 * f + 1];
         double ex = q[0] - a[0], ey = q[1] - a[1];
         double den = dir[0] * ey - dir[1] * ex;
@@ -541,39 +630,71 @@ __device__ double line_hit2d(const Body &b, const double *x, const double *dir, 
         if (best < 0.0 || sig < best)
             best = sig;
     }
-    return best;
+    return wave_min_hit(best);
 }
 
 // Moller-Trumbore line/triangle intersection (section 3.2)
-__device__ double line_hit3d(const Body &b, const double *x, const double *dir, double smax)
+// Moller-Trumbore: parameter sig in [0, smax] where x + sig dir meets facet
+// f, or -1
+__device__ inline double facet_hit(const Body &b, const double *x, const double *dir, double smax, int f)
+{
+    const int *tv = b.facet + 3 * f;
+    const double *A = b.v + 3 * tv[0], *B = b.v + 3 * tv[1], *C = b.v + 3 * tv[2];
+    double e1[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+    double e2[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+    double pv[3];
+    cross3(dir, e2, pv);
+    double det = dot3(e1, pv);
+    if (det == 0.0)
+        return -1.0;
+    double tv_[3] = {x[0] - A[0], x[1] - A[1], x[2] - A[2]};
+    double u = dot3(tv_, pv) / det;
+    if (u < 0.0 || u > 1.0)
+        return -1.0;
+    double qv[3];
+    cross3(tv_, e1, qv);
+    double vv = dot3(dir, qv) / det;
+    if (vv < 0.0 || u + vv > 1.0)
+        return -1.0;
+    double sig = dot3(e2, qv) / det;
+    if (sig < 0.0 || sig > smax)
+        return -1.0;
+    return sig;
+}
+
+// First hit along the segment (smallest sig over all facets).  With bins,
+// only the bins that meet the segment's bounding box (widened by a little
+// for rounding) are searched: a facet the segment meets is listed in the bin
+// of the meeting point.
+__device__ double line_hit3d(const Body &b, const double *x, const double *dir, double smax, int lane)
 {
     double best = -1.0;
-    for (int f = 0; f < b.nfacet; ++f) {
-        const int *tv = b.facet + 3 * f;
-        const double *A = b.v + 3 * tv[0], *B = b.v + 3 * tv[1], *C = b.v + 3 * tv[2];
-        double e1[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
-        double e2[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
-        double pv[3];
-        cross3(dir, e2, pv);
-        double det = dot3(e1, pv);
-        if (det == 0.0)
-            continue;
-        double tv_[3] = {x[0] - A[0], x[1] - A[1], x[2] - A[2]};
-        double u = dot3(tv_, pv) / det;
-        if (u < 0.0 || u > 1.0)
-            continue;
-        double qv[3];
-        cross3(tv_, e1, qv);
-        double vv = dot3(dir, qv) / det;
-        if (vv < 0.0 || u + vv > 1.0)
-            continue;
-        double sig = dot3(e2, qv) / det;
-        if (sig < 0.0 || sig > smax)
-            continue;
-        if (best < 0.0 || sig < best)
-            best = sig;
+    if (b.nbin == 0) {
+        for (int f = lane; f < b.nfacet; f += kWave) {
+            double sig = facet_hit(b, x, dir, smax, f);
+            if (sig >= 0.0 && (best < 0.0 || sig < best))
+                best = sig;
+        }
+        return wave_min_hit(best);
     }
-    return best;
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        double y0 = x[d] - b.disp[d], y1 = y0 + smax * dir[d];
+        double slack = 1e-9 * b.bin_h;
+        lo[d] = max(0, bin_of(b, d, fmin(y0, y1) - slack));
+        hi[d] = min(b.bin_n[d] - 1, bin_of(b, d, fmax(y0, y1) + slack));
+    }
+    for (int kz = lo[2]; kz <= hi[2]; ++kz)
+        for (int ky = lo[1]; ky <= hi[1]; ++ky)
+            for (int kx = lo[0]; kx <= hi[0]; ++kx) {
+                int bin = (kz * b.bin_n[1] + ky) * b.bin_n[0] + kx;
+                for (int m = b.bin_start[bin] + lane; m < b.bin_start[bin + 1]; m += kWave) {
+                    double sig = facet_hit(b, x, dir, smax, b.bin_facet[m]);
+                    if (sig >= 0.0 && (best < 0.0 || sig < best))
+                        best = sig;
+                }
+            }
+    return wave_min_hit(best);
 }
 
 // enclosing cell along one axis: largest i0 with c[i0] <= y < c[i0 + 1];
@@ -671,18 +792,22 @@ __device__ bool probe_setup(const Grid &g, const uint8_t *cls, const double *y, 
 // Sections 4.1-4.3: closest feature, local normal (face normal or the
 // pseudo-normals of eqs 2-3), boundary point P' where the line through the
 // node parallel to the normal meets the surface, and probes along it.
-__device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib, int r, int nF);
+// One wavefront per node: every lane follows the same node (the facet
+// searches are split across the lanes); lane 0 writes.
+__device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib, int r, int nF, int lane);
 
 __global__ void records_kernel(Grid g, Body b, Flow fl, IB ib)
 {
     int nF = min(ib.counts[CNT_F], ib.cap);
     int nG = min(ib.counts[CNT_G], ib.cap - nF);
-    int stride = gridDim.x * blockDim.x;
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nF + nG; r += stride)
-        node_record(g, b, fl, ib, r, nF);
+    int lane = threadIdx.x % kWave;
+    int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    int nwave = gridDim.x * blockDim.x / kWave;
+    for (int r = wave; r < nF + nG; r += nwave)
+        node_record(g, b, fl, ib, r, nF, lane);
 }
 
-__device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib, int r, int nF)
+__device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib, int r, int nF, int lane)
 {
     bool forcing = r < nF;
     int c = forcing ? ib.listF[r] : ib.listG[r - nF];
@@ -692,7 +817,7 @@ __device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib
     double h = fmin(g.xf[0][i + 4] - g.xf[0][i + 3], g.xf[1][j + 4] - g.xf[1][j + 3]);
     if (nd == 3)
         h = fmin(h, g.xf[2][k + 4] - g.xf[2][k + 3]);
-    Closest cl = nd == 2 ? closest2d(b, X) : closest3d(b, X);
+    Closest cl = nd == 2 ? closest2d(b, X, lane) : closest3d(b, X, lane);
     const double *src = cl.kind == FEAT_FACE ? b.fnrm + 3 * cl.id
                         : cl.kind == FEAT_VERTEX ? b.vnrm + 3 * cl.id
                                                  : b.enrm + 3 * cl.id;
@@ -703,13 +828,14 @@ __device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib
         double dir[3] = {0.0, 0.0, 0.0};
         for (int d = 0; d < nd; ++d)
             dir[d] = forcing ? -n[d] : n[d];
-        double sig = nd == 2 ? line_hit2d(b, X, dir, 4.0 * h) : line_hit3d(b, X, dir, 4.0 * h);
+        double sig = nd == 2 ? line_hit2d(b, X, dir, 4.0 * h, lane) : line_hit3d(b, X, dir, 4.0 * h, lane);
         if (sig >= 0.0) {
             for (int d = 0; d < nd; ++d)
                 P[d] = X[d] + sig * dir[d];
         } else {
             fb |= 1;
-            atomicAdd(&ib.counts[CNT_FB_PPRIME], 1);
+            if (lane == 0)
+                atomicAdd(&ib.counts[CNT_FB_PPRIME], 1);
         }
     }
     double dist2 = 0.0;
@@ -749,7 +875,8 @@ __device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib
             y2[d] = P[d] + s2 * n[d];
         }
         fb |= 2;
-        atomicAdd(&ib.counts[CNT_FB_PROBE], 1);
+        if (lane == 0)
+            atomicAdd(&ib.counts[CNT_FB_PROBE], 1);
         mode1 = mode2 = 1;
         bool v1 = probe_setup(g, ib.cls, y1, 1, allow_forcing, ids1, w1);
         bool v2 = quad ? probe_setup(g, ib.cls, y2, 1, allow_forcing, ids2, w2) : true;
@@ -767,6 +894,8 @@ __device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib
         }
         mode2 = 3;
     }
+    if (lane != 0)  // every lane holds the same record
+        return;
     int *ir = ib.rec_i + (long long)kRecI * r;
     double *dr = ib.rec_d + (long long)kRecD * r;
     ir[0] = c;
@@ -869,9 +998,9 @@ hipError_t launch_records(const Grid &g, const Body &b, const Flow &f, IB &ib, h
 {
     if (ib.cap == 0 || b.nfacet == 0)
         return hipSuccess;
-    int nb = blocks_for(ib.cap, 64);
-    nb = nb < 1024 ? nb : 1024;
-    hipLaunchKernelGGL(records_kernel, dim3(nb), dim3(64), 0, s, g, b, f, ib);
+    int nb = blocks_for(ib.cap, kBlock / kWave);  // one wavefront per node
+    nb = nb < 4096 ? nb : 4096;
+    hipLaunchKernelGGL(records_kernel, dim3(nb), dim3(kBlock), 0, s, g, b, f, ib);
     return hipGetLastError();
 }
 
