@@ -399,27 +399,49 @@ template <int DIM> __device__ inline bool ghost_source(const Grid &g, int *c)
     return ff;
 }
 
-// WENO5 (Jiang-Shu, eps 1e-6, linear weights 0.1, 0.6, 0.3) left state at
-// i+1/2 from v(i-2..i+2).  The nonlinear weights are formed with a single
-// reciprocal: omega_k ~ d_k prod_{m != k} (eps + beta_m)^2.
+// WENO5 (Jiang-Shu, eps 1e-6, linear weights 0.1, 0.6, 0.3).  For the face
+// between cells v2 and v3 of the six cells v0..v5: wl from v0..v4 (left
+// state), wr from v5..v1 (right state).  Written on first differences
+// D_k = v_{k+1} - v_k, which the two states share (the right state's are
+// the left state's mirrored and negated), as are two of the three second
+// differences.  Per state, with d1..d4 its first differences and c its
+// central cell:
+//   12 (eps + beta_k) = 12 eps + 13 t_k^2 + 3 u_k^2,
+//   t = (d2 - d1, d3 - d2, d4 - d3), u = (3 d2 - d1, d2 + d3, d4 - 3 d3);
+// the candidate values are c + r_k / 6 with r = (5 d2 - 2 d1, d2 + 2 d3,
+// 4 d3 - d4), and the state is c + sum_k w_k r_k / 6 with
+// w_k ~ gamma_k / (12 (eps + beta_k))^2, formed with a single reciprocal
+// (the common factor 12 cancels in the normalised weights).
 template <typename R>
-__device__ inline R weno5(R a, R b, R c, R d, R e)
+__device__ inline R weno5_state(R c, R d1, R d2, R d3, R d4, R t0, R t1, R t2)
 {
-    const R k13 = R(13.0 / 12.0), q = R(0.25), eps = R(1.0e-6);
-    R t0 = a - R(2) * b + c, u0 = a - R(4) * b + R(3) * c;
-    R t1 = b - R(2) * c + d, u1 = b - d;
-    R t2 = c - R(2) * d + e, u2 = R(3) * c - R(4) * d + e;
-    R s0 = eps + (k13 * t0 * t0 + q * u0 * u0);
-    R s1 = eps + (k13 * t1 * t1 + q * u1 * u1);
-    R s2 = eps + (k13 * t2 * t2 + q * u2 * u2);
+    const R e12 = R(12.0e-6);
+    R u0 = R(3) * d2 - d1, u1 = d2 + d3, u2 = d4 - R(3) * d3;
+    R s0 = e12 + (R(13) * t0 * t0 + R(3) * u0 * u0);
+    R s1 = e12 + (R(13) * t1 * t1 + R(3) * u1 * u1);
+    R s2 = e12 + (R(13) * t2 * t2 + R(3) * u2 * u2);
     s0 *= s0;
     s1 *= s1;
     s2 *= s2;
-    R a0 = R(0.1) * (s1 * s2), a1 = R(0.6) * (s0 * s2), a2 = R(0.3) * (s0 * s1);
-    R q0 = (R(2) * a - R(7) * b + R(11) * c);
-    R q1 = (-b + R(5) * c + R(2) * d);
-    R q2 = (R(2) * c + R(5) * d - e);
-    return (a0 * q0 + a1 * q1 + a2 * q2) * rcp_fast<R>(R(6) * (a0 + a1 + a2));
+    R a0 = s1 * s2, a1 = s0 * s2, a2 = s0 * s1;
+    // gamma_k r_k / 6
+    R r0 = R(0.5 / 6.0) * d2 - R(0.2 / 6.0) * d1;
+    R r1 = R(0.6 / 6.0) * d2 + R(1.2 / 6.0) * d3;
+    R r2 = R(1.2 / 6.0) * d3 - R(0.3 / 6.0) * d4;
+    R num = a0 * r0 + a1 * r1 + a2 * r2;
+    R den = R(0.1) * a0 + R(0.6) * a1 + R(0.3) * a2;
+    return c + num * rcp_fast<R>(den);
+}
+
+template <typename R>
+__device__ inline void weno5_pair(R v0, R v1, R v2, R v3, R v4, R v5, R &wl, R &wr)
+{
+    R D0 = v1 - v0, D1 = v2 - v1, D2 = v3 - v2, D3 = v4 - v3, D4 = v5 - v4;
+    R T1 = D1 - D0, T2 = D2 - D1, T3 = D3 - D2, T4 = D4 - D3;
+    // left: d = (D0, D1, D2, D3), t = (T1, T2, T3)
+    wl = weno5_state<R>(v2, D0, D1, D2, D3, T1, T2, T3);
+    // right (v5, v4, v3, v2, v1): d = (-D4, -D3, -D2, -D1), t = (T4, T3, T2)
+    wr = weno5_state<R>(v3, -D4, -D3, -D2, -D1, T4, T3, T2);
 }
 
 template <typename R> struct FlowR {
@@ -542,8 +564,7 @@ __device__ inline void face_flux(const Real *__restrict__ S, int base, const int
     for (int m = 0; m < NV; ++m) {
         const Real *s = S + m * LCELLS + base;
         Real v0 = s[-2 * SD], v1 = s[-SD], v2 = s[0], v3 = s[SD], v4 = s[2 * SD], v5 = s[3 * SD];
-        wl[m] = weno5<Real>(v0, v1, v2, v3, v4);
-        wr[m] = weno5<Real>(v5, v4, v3, v2, v1);
+        weno5_pair<Real>(v0, v1, v2, v3, v4, v5, wl[m], wr[m]);
     }
     ldfss_pert<Real, NV, D>(wl, wr, fp, flux);
 
@@ -665,20 +686,22 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
 
 
     // perturbation primitives of state values qv into LDS cell t
+    const double rinv = 1.0 / f.R;
     auto put = [&](int t, const double *qv) {
         double v[NS];
         if (f.scheme == IBM_RK3) {
             double rho = qv[0];
+            double ri = 1.0 / rho;  // one divide per cell
             double ke = 0.0;
 #pragma unroll
             for (int d = 0; d < DIM; ++d) {
-                v[1 + d] = qv[1 + d] / rho;
+                v[1 + d] = qv[1 + d] * ri;
                 ke += v[1 + d] * v[1 + d];
             }
             double p = (f.gamma - 1.0) * (qv[DIM + 1] - 0.5 * rho * ke);
             v[0] = rho - 1.0;
             v[DIM + 1] = p - f.pinf;
-            v[DIM + 2] = p / (rho * f.R) - 1.0;
+            v[DIM + 2] = p * ri * rinv - 1.0;
         } else {
             double pp = qv[0], tp = qv[DIM + 1];
 #pragma unroll
