@@ -99,7 +99,7 @@ def serving(n, rate):
     reqs = request_stream(n=n, rate=rate, steps=500)
     init = lambda c: w.freestream_prim(c.ndim, c.ni, c.nj, c.nk, c.p_inf)  # noqa: E731
     backend = GpuBackend("mixed", init=init)
-    st = Server(backend, mem_budget=64 << 30, max_active=128, tick_steps=10).run(reqs)
+    st = Server(backend, mem_budget=64 << 30, max_active=128, tick_evals=30).run(reqs)
     out = st.summary()
     out.update({"workload": f"{n} seeded 2D solves, Poisson arrivals at {rate:g}/s, grid side "
                             "64-512, 1500 residual evaluations each, mixed precision",

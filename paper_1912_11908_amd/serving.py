@@ -64,15 +64,21 @@ def case_cell_updates(case):
 
 
 class Server:
-    """FIFO admission under `mem_budget` bytes and `max_active` solves;
-    every tick advances all active solves by min(tick_steps, fewest steps
-    left) steps."""
+    """FIFO admission under `mem_budget` bytes and `max_active` solves.
+    Every tick advances each active solve by about `tick_evals` residual
+    evaluations (its steps per tick: tick_evals over its evaluations per
+    step, at least one, at most the steps it has left); solves advancing by
+    the same number of steps share one batched call."""
 
-    def __init__(self, backend, mem_budget, max_active=128, tick_steps=10):
+    def __init__(self, backend, mem_budget, max_active=128, tick_evals=30):
         self.backend = backend
         self.mem_budget = int(mem_budget)
         self.max_active = int(max_active)
-        self.tick_steps = int(tick_steps)
+        self.tick_evals = int(tick_evals)
+
+    def steps_per_tick(self, job):
+        k = max(1, self.tick_evals // int(job.case.evals_per_step))
+        return min(k, job.steps_left)
 
     def run(self, requests):
         be = self.backend
@@ -98,13 +104,14 @@ class Server:
                 active.append(j)
             stats.max_active = max(stats.max_active, len(active))
             if active:
-                k = min(self.tick_steps, min(j.steps_left for j in active))
-                be.advance([j.solver for j in active], k)
-                finished = []
+                by_k = {}
                 for j in active:
-                    j.steps_left -= k
-                    if j.steps_left == 0:
-                        finished.append(j)
+                    by_k.setdefault(self.steps_per_tick(j), []).append(j)
+                for k, jobs in sorted(by_k.items()):
+                    be.advance([j.solver for j in jobs], k)
+                    for j in jobs:
+                        j.steps_left -= k
+                finished = [j for j in active if j.steps_left == 0]
                 active = [j for j in active if j.steps_left > 0]
                 for j in finished:
                     be.finish(j.solver)
@@ -133,10 +140,12 @@ class Server:
 
 
 class GpuBackend:
-    """Solves on one GPU through the C ABI (Solver + batch_advance), all on
-    one non-blocking stream of their own, so that creating a solve (which
-    uploads its geometry synchronously) never waits for the batch in
-    flight."""
+    """Solves on one GPU through the C ABI (Solver + batch_advance), on
+    non-blocking streams of their own, so that creating a solve (which
+    uploads its geometry synchronously) never waits for the batch in flight.
+    RK3 and dual-time solves run on two streams, so the launch chains of the
+    two kinds overlap; a solve always stays on its kind's stream, and its
+    memory is released only after both streams' tick events have fired."""
 
     def __init__(self, precision="mixed", device="cuda:0", init=None):
         import torch
@@ -149,6 +158,7 @@ class GpuBackend:
         self.precision = precision
         self.device = torch.device(device)
         self.stream = torch.cuda.Stream(self.device)
+        self.streams = {"rk3": self.stream, "dual": torch.cuda.Stream(self.device)}
         self.init = init
 
     def bytes_needed(self, case):
@@ -159,24 +169,34 @@ class GpuBackend:
 
     def create(self, case):
         torch = self.torch
-        with torch.cuda.stream(self.stream):
-            s = self.Solver(case, self.precision, str(self.device), stream=self.stream)
+        st = self.streams[case.scheme]
+        with torch.cuda.stream(st):
+            s = self.Solver(case, self.precision, str(self.device), stream=st)
             if self.init is not None:
                 prim = torch.from_numpy(self.init(case)).pin_memory()
                 s.init_prim(prim.to(self.device, non_blocking=True))
+        s._serving_stream = st
         return s
 
     def advance(self, solvers, k):
-        for m in range(0, len(solvers), self.batch_max):
-            self.batch_advance(solvers[m:m + self.batch_max], k, stream=self.stream)
+        by_stream = {}
+        for s in solvers:
+            by_stream.setdefault(id(s._serving_stream), (s._serving_stream, []))[1].append(s)
+        for st, group in by_stream.values():
+            for m in range(0, len(group), self.batch_max):
+                self.batch_advance(group[m:m + self.batch_max], k, stream=st)
 
     def mark(self):
-        ev = self.torch.cuda.Event()
-        ev.record(self.stream)
-        return ev
+        evs = []
+        for st in self.streams.values():
+            ev = self.torch.cuda.Event()
+            ev.record(st)
+            evs.append(ev)
+        return evs
 
-    def wait(self, ev):
-        ev.synchronize()
+    def wait(self, evs):
+        for ev in evs:
+            ev.synchronize()
 
     def finish(self, solver):
         """Enqueue the copy of the solve's status word to pinned host memory
@@ -184,7 +204,7 @@ class GpuBackend:
         torch = self.torch
         off = solver.info().counts - solver.workspace.data_ptr()
         solver._status_host = torch.empty(8, dtype=torch.int32, pin_memory=True)
-        with torch.cuda.stream(self.stream):
+        with torch.cuda.stream(solver._serving_stream):
             src = solver.workspace[off:off + 32].view(torch.int32)
             solver._status_host.copy_(src, non_blocking=True)
 

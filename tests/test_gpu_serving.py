@@ -100,3 +100,30 @@ def test_batch_rejects_bad_input():
         batch_advance([solvers[0][3], solvers[0][3]], 1)
     with pytest.raises(ValueError):
         batch_advance([solvers[0][3]] * (BATCH_MAX + 1), 1)
+
+
+def test_server_end_to_end_matches_alone():
+    """The continuous-batching server on a short seeded stream (both
+    schemes, several grid sizes): every request completes without a status
+    error, and each final state equals the same solve advanced alone."""
+    import torch
+    from workloads.serving import request_stream
+    from paper_1912_11908_amd import Solver
+    from paper_1912_11908_amd.serving import Server, GpuBackend
+
+    reqs = request_stream(n=10, rate=400.0, steps=12, sides=(64, 96))
+    init = lambda c: w.freestream_prim(c.ndim, c.ni, c.nj, c.nk, c.p_inf)  # noqa: E731
+    finals = {}
+
+    class Keep(GpuBackend):
+        def release(self, solver):
+            finals[id(solver.case)] = solver.interior().clone()
+
+    st = Server(Keep("mixed", init=init), mem_budget=1 << 30, max_active=4, tick_evals=9).run(reqs)
+    torch.cuda.synchronize()
+    assert len(st.latencies) == len(reqs) and st.failed == 0
+    for _, case in reqs:
+        s = Solver(case, "mixed", "cuda:0")
+        s.init_prim(init(case))
+        s.advance(case.steps)
+        assert bool((s.interior() == finals[id(case)]).all()), case.name

@@ -96,7 +96,7 @@ def _requests(n=60, rate=50.0, seed=3):
 def test_every_request_completes_with_its_steps():
     reqs = _requests()
     be = SimBackend()
-    st = Server(be, mem_budget=10 ** 9, max_active=16, tick_steps=7).run(reqs)
+    st = Server(be, mem_budget=10 ** 9, max_active=16, tick_evals=21).run(reqs)
     assert len(st.latencies) == len(reqs)
     assert [be.steps_done[m] for m in range(len(reqs))] == [c.steps for _, c in reqs]
     assert st.cell_updates == sum(case_cell_updates(c) for _, c in reqs)
@@ -108,7 +108,7 @@ def test_memory_budget_and_cap_hold():
     reqs = _requests(80, rate=400.0)
     be = SimBackend(rate=2e8)
     budget = 256 * 256 * 100 * 3
-    st = Server(be, mem_budget=budget, max_active=5, tick_steps=4).run(reqs)
+    st = Server(be, mem_budget=budget, max_active=5, tick_evals=12).run(reqs)
     assert be.max_used <= budget          # finished solves hold memory until their tick ends
     assert be.max_batch <= 5
     assert len(st.latencies) == len(reqs)
@@ -132,12 +132,30 @@ def test_percentiles_match_latencies():
     assert s["requests"] == 40
 
 
+def test_ticks_equalise_evaluations():
+    """A solve with 20 evaluations per step advances one step per tick while
+    3-evaluation solves advance tick_evals / 3 steps."""
+    reqs = [(0.0, FakeCase(64 * 64, 40)), (0.0, FakeCase(64 * 64, 4, evals_per_step=20))]
+    be = SimBackend()
+    calls = []
+    orig = be.advance
+
+    def rec(solvers, k):
+        calls.append((tuple(solvers), k))
+        orig(solvers, k)
+    be.advance = rec
+    st = Server(be, mem_budget=10 ** 9, tick_evals=30).run(reqs)
+    assert len(st.latencies) == 2
+    assert ((0,), 10) in calls and ((1,), 1) in calls
+    assert be.steps_done == {0: 40, 1: 4}
+
+
 def test_latency_at_least_the_solve_alone():
     """Under light load a request's latency is its own solve time plus at
     most one tick of admission delay."""
     reqs = [(m * 10.0, FakeCase(128 * 128, 20)) for m in range(5)]
     be = SimBackend(rate=1e9, per_call=0.0)
-    st = Server(be, mem_budget=10 ** 9, tick_steps=5).run(reqs)
+    st = Server(be, mem_budget=10 ** 9, tick_evals=15).run(reqs)
     alone = 128 * 128 * 3 * 20 / 1e9
     for lat in st.latencies:
         assert alone * 0.999 <= lat <= alone * 1.5 + 1e-3
