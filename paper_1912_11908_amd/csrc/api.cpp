@@ -510,6 +510,7 @@ struct Layout {
     int32_t *plan_node, *plan_off, *plan_mode;
     double *plan_w, *plan_geo;
     int32_t *rmap;
+    int32_t *tile_slot, *slot_tile, *tg_cnt, *tg_t, *tg_rec;
     int32_t *tiles;
     char *args;
     double *q1, *q2, *wtmp, *qn, *qnm1;
@@ -560,6 +561,15 @@ size_t carve(const ibm_case *c, const HostGeom &h, char *base, Layout &L)
     L.plan_geo = cv.take<double>(6 * cap);
     L.plan_mode = cv.take<int32_t>(cap);
     L.rmap = cv.take<int32_t>(cap);
+    {
+        size_t ntile = h.tiles_far.size() + h.tiles_near.size(), nslot = h.tiles_near.size();
+        size_t stride = (size_t)tile_load_cells(nd);
+        L.tile_slot = cv.take<int32_t>(std::max<size_t>(ntile, 1));
+        L.slot_tile = cv.take<int32_t>(std::max<size_t>(nslot, 1));
+        L.tg_cnt = cv.take<int32_t>(std::max<size_t>(nslot, 1));
+        L.tg_t = cv.take<int32_t>(std::max<size_t>(nslot * stride, 1));
+        L.tg_rec = cv.take<int32_t>(std::max<size_t>(nslot * stride, 1));
+    }
     L.tiles = cv.take<int32_t>(h.tiles_far.size() + h.tiles_near.size() + 16);
     L.args = cv.take<char>(kSlots * stage_args_bytes());
     size_t st = (size_t)h.vs * (nd + 2);
@@ -624,6 +634,9 @@ int do_classify(ibm_ctx *c, double t, hipStream_t s)
     e = launch_records(c->g, c->b, c->f, c->ib, s);
     if (e != hipSuccess)
         return dev_err(c, e, "records");
+    e = launch_ghost_lists(c->g, c->ib, s);
+    if (e != hipSuccess)
+        return dev_err(c, e, "ghost lists");
     c->classified = true;
     return IBM_OK;
 }
@@ -803,6 +816,20 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     ib.plan_geo = L.plan_geo;
     ib.plan_mode = L.plan_mode;
     ib.rmap = L.rmap;
+    ib.tile_slot = L.tile_slot;
+    ib.slot_tile = L.slot_tile;
+    ib.tg_cnt = L.tg_cnt;
+    ib.tg_t = L.tg_t;
+    ib.tg_rec = L.tg_rec;
+    ib.nslot = (int)h.tiles_near.size();
+    ib.tg_stride = tile_load_cells(nd);
+    {
+        std::vector<int32_t> ts(h.tiles_far.size() + h.tiles_near.size(), -1);
+        for (size_t m = 0; m < h.tiles_near.size(); ++m)
+            ts[h.tiles_near[m]] = (int32_t)m;
+        if (e == hipSuccess) e = up(L.tile_slot, ts);
+        if (e == hipSuccess) e = up(L.slot_tile, h.tiles_near);
+    }
     // first launch: far tiles filling half of each CU's resident blocks
     // (measured best on the 1024x512 wedge in both precisions); the near
     // tiles are latency-bound and run with the rest in the second launch

@@ -82,6 +82,14 @@ struct IB {
     double *plan_geo;        // 6 * cap
     int32_t *plan_mode;      // cap: mode1 | mode2 << 4
     int32_t *rmap;           // cap: record index per region cell (IB nodes only)
+    // per near tile ("slot", a tile whose stencils reach the region): the
+    // ghost nodes G1-G3 among the cells it loads, as (tile-local cell,
+    // record); rebuilt after every classification
+    const int32_t *tile_slot;  // slot per tile id, -1 for the other tiles
+    const int32_t *slot_tile;  // tile id per slot
+    int32_t *tg_cnt;           // nslot
+    int32_t *tg_t, *tg_rec;    // nslot * tg_stride
+    int nslot, tg_stride;
 };
 
 // Tiles of the fused residual/update kernel: cells per block along x, y, z.
@@ -112,6 +120,10 @@ struct Motion {
 hipError_t launch_pose(const Grid &g, Body &b, long long disp, int axis, hipStream_t s);
 hipError_t launch_classify(const Grid &g, const Body &b, IB &ib, hipStream_t s);
 hipError_t launch_records(const Grid &g, const Body &b, const Flow &f, IB &ib, hipStream_t s);
+// per near tile ghost lists (after the records)
+hipError_t launch_ghost_lists(const Grid &g, const IB &ib, hipStream_t s);
+// cells a tile's stencils load (tile plus its halo) for this dimension
+int tile_load_cells(int ndim);
 
 // flow.hip
 hipError_t launch_domain_bc(const Grid &g, const Flow &f, double *q, hipStream_t s);

@@ -752,51 +752,42 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
     }
 
     // 1b. inline ghost fill (tiles whose stencils reach the IB region): the
-    //     ghost nodes G1-G3 among the loaded cells take their filled values,
-    //     computed from the stage input, whose FORCING nodes are already
-    //     filled.  Those nodes are first gathered into a block list so that
-    //     each thread fills at most one per pass; a node inside the tile
-    //     also stores the value as its stage output.
+    //     ghost nodes G1-G3 among the loaded cells (the tile's list, built
+    //     after classification) take their filled values, computed from the
+    //     stage input, whose FORCING nodes are already filled; one node per
+    //     thread and pass.  A node inside the tile also stores the value as
+    //     its stage output.
     if constexpr (INLINE_GHOSTS) {
-        __shared__ int gl_n;
-        __shared__ int gl_t[LCELLS];
-        if (tid == 0)
-            gl_n = 0;
-        __syncthreads();
         const IB &ib = A.ib;
-        for (int t = tid; t < LCELLS; t += kBlock) {
-            int lx = t % LX, ly = (t / LX) % LY, lz = t / (LX * LY);
-            int c[3] = {i0 + lx - 3, j0 + ly - 3, k0 + lz - HZ};
-            if (ghost_source<DIM>(g, c))
-                continue;
-            int li = c[0] - ib.region[0], lj = c[1] - ib.region[2], lk = c[2] - ib.region[4];
-            if (li < 0 || li >= ib.rw || lj < 0 || lj >= ib.rh || lk < 0 || lk >= ib.rd)
-                continue;
-            uint8_t kc = A.cls[((long long)c[2] * g.nj + c[1]) * g.ni + c[0]];
-            if (kc >= IBM_G1 && kc <= IBM_G3)
-                gl_t[atomicAdd(&gl_n, 1)] = t;
-        }
-        __syncthreads();
-        int n = gl_n;
-        for (int e = tid; e < n; e += kBlock) {
-            int t = gl_t[e];
-            int lx = t % LX, ly = (t / LX) % LY, lz = t / (LX * LY);
-            int c[3] = {i0 + lx - 3, j0 + ly - 3, k0 + lz - HZ};
-            bool inside = lx >= 3 && lx < 3 + TX && ly >= 3 && ly < 3 + TY && lz >= HZ && lz < HZ + TZ &&
-                          c[0] < g.ni && c[1] < g.nj && (DIM == 2 || c[2] < g.nk);
-            ghost_source<DIM>(g, c);
-            int li = c[0] - ib.region[0], lj = c[1] - ib.region[2], lk = c[2] - ib.region[4];
-            int rec = ib.rmap[(lk * ib.rh + lj) * ib.rw + li];
-            long long s = sidx(g, c[0], c[1], c[2]);
+        int slot = ib.tile_slot[tile];
+        int n = slot >= 0 ? ib.tg_cnt[slot] : 0;
+        for (int e0 = 0; e0 < n; e0 += kBlock) {
+            int e = e0 + tid;
             double qs[NV];
-            if (rec < 0) {  // no record (capacity exceeded, flagged): stored value
+            int t = 0;
+            bool inside = false, filled = false;
+            long long s = 0;
+            if (e < n) {
+                t = ib.tg_t[(long long)slot * ib.tg_stride + e];
+                int rec = ib.tg_rec[(long long)slot * ib.tg_stride + e];
+                int lx = t % LX, ly = (t / LX) % LY, lz = t / (LX * LY);
+                int c[3] = {i0 + lx - 3, j0 + ly - 3, k0 + lz - HZ};
+                inside = lx >= 3 && lx < 3 + TX && ly >= 3 && ly < 3 + TY && lz >= HZ && lz < HZ + TZ &&
+                         c[0] < g.ni && c[1] < g.nj && (DIM == 2 || c[2] < g.nk);
+                ghost_source<DIM>(g, c);
+                s = sidx(g, c[0], c[1], c[2]);
+                if (rec < 0) {  // no record (capacity exceeded, flagged): stored value
 #pragma unroll
-                for (int m = 0; m < NV; ++m)
-                    qs[m] = A.qin[s + m * g.vs];
-            } else {
-                node_fill<DIM>(g, f, ib, A.qin, rec, A.ub, A.ab, A.axis, qs);
-                put(t, qs);
+                    for (int m = 0; m < NV; ++m)
+                        qs[m] = A.qin[s + m * g.vs];
+                } else {
+                    node_fill<DIM>(g, f, ib, A.qin, rec, A.ub, A.ab, A.axis, qs);
+                    filled = true;
+                }
             }
+            __syncthreads();  // the loaded values are in LDS before they are replaced
+            if (filled)
+                put(t, qs);
             if (inside) {
 #pragma unroll
                 for (int m = 0; m < NV; ++m)
@@ -1056,6 +1047,43 @@ __global__ __launch_bounds__(kBlock) void step_batch_kernel(BatchArgs B)
     const ConstArgs *ap = (const ConstArgs *)(((unsigned long long)phi << 32) | plo);
     int first = __builtin_amdgcn_readfirstlane(B.off[lo]);
     step_body<DIM, Real, MODE, GHOSTS>(*(const StepArgs *)ap, b - first);
+}
+
+// Ghost lists of the near tiles: block p scans the cells tile slot_tile[p]
+// loads (tile plus halo, domain ghost cells resolved as the stencils do) and
+// lists those that are ghost nodes G1-G3, with their records.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void ghost_lists_kernel(Grid g, IB ib, int ntx, int nty)
+{
+    using C = TileCfg<DIM>;
+    constexpr int TX = C::TX, TY = C::TY, TZ = C::TZ, HZ = C::HZ;
+    constexpr int LX = TX + 6, LY = TY + 6, LZ = TZ + 2 * HZ;
+    constexpr int LCELLS = LX * LY * LZ;
+    __shared__ int n;
+    if (threadIdx.x == 0)
+        n = 0;
+    __syncthreads();
+    int slot = blockIdx.x;
+    int tile = ib.slot_tile[slot];
+    int i0 = (tile % ntx) * TX, j0 = ((tile / ntx) % nty) * TY, k0 = (tile / (ntx * nty)) * TZ;
+    for (int t = threadIdx.x; t < LCELLS; t += kBlock) {
+        int lx = t % LX, ly = (t / LX) % LY, lz = t / (LX * LY);
+        int c[3] = {i0 + lx - 3, j0 + ly - 3, k0 + lz - HZ};
+        if (ghost_source<DIM>(g, c))
+            continue;
+        int li = c[0] - ib.region[0], lj = c[1] - ib.region[2], lk = c[2] - ib.region[4];
+        if (li < 0 || li >= ib.rw || lj < 0 || lj >= ib.rh || lk < 0 || lk >= ib.rd)
+            continue;
+        uint8_t kc = ib.cls[((long long)c[2] * g.nj + c[1]) * g.ni + c[0]];
+        if (kc < IBM_G1 || kc > IBM_G3)
+            continue;
+        int e = atomicAdd(&n, 1);
+        ib.tg_t[(long long)slot * ib.tg_stride + e] = t;
+        ib.tg_rec[(long long)slot * ib.tg_stride + e] = ib.rmap[(lk * ib.rh + lj) * ib.rw + li];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        ib.tg_cnt[slot] = n;
 }
 
 // Q'^{n-1} <- Q'^n (at the first step Q'^{n-1} <- Q(W) - Q_inf too); Q'^n <- Q(W) - Q_inf
@@ -1346,6 +1374,26 @@ hipError_t launch_stage_batch(int ndim, int precision, int scheme, bool ghosts, 
     if (rk)
         return mixed ? batch_launch<3, float, MODE_RK3>(B, ghosts, s) : batch_launch<3, double, MODE_RK3>(B, ghosts, s);
     return mixed ? batch_launch<3, float, MODE_DUAL>(B, ghosts, s) : batch_launch<3, double, MODE_DUAL>(B, ghosts, s);
+}
+
+int tile_load_cells(int ndim)
+{
+    const int *T = ndim == 2 ? kTile2 : kTile3;
+    int hz = ndim == 2 ? 0 : 3;
+    return (T[0] + 6) * (T[1] + 6) * (T[2] + 2 * hz);
+}
+
+hipError_t launch_ghost_lists(const Grid &g, const IB &ib, hipStream_t s)
+{
+    if (ib.nslot == 0 || ib.cap == 0)
+        return hipSuccess;
+    const int *T = g.ndim == 2 ? kTile2 : kTile3;
+    int ntx = (g.ni + T[0] - 1) / T[0], nty = (g.nj + T[1] - 1) / T[1];
+    if (g.ndim == 2)
+        hipLaunchKernelGGL(ghost_lists_kernel<2>, dim3(ib.nslot), dim3(kBlock), 0, s, g, ib, ntx, nty);
+    else
+        hipLaunchKernelGGL(ghost_lists_kernel<3>, dim3(ib.nslot), dim3(kBlock), 0, s, g, ib, ntx, nty);
+    return hipGetLastError();
 }
 
 int stage_blocks_per_cu(const Grid &g, const Flow &f)
