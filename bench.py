@@ -86,6 +86,8 @@ def _parse():
     ap.add_argument("--precisions", default="mixed,fp64")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-rate", type=float, default=50.0)
+    ap.add_argument("--no-other-configs", action="store_true",
+                    help="skip the cylinder, airfoil and tube workloads")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="also run one plain device copy of 256 MiB (reference for HBM counters)")
     return ap.parse_args()
@@ -104,6 +106,40 @@ def serving(n, rate):
     out.update({"workload": f"{n} seeded 2D solves, Poisson arrivals at {rate:g}/s, grid side "
                             "64-512, 1500 residual evaluations each, mixed precision",
                 "precision": "mixed", "arrival_span_s": reqs[-1][0] if reqs else 0.0})
+    return out
+
+
+def other_configs():
+    """Throughput of the other fixed workloads (whole steps, free-stream
+    start, states resident in HBM): the cylinder for its full 200 steps in
+    FP64, prefixes of the airfoil (dual time, 20 pseudo-iterations per
+    physical step) and of the oscillating tube (moving body, reclassified
+    every step) in both precisions."""
+    import torch
+    import workloads as w
+    import paper_1912_11908_amd as P
+    out = {}
+    plan = [("cylinder 128x128, M=0.3, Re=40, RK3, 200 steps", w.case_c1(), ("fp64",), 200),
+            ("NACA0012 2048x1024, M=0.001, Re=1000, dual time, 10 physical steps", w.case_c3(),
+             ("mixed", "fp64"), 10),
+            ("oscillating tube 384x256x64, M=0.2, Re=185, RK3, moving, 50 steps", w.case_c4(),
+             ("mixed", "fp64"), 50)]
+    for name, case, precs, steps in plan:
+        for prec in precs:
+            prim = w.freestream_prim(case.ndim, case.ni, case.nj, case.nk, case.p_inf)
+            s = P.Solver(case, prec, "cuda:0")
+            s.init_prim(prim)
+            s.advance(1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.advance(steps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            s.check_status()
+            out[f"{name} [{prec}]"] = {
+                "cell_updates_per_s": case.ncells * case.evals_per_step * steps / dt,
+                "ms_per_step": dt * 1e3 / steps}
+            del s
     return out
 
 
@@ -225,6 +261,8 @@ def main():
         a, b = res["mixed"]["prim"], f["prim"]
         errs = [float(np.sqrt(np.sum((a[v] - b[v]) ** 2) / np.sum(b[v] ** 2))) for v in range(4)]
         out["mixed_vs_fp64_rel_l2"] = {"rho": errs[0], "u": errs[1], "v": errs[2], "p": errs[3]}
+    if not args.no_other_configs:
+        out["other_configs"] = other_configs()
     if args.calibration_copy:
         src = torch.ones(32 << 20, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)
