@@ -94,7 +94,9 @@ struct IB {
 
 // Tiles of the fused residual/update kernel: cells per block along x, y, z.
 constexpr int kTile2[3] = {16, 15, 1};  // 255 x-faces, 256 y-faces: one pass each
-constexpr int kTile3[3] = {8, 8, 4};
+constexpr int kTile3[3] = {8, 7, 8};  // 504, 512, 504 faces: one pass each for 512 threads
+// threads per block of the fused kernel: 2D 256, 3D 512
+constexpr int kThreads2 = 256, kThreads3 = 512;
 
 // One launch of the fused residual/update kernel for a stage: a list of
 // tiles (null: every tile of the grid) and what the launch also fills.  A

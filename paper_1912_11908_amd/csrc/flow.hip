@@ -200,8 +200,8 @@ __device__ inline void prim_of_state(const Flow &f, const double *qv, double &rh
 }
 
 template <int DIM>
-__device__ void node_fill(const Grid &g, const Flow &f, const IB &ib, const double *q, int r, double ub,
-                          double ab, int axis, double *qs);
+__device__ inline void node_fill(const Grid &g, const Flow &f, const IB &ib, const double *q, int r, double ub,
+                                 double ab, int axis, double *qs);
 
 // value at probe `p` (0 or 1) of record r: weighted sum of (p, u.., T) over
 // the plan's corners (unused corners carry zero weight)
@@ -237,7 +237,7 @@ __device__ inline void plan_probe(const Grid &g, const Flow &f, const IB &ib, co
 // State value qs of IB record r (its plan and the node's boundary
 // conditions) from the cells of q.
 template <int DIM>
-__device__ void node_fill(const Grid &g, const Flow &f, const IB &ib, const double *q, int r, double ub,
+__device__ inline void node_fill(const Grid &g, const Flow &f, const IB &ib, const double *q, int r, double ub,
                           double ab, int axis, double *qs)
 {
     constexpr int NV = DIM + 2;
@@ -314,7 +314,7 @@ __device__ void node_fill(const Grid &g, const Flow &f, const IB &ib, const doub
 
 // fill record r of q in place from the values stored in q
 template <int DIM>
-__device__ inline void fill_one(const Grid &g, const Flow &f, const IB &ib, double *q, int r, double ub,
+__device__ __forceinline__ void fill_one(const Grid &g, const Flow &f, const IB &ib, double *q, int r, double ub,
                                 double ab, int axis)
 {
     double qs[DIM + 2];
@@ -349,10 +349,10 @@ __global__ void ghost_fill_kernel(Grid g, Flow f, IB ib, double *q, double ub, d
 // ------------------------------------------------ fused residual / update
 template <int DIM> struct TileCfg;
 template <> struct TileCfg<2> {
-    static constexpr int TX = kTile2[0], TY = kTile2[1], TZ = kTile2[2], HZ = 0;
+    static constexpr int TX = kTile2[0], TY = kTile2[1], TZ = kTile2[2], HZ = 0, NT = kThreads2;
 };
 template <> struct TileCfg<3> {
-    static constexpr int TX = kTile3[0], TY = kTile3[1], TZ = kTile3[2], HZ = 3;
+    static constexpr int TX = kTile3[0], TY = kTile3[1], TZ = kTile3[2], HZ = 3, NT = kThreads3;
 };
 
 enum { MODE_RESID = 0, MODE_RK3 = 1, MODE_DUAL = 2 };
@@ -616,7 +616,8 @@ __device__ inline void face_pass(const Real *__restrict__ S, Real *__restrict__ 
     constexpr int NV = DIM + 2;
     constexpr int FX = TX + (D == 0), FY = TY + (D == 1), FZ = TZ + (D == 2);
     constexpr int NF = FX * FY * FZ;
-    for (int fi = tid; fi < NF; fi += kBlock) {
+    constexpr int NT = TileCfg<DIM>::NT;
+    for (int fi = tid; fi < NF; fi += NT) {
         int fx = fi % FX, fy = (fi / FX) % FY, fz = fi / (FX * FY);
         int lc[3] = {fx - (D == 0), fy - (D == 1), fz - (D == 2)};
         int gc[3] = {i0 + lc[0], j0 + lc[1], k0 + lc[2]};
@@ -641,7 +642,7 @@ template <int DIM, typename Real, int MODE, bool INLINE_GHOSTS>
 __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bid)
 {
     using C = TileCfg<DIM>;
-    constexpr int TX = C::TX, TY = C::TY, TZ = C::TZ, HZ = C::HZ;
+    constexpr int TX = C::TX, TY = C::TY, TZ = C::TZ, HZ = C::HZ, NT = C::NT;
     constexpr int LX = TX + 6, LY = TY + 6, LZ = TZ + 2 * HZ;
     constexpr int NV = DIM + 2;          // conserved variables
     constexpr int NS = DIM + 3;          // rho', u.., p', T'
@@ -649,7 +650,11 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
     constexpr int NF0 = (TX + 1) * TY * TZ;
     constexpr int NF1 = TX * (TY + 1) * TZ;
     constexpr int NF2 = DIM == 3 ? TX * TY * (TZ + 1) : 0;
-    constexpr int NFACE = NF0 + NF1 + NF2;
+    // 3D keeps the fluxes of one direction at a time (the residual
+    // accumulates per cell in registers), 2D all of them
+    constexpr bool SPLIT = DIM == 3;
+    constexpr int NFMAX = NF0 > NF1 ? (NF0 > NF2 ? NF0 : NF2) : (NF1 > NF2 ? NF1 : NF2);
+    constexpr int NFACE = SPLIT ? NFMAX : NF0 + NF1 + NF2;
     __shared__ Real S[NS * LCELLS];
     __shared__ Real F[NV * NFACE];
 
@@ -660,7 +665,7 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
         // (grid-stride); the tiles of such a launch never read those nodes
         if (bid < A.nfill) {
             int nF = min(A.ib.counts[CNT_F], A.ib.cap);
-            for (int r = bid * kBlock + threadIdx.x; r < nF; r += A.nfill * kBlock)
+            for (int r = bid * NT + threadIdx.x; r < nF; r += A.nfill * NT)
                 fill_one<DIM>(g, f, A.ib, A.qin, r, A.ub, A.ab, A.axis);
             return;
         }
@@ -681,8 +686,8 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
     int tx0 = tile % A.ntx, ty0 = (tile / A.ntx) % A.nty, tz0 = tile / (A.ntx * A.nty);
     int i0 = tx0 * TX, j0 = ty0 * TY, k0 = tz0 * TZ;
     int tid = threadIdx.x;
-    constexpr int NCELL = TX * TY * TZ;  // <= kBlock
-    static_assert(NCELL <= kBlock, "one thread per tile cell");
+    constexpr int NCELL = TX * TY * TZ;
+    static_assert(NCELL <= NT, "one thread per tile cell");
 
 
     // perturbation primitives of state values qv into LDS cell t
@@ -719,13 +724,13 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
     // 1. load the tile and its 3-cell halo, recovering (rho', u.., p', T');
     //    domain ghost cells are resolved on the fly.  Two rounds of loads
     //    are issued before either is converted.
-    constexpr int NR = (LCELLS + kBlock - 1) / kBlock;
+    constexpr int NR = (LCELLS + NT - 1) / NT;
     constexpr int NB = NR < 2 ? NR : 2;
     for (int r0 = 0; r0 < NR; r0 += NB) {
         double qv[NB][NV];
 #pragma unroll
         for (int rr = 0; rr < NB; ++rr) {
-            int t = tid + (r0 + rr) * kBlock;
+            int t = tid + (r0 + rr) * NT;
             if (r0 + rr >= NR || t >= LCELLS)
                 continue;
             int lx = t % LX, ly = (t / LX) % LY, lz = t / (LX * LY);
@@ -744,7 +749,7 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
         }
 #pragma unroll
         for (int rr = 0; rr < NB; ++rr) {
-            int t = tid + (r0 + rr) * kBlock;
+            int t = tid + (r0 + rr) * NT;
             if (r0 + rr >= NR || t >= LCELLS)
                 continue;
             put(t, qv[rr]);
@@ -761,7 +766,7 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
         const IB &ib = A.ib;
         int slot = ib.tile_slot[tile];
         int n = slot >= 0 ? ib.tg_cnt[slot] : 0;
-        for (int e0 = 0; e0 < n; e0 += kBlock) {
+        for (int e0 = 0; e0 < n; e0 += NT) {
             int e = e0 + tid;
             double qs[NV];
             int t = 0;
@@ -827,11 +832,58 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
     fp.uc2 = (Real)f.uc2;
     fp.precond = f.scheme == IBM_DUAL;
     // 2. face fluxes, one pass per direction (compile-time direction)
-    face_pass<DIM, 0, Real, TX, TY, TZ, HZ>(S, F, NFACE, 0, i0, j0, k0, g, fp, tid);
-    face_pass<DIM, 1, Real, TX, TY, TZ, HZ>(S, F, NFACE, NF0, i0, j0, k0, g, fp, tid);
-    if constexpr (DIM == 3)
-        face_pass<DIM, 2, Real, TX, TY, TZ, HZ>(S, F, NFACE, NF0 + NF1, i0, j0, k0, g, fp, tid);
-    __syncthreads();
+    int fl0 = (tz * TY + ty) * (TX + 1) + tx;  // x-face at i - 1/2
+    int fl1 = (tz * (TY + 1) + ty) * TX + tx;  // y-face at j - 1/2
+    int fl2 = (tz * TY + ty) * TX + tx;        // z-face at k - 1/2
+    // threads without a cell of their own (past the tile's cells or the
+    // grid) touch neither metrics nor fluxes
+    Real rd[3] = {Real(0), Real(0), Real(0)};
+    if (own) {
+        rd[0] = metric<Real>(g.rdx[0], g.rdx_f[0], i + 3);
+        rd[1] = metric<Real>(g.rdx[1], g.rdx_f[1], j + 3);
+        if (DIM == 3)
+            rd[2] = metric<Real>(g.rdx[2], g.rdx_f[2], k + 3);
+    }
+    Real racc[NV];
+#pragma unroll
+    for (int m = 0; m < NV; ++m)
+        racc[m] = Real(0);
+    if constexpr (SPLIT) {
+        face_pass<DIM, 0, Real, TX, TY, TZ, HZ>(S, F, NFACE, 0, i0, j0, k0, g, fp, tid);
+        __syncthreads();
+        if (own) {
+#pragma unroll
+            for (int m = 0; m < NV; ++m)
+                racc[m] = (F[m * NFACE + fl0 + 1] - F[m * NFACE + fl0]) * rd[0];
+        }
+        __syncthreads();
+        face_pass<DIM, 1, Real, TX, TY, TZ, HZ>(S, F, NFACE, 0, i0, j0, k0, g, fp, tid);
+        __syncthreads();
+        if (own) {
+#pragma unroll
+            for (int m = 0; m < NV; ++m)
+                racc[m] += (F[m * NFACE + fl1 + TX] - F[m * NFACE + fl1]) * rd[1];
+        }
+        __syncthreads();
+        face_pass<DIM, 2, Real, TX, TY, TZ, HZ>(S, F, NFACE, 0, i0, j0, k0, g, fp, tid);
+        __syncthreads();
+        if (own) {
+#pragma unroll
+            for (int m = 0; m < NV; ++m)
+                racc[m] += (F[m * NFACE + fl2 + TX * TY] - F[m * NFACE + fl2]) * rd[2];
+        }
+    } else {
+        face_pass<DIM, 0, Real, TX, TY, TZ, HZ>(S, F, NFACE, 0, i0, j0, k0, g, fp, tid);
+        face_pass<DIM, 1, Real, TX, TY, TZ, HZ>(S, F, NFACE, NF0, i0, j0, k0, g, fp, tid);
+        __syncthreads();
+        if (own) {
+#pragma unroll
+            for (int m = 0; m < NV; ++m) {
+                const Real *Fm = F + m * NFACE;
+                racc[m] = (Fm[fl0 + 1] - Fm[fl0]) * rd[0] + (Fm[NF0 + fl1 + TX] - Fm[NF0 + fl1]) * rd[1];
+            }
+        }
+    }
 
     // 3. per-cell residual and update
     if (!own)
@@ -852,22 +904,10 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
             A.out[m * g.ncell + cell] = 0.0;
         return;
     }
-    int fl0 = (tz * TY + ty) * (TX + 1) + tx;        // x-face at i - 1/2
-    int fl1 = NF0 + (tz * (TY + 1) + ty) * TX + tx;  // y-face at j - 1/2
-    int fl2 = NF0 + NF1 + (tz * TY + ty) * TX + tx;  // z-face at k - 1/2
-    Real rd[3];
-    rd[0] = metric<Real>(g.rdx[0], g.rdx_f[0], i + 3);
-    rd[1] = metric<Real>(g.rdx[1], g.rdx_f[1], j + 3);
-    rd[2] = DIM == 3 ? metric<Real>(g.rdx[2], g.rdx_f[2], k + 3) : Real(0);
     double R[NV];
 #pragma unroll
-    for (int m = 0; m < NV; ++m) {
-        const Real *Fm = F + m * NFACE;
-        Real r = (Fm[fl0 + 1] - Fm[fl0]) * rd[0] + (Fm[fl1 + TX] - Fm[fl1]) * rd[1];
-        if (DIM == 3)
-            r += (Fm[fl2 + TX * TY] - Fm[fl2]) * rd[2];
-        R[m] = (double)r;
-    }
+    for (int m = 0; m < NV; ++m)
+        R[m] = (double)racc[m];
     R[NV - 1] += f.Hinf * R[0];
 
     if (MODE == MODE_RESID) {
@@ -1004,13 +1044,13 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
 }
 
 template <int DIM, typename Real, int MODE>
-__global__ __launch_bounds__(kBlock) void step_kernel(StepArgs A)
+__global__ __launch_bounds__(TileCfg<DIM>::NT) void step_kernel(StepArgs A)
 {
     step_body<DIM, Real, MODE, false>(A, blockIdx.x);
 }
 
 template <int DIM, typename Real, int MODE>
-__global__ __launch_bounds__(kBlock) void step_ghost_kernel(StepArgs A)
+__global__ __launch_bounds__(TileCfg<DIM>::NT) void step_ghost_kernel(StepArgs A)
 {
     step_body<DIM, Real, MODE, true>(A, blockIdx.x);
 }
@@ -1024,7 +1064,7 @@ struct BatchArgs {
 };
 
 template <int DIM, typename Real, int MODE, bool GHOSTS>
-__global__ __launch_bounds__(kBlock) void step_batch_kernel(BatchArgs B)
+__device__ __forceinline__ void batch_body(const BatchArgs &B)
 {
     int b = blockIdx.x;
     int lo = 0, hi = B.n - 1;  // the m with off[m] <= b < off[m + 1]
@@ -1036,17 +1076,67 @@ __global__ __launch_bounds__(kBlock) void step_batch_kernel(BatchArgs B)
             hi = mid - 1;
     }
     // the solve, its argument block and its first block are the same for
-    // every lane: keep them in scalar registers, so the argument loads are
-    // scalar too (the arguments are read-only for the whole launch)
+    // every lane: keep them in scalar registers, and read the block (never
+    // written during a launch) through the constant address space, so the
+    // argument loads are scalar too
     lo = __builtin_amdgcn_readfirstlane(lo);
     unsigned long long pa = reinterpret_cast<unsigned long long>(B.args[lo]);
     unsigned plo = __builtin_amdgcn_readfirstlane((unsigned)pa);
     unsigned phi = __builtin_amdgcn_readfirstlane((unsigned)(pa >> 32));
-    // constant address space: the block is never written during a launch
     using ConstArgs = __attribute__((address_space(4))) const StepArgs;
     const ConstArgs *ap = (const ConstArgs *)(((unsigned long long)phi << 32) | plo);
     int first = __builtin_amdgcn_readfirstlane(B.off[lo]);
     step_body<DIM, Real, MODE, GHOSTS>(*(const StepArgs *)ap, b - first);
+}
+
+template <int DIM, typename Real, int MODE, bool GHOSTS>
+__global__ __launch_bounds__(TileCfg<DIM>::NT) void step_batch_kernel(BatchArgs B)
+{
+    batch_body<DIM, Real, MODE, GHOSTS>(B);
+}
+
+// 3D FP32: the tile fits two 512-thread blocks per CU in LDS (four waves
+// per SIMD), which leaves 128 registers per lane; the budget is stated
+// (left to itself the compiler takes more and halves the occupancy).
+template <int MODE>
+__global__ __launch_bounds__(kThreads3) __attribute__((amdgpu_num_vgpr(128))) void step_kernel_3f(StepArgs A)
+{
+    step_body<3, float, MODE, false>(A, blockIdx.x);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads3) __attribute__((amdgpu_num_vgpr(128))) void step_ghost_kernel_3f(StepArgs A)
+{
+    step_body<3, float, MODE, true>(A, blockIdx.x);
+}
+
+template <int MODE, bool GHOSTS>
+__global__ __launch_bounds__(kThreads3) __attribute__((amdgpu_num_vgpr(128))) void step_batch_kernel_3f(BatchArgs B)
+{
+    batch_body<3, float, MODE, GHOSTS>(B);
+}
+
+// the kernel of each launch kind for (DIM, Real, MODE)
+template <int DIM, typename Real, int MODE> constexpr auto plain_kernel()
+{
+    if constexpr (DIM == 3 && sizeof(Real) == 4)
+        return &step_kernel_3f<MODE>;
+    else
+        return &step_kernel<DIM, Real, MODE>;
+}
+template <int DIM, typename Real, int MODE> constexpr auto ghost_kernel()
+{
+    if constexpr (DIM == 3 && sizeof(Real) == 4)
+        return &step_ghost_kernel_3f<MODE>;
+    else
+        return &step_ghost_kernel<DIM, Real, MODE>;
+}
+template <int DIM, typename Real, int MODE, bool GHOSTS> constexpr auto batch_kernel()
+{
+    if constexpr (DIM == 3 && sizeof(Real) == 4)
+        return &step_batch_kernel_3f<MODE, GHOSTS>;
+    else
+        return &step_batch_kernel<DIM, Real, MODE, GHOSTS>;
 }
 
 // Ghost lists of the near tiles: block p scans the cells tile slot_tile[p]
@@ -1206,7 +1296,7 @@ StepArgs make_args(const Grid &g, const Flow &f, const IB &ib, double *qin, cons
     A.fs = freestream_of(g, f);
     int nt = A.tiles ? A.ntiles : A.ntx * A.nty * A.ntz;
     if (!resid && part && part->fill_forcing && ib.cap > 0) {
-        int nb = blocks_for(ib.cap, kBlock);
+        int nb = blocks_for(ib.cap, TileCfg<DIM>::NT);
         nb = nb < 64 ? nb : 64;
         A.nfill = (nb + 7) / 8 * 8;
     }
@@ -1225,11 +1315,11 @@ hipError_t run_step(const Grid &g, const Flow &f, const IB &ib, double *qin, con
         return hipSuccess;
     if constexpr (MODE != MODE_RESID) {
         if (part && part->inline_ghosts && ib.cap > 0) {
-            hipLaunchKernelGGL((step_ghost_kernel<DIM, Real, MODE>), dim3(nblk), dim3(kBlock), 0, s, A);
+            hipLaunchKernelGGL((ghost_kernel<DIM, Real, MODE>()), dim3(nblk), dim3(TileCfg<DIM>::NT), 0, s, A);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((step_kernel<DIM, Real, MODE>), dim3(nblk), dim3(kBlock), 0, s, A);
+    hipLaunchKernelGGL((plain_kernel<DIM, Real, MODE>()), dim3(nblk), dim3(TileCfg<DIM>::NT), 0, s, A);
     return hipGetLastError();
 }
 
@@ -1344,9 +1434,9 @@ hipError_t batch_launch(const BatchArgs &B, bool ghosts, hipStream_t s)
 {
     int nblk = B.off[B.n];
     if (ghosts)
-        hipLaunchKernelGGL((step_batch_kernel<DIM, Real, MODE, true>), dim3(nblk), dim3(kBlock), 0, s, B);
+        hipLaunchKernelGGL((batch_kernel<DIM, Real, MODE, true>()), dim3(nblk), dim3(TileCfg<DIM>::NT), 0, s, B);
     else
-        hipLaunchKernelGGL((step_batch_kernel<DIM, Real, MODE, false>), dim3(nblk), dim3(kBlock), 0, s, B);
+        hipLaunchKernelGGL((batch_kernel<DIM, Real, MODE, false>()), dim3(nblk), dim3(TileCfg<DIM>::NT), 0, s, B);
     return hipGetLastError();
 }
 
@@ -1402,15 +1492,15 @@ int stage_blocks_per_cu(const Grid &g, const Flow &f)
     bool mixed = f.precision == IBM_MIXED, rk = f.scheme == IBM_RK3;
     hipError_t e;
     if (g.ndim == 2)
-        e = mixed ? (rk ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<2, float, MODE_RK3>, kBlock, 0)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<2, float, MODE_DUAL>, kBlock, 0))
-                  : (rk ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<2, double, MODE_RK3>, kBlock, 0)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<2, double, MODE_DUAL>, kBlock, 0));
+        e = mixed ? (rk ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<2, float, MODE_RK3>, kThreads2, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<2, float, MODE_DUAL>, kThreads2, 0))
+                  : (rk ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<2, double, MODE_RK3>, kThreads2, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<2, double, MODE_DUAL>, kThreads2, 0));
     else
-        e = mixed ? (rk ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<3, float, MODE_RK3>, kBlock, 0)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<3, float, MODE_DUAL>, kBlock, 0))
-                  : (rk ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<3, double, MODE_RK3>, kBlock, 0)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<3, double, MODE_DUAL>, kBlock, 0));
+        e = mixed ? (rk ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel_3f<MODE_RK3>, kThreads3, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel_3f<MODE_DUAL>, kThreads3, 0))
+                  : (rk ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<3, double, MODE_RK3>, kThreads3, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<3, double, MODE_DUAL>, kThreads3, 0));
     return e == hipSuccess ? n : 0;
 }
 
