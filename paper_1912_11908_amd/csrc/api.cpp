@@ -158,6 +158,7 @@ struct HostGeom {
     double bin_o[3], bin_h;
     int bin_n[3], nbin;
     std::vector<int32_t> bin_start, bin_facet;
+    std::vector<double> fbox;
 };
 
 // Uniform bins over the rest-pose body box for the 3D closest-feature and
@@ -174,9 +175,21 @@ void facet_bins(HostGeom &h, const std::vector<double> &v)
     }
     h.bin_start.assign(1, 0);
     h.bin_facet.clear();
+    h.fbox.clear();
     int nf = (int)(h.facet.size() / 3);
     if (h.nd != 3 || nf == 0)
         return;
+    h.fbox.assign((size_t)6 * nf, 0.0);
+    for (int f = 0; f < nf; ++f)
+        for (int d = 0; d < 3; ++d) {
+            double fl = 1e300, fh = -1e300;
+            for (int m = 0; m < 3; ++m) {
+                fl = std::min(fl, v[3 * h.facet[3 * f + m] + d]);
+                fh = std::max(fh, v[3 * h.facet[3 * f + m] + d]);
+            }
+            h.fbox[6 * f + d] = fl;
+            h.fbox[6 * f + 3 + d] = fh;
+        }
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (size_t m = 0; m < v.size() / 3; ++m)
         for (int d = 0; d < 3; ++d) {
@@ -503,6 +516,7 @@ struct Layout {
     double *fnrm, *vnrm, *enrm;
     int *edge_of;
     int32_t *bin_start, *bin_facet;
+    double *fbox;
     uint8_t *cls, *inside;
     uint32_t *toggle;
     int32_t *counts, *blk, *listF, *listG, *rec_i;
@@ -544,6 +558,7 @@ size_t carve(const ibm_case *c, const HostGeom &h, char *base, Layout &L)
     L.edge_of = cv.take<int>(nfx * 3);
     L.bin_start = cv.take<int32_t>(h.bin_start.size());
     L.bin_facet = cv.take<int32_t>(std::max<size_t>(h.bin_facet.size(), 1));
+    L.fbox = cv.take<double>(std::max<size_t>(h.fbox.size(), 1));
     size_t cap = (size_t)std::max(h.cap, 1);
     int rows = (h.region[3] - h.region[2]) * (h.region[5] - h.region[4]);
     L.cls = cv.take<uint8_t>(h.ncell);
@@ -756,8 +771,10 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     b.nbin = h.nbin;
     b.bin_start = L.bin_start;
     b.bin_facet = L.bin_facet;
+    b.fbox = L.fbox;
     if (e == hipSuccess) e = up(L.bin_start, h.bin_start);
     if (e == hipSuccess) e = up(L.bin_facet, h.bin_facet);
+    if (e == hipSuccess && !h.fbox.empty()) e = up(L.fbox, h.fbox);
     if (e == hipSuccess) e = up(L.V0, h.V0);
     if (e == hipSuccess) e = up(L.V, h.V0);
     if (e == hipSuccess) e = up(L.v, h.v0);

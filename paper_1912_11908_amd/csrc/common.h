@@ -50,6 +50,7 @@ struct Body {
     double bin_o[3], bin_h;
     int bin_n[3], nbin;
     const int *bin_start, *bin_facet;
+    const double *fbox;      // per facet: rest-frame bounding box lo[3], hi[3]
     double disp[3];          // current displacement of the pose (exact)
 };
 

@@ -559,15 +559,85 @@ __device__ inline Closest facet_closest(const Body &b, const double *p, int f)
 // bin index of rest-frame coordinate y along axis d (may lie outside the grid)
 __device__ inline int bin_of(const Body &b, int d, double y) { return (int)floor((y - b.bin_o[d]) / b.bin_h); }
 
+// Visits the facets listed in the bins of the box lo..lo+ext-1 (clipped to
+// the bin grid; with shell >= 0 only the bins on the surface of the cube of
+// half-width shell around lo + shell), spread over the whole wavefront:
+// lane l reads the range of the box's bin l of each group of 64, a prefix
+// sum over the lanes numbers the group's entries, and every lane takes
+// every 64th entry, finding its bin by bisection over the sums in LDS.
+// A facet listed in several bins is visited once per listing.
+// Wavefront-uniform control flow; `nb` (the sums) and `st` (the bin
+// starts) are this wavefront's 64-entry LDS slices.
+template <typename Visit>
+__device__ inline void visit_bins(const Body &b, const int *lo, const int *ext, int shell, int lane, int *nb,
+                                  int *st, Visit &&visit)
+{
+    int nbox = ext[0] * ext[1] * ext[2];
+    for (int base = 0; base < nbox; base += kWave) {
+        int e = base + lane, s = 0, n = 0;
+        if (e < nbox) {
+            int ex = e % ext[0], ey = (e / ext[0]) % ext[1], ez = e / (ext[0] * ext[1]);
+            bool on = shell < 0 || max(abs(ex - shell), max(abs(ey - shell), abs(ez - shell))) == shell;
+            int kx = lo[0] + ex, ky = lo[1] + ey, kz = lo[2] + ez;
+            if (on && kx >= 0 && kx < b.bin_n[0] && ky >= 0 && ky < b.bin_n[1] && kz >= 0 && kz < b.bin_n[2]) {
+                int bin = (kz * b.bin_n[1] + ky) * b.bin_n[0] + kx;
+                s = b.bin_start[bin];
+                n = b.bin_start[bin + 1] - s;
+            }
+        }
+        int incl = n;
+        for (int o = 1; o < kWave; o <<= 1) {
+            int t = __shfl_up(incl, o, kWave);
+            if (lane >= o)
+                incl += t;
+        }
+        int total = __shfl(incl, kWave - 1, kWave);
+        if (total == 0)
+            continue;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        nb[lane] = incl;
+        st[lane] = s - (incl - n);  // entry of item t of this bin: st + t
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int t = lane; t < total; t += kWave) {
+            int l0 = 0, l1 = kWave - 1;  // first lane whose sum exceeds t
+            while (l0 < l1) {
+                int mid = (l0 + l1) >> 1;
+                if (nb[mid] > t)
+                    l1 = mid;
+                else
+                    l0 = mid + 1;
+            }
+            visit(b.bin_facet[st[l0] + t]);
+        }
+    }
+}
+
+// squared distance from rest-frame point y to facet f's bounding box
+__device__ inline double box_dist2(const Body &b, const double *y, int f)
+{
+    const double *bx = b.fbox + 6 * f;
+    double s = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        double u = fmax(fmax(bx[d] - y[d], y[d] - bx[3 + d]), 0.0);
+        s += u * u;
+    }
+    return s;
+}
+
 // The brute-force minimum over all facets, smallest squared distance first
 // and the lowest facet id among equals.  With bins, cubic shells of bins
-// around the node are searched outwards: after the shells up to K every
-// facet closer than (K - 1) bin sides has been examined (one side of slack
-// for the rounding of the node's own bin), so the search stops there with
-// the same result as the brute force.
-// Called by a whole wavefront for one node: lanes split the facets of
-// each bin, and the shells end on the wavefront's minimum.
-__device__ Closest closest3d(const Body &b, const double *p, int lane)
+// around the node's bin are searched outwards.  A facet not listed in any
+// bin of the shells up to K lies outside their cube, so it is no closer
+// than the node's distance r to the cube's surface: once the minimum so far
+// is below r (less a margin far above rounding) the search stops with the
+// brute-force result.  Within a shell a facet whose bounding box is farther
+// than the lane's minimum so far (by the same margin) cannot win or tie and
+// is skipped.  Called by a whole wavefront for one node: lanes split the
+// facets of each shell, and every shell ends on the wavefront's minimum.
+__device__ Closest closest3d(const Body &b, const double *p, int lane, int *nb, int *st)
 {
     Closest best;
     best.d2 = __builtin_inf();
@@ -578,39 +648,36 @@ __device__ Closest closest3d(const Body &b, const double *p, int lane)
             keep(best, facet_closest(b, p, f));
         return wave_min(best);
     }
+    double y[3];
     int ic[3], far = 0;
     for (int d = 0; d < 3; ++d) {
-        ic[d] = bin_of(b, d, p[d] - b.disp[d]);
+        y[d] = p[d] - b.disp[d];
+        ic[d] = bin_of(b, d, y[d]);
         far = max(far, max(ic[d], b.bin_n[d] - 1 - ic[d]));
     }
+    double margin = 1e-9 * b.bin_h;
     for (int K = 0; K <= far; ++K) {
-        for (int dz = -K; dz <= K; ++dz) {
-            int kz = ic[2] + dz;
-            if (kz < 0 || kz >= b.bin_n[2])
-                continue;
-            for (int dy = -K; dy <= K; ++dy) {
-                int ky = ic[1] + dy;
-                if (ky < 0 || ky >= b.bin_n[1])
-                    continue;
-                bool edge = abs(dz) == K || abs(dy) == K;
-                for (int dx = -K; dx <= K; dx += (edge || K == 0) ? 1 : 2 * K) {
-                    int kx = ic[0] + dx;
-                    if (kx < 0 || kx >= b.bin_n[0])
-                        continue;
-                    int bin = (kz * b.bin_n[1] + ky) * b.bin_n[0] + kx;
-                    for (int m = b.bin_start[bin] + lane; m < b.bin_start[bin + 1]; m += kWave)
-                        keep(best, facet_closest(b, p, b.bin_facet[m]));
-                }
+        int lo[3] = {ic[0] - K, ic[1] - K, ic[2] - K}, ext[3] = {2 * K + 1, 2 * K + 1, 2 * K + 1};
+        visit_bins(b, lo, ext, K, lane, nb, st, [&](int f) {
+            double bd2 = box_dist2(b, y, f);
+            if (bd2 > best.d2) {
+                double lb = sqrt(bd2) - margin;
+                if (lb > 0.0 && lb * lb > best.d2)
+                    return;
             }
+            keep(best, facet_closest(b, p, f));
+        });
+        best = wave_min(best);
+        double r = __builtin_inf();
+        for (int d = 0; d < 3; ++d) {
+            double c0 = b.bin_o[d] + (ic[d] - K) * b.bin_h, c1 = b.bin_o[d] + (ic[d] + K + 1) * b.bin_h;
+            r = fmin(r, fmin(y[d] - c0, c1 - y[d]));
         }
-        double reach = (K - 1) * b.bin_h;
-        if (K >= 1) {
-            best = wave_min(best);
-            if (best.d2 < reach * reach * (1.0 - 1e-9))
-                break;
-        }
+        r -= margin;
+        if (r > 0.0 && best.d2 < r * r)
+            break;
     }
-    return wave_min(best);
+    return best;
 }
 
 __device__ double line_hit2d(const Body &b, const double *x, const double *dir, double smax, int lane)
@@ -666,7 +733,8 @@ __device__ inline double facet_hit(const Body &b, const double *x, const double 
 // only the bins that meet the segment's bounding box (widened by a little
 // for rounding) are searched: a facet the segment meets is listed in the bin
 // of the meeting point.
-__device__ double line_hit3d(const Body &b, const double *x, const double *dir, double smax, int lane)
+__device__ double line_hit3d(const Body &b, const double *x, const double *dir, double smax, int lane, int *nb,
+                             int *st)
 {
     double best = -1.0;
     if (b.nbin == 0) {
@@ -677,23 +745,18 @@ __device__ double line_hit3d(const Body &b, const double *x, const double *dir, 
         }
         return wave_min_hit(best);
     }
-    int lo[3], hi[3];
+    int lo[3], ext[3];
     for (int d = 0; d < 3; ++d) {
         double y0 = x[d] - b.disp[d], y1 = y0 + smax * dir[d];
         double slack = 1e-9 * b.bin_h;
         lo[d] = max(0, bin_of(b, d, fmin(y0, y1) - slack));
-        hi[d] = min(b.bin_n[d] - 1, bin_of(b, d, fmax(y0, y1) + slack));
+        ext[d] = max(0, min(b.bin_n[d] - 1, bin_of(b, d, fmax(y0, y1) + slack)) - lo[d] + 1);
     }
-    for (int kz = lo[2]; kz <= hi[2]; ++kz)
-        for (int ky = lo[1]; ky <= hi[1]; ++ky)
-            for (int kx = lo[0]; kx <= hi[0]; ++kx) {
-                int bin = (kz * b.bin_n[1] + ky) * b.bin_n[0] + kx;
-                for (int m = b.bin_start[bin] + lane; m < b.bin_start[bin + 1]; m += kWave) {
-                    double sig = facet_hit(b, x, dir, smax, b.bin_facet[m]);
-                    if (sig >= 0.0 && (best < 0.0 || sig < best))
-                        best = sig;
-                }
-            }
+    visit_bins(b, lo, ext, -1, lane, nb, st, [&](int f) {
+        double sig = facet_hit(b, x, dir, smax, f);
+        if (sig >= 0.0 && (best < 0.0 || sig < best))
+            best = sig;
+    });
     return wave_min_hit(best);
 }
 
@@ -794,20 +857,24 @@ __device__ bool probe_setup(const Grid &g, const uint8_t *cls, const double *y, 
 // node parallel to the normal meets the surface, and probes along it.
 // One wavefront per node: every lane follows the same node (the facet
 // searches are split across the lanes); lane 0 writes.
-__device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib, int r, int nF, int lane);
+__device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib, int r, int nF, int lane,
+                            int *nb, int *st);
 
-__global__ void records_kernel(Grid g, Body b, Flow fl, IB ib)
+__global__ __launch_bounds__(kBlock) void records_kernel(Grid g, Body b, Flow fl, IB ib)
 {
+    __shared__ int lds[kBlock / kWave][2][kWave];
     int nF = min(ib.counts[CNT_F], ib.cap);
     int nG = min(ib.counts[CNT_G], ib.cap - nF);
     int lane = threadIdx.x % kWave;
-    int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    int *nb = lds[threadIdx.x / kWave][0], *st = lds[threadIdx.x / kWave][1];
+    int wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
     int nwave = gridDim.x * blockDim.x / kWave;
     for (int r = wave; r < nF + nG; r += nwave)
-        node_record(g, b, fl, ib, r, nF, lane);
+        node_record(g, b, fl, ib, r, nF, lane, nb, st);
 }
 
-__device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib, int r, int nF, int lane)
+__device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib, int r, int nF, int lane,
+                            int *nb, int *st)
 {
     bool forcing = r < nF;
     int c = forcing ? ib.listF[r] : ib.listG[r - nF];
@@ -817,7 +884,7 @@ __device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib
     double h = fmin(g.xf[0][i + 4] - g.xf[0][i + 3], g.xf[1][j + 4] - g.xf[1][j + 3]);
     if (nd == 3)
         h = fmin(h, g.xf[2][k + 4] - g.xf[2][k + 3]);
-    Closest cl = nd == 2 ? closest2d(b, X, lane) : closest3d(b, X, lane);
+    Closest cl = nd == 2 ? closest2d(b, X, lane) : closest3d(b, X, lane, nb, st);
     const double *src = cl.kind == FEAT_FACE ? b.fnrm + 3 * cl.id
                         : cl.kind == FEAT_VERTEX ? b.vnrm + 3 * cl.id
                                                  : b.enrm + 3 * cl.id;
@@ -828,7 +895,7 @@ __device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib
         double dir[3] = {0.0, 0.0, 0.0};
         for (int d = 0; d < nd; ++d)
             dir[d] = forcing ? -n[d] : n[d];
-        double sig = nd == 2 ? line_hit2d(b, X, dir, 4.0 * h, lane) : line_hit3d(b, X, dir, 4.0 * h, lane);
+        double sig = nd == 2 ? line_hit2d(b, X, dir, 4.0 * h, lane) : line_hit3d(b, X, dir, 4.0 * h, lane, nb, st);
         if (sig >= 0.0) {
             for (int d = 0; d < nd; ++d)
                 P[d] = X[d] + sig * dir[d];
