@@ -4,9 +4,9 @@ Workload: the supersonic wedge -- 15 degree half-angle triangle of length 1,
 M = 2, Re = 1e4, 1024 x 512 rectilinear grid (x uniform on [-1, 3], y tanh
 clustered toward the wedge axis with adjacent-width ratio 1.02), SSP-RK3 with
 the compressible (IDW + image point) immersed-boundary family, free-stream
-start.  A step is one RK3 step: three stages, each an IB fill and a fused
-residual + update over every cell (two launches), so one step is
-3 * 1024 * 512 cell-updates.
+start.  A step is one RK3 step: three stages, each one launch of the fused
+residual + update over every cell, whose tiles near the body also fill the
+IB nodes they read, so one step is 3 * 1024 * 512 cell-updates.
 
 The serving workload runs after it: the seeded stream of 2000 independent
 2D solves (grid side 64-512, cylinder / wedge / NACA 00tt, M 0.01-2, Re

@@ -32,8 +32,8 @@ struct ibm_ctx {
     // tile lists of the two stage launches (device): the first holds far
     // tiles only, the second the near tiles spread over the XCD chunks and
     // the remaining far tiles, padded with -1
-    const int32_t *tiles1, *tiles2;
-    int ntiles1, ntiles2;
+    const int32_t *tiles;    // the stage launch's tile list (body present)
+    int ntiles;
     // graph replay of whole steps (stationary bodies): slot 0 holds one
     // step, slot 1 a chunk of kChunk steps
     bool use_graphs;
@@ -521,10 +521,10 @@ struct Layout {
     uint32_t *toggle;
     int32_t *counts, *blk, *listF, *listG, *rec_i;
     double *rec_d;
-    int32_t *plan_node, *plan_off, *plan_mode;
-    double *plan_w, *plan_geo;
+    int32_t *plan_node, *plan_off, *plan_mode, *plan_frec;
+    double *plan_w, *plan_geo, *fval;
     int32_t *rmap;
-    int32_t *tile_slot, *slot_tile, *tg_cnt, *tg_t, *tg_rec;
+    int32_t *tile_slot, *slot_tile, *tg_cnt, *tg_t, *tg_rec, *tj_cnt, *tj_rec;
     int32_t *tiles;
     char *args;
     double *q1, *q2, *wtmp, *qn, *qnm1;
@@ -575,6 +575,8 @@ size_t carve(const ibm_case *c, const HostGeom &h, char *base, Layout &L)
     L.plan_w = cv.take<double>(16 * cap);
     L.plan_geo = cv.take<double>(6 * cap);
     L.plan_mode = cv.take<int32_t>(cap);
+    L.plan_frec = cv.take<int32_t>(16 * cap);
+    L.fval = cv.take<double>((size_t)(nd + 2) * cap);
     L.rmap = cv.take<int32_t>(cap);
     {
         size_t ntile = h.tiles_far.size() + h.tiles_near.size(), nslot = h.tiles_near.size();
@@ -584,6 +586,8 @@ size_t carve(const ibm_case *c, const HostGeom &h, char *base, Layout &L)
         L.tg_cnt = cv.take<int32_t>(std::max<size_t>(nslot, 1));
         L.tg_t = cv.take<int32_t>(std::max<size_t>(nslot * stride, 1));
         L.tg_rec = cv.take<int32_t>(std::max<size_t>(nslot * stride, 1));
+        L.tj_cnt = cv.take<int32_t>(std::max<size_t>(nslot, 1));
+        L.tj_rec = cv.take<int32_t>(std::max<size_t>(nslot * stride, 1));
     }
     L.tiles = cv.take<int32_t>(h.tiles_far.size() + h.tiles_near.size() + 16);
     L.args = cv.take<char>(kSlots * stage_args_bytes());
@@ -649,7 +653,7 @@ int do_classify(ibm_ctx *c, double t, hipStream_t s)
     e = launch_records(c->g, c->b, c->f, c->ib, s);
     if (e != hipSuccess)
         return dev_err(c, e, "records");
-    e = launch_ghost_lists(c->g, c->ib, s);
+    e = launch_ghost_lists(c->g, c->ib, c->f.family == IBM_IB_QUADRATIC, s);
     if (e != hipSuccess)
         return dev_err(c, e, "ghost lists");
     c->classified = true;
@@ -832,12 +836,16 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     ib.plan_w = L.plan_w;
     ib.plan_geo = L.plan_geo;
     ib.plan_mode = L.plan_mode;
+    ib.plan_frec = L.plan_frec;
+    ib.fval = L.fval;
     ib.rmap = L.rmap;
     ib.tile_slot = L.tile_slot;
     ib.slot_tile = L.slot_tile;
     ib.tg_cnt = L.tg_cnt;
     ib.tg_t = L.tg_t;
     ib.tg_rec = L.tg_rec;
+    ib.tj_cnt = L.tj_cnt;
+    ib.tj_rec = L.tj_rec;
     ib.nslot = (int)h.tiles_near.size();
     ib.tg_stride = tile_load_cells(nd);
     {
@@ -847,35 +855,28 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
         if (e == hipSuccess) e = up(L.tile_slot, ts);
         if (e == hipSuccess) e = up(L.slot_tile, h.tiles_near);
     }
-    // first launch: far tiles filling half of each CU's resident blocks
-    // (measured best on the 1024x512 wedge in both precisions); the near
-    // tiles are latency-bound and run with the rest in the second launch
-    std::vector<int32_t> list1, list2;
+    // one launch per stage: the blocks of one XCD (same index mod 8) take a
+    // contiguous chunk of the list; the near tiles, which also fill the IB
+    // nodes they read, are spread evenly over the chunks and start first,
+    // then the far tiles follow in raster order
+    std::vector<int32_t> list;
     {
-        int ncu = 0;
-        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, x->device) != hipSuccess)
-            ncu = 0;
-        int occ = stage_blocks_per_cu(g, f);
         int nfar = (int)h.tiles_far.size(), nnear = (int)h.tiles_near.size();
-        int k = occ > 0 && ncu > 0 ? std::min(nfar, ncu * ((occ + 1) / 2)) : nfar;
-        list1.assign(h.tiles_far.begin(), h.tiles_far.begin() + k);
         std::vector<int32_t> chunk[8];
-        int nf2 = nfar - k;
         size_t per = 0;
         for (int x = 0; x < 8; ++x) {
             for (long long m = (long long)x * nnear / 8; m < (long long)(x + 1) * nnear / 8; ++m)
                 chunk[x].push_back(h.tiles_near[m]);
-            for (long long m = (long long)x * nf2 / 8; m < (long long)(x + 1) * nf2 / 8; ++m)
-                chunk[x].push_back(h.tiles_far[k + m]);
+            for (long long m = (long long)x * nfar / 8; m < (long long)(x + 1) * nfar / 8; ++m)
+                chunk[x].push_back(h.tiles_far[m]);
             per = std::max(per, chunk[x].size());
         }
         for (int x = 0; x < 8; ++x) {
             chunk[x].resize(per, -1);
-            list2.insert(list2.end(), chunk[x].begin(), chunk[x].end());
+            list.insert(list.end(), chunk[x].begin(), chunk[x].end());
         }
     }
-    if (e == hipSuccess) e = up(L.tiles, list1);
-    if (e == hipSuccess) e = up(L.tiles + list1.size(), list2);
+    if (e == hipSuccess) e = up(L.tiles, list);
     if (e == hipSuccess) e = hipMemset(L.cls, IBM_FLUID, (size_t)h.ncell);
     if (e == hipSuccess) e = hipMemset(L.counts, 0, sizeof(int32_t) * CNT_WORDS);
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
@@ -904,10 +905,8 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     x->batch_q = nullptr;
     for (int k = 0; k < kSlots; ++k)
         x->slot_nblk[k] = 0;
-    x->tiles1 = L.tiles;
-    x->ntiles1 = (int)list1.size();
-    x->tiles2 = L.tiles + list1.size();
-    x->ntiles2 = (int)list2.size();
+    x->tiles = L.tiles;
+    x->ntiles = (int)list.size();
     if (e != hipSuccess) {
         delete x;
         return IBM_EDEVICE;
@@ -994,11 +993,8 @@ int ibm_residual(ibm_ctx *c, const double *q, double *r, void *stream)
 
 namespace {
 
-// One stage with a body is two launches on the stream: the FORCING fill
-// (it reads FLUID cells only) with the tiles whose stencils never reach the
-// immersed-boundary region, then the remaining tiles, which fill the ghost
-// layers they read from the FORCING values just stored.  Without a body
-// every tile runs in one launch.
+// One stage is one launch on the stream.  With a body it runs the tile list,
+// whose near tiles fill the IB nodes they read; without one, every tile.
 template <typename Launch> int enqueue_stage(ibm_ctx *c, double t, hipStream_t s, Launch launch)
 {
     if (c->b.nfacet == 0 || c->ib.cap == 0)
@@ -1009,12 +1005,8 @@ template <typename Launch> int enqueue_stage(ibm_ctx *c, double t, hipStream_t s
         motion_kin(c, t, disp, vel, acc);
         axis = c->mo.axis;
     }
-    StagePart p1{c->tiles1, c->ntiles1, true, false, vel, acc, axis};
-    StagePart p2{c->tiles2, c->ntiles2, false, true, vel, acc, axis};
-    hipError_t e = launch(s, &p1);
-    if (e == hipSuccess)
-        e = launch(s, &p2);
-    return dev_err(c, e, "stage");
+    StagePart p{c->tiles, c->ntiles, vel, acc, axis};
+    return dev_err(c, launch(s, &p), "stage");
 }
 
 // One SSP-RK3 step (Shu-Osher) starting at time t; a fill at each stage time.
@@ -1072,12 +1064,13 @@ int prepare_batch(ibm_ctx *c, double *q, hipStream_t s)
     size_t nb = stage_args_bytes();
     c->h_args.assign(kSlots * nb, 0);
     bool body = c->b.nfacet > 0 && c->ib.cap > 0;
-    StagePart p1{c->tiles1, c->ntiles1, true, false, 0.0, 0.0, -1};
-    StagePart p2{c->tiles2, c->ntiles2, false, true, 0.0, 0.0, -1};
+    StagePart p{c->tiles, c->ntiles, 0.0, 0.0, -1};
+    // launch 0 of a stage is the plain kernel (solves without a body), launch
+    // 1 the kernel with the inline IB fill (solves with one)
     auto put = [&](int slot, int launch, double *qin, const double *qn, const double *qnm1, double *out,
                    double a, double b) {
-        const StagePart *part = body ? (launch == 0 ? &p1 : &p2) : nullptr;
-        if (!body && launch == 1) {
+        const StagePart *part = body ? &p : nullptr;
+        if (body != (launch == 1)) {
             c->slot_nblk[slot] = 0;
             return;
         }

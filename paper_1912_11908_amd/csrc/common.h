@@ -82,14 +82,23 @@ struct IB {
     double *plan_w;          // 16 * cap
     double *plan_geo;        // 6 * cap
     int32_t *plan_mode;      // cap: mode1 | mode2 << 4
+    // 16 * cap, ghost records: the FORCING record of each weighted probe
+    // corner that is a FORCING node (-1 otherwise, and for FORCING records)
+    int32_t *plan_frec;
+    double *fval;            // NV * cap: filled values of FORCING corners, by record
     int32_t *rmap;           // cap: record index per region cell (IB nodes only)
     // per near tile ("slot", a tile whose stencils reach the region): the
-    // ghost nodes G1-G3 among the cells it loads, as (tile-local cell,
-    // record); rebuilt after every classification
+    // IB nodes (FORCING and G1-G3) among the cells it loads, as (tile-local
+    // cell, record); rebuilt after every classification
     const int32_t *tile_slot;  // slot per tile id, -1 for the other tiles
     const int32_t *slot_tile;  // tile id per slot
     int32_t *tg_cnt;           // nslot
     int32_t *tg_t, *tg_rec;    // nslot * tg_stride
+    // per slot: FORCING records outside the loaded cells that its ghost
+    // nodes read as probe corners (repeats allowed; count -1 if they did
+    // not fit, and the ghosts then fill those corners themselves)
+    int32_t *tj_cnt;           // nslot
+    int32_t *tj_rec;           // nslot * tg_stride
     int nslot, tg_stride;
 };
 
@@ -99,16 +108,12 @@ constexpr int kTile3[3] = {8, 7, 8};  // 504, 512, 504 faces: one pass each for 
 // threads per block of the fused kernel: 2D 256, 3D 512
 constexpr int kThreads2 = 256, kThreads3 = 512;
 
-// One launch of the fused residual/update kernel for a stage: a list of
-// tiles (null: every tile of the grid) and what the launch also fills.  A
-// stage with a body is two launches: the FORCING fill (leading blocks) with
-// the tiles whose stencils never reach the IB region, then the other tiles,
-// which fill the ghost layers G1-G3 they read on the fly.
+// The launch of the fused residual/update kernel for a stage with a body:
+// a list of tiles (the near tiles among them fill, on the fly, the IB nodes
+// they read) and the body's motion at the stage time.
 struct StagePart {
     const int32_t *tiles;    // tile ids, -1 entries are padding
     int ntiles;
-    bool fill_forcing;       // leading blocks fill the FORCING nodes of qin
-    bool inline_ghosts;      // tiles fill the ghost nodes they read
     double ub, ab;           // body velocity and acceleration along `axis`
     int axis;                // motion axis, -1 for a stationary body
 };
@@ -123,8 +128,8 @@ struct Motion {
 hipError_t launch_pose(const Grid &g, Body &b, long long disp, int axis, hipStream_t s);
 hipError_t launch_classify(const Grid &g, const Body &b, IB &ib, hipStream_t s);
 hipError_t launch_records(const Grid &g, const Body &b, const Flow &f, IB &ib, hipStream_t s);
-// per near tile ghost lists (after the records)
-hipError_t launch_ghost_lists(const Grid &g, const IB &ib, hipStream_t s);
+// per near tile IB lists and FORCING corner lists (after the records)
+hipError_t launch_ghost_lists(const Grid &g, const IB &ib, bool quad, hipStream_t s);
 // cells a tile's stencils load (tile plus its halo) for this dimension
 int tile_load_cells(int ndim);
 
@@ -149,8 +154,6 @@ hipError_t launch_prim_to_state(const Grid &g, const Flow &f, const double *prim
 hipError_t launch_state_to_prim(const Grid &g, const Flow &f, const double *q, double *prim,
                                 hipStream_t s);
 hipError_t launch_copy_state(const Grid &g, const double *src, double *dst, hipStream_t s);
-// resident blocks per CU of the stage kernel for this grid and flow (0 if unknown)
-int stage_blocks_per_cu(const Grid &g, const Flow &f);
 
 // Batched stages (several solves per launch): the arguments of one stage
 // launch of a solve are written as stage_args_bytes() opaque bytes to host

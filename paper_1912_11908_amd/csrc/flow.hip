@@ -199,46 +199,68 @@ __device__ inline void prim_of_state(const Flow &f, const double *qv, double &rh
     }
 }
 
-template <int DIM>
-__device__ inline void node_fill(const Grid &g, const Flow &f, const IB &ib, const double *q, int r, double ub,
-                                 double ab, int axis, double *qs);
+template <int DIM, bool NEST>
+__device__ __forceinline__ void node_fill(const Grid &g, const Flow &f, const IB &ib, const double *q, int r,
+                                          double ub, double ab, int axis, double *qs);
 
 // value at probe `p` (0 or 1) of record r: weighted sum of (p, u.., T) over
-// the plan's corners (unused corners carry zero weight)
+// the plan's corners (unused corners carry zero weight).  With NEST, a
+// weighted corner that is a FORCING node takes its filled value from
+// ib.fval (stored there by forcing_corners), not from q.
 template <int DIM>
-__device__ inline void plan_probe(const Grid &g, const Flow &f, const IB &ib, const double *q, int r,
-                                  int p, double *phi)
+__device__ __forceinline__ void probe_add(const Flow &f, const double *qv, double w, double *phi)
+{
+    double rho, u[DIM], pr, T;
+    prim_of_state<DIM>(f, qv, rho, u, pr, T);
+    if (w != 0.0) {
+        phi[0] += w * pr;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+            phi[1 + d] += w * u[d];
+        phi[DIM + 1] += w * T;
+    }
+}
+
+template <int DIM, bool NEST>
+__device__ __forceinline__ void plan_probe(const Grid &g, const Flow &f, const IB &ib, const double *q, int r,
+                                           int p, double ub, double ab, int axis, double *phi)
 {
     constexpr int NC = 1 << DIM;
     constexpr int NV = DIM + 2;
 #pragma unroll
     for (int v = 0; v < NV; ++v)
         phi[v] = 0.0;
+    if constexpr (NEST) {
+#pragma nounroll
+        for (int m = 0; m < NC; ++m) {
+            int off = ib.plan_off[(8 * p + m) * ib.cap + r];
+            double w = ib.plan_w[(8 * p + m) * ib.cap + r];
+            int fr = ib.plan_frec[(8 * p + m) * ib.cap + r];
+            double qv[NV];
 #pragma unroll
-    for (int m = 0; m < NC; ++m) {
-        int off = ib.plan_off[(8 * p + m) * ib.cap + r];
-        double w = ib.plan_w[(8 * p + m) * ib.cap + r];
-        double qv[NV];
+            for (int v = 0; v < NV; ++v)
+                qv[v] = fr >= 0 ? ib.fval[(long long)v * ib.cap + fr] : q[off + v * g.vs];
+            probe_add<DIM>(f, qv, w, phi);
+        }
+    } else {
+#pragma nounroll
+        for (int m = 0; m < NC; ++m) {
+            int off = ib.plan_off[(8 * p + m) * ib.cap + r];
+            double w = ib.plan_w[(8 * p + m) * ib.cap + r];
+            double qv[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
-            qv[v] = q[off + v * g.vs];
-        double rho, u[DIM], pr, T;
-        prim_of_state<DIM>(f, qv, rho, u, pr, T);
-        if (w != 0.0) {
-            phi[0] += w * pr;
-#pragma unroll
-            for (int d = 0; d < DIM; ++d)
-                phi[1 + d] += w * u[d];
-            phi[DIM + 1] += w * T;
+            for (int v = 0; v < NV; ++v)
+                qv[v] = q[off + v * g.vs];
+            probe_add<DIM>(f, qv, w, phi);
         }
     }
 }
 
 // State value qs of IB record r (its plan and the node's boundary
-// conditions) from the cells of q.
-template <int DIM>
-__device__ inline void node_fill(const Grid &g, const Flow &f, const IB &ib, const double *q, int r, double ub,
-                          double ab, int axis, double *qs)
+// conditions) from the cells of q; NEST as for plan_probe.
+template <int DIM, bool NEST>
+__device__ __forceinline__ void node_fill(const Grid &g, const Flow &f, const IB &ib, const double *q, int r,
+                                          double ub, double ab, int axis, double *qs)
 {
     constexpr int NV = DIM + 2;
     int cap = ib.cap;
@@ -262,7 +284,7 @@ __device__ inline void node_fill(const Grid &g, const Flow &f, const IB &ib, con
             ru[d] = ubv[d];
     } else {
         double phi1[NV];
-        plan_probe<DIM>(g, f, ib, q, r, 0, phi1);
+        plan_probe<DIM, NEST>(g, f, ib, q, r, 0, ub, ab, axis, phi1);
         double rho1 = phi1[0] / (f.R * phi1[NV - 1]);
         double an = 0.0;
 #pragma unroll
@@ -277,7 +299,7 @@ __device__ inline void node_fill(const Grid &g, const Flow &f, const IB &ib, con
             rT = phi1[NV - 1] + gT * (sx - s1);
         } else {
             double phi2[NV];
-            plan_probe<DIM>(g, f, ib, q, r, 1, phi2);
+            plan_probe<DIM, NEST>(g, f, ib, q, r, 1, ub, ab, axis, phi2);
             double L0 = (sx - s1) * (sx - s2) / (s1 * s2);
             double L1 = sx * (sx - s2) / (s1 * (s1 - s2));
             double L2 = sx * (sx - s1) / (s2 * (s2 - s1));
@@ -312,13 +334,35 @@ __device__ inline void node_fill(const Grid &g, const Flow &f, const IB &ib, con
     }
 }
 
+// The FORCING corners of ghost record r: each one's filled value, from the
+// FLUID cells of q, stored at ib.fval for node_fill<DIM, true>.  Several
+// threads may store the same corner; they store the same value.
+template <int DIM>
+__device__ __forceinline__ void forcing_corners(const Grid &g, const Flow &f, const IB &ib, const double *q,
+                                                int r, double ub, double ab, int axis)
+{
+    constexpr int NC = 1 << DIM;
+#pragma nounroll
+    for (int k = 0; k < 2 * NC; ++k) {
+        int p = k / NC, m = k % NC;
+        int fr = ib.plan_frec[(8 * p + m) * ib.cap + r];
+        if (fr < 0)
+            continue;
+        double qv[DIM + 2];
+        node_fill<DIM, false>(g, f, ib, q, fr, ub, ab, axis, qv);
+#pragma unroll
+        for (int v = 0; v < DIM + 2; ++v)
+            ib.fval[(long long)v * ib.cap + fr] = qv[v];
+    }
+}
+
 // fill record r of q in place from the values stored in q
 template <int DIM>
 __device__ __forceinline__ void fill_one(const Grid &g, const Flow &f, const IB &ib, double *q, int r, double ub,
                                 double ab, int axis)
 {
     double qs[DIM + 2];
-    node_fill<DIM>(g, f, ib, q, r, ub, ab, axis, qs);
+    node_fill<DIM, false>(g, f, ib, q, r, ub, ab, axis, qs);
     int node = ib.plan_node[r];
 #pragma unroll
     for (int v = 0; v < DIM + 2; ++v)
@@ -362,7 +406,7 @@ struct StepArgs {
     Flow f;
     const uint8_t *cls;
     int32_t *counts;
-    double *qin;         // state read by the stencils (and filled by fill blocks)
+    const double *qin;   // state read by the stencils (its IB nodes are filled on the fly)
     const double *qn;    // RK3: Q^n (state layout); dual: Q'^n (interior layout)
     const double *qnm1;  // dual: Q'^{n-1} (interior layout)
     double *out;         // RK3/dual: next state; residual mode: R (interior)
@@ -370,7 +414,6 @@ struct StepArgs {
     int ntx, nty, ntz;
     const int32_t *tiles;  // tile ids to run (null: every tile, in order)
     int ntiles;
-    int nfill;           // leading blocks that fill the FORCING nodes of qin
     IB ib;
     double ub, ab;       // body velocity / acceleration along `axis`
     int axis;
@@ -660,22 +703,12 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
 
     const Grid &g = A.g;
     const Flow &f = A.f;
-    if constexpr (MODE != MODE_RESID) {
-        // leading blocks: fill the FORCING nodes of the stage input
-        // (grid-stride); the tiles of such a launch never read those nodes
-        if (bid < A.nfill) {
-            int nF = min(A.ib.counts[CNT_F], A.ib.cap);
-            for (int r = bid * NT + threadIdx.x; r < nF; r += A.nfill * NT)
-                fill_one<DIM>(g, f, A.ib, A.qin, r, A.ub, A.ab, A.axis);
-            return;
-        }
-    }
     // tile id: the blocks b with the same b mod 8 (dispatched to the same
     // XCD) take a contiguous run of the tile list, so neighbouring tiles
     // share that XCD's L2
     const int32_t *list = A.tiles;
     int nt = list ? A.ntiles : A.ntx * A.nty * A.ntz;
-    int b = bid - (MODE != MODE_RESID ? A.nfill : 0);
+    int b = bid;
     int per = (nt + 7) / 8;
     int pos = (b % 8) * per + b / 8;
     if (pos >= nt)
@@ -756,47 +789,93 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
         }
     }
 
-    // 1b. inline ghost fill (tiles whose stencils reach the IB region): the
-    //     ghost nodes G1-G3 among the loaded cells (the tile's list, built
-    //     after classification) take their filled values, computed from the
-    //     stage input, whose FORCING nodes are already filled; one node per
-    //     thread and pass.  A node inside the tile also stores the value as
-    //     its stage output.
+    // 1b. inline IB fill (tiles whose stencils reach the IB region): the IB
+    //     nodes among the loaded cells (the tile's list, built after
+    //     classification) take their filled values, computed from the stage
+    //     input in two sweeps, one node per thread: FORCING nodes from FLUID
+    //     cells, then ghost nodes G1-G3 from FLUID cells and the filled
+    //     values of their FORCING corners.  A node inside the tile also
+    //     stores its value as its stage output.
     if constexpr (INLINE_GHOSTS) {
         const IB &ib = A.ib;
-        int slot = ib.tile_slot[tile];
+        int slot = ib.cap > 0 ? ib.tile_slot[tile] : -1;
         int n = slot >= 0 ? ib.tg_cnt[slot] : 0;
-        for (int e0 = 0; e0 < n; e0 += NT) {
-            int e = e0 + tid;
-            double qs[NV];
-            int t = 0;
-            bool inside = false, filled = false;
-            long long s = 0;
-            if (e < n) {
-                t = ib.tg_t[(long long)slot * ib.tg_stride + e];
-                int rec = ib.tg_rec[(long long)slot * ib.tg_stride + e];
+        if (n > 0) {
+            int nF = min(ib.counts[CNT_F], ib.cap);
+            int nj = ib.tj_cnt[slot];
+            bool own_corners = nj < 0;  // the corner list did not fit
+            nj = max(nj, 0);
+            const int32_t *lt = ib.tg_t + (long long)slot * ib.tg_stride;
+            const int32_t *lr = ib.tg_rec + (long long)slot * ib.tg_stride;
+            const int32_t *lj = ib.tj_rec + (long long)slot * ib.tg_stride;
+            // list entry e: its LDS cell, its state offset, whether it lies
+            // in the tile (then its value is also the stage output)
+            auto where = [&](int e, int &t, long long &so, bool &inside) {
+                t = lt[e];
                 int lx = t % LX, ly = (t / LX) % LY, lz = t / (LX * LY);
                 int c[3] = {i0 + lx - 3, j0 + ly - 3, k0 + lz - HZ};
                 inside = lx >= 3 && lx < 3 + TX && ly >= 3 && ly < 3 + TY && lz >= HZ && lz < HZ + TZ &&
                          c[0] < g.ni && c[1] < g.nj && (DIM == 2 || c[2] < g.nk);
                 ghost_source<DIM>(g, c);
-                s = sidx(g, c[0], c[1], c[2]);
-                if (rec < 0) {  // no record (capacity exceeded, flagged): stored value
+                so = sidx(g, c[0], c[1], c[2]);
+            };
+            auto place = [&](int t, long long so, bool inside, const double *qs) {
+                put(t, qs);
+                if (inside) {
 #pragma unroll
                     for (int m = 0; m < NV; ++m)
-                        qs[m] = A.qin[s + m * g.vs];
+                        A.out[so + m * g.vs] = qs[m];
+                }
+            };
+            __syncthreads();  // the loaded values are in LDS before IB values replace them
+            // sweep 1: the listed FORCING nodes and the FORCING corners the
+            // listed ghosts read outside the loaded cells, each filled from
+            // FLUID cells and kept in fval; entries without a record keep
+            // their stored value
+            for (int e = tid; e < n + nj; e += NT) {
+                double qs[NV];
+                if (e < n) {
+                    int rec = lr[e];
+                    if (rec >= nF)
+                        continue;  // ghost node: sweep 2
+                    int t;
+                    long long so;
+                    bool inside;
+                    where(e, t, so, inside);
+                    if (rec < 0) {  // no record (capacity exceeded, flagged)
+#pragma unroll
+                        for (int m = 0; m < NV; ++m)
+                            qs[m] = A.qin[so + m * g.vs];
+                    } else {
+                        node_fill<DIM, false>(g, f, ib, A.qin, rec, A.ub, A.ab, A.axis, qs);
+#pragma unroll
+                        for (int m = 0; m < NV; ++m)
+                            ib.fval[(long long)m * ib.cap + rec] = qs[m];
+                    }
+                    place(t, so, inside, qs);
                 } else {
-                    node_fill<DIM>(g, f, ib, A.qin, rec, A.ub, A.ab, A.axis, qs);
-                    filled = true;
+                    int rec = lj[e - n];
+                    node_fill<DIM, false>(g, f, ib, A.qin, rec, A.ub, A.ab, A.axis, qs);
+#pragma unroll
+                    for (int m = 0; m < NV; ++m)
+                        ib.fval[(long long)m * ib.cap + rec] = qs[m];
                 }
             }
-            __syncthreads();  // the loaded values are in LDS before they are replaced
-            if (filled)
-                put(t, qs);
-            if (inside) {
-#pragma unroll
-                for (int m = 0; m < NV; ++m)
-                    A.out[s + m * g.vs] = qs[m];
+            __syncthreads();  // sweep 1's fval stores are seen by the whole block
+            // sweep 2: ghost nodes G1-G3, their FORCING corners from fval
+            for (int e = tid; e < n; e += NT) {
+                int rec = lr[e];
+                if (rec < nF)
+                    continue;
+                int t;
+                long long so;
+                bool inside;
+                where(e, t, so, inside);
+                double qs[NV];
+                if (own_corners)
+                    forcing_corners<DIM>(g, f, ib, A.qin, rec, A.ub, A.ab, A.axis);
+                node_fill<DIM, true>(g, f, ib, A.qin, rec, A.ub, A.ab, A.axis, qs);
+                place(t, so, inside, qs);
             }
         }
     }
@@ -891,8 +970,8 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
     long long s = s_own;
     if (MODE != MODE_RESID) {
         if (cls != IBM_FLUID) {  // IB nodes carry their filled value, solid cells their state
-            if (INLINE_GHOSTS && cls >= IBM_G1 && cls <= IBM_G3)
-                return;  // written by the inline ghost fill
+            if (INLINE_GHOSTS && cls >= IBM_FORCING && cls <= IBM_G3)
+                return;  // written by the inline fill
 #pragma unroll
             for (int m = 0; m < NV; ++m)
                 A.out[s + m * g.vs] = qc[m];
@@ -1116,11 +1195,39 @@ __global__ __launch_bounds__(kThreads3) __attribute__((amdgpu_num_vgpr(128))) vo
     batch_body<3, float, MODE, GHOSTS>(B);
 }
 
+// 2D FP32: the tile fits eight 256-thread blocks per CU in LDS; the
+// register budget for eight (RK3) or seven (dual time, whose FP64 update is
+// larger) waves per SIMD is stated, which the kernels meet without spills
+// (left to itself the compiler takes a few registers more and loses a wave).
+template <int MODE> constexpr int waves2f() { return MODE == MODE_DUAL ? 7 : 8; }
+template <int MODE>
+__global__ __launch_bounds__(kThreads2) __attribute__((amdgpu_waves_per_eu(waves2f<MODE>(), waves2f<MODE>()))) void
+step_kernel_2f(StepArgs A)
+{
+    step_body<2, float, MODE, false>(A, blockIdx.x);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads2) __attribute__((amdgpu_waves_per_eu(waves2f<MODE>(), waves2f<MODE>()))) void
+step_ghost_kernel_2f(StepArgs A)
+{
+    step_body<2, float, MODE, true>(A, blockIdx.x);
+}
+
+template <int MODE, bool GHOSTS>
+__global__ __launch_bounds__(kThreads2) __attribute__((amdgpu_waves_per_eu(waves2f<MODE>(), waves2f<MODE>()))) void
+step_batch_kernel_2f(BatchArgs B)
+{
+    batch_body<2, float, MODE, GHOSTS>(B);
+}
+
 // the kernel of each launch kind for (DIM, Real, MODE)
 template <int DIM, typename Real, int MODE> constexpr auto plain_kernel()
 {
     if constexpr (DIM == 3 && sizeof(Real) == 4)
         return &step_kernel_3f<MODE>;
+    else if constexpr (DIM == 2 && sizeof(Real) == 4 && MODE != MODE_RESID)
+        return &step_kernel_2f<MODE>;
     else
         return &step_kernel<DIM, Real, MODE>;
 }
@@ -1128,6 +1235,8 @@ template <int DIM, typename Real, int MODE> constexpr auto ghost_kernel()
 {
     if constexpr (DIM == 3 && sizeof(Real) == 4)
         return &step_ghost_kernel_3f<MODE>;
+    else if constexpr (DIM == 2 && sizeof(Real) == 4)
+        return &step_ghost_kernel_2f<MODE>;
     else
         return &step_ghost_kernel<DIM, Real, MODE>;
 }
@@ -1135,15 +1244,19 @@ template <int DIM, typename Real, int MODE, bool GHOSTS> constexpr auto batch_ke
 {
     if constexpr (DIM == 3 && sizeof(Real) == 4)
         return &step_batch_kernel_3f<MODE, GHOSTS>;
+    else if constexpr (DIM == 2 && sizeof(Real) == 4)
+        return &step_batch_kernel_2f<MODE, GHOSTS>;
     else
         return &step_batch_kernel<DIM, Real, MODE, GHOSTS>;
 }
 
-// Ghost lists of the near tiles: block p scans the cells tile slot_tile[p]
+// IB lists of the near tiles: block p scans the cells tile slot_tile[p]
 // loads (tile plus halo, domain ghost cells resolved as the stencils do) and
-// lists those that are ghost nodes G1-G3, with their records.
+// lists those that are IB nodes (FORCING, G1-G3), with their records; then
+// the FORCING probe corners of the listed ghost nodes that lie outside the
+// loaded cells (the ones inside are listed already).
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void ghost_lists_kernel(Grid g, IB ib, int ntx, int nty)
+__global__ __launch_bounds__(kBlock) void ghost_lists_kernel(Grid g, IB ib, int ntx, int nty, int quad)
 {
     using C = TileCfg<DIM>;
     constexpr int TX = C::TX, TY = C::TY, TZ = C::TZ, HZ = C::HZ;
@@ -1165,15 +1278,48 @@ __global__ __launch_bounds__(kBlock) void ghost_lists_kernel(Grid g, IB ib, int 
         if (li < 0 || li >= ib.rw || lj < 0 || lj >= ib.rh || lk < 0 || lk >= ib.rd)
             continue;
         uint8_t kc = ib.cls[((long long)c[2] * g.nj + c[1]) * g.ni + c[0]];
-        if (kc < IBM_G1 || kc > IBM_G3)
+        if (kc < IBM_FORCING || kc > IBM_G3)
             continue;
         int e = atomicAdd(&n, 1);
         ib.tg_t[(long long)slot * ib.tg_stride + e] = t;
         ib.tg_rec[(long long)slot * ib.tg_stride + e] = ib.rmap[(lk * ib.rh + lj) * ib.rw + li];
     }
     __syncthreads();
+    int nl = n;
+    int nF = min(ib.counts[CNT_F], ib.cap);
+    __shared__ int nj;
     if (threadIdx.x == 0)
-        ib.tg_cnt[slot] = n;
+        nj = 0;
+    __syncthreads();
+    constexpr int NC = 1 << DIM;
+    int np = quad ? 2 : 1;  // probes per node
+    for (int e = threadIdx.x; e < nl; e += kBlock) {
+        int rec = ib.tg_rec[(long long)slot * ib.tg_stride + e];
+        if (rec < nF)  // FORCING entry, or no record
+            continue;
+        int fr[2 * NC];
+#pragma unroll
+        for (int k = 0; k < 2 * NC; ++k)
+            fr[k] = k < np * NC ? ib.plan_frec[(8 * (k / NC) + k % NC) * ib.cap + rec] : -1;
+#pragma unroll
+        for (int k = 0; k < 2 * NC; ++k) {
+            if (fr[k] < 0)
+                continue;
+            int cc = ib.listF[fr[k]];
+            int ci = cc % g.ni, cj = (cc / g.ni) % g.nj, ck = cc / (g.ni * g.nj);
+            int lx = ci - i0 + 3, ly = cj - j0 + 3, lz = ck - k0 + HZ;
+            if (lx >= 0 && lx < LX && ly >= 0 && ly < LY && lz >= 0 && lz < LZ)
+                continue;
+            int q = atomicAdd(&nj, 1);
+            if (q < ib.tg_stride)
+                ib.tj_rec[(long long)slot * ib.tg_stride + q] = fr[k];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ib.tg_cnt[slot] = nl;
+        ib.tj_cnt[slot] = nj <= ib.tg_stride ? nj : -1;
+    }
 }
 
 // Q'^{n-1} <- Q'^n (at the first step Q'^{n-1} <- Q(W) - Q_inf too); Q'^n <- Q(W) - Q_inf
@@ -1268,7 +1414,7 @@ FreeStream freestream_of(const Grid &g, const Flow &f)
 // Arguments of one stage launch, and its block count.
 template <int DIM>
 StepArgs make_args(const Grid &g, const Flow &f, const IB &ib, double *qin, const double *qn,
-                   const double *qnm1, double *out, double a, double b, bool resid, const StagePart *part,
+                   const double *qnm1, double *out, double a, double b, const StagePart *part,
                    int *nblk)
 {
     const int *T = DIM == 2 ? kTile2 : kTile3;
@@ -1288,19 +1434,13 @@ StepArgs make_args(const Grid &g, const Flow &f, const IB &ib, double *qin, cons
     A.ntz = DIM == 3 ? (g.nk + T[2] - 1) / T[2] : 1;
     A.tiles = part ? part->tiles : nullptr;
     A.ntiles = part ? part->ntiles : 0;
-    A.nfill = 0;
     A.ib = ib;
     A.ub = part ? part->ub : 0.0;
     A.ab = part ? part->ab : 0.0;
     A.axis = part ? part->axis : -1;
     A.fs = freestream_of(g, f);
     int nt = A.tiles ? A.ntiles : A.ntx * A.nty * A.ntz;
-    if (!resid && part && part->fill_forcing && ib.cap > 0) {
-        int nb = blocks_for(ib.cap, TileCfg<DIM>::NT);
-        nb = nb < 64 ? nb : 64;
-        A.nfill = (nb + 7) / 8 * 8;
-    }
-    *nblk = A.nfill + 8 * ((nt + 7) / 8);
+    *nblk = 8 * ((nt + 7) / 8);
     return A;
 }
 
@@ -1310,11 +1450,11 @@ hipError_t run_step(const Grid &g, const Flow &f, const IB &ib, double *qin, con
                     const StagePart *part)
 {
     int nblk = 0;
-    StepArgs A = make_args<DIM>(g, f, ib, qin, qn, qnm1, out, a, b, MODE == MODE_RESID, part, &nblk);
+    StepArgs A = make_args<DIM>(g, f, ib, qin, qn, qnm1, out, a, b, part, &nblk);
     if (nblk == 0)
         return hipSuccess;
     if constexpr (MODE != MODE_RESID) {
-        if (part && part->inline_ghosts && ib.cap > 0) {
+        if (part && ib.cap > 0) {
             hipLaunchKernelGGL((ghost_kernel<DIM, Real, MODE>()), dim3(nblk), dim3(TileCfg<DIM>::NT), 0, s, A);
             return hipGetLastError();
         }
@@ -1423,8 +1563,8 @@ int stage_args(const Grid &g, const Flow &f, const IB &ib, double *qin, const do
                const double *qnm1, double *out, double a, double b, const StagePart *part, void *dst)
 {
     int nblk = 0;
-    StepArgs A = g.ndim == 2 ? make_args<2>(g, f, ib, qin, qn, qnm1, out, a, b, false, part, &nblk)
-                             : make_args<3>(g, f, ib, qin, qn, qnm1, out, a, b, false, part, &nblk);
+    StepArgs A = g.ndim == 2 ? make_args<2>(g, f, ib, qin, qn, qnm1, out, a, b, part, &nblk)
+                             : make_args<3>(g, f, ib, qin, qn, qnm1, out, a, b, part, &nblk);
     std::memcpy(dst, &A, sizeof A);
     return nblk;
 }
@@ -1473,35 +1613,17 @@ int tile_load_cells(int ndim)
     return (T[0] + 6) * (T[1] + 6) * (T[2] + 2 * hz);
 }
 
-hipError_t launch_ghost_lists(const Grid &g, const IB &ib, hipStream_t s)
+hipError_t launch_ghost_lists(const Grid &g, const IB &ib, bool quad, hipStream_t s)
 {
     if (ib.nslot == 0 || ib.cap == 0)
         return hipSuccess;
     const int *T = g.ndim == 2 ? kTile2 : kTile3;
     int ntx = (g.ni + T[0] - 1) / T[0], nty = (g.nj + T[1] - 1) / T[1];
     if (g.ndim == 2)
-        hipLaunchKernelGGL(ghost_lists_kernel<2>, dim3(ib.nslot), dim3(kBlock), 0, s, g, ib, ntx, nty);
+        hipLaunchKernelGGL(ghost_lists_kernel<2>, dim3(ib.nslot), dim3(kBlock), 0, s, g, ib, ntx, nty, (int)quad);
     else
-        hipLaunchKernelGGL(ghost_lists_kernel<3>, dim3(ib.nslot), dim3(kBlock), 0, s, g, ib, ntx, nty);
+        hipLaunchKernelGGL(ghost_lists_kernel<3>, dim3(ib.nslot), dim3(kBlock), 0, s, g, ib, ntx, nty, (int)quad);
     return hipGetLastError();
-}
-
-int stage_blocks_per_cu(const Grid &g, const Flow &f)
-{
-    int n = 0;
-    bool mixed = f.precision == IBM_MIXED, rk = f.scheme == IBM_RK3;
-    hipError_t e;
-    if (g.ndim == 2)
-        e = mixed ? (rk ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<2, float, MODE_RK3>, kThreads2, 0)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<2, float, MODE_DUAL>, kThreads2, 0))
-                  : (rk ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<2, double, MODE_RK3>, kThreads2, 0)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<2, double, MODE_DUAL>, kThreads2, 0));
-    else
-        e = mixed ? (rk ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel_3f<MODE_RK3>, kThreads3, 0)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel_3f<MODE_DUAL>, kThreads3, 0))
-                  : (rk ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<3, double, MODE_RK3>, kThreads3, 0)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<3, double, MODE_DUAL>, kThreads3, 0));
-    return e == hipSuccess ? n : 0;
 }
 
 hipError_t launch_copy_state(const Grid &g, const double *src, double *dst, hipStream_t s)

@@ -961,7 +961,41 @@ __device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib
         }
         mode2 = 3;
     }
-    if (lane != 0)  // every lane holds the same record
+    // every lane holds the same record.  Fill plan: state offsets instead of
+    // cell ids, unused corners aimed at the node itself with zero weight, so
+    // the fill loops are branch-free; lane 8 p + m writes probe p's corner m
+    int cap = ib.cap;
+    long long node_off = ((long long)(k + g.hz) * g.sy + (j + 3)) * g.sx + (i + 3);
+    if (lane < 16) {
+        int p = lane / 8, m = lane % 8;
+        int cc = -1;
+        double ws = 0.0;
+#pragma unroll
+        for (int mm = 0; mm < 8; ++mm)
+            if (mm == m) {
+                cc = p ? ids2[mm] : ids1[mm];
+                ws = p ? w2[mm] : w1[mm];
+            }
+        int off = (int)node_off;
+        double wt = 0.0;
+        int frec = -1;
+        if (cc >= 0 && ws != 0.0) {
+            int ci = cc % g.ni, cj = (cc / g.ni) % g.nj, ck = cc / (g.ni * g.nj);
+            off = (int)(((long long)(ck + g.hz) * g.sy + (cj + 3)) * g.sx + (ci + 3));
+            wt = ws;
+            // a ghost's weighted FORCING corner: its record, so that a tile
+            // can fill the corner before the ghost
+            if (!forcing && ib.cls[cc] == IBM_FORCING) {
+                int li = ci - ib.region[0], lj = cj - ib.region[2], lk = ck - ib.region[4];
+                if (li >= 0 && li < ib.rw && lj >= 0 && lj < ib.rh && lk >= 0 && lk < ib.rd)
+                    frec = ib.rmap[(lk * ib.rh + lj) * ib.rw + li];
+            }
+        }
+        ib.plan_off[(8 * p + m) * cap + r] = off;
+        ib.plan_w[(8 * p + m) * cap + r] = wt;
+        ib.plan_frec[(8 * p + m) * cap + r] = frec;
+    }
+    if (lane != 0)
         return;
     int *ir = ib.rec_i + (long long)kRecI * r;
     double *dr = ib.rec_d + (long long)kRecD * r;
@@ -989,28 +1023,7 @@ __device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib
     dr[25] = sqrt(cl.d2);
     for (int m = 26; m < kRecD; ++m)
         dr[m] = 0.0;
-
-    // fill plan: state offsets instead of cell ids, unused corners aimed at
-    // the node itself with zero weight, so the fill loops are branch-free
-    int cap = ib.cap;
-    long long node_off = ((long long)(k + g.hz) * g.sy + (j + 3)) * g.sx + (i + 3);
     ib.plan_node[r] = (int)node_off;
-    for (int m = 0; m < 8; ++m) {
-        int ids[2] = {ids1[m], ids2[m]};
-        double ws[2] = {w1[m], w2[m]};
-        for (int p = 0; p < 2; ++p) {
-            int off = (int)node_off;
-            double wt = 0.0;
-            if (ids[p] >= 0 && ws[p] != 0.0) {
-                int cc = ids[p];
-                int ci = cc % g.ni, cj = (cc / g.ni) % g.nj, ck = cc / (g.ni * g.nj);
-                off = (int)(((long long)(ck + g.hz) * g.sy + (cj + 3)) * g.sx + (ci + 3));
-                wt = ws[p];
-            }
-            ib.plan_off[(8 * p + m) * cap + r] = off;
-            ib.plan_w[(8 * p + m) * cap + r] = wt;
-        }
-    }
     for (int d = 0; d < 3; ++d)
         ib.plan_geo[d * cap + r] = n[d];
     ib.plan_geo[3 * cap + r] = sx;
