@@ -88,6 +88,8 @@ def _parse():
     ap.add_argument("--serving-rate", type=float, default=50.0)
     ap.add_argument("--no-other-configs", action="store_true",
                     help="skip the cylinder, airfoil and tube workloads")
+    ap.add_argument("--config-only", choices=("cylinder", "airfoil", "tube"),
+                    help="time only that one of the other workloads and print its line (for profiling)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="also run one plain device copy of 256 MiB (reference for HBM counters)")
     return ap.parse_args()
@@ -109,7 +111,7 @@ def serving(n, rate):
     return out
 
 
-def other_configs():
+def other_configs(only=None):
     """Throughput of the other fixed workloads (whole steps, free-stream
     start, states resident in HBM): the cylinder for its full 200 steps in
     FP64, prefixes of the airfoil (dual time, 20 pseudo-iterations per
@@ -119,11 +121,12 @@ def other_configs():
     import workloads as w
     import paper_1912_11908_amd as P
     out = {}
-    plan = [("cylinder 128x128, M=0.3, Re=40, RK3, 200 steps", w.case_c1(), ("fp64",), 200),
-            ("NACA0012 2048x1024, M=0.001, Re=1000, dual time, 10 physical steps", w.case_c3(),
+    plan = [("cylinder", "cylinder 128x128, M=0.3, Re=40, RK3, 200 steps", w.case_c1, ("fp64",), 200),
+            ("airfoil", "NACA0012 2048x1024, M=0.001, Re=1000, dual time, 10 physical steps", w.case_c3,
              ("mixed", "fp64"), 10),
-            ("oscillating tube 384x256x64, M=0.2, Re=185, RK3, moving, 50 steps", w.case_c4(),
+            ("tube", "oscillating tube 384x256x64, M=0.2, Re=185, RK3, moving, 50 steps", w.case_c4,
              ("mixed", "fp64"), 50)]
+    plan = [(name, make(), precs, steps) for key, name, make, precs, steps in plan if only in (None, key)]
     for name, case, precs, steps in plan:
         for prec in precs:
             prim = w.freestream_prim(case.ndim, case.ni, case.nj, case.nk, case.p_inf)
@@ -205,6 +208,9 @@ def main():
     import torch
     import workloads as w
 
+    if args.config_only:
+        print(json.dumps({"other_configs": other_configs(args.config_only)}), flush=True)
+        return
     case = w.case_c2(steps=args.steps)
     prim = w.freestream_prim(2, case.ni, case.nj, 1, case.p_inf)
     ncell = case.ncells
@@ -236,7 +242,7 @@ def main():
                  "unit": "TFLOP/s", "frac": round(achieved_tf / fpeak, 4)}
     # measured HBM bytes per launch (mixed path only: the counters were taken on it)
     roof["traffic"] = measured_traffic() if head == "mixed" else None
-    roof["kernel"] = "step_batch_kernel<2,%s,RK3>" % ("float" if head == "mixed" else "double")
+    roof["kernel"] = "step_batch_kernel_2f<RK3, false>" if head == "mixed" else "step_batch_kernel<2, double, RK3, false>"
     roof["kernel_avg_ms"] = round(avg_ms, 5)
     roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     roof["per_unit"] = {"flops_per_cell_update": FLOPS_PER_CELL_2D_RK3,

@@ -179,6 +179,13 @@ int ibm_info_get(const ibm_ctx *ctx, ibm_info *out);
  * stream) instead of enqueuing its kernels one by one; 0 enqueues eagerly.
  * Both give bit-identical results. */
 #define IBM_OPT_GRAPHS 1
+/* IBM_OPT_CORNER_LISTS (default 1): each tile near the body fills, before
+ * its ghost nodes, the FORCING probe corners they read outside its loaded
+ * cells, listed at classification; 0 makes every ghost node fill its own
+ * FORCING corners instead (the path a tile takes when its list does not
+ * fit).  Both give bit-identical results; takes effect at the next
+ * classification. */
+#define IBM_OPT_CORNER_LISTS 2
 #define IBM_BATCH_MAX 64
 int ibm_set_option(ibm_ctx *ctx, int option, int value);
 const char *ibm_last_error(const ibm_ctx *ctx);

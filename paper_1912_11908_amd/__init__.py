@@ -170,6 +170,11 @@ class Solver:
         """Replay whole steps as HIP graphs (stationary bodies; default on)."""
         _lib.check(self.L.ibm_set_option(self.h, 1, 1 if on else 0), "ibm_set_option", self.h)
 
+    def set_corner_lists(self, on):
+        """Fill the FORCING probe corners of ghost nodes per tile from lists
+        built at classification (default), or per ghost node."""
+        _lib.check(self.L.ibm_set_option(self.h, 2, 1 if on else 0), "ibm_set_option", self.h)
+
     def status(self):
         return self.L.ibm_status(self.h, self._s())
 

@@ -37,6 +37,7 @@ struct ibm_ctx {
     // graph replay of whole steps (stationary bodies): slot 0 holds one
     // step, slot 1 a chunk of kChunk steps
     bool use_graphs;
+    bool corner_lists;       // IBM_OPT_CORNER_LISTS
     hipStream_t cap_stream;
     hipGraph_t graph[2];
     hipGraphExec_t graph_exec[2];
@@ -653,7 +654,7 @@ int do_classify(ibm_ctx *c, double t, hipStream_t s)
     e = launch_records(c->g, c->b, c->f, c->ib, s);
     if (e != hipSuccess)
         return dev_err(c, e, "records");
-    e = launch_ghost_lists(c->g, c->ib, c->f.family == IBM_IB_QUADRATIC, s);
+    e = launch_ghost_lists(c->g, c->ib, c->f.family == IBM_IB_QUADRATIC, c->corner_lists, s);
     if (e != hipSuccess)
         return dev_err(c, e, "ghost lists");
     c->classified = true;
@@ -858,7 +859,9 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     // one launch per stage: the blocks of one XCD (same index mod 8) take a
     // contiguous chunk of the list; the near tiles, which also fill the IB
     // nodes they read, are spread evenly over the chunks and start first,
-    // then the far tiles follow in raster order
+    // then the far tiles follow in raster order.  (Chunks of whole raster
+    // runs, near tiles first, keep the cache lines neighbouring tiles share
+    // in one L2 but load the XCDs unevenly: measured slower.)
     std::vector<int32_t> list;
     {
         int nfar = (int)h.tiles_far.size(), nnear = (int)h.tiles_near.size();
@@ -895,6 +898,7 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     x->n_inner = c->n_inner;
     x->classified = false;
     x->use_graphs = true;
+    x->corner_lists = true;
     x->cap_stream = nullptr;
     for (int k = 0; k < 2; ++k) {
         x->graph[k] = nullptr;
@@ -945,6 +949,11 @@ int ibm_set_option(ibm_ctx *c, int option, int value)
     if (option == IBM_OPT_GRAPHS) {
         c->use_graphs = value != 0;
         drop_graph(c);
+        return IBM_OK;
+    }
+    if (option == IBM_OPT_CORNER_LISTS) {
+        c->corner_lists = value != 0;
+        c->classified = false;  // the lists are rebuilt by the next classification
         return IBM_OK;
     }
     return IBM_EINVAL;

@@ -129,7 +129,7 @@ hipError_t launch_pose(const Grid &g, Body &b, long long disp, int axis, hipStre
 hipError_t launch_classify(const Grid &g, const Body &b, IB &ib, hipStream_t s);
 hipError_t launch_records(const Grid &g, const Body &b, const Flow &f, IB &ib, hipStream_t s);
 // per near tile IB lists and FORCING corner lists (after the records)
-hipError_t launch_ghost_lists(const Grid &g, const IB &ib, bool quad, hipStream_t s);
+hipError_t launch_ghost_lists(const Grid &g, const IB &ib, bool quad, bool corner_lists, hipStream_t s);
 // cells a tile's stencils load (tile plus its halo) for this dimension
 int tile_load_cells(int ndim);
 

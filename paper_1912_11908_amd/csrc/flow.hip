@@ -1254,9 +1254,11 @@ template <int DIM, typename Real, int MODE, bool GHOSTS> constexpr auto batch_ke
 // loads (tile plus halo, domain ghost cells resolved as the stencils do) and
 // lists those that are IB nodes (FORCING, G1-G3), with their records; then
 // the FORCING probe corners of the listed ghost nodes that lie outside the
-// loaded cells (the ones inside are listed already).
+// loaded cells (the ones inside are listed already).  Without corner lists
+// (or when one does not fit) the count is -1: the tile's ghost nodes then
+// fill their FORCING corners themselves, with the same results.
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void ghost_lists_kernel(Grid g, IB ib, int ntx, int nty, int quad)
+__global__ __launch_bounds__(kBlock) void ghost_lists_kernel(Grid g, IB ib, int ntx, int nty, int quad, int corner_lists)
 {
     using C = TileCfg<DIM>;
     constexpr int TX = C::TX, TY = C::TY, TZ = C::TZ, HZ = C::HZ;
@@ -1318,7 +1320,7 @@ __global__ __launch_bounds__(kBlock) void ghost_lists_kernel(Grid g, IB ib, int 
     __syncthreads();
     if (threadIdx.x == 0) {
         ib.tg_cnt[slot] = nl;
-        ib.tj_cnt[slot] = nj <= ib.tg_stride ? nj : -1;
+        ib.tj_cnt[slot] = corner_lists && nj <= ib.tg_stride ? nj : -1;
     }
 }
 
@@ -1613,16 +1615,16 @@ int tile_load_cells(int ndim)
     return (T[0] + 6) * (T[1] + 6) * (T[2] + 2 * hz);
 }
 
-hipError_t launch_ghost_lists(const Grid &g, const IB &ib, bool quad, hipStream_t s)
+hipError_t launch_ghost_lists(const Grid &g, const IB &ib, bool quad, bool corner_lists, hipStream_t s)
 {
     if (ib.nslot == 0 || ib.cap == 0)
         return hipSuccess;
     const int *T = g.ndim == 2 ? kTile2 : kTile3;
     int ntx = (g.ni + T[0] - 1) / T[0], nty = (g.nj + T[1] - 1) / T[1];
     if (g.ndim == 2)
-        hipLaunchKernelGGL(ghost_lists_kernel<2>, dim3(ib.nslot), dim3(kBlock), 0, s, g, ib, ntx, nty, (int)quad);
+        hipLaunchKernelGGL(ghost_lists_kernel<2>, dim3(ib.nslot), dim3(kBlock), 0, s, g, ib, ntx, nty, (int)quad, (int)corner_lists);
     else
-        hipLaunchKernelGGL(ghost_lists_kernel<3>, dim3(ib.nslot), dim3(kBlock), 0, s, g, ib, ntx, nty, (int)quad);
+        hipLaunchKernelGGL(ghost_lists_kernel<3>, dim3(ib.nslot), dim3(kBlock), 0, s, g, ib, ntx, nty, (int)quad, (int)corner_lists);
     return hipGetLastError();
 }
 

@@ -146,6 +146,26 @@ def test_deterministic():
     assert bool((a == s2.state).all())
 
 
+@pytest.mark.parametrize("kind,precision", [("cylinder", "fp64"), ("cylinder-quad", "mixed"),
+                                            ("wedge", "mixed"), ("naca", "fp64"),
+                                            ("tube-moving", "mixed"), ("octahedron", "fp64")])
+def test_corner_lists_match_own_corners(kind, precision):
+    """Near tiles fill the FORCING probe corners of their ghost nodes from
+    per-tile lists, or (when a list does not fit) each ghost node fills its
+    own: both paths give bit-identical states."""
+    case = SMALL[kind]()
+    prim = smooth_prim(case)
+    out = []
+    for lists in (True, False):
+        s, _ = make_pair(case, prim, precision)
+        s.set_corner_lists(lists)
+        s.classify()
+        s.advance(case.steps)
+        s.check_status()
+        out.append(s.interior().clone())
+    assert bool((out[0] == out[1]).all())
+
+
 def test_nonfinite_status_reported():
     import torch
     case, prim, s, o = _classified("cylinder")
