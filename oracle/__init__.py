@@ -57,6 +57,8 @@ def lib():
         L.orc_dual_iterate.argtypes = [P, P, P, P, P, i, d, i]
         L.orc_prim_to_state.argtypes = [P, P, P]
         L.orc_state_to_prim.argtypes = [P, P, P]
+        L.orc_forces.argtypes = [P, P, P, P]
+        L.orc_forces.restype = i
         L.orc_get_class.argtypes = [P, P]
         L.orc_get_lists.argtypes = [P, P, P, P]
         L.orc_get_lists.restype = i
@@ -240,22 +242,10 @@ class Oracle:
                 self.step_index += 1
         return q
 
-    def dual_begin(self, q):
-        """Start a physical dual-time step (history rotation); returns the
-        'first step' flag to pass to dual_iterate."""
-        c = self.case
-        if not hasattr(self, "_qn"):
-            n = self.nv * self.ni * self.nj * self.nk
-            self._qn = np.zeros(n)
-            self._qnm1 = np.zeros(n)
-        first = 1 if self.step_index == 0 else 0
-        self.t += c.dt
-        lib().orc_dual_begin(self.h, _p(q), _p(self._qn), _p(self._qnm1), first, self.t)
-        self.step_index += 1
-        return first
-
-    def dual_iterate(self, q, first, n_iter):
-        wt = q.copy()
-        lib().orc_dual_iterate(self.h, _p(q), _p(wt), _p(self._qn), _p(self._qnm1), first,
-                               self.t, n_iter)
-        return q
+    def forces(self, q):
+        """Section 6, eq.9 on a filled state q: (F[3], per-facet rows
+        [p - p_inf, (tau n)_x, (tau n)_y, (tau n)_z, area], facets missed)."""
+        F = np.zeros(3)
+        per = np.zeros((max(len(self.case.facet), 1), 5))
+        missed = lib().orc_forces(self.h, _p(q), _p(F), _p(per))
+        return F, per[:len(self.case.facet)], missed

@@ -59,6 +59,9 @@ void orc_prim_to_state(orc *o, const double *prim, double *q);
 void orc_state_to_prim(orc *o, const double *q, double *prim);
 
 /* accessors for tests */
+/* section 6, eq.9: force on the body of a filled state; returns the number
+ * of facets with no FLUID / FORCING centre around their centroid */
+int orc_forces(orc *o, const double *q, double *F, double *facet_out);
 void orc_get_class(orc *o, uint8_t *cls);
 int orc_get_lists(orc *o, int32_t *listF, int32_t *listG, int32_t *counts);
 void orc_get_records(orc *o, int which, int32_t *ifeat, double *dfeat);
