@@ -142,6 +142,24 @@ int ibm_fill(ibm_ctx *ctx, double *d_q, double t, void *stream);
  * boundary types. */
 int ibm_residual(ibm_ctx *ctx, const double *d_q, double *d_r, void *stream);
 
+/* Section 6, eq.9: the force on the body, F_i = surface integral of
+ * (-P delta_ij + tau_ij) n_j, from the state d_q, whose IB nodes and halo
+ * must be filled (ibm_fill), at the pose of the last classification.  One
+ * point per facet (centroid; 2D: segment midpoint) weighted by the facet's
+ * length (per unit span) or area, outward unit normal; P - p_inf and the
+ * velocity gradient at the point by inverse-distance weights (1/r^2) over the
+ * centres of the enclosing cell box that are FLUID or FORCING (a centre at
+ * r = 0 takes the whole weight), the gradient at a cell by central
+ * differences over its face neighbours; tau = mu (grad u + grad u^T -
+ * 2/3 div u I).  Nondimensional (rho_inf U_inf^2 L^(ndim-1)).
+ * d_force: device, 3 doubles (F_z = 0 in 2D).  d_facet: device or NULL,
+ * nfacet rows of 5 doubles: P - p_inf, (tau n)_x, (tau n)_y, (tau n)_z, area.
+ * d_missed: device int32 or NULL: facets with no FLUID / FORCING centre
+ * around them (they add nothing).  Asynchronous on stream; the sums are
+ * taken in a fixed order (reproducible).  IBM_EINVAL without a body. */
+int ibm_forces(ibm_ctx *ctx, const double *d_q, double *d_force, double *d_facet, int32_t *d_missed,
+               void *stream);
+
 /* a1-a10: advance nsteps SSP-RK3 steps (IBM_RK3) or physical dual-time steps
  * of n_inner pseudo-iterations each (IBM_DUAL), in place on d_q.  Moving
  * bodies are reclassified at the pose of each step's start time.  The

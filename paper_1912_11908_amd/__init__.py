@@ -153,6 +153,23 @@ class Solver:
         q = self.state if q is None else q
         _lib.check(self.L.ibm_fill(self.h, self._p(q), float(t), self._s()), "ibm_fill", self.h)
 
+    def forces(self, q=None, facets=False):
+        """Section 6, eq.9 on a filled state (call fill first): the force on
+        the body as a float64 device tensor [3]; with facets, also the
+        per-facet rows [P - p_inf, (tau n)_x, (tau n)_y, (tau n)_z, area] and
+        the count of facets without a valid centre (device tensors)."""
+        torch = _torch()
+        q = self.state if q is None else q
+        F = torch.zeros(3, dtype=torch.float64, device=self.device)
+        rows = torch.zeros((max(self.case.facet.shape[0], 1), 5), dtype=torch.float64,
+                           device=self.device) if facets else None
+        missed = torch.zeros(1, dtype=torch.int32, device=self.device)
+        _lib.check(self.L.ibm_forces(self.h, self._p(q), self._p(F), self._p(rows) if facets else None,
+                                     self._p(missed), self._s()), "ibm_forces", self.h)
+        if facets:
+            return F, rows[:self.case.facet.shape[0]], missed
+        return F
+
     def residual(self, q=None):
         torch = _torch()
         q = self.state if q is None else q

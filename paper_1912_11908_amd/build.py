@@ -18,7 +18,8 @@ ARCH = os.environ.get("IBM_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument", "-I", os.path.join(HERE, "..", "include")]
-SOURCES = [("geometry.hip", ["-ffp-contract=off"]), ("flow.hip", []), ("api.cpp", ["-x", "hip"])]
+SOURCES = [("geometry.hip", ["-ffp-contract=off"]), ("forces.hip", ["-ffp-contract=off"]), ("flow.hip", []),
+           ("api.cpp", ["-x", "hip"])]
 
 
 def hipcc():

@@ -29,11 +29,12 @@ struct ibm_ctx {
     long long step;
     int n_inner;
     bool classified;
-    // tile lists of the two stage launches (device): the first holds far
-    // tiles only, the second the near tiles spread over the XCD chunks and
-    // the remaining far tiles, padded with -1
-    const int32_t *tiles;    // the stage launch's tile list (body present)
+    // the stage launch's tile list (device, body present): eight XCD
+    // chunks, near tiles spread over them first, padded with -1
+    const int32_t *tiles;
     int ntiles;
+    double *fpart;           // surface force block sums
+    int32_t *fmissed;        // surface force: facets without a valid centre
     // graph replay of whole steps (stationary bodies): slot 0 holds one
     // step, slot 1 a chunk of kChunk steps
     bool use_graphs;
@@ -43,8 +44,9 @@ struct ibm_ctx {
     hipGraphExec_t graph_exec[2];
     const double *graph_q[2];
     // batched serving: device argument blocks of every stage launch of a
-    // step (RK3: 3 stages x 2 launches; dual time: first / later step x
-    // iteration parity x 2 launches), prepared for the state batch_q
+    // step (RK3: 3 stages x 2 kernel kinds; dual time: first / later step x
+    // iteration parity x 2 kernel kinds; one kind is empty per solve),
+    // prepared for the state batch_q
     void *d_args;
     int slot_nblk[kSlots];
     const double *batch_q;
@@ -524,6 +526,8 @@ struct Layout {
     double *rec_d;
     int32_t *plan_node, *plan_off, *plan_mode, *plan_frec;
     double *plan_w, *plan_geo, *fval;
+    double *fpart;           // surface force block sums
+    int32_t *fmissed;        // surface force: facets without a valid centre
     int32_t *rmap;
     int32_t *tile_slot, *slot_tile, *tg_cnt, *tg_t, *tg_rec, *tj_cnt, *tj_rec;
     int32_t *tiles;
@@ -578,6 +582,8 @@ size_t carve(const ibm_case *c, const HostGeom &h, char *base, Layout &L)
     L.plan_mode = cv.take<int32_t>(cap);
     L.plan_frec = cv.take<int32_t>(16 * cap);
     L.fval = cv.take<double>((size_t)(nd + 2) * cap);
+    L.fpart = cv.take<double>((size_t)3 * std::max(forces_blocks(c->nfacet), 1));
+    L.fmissed = cv.take<int32_t>(1);
     L.rmap = cv.take<int32_t>(cap);
     {
         size_t ntile = h.tiles_far.size() + h.tiles_near.size(), nslot = h.tiles_near.size();
@@ -906,6 +912,8 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
         x->graph_q[k] = nullptr;
     }
     x->d_args = L.args;
+    x->fpart = L.fpart;
+    x->fmissed = L.fmissed;
     x->batch_q = nullptr;
     for (int k = 0; k < kSlots; ++k)
         x->slot_nblk[k] = 0;
@@ -984,6 +992,24 @@ int ibm_fill(ibm_ctx *c, double *q, double t, void *stream)
             return rc;
     }
     return do_fill(c, q, t, S(stream));
+}
+
+int ibm_forces(ibm_ctx *c, const double *q, double *force, double *facet_out, int32_t *missed, void *stream)
+{
+    if (!c || !q || !force)
+        return IBM_EINVAL;
+    if (c->b.nfacet == 0)
+        return IBM_EINVAL;
+    if (!c->classified) {
+        int rc = do_classify(c, c->t, S(stream));
+        if (rc)
+            return rc;
+    }
+    int32_t *m = missed ? missed : c->fmissed;
+    hipError_t e = hipMemsetAsync(m, 0, sizeof(int32_t), S(stream));
+    if (e == hipSuccess)
+        e = launch_forces(c->g, c->b, c->f, c->ib, q, force, facet_out, c->fpart, m, S(stream));
+    return dev_err(c, e, "forces");
 }
 
 int ibm_residual(ibm_ctx *c, const double *q, double *r, void *stream)

@@ -128,6 +128,11 @@ struct Motion {
 hipError_t launch_pose(const Grid &g, Body &b, long long disp, int axis, hipStream_t s);
 hipError_t launch_classify(const Grid &g, const Body &b, IB &ib, hipStream_t s);
 hipError_t launch_records(const Grid &g, const Body &b, const Flow &f, IB &ib, hipStream_t s);
+// forces.hip: surface force (eq.9) of a filled state; part holds
+// 3 * forces_blocks(nfacet) doubles
+int forces_blocks(int nfacet);
+hipError_t launch_forces(const Grid &g, const Body &b, const Flow &f, const IB &ib, const double *q, double *force,
+                         double *facet_out, double *part, int32_t *missed, hipStream_t s);
 // per near tile IB lists and FORCING corner lists (after the records)
 hipError_t launch_ghost_lists(const Grid &g, const IB &ib, bool quad, bool corner_lists, hipStream_t s);
 // cells a tile's stencils load (tile plus its halo) for this dimension
