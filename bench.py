@@ -121,13 +121,15 @@ def other_configs(only=None):
     import workloads as w
     import paper_1912_11908_amd as P
     out = {}
-    plan = [("cylinder", "cylinder 128x128, M=0.3, Re=40, RK3, 200 steps", w.case_c1, ("fp64",), 200),
+    # reference length (2D, per unit span) or area for the force coefficients
+    plan = [("cylinder", "cylinder 128x128, M=0.3, Re=40, RK3, 200 steps", w.case_c1, ("fp64",), 200, 1.0),
             ("airfoil", "NACA0012 2048x1024, M=0.001, Re=1000, dual time, 10 physical steps", w.case_c3,
-             ("mixed", "fp64"), 10),
+             ("mixed", "fp64"), 10, 1.0),
             ("tube", "oscillating tube 384x256x64, M=0.2, Re=185, RK3, moving, 50 steps", w.case_c4,
-             ("mixed", "fp64"), 50)]
-    plan = [(name, make(), precs, steps) for key, name, make, precs, steps in plan if only in (None, key)]
-    for name, case, precs, steps in plan:
+             ("mixed", "fp64"), 50, 4.0)]
+    plan = [(name, make(), precs, steps, lref) for key, name, make, precs, steps, lref in plan
+            if only in (None, key)]
+    for name, case, precs, steps, lref in plan:
         for prec in precs:
             prim = w.freestream_prim(case.ndim, case.ni, case.nj, case.nk, case.p_inf)
             s = P.Solver(case, prec, "cuda:0")
@@ -142,6 +144,23 @@ def other_configs(only=None):
             out[f"{name} [{prec}]"] = {
                 "cell_updates_per_s": case.ncells * case.evals_per_step * steps / dt,
                 "ms_per_step": dt * 1e3 / steps}
+            # surface force of the final state (eq.9): coefficients and the
+            # device time of one evaluation (fill excluded)
+            t_end = s.info().time
+            s.set_time(t_end)
+            s.classify()
+            s.fill(t_end)
+            nrep = 20
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(nrep):
+                F = s.forces()
+            torch.cuda.synchronize()
+            tf = (time.perf_counter() - t0) / nrep
+            F = F.cpu().numpy()
+            out[f"{name} [{prec}]"]["forces"] = {
+                "C_x": float(2.0 * F[0] / lref), "C_y": float(2.0 * F[1] / lref),
+                "facets": int(case.facet.shape[0]), "ms_per_evaluation": tf * 1e3}
             del s
     return out
 

@@ -50,3 +50,23 @@ def test_forces_match_oracle(kind, precision, t):
     bound = 1e-11 * terms.sum(axis=0) + floor * per[:, 4].sum() + 1e-300
     assert np.all(np.abs(F - Fo)[:nd] <= bound[:nd]), (F, Fo)
     assert F[2] == 0.0 or nd == 3
+
+
+def test_symmetric_airfoil_has_no_lift():
+    """NACA 00xx at zero incidence on a grid symmetric about its chord, in a
+    uniform stream: the solution stays mirror-symmetric, so the lift is zero
+    up to rounding (a property that holds at any size)."""
+    import torch
+    import workloads as w
+    case = SMALL["naca"]()
+    prim = w.freestream_prim(2, case.ni, case.nj, 1, case.p_inf)
+    for precision in ("fp64", "mixed"):
+        s, _ = make_pair(case, prim, precision)
+        s.advance(case.steps)
+        t = s.info().time
+        s.fill(t)
+        F = s.forces().cpu().numpy()
+        torch.cuda.synchronize()
+        s.check_status()
+        assert F[0] > 0.0
+        assert abs(F[1]) <= 1e-7 * abs(F[0]), (precision, F)
