@@ -63,6 +63,7 @@ enum { IBM_RK3 = 0, IBM_DUAL = 1 };
 enum { IBM_IB_LINEAR = 0, IBM_IB_QUADRATIC = 1 };
 enum { IBM_FP64 = 0, IBM_MIXED = 1 };
 enum { IBM_FLUID = 0, IBM_FORCING = 1, IBM_G1 = 2, IBM_G2 = 3, IBM_G3 = 4, IBM_SOLID = 5 };
+enum { IBM_WALL_EQ6 = 0, IBM_WALL_EQ7 = 1 };
 
 /* Case descriptor; all pointers are host pointers, copied by ibm_create. */
 typedef struct ibm_case {
@@ -77,7 +78,8 @@ typedef struct ibm_case {
                               /* seen from outside                                 */
     int motion;               /* 0: stationary; 1: translation along one axis      */
     double motion_par[4];     /* axis, amplitude A, frequency f, phase:            */
-                              /* x_axis(t) = A cos(2 pi f t + phase) (section 8.2.2) */
+                              /* x_axis(t) = A cos(2 pi f t + phase) + V t         */
+                              /* (section 8.2.2; V = motion_vel, section 8.2.3)    */
     double mach, reynolds, prandtl, gamma;
     int scheme;               /* IBM_RK3 or IBM_DUAL                               */
     int ib_family;            /* IBM_IB_LINEAR (IDW + image point) or QUADRATIC    */
@@ -86,6 +88,13 @@ typedef struct ibm_case {
     double dt;                /* physical time step                                */
     double cfl_tau;           /* pseudo-time CFL (dual time)                       */
     int n_inner;              /* pseudo-iterations per physical step (dual time)   */
+    double u_inf[3];          /* free-stream velocity (unused components 0); M and */
+                              /* Re take unit reference speed: |u_inf| = 1, or     */
+                              /* u_inf = 0 for a body moving in still fluid        */
+    double motion_vel;        /* V: constant speed along the motion axis           */
+    int wall_pressure;        /* IBM_WALL_EQ6: dp/dn = -rho a_n (eq.6);            */
+                              /* IBM_WALL_EQ7: dp/dn = rho u_t^2 / R - rho a_n     */
+                              /* (eq.7, supersonic moving bodies; 2D only)         */
 } ibm_case;
 
 typedef struct ibm_ctx ibm_ctx;

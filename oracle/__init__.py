@@ -43,7 +43,7 @@ def lib():
         P = ctypes.c_void_p
         d, i = ctypes.c_double, ctypes.c_int
         L.orc_create.restype = P
-        L.orc_create.argtypes = [i, i, i, i, P, P, P, P, i, i, P, P, d, d, d, d, i, i, d, d, i, i, P]
+        L.orc_create.argtypes = [i, i, i, i, P, P, P, P, i, i, P, P, d, d, d, d, i, i, d, d, i, i, P, P, i]
         L.orc_destroy.argtypes = [P]
         L.orc_set_pose.argtypes = [P, d]
         L.orc_classify.argtypes = [P]
@@ -114,12 +114,14 @@ class Oracle:
         facet = arr(c.facet.reshape(-1) if len(c.facet) else np.zeros(1, np.int32), np.int32)
         mo = c.motion or {}
         mpar = arr([mo.get("axis", 0), mo.get("amplitude", 0.0), mo.get("frequency", 0.0),
-                    mo.get("phase", 0.0)], np.float64)
+                    mo.get("phase", 0.0), mo.get("velocity", 0.0)], np.float64)
+        uinf = arr(list(c.u_inf) + [0.0] * (3 - len(c.u_inf)), np.float64)
         self.h = lib().orc_create(
             c.ndim, c.ni, c.nj, c.nk, _p(xf), _p(yf), _p(zf), _p(bc), len(c.vert), len(c.facet),
             _p(vert), _p(facet), c.mach, c.reynolds, c.prandtl, c.gamma,
             0 if c.scheme == "rk3" else 1, 0 if c.ib_family == "linear" else 1, c.dt,
-            c.cfl_tau, c.n_inner, 1 if mo else 0, _p(mpar))
+            c.cfl_tau, c.n_inner, 1 if mo else 0, _p(mpar), _p(uinf),
+            {"eq6": 0, "eq7": 1}[c.wall_pressure])
         self.t = 0.0
         self.step_index = 0
 

@@ -49,7 +49,9 @@ struct orc {
     double dt, cfl_tau;
     int n_inner;
     int motion, maxis;
-    double mamp, mfreq, mphase;
+    double mamp, mfreq, mphase, mvel;
+    double uinf[3];       /* free-stream velocity */
+    int wallp;            /* ORC_WALL_EQ6 / ORC_WALL_EQ7 */
     i64 disp;
     /* classification */
     uint8_t *cls, *cls_prev;
@@ -236,7 +238,7 @@ orc *orc_create(int ndim, int ni, int nj, int nk, const double *xf, const double
                 const double *zf, const int *bc, int nvert, int nfacet, const double *vert,
                 const int *facet, double mach, double re, double pr, double gamma, int scheme,
                 int family, double dt, double cfl_tau, int n_inner, int motion,
-                const double *mpar)
+                const double *mpar, const double *uinf, int wall_pressure)
 {
     orc *o = (orc *)calloc(1, sizeof(orc));
     o->ndim = ndim;
@@ -279,8 +281,12 @@ orc *orc_create(int ndim, int ni, int nj, int nk, const double *xf, const double
     o->facet = (int *)malloc(sizeof(int) * (size_t)(nfacet > 0 ? nfacet : 1) * ndim);
     memcpy(o->facet, facet, sizeof(int) * (size_t)nfacet * ndim);
 
-    /* c.0 reading: rho_inf = U_inf = T_inf = L = 1, so p_inf = R = 1/(gamma M^2);
+    /* c.0 reading: rho_inf = T_inf = L = 1 and unit reference speed (the
+     * free stream's, or the body's in still fluid), so p_inf = R = 1/(gamma M^2);
      * constant mu = 1/Re, Pr fixed, Stokes hypothesis. */
+    for (int d = 0; d < 3; d++)
+        o->uinf[d] = uinf[d];
+    o->wallp = wall_pressure;
     o->gamma = gamma;
     o->mach = mach;
     o->re = re;
@@ -305,8 +311,9 @@ orc *orc_create(int ndim, int ni, int nj, int nk, const double *xf, const double
         if (ndim == 3)
             for (int k = 0; k < nk; k++)
                 hmin = fmin(hmin, zf[k + 1] - zf[k]);
-        double a = 1.0, b = o->mu / hmin, c = hmin / (M_PI * dt);
-        o->uc2 = fmax(a * a, fmax(b * b, c * c));
+        double a2 = o->uinf[0] * o->uinf[0] + o->uinf[1] * o->uinf[1] + o->uinf[2] * o->uinf[2];
+        double b = o->mu / hmin, c = hmin / (M_PI * dt);
+        o->uc2 = fmax(a2, fmax(b * b, c * c));
     }
     o->motion = motion;
     if (motion) {
@@ -314,6 +321,7 @@ orc *orc_create(int ndim, int ni, int nj, int nk, const double *xf, const double
         o->mamp = mpar[1];
         o->mfreq = mpar[2];
         o->mphase = mpar[3];
+        o->mvel = mpar[4];
     }
     long ncell = (long)ni * nj * o->nk;
     o->cls = (uint8_t *)calloc(ncell, 1);
@@ -342,13 +350,15 @@ void orc_destroy(orc *o)
 /* Prescribed translation along one axis, y(t) = A cos(2 pi f t + phase)
  * (section 8.2.2 motion law).  The displacement is snapped to the lattice and
  * added to the integer vertices, so posed coordinates stay exact. */
+/* x_axis(t) = A cos(2 pi f t + phase) + V t: the oscillation of section 8.2.2
+ * plus a constant speed (section 8.2.3) */
 static double pose_disp(const orc *o, double t)
 {
-    return o->mamp * cos(2.0 * M_PI * o->mfreq * t + o->mphase);
+    return o->mamp * cos(2.0 * M_PI * o->mfreq * t + o->mphase) + o->mvel * t;
 }
 static double pose_vel(const orc *o, double t)
 {
-    return -2.0 * M_PI * o->mfreq * o->mamp * sin(2.0 * M_PI * o->mfreq * t + o->mphase);
+    return -2.0 * M_PI * o->mfreq * o->mamp * sin(2.0 * M_PI * o->mfreq * t + o->mphase) + o->mvel;
 }
 static double pose_acc(const orc *o, double t)
 {
@@ -1095,8 +1105,8 @@ void orc_state_to_prim(orc *o, const double *q, double *prim)
 static void freestream_prim(const orc *o, prim_t *w)
 {
     w->rho = 1.0;
-    w->u[0] = 1.0;
-    w->u[1] = w->u[2] = 0.0;
+    for (int d = 0; d < 3; d++)
+        w->u[d] = o->uinf[d];
     w->p = o->pinf;
     w->T = 1.0;
 }

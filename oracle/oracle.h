@@ -28,12 +28,13 @@ enum { ORC_FLUID = 0, ORC_FORCING = 1, ORC_G1 = 2, ORC_G2 = 3, ORC_G3 = 4, ORC_S
 enum { ORC_BC_FARFIELD = 0, ORC_BC_EXTRAP = 1, ORC_BC_PERIODIC = 2 };
 enum { ORC_RK3 = 0, ORC_DUAL = 1 };
 enum { ORC_IB_LINEAR = 0, ORC_IB_QUADRATIC = 1 };
+enum { ORC_WALL_EQ6 = 0, ORC_WALL_EQ7 = 1 };
 
 orc *orc_create(int ndim, int ni, int nj, int nk, const double *xf, const double *yf,
                 const double *zf, const int *bc, int nvert, int nfacet, const double *vert,
                 const int *facet, double mach, double re, double pr, double gamma, int scheme,
                 int family, double dt, double cfl_tau, int n_inner, int motion,
-                const double *mpar);
+                const double *mpar, const double *uinf, int wall_pressure);
 void orc_destroy(orc *o);
 
 /* a1: body pose at time t (no-op for a stationary body). */

@@ -55,6 +55,11 @@ def case_struct(case, precision="fp64"):
     c.ib_family = 0 if case.ib_family == "linear" else 1
     c.precision = {"fp64": 0, "mixed": 1}[precision]
     c.dt, c.cfl_tau, c.n_inner = case.dt, case.cfl_tau, case.n_inner
+    u = list(getattr(case, "u_inf", (1.0, 0.0, 0.0)))
+    for d in range(3):
+        c.u_inf[d] = float(u[d]) if d < len(u) else 0.0
+    c.motion_vel = float(mo.get("velocity", 0.0))
+    c.wall_pressure = {"eq6": 0, "eq7": 1}[getattr(case, "wall_pressure", "eq6")]
     return c, keep
 
 

@@ -117,6 +117,15 @@ int check_desc(const ibm_case *c)
         return IBM_EINVAL;
     if (c->motion && (c->motion_par[0] < 0 || c->motion_par[0] >= c->ndim))
         return IBM_EINVAL;
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(c->u_inf[d]) || (d >= c->ndim && c->u_inf[d] != 0.0))
+            return IBM_EINVAL;
+    if (!std::isfinite(c->motion_vel) || (c->motion_vel != 0.0 && !c->motion))
+        return IBM_EINVAL;
+    if (c->wall_pressure != IBM_WALL_EQ6 && c->wall_pressure != IBM_WALL_EQ7)
+        return IBM_EINVAL;
+    if (c->wall_pressure == IBM_WALL_EQ7 && c->ndim != 2)
+        return IBM_EINVAL;
     return IBM_OK;
 }
 
@@ -483,6 +492,10 @@ int host_geom(const ibm_case *c, HostGeom &h)
                 double a = std::fabs(c->motion_par[1]) + 1e-6;
                 lo -= a;
                 hi += a;
+                if (c->motion_vel != 0.0) {  // unbounded travel: the whole axis
+                    lo = -1e300;
+                    hi = 1e300;
+                }
             }
             int i0 = 0, i1 = n;
             while (i0 < n && h.xc[d][i0 + 3] < lo)
@@ -632,8 +645,8 @@ hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 void motion_kin(const ibm_ctx *c, double t, double &disp, double &vel, double &acc)
 {
     double w = 2.0 * M_PI * c->mo.freq;
-    disp = c->mo.amp * std::cos(w * t + c->mo.phase);
-    vel = -w * c->mo.amp * std::sin(w * t + c->mo.phase);
+    disp = c->mo.amp * std::cos(w * t + c->mo.phase) + c->mo.vel * t;
+    vel = -w * c->mo.amp * std::sin(w * t + c->mo.phase) + c->mo.vel;
     acc = -w * w * c->mo.amp * std::cos(w * t + c->mo.phase);
 }
 
@@ -803,7 +816,13 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     f.mu = 1.0 / c->reynolds;
     f.kc = f.mu * f.cp / c->prandtl;
     f.pr = c->prandtl;
-    f.Hinf = c->gamma / (c->gamma - 1.0) * f.pinf + 0.5;
+    f.uinf2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        f.uinf[d] = c->u_inf[d];
+        f.uinf2 += c->u_inf[d] * c->u_inf[d];
+    }
+    f.wallp = c->wall_pressure;
+    f.Hinf = c->gamma / (c->gamma - 1.0) * f.pinf + 0.5 * f.uinf2;
     f.dt = c->dt;
     f.cfl_tau = c->cfl_tau;
     f.scheme = c->scheme;
@@ -815,8 +834,8 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
         for (int d = 0; d < nd; ++d)
             for (int i = 0; i < h.n[d]; ++i)
                 hmin = std::min(hmin, h.xf[d][i + 4] - h.xf[d][i + 3]);
-        double a = 1.0, bb = f.mu / hmin, cc = hmin / (M_PI * c->dt);
-        f.uc2 = std::max(a * a, std::max(bb * bb, cc * cc));
+        double bb = f.mu / hmin, cc = hmin / (M_PI * c->dt);
+        f.uc2 = std::max(f.uinf2, std::max(bb * bb, cc * cc));
     }
     IB &ib = x->ib;
     for (int s = 0; s < 6; ++s)
@@ -894,6 +913,7 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     x->mo.amp = c->motion_par[1];
     x->mo.freq = c->motion_par[2];
     x->mo.phase = c->motion_par[3];
+    x->mo.vel = c->motion_vel;
     x->q1 = L.q1;
     x->q2 = L.q2;
     x->wtmp = L.wtmp;

@@ -56,7 +56,9 @@ struct Body {
 
 struct Flow {
     double gamma, pinf, R, cp, mu, kc, pr, uc2, Hinf, dt, cfl_tau;
+    double uinf[3], uinf2;   // free-stream velocity and its square
     int scheme, family, precision;
+    int wallp;               // IBM_WALL_EQ6 / IBM_WALL_EQ7
 };
 
 // Immersed-boundary work area.
@@ -120,7 +122,7 @@ struct StagePart {
 
 struct Motion {
     int on, axis;
-    double amp, freq, phase;
+    double amp, freq, phase, vel;
 };
 
 // ------------------------------------------------------------ launchers

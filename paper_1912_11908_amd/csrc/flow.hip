@@ -488,7 +488,7 @@ __device__ inline void weno5_pair(R v0, R v1, R v2, R v3, R v4, R v5, R &wl, R &
 }
 
 template <typename R> struct FlowR {
-    R gamma, gm1inv, pinf, mu, kc, uc2;
+    R gamma, gm1inv, pinf, mu, kc, uc2, uinf2;
     bool precond;
 };
 
@@ -580,8 +580,8 @@ __device__ inline void ldfss_pert(const R *wl, const R *wr, const FlowR<R> &fp, 
     for (int e = 0; e < ND; ++e)
         fl_out[1 + e] = fl * wl[1 + e] + fr * wr[1 + e] + (e == d ? pf : R(0));
     R g1 = fp.gamma * fp.gm1inv;
-    R hl = g1 * (plp - fp.pinf * wl[0]) * rcp_fast<R>(rl) + R(0.5) * (ql2 - R(1));
-    R hr = g1 * (prp - fp.pinf * wr[0]) * rcp_fast<R>(rr) + R(0.5) * (qr2 - R(1));
+    R hl = g1 * (plp - fp.pinf * wl[0]) * rcp_fast<R>(rl) + R(0.5) * (ql2 - fp.uinf2);
+    R hr = g1 * (prp - fp.pinf * wr[0]) * rcp_fast<R>(rr) + R(0.5) * (qr2 - fp.uinf2);
     fl_out[NV - 1] = fl * hl + fr * hr;
 }
 
@@ -909,6 +909,7 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
     fp.mu = (Real)f.mu;
     fp.kc = (Real)f.kc;
     fp.uc2 = (Real)f.uc2;
+    fp.uinf2 = (Real)f.uinf2;
     fp.precond = f.scheme == IBM_DUAL;
     // 2. face fluxes, one pass per direction (compile-time direction)
     int fl0 = (tz * TY + ty) * (TX + 1) + tx;  // x-face at i - 1/2
@@ -1047,8 +1048,8 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
         double Qp[N];
         Qp[0] = rhop;
         for (int d = 0; d < DIM; ++d)
-            Qp[1 + d] = rhop * u[d] + (u[d] - (d == 0 ? 1.0 : 0.0));
-        Qp[N - 1] = pp / (f.gamma - 1.0) + 0.5 * (rhop * q2 + q2 - 1.0);
+            Qp[1 + d] = rhop * u[d] + (u[d] - f.uinf[d]);
+        Qp[N - 1] = pp / (f.gamma - 1.0) + 0.5 * (rhop * q2 + q2 - f.uinf2);
         double rhs[N];
         for (int m = 0; m < N; ++m) {
             double qn = A.qn[m * g.ncell + cell], qm = A.qnm1[m * g.ncell + cell];
@@ -1057,7 +1058,7 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
         // energy row minus H times the mass row: exact row operation that
         // removes the O(H) terms (H' = c_p T' + (|u|^2 - 1) / 2)
         double H = f.cp * T + 0.5 * q2;
-        double Hp = f.cp * tp + 0.5 * (q2 - 1.0);
+        double Hp = f.cp * tp + 0.5 * (q2 - f.uinf2);
         {
             double qn0 = A.qn[cell], qm0 = A.qnm1[cell];
             double qnE = A.qn[(N - 1) * g.ncell + cell], qmE = A.qnm1[(N - 1) * g.ncell + cell];
@@ -1345,8 +1346,8 @@ __global__ void dual_begin_kernel(Grid g, Flow f, const double *w, double *qn, d
     double Q[5];
     Q[0] = rhop;
     for (int d = 0; d < nd; ++d)
-        Q[1 + d] = rhop * u[d] + (u[d] - (d == 0 ? 1.0 : 0.0));
-    Q[N - 1] = pp / (f.gamma - 1.0) + 0.5 * (rhop * q2 + q2 - 1.0);
+        Q[1 + d] = rhop * u[d] + (u[d] - f.uinf[d]);
+    Q[N - 1] = pp / (f.gamma - 1.0) + 0.5 * (rhop * q2 + q2 - f.uinf2);
     // the first step (BDF1) weights Q'^{n-1} by zero; it is set to Q'^n so
     // that the term is an exact zero whatever the workspace held
     for (int m = 0; m < N; ++m) {
@@ -1405,10 +1406,12 @@ FreeStream freestream_of(const Grid &g, const Flow &f)
         fs.v[m] = 0.0;
     if (f.scheme == IBM_RK3) {
         fs.v[0] = 1.0;
-        fs.v[1] = 1.0;
-        fs.v[g.nv - 1] = f.pinf / (f.gamma - 1.0) + 0.5;
+        for (int d = 0; d < g.ndim; ++d)
+            fs.v[1 + d] = f.uinf[d];
+        fs.v[g.nv - 1] = f.pinf / (f.gamma - 1.0) + 0.5 * f.uinf2;
     } else {
-        fs.v[1] = 1.0;
+        for (int d = 0; d < g.ndim; ++d)
+            fs.v[1 + d] = f.uinf[d];
     }
     return fs;
 }

@@ -14,7 +14,7 @@ def smooth_prim(case, seed=0, amp=0.03, u_amp=0.1):
     # than the flow itself at low Mach
     p_amp = amp * min(1.0, case.gamma * case.mach ** 2)
     prim = w.random_periodic_prim(case.ndim, case.xf, case.yf, case.zf, case.p_inf, seed=seed,
-                                  amp=amp, u_amp=u_amp, p_amp=p_amp)
+                                  amp=amp, u_amp=u_amp, p_amp=p_amp, u_base=case.u_inf)
     return prim
 
 

@@ -34,8 +34,13 @@ class Case:
     dt: float = 0.0
     cfl_tau: float = 0.5
     n_inner: int = 20
-    motion: dict = field(default_factory=dict)   # {} or {axis, amplitude, frequency, phase}
+    # {} or {axis, amplitude, frequency, phase[, velocity]}:
+    # x_axis(t) = amplitude cos(2 pi frequency t + phase) + velocity t
+    motion: dict = field(default_factory=dict)
     steps: int = 1                 # RK3 steps, or physical steps for dual time
+    # free-stream velocity (unit speed, or zero for a body moving through still fluid)
+    u_inf: tuple = (1.0, 0.0, 0.0)
+    wall_pressure: str = "eq6"     # "eq6" | "eq7" (supersonic moving body, 2D)
 
     @property
     def ni(self):
@@ -147,6 +152,18 @@ def small_case(kind, n=64, steps=2, **kw):
         return Case(f"small-moving-cylinder-{n}", 2, f, f.copy(), _z_dummy(),
                     ("farfield",) * 4 + ("periodic",) * 2, v, s, 0.2, 185.0,
                     dt=rk3_dt(0.2, 185.0, [f, f]), motion=motion, steps=steps)
+    if kind == "supersonic-moving-cylinder":
+        # section 8.2.3 in miniature: the body moves at unit speed (M, Re on
+        # that speed) through still fluid
+        xf = uniform_faces(2 * n, -6.0, 2.0)
+        yf = uniform_faces(n, -2.0, 2.0)
+        v, s = circle_polygon(kw.get("nseg", 64), 1.0)
+        m = kw.get("mach", 1.2)
+        motion = dict(axis=0, amplitude=0.0, frequency=0.0, phase=0.0, velocity=-1.0)
+        return Case(f"small-supersonic-moving-cylinder-{2*n}x{n}", 2, xf, yf, _z_dummy(),
+                    ("farfield",) * 4 + ("periodic",) * 2, v, s, m, 300.0,
+                    dt=rk3_dt(m, 300.0, [xf, yf]), motion=motion, steps=steps,
+                    u_inf=(0.0, 0.0, 0.0), wall_pressure=kw.get("wall_pressure", "eq6"))
     if kind == "wedge":
         xf = uniform_faces(2 * n, -1.0, 3.0)
         yf = tanh_center_faces(n, -2.0, 2.0, 1.02)

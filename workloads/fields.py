@@ -23,12 +23,12 @@ def freestream_prim(ndim, ni, nj, nk, p_ref, velocity=(1.0, 0.0, 0.0), rho=1.0):
 
 
 def random_periodic_prim(ndim, xf, yf, zf, p_ref, seed=0, modes=3, amp=0.05,
-                         u_amp=0.3, p_amp=None):
+                         u_amp=0.3, p_amp=None, u_base=(1.0, 0.0, 0.0)):
     """Smooth periodic random field: a few Fourier modes per variable with
     seeded amplitudes and phases (numpy PCG64).  The box must be periodic in
     every direction for the field to be smooth across the boundaries.
     Relative amplitudes: amp for density, p_amp (default amp) for pressure,
-    u_amp absolute for velocity."""
+    u_amp absolute for velocity (about u_base)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     xs = [_centres(xf), _centres(yf)] + ([_centres(zf)] if ndim == 3 else [np.zeros(1)])
     lens = [xf[-1] - xf[0], yf[-1] - yf[0], (zf[-1] - zf[0]) if ndim == 3 else 1.0]
@@ -51,7 +51,7 @@ def random_periodic_prim(ndim, xf, yf, zf, p_ref, seed=0, modes=3, amp=0.05,
     out = np.empty((nv,) + x.shape)
     out[0] = 1.0 + amp * smooth()
     for d in range(ndim):
-        out[1 + d] = (1.0 if d == 0 else 0.0) + u_amp * smooth()
+        out[1 + d] = u_base[d] + u_amp * smooth()
     out[nv - 1] = p_ref * (1.0 + (amp if p_amp is None else p_amp) * smooth())
     return out
 
