@@ -42,6 +42,7 @@ struct orc {
     double *vnrm;       /* vertex pseudo-normals */
     int *edge_of;       /* 3D: per facet edge, global edge id */
     double *enrm;       /* 3D: edge pseudo-normals per global edge */
+    double *fcurv, *vcurv; /* 2D: signed curvature per segment / vertex (eq.7) */
     int nedge;
     /* flow */
     double gamma, mach, re, pr, R, cp, mu, kc, pinf, uc2;
@@ -172,6 +173,25 @@ static void body_normals(orc *o)
             }
         for (int vtx = 0; vtx < o->nvert; vtx++)
             normalize3(o->vnrm + 3 * vtx);
+        /* curvature for eq.7 (reading): the turn of the unit vertex normals
+         * along a segment over its length, (n_b - n_a).(b - a) / |b - a|^2,
+         * exactly 1/r on a regular polygon inscribed in a circle of radius r,
+         * positive where the surface bends away from the fluid (convex); a
+         * vertex takes the mean of its two segments */
+        free(o->fcurv);
+        free(o->vcurv);
+        o->fcurv = (double *)calloc((size_t)(o->nfacet > 0 ? o->nfacet : 1), sizeof(double));
+        o->vcurv = (double *)calloc((size_t)(o->nvert > 0 ? o->nvert : 1), sizeof(double));
+        for (int f = 0; f < o->nfacet; f++) {
+            int ia = o->facet[2 * f], ib = o->facet[2 * f + 1];
+            const double *a = o->v + 2 * ia, *b = o->v + 2 * ib;
+            double ex = b[0] - a[0], ey = b[1] - a[1];
+            double dn = (o->vnrm[3 * ib] - o->vnrm[3 * ia]) * ex + (o->vnrm[3 * ib + 1] - o->vnrm[3 * ia + 1]) * ey;
+            o->fcurv[f] = dn / (ex * ex + ey * ey);
+        }
+        for (int f = 0; f < o->nfacet; f++)
+            for (int e = 0; e < 2; e++)
+                o->vcurv[o->facet[2 * f + e]] += 0.5 * o->fcurv[f];
         return;
     }
     for (int f = 0; f < o->nfacet; f++) {
@@ -340,7 +360,7 @@ void orc_destroy(orc *o)
     free(o->xc); free(o->yc); free(o->zc);
     free(o->Xc); free(o->Yc); free(o->Zc);
     free(o->V0); free(o->V); free(o->v); free(o->facet);
-    free(o->fnrm); free(o->vnrm); free(o->edge_of); free(o->enrm);
+    free(o->fnrm); free(o->vnrm); free(o->edge_of); free(o->enrm); free(o->fcurv); free(o->vcurv);
     free(o->cls); free(o->cls_prev); free(o->listF); free(o->listG);
     free(o->irec); free(o->drec);
     free(o);
@@ -981,6 +1001,8 @@ static void node_geometry(orc *o, int r, long c, int is_forcing)
     dr[7] = s1;
     dr[8] = s2;
     dr[25] = sqrt(cl.d2);
+    /* eq.7: curvature of the closest feature (2D) */
+    dr[26] = nd == 2 ? (cl.kind == FEAT_FACE ? o->fcurv[cl.id] : o->vcurv[cl.id]) : 0.0;
 }
 
 int orc_geometry(orc *o)
@@ -1231,6 +1253,13 @@ static void fill_range(orc *o, double *q, int r0, int r1, double t)
             for (int d = 0; d < nd; d++)
                 an += n[d] * ab[d];
             double gp = -rho1 * an, gT = 0.0;
+            if (o->wallp == ORC_WALL_EQ7 && nd == 2) {
+                /* eq.7 (reading: the normal momentum balance at the wall, n
+                 * into the fluid): dp/dn = rho u_t^2 kappa - rho a_n, u_t the
+                 * tangential velocity relative to the wall at probe 1 */
+                double ut = -(phi1[1] - ub[0]) * n[1] + (phi1[2] - ub[1]) * n[0];
+                gp = rho1 * ut * ut * dr[26] - rho1 * an;
+            }
             if (!quad || ir[5] == 2) {
                 for (int d = 0; d < nd; d++)
                     res.u[d] = ub[d] + (phi1[1 + d] - ub[d]) * sx / s1;
