@@ -159,6 +159,7 @@ struct HostGeom {
     std::vector<double> v0;
     std::vector<int> facet;
     std::vector<double> fnrm, vnrm, enrm;
+    std::vector<double> fcurv, vcurv;  // 2D: signed curvature per segment / vertex (eq.7)
     std::vector<int> edge_of;
     int nedge;
     int region[6];
@@ -336,6 +337,21 @@ void body_normals(HostGeom &h, const std::vector<double> &v)
             }
         for (int m = 0; m < nv; ++m)
             unit3(&h.vnrm[3 * m]);
+        // eq.7 curvature: the turn of the unit vertex normals along a segment
+        // over its length, (n_b - n_a).(b - a) / |b - a|^2 (1/r on a regular
+        // polygon inscribed in a circle of radius r; positive where convex);
+        // a vertex takes the mean of its two segments
+        h.fcurv.assign((size_t)std::max(nf, 1), 0.0);
+        h.vcurv.assign((size_t)std::max(nv, 1), 0.0);
+        for (int f = 0; f < nf; ++f) {
+            int ia = h.facet[2 * f], ib = h.facet[2 * f + 1];
+            double ex = v[2 * ib] - v[2 * ia], ey = v[2 * ib + 1] - v[2 * ia + 1];
+            double dn = (h.vnrm[3 * ib] - h.vnrm[3 * ia]) * ex + (h.vnrm[3 * ib + 1] - h.vnrm[3 * ia + 1]) * ey;
+            h.fcurv[f] = dn / (ex * ex + ey * ey);
+        }
+        for (int f = 0; f < nf; ++f)
+            for (int e = 0; e < 2; ++e)
+                h.vcurv[h.facet[2 * f + e]] += 0.5 * h.fcurv[f];
         h.nedge = 0;
         h.enrm.assign(3, 0.0);
         h.edge_of.assign(3, 0);
@@ -530,6 +546,7 @@ struct Layout {
     double *v;
     int *facet;
     double *fnrm, *vnrm, *enrm;
+    double *fcurv, *vcurv;
     int *edge_of;
     int32_t *bin_start, *bin_facet;
     double *fbox;
@@ -538,6 +555,7 @@ struct Layout {
     int32_t *counts, *blk, *listF, *listG, *rec_i;
     double *rec_d;
     int32_t *plan_node, *plan_off, *plan_mode, *plan_frec;
+    double *plan_kappa;
     double *plan_w, *plan_geo, *fval;
     double *fpart;           // surface force block sums
     int32_t *fmissed;        // surface force: facets without a valid centre
@@ -574,6 +592,8 @@ size_t carve(const ibm_case *c, const HostGeom &h, char *base, Layout &L)
     L.vnrm = cv.take<double>((size_t)std::max(c->nvert, 1) * 3);
     L.enrm = cv.take<double>(nfx * 3 * 3);
     L.edge_of = cv.take<int>(nfx * 3);
+    L.fcurv = cv.take<double>(nfx);
+    L.vcurv = cv.take<double>((size_t)std::max(c->nvert, 1));
     L.bin_start = cv.take<int32_t>(h.bin_start.size());
     L.bin_facet = cv.take<int32_t>(std::max<size_t>(h.bin_facet.size(), 1));
     L.fbox = cv.take<double>(std::max<size_t>(h.fbox.size(), 1));
@@ -594,6 +614,7 @@ size_t carve(const ibm_case *c, const HostGeom &h, char *base, Layout &L)
     L.plan_geo = cv.take<double>(6 * cap);
     L.plan_mode = cv.take<int32_t>(cap);
     L.plan_frec = cv.take<int32_t>(16 * cap);
+    L.plan_kappa = cv.take<double>(cap);
     L.fval = cv.take<double>((size_t)(nd + 2) * cap);
     L.fpart = cv.take<double>((size_t)3 * std::max(forces_blocks(c->nfacet), 1));
     L.fmissed = cv.take<int32_t>(1);
@@ -786,6 +807,8 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     b.vnrm = L.vnrm;
     b.enrm = L.enrm;
     b.edge_of = L.edge_of;
+    b.fcurv = L.fcurv;
+    b.vcurv = L.vcurv;
     for (int d = 0; d < 3; ++d) {
         b.bin_o[d] = h.bin_o[d];
         b.bin_n[d] = h.bin_n[d];
@@ -807,6 +830,8 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     if (e == hipSuccess) e = up(L.vnrm, h.vnrm);
     if (e == hipSuccess && !h.enrm.empty()) e = up(L.enrm, h.enrm);
     if (e == hipSuccess && !h.edge_of.empty()) e = up(L.edge_of, h.edge_of);
+    if (e == hipSuccess && !h.fcurv.empty()) e = up(L.fcurv, h.fcurv);
+    if (e == hipSuccess && !h.vcurv.empty()) e = up(L.vcurv, h.vcurv);
 
     Flow &f = x->f;
     f.gamma = c->gamma;
@@ -863,6 +888,7 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     ib.plan_geo = L.plan_geo;
     ib.plan_mode = L.plan_mode;
     ib.plan_frec = L.plan_frec;
+    ib.plan_kappa = L.plan_kappa;
     ib.fval = L.fval;
     ib.rmap = L.rmap;
     ib.tile_slot = L.tile_slot;

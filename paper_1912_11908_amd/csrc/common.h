@@ -44,6 +44,8 @@ struct Body {
     const double *vnrm;      // nvert * 3
     const double *enrm;      // nedge * 3 (3D)
     const int *edge_of;      // nfacet * 3 (3D): global edge id per facet edge
+    const double *fcurv;     // 2D: signed curvature per segment (eq.7)
+    const double *vcurv;     // 2D: signed curvature per vertex
     // 3D facet bins in the rest frame (uniform cubes of side bin_h from
     // bin_o; a facet is listed in every bin its bounding box meets), CSR:
     // bin_start[nbin + 1], bin_facet; nbin = 0 for brute-force search
@@ -87,6 +89,7 @@ struct IB {
     // 16 * cap, ghost records: the FORCING record of each weighted probe
     // corner that is a FORCING node (-1 otherwise, and for FORCING records)
     int32_t *plan_frec;
+    double *plan_kappa;      // cap: surface curvature at the node's feature (2D, eq.7)
     double *fval;            // NV * cap: filled values of FORCING corners, by record
     int32_t *rmap;           // cap: record index per region cell (IB nodes only)
     // per near tile ("slot", a tile whose stencils reach the region): the

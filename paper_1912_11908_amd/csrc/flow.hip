@@ -291,6 +291,13 @@ __device__ __forceinline__ void node_fill(const Grid &g, const Flow &f, const IB
         for (int d = 0; d < DIM; ++d)
             an += n[d] * abv[d];
         double gp = -rho1 * an, gT = 0.0;
+        if (DIM == 2 && f.wallp == IBM_WALL_EQ7) {
+            // eq.7, read as the normal momentum balance at the wall (n into
+            // the fluid): dp/dn = rho u_t^2 kappa - rho a_n, u_t the
+            // tangential velocity relative to the wall at probe 1
+            double ut = -(phi1[1] - ubv[0]) * n[1] + (phi1[2] - ubv[1]) * n[0];
+            gp = rho1 * ut * ut * ib.plan_kappa[r] - rho1 * an;
+        }
         if (!quad || mode2 == 2) {
 #pragma unroll
             for (int d = 0; d < DIM; ++d)

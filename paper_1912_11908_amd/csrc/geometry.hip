@@ -1021,8 +1021,12 @@ __device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib
     dr[7] = s1;
     dr[8] = s2;
     dr[25] = sqrt(cl.d2);
-    for (int m = 26; m < kRecD; ++m)
+    // eq.7: curvature of the closest feature (2D)
+    double kappa = nd == 2 ? (cl.kind == FEAT_FACE ? b.fcurv[cl.id] : b.vcurv[cl.id]) : 0.0;
+    dr[26] = kappa;
+    for (int m = 27; m < kRecD; ++m)
         dr[m] = 0.0;
+    ib.plan_kappa[r] = kappa;
     ib.plan_node[r] = (int)node_off;
     for (int d = 0; d < 3; ++d)
         ib.plan_geo[d * cap + r] = n[d];

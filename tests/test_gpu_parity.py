@@ -23,6 +23,8 @@ SMALL = {
     "tube-static": lambda: w.small_case("tube", 30, steps=2, nz=10, ntheta=48, nzt=5, moving=False),
     "octahedron": lambda: _octahedron_case(),
     "supersonic-moving": lambda: w.small_case("supersonic-moving-cylinder", 40, steps=4),
+    "supersonic-moving-eq7": lambda: w.small_case("supersonic-moving-cylinder", 40, steps=4,
+                                                  wall_pressure="eq7"),
 }
 
 
@@ -62,11 +64,11 @@ def test_classification_lists_records_exact(kind):
     oir, odr = o.records()
     assert ir.shape == oir.shape
     assert np.array_equal(ir[:, :23], oir[:, :23])
-    assert np.abs(dr[:, :26] - odr[:, :26]).max() <= 1e-14
+    assert np.abs(dr[:, :27] - odr[:, :27]).max() <= 1e-14
 
 
 @pytest.mark.parametrize("kind", ["cylinder", "cylinder-quad", "wedge", "naca", "ragged",
-                                  "tube-static", "octahedron", "supersonic-moving"])
+                                  "tube-static", "octahedron", "supersonic-moving", "supersonic-moving-eq7"])
 def test_fill_and_residual_fp64(kind):
     case, prim, s, o = _classified(kind)
     s.fill(0.0)
@@ -90,7 +92,8 @@ def test_fill_and_residual_fp64(kind):
 
 
 @pytest.mark.parametrize("kind", ["cylinder", "cylinder-quad", "wedge", "ragged", "moving-cylinder",
-                                  "tube-moving", "tube-static", "octahedron", "supersonic-moving"])
+                                  "tube-moving", "tube-static", "octahedron", "supersonic-moving",
+                                  "supersonic-moving-eq7"])
 def test_rk3_steps_fp64(kind):
     case, prim, s, o = _classified(kind)
     n = case.steps
@@ -267,7 +270,7 @@ def test_c4_full_size_prefix_fp64():
     ir, dr = s.records()
     oir, odr = o.records()
     assert np.array_equal(ir[:, :23], oir[:, :23])
-    assert np.abs(dr[:, :26] - odr[:, :26]).max() <= 1e-14
+    assert np.abs(dr[:, :27] - odr[:, :27]).max() <= 1e-14
     s.advance(1)
     s.check_status()
     q = o.prim_to_state(prim)
