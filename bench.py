@@ -88,8 +88,11 @@ def _parse():
     ap.add_argument("--serving-rate", type=float, default=50.0)
     ap.add_argument("--no-other-configs", action="store_true",
                     help="skip the cylinder, airfoil and tube workloads")
-    ap.add_argument("--config-only", choices=("cylinder", "airfoil", "tube"),
-                    help="time only that one of the other workloads and print its line (for profiling)")
+    ap.add_argument("--config-only", choices=("cylinder", "airfoil", "tube", "supersonic"),
+                    help="time only that one of the other workloads and print its line (for profiling); "
+                         "supersonic: the moving / stationary cylinder pair of section 8.2.3")
+    ap.add_argument("--supersonic-t", type=float, default=10.0,
+                    help="convective times t* of the supersonic cylinder pair")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="also run one plain device copy of 256 MiB (reference for HBM counters)")
     return ap.parse_args()
@@ -165,6 +168,55 @@ def other_configs(only=None):
     return out
 
 
+def supersonic_pair(t_end, mach=1.2, precision="mixed"):
+    """Section 8.2.3 as a Galilean check: the cylinder moving at unit speed
+    through still fluid and the same cylinder held in a unit stream, both
+    from an impulsive start, eq.7 wall pressure; after t_end their surface
+    pressure coefficients and drag, seen from the body, must agree up to the
+    discretisation (the grid moves relative to one body, not the other)."""
+    import numpy as np
+    import torch
+    import workloads as w
+    from workloads.cases import case_supersonic_cylinder
+    import paper_1912_11908_amd as P
+    out = {}
+    cp, cx = {}, {}
+    for moving in (True, False):
+        case = case_supersonic_cylinder(mach, moving=moving, t_end=t_end)
+        prim = w.freestream_prim(2, case.ni, case.nj, 1, case.p_inf, velocity=case.u_inf)
+        s = P.Solver(case, precision, "cuda:0")
+        s.init_prim(prim)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.advance(case.steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s.check_status()
+        t_now = s.info().time
+        s.set_time(t_now)
+        s.classify()
+        s.fill(t_now)
+        F, rows, missed = s.forces(facets=True)
+        rows = rows.cpu().numpy()
+        # seen from either body the fluid streams along -x, so the drag
+        # points along -x in both problems
+        cx["moving" if moving else "stationary"] = float(2.0 * F[0].item())
+        cp["moving" if moving else "stationary"] = 2.0 * rows[:, 0]
+        out["moving" if moving else "stationary"] = {
+            "case": case.name, "cells": case.ncells, "steps": case.steps, "dt": case.dt,
+            "ms_per_step": dt * 1e3 / case.steps,
+            "cell_updates_per_s": case.ncells * 3 * case.steps / dt,
+            "C_x": cx["moving" if moving else "stationary"], "facets_missed": int(missed.item())}
+        del s
+    d = cp["moving"] - cp["stationary"]
+    out["galilean"] = {"t_star": t_end, "mach": mach, "precision": precision,
+                       "Cp_max_abs_diff": float(np.abs(d).max()),
+                       "Cp_rel_l2_diff": float(np.sqrt((d ** 2).sum() / (cp["stationary"] ** 2).sum())),
+                       "Cp_stagnation": float(cp["stationary"].max()),
+                       "C_D_moving": -cx["moving"], "C_D_stationary": -cx["stationary"]}
+    return out
+
+
 def run_gpu(case, prim, precision, steps, warmup, reps):
     import torch
     import paper_1912_11908_amd as P
@@ -227,6 +279,9 @@ def main():
     import torch
     import workloads as w
 
+    if args.config_only == "supersonic":
+        print(json.dumps({"supersonic_pair": supersonic_pair(args.supersonic_t)}), flush=True)
+        return
     if args.config_only:
         print(json.dumps({"other_configs": other_configs(args.config_only)}), flush=True)
         return

@@ -134,6 +134,33 @@ def case_c4(steps=1000):
                 dt=rk3_dt(0.2, 185.0, [xf, yf, zf]), motion=motion, steps=steps)
 
 
+def case_supersonic_cylinder(mach=1.2, moving=True, t_end=60.0, nx=5740, ny=242):
+    """Section 8.2.3: a cylinder (D = 1, 256-segment polygon) at supersonic
+    speed, Re_D = 300 (M and Re on the body speed), on an 80 D x 16 D box of
+    nx x ny cells: x uniform (the body's whole path), y uniform at D/80 over
+    the band [7, 9] and stretched outside.  moving: the body starts at
+    (1.5, 8) and moves at unit speed along +x through still fluid for
+    t_end (it reaches x = 61.5 at t* = 60).  Otherwise the same body is held
+    at (61.5, 8) in a stream of unit speed along -x: in the body's frame the
+    two problems are the same, so their steady surface pressures agree
+    (Galilean invariance).  Both use the eq.7 wall pressure."""
+    xf = uniform_faces(nx, 0.0, 80.0)
+    yf = core_stretched_faces(ny, 0.0, 16.0, 7.0, 9.0, 1.0 / 80.0)
+    x0 = 1.5 if moving else 61.5
+    v, s = circle_polygon(256, 1.0, (x0, 8.0))
+    re = 300.0
+    dt = rk3_dt(mach, re, [xf, yf])
+    steps = int(round(t_end / dt))
+    dt = t_end / steps
+    bc = ("farfield",) * 4 + ("periodic",) * 2
+    if moving:
+        return Case(f"supersonic-moving-cylinder-M{mach:g}", 2, xf, yf, _z_dummy(), bc, v, s, mach, re,
+                    dt=dt, steps=steps, u_inf=(0.0, 0.0, 0.0), wall_pressure="eq7",
+                    motion=dict(axis=0, amplitude=0.0, frequency=0.0, phase=0.0, velocity=1.0))
+    return Case(f"supersonic-stationary-cylinder-M{mach:g}", 2, xf, yf, _z_dummy(), bc, v, s, mach, re,
+                dt=dt, steps=steps, u_inf=(-1.0, 0.0, 0.0), wall_pressure="eq7")
+
+
 def small_case(kind, n=64, steps=2, **kw):
     """Scaled-down parity cases: kind in cylinder | wedge | naca | tube |
     moving-cylinder | box (no body, periodic)."""
