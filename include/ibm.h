@@ -76,10 +76,14 @@ typedef struct ibm_case {
     const int32_t *facet;     /* 2D: nfacet * 2 vertex ids, counter-clockwise      */
                               /* polygon; 3D: nfacet * 3 ids, counter-clockwise    */
                               /* seen from outside                                 */
-    int motion;               /* 0: stationary; 1: translation along one axis      */
-    double motion_par[4];     /* axis, amplitude A, frequency f, phase:            */
+    int motion;               /* 0: stationary; 1: prescribed translation along    */
+                              /* one axis; 2: free translation along one axis      */
+                              /* (section 6, eq.10; IBM_RK3 only)                  */
+    double motion_par[4];     /* 1: axis, amplitude A, frequency f, phase:         */
                               /* x_axis(t) = A cos(2 pi f t + phase) + V t         */
-                              /* (section 8.2.2; V = motion_vel, section 8.2.3)    */
+                              /* (section 8.2.2; V = motion_vel, section 8.2.3);   */
+                              /* 2: axis, mass (rho_inf L^ndim units; 2D: per unit */
+                              /* span), -, -; motion_vel is the initial velocity   */
     double mach, reynolds, prandtl, gamma;
     int scheme;               /* IBM_RK3 or IBM_DUAL                               */
     int ib_family;            /* IBM_IB_LINEAR (IDW + image point) or QUADRATIC    */
@@ -168,6 +172,15 @@ int ibm_residual(ibm_ctx *ctx, const double *d_q, double *d_r, void *stream);
  * taken in a fixed order (reproducible).  IBM_EINVAL without a body. */
 int ibm_forces(ibm_ctx *ctx, const double *d_q, double *d_force, double *d_facet, int32_t *d_missed,
                void *stream);
+
+/* Free body (motion 2): displacement, velocity and acceleration along the
+ * axis after the last step, and the axial force of that step (host out[4]).
+ * Each step of a free body: pose at x^n, fill and ibm_forces at t^n (the
+ * only host synchronisation of the step), a^n = F^n / M, the RK3 stages with
+ * the body moving at u^n and accelerating at a^n, then eq.10 with the 1/2 of
+ * the standard Verlet form: x^{n+1} = x^n + u^n dt + dt^2 a^n / 2,
+ * u^{n+1} = u^n + dt a^n.  IBM_EINVAL for other motions. */
+int ibm_body_state(const ibm_ctx *ctx, double *out);
 
 /* a1-a10: advance nsteps SSP-RK3 steps (IBM_RK3) or physical dual-time steps
  * of n_inner pseudo-iterations each (IBM_DUAL), in place on d_q.  Moving

@@ -46,6 +46,7 @@ def lib():
         L.orc_create.argtypes = [i, i, i, i, P, P, P, P, i, i, P, P, d, d, d, d, i, i, d, d, i, i, P, P, i]
         L.orc_destroy.argtypes = [P]
         L.orc_set_pose.argtypes = [P, d]
+        L.orc_set_body.argtypes = [P, d, d, d]
         L.orc_classify.argtypes = [P]
         L.orc_geometry.argtypes = [P]
         L.orc_bc.argtypes = [P, P]
@@ -113,14 +114,16 @@ class Oracle:
         vert = arr(c.vert.reshape(-1) if len(c.vert) else np.zeros(1), np.float64)
         facet = arr(c.facet.reshape(-1) if len(c.facet) else np.zeros(1, np.int32), np.int32)
         mo = c.motion or {}
-        mpar = arr([mo.get("axis", 0), mo.get("amplitude", 0.0), mo.get("frequency", 0.0),
-                    mo.get("phase", 0.0), mo.get("velocity", 0.0)], np.float64)
+        mpar = arr([mo.get("axis", 0), mo.get("mass", 0.0) if mo.get("free") else mo.get("amplitude", 0.0),
+                    mo.get("frequency", 0.0), mo.get("phase", 0.0), mo.get("velocity", 0.0)], np.float64)
+        # free body (section 6): displacement, velocity, acceleration along the axis
+        self.body = [0.0, float(mo.get("velocity", 0.0)), 0.0]
         uinf = arr(list(c.u_inf) + [0.0] * (3 - len(c.u_inf)), np.float64)
         self.h = lib().orc_create(
             c.ndim, c.ni, c.nj, c.nk, _p(xf), _p(yf), _p(zf), _p(bc), len(c.vert), len(c.facet),
             _p(vert), _p(facet), c.mach, c.reynolds, c.prandtl, c.gamma,
             0 if c.scheme == "rk3" else 1, 0 if c.ib_family == "linear" else 1, c.dt,
-            c.cfl_tau, c.n_inner, 1 if mo else 0, _p(mpar), _p(uinf),
+            c.cfl_tau, c.n_inner, (2 if mo.get("free") else 1) if mo else 0, _p(mpar), _p(uinf),
             {"eq6": 0, "eq7": 1}[c.wall_pressure])
         self.t = 0.0
         self.step_index = 0
@@ -251,3 +254,30 @@ class Oracle:
         per = np.zeros((max(len(self.case.facet), 1), 5))
         missed = lib().orc_forces(self.h, _p(q), _p(F), _p(per))
         return F, per[:len(self.case.facet)], missed
+
+    def run_free(self, q, nsteps):
+        """Section 6, eq.10: a free rigid body translating along the motion
+        axis, RK3.  Per step: the body posed at x^n; the force F^n on the
+        state at t^n, filled with the body's velocity u^n and its last
+        acceleration; a^n = F^n / M; one RK3 step with the body at x^n
+        moving at u^n and accelerating at a^n; then (Verlet, with the 1/2 of
+        the standard form) x^{n+1} = x^n + u^n dt + dt^2 a^n / 2,
+        u^{n+1} = u^n + dt a^n."""
+        c = self.case
+        ax, mass, dt = c.motion["axis"], c.motion["mass"], c.dt
+        q1, q2 = q.copy(), q.copy()
+        for _ in range(nsteps):
+            x, u, a_prev = self.body
+            lib().orc_set_body(self.h, x, u, a_prev)
+            self.classify(self.t)
+            self.fill(q, self.t)
+            self.bc(q)
+            F, _, _ = self.forces(q)
+            a = F[ax] / mass
+            lib().orc_set_body(self.h, x, u, a)
+            lib().orc_rk3_step(self.h, _p(q), _p(q1), _p(q2), self.t)
+            self.t += dt
+            self.step_index += 1
+            self.body = [x + u * dt + 0.5 * dt * dt * a, u + dt * a, a]
+            self.last_force = F
+        return q

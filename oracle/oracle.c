@@ -51,6 +51,7 @@ struct orc {
     int n_inner;
     int motion, maxis;
     double mamp, mfreq, mphase, mvel;
+    double bx, bu, ba;    /* free body (motion 2): displacement, velocity, acceleration */
     double uinf[3];       /* free-stream velocity */
     int wallp;            /* ORC_WALL_EQ6 / ORC_WALL_EQ7 */
     i64 disp;
@@ -371,19 +372,33 @@ void orc_destroy(orc *o)
  * (section 8.2.2 motion law).  The displacement is snapped to the lattice and
  * added to the integer vertices, so posed coordinates stay exact. */
 /* x_axis(t) = A cos(2 pi f t + phase) + V t: the oscillation of section 8.2.2
- * plus a constant speed (section 8.2.3) */
+ * plus a constant speed (section 8.2.3).  A free body (motion 2, section 6)
+ * has the displacement, velocity and acceleration its driver last set. */
 static double pose_disp(const orc *o, double t)
 {
+    if (o->motion == 2)
+        return o->bx;
     return o->mamp * cos(2.0 * M_PI * o->mfreq * t + o->mphase) + o->mvel * t;
 }
 static double pose_vel(const orc *o, double t)
 {
+    if (o->motion == 2)
+        return o->bu;
     return -2.0 * M_PI * o->mfreq * o->mamp * sin(2.0 * M_PI * o->mfreq * t + o->mphase) + o->mvel;
 }
 static double pose_acc(const orc *o, double t)
 {
+    if (o->motion == 2)
+        return o->ba;
     double w = 2.0 * M_PI * o->mfreq;
     return -w * w * o->mamp * cos(w * t + o->mphase);
+}
+
+void orc_set_body(orc *o, double x, double u, double a)
+{
+    o->bx = x;
+    o->bu = u;
+    o->ba = a;
 }
 
 void orc_set_pose(orc *o, double t)

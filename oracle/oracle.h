@@ -39,6 +39,9 @@ void orc_destroy(orc *o);
 
 /* a1: body pose at time t (no-op for a stationary body). */
 void orc_set_pose(orc *o, double t);
+/* free body (motion 2): displacement, velocity and acceleration along the
+ * motion axis used by the next pose and fills */
+void orc_set_body(orc *o, double x, double u, double a);
 /* a2 + a3: classification, tagging and list compaction; returns 0 or <0. */
 int orc_classify(orc *o);
 /* a4: closest feature, local normal, boundary point and probes per listed node. */

@@ -47,8 +47,9 @@ def case_struct(case, precision="fp64"):
     c.vert = arr(np.asarray(case.vert).reshape(-1), np.float64) if c.nvert else None
     c.facet = arr(np.asarray(case.facet).reshape(-1), np.int32) if c.nfacet else None
     mo = case.motion or {}
-    c.motion = 1 if mo else 0
-    for m, key in enumerate(["axis", "amplitude", "frequency", "phase"]):
+    c.motion = (2 if mo.get("free") else 1) if mo else 0
+    keys = ["axis", "mass", "frequency", "phase"] if mo.get("free") else ["axis", "amplitude", "frequency", "phase"]
+    for m, key in enumerate(keys):
         c.motion_par[m] = float(mo.get(key, 0.0))
     c.mach, c.reynolds, c.prandtl, c.gamma = case.mach, case.reynolds, case.prandtl, case.gamma
     c.scheme = 0 if case.scheme == "rk3" else 1
@@ -191,6 +192,13 @@ class Solver:
     def set_graphs(self, on):
         """Replay whole steps as HIP graphs (stationary bodies; default on)."""
         _lib.check(self.L.ibm_set_option(self.h, 1, 1 if on else 0), "ibm_set_option", self.h)
+
+    def body_state(self):
+        """Free body: (displacement, velocity, acceleration, axial force) of
+        the last step along the motion axis."""
+        out = np.zeros(4)
+        _lib.check(self.L.ibm_body_state(self.h, out.ctypes.data_as(ctypes.c_void_p)), "ibm_body_state", self.h)
+        return out
 
     def set_corner_lists(self, on):
         """Fill the FORCING probe corners of ghost nodes per tile from lists

@@ -35,6 +35,7 @@ struct ibm_ctx {
     int ntiles;
     double *fpart;           // surface force block sums
     int32_t *fmissed;        // surface force: facets without a valid centre
+    double *fforce;          // surface force of a free body's step (device, 3)
     // graph replay of whole steps (stationary bodies): slot 0 holds one
     // step, slot 1 a chunk of kChunk steps
     bool use_graphs;
@@ -115,7 +116,11 @@ int check_desc(const ibm_case *c)
         return IBM_EINVAL;
     if (c->scheme == IBM_DUAL && (c->n_inner < 1 || !(c->cfl_tau > 0)))
         return IBM_EINVAL;
+    if (c->motion < 0 || c->motion > 2)
+        return IBM_EINVAL;
     if (c->motion && (c->motion_par[0] < 0 || c->motion_par[0] >= c->ndim))
+        return IBM_EINVAL;
+    if (c->motion == 2 && (!(c->motion_par[1] > 0) || c->scheme != IBM_RK3 || c->nfacet == 0))
         return IBM_EINVAL;
     for (int d = 0; d < 3; ++d)
         if (!std::isfinite(c->u_inf[d]) || (d >= c->ndim && c->u_inf[d] != 0.0))
@@ -508,7 +513,7 @@ int host_geom(const ibm_case *c, HostGeom &h)
                 double a = std::fabs(c->motion_par[1]) + 1e-6;
                 lo -= a;
                 hi += a;
-                if (c->motion_vel != 0.0) {  // unbounded travel: the whole axis
+                if (c->motion_vel != 0.0 || c->motion == 2) {  // unbounded travel: the whole axis
                     lo = -1e300;
                     hi = 1e300;
                 }
@@ -559,6 +564,7 @@ struct Layout {
     double *plan_w, *plan_geo, *fval;
     double *fpart;           // surface force block sums
     int32_t *fmissed;        // surface force: facets without a valid centre
+    double *fforce;          // surface force of a free body's step
     int32_t *rmap;
     int32_t *tile_slot, *slot_tile, *tg_cnt, *tg_t, *tg_rec, *tj_cnt, *tj_rec;
     int32_t *tiles;
@@ -617,6 +623,7 @@ size_t carve(const ibm_case *c, const HostGeom &h, char *base, Layout &L)
     L.plan_kappa = cv.take<double>(cap);
     L.fval = cv.take<double>((size_t)(nd + 2) * cap);
     L.fpart = cv.take<double>((size_t)3 * std::max(forces_blocks(c->nfacet), 1));
+    L.fforce = cv.take<double>(3);
     L.fmissed = cv.take<int32_t>(1);
     L.rmap = cv.take<int32_t>(cap);
     {
@@ -665,6 +672,12 @@ hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 void motion_kin(const ibm_ctx *c, double t, double &disp, double &vel, double &acc)
 {
+    if (c->mo.free) {
+        disp = c->mo.x;
+        vel = c->mo.u;
+        acc = c->mo.a;
+        return;
+    }
     double w = 2.0 * M_PI * c->mo.freq;
     disp = c->mo.amp * std::cos(w * t + c->mo.phase) + c->mo.vel * t;
     vel = -w * c->mo.amp * std::sin(w * t + c->mo.phase) + c->mo.vel;
@@ -940,6 +953,15 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     x->mo.freq = c->motion_par[2];
     x->mo.phase = c->motion_par[3];
     x->mo.vel = c->motion_vel;
+    x->mo.free = c->motion == 2;
+    x->mo.mass = c->motion == 2 ? c->motion_par[1] : 0.0;
+    x->mo.x = 0.0;
+    x->mo.u = c->motion == 2 ? c->motion_vel : 0.0;
+    x->mo.a = 0.0;
+    x->mo.force = 0.0;
+    if (x->mo.free) {
+        x->mo.amp = x->mo.freq = x->mo.phase = x->mo.vel = 0.0;
+    }
     x->q1 = L.q1;
     x->q2 = L.q2;
     x->wtmp = L.wtmp;
@@ -960,6 +982,7 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     x->d_args = L.args;
     x->fpart = L.fpart;
     x->fmissed = L.fmissed;
+    x->fforce = L.fforce;
     x->batch_q = nullptr;
     for (int k = 0; k < kSlots; ++k)
         x->slot_nblk[k] = 0;
@@ -1056,6 +1079,17 @@ int ibm_forces(ibm_ctx *c, const double *q, double *force, double *facet_out, in
     if (e == hipSuccess)
         e = launch_forces(c->g, c->b, c->f, c->ib, q, force, facet_out, c->fpart, m, S(stream));
     return dev_err(c, e, "forces");
+}
+
+int ibm_body_state(const ibm_ctx *c, double *out)
+{
+    if (!c || !out || !c->mo.free)
+        return IBM_EINVAL;
+    out[0] = c->mo.x;
+    out[1] = c->mo.u;
+    out[2] = c->mo.a;
+    out[3] = c->mo.force;
+    return IBM_OK;
 }
 
 int ibm_residual(ibm_ctx *c, const double *q, double *r, void *stream)
@@ -1239,6 +1273,43 @@ int enqueue_group_step(ibm_ctx *const *ctx, double *const *q, const std::vector<
     return IBM_OK;
 }
 
+// One step of a free body (section 6, eq.10): the force on the state at t^n
+// (filled with the body's velocity and last acceleration), a = F / M, the
+// RK3 stages with the body at x^n moving at u^n and accelerating at a, then
+// the Verlet update with the 1/2 of its standard form.
+int free_step(ibm_ctx *c, double *q, hipStream_t s)
+{
+    int rc;
+    if ((rc = do_classify(c, c->t, s)))
+        return rc;
+    if ((rc = do_fill(c, q, c->t, s)))
+        return rc;
+    hipError_t e = hipMemsetAsync(c->fmissed, 0, sizeof(int32_t), s);
+    if (e == hipSuccess)
+        e = launch_forces(c->g, c->b, c->f, c->ib, q, c->fforce, nullptr, c->fpart, c->fmissed, s);
+    double F[3] = {0.0, 0.0, 0.0};
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(F, c->fforce, sizeof F, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if ((rc = dev_err(c, e, "free-body force")))
+        return rc;
+    double a = F[c->mo.axis] / c->mo.mass;
+    if (!std::isfinite(a))
+        return set_err(c, IBM_ENONFINITE, "free-body force is not finite");
+    c->mo.a = a;
+    c->mo.force = F[c->mo.axis];
+    if ((rc = enqueue_rk3_step(c, q, c->t, s)))
+        return rc;
+    double dt = c->f.dt, x = c->mo.x, u = c->mo.u;
+    {
+#pragma clang fp contract(off)
+        c->mo.x = x + u * dt + 0.5 * dt * dt * a;
+        c->mo.u = u + dt * a;
+    }
+    return IBM_OK;
+}
+
 // Steps per chunk graph: RK3 steps are 9 launches, dual-time steps 3 n_inner + 1.
 int chunk_steps(const ibm_ctx *c) { return c->f.scheme == IBM_RK3 ? 8 : 2; }
 
@@ -1300,6 +1371,14 @@ int ibm_advance(ibm_ctx *c, double *q, int nsteps, void *stream)
     int rc;
     double dt = c->f.dt;
     for (int n = 0; n < nsteps;) {
+        if (c->mo.free) {
+            if ((rc = free_step(c, q, s)))
+                return rc;
+            c->t += dt;
+            c->step += 1;
+            n += 1;
+            continue;
+        }
         bool rk = c->f.scheme == IBM_RK3;
         // moving bodies are posed at t^n (RK3) or t^{n+1} (dual time)
         double tpose = rk ? c->t : c->t + dt;

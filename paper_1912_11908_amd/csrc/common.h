@@ -126,6 +126,10 @@ struct StagePart {
 struct Motion {
     int on, axis;
     double amp, freq, phase, vel;
+    // free rigid body (section 6): mass, and the displacement, velocity,
+    // acceleration and axial force of its last step
+    int free;
+    double mass, x, u, a, force;
 };
 
 // ------------------------------------------------------------ launchers

@@ -161,6 +161,52 @@ def case_supersonic_cylinder(mach=1.2, moving=True, t_end=60.0, nx=5740, ny=242)
                 dt=dt, steps=steps, u_inf=(-1.0, 0.0, 0.0), wall_pressure="eq7")
 
 
+def shock_states(mach_s=1.5, gamma=1.4):
+    """Quiescent gas ahead of a planar shock of Mach mach_s and the
+    Rankine-Hugoniot state behind it, in units of the gas ahead (rho0 = 1)
+    and the shock speed (U_S = 1): p0 = 1 / (gamma M_s^2)."""
+    m2 = mach_s * mach_s
+    p0 = 1.0 / (gamma * m2)
+    r1 = (gamma + 1.0) * m2 / ((gamma - 1.0) * m2 + 2.0)
+    p1 = p0 * (1.0 + 2.0 * gamma / (gamma + 1.0) * (m2 - 1.0))
+    u1 = 1.0 - 1.0 / r1
+    return (1.0, 0.0, p0), (r1, u1, p1)
+
+
+def shock_prim(case, x_shock, mach_s=1.5):
+    """Primitive field of a planar shock at x = x_shock moving along +x into
+    gas at rest (the state behind it on the left)."""
+    (r0, u0, p0), (r1, u1, p1) = shock_states(mach_s, case.gamma)
+    xc = 0.5 * (case.xf[1:] + case.xf[:-1])
+    behind = (xc < x_shock)[None, None, :]
+    prim = np.zeros((case.ndim + 2, case.nk, case.nj, case.ni))
+    prim[0] = np.where(behind, r1, r0)
+    prim[1] = np.where(behind, u1, u0)
+    prim[case.ndim + 1] = np.where(behind, p1, p0)
+    return prim
+
+
+def case_shock_cylinder(n=656, t_end=2.0, density_ratio=1.0):
+    """Section 8.2.6 in units of D, the gas ahead of the shock and the shock
+    speed (t* = t U_S / D): a free cylinder (D = 1, 256-segment polygon,
+    centre (1.5, 2)) in a 4 x 4 box of n x n cells (D / 164 at n = 656),
+    driven along x by a Mach 1.5 shock; zero-gradient sides, Re = 3.5e6
+    (air at the printed speeds: nearly inviscid), linear (IDW / image point)
+    family.  The body's mass per unit span is density_ratio times the mass
+    of the gas it displaces (pi / 4)."""
+    xf = uniform_faces(n, 0.0, 4.0)
+    yf = uniform_faces(n, 0.0, 4.0)
+    v, s = circle_polygon(256, 1.0, (1.5, 2.0))
+    m, re = 1.5, 3.5e6
+    dt = rk3_dt(m, re, [xf, yf])
+    steps = int(round(t_end / dt))
+    dt = t_end / steps
+    mass = density_ratio * np.pi / 4.0
+    return Case(f"shock-driven-cylinder-{n}", 2, xf, yf, _z_dummy(), ("extrap",) * 4 + ("periodic",) * 2, v, s,
+                m, re, dt=dt, steps=steps, u_inf=(0.0, 0.0, 0.0),
+                motion=dict(axis=0, mass=mass, free=True, velocity=0.0))
+
+
 def small_case(kind, n=64, steps=2, **kw):
     """Scaled-down parity cases: kind in cylinder | wedge | naca | tube |
     moving-cylinder | box (no body, periodic)."""
@@ -179,6 +225,12 @@ def small_case(kind, n=64, steps=2, **kw):
         return Case(f"small-moving-cylinder-{n}", 2, f, f.copy(), _z_dummy(),
                     ("farfield",) * 4 + ("periodic",) * 2, v, s, 0.2, 185.0,
                     dt=rk3_dt(0.2, 185.0, [f, f]), motion=motion, steps=steps)
+    if kind == "shock-cylinder":
+        # section 8.2.6 in miniature: a free cylinder, the shock already over
+        # its front half
+        c = case_shock_cylinder(n, t_end=1.0, density_ratio=kw.get("density_ratio", 1.0))
+        return Case(f"small-shock-cylinder-{n}", 2, c.xf, c.yf, c.zf, c.bc, c.vert, c.facet, c.mach,
+                    c.reynolds, dt=c.dt, steps=steps, u_inf=c.u_inf, motion=c.motion)
     if kind == "supersonic-moving-cylinder":
         # section 8.2.3 in miniature: the body moves at unit speed (M, Re on
         # that speed) through still fluid
