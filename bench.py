@@ -88,9 +88,10 @@ def _parse():
     ap.add_argument("--serving-rate", type=float, default=50.0)
     ap.add_argument("--no-other-configs", action="store_true",
                     help="skip the cylinder, airfoil and tube workloads")
-    ap.add_argument("--config-only", choices=("cylinder", "airfoil", "tube", "supersonic"),
+    ap.add_argument("--config-only", choices=("cylinder", "airfoil", "tube", "supersonic", "shock"),
                     help="time only that one of the other workloads and print its line (for profiling); "
-                         "supersonic: the moving / stationary cylinder pair of section 8.2.3")
+                         "supersonic: the moving / stationary cylinder pair of section 8.2.3; "
+                         "shock: the shock-driven free cylinder of section 8.2.6")
     ap.add_argument("--supersonic-t", type=float, default=10.0,
                     help="convective times t* of the supersonic cylinder pair")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -217,6 +218,43 @@ def supersonic_pair(t_end, mach=1.2, precision="mixed"):
     return out
 
 
+def shock_driven(t_end=2.0):
+    """Section 8.2.6: a free cylinder driven by a Mach 1.5 shock (656^2
+    cells, D / 164), eq.10 coupling; per precision the wall time per coupled
+    step (force, host synchronisation, reclassification and the RK3 stages)
+    and the body's trajectory at t* = 0.5, 1, 1.5, 2."""
+    import torch
+    from workloads.cases import case_shock_cylinder, shock_prim
+    import paper_1912_11908_amd as P
+    out = {}
+    for prec in ("mixed", "fp64"):
+        case = case_shock_cylinder(656, t_end=t_end)
+        s = P.Solver(case, prec, "cuda:0")
+        s.init_prim(shock_prim(case, 0.5))
+        marks = [int(round(k * case.steps / 4)) for k in range(1, 5)]
+        traj, done, wall = [], 0, 0.0
+        for m in marks:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.advance(m - done)
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - t0
+            done = m
+            x, u, a, fx = s.body_state()
+            traj.append({"t_star": round(m * case.dt, 6), "x": float(x), "u": float(u), "C_x": float(2.0 * fx)})
+        s.check_status()
+        t_now = s.info().time
+        s.set_time(t_now)
+        s.classify()
+        s.fill(t_now)
+        F = s.forces().cpu().numpy()
+        out[prec] = {"cells": case.ncells, "steps": case.steps, "ms_per_step": wall * 1e3 / case.steps,
+                     "cell_updates_per_s": case.ncells * 3 * case.steps / wall, "trajectory": traj,
+                     "lift_over_drag": float(abs(F[1]) / abs(F[0]))}
+        del s
+    return out
+
+
 def run_gpu(case, prim, precision, steps, warmup, reps):
     import torch
     import paper_1912_11908_amd as P
@@ -279,6 +317,9 @@ def main():
     import torch
     import workloads as w
 
+    if args.config_only == "shock":
+        print(json.dumps({"shock_driven": shock_driven()}), flush=True)
+        return
     if args.config_only == "supersonic":
         print(json.dumps({"supersonic_pair": supersonic_pair(args.supersonic_t)}), flush=True)
         return
