@@ -43,7 +43,7 @@ def lib():
         P = ctypes.c_void_p
         d, i = ctypes.c_double, ctypes.c_int
         L.orc_create.restype = P
-        L.orc_create.argtypes = [i, i, i, i, P, P, P, P, i, i, P, P, d, d, d, d, i, i, d, d, i, i, P, P, i]
+        L.orc_create.argtypes = [i, i, i, i, P, P, P, P, i, i, P, P, d, d, d, d, i, i, d, d, i, i, P, P, i, i]
         L.orc_destroy.argtypes = [P]
         L.orc_set_pose.argtypes = [P, d]
         L.orc_set_body.argtypes = [P, d, d, d]
@@ -69,6 +69,8 @@ def lib():
         L.orc_get_param.restype = d
         L.orc_weno5.argtypes = [d] * 5
         L.orc_weno5.restype = d
+        L.orc_tvd2.argtypes = [d] * 3
+        L.orc_tvd2.restype = d
         L.orc_ldfss.argtypes = [i, P, P, P, d, i, d, P]
         _lib = L
     return _lib
@@ -80,6 +82,10 @@ def _p(a):
 
 def weno5(a, b, c, d, e):
     return lib().orc_weno5(a, b, c, d, e)
+
+
+def tvd2(a, b, c):
+    return lib().orc_tvd2(a, b, c)
 
 
 def ldfss(ndim, wl, wr, nrm, gamma=1.4, precond=False, uc2=1.0):
@@ -124,7 +130,7 @@ class Oracle:
             _p(vert), _p(facet), c.mach, c.reynolds, c.prandtl, c.gamma,
             0 if c.scheme == "rk3" else 1, 0 if c.ib_family == "linear" else 1, c.dt,
             c.cfl_tau, c.n_inner, (2 if mo.get("free") else 1) if mo else 0, _p(mpar), _p(uinf),
-            {"eq6": 0, "eq7": 1}[c.wall_pressure])
+            {"eq6": 0, "eq7": 1}[c.wall_pressure], {"weno5": 0, "tvd2": 1}[c.reconstruction])
         self.t = 0.0
         self.step_index = 0
 

@@ -54,6 +54,7 @@ struct orc {
     double bx, bu, ba;    /* free body (motion 2): displacement, velocity, acceleration */
     double uinf[3];       /* free-stream velocity */
     int wallp;            /* ORC_WALL_EQ6 / ORC_WALL_EQ7 */
+    int recon;            /* ORC_RECON_WENO5 / ORC_RECON_TVD2 */
     i64 disp;
     /* classification */
     uint8_t *cls, *cls_prev;
@@ -259,7 +260,7 @@ orc *orc_create(int ndim, int ni, int nj, int nk, const double *xf, const double
                 const double *zf, const int *bc, int nvert, int nfacet, const double *vert,
                 const int *facet, double mach, double re, double pr, double gamma, int scheme,
                 int family, double dt, double cfl_tau, int n_inner, int motion,
-                const double *mpar, const double *uinf, int wall_pressure)
+                const double *mpar, const double *uinf, int wall_pressure, int reconstruction)
 {
     orc *o = (orc *)calloc(1, sizeof(orc));
     o->ndim = ndim;
@@ -308,6 +309,7 @@ orc *orc_create(int ndim, int ni, int nj, int nk, const double *xf, const double
     for (int d = 0; d < 3; d++)
         o->uinf[d] = uinf[d];
     o->wallp = wall_pressure;
+    o->recon = reconstruction;
     o->gamma = gamma;
     o->mach = mach;
     o->re = re;
@@ -1318,6 +1320,23 @@ void orc_fill(orc *o, double *q, double t)
 /* Fifth-order WENO (section 2, [74]); reading: the Jiang-Shu weights with
  * eps = 1e-6 and linear weights (0.1, 0.6, 0.3).  Left state at i+1/2 from
  * v(i-2 .. i+2); the right state is the same function of v(i+3 .. i-1). */
+/* Second-order TVD reconstruction (section 2 names the scheme, not its
+ * limiter; reading: MUSCL with the minmod limiter): the state at the face
+ * between b and c seen from b's side, b + (1/2) minmod(b - a, c - b). */
+static double minmod(double x, double y)
+{
+    if (x > 0.0 && y > 0.0)
+        return x < y ? x : y;
+    if (x < 0.0 && y < 0.0)
+        return x > y ? x : y;
+    return 0.0;
+}
+
+double orc_tvd2(double a, double b, double c)
+{
+    return b + 0.5 * minmod(b - a, c - b);
+}
+
 double orc_weno5(double a, double b, double c, double d, double e)
 {
     double q0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;
@@ -1438,8 +1457,13 @@ static void face_flux(const orc *o, const double *q, int i, int j, int k, int ax
     }
     double wl[5], wr[5];
     for (int var = 0; var < nv; var++) {
-        wl[var] = orc_weno5(v[0][var], v[1][var], v[2][var], v[3][var], v[4][var]);
-        wr[var] = orc_weno5(v[5][var], v[4][var], v[3][var], v[2][var], v[1][var]);
+        if (o->recon == ORC_RECON_TVD2) {
+            wl[var] = orc_tvd2(v[1][var], v[2][var], v[3][var]);
+            wr[var] = orc_tvd2(v[4][var], v[3][var], v[2][var]);
+        } else {
+            wl[var] = orc_weno5(v[0][var], v[1][var], v[2][var], v[3][var], v[4][var]);
+            wr[var] = orc_weno5(v[5][var], v[4][var], v[3][var], v[2][var], v[1][var]);
+        }
     }
     double nrm[3] = {0, 0, 0};
     nrm[ax] = 1.0;

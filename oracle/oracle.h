@@ -29,12 +29,13 @@ enum { ORC_BC_FARFIELD = 0, ORC_BC_EXTRAP = 1, ORC_BC_PERIODIC = 2 };
 enum { ORC_RK3 = 0, ORC_DUAL = 1 };
 enum { ORC_IB_LINEAR = 0, ORC_IB_QUADRATIC = 1 };
 enum { ORC_WALL_EQ6 = 0, ORC_WALL_EQ7 = 1 };
+enum { ORC_RECON_WENO5 = 0, ORC_RECON_TVD2 = 1 };
 
 orc *orc_create(int ndim, int ni, int nj, int nk, const double *xf, const double *yf,
                 const double *zf, const int *bc, int nvert, int nfacet, const double *vert,
                 const int *facet, double mach, double re, double pr, double gamma, int scheme,
                 int family, double dt, double cfl_tau, int n_inner, int motion,
-                const double *mpar, const double *uinf, int wall_pressure);
+                const double *mpar, const double *uinf, int wall_pressure, int reconstruction);
 void orc_destroy(orc *o);
 
 /* a1: body pose at time t (no-op for a stationary body). */
@@ -74,6 +75,8 @@ double orc_get_param(orc *o, int which);
 
 /* pins */
 double orc_weno5(double a, double b, double c, double d, double e);
+/* second-order TVD face state (MUSCL, minmod) seen from b, between b and c */
+double orc_tvd2(double a, double b, double c);
 void orc_ldfss(int ndim, const double *wl, const double *wr, const double *nrm, double gamma,
                int precond, double uc2, double *flux);
 

@@ -41,6 +41,7 @@ class Case:
     # free-stream velocity (unit speed, or zero for a body moving through still fluid)
     u_inf: tuple = (1.0, 0.0, 0.0)
     wall_pressure: str = "eq6"     # "eq6" | "eq7" (supersonic moving body, 2D)
+    reconstruction: str = "weno5"  # "weno5" | "tvd2" (section 2)
 
     @property
     def ni(self):
@@ -217,7 +218,8 @@ def small_case(kind, n=64, steps=2, **kw):
         return Case(f"small-cylinder-{n}", 2, f, f.copy(), _z_dummy(),
                     ("farfield",) * 4 + ("periodic",) * 2, v, s, m, 40.0,
                     dt=rk3_dt(m, 40.0, [f, f]), steps=steps,
-                    ib_family=kw.get("ib_family", "linear"))
+                    ib_family=kw.get("ib_family", "linear"),
+                    reconstruction=kw.get("reconstruction", "weno5"))
     if kind == "moving-cylinder":
         f = uniform_faces(n, -4.0, 4.0)
         v, s = circle_polygon(kw.get("nseg", 64), 1.0)
