@@ -64,6 +64,7 @@ enum { IBM_IB_LINEAR = 0, IBM_IB_QUADRATIC = 1 };
 enum { IBM_FP64 = 0, IBM_MIXED = 1 };
 enum { IBM_FLUID = 0, IBM_FORCING = 1, IBM_G1 = 2, IBM_G2 = 3, IBM_G3 = 4, IBM_SOLID = 5 };
 enum { IBM_WALL_EQ6 = 0, IBM_WALL_EQ7 = 1 };
+enum { IBM_RECON_WENO5 = 0, IBM_RECON_TVD2 = 1 };
 
 /* Case descriptor; all pointers are host pointers, copied by ibm_create. */
 typedef struct ibm_case {
@@ -99,6 +100,8 @@ typedef struct ibm_case {
     int wall_pressure;        /* IBM_WALL_EQ6: dp/dn = -rho a_n (eq.6);            */
                               /* IBM_WALL_EQ7: dp/dn = rho u_t^2 / R - rho a_n     */
                               /* (eq.7, supersonic moving bodies; 2D only)         */
+    int reconstruction;       /* IBM_RECON_WENO5 (fifth order) or IBM_RECON_TVD2   */
+                              /* (second-order MUSCL, minmod limiter) (section 2)  */
 } ibm_case;
 
 typedef struct ibm_ctx ibm_ctx;

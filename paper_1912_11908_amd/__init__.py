@@ -61,6 +61,7 @@ def case_struct(case, precision="fp64"):
         c.u_inf[d] = float(u[d]) if d < len(u) else 0.0
     c.motion_vel = float(mo.get("velocity", 0.0))
     c.wall_pressure = {"eq6": 0, "eq7": 1}[getattr(case, "wall_pressure", "eq6")]
+    c.reconstruction = {"weno5": 0, "tvd2": 1}[getattr(case, "reconstruction", "weno5")]
     return c, keep
 
 

@@ -131,6 +131,8 @@ int check_desc(const ibm_case *c)
         return IBM_EINVAL;
     if (c->wall_pressure == IBM_WALL_EQ7 && c->ndim != 2)
         return IBM_EINVAL;
+    if (c->reconstruction != IBM_RECON_WENO5 && c->reconstruction != IBM_RECON_TVD2)
+        return IBM_EINVAL;
     return IBM_OK;
 }
 
@@ -860,6 +862,7 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
         f.uinf2 += c->u_inf[d] * c->u_inf[d];
     }
     f.wallp = c->wall_pressure;
+    f.recon = c->reconstruction;
     f.Hinf = c->gamma / (c->gamma - 1.0) * f.pinf + 0.5 * f.uinf2;
     f.dt = c->dt;
     f.cfl_tau = c->cfl_tau;

@@ -61,6 +61,7 @@ struct Flow {
     double uinf[3], uinf2;   // free-stream velocity and its square
     int scheme, family, precision;
     int wallp;               // IBM_WALL_EQ6 / IBM_WALL_EQ7
+    int recon;               // IBM_RECON_WENO5 / IBM_RECON_TVD2
 };
 
 // Immersed-boundary work area.

@@ -497,7 +497,27 @@ __device__ inline void weno5_pair(R v0, R v1, R v2, R v3, R v4, R v5, R &wl, R &
 template <typename R> struct FlowR {
     R gamma, gm1inv, pinf, mu, kc, uc2, uinf2;
     bool precond;
+    bool tvd;  // second-order TVD faces instead of WENO5
 };
+
+// Second-order TVD face states (section 2 names the scheme, not its limiter;
+// MUSCL with the minmod limiter): from cell v1 | v2 | v3 | v4 the left and
+// right states at the face between v2 and v3.
+template <typename R> __device__ inline R minmod(R x, R y)
+{
+    if (x > R(0) && y > R(0))
+        return x < y ? x : y;
+    if (x < R(0) && y < R(0))
+        return x > y ? x : y;
+    return R(0);
+}
+
+template <typename R>
+__device__ inline void tvd2_pair(R v1, R v2, R v3, R v4, R &wl, R &wr)
+{
+    wl = v2 + R(0.5) * minmod<R>(v2 - v1, v3 - v2);
+    wr = v3 + R(0.5) * minmod<R>(v3 - v4, v2 - v3);
+}
 
 __device__ inline double sgn1(double m) { return m >= 0.0 ? 1.0 : -1.0; }
 __device__ inline float sgn1(float m) { return m >= 0.0f ? 1.0f : -1.0f; }
@@ -613,8 +633,12 @@ __device__ inline void face_flux(const Real *__restrict__ S, int base, const int
 #pragma unroll
     for (int m = 0; m < NV; ++m) {
         const Real *s = S + m * LCELLS + base;
-        Real v0 = s[-2 * SD], v1 = s[-SD], v2 = s[0], v3 = s[SD], v4 = s[2 * SD], v5 = s[3 * SD];
-        weno5_pair<Real>(v0, v1, v2, v3, v4, v5, wl[m], wr[m]);
+        if (fp.tvd) {
+            tvd2_pair<Real>(s[-SD], s[0], s[SD], s[2 * SD], wl[m], wr[m]);
+        } else {
+            Real v0 = s[-2 * SD], v1 = s[-SD], v2 = s[0], v3 = s[SD], v4 = s[2 * SD], v5 = s[3 * SD];
+            weno5_pair<Real>(v0, v1, v2, v3, v4, v5, wl[m], wr[m]);
+        }
     }
     ldfss_pert<Real, NV, D>(wl, wr, fp, flux);
 
@@ -918,6 +942,7 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
     fp.uc2 = (Real)f.uc2;
     fp.uinf2 = (Real)f.uinf2;
     fp.precond = f.scheme == IBM_DUAL;
+    fp.tvd = f.recon == IBM_RECON_TVD2;
     // 2. face fluxes, one pass per direction (compile-time direction)
     int fl0 = (tz * TY + ty) * (TX + 1) + tx;  // x-face at i - 1/2
     int fl1 = (tz * (TY + 1) + ty) * TX + tx;  // y-face at j - 1/2

@@ -22,6 +22,7 @@ SMALL = {
     "tube-moving": lambda: w.small_case("tube", 32, steps=3, nz=8, ntheta=64, nzt=4),
     "tube-static": lambda: w.small_case("tube", 30, steps=2, nz=10, ntheta=48, nzt=5, moving=False),
     "octahedron": lambda: _octahedron_case(),
+    "cylinder-tvd": lambda: w.small_case("cylinder", 64, steps=4, reconstruction="tvd2"),
     "supersonic-moving": lambda: w.small_case("supersonic-moving-cylinder", 40, steps=4),
     "supersonic-moving-eq7": lambda: w.small_case("supersonic-moving-cylinder", 40, steps=4,
                                                   wall_pressure="eq7"),
@@ -68,7 +69,8 @@ def test_classification_lists_records_exact(kind):
 
 
 @pytest.mark.parametrize("kind", ["cylinder", "cylinder-quad", "wedge", "naca", "ragged",
-                                  "tube-static", "octahedron", "supersonic-moving", "supersonic-moving-eq7"])
+                                  "tube-static", "octahedron", "supersonic-moving", "supersonic-moving-eq7",
+                                  "cylinder-tvd"])
 def test_fill_and_residual_fp64(kind):
     case, prim, s, o = _classified(kind)
     s.fill(0.0)
@@ -93,7 +95,7 @@ def test_fill_and_residual_fp64(kind):
 
 @pytest.mark.parametrize("kind", ["cylinder", "cylinder-quad", "wedge", "ragged", "moving-cylinder",
                                   "tube-moving", "tube-static", "octahedron", "supersonic-moving",
-                                  "supersonic-moving-eq7"])
+                                  "supersonic-moving-eq7", "cylinder-tvd"])
 def test_rk3_steps_fp64(kind):
     case, prim, s, o = _classified(kind)
     n = case.steps
@@ -180,7 +182,7 @@ def test_nonfinite_status_reported():
     assert s.status() == -4
 
 
-@pytest.mark.parametrize("kind", ["cylinder", "wedge", "naca", "tube-moving", "supersonic-moving"])
+@pytest.mark.parametrize("kind", ["cylinder", "wedge", "naca", "tube-moving", "supersonic-moving", "cylinder-tvd"])
 def test_mixed_precision_error(kind):
     """Mixed mode (FP32 reconstruction and fluxes on perturbation variables,
     FP64 update) stays within a stated distance of the FP64 oracle."""
