@@ -88,10 +88,11 @@ def _parse():
     ap.add_argument("--serving-rate", type=float, default=50.0)
     ap.add_argument("--no-other-configs", action="store_true",
                     help="skip the cylinder, airfoil and tube workloads")
-    ap.add_argument("--config-only", choices=("cylinder", "airfoil", "tube", "supersonic", "shock"),
+    ap.add_argument("--config-only", choices=("cylinder", "airfoil", "tube", "supersonic", "shock", "preprocessing"),
                     help="time only that one of the other workloads and print its line (for profiling); "
                          "supersonic: the moving / stationary cylinder pair of section 8.2.3; "
-                         "shock: the shock-driven free cylinder of section 8.2.6")
+                         "shock: the shock-driven free cylinder of section 8.2.6; "
+                         "preprocessing: the sphere-in-a-cube timing of appendix A")
     ap.add_argument("--supersonic-t", type=float, default=10.0,
                     help="convective times t* of the supersonic cylinder pair")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -218,6 +219,44 @@ def supersonic_pair(t_end, mach=1.2, precision="mixed"):
     return out
 
 
+def preprocessing(reps=50):
+    """Appendix A (Table A1) on the GPU: the IB preprocessing of a
+    1200-triangle sphere in a 40^3 cube -- ray-parity classification,
+    tagging, list compaction, closest features, normals, P' and probe
+    stencils (one ibm_classify call) -- timed with HIP events, next to the
+    oracle's same work on the host cores."""
+    import torch
+    import workloads as w
+    from workloads.cases import case_sphere_preprocessing
+    import paper_1912_11908_amd as P
+    import oracle
+    case = case_sphere_preprocessing(40)
+    s = P.Solver(case, "fp64", "cuda:0")
+    s.init_prim(w.freestream_prim(3, case.ni, case.nj, case.nk, case.p_inf))
+    s.classify()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        s.classify()
+    e1.record(st)
+    torch.cuda.synchronize()
+    gpu_s = e0.elapsed_time(e1) / 1e3 / reps
+    cnt = s.counts()
+    o = oracle.Oracle(case)
+    o.classify()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        o.classify()
+    cpu_s = (time.perf_counter() - t0) / 3
+    return {"workload": "sphere of 1200 triangles (D = 1) in a 40^3 cube [-1, 1]^3",
+            "forcing_nodes": int(cnt[0]), "ghost_nodes": int(cnt[4]),
+            "gpu_s_per_preprocessing": gpu_s, "oracle_s_per_preprocessing": cpu_s,
+            "oracle_threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+            "paper_table_A1_rtln_s": {"1 core": 4.296e-2, "8 cores": 5.3778e-3}}
+
+
 def shock_driven(t_end=2.0):
     """Section 8.2.6: a free cylinder driven by a Mach 1.5 shock (656^2
     cells, D / 164), eq.10 coupling; per precision the wall time per coupled
@@ -317,6 +356,9 @@ def main():
     import torch
     import workloads as w
 
+    if args.config_only == "preprocessing":
+        print(json.dumps({"preprocessing": preprocessing()}), flush=True)
+        return
     if args.config_only == "shock":
         print(json.dumps({"shock_driven": shock_driven()}), flush=True)
         return

@@ -23,6 +23,7 @@ SMALL = {
     "tube-static": lambda: w.small_case("tube", 30, steps=2, nz=10, ntheta=48, nzt=5, moving=False),
     "octahedron": lambda: _octahedron_case(),
     "cylinder-tvd": lambda: w.small_case("cylinder", 64, steps=4, reconstruction="tvd2"),
+    "sphere": lambda: w.cases.case_sphere_preprocessing(24),
     "supersonic-moving": lambda: w.small_case("supersonic-moving-cylinder", 40, steps=4),
     "supersonic-moving-eq7": lambda: w.small_case("supersonic-moving-cylinder", 40, steps=4,
                                                   wall_pressure="eq7"),

@@ -75,3 +75,36 @@ def tube_mesh(radius=0.5, n_theta=512, n_z=64, z_lo=-2.0, z_hi=2.0,
             tri.append((p00, p10, p11))
             tri.append((p00, p11, p01))
     return v, np.asarray(tri, dtype=np.int32)
+
+
+def sphere_mesh(n_theta=30, n_phi=21, diameter=1.0, center=(0.0, 0.0, 0.0)):
+    """Closed UV sphere: n_phi - 1 latitude rings of n_theta vertices plus
+    the two poles, 2 n_theta (n_phi - 1) triangles (1200 for 30 x 21),
+    counter-clockwise seen from outside."""
+    r = 0.5 * diameter
+    phis = np.pi * np.arange(1, n_phi) / n_phi            # interior latitudes
+    t = 2.0 * np.pi * np.arange(n_theta) / n_theta
+    verts = [(center[0], center[1], center[2] + r)]          # north pole
+    for ph in phis:
+        for a in t:
+            verts.append((center[0] + r * np.sin(ph) * np.cos(a), center[1] + r * np.sin(ph) * np.sin(a),
+                          center[2] + r * np.cos(ph)))
+    verts.append((center[0], center[1], center[2] - r))      # south pole
+    v = snap(np.asarray(verts))
+    south = len(verts) - 1
+
+    def ring(k, a):
+        return 1 + k * n_theta + (a % n_theta)
+
+    tri = []
+    for a in range(n_theta):
+        tri.append((0, ring(0, a), ring(0, a + 1)))
+    for k in range(n_phi - 2):
+        for a in range(n_theta):
+            p00, p01 = ring(k, a), ring(k, a + 1)
+            p10, p11 = ring(k + 1, a), ring(k + 1, a + 1)
+            tri.append((p00, p10, p11))
+            tri.append((p00, p11, p01))
+    for a in range(n_theta):
+        tri.append((south, ring(n_phi - 2, a + 1), ring(n_phi - 2, a)))
+    return v, np.asarray(tri, dtype=np.int32)

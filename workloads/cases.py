@@ -10,7 +10,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .grids import uniform_faces, tanh_center_faces, core_stretched_faces
-from .bodies import circle_polygon, wedge_polygon, naca00_polygon, tube_mesh
+from .bodies import circle_polygon, wedge_polygon, naca00_polygon, tube_mesh, sphere_mesh
 
 BC_NAMES = ("farfield", "extrap", "periodic")
 
@@ -206,6 +206,16 @@ def case_shock_cylinder(n=656, t_end=2.0, density_ratio=1.0):
     return Case(f"shock-driven-cylinder-{n}", 2, xf, yf, _z_dummy(), ("extrap",) * 4 + ("periodic",) * 2, v, s,
                 m, re, dt=dt, steps=steps, u_inf=(0.0, 0.0, 0.0),
                 motion=dict(axis=0, mass=mass, free=True, velocity=0.0))
+
+
+def case_sphere_preprocessing(n=40):
+    """Appendix A: a sphere of 1200 triangles (D = 1, centre at the origin)
+    in a cube [-1, 1]^3 of n^3 cells, for timing the IB preprocessing
+    (classification, tagging, closest features, stencils)."""
+    f = uniform_faces(n, -1.0, 1.0)
+    v, t = sphere_mesh(30, 21, 1.0)
+    return Case(f"sphere-preprocessing-{n}", 3, f, f.copy(), f.copy(), ("farfield",) * 6, v, t, 0.3, 100.0,
+                dt=rk3_dt(0.3, 100.0, [f, f, f]))
 
 
 def small_case(kind, n=64, steps=2, **kw):
