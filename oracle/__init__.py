@@ -43,7 +43,7 @@ def lib():
         P = ctypes.c_void_p
         d, i = ctypes.c_double, ctypes.c_int
         L.orc_create.restype = P
-        L.orc_create.argtypes = [i, i, i, i, P, P, P, P, i, i, P, P, d, d, d, d, i, i, d, d, i, i, P, P, i, i]
+        L.orc_create.argtypes = [i, i, i, i, P, P, P, P, i, i, P, P, d, d, d, d, i, i, d, d, i, i, P, P, i, i, i]
         L.orc_destroy.argtypes = [P]
         L.orc_set_pose.argtypes = [P, d]
         L.orc_set_body.argtypes = [P, d, d, d]
@@ -130,7 +130,8 @@ class Oracle:
             _p(vert), _p(facet), c.mach, c.reynolds, c.prandtl, c.gamma,
             0 if c.scheme == "rk3" else 1, 0 if c.ib_family == "linear" else 1, c.dt,
             c.cfl_tau, c.n_inner, (2 if mo.get("free") else 1) if mo else 0, _p(mpar), _p(uinf),
-            {"eq6": 0, "eq7": 1}[c.wall_pressure], {"weno5": 0, "tvd2": 1}[c.reconstruction])
+            {"eq6": 0, "eq7": 1}[c.wall_pressure], {"weno5": 0, "tvd2": 1}[c.reconstruction],
+            {"rtln": 0, "sdsn": 1}[c.ib_framework])
         self.t = 0.0
         self.step_index = 0
 

@@ -55,6 +55,7 @@ struct orc {
     double uinf[3];       /* free-stream velocity */
     int wallp;            /* ORC_WALL_EQ6 / ORC_WALL_EQ7 */
     int recon;            /* ORC_RECON_WENO5 / ORC_RECON_TVD2 */
+    int frame;            /* ORC_FRAME_RTLN / ORC_FRAME_SDSN */
     i64 disp;
     /* classification */
     uint8_t *cls, *cls_prev;
@@ -260,7 +261,8 @@ orc *orc_create(int ndim, int ni, int nj, int nk, const double *xf, const double
                 const double *zf, const int *bc, int nvert, int nfacet, const double *vert,
                 const int *facet, double mach, double re, double pr, double gamma, int scheme,
                 int family, double dt, double cfl_tau, int n_inner, int motion,
-                const double *mpar, const double *uinf, int wall_pressure, int reconstruction)
+                const double *mpar, const double *uinf, int wall_pressure, int reconstruction,
+                int framework)
 {
     orc *o = (orc *)calloc(1, sizeof(orc));
     o->ndim = ndim;
@@ -310,6 +312,7 @@ orc *orc_create(int ndim, int ni, int nj, int nk, const double *xf, const double
         o->uinf[d] = uinf[d];
     o->wallp = wall_pressure;
     o->recon = reconstruction;
+    o->frame = framework;
     o->gamma = gamma;
     o->mach = mach;
     o->re = re;
@@ -519,6 +522,8 @@ static int nbr(const orc *o, int i, int j, int k, int d, int s, long *out)
     return 1;
 }
 
+static int sd_inside2d(const orc *o, const double *X);
+
 int orc_classify(orc *o)
 {
     long ncell = (long)o->ni * o->nj * o->nk;
@@ -535,7 +540,10 @@ int orc_classify(orc *o)
         i64 px = o->Xc[i], py = o->Yc[j];
         if (px < lo[0] || px > hi[0] || py < lo[1] || py > hi[1])
             continue;
-        if (o->ndim == 2)
+        if (o->ndim == 2 && o->frame == ORC_FRAME_SDSN) {
+            double X[3] = {o->xc[i + 3], o->yc[j + 3], 0.0};
+            in[c] = (uint8_t)sd_inside2d(o, X);
+        } else if (o->ndim == 2)
             in[c] = (uint8_t)inside2d(o, px, py);
         else {
             i64 pz = o->Zc[k];
@@ -653,6 +661,19 @@ static closest_t closest2d(const orc *o, const double *p)
         }
     }
     return best;
+}
+
+/* The standard HCIB/GC classification the paper replaces (section 3.2; its
+ * comparison in section 7): signed distance, inside where (X - P0) . n_f < 0
+ * with P0 the closest surface point and n_f the outward normal of the
+ * closest facet (the lowest facet id among equals).  Near a
+ * sharp corner the closest facet's normal does not separate inside from
+ * outside, which is its known failure. */
+static int sd_inside2d(const orc *o, const double *X)
+{
+    closest_t cl = closest2d(o, X);
+    const double *n = o->fnrm + 3 * cl.facet;
+    return (X[0] - cl.c[0]) * n[0] + (X[1] - cl.c[1]) * n[1] < 0.0;
 }
 
 /* 3D closest point on a triangle: the minimiser of eq.1 is either the
@@ -921,7 +942,12 @@ static void node_geometry(orc *o, int r, long c, int is_forcing)
         n[d] = src[d];
     double P[3] = {cl.c[0], cl.c[1], cl.c[2]};
     int fb = 0;
-    if (cl.kind != FEAT_FACE) {
+    if (o->frame == ORC_FRAME_SDSN) {
+        /* surface-normal reconstruction (the standard HCIB/GC): the closest
+         * facet's normal through the closest point, whatever the feature */
+        for (int d = 0; d < 3; d++)
+            n[d] = o->fnrm[3 * cl.facet + d];
+    } else if (cl.kind != FEAT_FACE) {
         double dir[3] = {0, 0, 0};
         for (int d = 0; d < nd; d++)
             dir[d] = is_forcing ? -n[d] : n[d];

@@ -30,12 +30,17 @@ enum { ORC_RK3 = 0, ORC_DUAL = 1 };
 enum { ORC_IB_LINEAR = 0, ORC_IB_QUADRATIC = 1 };
 enum { ORC_WALL_EQ6 = 0, ORC_WALL_EQ7 = 1 };
 enum { ORC_RECON_WENO5 = 0, ORC_RECON_TVD2 = 1 };
+/* RTLN: ray-tracing classification and local normals (the paper's
+ * framework); SDSN: signed-distance classification and surface normals (the
+ * standard HCIB/GC it is compared with; 2D) */
+enum { ORC_FRAME_RTLN = 0, ORC_FRAME_SDSN = 1 };
 
 orc *orc_create(int ndim, int ni, int nj, int nk, const double *xf, const double *yf,
                 const double *zf, const int *bc, int nvert, int nfacet, const double *vert,
                 const int *facet, double mach, double re, double pr, double gamma, int scheme,
                 int family, double dt, double cfl_tau, int n_inner, int motion,
-                const double *mpar, const double *uinf, int wall_pressure, int reconstruction);
+                const double *mpar, const double *uinf, int wall_pressure, int reconstruction,
+                int framework);
 void orc_destroy(orc *o);
 
 /* a1: body pose at time t (no-op for a stationary body). */

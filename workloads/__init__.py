@@ -10,14 +10,14 @@ inside/outside decisions on exact integers.
 """
 from .grids import (LATTICE_BITS, snap, uniform_faces, tanh_center_faces,
                     core_stretched_faces)
-from .bodies import circle_polygon, wedge_polygon, naca00_polygon, tube_mesh, sphere_mesh
+from .bodies import circle_polygon, wedge_polygon, naca00_polygon, star_polygon, tube_mesh, sphere_mesh
 from .fields import freestream_prim, random_periodic_prim, entropy_wave_prim
 from .cases import Case, case_c1, case_c2, case_c3, case_c4, small_case, CASES
 from .serving import request_stream
 
 __all__ = [
     "LATTICE_BITS", "snap", "uniform_faces", "tanh_center_faces",
-    "core_stretched_faces", "circle_polygon", "wedge_polygon", "naca00_polygon",
+    "core_stretched_faces", "circle_polygon", "wedge_polygon", "naca00_polygon", "star_polygon",
     "tube_mesh", "sphere_mesh", "freestream_prim", "random_periodic_prim", "entropy_wave_prim",
     "Case", "case_c1", "case_c2", "case_c3", "case_c4", "small_case", "CASES",
     "request_stream",

@@ -33,6 +33,16 @@ def wedge_polygon(half_angle_deg=15.0, length=1.0, apex=(-0.5, 0.0)):
     return _polygon(v)
 
 
+def star_polygon(n_tips=5, r_out=1.0, r_in=0.38, center=(0.0, 0.0), rot_deg=90.0):
+    """Regular star: n_tips outer vertices on radius r_out alternating with
+    inner vertices on r_in (a non-convex body with acute tips)."""
+    k = np.arange(2 * n_tips)
+    t = np.radians(rot_deg) + np.pi * k / n_tips
+    r = np.where(k % 2 == 0, r_out, r_in)
+    v = np.stack([center[0] + r * np.cos(t), center[1] + r * np.sin(t)], axis=1)
+    return _polygon(v)
+
+
 def naca00_polygon(thickness=0.12, n_vert=1024, x0=0.0, chord=1.0):
     """Symmetric NACA 4-digit section with a closed, sharp trailing edge
     (last coefficient -0.1036), cosine-spaced; n_vert unique vertices."""

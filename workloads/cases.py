@@ -10,7 +10,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .grids import uniform_faces, tanh_center_faces, core_stretched_faces
-from .bodies import circle_polygon, wedge_polygon, naca00_polygon, tube_mesh, sphere_mesh
+from .bodies import circle_polygon, wedge_polygon, naca00_polygon, star_polygon, tube_mesh, sphere_mesh
 
 BC_NAMES = ("farfield", "extrap", "periodic")
 
@@ -42,6 +42,9 @@ class Case:
     u_inf: tuple = (1.0, 0.0, 0.0)
     wall_pressure: str = "eq6"     # "eq6" | "eq7" (supersonic moving body, 2D)
     reconstruction: str = "weno5"  # "weno5" | "tvd2" (section 2)
+    # "rtln": ray tracing + local normals (the paper's framework); "sdsn":
+    # signed distance + surface normals (the standard HCIB/GC, 2D)
+    ib_framework: str = "rtln"
 
     @property
     def ni(self):
@@ -229,14 +232,24 @@ def small_case(kind, n=64, steps=2, **kw):
                     ("farfield",) * 4 + ("periodic",) * 2, v, s, m, 40.0,
                     dt=rk3_dt(m, 40.0, [f, f]), steps=steps,
                     ib_family=kw.get("ib_family", "linear"),
-                    reconstruction=kw.get("reconstruction", "weno5"))
+                    reconstruction=kw.get("reconstruction", "weno5"),
+                    ib_framework=kw.get("ib_framework", "rtln"))
+    if kind == "star":
+        # a non-convex body with acute tips (the signed-distance failure case)
+        f = uniform_faces(n, -1.5, 1.5)
+        v, s = star_polygon(5, 1.0, 0.38)
+        return Case(f"small-star-{n}", 2, f, f.copy(), _z_dummy(),
+                    ("farfield",) * 4 + ("periodic",) * 2, v, s, 0.3, 100.0,
+                    dt=rk3_dt(0.3, 100.0, [f, f]), steps=steps,
+                    ib_framework=kw.get("ib_framework", "rtln"))
     if kind == "moving-cylinder":
         f = uniform_faces(n, -4.0, 4.0)
         v, s = circle_polygon(kw.get("nseg", 64), 1.0)
         motion = dict(axis=1, amplitude=0.2, frequency=0.2, phase=0.0)
         return Case(f"small-moving-cylinder-{n}", 2, f, f.copy(), _z_dummy(),
                     ("farfield",) * 4 + ("periodic",) * 2, v, s, 0.2, 185.0,
-                    dt=rk3_dt(0.2, 185.0, [f, f]), motion=motion, steps=steps)
+                    dt=rk3_dt(0.2, 185.0, [f, f]), motion=motion, steps=steps,
+                    ib_framework=kw.get("ib_framework", "rtln"))
     if kind == "shock-cylinder":
         # section 8.2.6 in miniature: a free cylinder, the shock already over
         # its front half
@@ -261,7 +274,8 @@ def small_case(kind, n=64, steps=2, **kw):
         v, s = wedge_polygon(15.0, 1.0, (-0.5, 0.0))
         bc = ("farfield", "extrap", "extrap", "extrap", "periodic", "periodic")
         return Case(f"small-wedge-{2*n}x{n}", 2, xf, yf, _z_dummy(), bc, v, s, 2.0, 1.0e4,
-                    dt=rk3_dt(2.0, 1.0e4, [xf, yf]), steps=steps)
+                    dt=rk3_dt(2.0, 1.0e4, [xf, yf]), steps=steps,
+                    ib_framework=kw.get("ib_framework", "rtln"))
     if kind == "naca":
         h = kw.get("h", 1.0 / 32)
         xf = core_stretched_faces(2 * n, -4.0, 5.0, -0.5, 1.5, h)
@@ -270,7 +284,8 @@ def small_case(kind, n=64, steps=2, **kw):
         m = kw.get("mach", 0.001)
         return Case(f"small-naca-{2*n}x{n}", 2, xf, yf, _z_dummy(), ("farfield",) * 4 + ("periodic",) * 2,
                     v, s, m, 1000.0, scheme="dual", ib_family="quadratic",
-                    dt=dual_dt([xf, yf]), n_inner=kw.get("n_inner", 4), steps=steps)
+                    dt=dual_dt([xf, yf]), n_inner=kw.get("n_inner", 4), steps=steps,
+                    ib_framework=kw.get("ib_framework", "rtln"))
     if kind == "tube":
         xf = uniform_faces(n, -2.0, 4.0)
         yf = uniform_faces(n, -3.0, 3.0)
