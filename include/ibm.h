@@ -65,6 +65,12 @@ enum { IBM_FP64 = 0, IBM_MIXED = 1 };
 enum { IBM_FLUID = 0, IBM_FORCING = 1, IBM_G1 = 2, IBM_G2 = 3, IBM_G3 = 4, IBM_SOLID = 5 };
 enum { IBM_WALL_EQ6 = 0, IBM_WALL_EQ7 = 1 };
 enum { IBM_RECON_WENO5 = 0, IBM_RECON_TVD2 = 1 };
+/* IB framework: ray-tracing classification with local normals (sections 3-4),
+ * or the standard HCIB/GC one it is compared with in section 7: signed-distance
+ * classification (inside where (X - P0) . n_f < 0, n_f the outward normal of
+ * the closest facet, lowest id among equals) with the facet normal through the
+ * closest point as the reconstruction direction (2D only). */
+enum { IBM_FRAME_RTLN = 0, IBM_FRAME_SDSN = 1 };
 
 /* Case descriptor; all pointers are host pointers, copied by ibm_create. */
 typedef struct ibm_case {
@@ -102,6 +108,7 @@ typedef struct ibm_case {
                               /* (eq.7, supersonic moving bodies; 2D only)         */
     int reconstruction;       /* IBM_RECON_WENO5 (fifth order) or IBM_RECON_TVD2   */
                               /* (second-order MUSCL, minmod limiter) (section 2)  */
+    int ib_framework;         /* IBM_FRAME_RTLN, or IBM_FRAME_SDSN (2D only)       */
 } ibm_case;
 
 typedef struct ibm_ctx ibm_ctx;

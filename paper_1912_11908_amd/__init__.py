@@ -62,6 +62,7 @@ def case_struct(case, precision="fp64"):
     c.motion_vel = float(mo.get("velocity", 0.0))
     c.wall_pressure = {"eq6": 0, "eq7": 1}[getattr(case, "wall_pressure", "eq6")]
     c.reconstruction = {"weno5": 0, "tvd2": 1}[getattr(case, "reconstruction", "weno5")]
+    c.ib_framework = {"rtln": 0, "sdsn": 1}[getattr(case, "ib_framework", "rtln")]
     return c, keep
 
 

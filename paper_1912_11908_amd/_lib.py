@@ -37,7 +37,7 @@ class IbmCase(ctypes.Structure):
         ("scheme", ctypes.c_int), ("ib_family", ctypes.c_int), ("precision", ctypes.c_int),
         ("dt", ctypes.c_double), ("cfl_tau", ctypes.c_double), ("n_inner", ctypes.c_int),
         ("u_inf", ctypes.c_double * 3), ("motion_vel", ctypes.c_double), ("wall_pressure", ctypes.c_int),
-        ("reconstruction", ctypes.c_int),
+        ("reconstruction", ctypes.c_int), ("ib_framework", ctypes.c_int),
     ]
 
 

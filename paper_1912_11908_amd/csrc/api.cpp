@@ -133,6 +133,10 @@ int check_desc(const ibm_case *c)
         return IBM_EINVAL;
     if (c->reconstruction != IBM_RECON_WENO5 && c->reconstruction != IBM_RECON_TVD2)
         return IBM_EINVAL;
+    if (c->ib_framework != IBM_FRAME_RTLN && c->ib_framework != IBM_FRAME_SDSN)
+        return IBM_EINVAL;
+    if (c->ib_framework == IBM_FRAME_SDSN && c->ndim != 2)
+        return IBM_EINVAL;
     return IBM_OK;
 }
 
@@ -693,8 +697,12 @@ int do_classify(ibm_ctx *c, double t, hipStream_t s)
         double disp, vel, acc;
         motion_kin(c, t, disp, vel, acc);
         long long dl = std::llrint(disp * kLatScale);
-        for (int d = 0; d < 3; ++d)
-            c->b.disp[d] = d == c->mo.axis ? (double)dl / kLatScale : 0.0;
+        for (int d = 0; d < 3; ++d) {
+            long long sh = d == c->mo.axis ? dl : 0;
+            c->b.disp[d] = (double)sh / kLatScale;
+            c->b.lat_lo[d] = c->rest_box_lat[2 * d] + sh;
+            c->b.lat_hi[d] = c->rest_box_lat[2 * d + 1] + sh;
+        }
         e = launch_pose(c->g, c->b, dl, c->mo.axis, s);
         if (e != hipSuccess)
             return dev_err(c, e, "pose");
@@ -834,6 +842,17 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     b.bin_start = L.bin_start;
     b.bin_facet = L.bin_facet;
     b.fbox = L.fbox;
+    b.frame = c->ib_framework;
+    for (int d = 0; d < 3; ++d) {
+        long long lo = 0, hi = 0;
+        for (int m = 0; m < c->nvert && d < nd; ++m) {
+            long long v = h.V0[(size_t)m * nd + d];
+            lo = m == 0 ? v : std::min(lo, v);
+            hi = m == 0 ? v : std::max(hi, v);
+        }
+        x->rest_box_lat[2 * d] = b.lat_lo[d] = lo;
+        x->rest_box_lat[2 * d + 1] = b.lat_hi[d] = hi;
+    }
     if (e == hipSuccess) e = up(L.bin_start, h.bin_start);
     if (e == hipSuccess) e = up(L.bin_facet, h.bin_facet);
     if (e == hipSuccess && !h.fbox.empty()) e = up(L.fbox, h.fbox);

@@ -54,6 +54,10 @@ struct Body {
     const int *bin_start, *bin_facet;
     const double *fbox;      // per facet: rest-frame bounding box lo[3], hi[3]
     double disp[3];          // current displacement of the pose (exact)
+    // IBM_FRAME_*; for the signed-distance classification the posed lattice
+    // box of the vertices (cells outside it are outside the body)
+    int frame;
+    long long lat_lo[3], lat_hi[3];
 };
 
 struct Flow {

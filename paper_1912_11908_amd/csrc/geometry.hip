@@ -891,7 +891,12 @@ __device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib
     double n[3] = {src[0], src[1], src[2]};
     double P[3] = {cl.c[0], cl.c[1], cl.c[2]};
     int fb = 0;
-    if (cl.kind != FEAT_FACE) {
+    if (b.frame == IBM_FRAME_SDSN) {
+        // surface normal: the closest segment's normal through the closest
+        // point, whatever the feature
+        for (int d = 0; d < 3; ++d)
+            n[d] = b.fnrm[3 * cl.facet + d];
+    } else if (cl.kind != FEAT_FACE) {
         double dir[3] = {0.0, 0.0, 0.0};
         for (int d = 0; d < nd; ++d)
             dir[d] = forcing ? -n[d] : n[d];
@@ -1036,6 +1041,32 @@ __device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib
     ib.plan_mode[r] = mode1 | (mode2 << 4);
 }
 
+// Signed-distance classification (the standard HCIB/GC compared with in
+// section 7, 2D): a region cell inside the posed lattice box of the body is
+// inside iff (X - P0) . n_f < 0, with P0 its closest surface point and n_f
+// the outward normal of the closest segment (lowest id among equals).  One
+// wavefront per cell; overwrites the inside flags.
+__global__ __launch_bounds__(kBlock) void sd_inside_kernel(Grid g, Body b, IB ib, int ncell)
+{
+    int lane = threadIdx.x % kWave;
+    int wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+    int nwave = gridDim.x * blockDim.x / kWave;
+    for (int rc = wave; rc < ncell; rc += nwave) {
+        int li = rc % ib.rw, lj = rc / ib.rw;
+        int i = li + ib.region[0], j = lj + ib.region[2];
+        long long px = g.Xc[0][i], py = g.Xc[1][j];
+        int in = 0;
+        if (px >= b.lat_lo[0] && px <= b.lat_hi[0] && py >= b.lat_lo[1] && py <= b.lat_hi[1]) {
+            double X[3] = {g.xc[0][i + 3], g.xc[1][j + 3], 0.0};
+            Closest cl = closest2d(b, X, lane);
+            const double *n = b.fnrm + 3 * cl.facet;
+            in = (X[0] - cl.c[0]) * n[0] + (X[1] - cl.c[1]) * n[1] < 0.0;
+        }
+        if (lane == 0)
+            ib.inside[rc] = (uint8_t)in;
+    }
+}
+
 inline int blocks_for(long long n, int bs) { return (int)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -1061,7 +1092,11 @@ hipError_t launch_classify(const Grid &g, const Body &b, IB &ib, hipStream_t s)
         return hipGetLastError();
     hipLaunchKernelGGL(clear_kernel, dim3(blocks_for(nmax, kBlock)), dim3(kBlock), 0, s, ib.inside,
                        ncell, ib.toggle, nwords);
-    if (b.nfacet > 0) {
+    if (b.nfacet > 0 && b.frame == IBM_FRAME_SDSN) {
+        int nb = blocks_for(ncell, kBlock / kWave);
+        nb = nb < 8192 ? nb : 8192;
+        hipLaunchKernelGGL(sd_inside_kernel, dim3(nb), dim3(kBlock), 0, s, g, b, ib, ncell);
+    } else if (b.nfacet > 0) {
         if (g.ndim == 2)
             hipLaunchKernelGGL(cross2d_kernel, dim3(blocks_for(b.nfacet, kBlock / kWave)), dim3(kBlock),
                                0, s, g, b, ib);

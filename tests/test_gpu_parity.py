@@ -27,6 +27,15 @@ SMALL = {
     "supersonic-moving": lambda: w.small_case("supersonic-moving-cylinder", 40, steps=4),
     "supersonic-moving-eq7": lambda: w.small_case("supersonic-moving-cylinder", 40, steps=4,
                                                   wall_pressure="eq7"),
+    # signed-distance classification + surface normals, and the non-convex
+    # star on which it differs from ray parity
+    "star": lambda: w.small_case("star", 64, steps=4),
+    "star-sdsn": lambda: w.small_case("star", 64, steps=4, ib_framework="sdsn"),
+    "wedge-sdsn": lambda: w.small_case("wedge", 48, steps=4, ib_framework="sdsn"),
+    "naca-sdsn": lambda: w.small_case("naca", 48, steps=2, n_inner=3, ib_framework="sdsn"),
+    "cylinder-quad-sdsn": lambda: w.small_case("cylinder", 64, steps=4, ib_family="quadratic",
+                                               nseg=32, ib_framework="sdsn"),
+    "moving-cylinder-sdsn": lambda: w.small_case("moving-cylinder", 64, steps=4, ib_framework="sdsn"),
 }
 
 
@@ -71,7 +80,8 @@ def test_classification_lists_records_exact(kind):
 
 @pytest.mark.parametrize("kind", ["cylinder", "cylinder-quad", "wedge", "naca", "ragged",
                                   "tube-static", "octahedron", "supersonic-moving", "supersonic-moving-eq7",
-                                  "cylinder-tvd"])
+                                  "cylinder-tvd", "star", "star-sdsn", "wedge-sdsn", "naca-sdsn",
+                                  "cylinder-quad-sdsn"])
 def test_fill_and_residual_fp64(kind):
     case, prim, s, o = _classified(kind)
     s.fill(0.0)
@@ -96,7 +106,8 @@ def test_fill_and_residual_fp64(kind):
 
 @pytest.mark.parametrize("kind", ["cylinder", "cylinder-quad", "wedge", "ragged", "moving-cylinder",
                                   "tube-moving", "tube-static", "octahedron", "supersonic-moving",
-                                  "supersonic-moving-eq7", "cylinder-tvd"])
+                                  "supersonic-moving-eq7", "cylinder-tvd", "star", "star-sdsn", "wedge-sdsn",
+                                  "cylinder-quad-sdsn", "moving-cylinder-sdsn"])
 def test_rk3_steps_fp64(kind):
     case, prim, s, o = _classified(kind)
     n = case.steps

@@ -87,7 +87,8 @@ def test_invalid_descriptors_rejected():
     c, keep = P.case_struct(case)
     n = ctypes.c_size_t(0)
     assert L.ibm_workspace_bytes(ctypes.byref(c), ctypes.byref(n)) == 0
-    bad = [("ndim", 4), ("ni", 2), ("mach", -1.0), ("scheme", 7), ("precision", 3), ("dt", 0.0)]
+    bad = [("ndim", 4), ("ni", 2), ("mach", -1.0), ("scheme", 7), ("precision", 3), ("dt", 0.0),
+           ("ib_framework", 2), ("reconstruction", 5), ("wall_pressure", 3)]
     for field, val in bad:
         c2, keep2 = P.case_struct(case)
         setattr(c2, field, val)
@@ -104,10 +105,16 @@ def test_invalid_descriptors_rejected():
     case3.facet[0, 0] = 10 ** 6
     c4, keep4 = P.case_struct(case3)
     assert L.ibm_workspace_bytes(ctypes.byref(c4), ctypes.byref(n)) == -1
+    # the signed-distance framework is 2D only
+    tube = w.small_case("tube", 16, nz=4, ntheta=16, nzt=2)
+    c5, keep5 = P.case_struct(tube)
+    assert L.ibm_workspace_bytes(ctypes.byref(c5), ctypes.byref(n)) == 0
+    c5.ib_framework = 1
+    assert L.ibm_workspace_bytes(ctypes.byref(c5), ctypes.byref(n)) == -1
     # null output pointer and workspace too small never touch the device
     h = ctypes.c_void_p()
     assert L.ibm_create(ctypes.byref(c), ctypes.c_void_p(1), 16, ctypes.byref(h)) == -5
-    del keep, keep2, keep3, keep4
+    del keep, keep2, keep3, keep4, keep5
 
 
 def test_product_path_has_no_cpu_fallback():
