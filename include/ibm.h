@@ -69,7 +69,7 @@ enum { IBM_RECON_WENO5 = 0, IBM_RECON_TVD2 = 1 };
  * or the standard HCIB/GC one it is compared with in section 7: signed-distance
  * classification (inside where (X - P0) . n_f < 0, n_f the outward normal of
  * the closest facet, lowest id among equals) with the facet normal through the
- * closest point as the reconstruction direction (2D only). */
+ * closest point as the reconstruction direction. */
 enum { IBM_FRAME_RTLN = 0, IBM_FRAME_SDSN = 1 };
 
 /* Case descriptor; all pointers are host pointers, copied by ibm_create. */
@@ -108,7 +108,7 @@ typedef struct ibm_case {
                               /* (eq.7, supersonic moving bodies; 2D only)         */
     int reconstruction;       /* IBM_RECON_WENO5 (fifth order) or IBM_RECON_TVD2   */
                               /* (second-order MUSCL, minmod limiter) (section 2)  */
-    int ib_framework;         /* IBM_FRAME_RTLN, or IBM_FRAME_SDSN (2D only)       */
+    int ib_framework;         /* IBM_FRAME_RTLN or IBM_FRAME_SDSN                  */
 } ibm_case;
 
 typedef struct ibm_ctx ibm_ctx;

@@ -522,7 +522,7 @@ static int nbr(const orc *o, int i, int j, int k, int d, int s, long *out)
     return 1;
 }
 
-static int sd_inside2d(const orc *o, const double *X);
+static int sd_inside(const orc *o, const double *X);
 
 int orc_classify(orc *o)
 {
@@ -540,17 +540,15 @@ int orc_classify(orc *o)
         i64 px = o->Xc[i], py = o->Yc[j];
         if (px < lo[0] || px > hi[0] || py < lo[1] || py > hi[1])
             continue;
-        if (o->ndim == 2 && o->frame == ORC_FRAME_SDSN) {
-            double X[3] = {o->xc[i + 3], o->yc[j + 3], 0.0};
-            in[c] = (uint8_t)sd_inside2d(o, X);
+        if (o->ndim == 3 && (o->Zc[k] < lo[2] || o->Zc[k] > hi[2]))
+            continue;
+        if (o->frame == ORC_FRAME_SDSN) {
+            double X[3] = {o->xc[i + 3], o->yc[j + 3], o->ndim == 3 ? o->zc[k + 3] : 0.0};
+            in[c] = (uint8_t)sd_inside(o, X);
         } else if (o->ndim == 2)
             in[c] = (uint8_t)inside2d(o, px, py);
-        else {
-            i64 pz = o->Zc[k];
-            if (pz < lo[2] || pz > hi[2])
-                continue;
-            in[c] = (uint8_t)inside3d(o, px, py, pz);
-        }
+        else
+            in[c] = (uint8_t)inside3d(o, px, py, o->Zc[k]);
     }
     /* tagging */
     for (long c = 0; c < ncell; c++)
@@ -663,19 +661,6 @@ static closest_t closest2d(const orc *o, const double *p)
     return best;
 }
 
-/* The standard HCIB/GC classification the paper replaces (section 3.2; its
- * comparison in section 7): signed distance, inside where (X - P0) . n_f < 0
- * with P0 the closest surface point and n_f the outward normal of the
- * closest facet (the lowest facet id among equals).  Near a
- * sharp corner the closest facet's normal does not separate inside from
- * outside, which is its known failure. */
-static int sd_inside2d(const orc *o, const double *X)
-{
-    closest_t cl = closest2d(o, X);
-    const double *n = o->fnrm + 3 * cl.facet;
-    return (X[0] - cl.c[0]) * n[0] + (X[1] - cl.c[1]) * n[1] < 0.0;
-}
-
 /* 3D closest point on a triangle: the minimiser of eq.1 is either the
  * interior stationary point (region R1, a face feature) or lies on the
  * boundary, where it is the best of the three segment minimisers (edge
@@ -760,6 +745,22 @@ static closest_t closest3d(const orc *o, const double *p)
         }
     }
     return best;
+}
+
+/* The standard HCIB/GC classification the paper replaces (section 3.2; its
+ * comparison in section 7): signed distance, inside where (X - P0) . n_f < 0
+ * with P0 the closest surface point and n_f the outward normal of the
+ * closest facet (the lowest facet id among equals).  Near a sharp edge or
+ * corner the closest facet's normal need not separate inside from outside,
+ * which is its known failure. */
+static int sd_inside(const orc *o, const double *X)
+{
+    closest_t cl = o->ndim == 2 ? closest2d(o, X) : closest3d(o, X);
+    const double *n = o->fnrm + 3 * cl.facet;
+    double s = 0.0;
+    for (int d = 0; d < o->ndim; d++)
+        s += (X[d] - cl.c[d]) * n[d];
+    return s < 0.0;
 }
 
 /* First intersection (smallest sigma >= 0, sigma <= smax) of the line

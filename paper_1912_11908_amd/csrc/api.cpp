@@ -135,8 +135,6 @@ int check_desc(const ibm_case *c)
         return IBM_EINVAL;
     if (c->ib_framework != IBM_FRAME_RTLN && c->ib_framework != IBM_FRAME_SDSN)
         return IBM_EINVAL;
-    if (c->ib_framework == IBM_FRAME_SDSN && c->ndim != 2)
-        return IBM_EINVAL;
     return IBM_OK;
 }
 

@@ -1042,25 +1042,35 @@ __device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib
 }
 
 // Signed-distance classification (the standard HCIB/GC compared with in
-// section 7, 2D): a region cell inside the posed lattice box of the body is
+// section 7): a region cell inside the posed lattice box of the body is
 // inside iff (X - P0) . n_f < 0, with P0 its closest surface point and n_f
-// the outward normal of the closest segment (lowest id among equals).  One
+// the outward normal of the closest facet (lowest id among equals).  One
 // wavefront per cell; overwrites the inside flags.
 __global__ __launch_bounds__(kBlock) void sd_inside_kernel(Grid g, Body b, IB ib, int ncell)
 {
+    __shared__ int lds[kBlock / kWave][2][kWave];
     int lane = threadIdx.x % kWave;
+    int *nb = lds[threadIdx.x / kWave][0], *st = lds[threadIdx.x / kWave][1];
     int wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
     int nwave = gridDim.x * blockDim.x / kWave;
+    int nd = g.ndim;
     for (int rc = wave; rc < ncell; rc += nwave) {
-        int li = rc % ib.rw, lj = rc / ib.rw;
-        int i = li + ib.region[0], j = lj + ib.region[2];
-        long long px = g.Xc[0][i], py = g.Xc[1][j];
+        int li = rc % ib.rw, lj = (rc / ib.rw) % ib.rh, lk = rc / (ib.rw * ib.rh);
+        int c[3] = {li + ib.region[0], lj + ib.region[2], lk + ib.region[4]};
+        bool inbox = true;
+        for (int d = 0; d < nd; ++d) {
+            long long p = g.Xc[d][c[d]];
+            inbox = inbox && p >= b.lat_lo[d] && p <= b.lat_hi[d];
+        }
         int in = 0;
-        if (px >= b.lat_lo[0] && px <= b.lat_hi[0] && py >= b.lat_lo[1] && py <= b.lat_hi[1]) {
-            double X[3] = {g.xc[0][i + 3], g.xc[1][j + 3], 0.0};
-            Closest cl = closest2d(b, X, lane);
+        if (inbox) {
+            double X[3] = {g.xc[0][c[0] + 3], g.xc[1][c[1] + 3], nd == 3 ? g.xc[2][c[2] + 3] : 0.0};
+            Closest cl = nd == 2 ? closest2d(b, X, lane) : closest3d(b, X, lane, nb, st);
             const double *n = b.fnrm + 3 * cl.facet;
-            in = (X[0] - cl.c[0]) * n[0] + (X[1] - cl.c[1]) * n[1] < 0.0;
+            double sd = 0.0;
+            for (int d = 0; d < nd; ++d)
+                sd += (X[d] - cl.c[d]) * n[d];
+            in = sd < 0.0;
         }
         if (lane == 0)
             ib.inside[rc] = (uint8_t)in;

@@ -36,6 +36,10 @@ SMALL = {
     "cylinder-quad-sdsn": lambda: w.small_case("cylinder", 64, steps=4, ib_family="quadratic",
                                                nseg=32, ib_framework="sdsn"),
     "moving-cylinder-sdsn": lambda: w.small_case("moving-cylinder", 64, steps=4, ib_framework="sdsn"),
+    "sphere-sdsn": lambda: w.cases.case_sphere_preprocessing(24, "sdsn"),
+    "tube-static-sdsn": lambda: w.small_case("tube", 30, steps=2, nz=10, ntheta=48, nzt=5, moving=False,
+                                             ib_framework="sdsn"),
+    "tube-moving-sdsn": lambda: w.small_case("tube", 32, steps=3, nz=8, ntheta=64, nzt=4, ib_framework="sdsn"),
 }
 
 
@@ -81,7 +85,7 @@ def test_classification_lists_records_exact(kind):
 @pytest.mark.parametrize("kind", ["cylinder", "cylinder-quad", "wedge", "naca", "ragged",
                                   "tube-static", "octahedron", "supersonic-moving", "supersonic-moving-eq7",
                                   "cylinder-tvd", "star", "star-sdsn", "wedge-sdsn", "naca-sdsn",
-                                  "cylinder-quad-sdsn"])
+                                  "cylinder-quad-sdsn", "tube-static-sdsn"])
 def test_fill_and_residual_fp64(kind):
     case, prim, s, o = _classified(kind)
     s.fill(0.0)
@@ -107,7 +111,8 @@ def test_fill_and_residual_fp64(kind):
 @pytest.mark.parametrize("kind", ["cylinder", "cylinder-quad", "wedge", "ragged", "moving-cylinder",
                                   "tube-moving", "tube-static", "octahedron", "supersonic-moving",
                                   "supersonic-moving-eq7", "cylinder-tvd", "star", "star-sdsn", "wedge-sdsn",
-                                  "cylinder-quad-sdsn", "moving-cylinder-sdsn"])
+                                  "cylinder-quad-sdsn", "moving-cylinder-sdsn", "tube-static-sdsn",
+                                  "tube-moving-sdsn"])
 def test_rk3_steps_fp64(kind):
     case, prim, s, o = _classified(kind)
     n = case.steps

@@ -105,11 +105,13 @@ def test_invalid_descriptors_rejected():
     case3.facet[0, 0] = 10 ** 6
     c4, keep4 = P.case_struct(case3)
     assert L.ibm_workspace_bytes(ctypes.byref(c4), ctypes.byref(n)) == -1
-    # the signed-distance framework is 2D only
+    # eq.7 is 2D only; both IB frameworks exist in 2D and 3D
     tube = w.small_case("tube", 16, nz=4, ntheta=16, nzt=2)
     c5, keep5 = P.case_struct(tube)
     assert L.ibm_workspace_bytes(ctypes.byref(c5), ctypes.byref(n)) == 0
     c5.ib_framework = 1
+    assert L.ibm_workspace_bytes(ctypes.byref(c5), ctypes.byref(n)) == 0
+    c5.wall_pressure = 1
     assert L.ibm_workspace_bytes(ctypes.byref(c5), ctypes.byref(n)) == -1
     # null output pointer and workspace too small never touch the device
     h = ctypes.c_void_p()

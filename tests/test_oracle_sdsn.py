@@ -46,7 +46,8 @@ FEAT_FACE, FEAT_VERTEX = 0, 1
 def classes(case):
     o = oracle.Oracle(case)
     o.classify()
-    return o.classes()[0], o
+    cl = o.classes()
+    return (cl[0] if case.ndim == 2 else cl), o
 
 
 @pytest.mark.parametrize("kind,n", [("cylinder", 64), ("wedge", 48), ("naca", 48), ("cylinder", 61)])
@@ -167,3 +168,53 @@ def test_surface_normal_turning_bound_on_polygon_circle(n, nseg):
     assert ang.max() <= np.pi / nseg + 1e-6
     assert ang.max() > 0.1 * np.pi / nseg
     assert ang[~vert].max() < 1e-12
+
+
+def _octahedron(framework):
+    r = 1.1
+    v = w.snap(np.array([[r, 0, 0], [-r, 0, 0], [0, r, 0], [0, -r, 0], [0, 0, r], [0, 0, -r]], float))
+    t = []
+    for a, b in ((0, 2), (2, 1), (1, 3), (3, 0)):
+        t.append([a, b, 4])
+        t.append([b, a, 5])
+    xf = w.uniform_faces(23, -1.37, 1.45)
+    yf = w.uniform_faces(21, -1.41, 1.39)
+    zf = w.uniform_faces(19, -1.33, 1.42)
+    return Case("octahedron", 3, xf, yf, zf, ("farfield",) * 6, v, np.array(t, np.int32), 0.3, 100.0,
+                dt=rk3_dt(0.3, 100.0, [xf, yf, zf]), ib_framework=framework)
+
+
+def _sphere(framework):
+    return w.cases.case_sphere_preprocessing(24, framework)
+
+
+def _tube(framework):
+    return w.small_case("tube", 32, nz=8, ntheta=64, nzt=4, ib_framework=framework)
+
+
+@pytest.mark.parametrize("make", [_sphere, _octahedron, _tube])
+def test_convex_3d_signed_distance_equals_ray_parity(make):
+    """3D: on the UV sphere and the open tube all dihedral angles are
+    obtuse, and every vertex normal cone of the octahedron points out of
+    its box, so the classes agree with ray parity exactly."""
+    rt, _ = classes(make("rtln"))
+    sd, o = classes(make("sdsn"))
+    assert (rt >= SOLID_MIN).sum() > 20
+    np.testing.assert_array_equal(sd, rt)
+
+
+@pytest.mark.parametrize("make", [_sphere, _octahedron])
+def test_surface_normal_records_3d(make):
+    case = make("sdsn")
+    _, o = classes(case)
+    ir, dr = o.records()
+    tri = case.vert[case.facet[ir[:, 3]]]
+    nrm = np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0])
+    nrm /= np.linalg.norm(nrm, axis=1)[:, None]
+    np.testing.assert_allclose(dr[:, :3], nrm, atol=1e-12)
+    P = dr[:, 3:6]
+    assert np.abs(((P - tri[:, 0]) * nrm).sum(1)).max() < 1e-12
+    xc = [0.5 * (f[1:] + f[:-1]) for f in (case.xf, case.yf, case.zf)]
+    c = ir[:, 0]
+    X = np.stack([xc[0][c % case.ni], xc[1][(c // case.ni) % case.nj], xc[2][c // (case.ni * case.nj)]], axis=1)
+    np.testing.assert_allclose(np.linalg.norm(X - P, axis=1), dr[:, 25], rtol=0, atol=1e-13)

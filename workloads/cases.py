@@ -211,14 +211,15 @@ def case_shock_cylinder(n=656, t_end=2.0, density_ratio=1.0):
                 motion=dict(axis=0, mass=mass, free=True, velocity=0.0))
 
 
-def case_sphere_preprocessing(n=40):
+def case_sphere_preprocessing(n=40, ib_framework="rtln"):
     """Appendix A: a sphere of 1200 triangles (D = 1, centre at the origin)
     in a cube [-1, 1]^3 of n^3 cells, for timing the IB preprocessing
-    (classification, tagging, closest features, stencils)."""
+    (classification, tagging, closest features, stencils) of either
+    framework."""
     f = uniform_faces(n, -1.0, 1.0)
     v, t = sphere_mesh(30, 21, 1.0)
     return Case(f"sphere-preprocessing-{n}", 3, f, f.copy(), f.copy(), ("farfield",) * 6, v, t, 0.3, 100.0,
-                dt=rk3_dt(0.3, 100.0, [f, f, f]))
+                dt=rk3_dt(0.3, 100.0, [f, f, f]), ib_framework=ib_framework)
 
 
 def small_case(kind, n=64, steps=2, **kw):
@@ -294,7 +295,8 @@ def small_case(kind, n=64, steps=2, **kw):
         bc = ("farfield",) * 4 + ("periodic",) * 2
         motion = dict(axis=1, amplitude=0.2, frequency=0.2, phase=0.0) if kw.get("moving", True) else {}
         return Case(f"small-tube-{n}", 3, xf, yf, zf, bc, v, t, 0.2, 185.0,
-                    dt=rk3_dt(0.2, 185.0, [xf, yf, zf]), motion=motion, steps=steps)
+                    dt=rk3_dt(0.2, 185.0, [xf, yf, zf]), motion=motion, steps=steps,
+                    ib_framework=kw.get("ib_framework", "rtln"))
     if kind == "box":
         ndim = kw.get("ndim", 2)
         f = uniform_faces(n, 0.0, 1.0)
