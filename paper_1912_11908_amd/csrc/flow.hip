@@ -201,58 +201,42 @@ __device__ inline void prim_of_state(const Flow &f, const double *qv, double &rh
 
 template <int DIM, bool NEST>
 __device__ __forceinline__ void node_fill(const Grid &g, const Flow &f, const IB &ib, const double *q, int r,
-                                          double ub, double ab, int axis, double *qs);
+                                          int c, double ub, double ab, int axis, double *qs);
 
-// value at probe `p` (0 or 1) of record r: weighted sum of (p, u.., T) over
-// the plan's corners (unused corners carry zero weight).  With NEST, a
-// weighted corner that is a FORCING node takes its filled value from
-// ib.fval (stored there by forcing_corners), not from q.
-template <int DIM>
-__device__ __forceinline__ void probe_add(const Flow &f, const double *qv, double w, double *phi)
-{
-    double rho, u[DIM], pr, T;
-    prim_of_state<DIM>(f, qv, rho, u, pr, T);
-    if (w != 0.0) {
-        phi[0] += w * pr;
-#pragma unroll
-        for (int d = 0; d < DIM; ++d)
-            phi[1 + d] += w * u[d];
-        phi[DIM + 1] += w * T;
-    }
-}
-
+// Records are filled by groups of 2^DIM consecutive lanes: lane c of the
+// group takes probe corner c, so that the corners' loads are in flight
+// together.  Value at probe `p` (0 or 1) of record r: the weighted sum of
+// (p, u.., T) over the plan's corners (unused corners carry zero weight),
+// added by butterfly shuffles, so that every lane of the group holds the
+// same sums.  With NEST, a weighted corner that is a FORCING node takes its
+// filled value from ib.fval (stored there by forcing_corners), not from q.
 template <int DIM, bool NEST>
 __device__ __forceinline__ void plan_probe(const Grid &g, const Flow &f, const IB &ib, const double *q, int r,
-                                           int p, double ub, double ab, int axis, double *phi)
+                                           int p, int c, double *phi)
 {
     constexpr int NC = 1 << DIM;
     constexpr int NV = DIM + 2;
+    int idx = (8 * p + c) * ib.cap + r;
+    int off = ib.plan_off[idx];
+    double w = ib.plan_w[idx];
+    int fr = NEST ? ib.plan_frec[idx] : -1;
+    double qv[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
-        phi[v] = 0.0;
-    if constexpr (NEST) {
-#pragma nounroll
-        for (int m = 0; m < NC; ++m) {
-            int off = ib.plan_off[(8 * p + m) * ib.cap + r];
-            double w = ib.plan_w[(8 * p + m) * ib.cap + r];
-            int fr = ib.plan_frec[(8 * p + m) * ib.cap + r];
-            double qv[NV];
+        qv[v] = fr >= 0 ? ib.fval[(long long)v * ib.cap + fr] : q[off + v * g.vs];
+    double rho, u[DIM], pr, T;
+    prim_of_state<DIM>(f, qv, rho, u, pr, T);
+    bool on = w != 0.0;
+    phi[0] = on ? w * pr : 0.0;
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
-                qv[v] = fr >= 0 ? ib.fval[(long long)v * ib.cap + fr] : q[off + v * g.vs];
-            probe_add<DIM>(f, qv, w, phi);
-        }
-    } else {
-#pragma nounroll
-        for (int m = 0; m < NC; ++m) {
-            int off = ib.plan_off[(8 * p + m) * ib.cap + r];
-            double w = ib.plan_w[(8 * p + m) * ib.cap + r];
-            double qv[NV];
+    for (int d = 0; d < DIM; ++d)
+        phi[1 + d] = on ? w * u[d] : 0.0;
+    phi[NV - 1] = on ? w * T : 0.0;
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
-                qv[v] = q[off + v * g.vs];
-            probe_add<DIM>(f, qv, w, phi);
-        }
+    for (int o = 1; o < NC; o <<= 1) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            phi[v] += __shfl_xor(phi[v], o);
     }
 }
 
@@ -260,7 +244,7 @@ __device__ __forceinline__ void plan_probe(const Grid &g, const Flow &f, const I
 // conditions) from the cells of q; NEST as for plan_probe.
 template <int DIM, bool NEST>
 __device__ __forceinline__ void node_fill(const Grid &g, const Flow &f, const IB &ib, const double *q, int r,
-                                          double ub, double ab, int axis, double *qs)
+                                          int c, double ub, double ab, int axis, double *qs)
 {
     constexpr int NV = DIM + 2;
     int cap = ib.cap;
@@ -284,7 +268,7 @@ __device__ __forceinline__ void node_fill(const Grid &g, const Flow &f, const IB
             ru[d] = ubv[d];
     } else {
         double phi1[NV];
-        plan_probe<DIM, NEST>(g, f, ib, q, r, 0, ub, ab, axis, phi1);
+        plan_probe<DIM, NEST>(g, f, ib, q, r, 0, c, phi1);
         double rho1 = phi1[0] / (f.R * phi1[NV - 1]);
         double an = 0.0;
 #pragma unroll
@@ -306,7 +290,7 @@ __device__ __forceinline__ void node_fill(const Grid &g, const Flow &f, const IB
             rT = phi1[NV - 1] + gT * (sx - s1);
         } else {
             double phi2[NV];
-            plan_probe<DIM, NEST>(g, f, ib, q, r, 1, ub, ab, axis, phi2);
+            plan_probe<DIM, NEST>(g, f, ib, q, r, 1, c, phi2);
             double L0 = (sx - s1) * (sx - s2) / (s1 * s2);
             double L1 = sx * (sx - s2) / (s1 * (s1 - s2));
             double L2 = sx * (sx - s1) / (s2 * (s2 - s1));
@@ -342,11 +326,12 @@ __device__ __forceinline__ void node_fill(const Grid &g, const Flow &f, const IB
 }
 
 // The FORCING corners of ghost record r: each one's filled value, from the
-// FLUID cells of q, stored at ib.fval for node_fill<DIM, true>.  Several
-// threads may store the same corner; they store the same value.
+// FLUID cells of q, stored at ib.fval for node_fill<DIM, true>.  Called by
+// the record's lane group; every lane stores every corner (the same value),
+// so that each lane reads back its own store.
 template <int DIM>
 __device__ __forceinline__ void forcing_corners(const Grid &g, const Flow &f, const IB &ib, const double *q,
-                                                int r, double ub, double ab, int axis)
+                                                int r, int c, double ub, double ab, int axis)
 {
     constexpr int NC = 1 << DIM;
 #pragma nounroll
@@ -356,45 +341,54 @@ __device__ __forceinline__ void forcing_corners(const Grid &g, const Flow &f, co
         if (fr < 0)
             continue;
         double qv[DIM + 2];
-        node_fill<DIM, false>(g, f, ib, q, fr, ub, ab, axis, qv);
+        node_fill<DIM, false>(g, f, ib, q, fr, c, ub, ab, axis, qv);
 #pragma unroll
         for (int v = 0; v < DIM + 2; ++v)
             ib.fval[(long long)v * ib.cap + fr] = qv[v];
     }
 }
 
-// fill record r of q in place from the values stored in q
+// fill record r of q in place from the values stored in q (lane group;
+// lane 0 stores)
 template <int DIM>
-__device__ __forceinline__ void fill_one(const Grid &g, const Flow &f, const IB &ib, double *q, int r, double ub,
-                                double ab, int axis)
+__device__ __forceinline__ void fill_one(const Grid &g, const Flow &f, const IB &ib, double *q, int r, int c,
+                                         double ub, double ab, int axis)
 {
     double qs[DIM + 2];
-    node_fill<DIM, false>(g, f, ib, q, r, ub, ab, axis, qs);
+    node_fill<DIM, false>(g, f, ib, q, r, c, ub, ab, axis, qs);
     int node = ib.plan_node[r];
+    if (c == 0) {
 #pragma unroll
-    for (int v = 0; v < DIM + 2; ++v)
-        q[node + v * g.vs] = qs[v];
+        for (int v = 0; v < DIM + 2; ++v)
+            q[node + v * g.vs] = qs[v];
+    }
 }
 
-// FORCING nodes (they read interior FLUID cells only), grid-stride.
+// FORCING nodes (they read interior FLUID cells only), one lane group per
+// record, grid-stride.
 template <int DIM>
 __global__ void forcing_fill_kernel(Grid g, Flow f, IB ib, double *q, double ub, double ab, int axis)
 {
+    constexpr int G = 1 << DIM;
     int nF = min(ib.counts[CNT_F], ib.cap);
-    int stride = gridDim.x * blockDim.x;
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nF; r += stride)
-        fill_one<DIM>(g, f, ib, q, r, ub, ab, axis);
+    int stride = gridDim.x * blockDim.x / G;
+    int c = threadIdx.x % G;
+    for (int r = (blockIdx.x * blockDim.x + threadIdx.x) / G; r < nF; r += stride)
+        fill_one<DIM>(g, f, ib, q, r, c, ub, ab, axis);
 }
 
-// Ghost layers G1-G3 (they read FLUID and FORCING cells), grid-stride.
+// Ghost layers G1-G3 (they read FLUID and FORCING cells), one lane group
+// per record, grid-stride.
 template <int DIM>
 __global__ void ghost_fill_kernel(Grid g, Flow f, IB ib, double *q, double ub, double ab, int axis)
 {
+    constexpr int G = 1 << DIM;
     int nF = min(ib.counts[CNT_F], ib.cap);
     int nG = min(ib.counts[CNT_G], ib.cap - nF);
-    int stride = gridDim.x * blockDim.x;
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nG; t += stride)
-        fill_one<DIM>(g, f, ib, q, nF + t, ub, ab, axis);
+    int stride = gridDim.x * blockDim.x / G;
+    int c = threadIdx.x % G;
+    for (int t = (blockIdx.x * blockDim.x + threadIdx.x) / G; t < nG; t += stride)
+        fill_one<DIM>(g, f, ib, q, nF + t, c, ub, ab, axis);
 }
 
 // ------------------------------------------------ fused residual / update
@@ -859,11 +853,14 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
                 }
             };
             __syncthreads();  // the loaded values are in LDS before IB values replace them
+            // one lane group (2^DIM lanes) per list entry; lane 0 stores
+            constexpr int G = 1 << DIM, NG = NT / G;
+            const int gc = tid % G;
             // sweep 1: the listed FORCING nodes and the FORCING corners the
             // listed ghosts read outside the loaded cells, each filled from
             // FLUID cells and kept in fval; entries without a record keep
             // their stored value
-            for (int e = tid; e < n + nj; e += NT) {
+            for (int e = tid / G; e < n + nj; e += NG) {
                 double qs[NV];
                 if (e < n) {
                     int rec = lr[e];
@@ -878,23 +875,28 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
                         for (int m = 0; m < NV; ++m)
                             qs[m] = A.qin[so + m * g.vs];
                     } else {
-                        node_fill<DIM, false>(g, f, ib, A.qin, rec, A.ub, A.ab, A.axis, qs);
+                        node_fill<DIM, false>(g, f, ib, A.qin, rec, gc, A.ub, A.ab, A.axis, qs);
+                        if (gc == 0) {
+#pragma unroll
+                            for (int m = 0; m < NV; ++m)
+                                ib.fval[(long long)m * ib.cap + rec] = qs[m];
+                        }
+                    }
+                    if (gc == 0)
+                        place(t, so, inside, qs);
+                } else {
+                    int rec = lj[e - n];
+                    node_fill<DIM, false>(g, f, ib, A.qin, rec, gc, A.ub, A.ab, A.axis, qs);
+                    if (gc == 0) {
 #pragma unroll
                         for (int m = 0; m < NV; ++m)
                             ib.fval[(long long)m * ib.cap + rec] = qs[m];
                     }
-                    place(t, so, inside, qs);
-                } else {
-                    int rec = lj[e - n];
-                    node_fill<DIM, false>(g, f, ib, A.qin, rec, A.ub, A.ab, A.axis, qs);
-#pragma unroll
-                    for (int m = 0; m < NV; ++m)
-                        ib.fval[(long long)m * ib.cap + rec] = qs[m];
                 }
             }
             __syncthreads();  // sweep 1's fval stores are seen by the whole block
             // sweep 2: ghost nodes G1-G3, their FORCING corners from fval
-            for (int e = tid; e < n; e += NT) {
+            for (int e = tid / G; e < n; e += NG) {
                 int rec = lr[e];
                 if (rec < nF)
                     continue;
@@ -904,9 +906,10 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
                 where(e, t, so, inside);
                 double qs[NV];
                 if (own_corners)
-                    forcing_corners<DIM>(g, f, ib, A.qin, rec, A.ub, A.ab, A.axis);
-                node_fill<DIM, true>(g, f, ib, A.qin, rec, A.ub, A.ab, A.axis, qs);
-                place(t, so, inside, qs);
+                    forcing_corners<DIM>(g, f, ib, A.qin, rec, gc, A.ub, A.ab, A.axis);
+                node_fill<DIM, true>(g, f, ib, A.qin, rec, gc, A.ub, A.ab, A.axis, qs);
+                if (gc == 0)
+                    place(t, so, inside, qs);
             }
         }
     }
@@ -1529,8 +1532,8 @@ hipError_t launch_bc_fill(const Grid &g, const Flow &f, const IB &ib, double *q,
                           double ab_axis, int axis, hipStream_t s)
 {
     if (ib.cap > 0) {
-        int nbf = blocks_for(ib.cap, kBlock);
-        nbf = nbf < 64 ? nbf : 64;
+        int nbf = blocks_for((long long)ib.cap * (1 << g.ndim), kBlock);
+        nbf = nbf < 256 ? nbf : 256;
         if (g.ndim == 2) {
             hipLaunchKernelGGL(forcing_fill_kernel<2>, dim3(nbf), dim3(kBlock), 0, s, g, f, ib, q, ub_axis,
                                ab_axis, axis);
