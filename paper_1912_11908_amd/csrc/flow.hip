@@ -24,6 +24,12 @@ inline int blocks_for(long long n, int bs) { return (int)((n + bs - 1) / bs); }
 template <typename R> __device__ inline R rcp_fast(R x);
 template <> __device__ inline double rcp_fast<double>(double x) { return 1.0 / x; }
 template <> __device__ inline float rcp_fast<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+// square root: FP64 correctly rounded; FP32 the hardware instruction (about
+// 1 ulp), without the denormal scaling and rounding fix-up of sqrtf (the
+// arguments here are squared sound speeds and Mach numbers, never denormal)
+template <typename R> __device__ inline R sqrt_fast(R x);
+template <> __device__ inline double sqrt_fast<double>(double x) { return sqrt(x); }
+template <> __device__ inline float sqrt_fast<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 __device__ inline long long sidx(const Grid &g, int i, int j, int k)
 {
@@ -457,13 +463,14 @@ template <int DIM> __device__ inline bool ghost_source(const Grid &g, int *c)
 // w_k ~ gamma_k / (12 (eps + beta_k))^2, formed with a single reciprocal
 // (the common factor 12 cancels in the normalised weights).
 template <typename R>
-__device__ inline R weno5_state(R c, R d1, R d2, R d3, R d4, R t0, R t1, R t2)
+__device__ inline R weno5_state(R c, R d1, R d2, R d3, R d4, R t0, R t1, R t2, R k0, R k1, R k2)
 {
+    // k = 13 t (shared with the other state of the face)
     const R e12 = R(12.0e-6);
     R u0 = R(3) * d2 - d1, u1 = d2 + d3, u2 = d4 - R(3) * d3;
-    R s0 = e12 + (R(13) * t0 * t0 + R(3) * u0 * u0);
-    R s1 = e12 + (R(13) * t1 * t1 + R(3) * u1 * u1);
-    R s2 = e12 + (R(13) * t2 * t2 + R(3) * u2 * u2);
+    R s0 = fma(t0, k0, fma(u0, R(3) * u0, e12));
+    R s1 = fma(t1, k1, fma(u1, R(3) * u1, e12));
+    R s2 = fma(t2, k2, fma(u2, R(3) * u2, e12));
     s0 *= s0;
     s1 *= s1;
     s2 *= s2;
@@ -482,10 +489,11 @@ __device__ inline void weno5_pair(R v0, R v1, R v2, R v3, R v4, R v5, R &wl, R &
 {
     R D0 = v1 - v0, D1 = v2 - v1, D2 = v3 - v2, D3 = v4 - v3, D4 = v5 - v4;
     R T1 = D1 - D0, T2 = D2 - D1, T3 = D3 - D2, T4 = D4 - D3;
+    R K1 = R(13) * T1, K2 = R(13) * T2, K3 = R(13) * T3, K4 = R(13) * T4;
     // left: d = (D0, D1, D2, D3), t = (T1, T2, T3)
-    wl = weno5_state<R>(v2, D0, D1, D2, D3, T1, T2, T3);
+    wl = weno5_state<R>(v2, D0, D1, D2, D3, T1, T2, T3, K1, K2, K3);
     // right (v5, v4, v3, v2, v1): d = (-D4, -D3, -D2, -D1), t = (T4, T3, T2)
-    wr = weno5_state<R>(v3, -D4, -D3, -D2, -D1, T4, T3, T2);
+    wr = weno5_state<R>(v3, -D4, -D3, -D2, -D1, T4, T3, T2, K4, K3, K2);
 }
 
 template <typename R> struct FlowR {
@@ -558,7 +566,7 @@ __device__ inline void ldfss_pert(const R *wl, const R *wr, const FlowR<R> &fp, 
         ql2 += wl[1 + e] * wl[1 + e];
         qr2 += wr[1 + e] * wr[1 + e];
     }
-    R al = sqrt(fp.gamma * pl * rcp_fast<R>(rl)), ar = sqrt(fp.gamma * pr * rcp_fast<R>(rr));
+    R al = sqrt_fast<R>(fp.gamma * pl * rcp_fast<R>(rl)), ar = sqrt_fast<R>(fp.gamma * pr * rcp_fast<R>(rr));
     R ah = R(0.5) * (al + ar);
     R at = ah, eps = R(1);
     if (fp.precond) {
@@ -566,7 +574,7 @@ __device__ inline void ldfss_pert(const R *wl, const R *wr, const FlowR<R> &fp, 
         eps = fmin(R(1), fmax(R(0.5) * ql2 + R(0.5) * qr2, fp.uc2) * rcp_fast<R>(ah2));
         if (eps < R(1)) {
             R ub = R(0.5) * (UL + UR);
-            at = R(0.5) * sqrt((R(1) - eps) * (R(1) - eps) * ub * ub + R(4) * eps * ah2);
+            at = R(0.5) * sqrt_fast<R>((R(1) - eps) * (R(1) - eps) * ub * ub + R(4) * eps * ah2);
         }
     }
     R rat = rcp_fast<R>(at);
@@ -576,7 +584,7 @@ __device__ inline void ldfss_pert(const R *wl, const R *wr, const FlowR<R> &fp, 
     R mpl = R(0.25) * (ML + R(1)) * (ML + R(1)), mmr = R(-0.25) * (MR - R(1)) * (MR - R(1));
     R cp = apl * (R(1) + bl) * ML - bl * mpl;
     R cm = amr * (R(1) + br) * MR - br * mmr;
-    R sq = sqrt(R(0.5) * (ML * ML + MR * MR)) - R(1);
+    R sq = sqrt_fast<R>(R(0.5) * (ML * ML + MR * MR)) - R(1);
     R mh = R(0.25) * bl * br * sq * sq;
     R dpp = plp - prp;
     R ri = rcp_fast<R>(at * at);
