@@ -852,15 +852,19 @@ __device__ bool probe_setup(const Grid &g, const uint8_t *cls, const double *y, 
     return true;
 }
 
-// Sections 4.1-4.3: closest feature, local normal (face normal or the
-// pseudo-normals of eqs 2-3), boundary point P' where the line through the
-// node parallel to the normal meets the surface, and probes along it.
-// One wavefront per node: every lane follows the same node (the facet
-// searches are split across the lanes); lane 0 writes.
-__device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib, int r, int nF, int lane,
-                            int *nb, int *st);
+// Sections 4.1-4.3 in two launches.  records_kernel: closest feature,
+// local normal (face normal or the pseudo-normals of eqs 2-3) and the
+// boundary point P' where the line through the node parallel to the normal
+// meets the surface; one wavefront per node (the facet searches are split
+// across the lanes; lane 0 writes).  probes_kernel: the probes along that
+// line and their stencils, one thread per record.
+__device__ void node_geometry(const Grid &g, const Body &b, const Flow &fl, IB &ib, int r, int nF, int lane,
+                              int *nb, int *st);
 
-__global__ __launch_bounds__(kBlock) void records_kernel(Grid g, Body b, Flow fl, IB ib)
+// four wavefronts per SIMD (at most 128 VGPRs): the searches are latency
+// bound, and the occupancy outweighs the few spills it costs
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void records_kernel(Grid g, Body b,
+                                                                                               Flow fl, IB ib)
 {
     __shared__ int lds[kBlock / kWave][2][kWave];
     int nF = min(ib.counts[CNT_F], ib.cap);
@@ -870,20 +874,31 @@ __global__ __launch_bounds__(kBlock) void records_kernel(Grid g, Body b, Flow fl
     int wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
     int nwave = gridDim.x * blockDim.x / kWave;
     for (int r = wave; r < nF + nG; r += nwave)
-        node_record(g, b, fl, ib, r, nF, lane, nb, st);
+        node_geometry(g, b, fl, ib, r, nF, lane, nb, st);
 }
 
-__device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib, int r, int nF, int lane,
-                            int *nb, int *st)
+__device__ inline void node_coords(const Grid &g, int c, int &i, int &j, int &k, double *X, double &h)
+{
+    i = c % g.ni;
+    j = (c / g.ni) % g.nj;
+    k = c / (g.ni * g.nj);
+    X[0] = g.xc[0][i + 3];
+    X[1] = g.xc[1][j + 3];
+    X[2] = g.ndim == 3 ? g.xc[2][k + 3] : 0.0;
+    h = fmin(g.xf[0][i + 4] - g.xf[0][i + 3], g.xf[1][j + 4] - g.xf[1][j + 3]);
+    if (g.ndim == 3)
+        h = fmin(h, g.xf[2][k + 4] - g.xf[2][k + 3]);
+}
+
+__device__ void node_geometry(const Grid &g, const Body &b, const Flow &fl, IB &ib, int r, int nF, int lane,
+                              int *nb, int *st)
 {
     bool forcing = r < nF;
     int c = forcing ? ib.listF[r] : ib.listG[r - nF];
     int nd = g.ndim;
-    int i = c % g.ni, j = (c / g.ni) % g.nj, k = c / (g.ni * g.nj);
-    double X[3] = {g.xc[0][i + 3], g.xc[1][j + 3], nd == 3 ? g.xc[2][k + 3] : 0.0};
-    double h = fmin(g.xf[0][i + 4] - g.xf[0][i + 3], g.xf[1][j + 4] - g.xf[1][j + 3]);
-    if (nd == 3)
-        h = fmin(h, g.xf[2][k + 4] - g.xf[2][k + 3]);
+    int i, j, k;
+    double X[3], h;
+    node_coords(g, c, i, j, k, X, h);
     Closest cl = nd == 2 ? closest2d(b, X, lane) : closest3d(b, X, lane, nb, st);
     const double *src = cl.kind == FEAT_FACE ? b.fnrm + 3 * cl.id
                         : cl.kind == FEAT_VERTEX ? b.vnrm + 3 * cl.id
@@ -892,7 +907,7 @@ __device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib
     double P[3] = {cl.c[0], cl.c[1], cl.c[2]};
     int fb = 0;
     if (b.frame == IBM_FRAME_SDSN) {
-        // surface normal: the closest segment's normal through the closest
+        // surface normal: the closest facet's normal through the closest
         // point, whatever the feature
         for (int d = 0; d < 3; ++d)
             n[d] = b.fnrm[3 * cl.facet + d];
@@ -910,10 +925,60 @@ __device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib
                 atomicAdd(&ib.counts[CNT_FB_PPRIME], 1);
         }
     }
+    if (lane != 0)
+        return;
     double dist2 = 0.0;
     for (int d = 0; d < nd; ++d)
         dist2 += (X[d] - P[d]) * (X[d] - P[d]);
     double sx = forcing ? sqrt(dist2) : -sqrt(dist2);
+    int *ir = ib.rec_i + (long long)kRecI * r;
+    double *dr = ib.rec_d + (long long)kRecD * r;
+    ir[0] = c;
+    ir[1] = cl.kind;
+    ir[2] = cl.id;
+    ir[3] = cl.facet;
+    ir[6] = fb;
+    for (int d = 0; d < 3; ++d) {
+        dr[d] = n[d];
+        dr[3 + d] = P[d];
+    }
+    dr[6] = sx;
+    dr[25] = sqrt(cl.d2);
+    // eq.7: curvature of the closest feature (2D)
+    double kappa = nd == 2 ? (cl.kind == FEAT_FACE ? b.fcurv[cl.id] : b.vcurv[cl.id]) : 0.0;
+    dr[26] = kappa;
+    int cap = ib.cap;
+    ib.plan_kappa[r] = kappa;
+    ib.plan_node[r] = (int)(((long long)(k + g.hz) * g.sy + (j + 3)) * g.sx + (i + 3));
+    for (int d = 0; d < 3; ++d)
+        ib.plan_geo[d * cap + r] = n[d];
+    ib.plan_geo[3 * cap + r] = sx;
+}
+
+// Probes of record r along its line (sections 4.3, 4.5-4.6): s1 = s_X + h
+// (FORCING) or max(-s_X, h) (ghost), s2 = s1 + h; moved out by h/2 up to six
+// times until the stencils are valid, else inverse-distance weights over the
+// valid corners (flagged).  Fill plan: state offsets instead of cell ids,
+// unused corners aimed at the node itself with zero weight, so that the fill
+// loops are branch-free.
+__global__ __launch_bounds__(kBlock) void probes_kernel(Grid g, Flow fl, IB ib)
+{
+    int nF = min(ib.counts[CNT_F], ib.cap);
+    int nG = min(ib.counts[CNT_G], ib.cap - nF);
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nF + nG)
+        return;
+    bool forcing = r < nF;
+    int nd = g.ndim;
+    int *ir = ib.rec_i + (long long)kRecI * r;
+    double *dr = ib.rec_d + (long long)kRecD * r;
+    int c = ir[0];
+    int i, j, k;
+    double X[3], h;
+    node_coords(g, c, i, j, k, X, h);
+    double n[3] = {dr[0], dr[1], dr[2]}, P[3] = {dr[3], dr[4], dr[5]};
+    double sx = dr[6];
+    int fb = ir[6];
     bool quad = fl.family == IBM_IB_QUADRATIC;
     int mode = (!quad && forcing) ? 1 : 0;
     bool allow_forcing = !forcing;
@@ -947,8 +1012,7 @@ __device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib
             y2[d] = P[d] + s2 * n[d];
         }
         fb |= 2;
-        if (lane == 0)
-            atomicAdd(&ib.counts[CNT_FB_PROBE], 1);
+        atomicAdd(&ib.counts[CNT_FB_PROBE], 1);
         mode1 = mode2 = 1;
         bool v1 = probe_setup(g, ib.cls, y1, 1, allow_forcing, ids1, w1);
         bool v2 = quad ? probe_setup(g, ib.cls, y2, 1, allow_forcing, ids2, w2) : true;
@@ -966,22 +1030,27 @@ __device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib
         }
         mode2 = 3;
     }
-    // every lane holds the same record.  Fill plan: state offsets instead of
-    // cell ids, unused corners aimed at the node itself with zero weight, so
-    // the fill loops are branch-free; lane 8 p + m writes probe p's corner m
+    ir[4] = mode1;
+    ir[5] = mode2;
+    ir[6] = fb;
+    for (int m = 0; m < 8; ++m) {
+        ir[7 + m] = ids1[m];
+        ir[15 + m] = ids2[m];
+        dr[9 + m] = w1[m];
+        dr[17 + m] = w2[m];
+    }
+    ir[23] = 0;
+    dr[7] = s1;
+    dr[8] = s2;
+    for (int m = 27; m < kRecD; ++m)
+        dr[m] = 0.0;
     int cap = ib.cap;
-    long long node_off = ((long long)(k + g.hz) * g.sy + (j + 3)) * g.sx + (i + 3);
-    if (lane < 16) {
-        int p = lane / 8, m = lane % 8;
-        int cc = -1;
-        double ws = 0.0;
-#pragma unroll
-        for (int mm = 0; mm < 8; ++mm)
-            if (mm == m) {
-                cc = p ? ids2[mm] : ids1[mm];
-                ws = p ? w2[mm] : w1[mm];
-            }
-        int off = (int)node_off;
+    int node_off = ib.plan_node[r];
+    for (int pm = 0; pm < 16; ++pm) {
+        int p = pm / 8, m = pm % 8;
+        int cc = p ? ids2[m] : ids1[m];
+        double ws = p ? w2[m] : w1[m];
+        int off = node_off;
         double wt = 0.0;
         int frec = -1;
         if (cc >= 0 && ws != 0.0) {
@@ -996,46 +1065,10 @@ __device__ void node_record(const Grid &g, const Body &b, const Flow &fl, IB &ib
                     frec = ib.rmap[(lk * ib.rh + lj) * ib.rw + li];
             }
         }
-        ib.plan_off[(8 * p + m) * cap + r] = off;
-        ib.plan_w[(8 * p + m) * cap + r] = wt;
-        ib.plan_frec[(8 * p + m) * cap + r] = frec;
+        ib.plan_off[pm * cap + r] = off;
+        ib.plan_w[pm * cap + r] = wt;
+        ib.plan_frec[pm * cap + r] = frec;
     }
-    if (lane != 0)
-        return;
-    int *ir = ib.rec_i + (long long)kRecI * r;
-    double *dr = ib.rec_d + (long long)kRecD * r;
-    ir[0] = c;
-    ir[1] = cl.kind;
-    ir[2] = cl.id;
-    ir[3] = cl.facet;
-    ir[4] = mode1;
-    ir[5] = mode2;
-    ir[6] = fb;
-    for (int m = 0; m < 8; ++m) {
-        ir[7 + m] = ids1[m];
-        ir[15 + m] = ids2[m];
-        dr[9 + m] = w1[m];
-        dr[17 + m] = w2[m];
-    }
-    ir[23] = 0;
-    for (int d = 0; d < 3; ++d) {
-        dr[d] = n[d];
-        dr[3 + d] = P[d];
-    }
-    dr[6] = sx;
-    dr[7] = s1;
-    dr[8] = s2;
-    dr[25] = sqrt(cl.d2);
-    // eq.7: curvature of the closest feature (2D)
-    double kappa = nd == 2 ? (cl.kind == FEAT_FACE ? b.fcurv[cl.id] : b.vcurv[cl.id]) : 0.0;
-    dr[26] = kappa;
-    for (int m = 27; m < kRecD; ++m)
-        dr[m] = 0.0;
-    ib.plan_kappa[r] = kappa;
-    ib.plan_node[r] = (int)node_off;
-    for (int d = 0; d < 3; ++d)
-        ib.plan_geo[d * cap + r] = n[d];
-    ib.plan_geo[3 * cap + r] = sx;
     ib.plan_geo[4 * cap + r] = s1;
     ib.plan_geo[5 * cap + r] = s2;
     ib.plan_mode[r] = mode1 | (mode2 << 4);
@@ -1130,6 +1163,7 @@ hipError_t launch_records(const Grid &g, const Body &b, const Flow &f, IB &ib, h
     int nb = blocks_for(ib.cap, kBlock / kWave);  // one wavefront per node
     nb = nb < 4096 ? nb : 4096;
     hipLaunchKernelGGL(records_kernel, dim3(nb), dim3(kBlock), 0, s, g, b, f, ib);
+    hipLaunchKernelGGL(probes_kernel, dim3(blocks_for(ib.cap, kBlock)), dim3(kBlock), 0, s, g, f, ib);
     return hipGetLastError();
 }
 
