@@ -869,6 +869,8 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     f.gamma = c->gamma;
     f.pinf = 1.0 / (c->gamma * c->mach * c->mach);
     f.R = f.pinf;
+    f.rR = 1.0 / f.R;
+    f.gm1inv = 1.0 / (c->gamma - 1.0);
     f.cp = c->gamma * f.R / (c->gamma - 1.0);
     f.mu = 1.0 / c->reynolds;
     f.kc = f.mu * f.cp / c->prandtl;

@@ -63,6 +63,7 @@ struct Body {
 struct Flow {
     double gamma, pinf, R, cp, mu, kc, pr, uc2, Hinf, dt, cfl_tau;
     double uinf[3], uinf2;   // free-stream velocity and its square
+    double rR, gm1inv;       // 1 / R and 1 / (gamma - 1)
     int scheme, family, precision;
     int wallp;               // IBM_WALL_EQ6 / IBM_WALL_EQ7
     int recon;               // IBM_RECON_WENO5 / IBM_RECON_TVD2

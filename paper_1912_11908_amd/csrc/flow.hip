@@ -757,7 +757,7 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
 
 
     // perturbation primitives of state values qv into LDS cell t
-    const double rinv = 1.0 / f.R;
+    const double rinv = f.rR;
     auto put = [&](int t, const double *qv) {
         double v[NS];
         if (f.scheme == IBM_RK3) {
@@ -946,7 +946,7 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
 
     FlowR<Real> fp;
     fp.gamma = (Real)f.gamma;
-    fp.gm1inv = (Real)(1.0 / (f.gamma - 1.0));
+    fp.gm1inv = (Real)f.gm1inv;
     fp.pinf = (Real)f.pinf;
     fp.mu = (Real)f.mu;
     fp.kc = (Real)f.kc;
