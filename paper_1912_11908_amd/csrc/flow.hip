@@ -22,7 +22,17 @@ constexpr int kBlock = 256;
 inline int blocks_for(long long n, int bs) { return (int)((n + bs - 1) / bs); }
 
 template <typename R> __device__ inline R rcp_fast(R x);
-template <> __device__ inline double rcp_fast<double>(double x) { return 1.0 / x; }
+// FP64: the hardware reciprocal refined by two Newton steps (within an ulp
+// or so; the arguments are densities, sound speeds and WENO weight sums,
+// positive and normal)
+template <> __device__ inline double rcp_fast<double>(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
 template <> __device__ inline float rcp_fast<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 // square root: FP64 correctly rounded; FP32 the hardware instruction (about
 // 1 ulp), without the denormal scaling and rounding fix-up of sqrtf (the
@@ -762,7 +772,7 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
         double v[NS];
         if (f.scheme == IBM_RK3) {
             double rho = qv[0];
-            double ri = 1.0 / rho;  // one divide per cell
+            double ri = rcp_fast<double>(rho);  // one reciprocal per cell
             double ke = 0.0;
 #pragma unroll
             for (int d = 0; d < DIM; ++d) {
