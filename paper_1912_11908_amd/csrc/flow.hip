@@ -1074,39 +1074,42 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
         for (int d = 0; d < DIM; ++d)
             u[d] = qc[1 + d];
         double p = f.pinf + pp, T = 1.0 + tp;
-        double rho = p / (f.R * T);
-        double rhop = (pp - f.R * tp) / (f.R * T);  // rho - 1
+        // reciprocals instead of divides (within an ulp or so)
+        double rTi = rcp_fast<double>(T);
+        double rho = p * f.rR * rTi;
+        double rhop = (pp - f.R * tp) * f.rR * rTi;  // rho - 1
+        double rrho = rcp_fast<double>(rho);
         double q2 = 0.0;
         for (int d = 0; d < DIM; ++d)
             q2 += u[d] * u[d];
-        double a2 = f.gamma * p / rho;
+        double a2 = f.gamma * p * rrho;
         double ur2 = fmin(a2, fmax(q2, f.uc2));
-        double eps = ur2 / a2;
-        double nuv = f.mu / rho * fmax(4.0 / 3.0, f.gamma / f.pr);
-        double dxs[3] = {1.0 / g.rdx[0][i + 3], 1.0 / g.rdx[1][j + 3],
-                         DIM == 3 ? 1.0 / g.rdx[2][k + 3] : 1.0};
+        double eps = ur2 * rcp_fast<double>(a2);
+        double nuv = f.mu * rrho * fmax(4.0 / 3.0, f.gamma / f.pr);
         double lam = 0.0;
         for (int d = 0; d < DIM; ++d) {
+            double rdx = g.rdx[d][(d == 0 ? i : d == 1 ? j : k) + 3];
             double ud = u[d];
             double up = 0.5 * (1.0 + eps) * fabs(ud);
             double cpr = 0.5 * sqrt((1.0 - eps) * (1.0 - eps) * ud * ud + 4.0 * eps * a2);
-            lam += (up + cpr) / dxs[d] + 2.0 * nuv / (dxs[d] * dxs[d]);
+            lam += (up + cpr) * rdx + 2.0 * nuv * rdx * rdx;
         }
-        double dtau = f.cfl_tau / lam;
+        double rdt = rcp_fast<double>(f.dt);
         double b0 = A.a, b2 = A.b;
-        double cdt = b0 / f.dt, ctau = 1.0 / dtau;
-        double rp = 1.0 / (f.R * T), rT = -rho / T;
-        double th = 1.0 / ur2 + 1.0 / (f.cp * T);
+        double cdt = b0 * rdt, ctau = lam * rcp_fast<double>(f.cfl_tau);
+        double rp = f.rR * rTi, rT = -rho * rTi;
+        double th = rcp_fast<double>(ur2) + rcp_fast<double>(f.cp * T);
         // perturbation conserved vector of the current state
         double Qp[N];
         Qp[0] = rhop;
         for (int d = 0; d < DIM; ++d)
             Qp[1 + d] = rhop * u[d] + (u[d] - f.uinf[d]);
-        Qp[N - 1] = pp / (f.gamma - 1.0) + 0.5 * (rhop * q2 + q2 - f.uinf2);
+        Qp[N - 1] = pp * f.gm1inv + 0.5 * (rhop * q2 + q2 - f.uinf2);
         double rhs[N];
+#pragma unroll
         for (int m = 0; m < N; ++m) {
             double qn = A.qn[m * g.ncell + cell], qm = A.qnm1[m * g.ncell + cell];
-            rhs[m] = -((b0 * (Qp[m] - qn) - b2 * (qn - qm)) / f.dt + R[m]);
+            rhs[m] = -((b0 * (Qp[m] - qn) - b2 * (qn - qm)) * rdt + R[m]);
         }
         // energy row minus H times the mass row: exact row operation that
         // removes the O(H) terms (H' = c_p T' + (|u|^2 - 1) / 2)
@@ -1118,7 +1121,7 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
             double bdf0 = b0 * (Qp[0] - qn0) - b2 * (qn0 - qm0);
             double bdfE = b0 * (Qp[N - 1] - qnE) - b2 * (qnE - qmE);
             double Rrho = R[0], REp = R[N - 1] - f.Hinf * R[0];
-            rhs[N - 1] = -((bdfE - H * bdf0) / f.dt + (REp - Hp * Rrho));
+            rhs[N - 1] = -((bdfE - H * bdf0) * rdt + (REp - Hp * Rrho));
         }
         double M[N][N];
         for (int r = 0; r < N; ++r)
@@ -1136,34 +1139,51 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
         M[N - 1][0] = -cc;
         M[N - 1][N - 1] = rho * f.cp * cc;
         (void)H;
-        // Gaussian elimination with partial pivoting
+        // Gaussian elimination with partial pivoting; every index is fixed
+        // at compile time (row swaps by selects), so that the matrix stays
+        // in registers, and each pivot is inverted once
+        double dinv[N];
+#pragma unroll
         for (int c = 0; c < N; ++c) {
             int piv = c;
+            double big = fabs(M[c][c]);
+#pragma unroll
             for (int r = c + 1; r < N; ++r)
-                if (fabs(M[r][c]) > fabs(M[piv][c]))
+                if (fabs(M[r][c]) > big) {
+                    big = fabs(M[r][c]);
                     piv = r;
-            if (piv != c) {
-                for (int m = 0; m < N; ++m) {
-                    double t = M[c][m];
-                    M[c][m] = M[piv][m];
-                    M[piv][m] = t;
                 }
-                double t = rhs[c];
-                rhs[c] = rhs[piv];
-                rhs[piv] = t;
-            }
+#pragma unroll
             for (int r = c + 1; r < N; ++r) {
-                double fct = M[r][c] / M[c][c];
+                if (r == piv) {
+#pragma unroll
+                    for (int m = 0; m < N; ++m) {
+                        double t = M[c][m];
+                        M[c][m] = M[r][m];
+                        M[r][m] = t;
+                    }
+                    double t = rhs[c];
+                    rhs[c] = rhs[r];
+                    rhs[r] = t;
+                }
+            }
+            dinv[c] = rcp_fast<double>(M[c][c]);
+#pragma unroll
+            for (int r = c + 1; r < N; ++r) {
+                double fct = M[r][c] * dinv[c];
+#pragma unroll
                 for (int m = c; m < N; ++m)
                     M[r][m] -= fct * M[c][m];
                 rhs[r] -= fct * rhs[c];
             }
         }
+#pragma unroll
         for (int r = N - 1; r >= 0; --r) {
             double sum = rhs[r];
+#pragma unroll
             for (int m = r + 1; m < N; ++m)
                 sum -= M[r][m] * rhs[m];
-            rhs[r] = sum / M[r][r];
+            rhs[r] = sum * dinv[r];
         }
         bool bad = false;
         for (int m = 0; m < N; ++m) {
