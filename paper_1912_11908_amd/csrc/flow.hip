@@ -197,21 +197,22 @@ __device__ inline void prim_of_state(const Flow &f, const double *qv, double &rh
 {
     if (f.scheme == IBM_RK3) {
         rho = qv[0];
+        double ri = rcp_fast<double>(rho);
         double ke = 0.0;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-            u[d] = qv[1 + d] / rho;
+            u[d] = qv[1 + d] * ri;
             ke += u[d] * u[d];
         }
         p = (f.gamma - 1.0) * (qv[DIM + 1] - 0.5 * rho * ke);
-        T = p / (rho * f.R);
+        T = p * ri * f.rR;
     } else {
         p = f.pinf + qv[0];
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
             u[d] = qv[1 + d];
         T = 1.0 + qv[DIM + 1];
-        rho = p / (f.R * T);
+        rho = p * f.rR * rcp_fast<double>(T);
     }
 }
 
@@ -285,7 +286,7 @@ __device__ __forceinline__ void node_fill(const Grid &g, const Flow &f, const IB
     } else {
         double phi1[NV];
         plan_probe<DIM, NEST>(g, f, ib, q, r, 0, c, phi1);
-        double rho1 = phi1[0] / (f.R * phi1[NV - 1]);
+        double rho1 = phi1[0] * f.rR * rcp_fast<double>(phi1[NV - 1]);
         double an = 0.0;
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
@@ -299,29 +300,31 @@ __device__ __forceinline__ void node_fill(const Grid &g, const Flow &f, const IB
             gp = rho1 * ut * ut * ib.plan_kappa[r] - rho1 * an;
         }
         if (!quad || mode2 == 2) {
+            double ratio = sx * rcp_fast<double>(s1);
 #pragma unroll
             for (int d = 0; d < DIM; ++d)
-                ru[d] = ubv[d] + (phi1[1 + d] - ubv[d]) * sx / s1;
+                ru[d] = ubv[d] + (phi1[1 + d] - ubv[d]) * ratio;
             rp = phi1[0] + gp * (sx - s1);
             rT = phi1[NV - 1] + gT * (sx - s1);
         } else {
             double phi2[NV];
             plan_probe<DIM, NEST>(g, f, ib, q, r, 1, c, phi2);
-            double L0 = (sx - s1) * (sx - s2) / (s1 * s2);
-            double L1 = sx * (sx - s2) / (s1 * (s1 - s2));
-            double L2 = sx * (sx - s1) / (s2 * (s2 - s1));
+            double L0 = (sx - s1) * (sx - s2) * rcp_fast<double>(s1 * s2);
+            double L1 = sx * (sx - s2) * rcp_fast<double>(s1 * (s1 - s2));
+            double L2 = sx * (sx - s1) * rcp_fast<double>(s2 * (s2 - s1));
+            double rq = rcp_fast<double>(s2 * s2 - s1 * s1);
 #pragma unroll
             for (int d = 0; d < DIM; ++d)
                 ru[d] = ubv[d] * L0 + phi1[1 + d] * L1 + phi2[1 + d] * L2;
-            double c2p = (phi2[0] - phi1[0] - gp * (s2 - s1)) / (s2 * s2 - s1 * s1);
+            double c2p = (phi2[0] - phi1[0] - gp * (s2 - s1)) * rq;
             double c0p = phi1[0] - gp * s1 - c2p * s1 * s1;
             rp = c0p + gp * sx + c2p * sx * sx;
-            double c2T = (phi2[NV - 1] - phi1[NV - 1] - gT * (s2 - s1)) / (s2 * s2 - s1 * s1);
+            double c2T = (phi2[NV - 1] - phi1[NV - 1] - gT * (s2 - s1)) * rq;
             double c0T = phi1[NV - 1] - gT * s1 - c2T * s1 * s1;
             rT = c0T + gT * sx + c2T * sx * sx;
         }
     }
-    double rrho = rp / (f.R * rT);
+    double rrho = rp * f.rR * rcp_fast<double>(rT);
     if (f.scheme == IBM_RK3) {
         double ke = 0.0;
 #pragma unroll
@@ -331,7 +334,7 @@ __device__ __forceinline__ void node_fill(const Grid &g, const Flow &f, const IB
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
             qs[1 + d] = rrho * ru[d];
-        qs[DIM + 1] = rp / (f.gamma - 1.0) + 0.5 * rrho * ke;
+        qs[DIM + 1] = rp * f.gm1inv + 0.5 * rrho * ke;
     } else {
         qs[0] = rp - f.pinf;
 #pragma unroll
@@ -788,7 +791,7 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
 #pragma unroll
             for (int d = 0; d < DIM; ++d)
                 v[1 + d] = qv[1 + d];
-            v[0] = (pp - f.R * tp) / (f.R * (1.0 + tp));
+            v[0] = (pp - f.R * tp) * f.rR * rcp_fast<double>(1.0 + tp);
             v[DIM + 1] = pp;
             v[DIM + 2] = tp;
         }
