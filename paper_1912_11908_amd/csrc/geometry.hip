@@ -566,11 +566,15 @@ __device__ inline int bin_of(const Body &b, int d, double y) { return (int)floor
 // sum over the lanes numbers the group's entries, and every lane takes
 // every 64th entry, finding its bin by bisection over the sums in LDS.
 // A facet listed in several bins is visited once per listing.
+// With a finite cut2 (the same on every lane), a bin whose box lies farther
+// from the point y than sqrt(cut2) (by more than a margin far above
+// rounding) is skipped: a facet listed there that came closer than that
+// would also be listed in a bin that does not lie that far.
 // Wavefront-uniform control flow; `nb` (the sums) and `st` (the bin
 // starts) are this wavefront's 64-entry LDS slices.
 template <typename Visit>
 __device__ inline void visit_bins(const Body &b, const int *lo, const int *ext, int shell, int lane, int *nb,
-                                  int *st, Visit &&visit)
+                                  int *st, const double *y, double cut2, Visit &&visit)
 {
     int nbox = ext[0] * ext[1] * ext[2];
     for (int base = 0; base < nbox; base += kWave) {
@@ -580,9 +584,23 @@ __device__ inline void visit_bins(const Body &b, const int *lo, const int *ext, 
             bool on = shell < 0 || max(abs(ex - shell), max(abs(ey - shell), abs(ez - shell))) == shell;
             int kx = lo[0] + ex, ky = lo[1] + ey, kz = lo[2] + ez;
             if (on && kx >= 0 && kx < b.bin_n[0] && ky >= 0 && ky < b.bin_n[1] && kz >= 0 && kz < b.bin_n[2]) {
-                int bin = (kz * b.bin_n[1] + ky) * b.bin_n[0] + kx;
-                s = b.bin_start[bin];
-                n = b.bin_start[bin + 1] - s;
+                int k3[3] = {kx, ky, kz};
+                double bd2 = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    double c0 = b.bin_o[d] + k3[d] * b.bin_h, c1 = c0 + b.bin_h;
+                    double u = fmax(fmax(c0 - y[d], y[d] - c1), 0.0);
+                    bd2 += u * u;
+                }
+                bool far = false;
+                if (bd2 > cut2) {
+                    double lb = sqrt(bd2) - 1e-9 * b.bin_h;
+                    far = lb > 0.0 && lb * lb > cut2;
+                }
+                if (!far) {
+                    int bin = (kz * b.bin_n[1] + ky) * b.bin_n[0] + kx;
+                    s = b.bin_start[bin];
+                    n = b.bin_start[bin + 1] - s;
+                }
             }
         }
         int incl = n;
@@ -658,7 +676,8 @@ __device__ Closest closest3d(const Body &b, const double *p, int lane, int *nb, 
     double margin = 1e-9 * b.bin_h;
     for (int K = 0; K <= far; ++K) {
         int lo[3] = {ic[0] - K, ic[1] - K, ic[2] - K}, ext[3] = {2 * K + 1, 2 * K + 1, 2 * K + 1};
-        visit_bins(b, lo, ext, K, lane, nb, st, [&](int f) {
+        double cut2 = best.d2;  // the wavefront's minimum after the inner shells
+        visit_bins(b, lo, ext, K, lane, nb, st, y, cut2, [&](int f) {
             double bd2 = box_dist2(b, y, f);
             if (bd2 > best.d2) {
                 double lb = sqrt(bd2) - margin;
@@ -752,7 +771,7 @@ __device__ double line_hit3d(const Body &b, const double *x, const double *dir, 
         lo[d] = max(0, bin_of(b, d, fmin(y0, y1) - slack));
         ext[d] = max(0, min(b.bin_n[d] - 1, bin_of(b, d, fmax(y0, y1) + slack)) - lo[d] + 1);
     }
-    visit_bins(b, lo, ext, -1, lane, nb, st, [&](int f) {
+    visit_bins(b, lo, ext, -1, lane, nb, st, x, __builtin_inf(), [&](int f) {
         double sig = facet_hit(b, x, dir, smax, f);
         if (sig >= 0.0 && (best < 0.0 || sig < best))
             best = sig;
