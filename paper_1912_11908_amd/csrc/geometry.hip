@@ -783,20 +783,20 @@ __device__ double line_hit3d(const Body &b, const double *x, const double *dir, 
 // interior pairs only, except on a periodic axis where the pair may
 // straddle the boundary (i0 = -1 or i0 + 1 = n, the extended centres being
 // the periodic images)
-__device__ inline bool locate(const double *c, int n, bool periodic, double y, int &i0, double &frac)
+__device__ inline bool locate(const double *c, int n, bool periodic, double y, int hint, int &i0, double &frac)
 {
+    // the unique lo with c[lo] <= y < c[lo + 1], walked to from the index
+    // `hint` (probes lie a few cells from their node)
     int lo = periodic ? -1 : 0, hi = periodic ? n : n - 1;
     if (!(y >= c[lo + 3]) || !(y < c[hi + 3]))
         return false;
-    while (hi - lo > 1) {
-        int mid = (lo + hi) / 2;
-        if (c[mid + 3] <= y)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    i0 = lo;
-    frac = (y - c[lo + 3]) / (c[lo + 4] - c[lo + 3]);
+    int k = min(max(hint, lo), hi - 1);
+    while (c[k + 3] > y)
+        --k;
+    while (c[k + 4] <= y)
+        ++k;
+    i0 = k;
+    frac = (y - c[k + 3]) / (c[k + 4] - c[k + 3]);
     return true;
 }
 
@@ -805,7 +805,7 @@ __device__ inline int wrap_idx(int i, int n) { return ((i % n) + n) % n; }
 // Probe stencil set-up: mode 0 multilinear (all corners valid), mode 1
 // inverse-distance 1/r^2 over the valid corners (a corner at r = 0 takes all
 // the weight).  Valid corners: FLUID, plus FORCING for ghost nodes.
-__device__ bool probe_setup(const Grid &g, const uint8_t *cls, const double *y, int mode,
+__device__ bool probe_setup(const Grid &g, const uint8_t *cls, const double *y, const int *hint, int mode,
                             bool allow_forcing, int *ids, double *w)
 {
     int nd = g.ndim, ncorner = 1 << nd;
@@ -816,10 +816,10 @@ __device__ bool probe_setup(const Grid &g, const uint8_t *cls, const double *y, 
     int i0[3] = {0, 0, 0};
     double fr[3] = {0.0, 0.0, 0.0};
     bool per[3] = {g.bc[0] == IBM_BC_PERIODIC, g.bc[2] == IBM_BC_PERIODIC, g.bc[4] == IBM_BC_PERIODIC};
-    if (!locate(g.xc[0], g.ni, per[0], y[0], i0[0], fr[0]) ||
-        !locate(g.xc[1], g.nj, per[1], y[1], i0[1], fr[1]))
+    if (!locate(g.xc[0], g.ni, per[0], y[0], hint[0], i0[0], fr[0]) ||
+        !locate(g.xc[1], g.nj, per[1], y[1], hint[1], i0[1], fr[1]))
         return false;
-    if (nd == 3 && !locate(g.xc[2], g.nk, per[2], y[2], i0[2], fr[2]))
+    if (nd == 3 && !locate(g.xc[2], g.nk, per[2], y[2], hint[2], i0[2], fr[2]))
         return false;
     int nvalid = 0, zero = -1;
     for (int m = 0; m < ncorner; ++m) {
@@ -997,6 +997,7 @@ __global__ __launch_bounds__(kBlock) void probes_kernel(Grid g, Flow fl, IB ib)
     node_coords(g, c, i, j, k, X, h);
     double n[3] = {dr[0], dr[1], dr[2]}, P[3] = {dr[3], dr[4], dr[5]};
     double sx = dr[6];
+    const int hint[3] = {i, j, k};
     int fb = ir[6];
     bool quad = fl.family == IBM_IB_QUADRATIC;
     int mode = (!quad && forcing) ? 1 : 0;
@@ -1013,8 +1014,8 @@ __global__ __launch_bounds__(kBlock) void probes_kernel(Grid g, Flow fl, IB ib)
             y1[d] = P[d] + s1 * n[d];
             y2[d] = P[d] + s2 * n[d];
         }
-        bool v1 = probe_setup(g, ib.cls, y1, mode, allow_forcing, ids1, w1);
-        bool v2 = quad ? probe_setup(g, ib.cls, y2, mode, allow_forcing, ids2, w2) : true;
+        bool v1 = probe_setup(g, ib.cls, y1, hint, mode, allow_forcing, ids1, w1);
+        bool v2 = quad ? probe_setup(g, ib.cls, y2, hint, mode, allow_forcing, ids2, w2) : true;
         if (v1 && v2) {
             ok = true;
             break;
@@ -1033,8 +1034,8 @@ __global__ __launch_bounds__(kBlock) void probes_kernel(Grid g, Flow fl, IB ib)
         fb |= 2;
         atomicAdd(&ib.counts[CNT_FB_PROBE], 1);
         mode1 = mode2 = 1;
-        bool v1 = probe_setup(g, ib.cls, y1, 1, allow_forcing, ids1, w1);
-        bool v2 = quad ? probe_setup(g, ib.cls, y2, 1, allow_forcing, ids2, w2) : true;
+        bool v1 = probe_setup(g, ib.cls, y1, hint, 1, allow_forcing, ids1, w1);
+        bool v2 = quad ? probe_setup(g, ib.cls, y2, hint, 1, allow_forcing, ids2, w2) : true;
         if (!v1)
             mode1 = 2;
         if (quad && !v2)
