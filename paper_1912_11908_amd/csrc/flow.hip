@@ -34,11 +34,22 @@ template <> __device__ inline double rcp_fast<double>(double x)
     return fma(y, e, y);
 }
 template <> __device__ inline float rcp_fast<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-// square root: FP64 correctly rounded; FP32 the hardware instruction (about
-// 1 ulp), without the denormal scaling and rounding fix-up of sqrtf (the
-// arguments here are squared sound speeds and Mach numbers, never denormal)
+// square root without the denormal scaling and final rounding fix-up of the
+// library (the arguments are squared sound speeds and Mach numbers: zero or
+// positive and normal).  FP64: the hardware reciprocal square root, one
+// Goldschmidt step and one Newton correction (within an ulp or two); FP32:
+// the hardware instruction (about 1 ulp)
 template <typename R> __device__ inline R sqrt_fast(R x);
-template <> __device__ inline double sqrt_fast<double>(double x) { return sqrt(x); }
+template <> __device__ inline double sqrt_fast<double>(double x)
+{
+    double r = __builtin_amdgcn_rsq(x);
+    double g = x * r, h = 0.5 * r;
+    double e = fma(-g, h, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    g = fma(fma(-g, g, x), h, g);
+    return x > 0.0 ? g : x;
+}
 template <> __device__ inline float sqrt_fast<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 __device__ inline long long sidx(const Grid &g, int i, int j, int k)
@@ -1094,7 +1105,7 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
             double rdx = g.rdx[d][(d == 0 ? i : d == 1 ? j : k) + 3];
             double ud = u[d];
             double up = 0.5 * (1.0 + eps) * fabs(ud);
-            double cpr = 0.5 * sqrt((1.0 - eps) * (1.0 - eps) * ud * ud + 4.0 * eps * a2);
+            double cpr = 0.5 * sqrt_fast<double>((1.0 - eps) * (1.0 - eps) * ud * ud + 4.0 * eps * a2);
             lam += (up + cpr) * rdx + 2.0 * nuv * rdx * rdx;
         }
         double rdt = rcp_fast<double>(f.dt);
