@@ -750,9 +750,10 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
     constexpr int NF0 = (TX + 1) * TY * TZ;
     constexpr int NF1 = TX * (TY + 1) * TZ;
     constexpr int NF2 = DIM == 3 ? TX * TY * (TZ + 1) : 0;
-    // 3D keeps the fluxes of one direction at a time (the residual
-    // accumulates per cell in registers), 2D all of them
-    constexpr bool SPLIT = DIM == 3;
+    // 3D and FP64 keep the fluxes of one direction at a time (the residual
+    // accumulates per cell in registers; for FP64 2D that halves the flux
+    // LDS, five blocks per CU instead of four), mixed 2D all of them
+    constexpr bool SPLIT = DIM == 3 || sizeof(Real) == 8;
     constexpr int NFMAX = NF0 > NF1 ? (NF0 > NF2 ? NF0 : NF2) : (NF1 > NF2 ? NF1 : NF2);
     constexpr int NFACE = SPLIT ? NFMAX : NF0 + NF1 + NF2;
     __shared__ Real S[NS * LCELLS];
@@ -1011,13 +1012,15 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
             for (int m = 0; m < NV; ++m)
                 racc[m] += (F[m * NFACE + fl1 + TX] - F[m * NFACE + fl1]) * rd[1];
         }
-        __syncthreads();
-        face_pass<DIM, 2, Real, TX, TY, TZ, HZ>(S, F, NFACE, 0, i0, j0, k0, g, fp, tid);
-        __syncthreads();
-        if (own) {
+        if constexpr (DIM == 3) {
+            __syncthreads();
+            face_pass<DIM, 2, Real, TX, TY, TZ, HZ>(S, F, NFACE, 0, i0, j0, k0, g, fp, tid);
+            __syncthreads();
+            if (own) {
 #pragma unroll
-            for (int m = 0; m < NV; ++m)
-                racc[m] += (F[m * NFACE + fl2 + TX * TY] - F[m * NFACE + fl2]) * rd[2];
+                for (int m = 0; m < NV; ++m)
+                    racc[m] += (F[m * NFACE + fl2 + TX * TY] - F[m * NFACE + fl2]) * rd[2];
+            }
         }
     } else {
         face_pass<DIM, 0, Real, TX, TY, TZ, HZ>(S, F, NFACE, 0, i0, j0, k0, g, fp, tid);
