@@ -135,6 +135,7 @@ def other_configs(only=None):
     plan = [(name, make(), precs, steps, lref) for key, name, make, precs, steps, lref in plan
             if only in (None, key)]
     for name, case, precs, steps, lref in plan:
+        prims = {}
         for prec in precs:
             prim = w.freestream_prim(case.ndim, case.ni, case.nj, case.nk, case.p_inf)
             s = P.Solver(case, prec, "cuda:0")
@@ -149,6 +150,7 @@ def other_configs(only=None):
             out[f"{name} [{prec}]"] = {
                 "cell_updates_per_s": case.ncells * case.evals_per_step * steps / dt,
                 "ms_per_step": dt * 1e3 / steps}
+            prims[prec] = s.to_prim()
             # surface force of the final state (eq.9): coefficients and the
             # device time of one evaluation (fill excluded)
             t_end = s.info().time
@@ -167,6 +169,30 @@ def other_configs(only=None):
                 "C_x": float(2.0 * F[0] / lref), "C_y": float(2.0 * F[1] / lref),
                 "facets": int(case.facet.shape[0]), "ms_per_evaluation": tf * 1e3}
             del s
+        if "mixed" in prims and "fp64" in prims:
+            out[f"{name} [mixed]"]["mixed_vs_fp64_rel_l2"] = mixed_error(prims["mixed"], prims["fp64"],
+                                                                        case.ndim, case.p_inf)
+        del prims
+    return out
+
+
+def mixed_error(a, b, ndim, p_inf):
+    """Relative L2 difference per primitive variable between the mixed and
+    the FP64 state of the same run (device tensors).  Velocity components
+    are measured against the free-stream scale (1 per cell) where their own
+    norm is smaller; the pressure also as p - p_inf, against its own norm."""
+    import torch
+    names = ["rho"] + ["u", "v", "w"][:ndim] + ["p"]
+    out = {}
+    ncell = b[0].numel()
+    for v, nm in enumerate(names):
+        d = torch.linalg.vector_norm(a[v] - b[v]).item()
+        ref = torch.linalg.vector_norm(b[v]).item()
+        if nm in ("u", "v", "w"):
+            ref = max(ref, ncell ** 0.5)
+        out[nm] = d / ref
+    pp = torch.linalg.vector_norm(b[ndim + 1] - p_inf).item()
+    out["p_minus_p_inf"] = torch.linalg.vector_norm(a[ndim + 1] - b[ndim + 1]).item() / pp if pp > 0 else None
     return out
 
 
