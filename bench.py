@@ -88,11 +88,13 @@ def _parse():
     ap.add_argument("--serving-rate", type=float, default=50.0)
     ap.add_argument("--no-other-configs", action="store_true",
                     help="skip the cylinder, airfoil and tube workloads")
-    ap.add_argument("--config-only", choices=("cylinder", "airfoil", "tube", "supersonic", "shock", "preprocessing"),
+    ap.add_argument("--config-only", choices=("cylinder", "airfoil", "tube", "supersonic", "shock", "preprocessing",
+                                              "faces"),
                     help="time only that one of the other workloads and print its line (for profiling); "
                          "supersonic: the moving / stationary cylinder pair of section 8.2.3; "
                          "shock: the shock-driven free cylinder of section 8.2.6; "
-                         "preprocessing: the sphere-in-a-cube timing of appendix A")
+                         "preprocessing: the sphere-in-a-cube timing of appendix A; "
+                         "faces: the wedge with WENO5 and with TVD-2 faces")
     ap.add_argument("--supersonic-t", type=float, default=10.0,
                     help="convective times t* of the supersonic cylinder pair")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -282,6 +284,33 @@ def preprocessing(reps=50):
     return out
 
 
+def face_schemes(steps=500):
+    """The supersonic wedge (1024 x 512, whole RK3 steps, graphs of eight
+    steps) with fifth-order WENO faces and with second-order TVD faces
+    (MUSCL, minmod; section 2), in both precisions."""
+    import dataclasses
+    import torch
+    import workloads as w
+    import paper_1912_11908_amd as P
+    out = {"workload": "supersonic wedge 1024x512, M=2, Re=1e4, SSP-RK3", "steps": steps}
+    for recon in ("weno5", "tvd2"):
+        case = dataclasses.replace(w.case_c2(), reconstruction=recon)
+        for prec in ("mixed", "fp64"):
+            s = P.Solver(case, prec, "cuda:0")
+            s.init_prim(w.freestream_prim(case.ndim, case.ni, case.nj, case.nk, case.p_inf))
+            s.advance(16)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.advance(steps)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            s.check_status()
+            out[f"{recon} [{prec}]"] = {"ms_per_step": dt * 1e3,
+                                         "cell_updates_per_s": case.ncells * case.evals_per_step / dt}
+            del s
+    return out
+
+
 def cpu_baseline_preprocessing(case, reps=3):
     """CPU baseline leg of the appendix A timing: the oracle's classification
     and records of the same case, on this host's cores."""
@@ -396,6 +425,9 @@ def main():
     import torch
     import workloads as w
 
+    if args.config_only == "faces":
+        print(json.dumps({"faces": face_schemes()}), flush=True)
+        return
     if args.config_only == "preprocessing":
         print(json.dumps({"preprocessing": preprocessing()}), flush=True)
         return
