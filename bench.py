@@ -22,6 +22,11 @@ stage kernel is timed separately with HIP events on the launch stream for
 the roofline entry; the CPU oracle is timed on a bounded sample of the same
 workload for the cpu_baseline entry.
 
+Unless --no-other-configs: the cylinder, airfoil and tube workloads (with
+their surface forces and mixed-vs-FP64 errors), the wedge with WENO5 and
+with TVD-2 faces, and the appendix A preprocessing of the 1200-triangle
+sphere in both IB frameworks.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                        [--serving-requests N] [--serving-rate R]
 """
@@ -498,6 +503,8 @@ def main():
         out["mixed_vs_fp64_rel_l2"] = {"rho": errs[0], "u": errs[1], "v": errs[2], "p": errs[3]}
     if not args.no_other_configs:
         out["other_configs"] = other_configs()
+        out["faces"] = face_schemes(200)
+        out["appendix_a"] = preprocessing()
     if args.calibration_copy:
         src = torch.ones(32 << 20, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)
