@@ -24,8 +24,8 @@ workload for the cpu_baseline entry.
 
 Unless --no-other-configs: the cylinder, airfoil and tube workloads (with
 their surface forces and mixed-vs-FP64 errors), the wedge with WENO5 and
-with TVD-2 faces, and the appendix A preprocessing of the 1200-triangle
-sphere in both IB frameworks.
+with TVD-2 faces, the appendix A preprocessing of the 1200-triangle
+sphere in both IB frameworks, and the wedge in both IB frameworks.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                        [--serving-requests N] [--serving-rate R]
@@ -94,12 +94,13 @@ def _parse():
     ap.add_argument("--no-other-configs", action="store_true",
                     help="skip the cylinder, airfoil and tube workloads")
     ap.add_argument("--config-only", choices=("cylinder", "airfoil", "tube", "supersonic", "shock", "preprocessing",
-                                              "faces"),
+                                              "faces", "frameworks"),
                     help="time only that one of the other workloads and print its line (for profiling); "
                          "supersonic: the moving / stationary cylinder pair of section 8.2.3; "
                          "shock: the shock-driven free cylinder of section 8.2.6; "
                          "preprocessing: the sphere-in-a-cube timing of appendix A; "
-                         "faces: the wedge with WENO5 and with TVD-2 faces")
+                         "faces: the wedge with WENO5 and with TVD-2 faces; "
+                         "frameworks: the wedge with ray tracing / local normals and signed distance / surface normals")
     ap.add_argument("--supersonic-t", type=float, default=10.0,
                     help="convective times t* of the supersonic cylinder pair")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -316,6 +317,51 @@ def face_schemes(steps=500):
     return out
 
 
+def frameworks(steps=3000):
+    """Section 7's contrast on the supersonic wedge (mixed precision, from a
+    free-stream start): ray tracing with local normals against signed
+    distance with surface normals.  On this convex body the classes agree
+    (the bounding box makes signed distance exact); the surface normal at the
+    three corners changes the reconstruction there.  Reported: the force
+    coefficients of each (per unit span, length 1), and where and by how much
+    their pressure fields differ."""
+    import dataclasses
+    import numpy as np
+    import torch
+    import workloads as w
+    import paper_1912_11908_amd as P
+    out = {"workload": f"supersonic wedge 1024x512, M=2, Re=1e4, {steps} RK3 steps, mixed", "steps": steps}
+    base = w.case_c2()
+    fields = {}
+    for fw in ("rtln", "sdsn"):
+        case = dataclasses.replace(base, ib_framework=fw)
+        s = P.Solver(case, "mixed", "cuda:0")
+        s.init_prim(w.freestream_prim(case.ndim, case.ni, case.nj, case.nk, case.p_inf))
+        s.advance(steps)
+        s.check_status()
+        t_end = s.info().time
+        fields[fw] = s.to_prim()[3, 0].cpu().numpy()
+        s.classify()
+        s.fill(t_end)
+        F = s.forces().cpu().numpy()
+        out[fw] = {"C_x": float(2.0 * F[0]), "C_y": float(2.0 * F[1]), "t": t_end}
+        del s
+    pinf = base.p_inf
+    a, b = fields["rtln"], fields["sdsn"]
+    d = np.abs(a - b) / pinf
+    j, i = np.unravel_index(np.argmax(d), d.shape)
+    xc = 0.5 * (base.xf[1:] + base.xf[:-1])
+    yc = 0.5 * (base.yf[1:] + base.yf[:-1])
+    corners = base.vert
+    dist = float(np.min(np.hypot(corners[:, 0] - xc[i], corners[:, 1] - yc[j])))
+    out["pressure_difference"] = {
+        "rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(a - pinf)),
+        "max_over_p_inf": float(d.max()), "at": [float(xc[i]), float(yc[j])],
+        "distance_to_nearest_corner": dist,
+        "cells_differing_by_1e-3_p_inf": int((d > 1e-3).sum())}
+    return out
+
+
 def cpu_baseline_preprocessing(case, reps=3):
     """CPU baseline leg of the appendix A timing: the oracle's classification
     and records of the same case, on this host's cores."""
@@ -430,6 +476,9 @@ def main():
     import torch
     import workloads as w
 
+    if args.config_only == "frameworks":
+        print(json.dumps({"frameworks": frameworks()}), flush=True)
+        return
     if args.config_only == "faces":
         print(json.dumps({"faces": face_schemes()}), flush=True)
         return
@@ -505,6 +554,7 @@ def main():
         out["other_configs"] = other_configs()
         out["faces"] = face_schemes(200)
         out["appendix_a"] = preprocessing()
+        out["frameworks"] = frameworks()
     if args.calibration_copy:
         src = torch.ones(32 << 20, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)
