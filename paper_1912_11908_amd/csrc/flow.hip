@@ -850,7 +850,7 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
     // 1b. inline IB fill (tiles whose stencils reach the IB region): the IB
     //     nodes among the loaded cells (the tile's list, built after
     //     classification) take their filled values, computed from the stage
-    //     input in two sweeps, one node per thread: FORCING nodes from FLUID
+    //     input in two sweeps, one node per lane group: FORCING nodes from FLUID
     //     cells, then ghost nodes G1-G3 from FLUID cells and the filled
     //     values of their FORCING corners.  A node inside the tile also
     //     stores its value as its stage output.
