@@ -199,7 +199,8 @@ def test_nonfinite_status_reported():
     assert s.status() == -4
 
 
-@pytest.mark.parametrize("kind", ["cylinder", "wedge", "naca", "tube-moving", "supersonic-moving", "cylinder-tvd"])
+@pytest.mark.parametrize("kind", ["cylinder", "wedge", "naca", "tube-moving", "supersonic-moving", "cylinder-tvd",
+                                  "star-sdsn", "tube-moving-sdsn"])
 def test_mixed_precision_error(kind):
     """Mixed mode (FP32 reconstruction and fluxes on perturbation variables,
     FP64 update) stays within a stated distance of the FP64 oracle."""
@@ -216,7 +217,7 @@ def test_mixed_precision_error(kind):
     assert errs.max() < 1e-4, errs
 
 
-@pytest.mark.parametrize("kind", ["wedge", "naca", "tube-static"])
+@pytest.mark.parametrize("kind", ["wedge", "naca", "tube-static", "naca-sdsn", "star-sdsn"])
 def test_graph_replay_matches_eager(kind):
     """Whole-step HIP graph replay (one-step and multi-step graphs) gives
     bit-identical states to eager launches, replay after replay, with eager

@@ -22,6 +22,7 @@ MIX = [
     ("tube-static", "mixed", lambda: w.small_case("tube", 30, steps=2, nz=10, ntheta=48, nzt=5,
                                                   moving=False)),
     ("tube-moving", "mixed", lambda: w.small_case("tube", 32, steps=3, nz=8, ntheta=64, nzt=4)),
+    ("star-sdsn", "mixed", lambda: w.small_case("star", 64, steps=3, ib_framework="sdsn")),
 ]
 
 
