@@ -1387,8 +1387,10 @@ double orc_weno5(double a, double b, double c, double d, double e)
  * the Weiss-Smith preconditioned one
  *   eps = min(1, max(|u_L|^2/2 + |u_R|^2/2, U_c^2) / a_half^2),
  *   a~  = (1/2) sqrt((1 - eps)^2 Ubar^2 + 4 eps a_half^2),
- * and the velocity-diffusion part of the split pressure, p_bar (D+ + D- - 1),
- * scaled by (a~ / a_half)^2 so that it follows a~ rather than a at low Mach.
+ * and the split pressure taken on the unpreconditioned interface Mach numbers
+ * U / a_half, with its velocity-diffusion part p_bar (D+ + D- - 1) scaled by
+ * a~ / a_half, so that the pressure dissipation is of the order of the
+ * dynamic pressure, rho U_r U, at low Mach.
  * With eps = 1 (or outside dual time) this is exactly LDFSS(0).
  * w = (rho, u, v[, w], p); nrm = unit normal; flux per unit area. */
 static double sgn1(double m) { return m >= 0.0 ? 1.0 : -1.0; }
