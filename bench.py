@@ -1,36 +1,41 @@
 """Throughput benchmark of the immersed-boundary residual + update step.
 
-Workload: the supersonic wedge -- 15 degree half-angle triangle of length 1,
-M = 2, Re = 1e4, 1024 x 512 rectilinear grid (x uniform on [-1, 3], y tanh
-clustered toward the wedge axis with adjacent-width ratio 1.02), SSP-RK3 with
-the compressible (IDW + image point) immersed-boundary family, free-stream
-start.  A step is one RK3 step: three stages, each one launch of the fused
-residual + update over every cell, whose tiles near the body also fill the
-IB nodes they read, so one step is 3 * 1024 * 512 cell-updates.
+Headline workload: the oscillating tube -- an open cylinder of radius 0.5 and
+span 4 (65,536 triangles) translating transversely as y(t) = 0.2 cos(2 pi 0.2
+t), M = 0.2, Re = 185, on a 384 x 256 x 64 grid (h = 1/16, periodic span),
+SSP-RK3 with the compressible (IDW + image point) immersed-boundary family,
+free-stream start.  A step re-poses the body, reclassifies every cell by ray
+parity, rebuilds the IB lists and reconstruction records, and runs three
+stages, each one launch of the fused residual + update over every cell whose
+tiles near the body also fill the IB nodes they read: 3 * 384 * 256 * 64
+cell-updates per step.  ``value`` is the mixed path's whole-job
+cell-updates/s (FP32 reconstruction and fluxes on perturbation variables,
+FP64 update) with the state resident in HBM; the FP64 path is timed the same
+way.  Every stage launch of the timed region records HIP events at its
+start and end on its own stream (the library's stage timer), which gives
+the roofline entry of that kernel.
 
-The serving workload runs after it: the seeded stream of 2000 independent
-2D solves (grid side 64-512, cylinder / wedge / NACA 00tt, M 0.01-2, Re
-40-1000, dual time below M 0.1, mixed precision, 1500 residual evaluations
-each) arriving as a Poisson process of 50 per second, served by the
-continuous-batching server; it reports the p50 / p99 latency from arrival
-to completion and the sustained cell-updates/s.
+Unless --no-other-configs: the cylinder (C1), the supersonic wedge (C2) and
+the low-Mach airfoil (C3), each with its throughput, its own stage-kernel
+roofline, its surface forces and (C2, C3) its mixed-vs-FP64 error; the wedge
+with WENO5 and with TVD-2 faces; the appendix A preprocessing of the
+1200-triangle sphere in both IB frameworks; the wedge in both IB frameworks.
 
-Both precision modes are timed (mixed = FP32 reconstruction and fluxes on
-perturbation variables with FP64 update; fp64); ``value`` is the mixed
-path's whole-job cell-updates/s with the state resident in HBM.  The fused
-stage kernel is timed separately with HIP events on the launch stream for
-the roofline entry; the CPU oracle is timed on a bounded sample of the same
-workload for the cpu_baseline entry.
+Then the serving workload: the seeded stream of 2000 independent 2D solves
+(grid side 64-512, cylinder / wedge / NACA 00tt, M 0.01-2, Re 40-1000, dual
+time below M 0.1, 1500 residual evaluations each) arriving as a Poisson
+process of 50 per second, served by the continuous-batching server in mixed
+precision and in FP64 (p50 / p99 latency from arrival to completion), and
+once with every request arriving at once (the server's capacity).
 
-Unless --no-other-configs: the cylinder, airfoil and tube workloads (with
-their surface forces and mixed-vs-FP64 errors), the wedge with WENO5 and
-with TVD-2 faces, the appendix A preprocessing of the 1200-triangle
-sphere in both IB frameworks, and the wedge in both IB frameworks.
+The CPU oracle is timed on bounded samples of the headline workload on all
+host cores and on one core (cpu_baseline).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--serving-requests N] [--serving-rate R]
+                       [--serving-requests N] [--serving-rate R] [--no-other-configs]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -48,54 +53,100 @@ FP64_PEAK_TFLOPS = 78.6
 # 157.3 TFLOP/s, is twice that.
 FP32_PEAK_TFLOPS = 78.6
 
-# Algorithmic work per cell-update of the fused stage kernel (2D, SSP-RK3),
-# counted from the formulas (each +, -, *, /, sqrt one flop):
-#   WENO5 reconstruction 68 flops, 8 per face (4 variables x 2 sides);
-#   LDFSS flux 118; central viscous flux 55  -> 717 per face, 2 faces/cell;
-#   flux differences 31, primitive recovery 11, RK3 update 20.
-FLOPS_PER_CELL_2D_RK3 = 2 * (8 * 68 + 118 + 55) + 31 + 11 + 20
-# HBM bytes per cell-update (algorithmic): stage input state 4 x 8 B read,
-# stage output 4 x 8 B written, class byte; stages 2 and 3 also read Q^n.
-BYTES_PER_CELL_STAGE = {1: 32 + 32 + 1, 2: 32 + 32 + 32 + 1, 3: 32 + 32 + 32 + 1}
+# Algorithmic work per cell-update of the fused stage kernel, counted from
+# the formulas (each +, -, *, /, sqrt one flop; the derivation is listed
+# with the kernels' rooflines in the design notes):
+#   2D face: WENO5 68 flops x 8 reconstructions (4 variables x 2 sides),
+#     LDFSS 118, central viscous flux 55 -> 717; 2 faces per cell;
+#     per cell flux differences 31, primitive recovery 11, and the update:
+#     SSP-RK3 20, or the dual-time point-implicit pseudo step 246 (local
+#     pseudo step, the preconditioned and Jacobian matrices, the 4 x 4
+#     system and its pivoted elimination);
+#   3D face: WENO5 68 x 10, LDFSS 130, viscous 104 -> 914; 3 faces per cell;
+#     per cell flux differences 42, recovery 17, SSP-RK3 update 25.
+FLOPS_PER_CELL = {(2, "rk3"): 2 * (8 * 68 + 118 + 55) + 31 + 11 + 20,
+                  (2, "dual"): 2 * (8 * 68 + 118 + 55) + 31 + 11 + 246,
+                  (3, "rk3"): 3 * (10 * 68 + 130 + 104) + 42 + 17 + 25}
+# HBM bytes per cell-update (algorithmic): stage input state read and output
+# written (nv doubles each), the class byte; RK3 stages 2 and 3 also read
+# Q^n (averaged over the three stages); a pseudo-iteration also reads the
+# two history states.
+BYTES_PER_CELL = {(2, "rk3"): (65 + 97 + 97) / 3.0, (2, "dual"): 129.0, (3, "rk3"): (81 + 121 + 121) / 3.0}
 
-
-COUNTERS = os.path.join(ROOT, "profiles", "step_batch_kernel_wedge_1024x512_hbm_counters.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1912_11908_amd", "csrc", "flow.hip")
+COUNTERS = {
+    "C4": os.path.join(ROOT, "profiles", "step_ghost_kernel_3f_tube_384x256x64_hbm_counters.md"),
+    "C2": os.path.join(ROOT, "profiles", "step_batch_kernel_wedge_1024x512_hbm_counters.md"),
+}
+KERNEL_NAME = {
+    (3, "rk3", "mixed"): "step_ghost_kernel_3f<RK3> (stage launch with inline IB fill)",
+    (3, "rk3", "fp64"): "step_ghost_kernel<3, double, RK3> (stage launch with inline IB fill)",
+    (2, "rk3", "mixed"): "step_batch_kernel_2f<RK3, true> (stage launch with inline IB fill)",
+    (2, "rk3", "fp64"): "step_batch_kernel<2, double, RK3, true> (stage launch with inline IB fill)",
+    (2, "dual", "mixed"): "step_batch_kernel_2f<DUAL, true> (pseudo-iteration with inline IB fill)",
+    (2, "dual", "fp64"): "step_batch_kernel<2, double, DUAL, true> (pseudo-iteration with inline IB fill)",
+}
 
 
-def measured_traffic():
-    """HBM bytes per launch of the timed kernel from the committed counter
-    summary, or None when the kernel source has changed since the counters
-    were taken (the summary records the source's SHA-256)."""
-    import hashlib
+def measured_traffic(key):
+    """HBM bytes per launch of the stage kernel of workload `key` from the
+    committed counter summary, or None when there is none or the kernel
+    source has changed since the counters were taken (the summary records
+    the source's SHA-256)."""
+    path = COUNTERS.get(key)
     try:
-        text = open(COUNTERS).read()
+        text = open(path).read()
         sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    except OSError:
+    except (OSError, TypeError):
         return None
     fields = dict(line.split(": ", 1) for line in text.splitlines()
                   if line.startswith(("traffic_bytes_per_launch: ", "kernel_source_sha256: ")))
-    if fields.get("kernel_source_sha256", "").strip() != sha:
+    if fields.get("kernel_source_sha256", "").strip() != sha or "traffic_bytes_per_launch" not in fields:
         return None
     return int(fields["traffic_bytes_per_launch"])
+
+
+def roofline(case, precision, avg_ms, key=None):
+    """Roofline entry of the stage kernel of `case` from its average launch
+    duration: algorithmic flops and bytes per cell-update times the cells of
+    one launch, over that duration, against the binding peak."""
+    kind = (case.ndim, case.scheme)
+    flops, nbytes = FLOPS_PER_CELL[kind], BYTES_PER_CELL[kind]
+    ncell = case.ncells
+    achieved_gbs = nbytes * ncell / (avg_ms * 1e-3) / 1e9
+    achieved_tf = flops * ncell / (avg_ms * 1e-3) / 1e12
+    fpeak = FP32_PEAK_TFLOPS if precision == "mixed" else FP64_PEAK_TFLOPS
+    alu = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": fpeak, "unit": "TFLOP/s",
+           "frac": round(achieved_tf / fpeak, 4)}
+    hbm = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved_gbs / HBM_PEAK_GBS, 4)}
+    alu_bound = flops / (fpeak * 1e12) >= nbytes / (HBM_PEAK_GBS * 1e9)
+    roof, other = (alu, hbm) if alu_bound else (hbm, alu)
+    roof["traffic"] = measured_traffic(key) if (key and precision == "mixed") else None
+    roof["kernel"] = KERNEL_NAME.get((case.ndim, case.scheme, precision))
+    roof["kernel_avg_ms"] = round(avg_ms, 5)
+    roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+    roof["per_unit"] = {"flops_per_cell_update": flops, "bytes_per_cell_update": round(nbytes, 2),
+                        "cells_per_launch": ncell}
+    return roof, other
 
 
 def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--precisions", default="mixed,fp64")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-rate", type=float, default=50.0)
+    ap.add_argument("--no-serving-fp64", action="store_true", help="serve the stream in mixed precision only")
+    ap.add_argument("--no-saturation", action="store_true", help="skip the all-at-once serving run")
     ap.add_argument("--no-other-configs", action="store_true",
-                    help="skip the cylinder, airfoil and tube workloads")
-    ap.add_argument("--config-only", choices=("cylinder", "airfoil", "tube", "supersonic", "shock", "preprocessing",
-                                              "faces", "frameworks"),
-                    help="time only that one of the other workloads and print its line (for profiling); "
+                    help="skip the cylinder, wedge and airfoil workloads and the side studies")
+    ap.add_argument("--config-only", choices=("cylinder", "wedge", "airfoil", "tube", "supersonic", "shock",
+                                              "preprocessing", "faces", "frameworks"),
+                    help="time only that one workload and print its line (for profiling); "
                          "supersonic: the moving / stationary cylinder pair of section 8.2.3; "
                          "shock: the shock-driven free cylinder of section 8.2.6; "
                          "preprocessing: the sphere-in-a-cube timing of appendix A; "
@@ -108,78 +159,136 @@ def _parse():
     return ap.parse_args()
 
 
-def serving(n, rate):
+def serving(n, rate, precision="mixed"):
     """The seeded serving stream through the continuous-batching server."""
     import workloads as w
     from workloads.serving import request_stream
     from paper_1912_11908_amd.serving import Server, GpuBackend
     reqs = request_stream(n=n, rate=rate, steps=500)
     init = lambda c: w.freestream_prim(c.ndim, c.ni, c.nj, c.nk, c.p_inf)  # noqa: E731
-    backend = GpuBackend("mixed", init=init)
+    backend = GpuBackend(precision, init=init)
     st = Server(backend, mem_budget=64 << 30, max_active=128, tick_evals=30).run(reqs)
     out = st.summary()
     out.update({"workload": f"{n} seeded 2D solves, Poisson arrivals at {rate:g}/s, grid side "
-                            "64-512, 1500 residual evaluations each, mixed precision",
-                "precision": "mixed", "arrival_span_s": reqs[-1][0] if reqs else 0.0})
+                            f"64-512, 1500 residual evaluations each, {precision} precision",
+                "precision": precision, "arrival_span_s": reqs[-1][0] if reqs else 0.0})
     return out
 
 
-def other_configs(only=None):
-    """Throughput of the other fixed workloads (whole steps, free-stream
-    start, states resident in HBM): the cylinder for its full 200 steps in
-    FP64, prefixes of the airfoil (dual time, 20 pseudo-iterations per
-    physical step) and of the oscillating tube (moving body, reclassified
-    every step) in both precisions."""
+def _warm_graphs(s, case):
+    """Build both whole-step graphs of a stationary solve (a chunk and a
+    single step) before any timed call uses them."""
+    if case.scheme == "rk3":
+        s.advance(8)
+        s.advance(1)
+    else:
+        s.advance(1)   # the first physical step runs eagerly (BDF1)
+        s.advance(2)
+        s.advance(1)
+
+
+def run_case(case, precision, steps, warmup, timed_stages=True):
+    """Whole steps of one workload from a free-stream start, state resident
+    in HBM.  Moving bodies: `warmup` untimed steps, then `steps` timed ones
+    with the stage timer on (HIP events at the start and end of every stage
+    launch, on its stream).  Stationary bodies: the graphs of whole steps
+    are built and `warmup` steps run untimed, `steps` timed steps replay the
+    graphs, then 2 eager steps with the stage timer time the stage kernel."""
     import torch
     import workloads as w
     import paper_1912_11908_amd as P
+    prim = w.freestream_prim(case.ndim, case.ni, case.nj, case.nk, case.p_inf, velocity=case.u_inf)
+    s = P.Solver(case, precision, "cuda:0")
+    s.init_prim(prim)
+    s.classify()
+    moving = bool(case.motion)
+    if not moving:
+        _warm_graphs(s, case)
+    s.advance(warmup)
+    torch.cuda.synchronize()
+    s.check_status()
+    per = case.evals_per_step
+    if moving and timed_stages:
+        s.set_stage_timing(steps * per)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    s.advance(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    s.check_status()
+    stages = None
+    if timed_stages:
+        if not moving:
+            k = 2
+            s.set_stage_timing(k * per)
+            s.advance(k)
+        tot, n, lo, hi = s.stage_timing()
+        s.set_stage_timing(0)
+        stages = {"avg_ms": tot / n, "launches": n, "min_ms": lo, "max_ms": hi,
+                  "where": "timed region" if moving else "2 eager steps after the timed region"}
+    torch.cuda.synchronize()
+    done = {"cell_updates_per_s": case.ncells * per * steps / wall, "ms_per_step": wall * 1e3 / steps,
+            "event_ms_per_step": ev_ms / steps, "steps": steps, "warmup": warmup}
+    return s, done, stages
+
+
+def surface_forces(s, lref, nrep=20):
+    """Force coefficients of the final state (eq.9) and the device time of
+    one evaluation (fill excluded)."""
+    import torch
+    t_end = s.info().time
+    s.set_time(t_end)
+    s.classify()
+    s.fill(t_end)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(nrep):
+        F = s.forces()
+    torch.cuda.synchronize()
+    tf = (time.perf_counter() - t0) / nrep
+    F = F.cpu().numpy()
+    return {"C_x": float(2.0 * F[0] / lref), "C_y": float(2.0 * F[1] / lref), "ms_per_evaluation": tf * 1e3}
+
+
+OTHER = [
+    # key, label, case maker, precisions, timed steps, reference length or area
+    ("cylinder", "C1", "cylinder 128x128, M=0.3, Re=40, RK3, 200 steps", "case_c1", ("fp64",), 200, 1.0),
+    ("wedge", "C2", "supersonic wedge 1024x512, M=2, Re=1e4, RK3", "case_c2", ("mixed", "fp64"), 500, 1.0),
+    ("airfoil", "C3", "NACA0012 2048x1024, M=0.001, Re=1000, dual time, 10 physical steps", "case_c3",
+     ("mixed", "fp64"), 10, 1.0),
+    ("tube", "C4", "oscillating tube 384x256x64, M=0.2, Re=185, RK3, moving", "case_c4", ("mixed", "fp64"), 50, 4.0),
+]
+
+
+def other_configs(only=None, exclude=("tube",)):
+    """Throughput and stage-kernel roofline of the other fixed workloads."""
+    import torch
+    import workloads as w
     out = {}
-    # reference length (2D, per unit span) or area for the force coefficients
-    plan = [("cylinder", "cylinder 128x128, M=0.3, Re=40, RK3, 200 steps", w.case_c1, ("fp64",), 200, 1.0),
-            ("airfoil", "NACA0012 2048x1024, M=0.001, Re=1000, dual time, 10 physical steps", w.case_c3,
-             ("mixed", "fp64"), 10, 1.0),
-            ("tube", "oscillating tube 384x256x64, M=0.2, Re=185, RK3, moving, 50 steps", w.case_c4,
-             ("mixed", "fp64"), 50, 4.0)]
-    plan = [(name, make(), precs, steps, lref) for key, name, make, precs, steps, lref in plan
-            if only in (None, key)]
-    for name, case, precs, steps, lref in plan:
+    for key, tag, label, maker, precs, steps, lref in OTHER:
+        if (only is None and key in exclude) or (only is not None and key != only):
+            continue
+        case = getattr(w, maker)()
         prims = {}
         for prec in precs:
-            prim = w.freestream_prim(case.ndim, case.ni, case.nj, case.nk, case.p_inf)
-            s = P.Solver(case, prec, "cuda:0")
-            s.init_prim(prim)
-            s.advance(1)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            s.advance(steps)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            s.check_status()
-            out[f"{name} [{prec}]"] = {
-                "cell_updates_per_s": case.ncells * case.evals_per_step * steps / dt,
-                "ms_per_step": dt * 1e3 / steps}
+            s, done, stages = run_case(case, prec, steps, 3)
+            roof, _ = roofline(case, prec, stages["avg_ms"], tag)
+            done["stage_kernel"] = stages
+            done["roofline"] = roof
             prims[prec] = s.to_prim()
-            # surface force of the final state (eq.9): coefficients and the
-            # device time of one evaluation (fill excluded)
-            t_end = s.info().time
-            s.set_time(t_end)
-            s.classify()
-            s.fill(t_end)
-            nrep = 20
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(nrep):
-                F = s.forces()
-            torch.cuda.synchronize()
-            tf = (time.perf_counter() - t0) / nrep
-            F = F.cpu().numpy()
-            out[f"{name} [{prec}]"]["forces"] = {
-                "C_x": float(2.0 * F[0] / lref), "C_y": float(2.0 * F[1] / lref),
-                "facets": int(case.facet.shape[0]), "ms_per_evaluation": tf * 1e3}
+            done["forces"] = surface_forces(s, lref)
+            done["forces"]["facets"] = int(case.facet.shape[0])
+            out[f"{tag} {label} [{prec}]"] = done
             del s
+            torch.cuda.synchronize()
         if "mixed" in prims and "fp64" in prims:
-            out[f"{name} [mixed]"]["mixed_vs_fp64_rel_l2"] = mixed_error(prims["mixed"], prims["fp64"],
-                                                                        case.ndim, case.p_inf)
+            out[f"{tag} {label} [mixed]"]["mixed_vs_fp64_rel_l2"] = mixed_error(prims["mixed"], prims["fp64"],
+                                                                              case.ndim, case.p_inf)
         del prims
     return out
 
@@ -418,56 +527,56 @@ def shock_driven(t_end=2.0):
     return out
 
 
-def run_gpu(case, prim, precision, steps, warmup, reps):
-    import torch
-    import paper_1912_11908_amd as P
-    s = P.Solver(case, precision, "cuda:0")
-    s.init_prim(prim)
-    s.classify()
-    s.advance(warmup)
-    torch.cuda.synchronize()
-    s.check_status()
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    s.advance(steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ev_ms = e0.elapsed_time(e1)
-    s.check_status()
-    # fused stage kernel, timed with HIP events around repeated launches
-    stage_ms = {st: s.time_update_kernel(st, reps) for st in (1, 2, 3)}
-    torch.cuda.synchronize()
-    prim_out = s.to_prim().cpu().numpy()
-    return dict(wall=wall, event_ms=ev_ms, stage_ms=stage_ms, prim=prim_out,
-                counts=s.counts().tolist())
+def cpu_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "host_cpus": os.cpu_count()}
 
 
-def cpu_baseline(case, prim, seconds):
-    """The oracle as it stands, on this host's cores, over whole RK3 steps of
-    the same workload until about `seconds` of wall time have passed."""
+def cpu_baseline(case):
+    """The oracle as it stands on this host's cores, on bounded samples of
+    the headline workload: two whole RK3 steps of the full grid on all
+    threads (each re-poses and reclassifies the body, as the GPU step does),
+    and one fill + residual evaluation of the full grid on one thread
+    (classification and update excluded; one evaluation is one cell-update
+    per cell)."""
     import numpy as np
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    import workloads as w
+    prim = w.freestream_prim(case.ndim, case.ni, case.nj, case.nk, case.p_inf)
+    threads = oracle.threads()
     o = oracle.Oracle(case)
-    o.classify()
     q = o.prim_to_state(prim)
+    steps = 2
     t0 = time.perf_counter()
-    steps = 0
-    while True:
-        o.run(q, 1)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds or steps >= 200:
-            break
-    cu = steps * 3 * case.ncells
+    o.run(q, steps)
+    el = time.perf_counter() - t0
     assert np.all(np.isfinite(o.interior(q)))
-    return {"value": cu / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} RK3 steps of the full {case.ni}x{case.nj} wedge grid "
-                      f"({cu:.3g} cell-updates, {el:.1f} s wall, OMP_NUM_THREADS={threads})"}
+    cu = steps * case.evals_per_step * case.ncells
+    oracle.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        o.fill(q, o.t)
+        o.bc(q)
+        o.residual(q)
+        el1 = time.perf_counter() - t1
+    finally:
+        oracle.set_threads(threads)
+    out = {"value": cu / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"{steps} RK3 steps of the full {case.ni}x{case.nj}x{case.nk} oscillating tube, "
+                     f"each reclassifying the body ({cu:.3g} cell-updates, {el:.1f} s wall, {threads} threads)",
+           "one_core": {"value": case.ncells / el1, "unit": "cell-updates/s", "cores": 1,
+                        "sample": f"one IB fill + residual evaluation of the full grid ({case.ncells} "
+                                  f"cell-updates, {el1:.1f} s wall; classification and update excluded)"}}
+    out.update(cpu_info())
+    out.update(oracle.compiler())
+    return out
 
 
 def main():
@@ -498,62 +607,40 @@ def main():
     if args.config_only:
         print(json.dumps({"other_configs": other_configs(args.config_only)}), flush=True)
         return
-    case = w.case_c2(steps=args.steps)
-    prim = w.freestream_prim(2, case.ni, case.nj, 1, case.p_inf)
+
+    case = w.case_c4(steps=args.steps)
     ncell = case.ncells
-    res = {}
+    res, prims = {}, {}
     for prec in [p for p in args.precisions.split(",") if p]:
-        res[prec] = run_gpu(case, prim, prec, args.steps, args.warmup, args.kernel_reps)
+        s, done, stages = run_case(case, prec, args.steps, args.warmup)
+        roof, other = roofline(case, prec, stages["avg_ms"], "C4")
+        done["stage_kernel"] = stages
+        res[prec] = (done, roof, other)
+        prims[prec] = s.to_prim()
+        done["forces"] = surface_forces(s, 4.0)
+        done["forces"]["facets"] = int(case.facet.shape[0])
+        del s
+        torch.cuda.synchronize()
     head = "mixed" if "mixed" in res else "fp64"
-    r = res[head]
-    cell_updates = args.steps * 3 * ncell
-    value = cell_updates / r["wall"]
-
-    # roofline of the fused stage kernel (average over the three stages)
-    avg_ms = sum(r["stage_ms"].values()) / 3.0
-    bytes_cell = sum(BYTES_PER_CELL_STAGE.values()) / 3.0
-    achieved_gbs = bytes_cell * ncell / (avg_ms * 1e-3) / 1e9
-    achieved_tf = FLOPS_PER_CELL_2D_RK3 * ncell / (avg_ms * 1e-3) / 1e12
-    fpeak = FP32_PEAK_TFLOPS if head == "mixed" else FP64_PEAK_TFLOPS
-    t_alu = FLOPS_PER_CELL_2D_RK3 / (fpeak * 1e12)
-    t_hbm = bytes_cell / (HBM_PEAK_GBS * 1e9)
-    if t_alu >= t_hbm:
-        roof = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": fpeak,
-                "unit": "TFLOP/s", "frac": round(achieved_tf / fpeak, 4)}
-        other = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
-                 "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4)}
-    else:
-        roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4)}
-        other = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": fpeak,
-                 "unit": "TFLOP/s", "frac": round(achieved_tf / fpeak, 4)}
-    # measured HBM bytes per launch (mixed path only: the counters were taken on it)
-    roof["traffic"] = measured_traffic() if head == "mixed" else None
-    roof["kernel"] = "step_batch_kernel_2f<RK3, false>" if head == "mixed" else "step_batch_kernel<2, double, RK3, false>"
-    roof["kernel_avg_ms"] = round(avg_ms, 5)
-    roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
-    roof["per_unit"] = {"flops_per_cell_update": FLOPS_PER_CELL_2D_RK3,
-                        "bytes_per_cell_update": round(bytes_cell, 2), "cells_per_launch": ncell}
-
+    r, roof, other = res[head]
     out = {
-        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": r["wall"] * 1e3 / args.steps,
+        "metric": METRIC, "value": r["cell_updates_per_s"], "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64" if head == "mixed" else "f64",
-        "data": "synthetic",
-        "config": {"workload": "supersonic wedge 1024x512, M=2, Re=1e4, SSP-RK3, IDW/image-point IB",
-                   "cells": ncell, "cell_updates_per_step": 3 * ncell, "precision": head},
+        "dtype": "f32+f64" if head == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": "oscillating tube 384x256x64 (65,536 triangles, y = 0.2 cos(2 pi 0.2 t)), "
+                               "M=0.2, Re=185, SSP-RK3, IDW/image-point IB, reclassified every step",
+                   "cells": ncell, "cell_updates_per_step": case.evals_per_step * ncell, "precision": head},
         "roofline": roof, "roofline_other": other,
+        "stage_kernel": r["stage_kernel"], "forces": r["forces"],
     }
     if "fp64" in res and "mixed" in res:
-        f = res["fp64"]
-        out["fp64"] = {"value": cell_updates / f["wall"], "ms_per_step": f["wall"] * 1e3 / args.steps,
-                       "kernel_avg_ms": round(sum(f["stage_ms"].values()) / 3.0, 5)}
-        out["mixed_speedup_vs_fp64"] = f["wall"] / r["wall"]
-        a, b = res["mixed"]["prim"], f["prim"]
-        errs = [float(np.sqrt(np.sum((a[v] - b[v]) ** 2) / np.sum(b[v] ** 2))) for v in range(4)]
-        out["mixed_vs_fp64_rel_l2"] = {"rho": errs[0], "u": errs[1], "v": errs[2], "p": errs[3]}
+        f, froof, fother = res["fp64"]
+        out["fp64"] = {"value": f["cell_updates_per_s"], "ms_per_step": f["ms_per_step"],
+                       "stage_kernel": f["stage_kernel"], "roofline": froof, "forces": f["forces"]}
+        out["mixed_speedup_vs_fp64"] = f["ms_per_step"] / r["ms_per_step"]
+        out["mixed_vs_fp64_rel_l2"] = mixed_error(prims["mixed"], prims["fp64"], case.ndim, case.p_inf)
+    del prims
     if not args.no_other_configs:
         out["other_configs"] = other_configs()
         out["faces"] = face_schemes(200)
@@ -567,12 +654,19 @@ def main():
         out["calibration_copy_bytes"] = 2 * src.numel() * 8
         del src, dst
     if args.serving_requests > 0:
-        sv = serving(args.serving_requests, args.serving_rate)
+        sv = serving(args.serving_requests, args.serving_rate, "mixed")
         out["latency_p50_s"] = sv["p50_s"]
         out["latency_p99_s"] = sv["p99_s"]
-        out["serving"] = sv
+        out["serving"] = {"mixed": sv}
+        if not args.no_serving_fp64:
+            out["serving"]["fp64"] = serving(args.serving_requests, args.serving_rate, "fp64")
+        if not args.no_saturation:
+            sat = serving(args.serving_requests, 1.0e5, "mixed")
+            sat["note"] = "every request arrives within the first 0.03 s: throughput is the server's capacity"
+            out["serving"]["saturated_mixed"] = sat
+            out["serving_capacity_cell_updates_per_s"] = sat["cell_updates_per_s"]
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case, prim, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w.case_c4())
     print(json.dumps(out), flush=True)
 
 

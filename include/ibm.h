@@ -236,15 +236,35 @@ int ibm_info_get(const ibm_ctx *ctx, ibm_info *out);
  * fit).  Both give bit-identical results; takes effect at the next
  * classification. */
 #define IBM_OPT_CORNER_LISTS 2
+/* IBM_OPT_STAGE_TIMING (default 0): value n > 0 makes the next n stage
+ * launches of ibm_advance (each RK3 stage or dual-time pseudo-iteration of
+ * the fused residual-and-update kernel, section 2) record HIP events at
+ * their start and end, read back by ibm_stage_timing; while it is on, steps
+ * are enqueued eagerly (no graph replay).  0 turns it off.  At most
+ * IBM_STAGE_TIMING_MAX.  Changing it discards unread timings. */
+#define IBM_OPT_STAGE_TIMING 3
+#define IBM_STAGE_TIMING_MAX 100000
 #define IBM_BATCH_MAX 64
 int ibm_set_option(ibm_ctx *ctx, int option, int value);
 const char *ibm_last_error(const ibm_ctx *ctx);
 
+/* Stage timing (section 2's residual and update, one launch per RK3 stage
+ * or pseudo-iteration): synchronises on the last timed launch and returns
+ * the summed device time of the stage launches timed since the option was
+ * set or since the last call (total_ms, host), their number (launches) and,
+ * if not NULL, the shortest and longest (min_ms, max_ms); then starts
+ * counting again.  Zero launches when the option is off. */
+int ibm_stage_timing(ibm_ctx *ctx, float *total_ms, int *launches, float *min_ms, float *max_ms);
+
 /* Average device time in milliseconds of one launch of the fused
- * residual-and-update kernel of the given RK3 stage (1..3) or of one dual-time
- * pseudo-iteration (stage 0), measured with HIP events around nrep launches
- * on stream.  The state d_q is used as input and scratch stage buffers as
- * output (d_q is not modified).  Synchronises. */
+ * residual-and-update kernel (section 2) of the given RK3 stage (1..3) or of
+ * one dual-time pseudo-iteration (stage 0, BDF2 coefficients), measured with
+ * HIP events around nrep launches on stream.  It is the kernel a step
+ * launches, on the same tiles: with a body, the tile list whose near tiles
+ * fill the IB nodes they read (body at the context time).  d_q is the input;
+ * the output goes to the context's scratch stage buffer, so neither d_q nor
+ * the solve's dual-time history changes.  Dual time needs one advanced step
+ * first (IBM_EINVAL otherwise).  Synchronises. */
 int ibm_time_update_kernel(ibm_ctx *ctx, const double *d_q, int stage, int nrep, void *stream,
                            float *avg_ms);
 

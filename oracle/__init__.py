@@ -23,10 +23,13 @@ FLUID, FORCING, G1, G2, G3, SOLID = range(6)
 IREC, DREC = 24, 32
 
 
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-D_GNU_SOURCE",
+          "-fPIC", "-shared", "-Wall", "-Wno-unused-function"]
+
+
 def build(openmp=True):
     """Compile oracle.c (gcc, -O2, no FP contraction, no fast-math)."""
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-D_GNU_SOURCE",
-           "-fPIC", "-shared", "-Wall", "-Wno-unused-function"]
+    cmd = ["gcc"] + CFLAGS
     if openmp:
         cmd.append("-fopenmp")
     cmd += ["-o", _SO + ".tmp", os.path.join(_HERE, "oracle.c"), "-lm"]
@@ -72,12 +75,33 @@ def lib():
         L.orc_tvd2.argtypes = [d] * 3
         L.orc_tvd2.restype = d
         L.orc_ldfss.argtypes = [i, P, P, P, d, i, d, P]
+        L.orc_set_threads.argtypes = [i]
+        L.orc_set_threads.restype = None
+        L.orc_get_threads.restype = i
         _lib = L
     return _lib
 
 
 def _p(a):
     return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle's cell loops (timing only)."""
+    lib().orc_set_threads(int(n))
+
+
+def threads():
+    return int(lib().orc_get_threads())
+
+
+def compiler():
+    """gcc version line and the flags the oracle is built with."""
+    try:
+        ver = subprocess.run(["gcc", "--version"], capture_output=True, text=True).stdout.splitlines()[0]
+    except (OSError, IndexError):
+        ver = "gcc (version unavailable)"
+    return {"compiler": ver, "flags": " ".join(CFLAGS + ["-fopenmp"])}
 
 
 def weno5(a, b, c, d, e):

@@ -16,6 +16,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define LAT_SCALE 16777216.0 /* 2^24: the integer lattice for exact predicates */
 #define WENO_EPS 1.0e-6
@@ -1959,6 +1962,27 @@ int orc_forces(orc *o, const double *q, double *F, double *facet_out)
         }
     }
     return missed;
+}
+
+/* ------------------------------------------------------------ threading */
+/* Threads of the OpenMP loops (1 without OpenMP); results do not depend on it. */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int orc_get_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* -------------------------------------------------------------- accessors */

@@ -78,6 +78,10 @@ void orc_get_records(orc *o, int which, int32_t *ifeat, double *dfeat);
 void orc_get_stats(orc *o, int64_t *stats);
 double orc_get_param(orc *o, int which);
 
+/* OpenMP threads of the cell loops (timing only; results do not depend on it) */
+void orc_set_threads(int n);
+int orc_get_threads(void);
+
 /* pins */
 double orc_weno5(double a, double b, double c, double d, double e);
 /* second-order TVD face state (MUSCL, minmod) seen from b, between b and c */

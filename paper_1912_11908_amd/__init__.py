@@ -219,6 +219,20 @@ class Solver:
                    "ibm_read_counts", self.h)
         return out
 
+    def set_stage_timing(self, launches):
+        """Time the next `launches` stage launches of advance() with HIP
+        events (0: off; steps then replay as graphs again)."""
+        _lib.check(self.L.ibm_set_option(self.h, 3, int(launches)), "ibm_set_option", self.h)
+
+    def stage_timing(self):
+        """(total_ms, launches, min_ms, max_ms) of the stage launches timed
+        since the last call; synchronises."""
+        tot, mn, mx = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
+        n = ctypes.c_int()
+        _lib.check(self.L.ibm_stage_timing(self.h, ctypes.byref(tot), ctypes.byref(n), ctypes.byref(mn),
+                                           ctypes.byref(mx)), "ibm_stage_timing", self.h)
+        return tot.value, n.value, mn.value, mx.value
+
     def time_update_kernel(self, stage, nrep, q=None):
         q = self.state if q is None else q
         ms = ctypes.c_float(0.0)

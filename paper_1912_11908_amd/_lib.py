@@ -19,7 +19,7 @@ REC_INT, REC_DBL = 24, 32
 EXPORTS = ["ibm_workspace_bytes", "ibm_create", "ibm_destroy", "ibm_set_time", "ibm_classify",
            "ibm_fill", "ibm_residual", "ibm_forces", "ibm_body_state", "ibm_advance", "ibm_init_state", "ibm_state_to_prim",
            "ibm_status", "ibm_read_counts", "ibm_info_get", "ibm_last_error",
-           "ibm_time_update_kernel", "ibm_set_option", "ibm_batch_advance"]
+           "ibm_time_update_kernel", "ibm_set_option", "ibm_batch_advance", "ibm_stage_timing"]
 
 BATCH_MAX = 64
 
@@ -92,6 +92,8 @@ def load():
     L.ibm_time_update_kernel.argtypes = [P, P, I, I, P, ctypes.POINTER(ctypes.c_float)]
     L.ibm_set_option.argtypes = [P, I, I]
     L.ibm_batch_advance.argtypes = [P, P, I, I, P]
+    F = ctypes.POINTER(ctypes.c_float)
+    L.ibm_stage_timing.argtypes = [P, F, ctypes.POINTER(I), F, F]
     for name in EXPORTS:
         if name not in ("ibm_destroy", "ibm_last_error"):
             getattr(L, name).restype = ctypes.c_int

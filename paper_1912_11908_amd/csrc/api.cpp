@@ -53,6 +53,11 @@ struct ibm_ctx {
     const double *batch_q;
     std::vector<char> h_args;
     long long rest_box_lat[6];
+    // stage timing (IBM_OPT_STAGE_TIMING): event pairs recorded at the start
+    // and end of each stage launch, tev_used of tev_cap taken since the last
+    // ibm_stage_timing
+    std::vector<hipEvent_t> tev;
+    int tev_used;
     char err[256];
 };
 
@@ -1010,6 +1015,7 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
         x->slot_nblk[k] = 0;
     x->tiles = L.tiles;
     x->ntiles = (int)list.size();
+    x->tev_used = 0;
     if (e != hipSuccess) {
         delete x;
         return IBM_EDEVICE;
@@ -1031,11 +1037,20 @@ static void drop_graph(ibm_ctx *c)
     }
 }
 
+static void drop_timing(ibm_ctx *c)
+{
+    for (hipEvent_t e : c->tev)
+        (void)hipEventDestroy(e);
+    c->tev.clear();
+    c->tev_used = 0;
+}
+
 void ibm_destroy(ibm_ctx *c)
 {
     if (!c)
         return;
     drop_graph(c);
+    drop_timing(c);
     if (c->cap_stream)
         (void)hipStreamDestroy(c->cap_stream);
     delete c;
@@ -1053,6 +1068,21 @@ int ibm_set_option(ibm_ctx *c, int option, int value)
     if (option == IBM_OPT_CORNER_LISTS) {
         c->corner_lists = value != 0;
         c->classified = false;  // the lists are rebuilt by the next classification
+        return IBM_OK;
+    }
+    if (option == IBM_OPT_STAGE_TIMING) {
+        if (value < 0 || value > IBM_STAGE_TIMING_MAX)
+            return set_err(c, IBM_EINVAL, "stage timing: 0 to IBM_STAGE_TIMING_MAX launches");
+        drop_timing(c);
+        for (int k = 0; k < 2 * value; ++k) {
+            hipEvent_t e = nullptr;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) {
+                drop_timing(c);
+                return dev_err(c, r, "stage timing events");
+            }
+            c->tev.push_back(e);
+        }
         return IBM_OK;
     }
     return IBM_EINVAL;
@@ -1130,6 +1160,18 @@ int ibm_residual(ibm_ctx *c, const double *q, double *r, void *stream)
 
 namespace {
 
+// Next free event pair of the stage timer (both null when timing is off or
+// the pool is used up).
+void take_timing_pair(ibm_ctx *c, hipEvent_t &e0, hipEvent_t &e1)
+{
+    e0 = e1 = nullptr;
+    if (2 * (c->tev_used + 1) > (int)c->tev.size())
+        return;
+    e0 = c->tev[2 * c->tev_used];
+    e1 = c->tev[2 * c->tev_used + 1];
+    ++c->tev_used;
+}
+
 // One stage is one launch on the stream.  With a body it runs the tile list,
 // whose near tiles fill the IB nodes they read; without one, every tile.
 template <typename Launch> int enqueue_stage(ibm_ctx *c, double t, hipStream_t s, Launch launch)
@@ -1143,6 +1185,7 @@ template <typename Launch> int enqueue_stage(ibm_ctx *c, double t, hipStream_t s
         axis = c->mo.axis;
     }
     StagePart p{c->tiles, c->ntiles, vel, acc, axis};
+    take_timing_pair(c, p.ev_start, p.ev_stop);
     return dev_err(c, launch(s, &p), "stage");
 }
 
@@ -1260,7 +1303,15 @@ int enqueue_group_step(ibm_ctx *const *ctx, double *const *q, const std::vector<
                 args.push_back(static_cast<char *>(ctx[m]->d_args) + (slot + l) * nb);
                 nblk.push_back(ctx[m]->slot_nblk[slot + l]);
             }
-            hipError_t e = launch_stage_batch(nd, prec, scheme, l == 1, (int)args.size(), args.data(), nblk.data(), s);
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            int tot = 0;
+            for (int b : nblk)
+                tot += b > 0 ? b : 0;
+            // the stage timer of a single solve times its stage launches
+            if (gp.size() == 1 && tot > 0)
+                take_timing_pair(ctx[gp[0]], e0, e1);
+            hipError_t e = launch_stage_batch(nd, prec, scheme, l == 1, (int)args.size(), args.data(), nblk.data(), s,
+                                              e0, e1);
             if (e != hipSuccess)
                 return dev_err(ctx[gp[0]], e, "batched stage");
         }
@@ -1412,7 +1463,9 @@ int ibm_advance(ibm_ctx *c, double *q, int nsteps, void *stream)
         // stationary bodies: the shared batched path on prepared arguments
         if (!c->mo.on && c->batch_q != q && (rc = prepare_batch(c, q, s)))
             return rc;
-        bool graphable = c->use_graphs && !c->mo.on && !first;
+        // graph replay, unless the stage timer is on (its events go with
+        // eager launches)
+        bool graphable = c->use_graphs && !c->mo.on && !first && c->tev.empty();
         if (graphable) {
             int slot = nsteps - n >= chunk_steps(c) ? 1 : 0;
             if (c->graph_q[slot] != q && !build_graph(c, q, slot))
@@ -1583,6 +1636,10 @@ int ibm_time_update_kernel(ibm_ctx *c, const double *q, int stage, int nrep, voi
     bool rk = c->f.scheme == IBM_RK3;
     if (rk && (stage < 1 || stage > 3))
         return IBM_EINVAL;
+    // a pseudo-iteration reads the step history Q'^n, Q'^{n-1}, which the
+    // solve's first step sets up; it is only read here
+    if (!rk && c->step == 0)
+        return set_err(c, IBM_EINVAL, "dual time: advance at least one step before timing a pseudo-iteration");
     static const double A[4] = {0.0, 0.0, 0.75, 1.0 / 3.0}, B[4] = {0.0, 1.0, 0.25, 2.0 / 3.0};
     hipEvent_t e0, e1;
     hipError_t e = hipEventCreate(&e0);
@@ -1590,22 +1647,29 @@ int ibm_time_update_kernel(ibm_ctx *c, const double *q, int stage, int nrep, voi
         e = hipEventCreate(&e1);
     if (e != hipSuccess)
         return dev_err(c, e, "event create");
-    // the kernel of the stage launches (batched form), over every tile with
-    // no fill part: d_q is only read
+    // the kernel of the step's stage launches (batched form): with a body,
+    // the tile list whose near tiles fill the IB nodes they read (the body
+    // at the context time), else every tile.  d_q is only read; the output
+    // goes to a scratch stage buffer (the filled FORCING corner values to
+    // their scratch slots)
     size_t nb = stage_args_bytes();
     std::vector<char> h(nb);
     double *qm = const_cast<double *>(q);
-    int nblk = rk ? stage_args(c->g, c->f, c->ib, qm, q, nullptr, c->q1, A[stage], B[stage], nullptr, h.data())
-                  : stage_args(c->g, c->f, c->ib, qm, c->qn, c->qnm1, c->wtmp, 1.0, 0.0, nullptr, h.data());
+    bool body = c->b.nfacet > 0 && c->ib.cap > 0;
+    double disp = 0.0, vel = 0.0, acc = 0.0;
+    if (c->mo.on)
+        motion_kin(c, c->t, disp, vel, acc);
+    StagePart p{c->tiles, c->ntiles, vel, acc, c->mo.on ? c->mo.axis : -1};
+    const StagePart *part = body ? &p : nullptr;
+    int nblk = rk ? stage_args(c->g, c->f, c->ib, qm, q, nullptr, c->q1, A[stage], B[stage], part, h.data())
+                  : stage_args(c->g, c->f, c->ib, qm, c->qn, c->qnm1, c->wtmp, 1.5, 0.5, part, h.data());
     const void *d = static_cast<char *>(c->d_args) + (kSlots - 1) * nb;
     if (e == hipSuccess)
         e = hipMemcpyAsync(const_cast<void *>(d), h.data(), nb, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess && !rk)
-        e = launch_dual_begin(c->g, c->f, q, c->qn, c->qnm1, 1, s);
     if (e == hipSuccess)
         e = hipEventRecord(e0, s);
     for (int r = 0; r < nrep && e == hipSuccess; ++r)
-        e = launch_stage_batch(c->g.ndim, c->f.precision, c->f.scheme, false, 1, &d, &nblk, s);
+        e = launch_stage_batch(c->g.ndim, c->f.precision, c->f.scheme, body, 1, &d, &nblk, s);
     if (e == hipSuccess)
         e = hipEventRecord(e1, s);
     if (e == hipSuccess)
@@ -1617,6 +1681,34 @@ int ibm_time_update_kernel(ibm_ctx *c, const double *q, int stage, int nrep, voi
     (void)hipEventDestroy(e1);
     *avg_ms = ms / nrep;
     return dev_err(c, e, "time kernel");
+}
+
+int ibm_stage_timing(ibm_ctx *c, float *total_ms, int *launches, float *min_ms, float *max_ms)
+{
+    if (!c || !total_ms || !launches)
+        return IBM_EINVAL;
+    *total_ms = 0.0f;
+    *launches = 0;
+    float lo = 0.0f, hi = 0.0f;
+    hipError_t e = hipSuccess;
+    if (c->tev_used > 0)
+        e = hipEventSynchronize(c->tev[2 * c->tev_used - 1]);
+    for (int k = 0; k < c->tev_used && e == hipSuccess; ++k) {
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, c->tev[2 * k], c->tev[2 * k + 1]);
+        if (e != hipSuccess)
+            break;
+        *total_ms += ms;
+        lo = k == 0 ? ms : std::min(lo, ms);
+        hi = k == 0 ? ms : std::max(hi, ms);
+        ++*launches;
+    }
+    c->tev_used = 0;
+    if (min_ms)
+        *min_ms = lo;
+    if (max_ms)
+        *max_ms = hi;
+    return dev_err(c, e, "stage timing");
 }
 
 }  // extern "C"

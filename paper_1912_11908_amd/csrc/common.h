@@ -127,6 +127,9 @@ struct StagePart {
     int ntiles;
     double ub, ab;           // body velocity and acceleration along `axis`
     int axis;                // motion axis, -1 for a stationary body
+    // when set, the launch records these events at its start and end (stage
+    // timing); null otherwise
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
 };
 
 struct Motion {
@@ -186,6 +189,7 @@ size_t stage_args_bytes();
 int stage_args(const Grid &g, const Flow &f, const IB &ib, double *qin, const double *qn,
                const double *qnm1, double *out, double a, double b, const StagePart *part, void *dst);
 hipError_t launch_stage_batch(int ndim, int precision, int scheme, bool ghosts, int n, const void *const *d_args,
-                              const int *nblk, hipStream_t s);
+                              const int *nblk, hipStream_t s, hipEvent_t ev_start = nullptr,
+                              hipEvent_t ev_stop = nullptr);
 
 }  // namespace ibm

@@ -12,6 +12,8 @@
 // recovery of (rho', p', T') from the state are FP64.
 #include <cstring>
 
+#include <hip/hip_ext.h>
+
 #include "common.h"
 
 namespace ibm {
@@ -1548,13 +1550,22 @@ hipError_t run_step(const Grid &g, const Flow &f, const IB &ib, double *qin, con
     StepArgs A = make_args<DIM>(g, f, ib, qin, qn, qnm1, out, a, b, part, &nblk);
     if (nblk == 0)
         return hipSuccess;
+    hipEvent_t e0 = part ? part->ev_start : nullptr, e1 = part ? part->ev_stop : nullptr;
     if constexpr (MODE != MODE_RESID) {
         if (part && ib.cap > 0) {
-            hipLaunchKernelGGL((ghost_kernel<DIM, Real, MODE>()), dim3(nblk), dim3(TileCfg<DIM>::NT), 0, s, A);
+            if (e0)
+                hipExtLaunchKernelGGL((ghost_kernel<DIM, Real, MODE>()), dim3(nblk), dim3(TileCfg<DIM>::NT), 0, s,
+                                      e0, e1, 0, A);
+            else
+                hipLaunchKernelGGL((ghost_kernel<DIM, Real, MODE>()), dim3(nblk), dim3(TileCfg<DIM>::NT), 0, s, A);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((plain_kernel<DIM, Real, MODE>()), dim3(nblk), dim3(TileCfg<DIM>::NT), 0, s, A);
+    if (e0)
+        hipExtLaunchKernelGGL((plain_kernel<DIM, Real, MODE>()), dim3(nblk), dim3(TileCfg<DIM>::NT), 0, s, e0, e1, 0,
+                              A);
+    else
+        hipLaunchKernelGGL((plain_kernel<DIM, Real, MODE>()), dim3(nblk), dim3(TileCfg<DIM>::NT), 0, s, A);
     return hipGetLastError();
 }
 
@@ -1665,18 +1676,19 @@ int stage_args(const Grid &g, const Flow &f, const IB &ib, double *qin, const do
 }
 
 template <int DIM, typename Real, int MODE>
-hipError_t batch_launch(const BatchArgs &B, bool ghosts, hipStream_t s)
+hipError_t batch_launch(const BatchArgs &B, bool ghosts, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     int nblk = B.off[B.n];
-    if (ghosts)
-        hipLaunchKernelGGL((batch_kernel<DIM, Real, MODE, true>()), dim3(nblk), dim3(TileCfg<DIM>::NT), 0, s, B);
+    auto k = ghosts ? batch_kernel<DIM, Real, MODE, true>() : batch_kernel<DIM, Real, MODE, false>();
+    if (e0)
+        hipExtLaunchKernelGGL(k, dim3(nblk), dim3(TileCfg<DIM>::NT), 0, s, e0, e1, 0, B);
     else
-        hipLaunchKernelGGL((batch_kernel<DIM, Real, MODE, false>()), dim3(nblk), dim3(TileCfg<DIM>::NT), 0, s, B);
+        hipLaunchKernelGGL(k, dim3(nblk), dim3(TileCfg<DIM>::NT), 0, s, B);
     return hipGetLastError();
 }
 
 hipError_t launch_stage_batch(int ndim, int precision, int scheme, bool ghosts, int n, const void *const *d_args,
-                              const int *nblk, hipStream_t s)
+                              const int *nblk, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     BatchArgs B;
     B.n = 0;
@@ -1693,12 +1705,16 @@ hipError_t launch_stage_batch(int ndim, int precision, int scheme, bool ghosts, 
     bool mixed = precision == IBM_MIXED, rk = scheme == IBM_RK3;
     if (ndim == 2) {
         if (rk)
-            return mixed ? batch_launch<2, float, MODE_RK3>(B, ghosts, s) : batch_launch<2, double, MODE_RK3>(B, ghosts, s);
-        return mixed ? batch_launch<2, float, MODE_DUAL>(B, ghosts, s) : batch_launch<2, double, MODE_DUAL>(B, ghosts, s);
+            return mixed ? batch_launch<2, float, MODE_RK3>(B, ghosts, s, e0, e1)
+                         : batch_launch<2, double, MODE_RK3>(B, ghosts, s, e0, e1);
+        return mixed ? batch_launch<2, float, MODE_DUAL>(B, ghosts, s, e0, e1)
+                     : batch_launch<2, double, MODE_DUAL>(B, ghosts, s, e0, e1);
     }
     if (rk)
-        return mixed ? batch_launch<3, float, MODE_RK3>(B, ghosts, s) : batch_launch<3, double, MODE_RK3>(B, ghosts, s);
-    return mixed ? batch_launch<3, float, MODE_DUAL>(B, ghosts, s) : batch_launch<3, double, MODE_DUAL>(B, ghosts, s);
+        return mixed ? batch_launch<3, float, MODE_RK3>(B, ghosts, s, e0, e1)
+                     : batch_launch<3, double, MODE_RK3>(B, ghosts, s, e0, e1);
+    return mixed ? batch_launch<3, float, MODE_DUAL>(B, ghosts, s, e0, e1)
+                 : batch_launch<3, double, MODE_DUAL>(B, ghosts, s, e0, e1);
 }
 
 int tile_load_cells(int ndim)

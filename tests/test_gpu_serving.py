@@ -128,3 +128,83 @@ def test_server_end_to_end_matches_alone():
         s.init_prim(init(case))
         s.advance(case.steps)
         assert bool((s.interior() == finals[id(case)]).all()), case.name
+
+
+def _poison(s, case):
+    """Put a NaN density into one FLUID cell of the solve's state, far from
+    the body (the cell at a quarter of each axis)."""
+    idx = (0, case.nk // 4 if case.ndim == 3 else 0, case.nj // 4, case.ni // 4)
+    s.interior()[idx] = float("nan")
+
+
+@pytest.mark.parametrize("victim", ["wedge", "naca-dual", "tube-moving", "box"])
+def test_nonfinite_solve_fails_alone_in_a_batch(victim):
+    """Failure isolation: a non-finite value in one solve of a batch makes
+    that solve report IBM_ENONFINITE, while every other solve of the batch
+    ends bit-identical to the same solve advanced alone, with a clean
+    status (each solve's status word and state are its own)."""
+    import torch
+    from paper_1912_11908_amd import batch_advance, IbmError
+    alone = _solvers()
+    batch = _solvers()
+    names = [name for name, _, _, _ in batch]
+    k = names.index(victim)
+    _poison(batch[k][3], batch[k][1])
+    for _, _, _, s in alone:
+        s.advance(3)
+    batch_advance([s for _, _, _, s in batch], 2)
+    batch_advance([s for _, _, _, s in batch], 1)
+    torch.cuda.synchronize()
+    for m, ((name, _, _, a), (_, _, _, b)) in enumerate(zip(alone, batch)):
+        a.check_status()
+        if m == k:
+            with pytest.raises(IbmError) as ei:
+                b.check_status()
+            assert ei.value.code == -4, (name, ei.value)
+            continue
+        b.check_status()
+        assert bool((a.interior() == b.interior()).all()), name
+
+
+def test_server_isolates_a_failed_request():
+    """The continuous-batching server with one poisoned request: that
+    request alone is reported failed (IBM_ENONFINITE); the others complete
+    with the same final state as alone."""
+    import torch
+    from workloads.serving import request_stream
+    from paper_1912_11908_amd import Solver
+    from paper_1912_11908_amd.serving import Server, GpuBackend
+
+    reqs = request_stream(n=10, rate=400.0, steps=12, sides=(64, 96))
+    init = lambda c: w.freestream_prim(c.ndim, c.ni, c.nj, c.nk, c.p_inf)  # noqa: E731
+    bad = reqs[3][1].name
+    finals, codes = {}, {}
+
+    class Keep(GpuBackend):
+        def create(self, case):
+            s = super().create(case)
+            if case.name == bad:
+                with torch.cuda.stream(s._serving_stream):
+                    _poison(s, case)
+            return s
+
+        def status(self, solver):
+            code = super().status(solver)
+            codes[solver.case.name] = code
+            return code
+
+        def release(self, solver):
+            finals[id(solver.case)] = solver.interior().clone()
+
+    st = Server(Keep("mixed", init=init), mem_budget=1 << 30, max_active=4, tick_evals=9).run(reqs)
+    torch.cuda.synchronize()
+    assert len(st.latencies) == len(reqs) and st.failed == 1
+    assert codes[bad] == -4
+    assert all(code == 0 for name, code in codes.items() if name != bad)
+    for _, case in reqs:
+        if case.name == bad:
+            continue
+        s = Solver(case, "mixed", "cuda:0")
+        s.init_prim(init(case))
+        s.advance(case.steps)
+        assert bool((s.interior() == finals[id(case)]).all()), case.name
