@@ -183,6 +183,21 @@ int ibm_residual(ibm_ctx *ctx, const double *d_q, double *d_r, void *stream);
 int ibm_forces(ibm_ctx *ctx, const double *d_q, double *d_force, double *d_facet, int32_t *d_missed,
                void *stream);
 
+/* For callers that cannot allocate device memory at call time (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid it): the
+ * force of ibm_forces, same arguments and bit-identical results, whose
+ * reduction scratch (block sums and, when d_missed is NULL, the
+ * facets-missed counter) lives in a fixed device array of the library
+ * instead of the context's workspace; nothing is allocated, no memset is
+ * enqueued.  Limit: IBM_FORCES_STATIC_MAX_FACETS facets (IBM_EINVAL beyond
+ * it); the context's device must be current.  The array is per device and
+ * shared by every call on that device: calls whose work overlaps on one
+ * device (other streams, other threads) race and must be serialised by the
+ * caller. */
+#define IBM_FORCES_STATIC_MAX_FACETS 262144
+int ibm_forces_static(ibm_ctx *ctx, const double *d_q, double *d_force, double *d_facet, int32_t *d_missed,
+                      void *stream);
+
 /* Free body (motion 2): displacement, velocity and acceleration along the
  * axis after the last step, and the axial force of that step (host out[4]).
  * Each step of a free body: pose at x^n, fill and ibm_forces at t^n (the

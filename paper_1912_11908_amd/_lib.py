@@ -19,9 +19,11 @@ REC_INT, REC_DBL = 24, 32
 EXPORTS = ["ibm_workspace_bytes", "ibm_create", "ibm_destroy", "ibm_set_time", "ibm_classify",
            "ibm_fill", "ibm_residual", "ibm_forces", "ibm_body_state", "ibm_advance", "ibm_init_state", "ibm_state_to_prim",
            "ibm_status", "ibm_read_counts", "ibm_info_get", "ibm_last_error",
-           "ibm_time_update_kernel", "ibm_set_option", "ibm_batch_advance", "ibm_stage_timing"]
+           "ibm_time_update_kernel", "ibm_set_option", "ibm_batch_advance", "ibm_stage_timing",
+           "ibm_forces_static"]
 
 BATCH_MAX = 64
+FORCES_STATIC_MAX_FACETS = 262144
 
 
 class IbmCase(ctypes.Structure):
@@ -80,6 +82,7 @@ def load():
     L.ibm_fill.argtypes = [P, P, D, P]
     L.ibm_residual.argtypes = [P, P, P, P]
     L.ibm_forces.argtypes = [P, P, P, P, P, P]
+    L.ibm_forces_static.argtypes = [P, P, P, P, P, P]
     L.ibm_body_state.argtypes = [P, P]
     L.ibm_advance.argtypes = [P, P, I, P]
     L.ibm_init_state.argtypes = [P, P, P, P]

@@ -1133,6 +1133,38 @@ int ibm_forces(ibm_ctx *c, const double *q, double *force, double *facet_out, in
     return dev_err(c, e, "forces");
 }
 
+int ibm_forces_static(ibm_ctx *c, const double *q, double *force, double *facet_out, int32_t *missed,
+                      void *stream)
+{
+    if (!c || !q || !force)
+        return IBM_EINVAL;
+    if (c->b.nfacet == 0)
+        return set_err(c, IBM_EINVAL, "ibm_forces_static: no body");
+    if (c->b.nfacet > IBM_FORCES_STATIC_MAX_FACETS)
+        return set_err(c, IBM_EINVAL, "ibm_forces_static: more facets than IBM_FORCES_STATIC_MAX_FACETS");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return dev_err(c, e, "ibm_forces_static: current device");
+    if (dev != c->device)
+        return set_err(c, IBM_EINVAL, "ibm_forces_static: the context's device must be current");
+    if (!c->classified) {
+        int rc = do_classify(c, c->t, S(stream));
+        if (rc)
+            return rc;
+    }
+    double *part = nullptr;
+    int32_t *own_missed = nullptr;
+    e = forces_static_scratch(dev, &part, &own_missed);
+    if (e != hipSuccess)
+        return dev_err(c, e, "ibm_forces_static: scratch address");
+    int32_t *m = missed ? missed : own_missed;
+    e = launch_zero_i32(m, S(stream));
+    if (e == hipSuccess)
+        e = launch_forces(c->g, c->b, c->f, c->ib, q, force, facet_out, part, m, S(stream));
+    return dev_err(c, e, "ibm_forces_static");
+}
+
 int ibm_body_state(const ibm_ctx *c, double *out)
 {
     if (!c || !out || !c->mo.free)

@@ -151,6 +151,12 @@ hipError_t launch_records(const Grid &g, const Body &b, const Flow &f, IB &ib, h
 int forces_blocks(int nfacet);
 hipError_t launch_forces(const Grid &g, const Body &b, const Flow &f, const IB &ib, const double *q, double *force,
                          double *facet_out, double *part, int32_t *missed, hipStream_t s);
+// the allocation-free variant's scratch on `device` (which must be current):
+// room for the block sums of IBM_FORCES_STATIC_MAX_FACETS facets and the
+// facets-missed counter
+hipError_t forces_static_scratch(int device, double **part, int32_t **missed);
+// *p = 0 by a one-thread kernel (no memset node when a caller captures)
+hipError_t launch_zero_i32(int32_t *p, hipStream_t s);
 // per near tile IB lists and FORCING corner lists (after the records)
 hipError_t launch_ghost_lists(const Grid &g, const IB &ib, bool quad, bool corner_lists, hipStream_t s);
 // cells a tile's stencils load (tile plus its halo) for this dimension

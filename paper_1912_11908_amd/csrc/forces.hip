@@ -16,12 +16,27 @@
 // One thread per facet; the block sums its facets in a fixed tree order and a
 // single block adds the block sums in a fixed order, so the result does not
 // depend on scheduling.  Built with -ffp-contract=off, like the geometry.
+#include <mutex>
+
 #include "common.h"
 
 namespace ibm {
 namespace {
 
 constexpr int kForceBlock = 256;
+
+// Scratch of the allocation-free force entry point: the block sums of
+// forces_kernel (3 doubles per block, at most kStaticForceBlocks blocks)
+// followed by the facets-missed counter (one int32 in the next double slot).
+// Each device holds its own copy until the process ends; host code reaches
+// it only through the address hipGetSymbolAddress gives on that device.
+constexpr int kStaticForceBlocks = IBM_FORCES_STATIC_MAX_FACETS / kForceBlock;
+static __device__ __align__(256) double scratch[3 * kStaticForceBlocks + 32];
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mutex;
+double *scratch_ptr[kMaxDevices];  // per device, once resolved
+
+__global__ void zero_i32_kernel(int32_t *p) { *p = 0; }
 
 __device__ inline long long state_index(const Grid &g, int i, int j, int k)
 {
@@ -224,6 +239,30 @@ __global__ __launch_bounds__(kForceBlock) void forces_sum_kernel(const double *p
 }  // namespace
 
 int forces_blocks(int nfacet) { return (nfacet + kForceBlock - 1) / kForceBlock; }
+
+hipError_t forces_static_scratch(int device, double **part, int32_t **missed)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_ptr[device]) {
+        // resolved once per device, with that device current (the caller's)
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        scratch_ptr[device] = static_cast<double *>(p);
+    }
+    *part = scratch_ptr[device];
+    *missed = reinterpret_cast<int32_t *>(scratch_ptr[device] + 3 * kStaticForceBlocks);
+    return hipSuccess;
+}
+
+hipError_t launch_zero_i32(int32_t *p, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, s, p);
+    return hipGetLastError();
+}
 
 hipError_t launch_forces(const Grid &g, const Body &b, const Flow &f, const IB &ib, const double *q, double *force,
                          double *facet_out, double *part, int32_t *missed, hipStream_t s)
