@@ -17,6 +17,12 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _lib = None
+# builds of the flow half in a wider scalar type (same arithmetic, loops and
+# order): long double and __float128, for parity at low Mach, where the
+# double oracle's absolute-variable rounding (about eps * p_inf per unit
+# dynamic pressure) is above the tolerance of the FP64 GPU path
+WIDE = {"long": ("liboracle_ld.so", 1, []), "quad": ("liboracle_q.so", 2, ["-lquadmath"])}
+_wide = {}
 
 BC = {"farfield": 0, "extrap": 1, "periodic": 2}
 FLUID, FORCING, G1, G2, G3, SOLID = range(6)
@@ -28,21 +34,39 @@ CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-D_GNU_SOUR
 
 
 def build(openmp=True):
-    """Compile oracle.c (gcc, -O2, no FP contraction, no fast-math)."""
-    cmd = ["gcc"] + CFLAGS
-    if openmp:
-        cmd.append("-fopenmp")
-    cmd += ["-o", _SO + ".tmp", os.path.join(_HERE, "oracle.c"), "-lm"]
-    subprocess.check_call(cmd)
-    os.replace(_SO + ".tmp", _SO)
+    """Compile oracle.c (gcc, -O2, no FP contraction, no fast-math): the
+    double oracle, and its flow half in long double and in __float128."""
+    for so, kind, libs in [("liboracle.so", 0, [])] + list(WIDE.values()):
+        path = os.path.join(_HERE, so)
+        cmd = ["gcc"] + CFLAGS + [f"-DORC_REAL_KIND={kind}"]
+        if openmp:
+            cmd.append("-fopenmp")
+        cmd += ["-o", path + ".tmp", os.path.join(_HERE, "oracle.c"), "-lm"] + libs
+        subprocess.check_call(cmd)
+        os.replace(path + ".tmp", path)
 
 
-def lib():
+def lib(precision="double"):
+    """The oracle library: precision "double" (the oracle), or "long" /
+    "quad" for the builds whose flow half computes in long double /
+    __float128."""
     global _lib
+    if precision != "double":
+        if precision not in _wide:
+            path = os.path.join(_HERE, WIDE[precision][0])
+            if not os.path.exists(path):
+                build()
+            _wide[precision] = _bind(ctypes.CDLL(path))
+        return _wide[precision]
     if _lib is None:
         if not os.path.exists(_SO):
             build()
-        L = ctypes.CDLL(_SO)
+        _lib = _bind(ctypes.CDLL(_SO))
+    return _lib
+
+
+def _bind(L):
+    if True:
         P = ctypes.c_void_p
         d, i = ctypes.c_double, ctypes.c_int
         L.orc_create.restype = P
@@ -78,8 +102,8 @@ def lib():
         L.orc_set_threads.argtypes = [i]
         L.orc_set_threads.restype = None
         L.orc_get_threads.restype = i
-        _lib = L
-    return _lib
+        L.orc_real_bytes.restype = ctypes.c_size_t
+    return L
 
 
 def _p(a):
@@ -125,7 +149,11 @@ class Oracle:
     """One solve on the CPU.  State arrays use the halo layout
     [nv][nk + 2 hz][nj + 6][ni + 6]; see ``new_state``."""
 
-    def __init__(self, case):
+    def __init__(self, case, precision="double"):
+        """precision: "double" (the oracle), or "long" / "quad" for its flow
+        half in long double / __float128 (states stay double)."""
+        self.L = lib(precision)
+        self.precision = precision
         self.case = case
         c = case
         self.ndim, self.ni, self.nj, self.nk = c.ndim, c.ni, c.nj, c.nk
@@ -149,7 +177,7 @@ class Oracle:
         # free body (section 6): displacement, velocity, acceleration along the axis
         self.body = [0.0, float(mo.get("velocity", 0.0)), 0.0]
         uinf = arr(list(c.u_inf) + [0.0] * (3 - len(c.u_inf)), np.float64)
-        self.h = lib().orc_create(
+        self.h = self.L.orc_create(
             c.ndim, c.ni, c.nj, c.nk, _p(xf), _p(yf), _p(zf), _p(bc), len(c.vert), len(c.facet),
             _p(vert), _p(facet), c.mach, c.reynolds, c.prandtl, c.gamma,
             0 if c.scheme == "rk3" else 1, 0 if c.ib_family == "linear" else 1, c.dt,
@@ -161,7 +189,7 @@ class Oracle:
 
     def __del__(self):
         if getattr(self, "h", None):
-            lib().orc_destroy(self.h)
+            self.L.orc_destroy(self.h)
             self.h = None
 
     @property
@@ -176,51 +204,56 @@ class Oracle:
         return q[:, h:h + self.nk, 3:3 + self.nj, 3:3 + self.ni]
 
     def param(self, which):
-        return lib().orc_get_param(self.h, {"pinf": 0, "R": 1, "cp": 2, "mu": 3, "k": 4,
+        return self.L.orc_get_param(self.h, {"pinf": 0, "R": 1, "cp": 2, "mu": 3, "k": 4,
                                             "uc2": 5, "disp": 6}[which])
 
     def prim_to_state(self, prim):
         prim = np.ascontiguousarray(prim, dtype=np.float64)
         q = self.new_state()
-        lib().orc_prim_to_state(self.h, _p(prim), _p(q))
+        self.L.orc_prim_to_state(self.h, _p(prim), _p(q))
         return q
 
     def dual_begin(self, q):
         """Start a physical dual-time step (history rotation); returns the
         'first step' flag to pass to dual_iterate."""
         c = self.case
-        if not hasattr(self, "_qn"):
-            n = self.nv * self.ni * self.nj * self.nk
-            self._qn = np.zeros(n)
-            self._qnm1 = np.zeros(n)
+        self._history()
         first = 1 if self.step_index == 0 else 0
         self.t += c.dt
-        lib().orc_dual_begin(self.h, _p(q), _p(self._qn), _p(self._qnm1), first, self.t)
+        self.L.orc_dual_begin(self.h, _p(q), _p(self._qn), _p(self._qnm1), first, self.t)
         self.step_index += 1
         return first
 
     def dual_iterate(self, q, first, n_iter):
         wt = q.copy()
-        lib().orc_dual_iterate(self.h, _p(q), _p(wt), _p(self._qn), _p(self._qnm1), first,
+        self.L.orc_dual_iterate(self.h, _p(q), _p(wt), _p(self._qn), _p(self._qnm1), first,
                                self.t, n_iter)
         return q
 
+    def _history(self):
+        """Dual-time history Q^n, Q^{n-1} (conserved, interior layout), in the
+        flow half's scalar type: opaque buffers of orc_real_bytes() per value."""
+        if not hasattr(self, "_qn"):
+            n = self.nv * self.ni * self.nj * self.nk * int(self.L.orc_real_bytes())
+            self._qn = np.zeros(n, dtype=np.uint8)
+            self._qnm1 = np.zeros(n, dtype=np.uint8)
+
     def state_to_prim(self, q):
         prim = np.zeros((self.nv, self.nk, self.nj, self.ni))
-        lib().orc_state_to_prim(self.h, _p(q), _p(prim))
+        self.L.orc_state_to_prim(self.h, _p(q), _p(prim))
         return prim
 
     def set_pose(self, t):
-        lib().orc_set_pose(self.h, t)
+        self.L.orc_set_pose(self.h, t)
 
     def classify(self, t=0.0):
         self.set_pose(t)
-        lib().orc_classify(self.h)
-        lib().orc_geometry(self.h)
+        self.L.orc_classify(self.h)
+        self.L.orc_geometry(self.h)
 
     def classes(self):
         out = np.zeros((self.nk, self.nj, self.ni), dtype=np.uint8)
-        lib().orc_get_class(self.h, _p(out))
+        self.L.orc_get_class(self.h, _p(out))
         return out
 
     def lists(self):
@@ -228,7 +261,7 @@ class Oracle:
         n = (self.ni * self.nj * self.nk) + 1
         lf = np.zeros(n, dtype=np.int32)
         lg = np.zeros(n, dtype=np.int32)
-        lib().orc_get_lists(self.h, _p(lf), _p(lg), _p(counts))
+        self.L.orc_get_lists(self.h, _p(lf), _p(lg), _p(counts))
         return lf[:counts[0]].copy(), lg[:counts[4]].copy(), counts
 
     def records(self):
@@ -236,24 +269,24 @@ class Oracle:
         nrec = int(counts[0] + counts[4])
         ir = np.zeros((max(nrec, 1), IREC), dtype=np.int32)
         dr = np.zeros((max(nrec, 1), DREC))
-        lib().orc_get_records(self.h, 0, _p(ir), _p(dr))
+        self.L.orc_get_records(self.h, 0, _p(ir), _p(dr))
         return ir[:nrec], dr[:nrec]
 
     def stats(self):
         s = np.zeros(6, dtype=np.int64)
-        lib().orc_get_stats(self.h, _p(s))
+        self.L.orc_get_stats(self.h, _p(s))
         return dict(zip(["fallback_pprime", "fallback_probe", "fallback_none",
                          "stencil_violation", "fresh_cleared", "fresh_violation"], s.tolist()))
 
     def bc(self, q):
-        lib().orc_bc(self.h, _p(q))
+        self.L.orc_bc(self.h, _p(q))
 
     def fill(self, q, t=0.0):
-        lib().orc_fill(self.h, _p(q), t)
+        self.L.orc_fill(self.h, _p(q), t)
 
     def residual(self, q):
         r = np.zeros((self.nv, self.nk, self.nj, self.ni))
-        lib().orc_residual(self.h, _p(q), _p(r))
+        self.L.orc_residual(self.h, _p(q), _p(r))
         return r
 
     def run(self, q, nsteps):
@@ -262,18 +295,15 @@ class Oracle:
         if c.scheme == "rk3":
             q1, q2 = q.copy(), q.copy()
             for _ in range(nsteps):
-                lib().orc_rk3_step(self.h, _p(q), _p(q1), _p(q2), self.t)
+                self.L.orc_rk3_step(self.h, _p(q), _p(q1), _p(q2), self.t)
                 self.t += c.dt
                 self.step_index += 1
         else:
-            if not hasattr(self, "_qn"):
-                n = self.nv * self.ni * self.nj * self.nk
-                self._qn = np.zeros(n)
-                self._qnm1 = np.zeros(n)
+            self._history()
             wt = q.copy()
             for _ in range(nsteps):
                 self.t += c.dt
-                lib().orc_dual_step(self.h, _p(q), _p(wt), _p(self._qn), _p(self._qnm1),
+                self.L.orc_dual_step(self.h, _p(q), _p(wt), _p(self._qn), _p(self._qnm1),
                                     1 if self.step_index == 0 else 0, self.t)
                 self.step_index += 1
         return q
@@ -283,7 +313,7 @@ class Oracle:
         [p - p_inf, (tau n)_x, (tau n)_y, (tau n)_z, area], facets missed)."""
         F = np.zeros(3)
         per = np.zeros((max(len(self.case.facet), 1), 5))
-        missed = lib().orc_forces(self.h, _p(q), _p(F), _p(per))
+        missed = self.L.orc_forces(self.h, _p(q), _p(F), _p(per))
         return F, per[:len(self.case.facet)], missed
 
     def run_free(self, q, nsteps):
@@ -299,14 +329,14 @@ class Oracle:
         q1, q2 = q.copy(), q.copy()
         for _ in range(nsteps):
             x, u, a_prev = self.body
-            lib().orc_set_body(self.h, x, u, a_prev)
+            self.L.orc_set_body(self.h, x, u, a_prev)
             self.classify(self.t)
             self.fill(q, self.t)
             self.bc(q)
             F, _, _ = self.forces(q)
             a = F[ax] / mass
-            lib().orc_set_body(self.h, x, u, a)
-            lib().orc_rk3_step(self.h, _p(q), _p(q1), _p(q2), self.t)
+            self.L.orc_set_body(self.h, x, u, a)
+            self.L.orc_rk3_step(self.h, _p(q), _p(q1), _p(q2), self.t)
             self.t += dt
             self.step_index += 1
             self.body = [x + u * dt + 0.5 * dt * dt * a, u + dt * a, a]

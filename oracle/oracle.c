@@ -11,6 +11,38 @@
  * Each function cites the paper passage it follows; where the paper names a
  * method without writing it out, the function states the reading it uses.
  */
+/* Scalar type of the flow half (fills, residual, updates): ORC_REAL_KIND 0
+ * double (the oracle), 1 long double, 2 __float128 (builds with less
+ * rounding for low-Mach parity: same arithmetic, loops and order).  Arrays
+ * that cross the interface (states, residuals, primitives, records) stay
+ * double; the dual-time history arrays take the scalar type. */
+#ifndef ORC_REAL_KIND
+#define ORC_REAL_KIND 0
+#endif
+#if ORC_REAL_KIND == 2
+#include <quadmath.h>
+#define ORC_REAL __float128
+#define RSQRT sqrtq
+#define RFABS fabsq
+#define RFLOOR floorq
+#define RFMIN fminq
+#define RFMAX fmaxq
+#elif ORC_REAL_KIND == 1
+#define ORC_REAL long double
+#define RSQRT sqrtl
+#define RFABS fabsl
+#define RFLOOR floorl
+#define RFMIN fminl
+#define RFMAX fmaxl
+#else
+#define ORC_REAL double
+#define RSQRT sqrt
+#define RFABS fabs
+#define RFLOOR floor
+#define RFMIN fmin
+#define RFMAX fmax
+#endif
+
 #include "oracle.h"
 
 #include <math.h>
@@ -27,6 +59,7 @@
 #define DREC 32
 
 typedef long long i64;
+typedef orc_real real;
 
 struct orc {
     int ndim, ni, nj, nk, nv, hz;
@@ -1074,7 +1107,7 @@ int orc_geometry(orc *o)
  * for dual time the state is Q_p' = (p - p_inf, u, v[, w], T - T_inf), the
  * primitive unknowns of section 4.4 taken as perturbations. */
 typedef struct {
-    double rho, u[3], p, T;
+    real rho, u[3], p, T;
 } prim_t;
 
 static prim_t state_prim(const orc *o, const double *q, long s)
@@ -1083,9 +1116,11 @@ static prim_t state_prim(const orc *o, const double *q, long s)
     long vs = o->vstride;
     int nd = o->ndim;
     w.u[0] = w.u[1] = w.u[2] = 0.0;
+    /* the sums below are taken in the scalar type (the state values and
+     * constants are double) */
     if (o->scheme == ORC_RK3) {
         w.rho = q[s];
-        double ke = 0.0;
+        real ke = 0.0;
         for (int d = 0; d < nd; d++) {
             w.u[d] = q[s + (1 + d) * vs] / w.rho;
             ke += w.u[d] * w.u[d];
@@ -1093,10 +1128,10 @@ static prim_t state_prim(const orc *o, const double *q, long s)
         w.p = (o->gamma - 1.0) * (q[s + (nd + 1) * vs] - 0.5 * w.rho * ke);
         w.T = w.p / (w.rho * o->R);
     } else {
-        w.p = o->pinf + q[s];
+        w.p = (real)o->pinf + q[s];
         for (int d = 0; d < nd; d++)
             w.u[d] = q[s + (1 + d) * vs];
-        w.T = 1.0 + q[s + (nd + 1) * vs];
+        w.T = (real)1.0 + q[s + (nd + 1) * vs];
         w.rho = w.p / (o->R * w.T);
     }
     return w;
@@ -1107,7 +1142,7 @@ static void prim_state(const orc *o, prim_t w, double *q, long s)
     long vs = o->vstride;
     int nd = o->ndim;
     if (o->scheme == ORC_RK3) {
-        double ke = 0.0;
+        real ke = 0.0;
         for (int d = 0; d < nd; d++)
             ke += w.u[d] * w.u[d];
         q[s] = w.rho;
@@ -1123,10 +1158,10 @@ static void prim_state(const orc *o, prim_t w, double *q, long s)
 }
 
 /* conserved vector of a primitive state (always conserved, any scheme) */
-static void prim_cons(const orc *o, prim_t w, double *Q)
+static void prim_cons(const orc *o, prim_t w, real *Q)
 {
     int nd = o->ndim;
-    double ke = 0.0;
+    real ke = 0.0;
     for (int d = 0; d < nd; d++)
         ke += w.u[d] * w.u[d];
     Q[0] = w.rho;
@@ -1187,10 +1222,10 @@ void orc_bc(orc *o, double *q)
     int n[3] = {o->ni, o->nj, o->nk};
     prim_t fs;
     freestream_prim(o, &fs);
-    double qfs[5];
+    real qfs[5];
     {
         /* the free stream in the state's own variables */
-        double tmp[5 * 1];
+        real tmp[5 * 1];
         (void)tmp;
         if (o->scheme == ORC_RK3)
             prim_cons(o, fs, qfs);
@@ -1251,10 +1286,18 @@ void orc_bc(orc *o, double *q)
  * sections 4.5 and 5): two multilinear probes and a quadratic profile.
  * Forcing nodes are filled first (they read FLUID cells only), then all ghost
  * layers (they read FLUID and FORCING cells); each pass is Jacobi. */
+/* The value at a probe: the weighted mean sum_m w_m phi_m / sum_m w_m of
+ * (p, u.., T) over its corners (multilinear or inverse-distance weights,
+ * sections 4.5-4.6).  The weights of a probe sum to one; dividing by their
+ * computed sum reproduces a constant field exactly, whatever the rounding of
+ * the weights (at low Mach p is p_inf plus a perturbation some 1e6 times
+ * smaller, so a sum of weights off by an ulp would otherwise shift p by
+ * that ulp of p_inf). */
 static void probe_value(const orc *o, const double *q, const int32_t *ids, const double *w,
-                        double *phi)
+                        real *phi)
 {
     int nd = o->ndim;
+    real wsum = 0.0;
     for (int v = 0; v < nd + 2; v++)
         phi[v] = 0.0;
     for (int m = 0; m < (1 << nd); m++) {
@@ -1267,13 +1310,17 @@ static void probe_value(const orc *o, const double *q, const int32_t *ids, const
         for (int d = 0; d < nd; d++)
             phi[1 + d] += w[m] * p.u[d];
         phi[nd + 1] += w[m] * p.T;
+        wsum += w[m];
     }
+    if (wsum > 0.0)
+        for (int v = 0; v < nd + 2; v++)
+            phi[v] /= wsum;
 }
 
 static void fill_range(orc *o, double *q, int r0, int r1, double t)
 {
     int nd = o->ndim, quad = o->family == ORC_IB_QUADRATIC;
-    double ub[3] = {0, 0, 0}, ab[3] = {0, 0, 0};
+    real ub[3] = {0, 0, 0}, ab[3] = {0, 0, 0};
     if (o->motion) {
         ub[o->maxis] = pose_vel(o, t);
         ab[o->maxis] = pose_acc(o, t);
@@ -1284,8 +1331,8 @@ static void fill_range(orc *o, double *q, int r0, int r1, double t)
         const int32_t *ir = o->irec + (long)IREC * r;
         const double *dr = o->drec + (long)DREC * r;
         const double *n = dr;
-        double sx = dr[6], s1 = dr[7], s2 = dr[8];
-        double phi1[5], phi2[5];
+        real sx = dr[6], s1 = dr[7], s2 = dr[8];
+        real phi1[5], phi2[5];
         prim_t res;
         res.u[0] = res.u[1] = res.u[2] = 0.0;
         if (ir[4] == 2) { /* no valid probe corner at all: counted fallback */
@@ -1295,16 +1342,16 @@ static void fill_range(orc *o, double *q, int r0, int r1, double t)
                 res.u[d] = ub[d];
         } else {
             probe_value(o, q, ir + 7, dr + 9, phi1);
-            double rho1 = phi1[0] / (o->R * phi1[nd + 1]);
-            double an = 0.0;
+            real rho1 = phi1[0] / (o->R * phi1[nd + 1]);
+            real an = 0.0;
             for (int d = 0; d < nd; d++)
                 an += n[d] * ab[d];
-            double gp = -rho1 * an, gT = 0.0;
+            real gp = -rho1 * an, gT = 0.0;
             if (o->wallp == ORC_WALL_EQ7 && nd == 2) {
                 /* eq.7 (reading: the normal momentum balance at the wall, n
                  * into the fluid): dp/dn = rho u_t^2 kappa - rho a_n, u_t the
                  * tangential velocity relative to the wall at probe 1 */
-                double ut = -(phi1[1] - ub[0]) * n[1] + (phi1[2] - ub[1]) * n[0];
+                real ut = -(phi1[1] - ub[0]) * n[1] + (phi1[2] - ub[1]) * n[0];
                 gp = rho1 * ut * ut * dr[26] - rho1 * an;
             }
             if (!quad || ir[5] == 2) {
@@ -1315,17 +1362,17 @@ static void fill_range(orc *o, double *q, int r0, int r1, double t)
             } else {
                 probe_value(o, q, ir + 15, dr + 17, phi2);
                 /* Dirichlet: parabola through (0, phiB), (s1, phi1), (s2, phi2) */
-                double L0 = (sx - s1) * (sx - s2) / (s1 * s2);
-                double L1 = sx * (sx - s2) / (s1 * (s1 - s2));
-                double L2 = sx * (sx - s1) / (s2 * (s2 - s1));
+                real L0 = (sx - s1) * (sx - s2) / (s1 * s2);
+                real L1 = sx * (sx - s2) / (s1 * (s1 - s2));
+                real L2 = sx * (sx - s1) / (s2 * (s2 - s1));
                 for (int d = 0; d < nd; d++)
                     res.u[d] = ub[d] * L0 + phi1[1 + d] * L1 + phi2[1 + d] * L2;
                 /* Neumann: phi = c0 + g s + c2 s^2 through the two probes */
-                double c2p = (phi2[0] - phi1[0] - gp * (s2 - s1)) / (s2 * s2 - s1 * s1);
-                double c0p = phi1[0] - gp * s1 - c2p * s1 * s1;
+                real c2p = (phi2[0] - phi1[0] - gp * (s2 - s1)) / (s2 * s2 - s1 * s1);
+                real c0p = phi1[0] - gp * s1 - c2p * s1 * s1;
                 res.p = c0p + gp * sx + c2p * sx * sx;
-                double c2T = (phi2[nd + 1] - phi1[nd + 1] - gT * (s2 - s1)) / (s2 * s2 - s1 * s1);
-                double c0T = phi1[nd + 1] - gT * s1 - c2T * s1 * s1;
+                real c2T = (phi2[nd + 1] - phi1[nd + 1] - gT * (s2 - s1)) / (s2 * s2 - s1 * s1);
+                real c0T = phi1[nd + 1] - gT * s1 - c2T * s1 * s1;
                 res.T = c0T + gT * sx + c2T * sx * sx;
             }
         }
@@ -1353,7 +1400,7 @@ void orc_fill(orc *o, double *q, double t)
 /* Second-order TVD reconstruction (section 2 names the scheme, not its
  * limiter; reading: MUSCL with the minmod limiter): the state at the face
  * between b and c seen from b's side, b + (1/2) minmod(b - a, c - b). */
-static double minmod(double x, double y)
+static real minmod(real x, real y)
 {
     if (x > 0.0 && y > 0.0)
         return x < y ? x : y;
@@ -1362,25 +1409,25 @@ static double minmod(double x, double y)
     return 0.0;
 }
 
-double orc_tvd2(double a, double b, double c)
+static real tvd2_r(real a, real b, real c)
 {
     return b + 0.5 * minmod(b - a, c - b);
 }
 
-double orc_weno5(double a, double b, double c, double d, double e)
+static real weno5_r(real a, real b, real c, real d, real e)
 {
-    double q0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;
-    double q1 = (-b + 5.0 * c + 2.0 * d) / 6.0;
-    double q2 = (2.0 * c + 5.0 * d - e) / 6.0;
-    double b0 = 13.0 / 12.0 * (a - 2.0 * b + c) * (a - 2.0 * b + c) +
+    real q0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;
+    real q1 = (-b + 5.0 * c + 2.0 * d) / 6.0;
+    real q2 = (2.0 * c + 5.0 * d - e) / 6.0;
+    real b0 = 13.0 / 12.0 * (a - 2.0 * b + c) * (a - 2.0 * b + c) +
                 0.25 * (a - 4.0 * b + 3.0 * c) * (a - 4.0 * b + 3.0 * c);
-    double b1 = 13.0 / 12.0 * (b - 2.0 * c + d) * (b - 2.0 * c + d) + 0.25 * (b - d) * (b - d);
-    double b2 = 13.0 / 12.0 * (c - 2.0 * d + e) * (c - 2.0 * d + e) +
+    real b1 = 13.0 / 12.0 * (b - 2.0 * c + d) * (b - 2.0 * c + d) + 0.25 * (b - d) * (b - d);
+    real b2 = 13.0 / 12.0 * (c - 2.0 * d + e) * (c - 2.0 * d + e) +
                 0.25 * (3.0 * c - 4.0 * d + e) * (3.0 * c - 4.0 * d + e);
-    double a0 = 0.1 / ((WENO_EPS + b0) * (WENO_EPS + b0));
-    double a1 = 0.6 / ((WENO_EPS + b1) * (WENO_EPS + b1));
-    double a2 = 0.3 / ((WENO_EPS + b2) * (WENO_EPS + b2));
-    double s = a0 + a1 + a2;
+    real a0 = 0.1 / ((WENO_EPS + b0) * (WENO_EPS + b0));
+    real a1 = 0.6 / ((WENO_EPS + b1) * (WENO_EPS + b1));
+    real a2 = 0.3 / ((WENO_EPS + b2) * (WENO_EPS + b2));
+    real s = a0 + a1 + a2;
     return (a0 / s) * q0 + (a1 / s) * q1 + (a2 / s) * q2;
 }
 
@@ -1389,70 +1436,70 @@ double orc_weno5(double a, double b, double c, double d, double e)
  * LDFSS(0) with the interface speed of sound replaced, in dual-time mode, by
  * the Weiss-Smith preconditioned one
  *   eps = min(1, max(|u_L|^2/2 + |u_R|^2/2, U_c^2) / a_half^2),
- *   a~  = (1/2) sqrt((1 - eps)^2 Ubar^2 + 4 eps a_half^2),
+ *   a~  = (1/2) RSQRT((1 - eps)^2 Ubar^2 + 4 eps a_half^2),
  * and the split pressure taken on the unpreconditioned interface Mach numbers
  * U / a_half, with its velocity-diffusion part p_bar (D+ + D- - 1) scaled by
  * a~ / a_half, so that the pressure dissipation is of the order of the
  * dynamic pressure, rho U_r U, at low Mach.
  * With eps = 1 (or outside dual time) this is exactly LDFSS(0).
  * w = (rho, u, v[, w], p); nrm = unit normal; flux per unit area. */
-static double sgn1(double m) { return m >= 0.0 ? 1.0 : -1.0; }
+static real sgn1(real m) { return m >= 0.0 ? 1.0 : -1.0; }
 
-void orc_ldfss(int ndim, const double *wl, const double *wr, const double *nrm, double gamma,
-               int precond, double uc2, double *flux)
+static void ldfss_r(int ndim, const real *wl, const real *wr, const double *nrm, double gamma,
+                    int precond, double uc2, real *flux)
 {
     int nv = ndim + 2;
-    double rl = wl[0], rr = wr[0], pl = wl[nv - 1], pr = wr[nv - 1];
-    double UL = 0.0, UR = 0.0, ql2 = 0.0, qr2 = 0.0;
+    real rl = wl[0], rr = wr[0], pl = wl[nv - 1], pr = wr[nv - 1];
+    real UL = 0.0, UR = 0.0, ql2 = 0.0, qr2 = 0.0;
     for (int d = 0; d < ndim; d++) {
         UL += wl[1 + d] * nrm[d];
         UR += wr[1 + d] * nrm[d];
         ql2 += wl[1 + d] * wl[1 + d];
         qr2 += wr[1 + d] * wr[1 + d];
     }
-    double al = sqrt(gamma * pl / rl), ar = sqrt(gamma * pr / rr);
-    double ah = 0.5 * (al + ar);
-    double at = ah, eps = 1.0;
+    real al = RSQRT(gamma * pl / rl), ar = RSQRT(gamma * pr / rr);
+    real ah = 0.5 * (al + ar);
+    real at = ah, eps = 1.0;
     if (precond) {
-        eps = fmin(1.0, fmax(0.5 * ql2 + 0.5 * qr2, uc2) / (ah * ah));
+        eps = RFMIN(1.0, RFMAX(0.5 * ql2 + 0.5 * qr2, uc2) / (ah * ah));
         if (eps < 1.0) {
-            double ub = 0.5 * (UL + UR);
-            at = 0.5 * sqrt((1.0 - eps) * (1.0 - eps) * ub * ub + 4.0 * eps * ah * ah);
+            real ub = 0.5 * (UL + UR);
+            at = 0.5 * RSQRT((1.0 - eps) * (1.0 - eps) * ub * ub + 4.0 * eps * ah * ah);
         }
     }
-    double ML = UL / at, MR = UR / at;
-    double apl = 0.5 * (1.0 + sgn1(ML)), amr = 0.5 * (1.0 - sgn1(MR));
-    double bl = -fmax(0.0, 1.0 - floor(fabs(ML))), br = -fmax(0.0, 1.0 - floor(fabs(MR)));
-    double mpl = 0.25 * (ML + 1.0) * (ML + 1.0), mmr = -0.25 * (MR - 1.0) * (MR - 1.0);
-    double cp = apl * (1.0 + bl) * ML - bl * mpl;
-    double cm = amr * (1.0 + br) * MR - br * mmr;
-    double mh = 0.25 * bl * br * (sqrt(0.5 * (ML * ML + MR * MR)) - 1.0) *
-                (sqrt(0.5 * (ML * ML + MR * MR)) - 1.0);
-    double dp = pl - pr;
-    double mhp = mh * (1.0 - (dp + fabs(dp)) / (2.0 * rl * at * at));
-    double mhm = mh * (1.0 + (dp - fabs(dp)) / (2.0 * rr * at * at));
-    double chp = cp - mhp, chm = cm + mhm;
-    double ppl = 0.25 * (ML + 1.0) * (ML + 1.0) * (2.0 - ML);
-    double pmr = 0.25 * (MR - 1.0) * (MR - 1.0) * (2.0 + MR);
-    double dpl = apl * (1.0 + bl) - bl * ppl;
-    double dmr = amr * (1.0 + br) - br * pmr;
-    double Hl = gamma / (gamma - 1.0) * pl / rl + 0.5 * ql2;
-    double Hr = gamma / (gamma - 1.0) * pr / rr + 0.5 * qr2;
-    double fl = at * rl * chp, fr = at * rr * chm;
-    double pf;
+    real ML = UL / at, MR = UR / at;
+    real apl = 0.5 * (1.0 + sgn1(ML)), amr = 0.5 * (1.0 - sgn1(MR));
+    real bl = -RFMAX(0.0, 1.0 - RFLOOR(RFABS(ML))), br = -RFMAX(0.0, 1.0 - RFLOOR(RFABS(MR)));
+    real mpl = 0.25 * (ML + 1.0) * (ML + 1.0), mmr = -0.25 * (MR - 1.0) * (MR - 1.0);
+    real cp = apl * (1.0 + bl) * ML - bl * mpl;
+    real cm = amr * (1.0 + br) * MR - br * mmr;
+    real mh = 0.25 * bl * br * (RSQRT(0.5 * (ML * ML + MR * MR)) - 1.0) *
+                (RSQRT(0.5 * (ML * ML + MR * MR)) - 1.0);
+    real dp = pl - pr;
+    real mhp = mh * (1.0 - (dp + RFABS(dp)) / (2.0 * rl * at * at));
+    real mhm = mh * (1.0 + (dp - RFABS(dp)) / (2.0 * rr * at * at));
+    real chp = cp - mhp, chm = cm + mhm;
+    real ppl = 0.25 * (ML + 1.0) * (ML + 1.0) * (2.0 - ML);
+    real pmr = 0.25 * (MR - 1.0) * (MR - 1.0) * (2.0 + MR);
+    real dpl = apl * (1.0 + bl) - bl * ppl;
+    real dmr = amr * (1.0 + br) - br * pmr;
+    real Hl = gamma / (gamma - 1.0) * pl / rl + 0.5 * ql2;
+    real Hr = gamma / (gamma - 1.0) * pr / rr + 0.5 * qr2;
+    real fl = at * rl * chp, fr = at * rr * chm;
+    real pf;
     if (eps >= 1.0)
         pf = dpl * pl + dmr * pr;
     else {
         /* pressure split on the unpreconditioned interface Mach numbers,
          * velocity-diffusion part scaled by a~ / a_half */
-        double mL = UL / ah, mR = UR / ah;
-        double aL = 0.5 * (1.0 + sgn1(mL)), aR = 0.5 * (1.0 - sgn1(mR));
-        double gL = -fmax(0.0, 1.0 - floor(fabs(mL))), gR = -fmax(0.0, 1.0 - floor(fabs(mR)));
-        double qL = 0.25 * (mL + 1.0) * (mL + 1.0) * (2.0 - mL);
-        double qR = 0.25 * (mR - 1.0) * (mR - 1.0) * (2.0 + mR);
-        double eL = aL * (1.0 + gL) - gL * qL;
-        double eR = aR * (1.0 + gR) - gR * qR;
-        double pbar = 0.5 * (pl + pr);
+        real mL = UL / ah, mR = UR / ah;
+        real aL = 0.5 * (1.0 + sgn1(mL)), aR = 0.5 * (1.0 - sgn1(mR));
+        real gL = -RFMAX(0.0, 1.0 - RFLOOR(RFABS(mL))), gR = -RFMAX(0.0, 1.0 - RFLOOR(RFABS(mR)));
+        real qL = 0.25 * (mL + 1.0) * (mL + 1.0) * (2.0 - mL);
+        real qR = 0.25 * (mR - 1.0) * (mR - 1.0) * (2.0 + mR);
+        real eL = aL * (1.0 + gL) - gL * qL;
+        real eR = aR * (1.0 + gR) - gR * qR;
+        real pbar = 0.5 * (pl + pr);
         pf = pbar + 0.5 * (eL - eR) * (pl - pr) + at / ah * pbar * (eL + eR - 1.0);
     }
     flux[0] = fl + fr;
@@ -1468,7 +1515,7 @@ void orc_ldfss(int ndim, const double *wl, const double *wr, const double *nrm, 
  * gradient from the two cell values, tangential gradients as the mean of the
  * two cells' central differences, face velocity the mean of the two cells,
  * constant mu, tau = mu (grad u + grad u^T - 2/3 div u I), q = -k grad T. */
-static void face_flux(const orc *o, const double *q, int i, int j, int k, int ax, double *F)
+static void face_flux(const orc *o, const double *q, int i, int j, int k, int ax, real *F)
 {
     int nd = o->ndim, nv = o->nv;
     int off[3] = {0, 0, 0};
@@ -1480,42 +1527,42 @@ static void face_flux(const orc *o, const double *q, int i, int j, int k, int ax
         st[m] = state_prim(o, q, sidx(o, i + s * off[0], j + s * off[1], k + s * off[2]));
         (void)st[m];
     }
-    double v[6][5];
+    real v[6][5];
     for (int m = 0; m < 6; m++) {
         v[m][0] = st[m].rho;
         for (int d = 0; d < nd; d++)
             v[m][1 + d] = st[m].u[d];
         v[m][nv - 1] = st[m].p;
     }
-    double wl[5], wr[5];
+    real wl[5], wr[5];
     for (int var = 0; var < nv; var++) {
         if (o->recon == ORC_RECON_TVD2) {
-            wl[var] = orc_tvd2(v[1][var], v[2][var], v[3][var]);
-            wr[var] = orc_tvd2(v[4][var], v[3][var], v[2][var]);
+            wl[var] = tvd2_r(v[1][var], v[2][var], v[3][var]);
+            wr[var] = tvd2_r(v[4][var], v[3][var], v[2][var]);
         } else {
-            wl[var] = orc_weno5(v[0][var], v[1][var], v[2][var], v[3][var], v[4][var]);
-            wr[var] = orc_weno5(v[5][var], v[4][var], v[3][var], v[2][var], v[1][var]);
+            wl[var] = weno5_r(v[0][var], v[1][var], v[2][var], v[3][var], v[4][var]);
+            wr[var] = weno5_r(v[5][var], v[4][var], v[3][var], v[2][var], v[1][var]);
         }
     }
     double nrm[3] = {0, 0, 0};
     nrm[ax] = 1.0;
-    double fi[5];
-    orc_ldfss(nd, wl, wr, nrm, o->gamma, o->scheme == ORC_DUAL, o->uc2, fi);
+    real fi[5];
+    ldfss_r(nd, wl, wr, nrm, o->gamma, o->scheme == ORC_DUAL, o->uc2, fi);
 
     /* viscous flux */
     const double *cc[3] = {o->xc, o->yc, o->zc};
     int lo[3] = {i, j, k}, hi[3] = {i + off[0], j + off[1], k + off[2]};
     prim_t PL = st[2], PR = st[3];
-    double grad[4][3]; /* d(u_m)/dx_d for m < 3, dT/dx_d in row 3 */
+    real grad[4][3]; /* d(u_m)/dx_d for m < 3, dT/dx_d in row 3 */
     int idx_lo = lo[ax] + 3, idx_hi = hi[ax] + 3;
-    double dn = cc[ax][idx_hi] - cc[ax][idx_lo];
+    real dn = cc[ax][idx_hi] - cc[ax][idx_lo];
     for (int m = 0; m < 3; m++)
         grad[m][ax] = (PR.u[m] - PL.u[m]) / dn;
     grad[3][ax] = (PR.T - PL.T) / dn;
     for (int e = 0; e < nd; e++) {
         if (e == ax)
             continue;
-        double g[4] = {0, 0, 0, 0};
+        real g[4] = {0, 0, 0, 0};
         for (int side = 0; side < 2; side++) {
             int b[3] = {side ? hi[0] : lo[0], side ? hi[1] : lo[1], side ? hi[2] : lo[2]};
             int p1[3] = {b[0], b[1], b[2]}, m1[3] = {b[0], b[1], b[2]};
@@ -1523,7 +1570,7 @@ static void face_flux(const orc *o, const double *q, int i, int j, int k, int ax
             m1[e] -= 1;
             prim_t A = state_prim(o, q, sidx(o, p1[0], p1[1], p1[2]));
             prim_t B = state_prim(o, q, sidx(o, m1[0], m1[1], m1[2]));
-            double de = cc[e][b[e] + 4] - cc[e][b[e] + 2];
+            real de = cc[e][b[e] + 4] - cc[e][b[e] + 2];
             for (int m = 0; m < 3; m++)
                 g[m] += 0.5 * (A.u[m] - B.u[m]) / de;
             g[3] += 0.5 * (A.T - B.T) / de;
@@ -1534,19 +1581,19 @@ static void face_flux(const orc *o, const double *q, int i, int j, int k, int ax
     for (int m = 0; m < 4; m++)
         for (int e = nd; e < 3; e++)
             grad[m][e] = 0.0;
-    double div = 0.0;
+    real div = 0.0;
     for (int d = 0; d < nd; d++)
         div += grad[d][d];
-    double uf[3];
+    real uf[3];
     for (int m = 0; m < 3; m++)
         uf[m] = 0.5 * (PL.u[m] + PR.u[m]);
-    double tau[3]; /* tau_{m, ax} */
+    real tau[3]; /* tau_{m, ax} */
     for (int m = 0; m < 3; m++)
         tau[m] = o->mu * (grad[m][ax] + grad[ax][m] - (m == ax ? 2.0 / 3.0 * div : 0.0));
-    double qn = -o->kc * grad[3][ax];
-    double fv[5];
+    real qn = -o->kc * grad[3][ax];
+    real fv[5];
     fv[0] = 0.0;
-    double work = 0.0;
+    real work = 0.0;
     for (int d = 0; d < nd; d++) {
         fv[1 + d] = tau[d];
         work += uf[d] * tau[d];
@@ -1565,7 +1612,7 @@ static int is_solid_at(const orc *o, int i, int j, int k)
     return o->cls[cidx(o, i, j, k)] == ORC_SOLID;
 }
 
-void orc_residual(orc *o, const double *q, double *r)
+static void residual_r(orc *o, const double *q, real *r)
 {
     int nd = o->ndim, nv = o->nv;
     long n = (long)o->ni * o->nj * o->nk;
@@ -1595,13 +1642,13 @@ void orc_residual(orc *o, const double *q, double *r)
                         if (is_solid_at(o, p[0], p[1], p[2]))
                             viol++;
                     }
-        double dx[3] = {o->xf[i + 4] - o->xf[i + 3], o->yf[j + 4] - o->yf[j + 3],
+        real dx[3] = {o->xf[i + 4] - o->xf[i + 3], o->yf[j + 4] - o->yf[j + 3],
                         o->zf[k + 4] - o->zf[k + 3]};
-        double vol = dx[0] * dx[1] * dx[2];
-        double acc[5] = {0, 0, 0, 0, 0};
+        real vol = dx[0] * dx[1] * dx[2];
+        real acc[5] = {0, 0, 0, 0, 0};
         for (int ax = 0; ax < nd; ax++) {
-            double area = vol / dx[ax];
-            double Fp[5], Fm[5];
+            real area = vol / dx[ax];
+            real Fp[5], Fm[5];
             int off[3] = {0, 0, 0};
             off[ax] = 1;
             face_flux(o, q, i, j, k, ax, Fp);
@@ -1614,6 +1661,40 @@ void orc_residual(orc *o, const double *q, double *r)
     }
     o->stat_stencil_violation += viol;
 }
+
+/* The exported evaluations take and return double; the arithmetic runs in
+ * the oracle's scalar type. */
+void orc_residual(orc *o, const double *q, double *r)
+{
+    long n = (long)o->ni * o->nj * o->nk * o->nv;
+    real *rr = (real *)malloc(sizeof(real) * n);
+    residual_r(o, q, rr);
+    for (long m = 0; m < n; m++)
+        r[m] = (double)rr[m];
+    free(rr);
+}
+
+double orc_weno5(double a, double b, double c, double d, double e)
+{
+    return (double)weno5_r(a, b, c, d, e);
+}
+
+double orc_tvd2(double a, double b, double c) { return (double)tvd2_r(a, b, c); }
+
+void orc_ldfss(int ndim, const double *wl, const double *wr, const double *nrm, double gamma,
+               int precond, double uc2, double *flux)
+{
+    real a[5] = {0, 0, 0, 0, 0}, b[5] = {0, 0, 0, 0, 0}, f[5];
+    for (int m = 0; m < ndim + 2; m++) {
+        a[m] = wl[m];
+        b[m] = wr[m];
+    }
+    ldfss_r(ndim, a, b, nrm, gamma, precond, uc2, f);
+    for (int m = 0; m < ndim + 2; m++)
+        flux[m] = (double)f[m];
+}
+
+size_t orc_real_bytes(void) { return sizeof(real); }
 
 /* ------------------------------------------------------ a10 SSP-RK3 step */
 /* Shu-Osher three-stage SSP Runge-Kutta (the explicit scheme of the
@@ -1630,8 +1711,8 @@ static void rk_stage(orc *o, const double *qn, const double *qin, double *qout, 
 {
     int nv = o->nv;
     long n = (long)o->ni * o->nj * o->nk, vs = o->vstride;
-    double *r = (double *)malloc(sizeof(double) * nv * n);
-    orc_residual(o, qin, r);
+    real *r = (real *)malloc(sizeof(real) * nv * n);
+    residual_r(o, qin, r);
 #pragma omp parallel for schedule(static)
     for (long c = 0; c < n; c++) {
         int i = (int)(c % o->ni), j = (int)((c / o->ni) % o->nj), k = (int)(c / ((long)o->ni * o->nj));
@@ -1639,7 +1720,7 @@ static void rk_stage(orc *o, const double *qn, const double *qin, double *qout, 
         uint8_t t = o->cls[c];
         if (t == ORC_FLUID) {
             for (int v = 0; v < nv; v++)
-                qout[s + v * vs] = a * qn[s + v * vs] + b * (qin[s + v * vs] - o->dt * r[v * n + c]);
+                qout[s + v * vs] = (real)a * qn[s + v * vs] + (real)b * (qin[s + v * vs] - o->dt * r[v * n + c]);
         } else if (t != ORC_SOLID) {
             for (int v = 0; v < nv; v++)
                 qout[s + v * vs] = qin[s + v * vs];
@@ -1679,49 +1760,49 @@ void orc_rk3_step(orc *o, double *q, double *q1, double *q2, double t)
  * theta = 1/U_r^2 + 1/(c_p T) (Weiss-Smith), U_r^2 = min(a^2, max(|u|^2,
  * U_c^2)); BDF2 (b0, b2) = (3/2, 1/2), BDF1 (1, 0) for the first physical
  * step; dtau = CFL_tau / sum_d [(|U'_d| + c'_d) / dx_d + 2 nu_v / dx_d^2] with
- * U' = (1 + eps) u_d / 2, c' = sqrt((1 - eps)^2 u_d^2 + 4 eps a^2) / 2,
+ * U' = (1 + eps) u_d / 2, c' = RSQRT((1 - eps)^2 u_d^2 + 4 eps a^2) / 2,
  * eps = U_r^2 / a^2, nu_v = mu / rho max(4/3, gamma / Pr).  The system is
  * solved by Gaussian elimination with partial pivoting. */
-static void gauss_solve(int n, double A[5][5], double *b)
+static void gauss_solve(int n, real A[5][5], real *b)
 {
     for (int c = 0; c < n; c++) {
         int piv = c;
         for (int r = c + 1; r < n; r++)
-            if (fabs(A[r][c]) > fabs(A[piv][c]))
+            if (RFABS(A[r][c]) > RFABS(A[piv][c]))
                 piv = r;
         if (piv != c) {
             for (int m = 0; m < n; m++) {
-                double t = A[c][m];
+                real t = A[c][m];
                 A[c][m] = A[piv][m];
                 A[piv][m] = t;
             }
-            double t = b[c];
+            real t = b[c];
             b[c] = b[piv];
             b[piv] = t;
         }
         for (int r = c + 1; r < n; r++) {
-            double f = A[r][c] / A[c][c];
+            real f = A[r][c] / A[c][c];
             for (int m = c; m < n; m++)
                 A[r][m] -= f * A[c][m];
             b[r] -= f * b[c];
         }
     }
     for (int r = n - 1; r >= 0; r--) {
-        double s = b[r];
+        real s = b[r];
         for (int m = r + 1; m < n; m++)
             s -= A[r][m] * b[m];
         b[r] = s / A[r][r];
     }
 }
 
-static void conserved_of_state(orc *o, const double *q, double *Q)
+static void conserved_of_state(orc *o, const double *q, real *Q)
 {
     int nv = o->nv;
     long n = (long)o->ni * o->nj * o->nk;
     for (long c = 0; c < n; c++) {
         int i = (int)(c % o->ni), j = (int)((c / o->ni) % o->nj), k = (int)(c / ((long)o->ni * o->nj));
         prim_t w = state_prim(o, q, sidx(o, i, j, k));
-        double v[5];
+        real v[5];
         prim_cons(o, w, v);
         for (int m = 0; m < nv; m++)
             Q[m * n + c] = v[m];
@@ -1729,7 +1810,7 @@ static void conserved_of_state(orc *o, const double *q, double *Q)
 }
 
 /* Start of a physical step: history rotation Q^{n-1} <- Q^n, Q^n <- Q(W). */
-void orc_dual_begin(orc *o, const double *w, double *qn, double *qnm1, int first, double t_new)
+void orc_dual_begin(orc *o, const double *w, real *qn, real *qnm1, int first, double t_new)
 {
     long n = (long)o->ni * o->nj * o->nk;
     if (o->motion) {
@@ -1738,23 +1819,23 @@ void orc_dual_begin(orc *o, const double *w, double *qn, double *qnm1, int first
         orc_geometry(o);
     }
     if (!first)
-        memcpy(qnm1, qn, sizeof(double) * o->nv * n);
+        memcpy(qnm1, qn, sizeof(real) * o->nv * n);
     conserved_of_state(o, w, qn);
 }
 
 /* n_iter pseudo-time iterations of the current physical step. */
-void orc_dual_iterate(orc *o, double *w, double *wtmp, const double *qn, const double *qnm1,
+void orc_dual_iterate(orc *o, double *w, double *wtmp, const real *qn, const real *qnm1,
                       int first, double t_new, int n_iter)
 {
     int nd = o->ndim, nv = o->nv;
     long n = (long)o->ni * o->nj * o->nk, vs = o->vstride;
     /* (b0 Q - (b0 + b2) Q^n + b2 Q^{n-1}) / dt: BDF2 (3/2, 1/2), BDF1 (1, 0) */
-    double b0 = first ? 1.0 : 1.5, b2 = first ? 0.0 : 0.5;
-    double *r = (double *)malloc(sizeof(double) * nv * n);
+    real b0 = first ? 1.0 : 1.5, b2 = first ? 0.0 : 0.5;
+    real *r = (real *)malloc(sizeof(real) * nv * n);
     for (int it = 0; it < n_iter; it++) {
         orc_fill(o, w, t_new);
         orc_bc(o, w);
-        orc_residual(o, w, r);
+        residual_r(o, w, r);
         memcpy(wtmp, w, sizeof(double) * nv * vs);
 #pragma omp parallel for schedule(static)
         for (long c = 0; c < n; c++) {
@@ -1763,35 +1844,35 @@ void orc_dual_iterate(orc *o, double *w, double *wtmp, const double *qn, const d
             int i = (int)(c % o->ni), j = (int)((c / o->ni) % o->nj), k = (int)(c / ((long)o->ni * o->nj));
             long s = sidx(o, i, j, k);
             prim_t P = state_prim(o, w, s);
-            double Q[5];
+            real Q[5];
             prim_cons(o, P, Q);
-            double q2 = 0.0;
+            real q2 = 0.0;
             for (int d = 0; d < nd; d++)
                 q2 += P.u[d] * P.u[d];
-            double a2 = o->gamma * P.p / P.rho;
-            double ur2 = fmin(a2, fmax(q2, o->uc2));
-            double eps = ur2 / a2;
+            real a2 = o->gamma * P.p / P.rho;
+            real ur2 = RFMIN(a2, RFMAX(q2, o->uc2));
+            real eps = ur2 / a2;
             double dx[3] = {o->xf[i + 4] - o->xf[i + 3], o->yf[j + 4] - o->yf[j + 3],
                             o->zf[k + 4] - o->zf[k + 3]};
-            double nuv = o->mu / P.rho * fmax(4.0 / 3.0, o->gamma / o->pr);
-            double lam = 0.0;
+            real nuv = o->mu / P.rho * RFMAX(4.0 / 3.0, o->gamma / o->pr);
+            real lam = 0.0;
             for (int d = 0; d < nd; d++) {
-                double ud = P.u[d];
-                double up = 0.5 * (1.0 + eps) * fabs(ud);
-                double cpr = 0.5 * sqrt((1.0 - eps) * (1.0 - eps) * ud * ud + 4.0 * eps * a2);
+                real ud = P.u[d];
+                real up = 0.5 * (1.0 + eps) * RFABS(ud);
+                real cpr = 0.5 * RSQRT((1.0 - eps) * (1.0 - eps) * ud * ud + 4.0 * eps * a2);
                 lam += (up + cpr) / dx[d] + 2.0 * nuv / (dx[d] * dx[d]);
             }
-            double dtau = o->cfl_tau / lam;
-            double H = o->cp * P.T + 0.5 * q2;
-            double rp = 1.0 / (o->R * P.T), rT = -P.rho / P.T;
-            double th = 1.0 / ur2 + 1.0 / (o->cp * P.T);
-            double Pm[5][5], Gm[5][5], A[5][5];
+            real dtau = o->cfl_tau / lam;
+            real H = o->cp * P.T + 0.5 * q2;
+            real rp = 1.0 / (o->R * P.T), rT = -P.rho / P.T;
+            real th = 1.0 / ur2 + 1.0 / (o->cp * P.T);
+            real Pm[5][5], Gm[5][5], A[5][5];
             memset(Pm, 0, sizeof Pm);
             memset(Gm, 0, sizeof Gm);
             int e = nv - 1;
             for (int pass = 0; pass < 2; pass++) {
-                double (*M)[5] = pass == 0 ? Pm : Gm;
-                double x = pass == 0 ? rp : th;
+                real (*M)[5] = pass == 0 ? Pm : Gm;
+                real x = pass == 0 ? rp : th;
                 M[0][0] = x;
                 M[0][e] = rT;
                 for (int d = 0; d < nd; d++) {
@@ -1806,7 +1887,7 @@ void orc_dual_iterate(orc *o, double *w, double *wtmp, const double *qn, const d
             for (int m = 0; m < nv; m++)
                 for (int l = 0; l < nv; l++)
                     A[m][l] = Gm[m][l] / dtau + b0 / o->dt * Pm[m][l];
-            double rhs[5];
+            real rhs[5];
             for (int m = 0; m < nv; m++)
                 rhs[m] = -((b0 * (Q[m] - qn[m * n + c]) - b2 * (qn[m * n + c] - qnm1[m * n + c])) /
                                o->dt +
@@ -1820,7 +1901,7 @@ void orc_dual_iterate(orc *o, double *w, double *wtmp, const double *qn, const d
     free(r);
 }
 
-void orc_dual_step(orc *o, double *w, double *wtmp, double *qn, double *qnm1, int first,
+void orc_dual_step(orc *o, double *w, double *wtmp, real *qn, real *qnm1, int first,
                    double t_new)
 {
     orc_dual_begin(o, w, qn, qnm1, first, t_new);

@@ -16,7 +16,14 @@
  */
 #ifndef IBM_ORACLE_H
 #define IBM_ORACLE_H
+#include <stddef.h>
 #include <stdint.h>
+
+/* scalar type of the flow half: double unless a wider build sets it */
+#ifndef ORC_REAL
+#define ORC_REAL double
+#endif
+typedef ORC_REAL orc_real;
 
 #ifdef __cplusplus
 extern "C" {
@@ -59,11 +66,14 @@ void orc_fill(orc *o, double *q, double t);
 void orc_residual(orc *o, const double *q, double *r);
 /* a10: one SSP-RK3 step (3 stages), or one physical dual-time step. */
 void orc_rk3_step(orc *o, double *q, double *q1, double *q2, double t);
-void orc_dual_step(orc *o, double *w, double *wtmp, double *qn, double *qnm1, int first,
+/* qn, qnm1: the step history Q^n, Q^{n-1}, conserved, [nv][nk][nj][ni], in the
+ * flow half's scalar type (orc_real_bytes() bytes per value) */
+void orc_dual_step(orc *o, double *w, double *wtmp, orc_real *qn, orc_real *qnm1, int first,
                    double t_new);
-void orc_dual_begin(orc *o, const double *w, double *qn, double *qnm1, int first, double t_new);
-void orc_dual_iterate(orc *o, double *w, double *wtmp, const double *qn, const double *qnm1,
+void orc_dual_begin(orc *o, const double *w, orc_real *qn, orc_real *qnm1, int first, double t_new);
+void orc_dual_iterate(orc *o, double *w, double *wtmp, const orc_real *qn, const orc_real *qnm1,
                       int first, double t_new, int n_iter);
+size_t orc_real_bytes(void);
 /* state <-> primitive (rho, u, v[, w], p) on interior cells. */
 void orc_prim_to_state(orc *o, const double *prim, double *q);
 void orc_state_to_prim(orc *o, const double *q, double *prim);

@@ -203,7 +203,10 @@ __global__ void bc_kernel(Grid g, FreeStream fs, double *q, int nhalo)
 // (Dirichlet) or slope (Neumann) and the probe; quadratic family: profile
 // through two probes (sections 4.5-4.6 and 5).  s = 0 at P', s > 0 in the
 // fluid; the node sits at s_X.
-// (rho, u.., p, T) of state values qv (the cell's NV state variables)
+// (rho, u.., p, T) of state values qv (the cell's NV state variables).  For
+// dual time p and T are the perturbations p - p_inf and T - 1: the fill's
+// profiles are affine in p and T (the weights of a probe sum to one), so
+// they run on the perturbations and no O(p_inf) value is ever rounded.
 template <int DIM>
 __device__ inline void prim_of_state(const Flow &f, const double *qv, double &rho, double *u, double &p,
                                      double &T)
@@ -220,12 +223,12 @@ __device__ inline void prim_of_state(const Flow &f, const double *qv, double &rh
         p = (f.gamma - 1.0) * (qv[DIM + 1] - 0.5 * rho * ke);
         T = p * ri * f.rR;
     } else {
-        p = f.pinf + qv[0];
+        p = qv[0];
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
             u[d] = qv[1 + d];
-        T = 1.0 + qv[DIM + 1];
-        rho = p * f.rR * rcp_fast<double>(T);
+        T = qv[DIM + 1];
+        rho = (f.pinf + p) * f.rR * rcp_fast<double>(1.0 + T);
     }
 }
 
@@ -289,17 +292,21 @@ __device__ __forceinline__ void node_fill(const Grid &g, const Flow &f, const IB
         abv[d] = d == axis ? ab : 0.0;
     }
     double sx = ib.plan_geo[3 * cap + r], s1 = ib.plan_geo[4 * cap + r], s2 = ib.plan_geo[5 * cap + r];
+    // p and T as prim_of_state gives them: absolute (RK3) or the
+    // perturbations (dual time)
+    const bool pert = f.scheme != IBM_RK3;
+    const double p0 = pert ? f.pinf : 0.0, T0 = pert ? 1.0 : 0.0;
     double rp, ru[DIM], rT;
     if (mode1 == 2) {  // no valid probe corner at all: counted fallback
-        rp = f.pinf;
-        rT = 1.0;
+        rp = f.pinf - p0;
+        rT = 1.0 - T0;
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
             ru[d] = ubv[d];
     } else {
         double phi1[NV];
         plan_probe<DIM, NEST>(g, f, ib, q, r, 0, c, phi1);
-        double rho1 = phi1[0] * f.rR * rcp_fast<double>(phi1[NV - 1]);
+        double rho1 = (p0 + phi1[0]) * f.rR * rcp_fast<double>(T0 + phi1[NV - 1]);
         double an = 0.0;
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
@@ -337,8 +344,8 @@ __device__ __forceinline__ void node_fill(const Grid &g, const Flow &f, const IB
             rT = c0T + gT * sx + c2T * sx * sx;
         }
     }
-    double rrho = rp * f.rR * rcp_fast<double>(rT);
     if (f.scheme == IBM_RK3) {
+        double rrho = rp * f.rR * rcp_fast<double>(rT);
         double ke = 0.0;
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
@@ -349,11 +356,11 @@ __device__ __forceinline__ void node_fill(const Grid &g, const Flow &f, const IB
             qs[1 + d] = rrho * ru[d];
         qs[DIM + 1] = rp * f.gm1inv + 0.5 * rrho * ke;
     } else {
-        qs[0] = rp - f.pinf;
+        qs[0] = rp;
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
             qs[1 + d] = ru[d];
-        qs[DIM + 1] = rT - 1.0;
+        qs[DIM + 1] = rT;
     }
 }
 

@@ -18,23 +18,38 @@ def smooth_prim(case, seed=0, amp=0.03, u_amp=0.1):
     return prim
 
 
-def make_pair(case, prim, precision="fp64"):
+# achieved errors of the parity tests, printed at the end of the session
+ACHIEVED = []
+
+
+def record(name, errs):
+    """Keep a test's achieved error(s) for the end-of-session summary."""
+    errs = np.atleast_1d(np.asarray(errs, dtype=float))
+    ACHIEVED.append((name, float(errs.max()), errs.tolist()))
+
+
+def oracle_precision(case):
+    """Scalar type of the oracle's flow half for a case.  The double oracle
+    forms fluxes in absolute variables, whose largest terms are p_inf and
+    rho H_inf, so at low Mach its own rounding is about eps (p_inf + H_inf)
+    per unit dynamic pressure (7e-9 at M = 0.001): the low-Mach cases use its
+    __float128 build, whose floor is far below the FP64 tolerance."""
+    return "quad" if case.mach <= 0.01 else "double"
+
+
+def make_pair(case, prim, precision="fp64", oracle_prec=None):
     from paper_1912_11908_amd import Solver
     s = Solver(case, precision, "cuda:0")
     s.init_prim(prim)
-    o = oracle.Oracle(case)
+    o = oracle.Oracle(case, oracle_prec or oracle_precision(case))
     return s, o
 
 
 def tol64(case):
-    """FP64 parity tolerance.  1e-12 relative L2, unless the oracle's own
-    rounding floor is higher: it forms fluxes in absolute variables, whose
-    largest terms are p_inf and rho H_inf, so its residual carries an
-    absolute error of about eps * (p_inf + H_inf) per unit dynamic pressure
-    (rho_inf U_inf^2 = 1); a factor 10 covers accumulation over a step."""
-    p_inf = case.p_inf
-    h_inf = case.gamma / (case.gamma - 1.0) * p_inf + 0.5
-    return max(1e-12, 10 * np.finfo(float).eps * (p_inf + h_inf))
+    """FP64 parity tolerance: 1e-12 relative L2 per variable (with the
+    scales of compare_state), at every Mach number: the low-Mach cases are
+    compared with the oracle's wide build (oracle_precision)."""
+    return 1e-12
 
 
 def resid_tol_abs(case, var):
@@ -87,3 +102,24 @@ def conserved_from_prim(prim, gamma=1.4):
         out[1 + d] = rho * u[d]
     out[nd + 1] = p / (gamma - 1) + 0.5 * rho * np.sum(u * u, axis=0)
     return out
+
+
+def compare_state(got, ref, case, mask=None):
+    """Per-variable relative L2 error of solver states (interior).  RK3
+    states (conserved) as compare_fields.  Dual-time states (p - p_inf, u..,
+    T - 1): velocities against the free-stream speed and p' against the
+    dynamic pressure rho_inf U_inf^2 (both 1 per cell) when their own norm
+    is smaller, T' against T_inf (1 per cell) likewise: the perturbations
+    at low Mach are O(M^2) of their absolute values, and these are the
+    scales on which the flow is measured."""
+    if case.scheme != "dual":
+        return compare_fields(got, ref, mask)
+    out = []
+    for v in range(ref.shape[0]):
+        a, b = got[v], ref[v]
+        if mask is not None:
+            a, b = a[mask], b[mask]
+        num = np.sqrt(np.sum((a - b) ** 2))
+        den = max(np.sqrt(np.sum(b ** 2)), np.sqrt(b.size))
+        out.append(num / den)
+    return np.array(out)

@@ -3,9 +3,10 @@ against the oracle on the same filled state: per-facet rows within 1e-11 of
 each column's scale, the total within 1e-11 of the sum of the facets'
 absolute contributions (the two sides add in different orders), the same
 count of facets without a valid centre, and bit-identical repeated calls.
-P - p_inf also carries the fill's own floor: a filled node's pressure is
-formed in absolute terms and then less p_inf, which leaves an absolute
-error of a few ulps of p_inf on either side (16 eps p_inf allowed)."""
+P - p_inf also carries the double oracle's fill floor: it forms a filled
+node's pressure in absolute terms and then less p_inf, which leaves an
+absolute error of a few ulps of p_inf (16 eps p_inf allowed; the low-Mach
+case is compared with the oracle's __float128 build, where it vanishes)."""
 import numpy as np
 import pytest
 

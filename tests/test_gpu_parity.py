@@ -1,12 +1,13 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle on
 the same seeded inputs.  Classification, lists and record integers must be
 bit-exact; FP64 flow fields must agree to a relative L2 of 1e-12 per
-variable."""
+variable (low-Mach cases against the oracle's __float128 build, whose own
+rounding is far below that); every test records its achieved error."""
 import numpy as np
 import pytest
 
 import workloads as w
-from gpu_common import make_pair, smooth_prim, compare_fields, rel_l2, tol64, resid_tol_abs
+from gpu_common import make_pair, smooth_prim, compare_fields, compare_state, rel_l2, tol64, resid_tol_abs, record
 
 pytestmark = pytest.mark.gpu
 
@@ -17,6 +18,7 @@ SMALL = {
     "cylinder-quad": lambda: w.small_case("cylinder", 64, steps=4, ib_family="quadratic"),
     "wedge": lambda: w.small_case("wedge", 48, steps=4),
     "naca": lambda: w.small_case("naca", 48, steps=2, n_inner=3),
+    "naca-m0.01": lambda: w.small_case("naca", 48, steps=3, n_inner=4, mach=0.01),
     "moving-cylinder": lambda: w.small_case("moving-cylinder", 64, steps=4),
     "ragged": lambda: w.small_case("cylinder", 61, steps=3),
     "tube-moving": lambda: w.small_case("tube", 32, steps=3, nz=8, ntheta=64, nzt=4),
@@ -93,18 +95,21 @@ def test_fill_and_residual_fp64(kind):
     o.fill(q, 0.0)
     o.bc(q)
     got = s.state.cpu().numpy().reshape(q.shape)
-    errs = compare_fields(got, q)
-    if case.scheme == "dual":
-        # p' carries O(eps p_inf) absolute rounding on both sides; compare it
-        # against the dynamic pressure (rho U^2 = 1) instead
-        assert np.abs(got[0] - q[0]).max() < tol64(case)
-        errs = errs[1:]
+    errs = compare_state(got, q, case)
+    record(f"fill[{kind}]", errs)
     assert errs.max() < 1e-13, errs
     r = s.residual().cpu().numpy()
     ro = o.residual(q)
+    rel = []
     for v in range(ro.shape[0]):
         err = np.abs(r[v] - ro[v]).max()
-        assert err <= max(TOL64 * np.abs(ro[v]).max(), resid_tol_abs(case, v)), (v, err)
+        scale = np.abs(ro[v]).max()
+        # the double oracle's own floor (absolute variables); none for its
+        # wide build
+        floor = resid_tol_abs(case, v) if o.precision == "double" else 0.0
+        rel.append(err / scale)
+        assert err <= max(TOL64 * scale, floor), (v, err, scale)
+    record(f"residual[{kind}]", rel)
     assert np.abs(ro).max() > 0
 
 
@@ -122,24 +127,27 @@ def test_rk3_steps_fp64(kind):
     o.run(q, n)
     got = s.interior().cpu().numpy()
     errs = compare_fields(got, o.interior(q))
+    record(f"rk3[{kind}]", errs)
     assert errs.max() < TOL64, errs
     assert np.array_equal(s.classes(), o.classes())
 
 
-def test_dual_time_fp64():
-    case, prim, s, o = _classified("naca")
+@pytest.mark.parametrize("kind", ["naca", "naca-sdsn", "naca-m0.01"])
+def test_dual_time_fp64(kind):
+    """Dual time at M = 0.001 (and 0.01): the FP64 state (p', u, v, T')
+    against the oracle's __float128 build within 1e-12 relative L2, with p'
+    measured against rho_inf U_inf^2 and the velocities against U_inf."""
+    case, prim, s, o = _classified(kind)
+    assert o.precision == "quad"
     n = case.steps
     s.advance(n)
     s.check_status()
     q = o.prim_to_state(prim)
     o.run(q, n)
-    gp = s.to_prim().cpu().numpy()
-    op = o.state_to_prim(q)
-    errs = compare_fields(gp, op)
-    assert errs.max() < tol64(case), errs
-    # pressure perturbation relative to the dynamic pressure rho U^2
-    dp = np.abs(gp[3] - op[3]).max()
-    assert dp < 1e-6, dp
+    errs = compare_state(s.interior().cpu().numpy(), o.interior(q), case)
+    record(f"dual[{kind}]", errs)
+    print(kind, "FP64 dual-time rel L2 (p', u, v, T')", errs)
+    assert errs.max() < TOL64, errs
 
 
 def test_c1_full_fp64():
@@ -154,6 +162,7 @@ def test_c1_full_fp64():
     q = o.prim_to_state(prim)
     o.run(q, case.steps)
     errs = compare_fields(s.interior().cpu().numpy(), o.interior(q))
+    record("C1 full 200 steps", errs)
     assert errs.max() < TOL64, errs
 
 
@@ -199,11 +208,20 @@ def test_nonfinite_status_reported():
     assert s.status() == -4
 
 
-@pytest.mark.parametrize("kind", ["cylinder", "wedge", "naca", "tube-moving", "supersonic-moving", "cylinder-tvd",
-                                  "star-sdsn", "tube-moving-sdsn"])
+# Mixed-precision gates: about ten times the errors measured on MI355X
+# (largest per-primitive relative L2 after the case's steps, p' against
+# rho U^2 at low Mach): cylinder 2.2e-8, wedge 5.9e-8, naca 4.9e-8,
+# tube-moving 1.8e-8, supersonic-moving 6.4e-9, cylinder-tvd 2.0e-8,
+# star-sdsn 2.1e-8, tube-moving-sdsn 1.8e-8.
+MIXED_GATE = {"cylinder": 3e-7, "wedge": 6e-7, "naca": 5e-7, "tube-moving": 2e-7, "supersonic-moving": 7e-8,
+              "cylinder-tvd": 2e-7, "star-sdsn": 3e-7, "tube-moving-sdsn": 2e-7}
+
+
+@pytest.mark.parametrize("kind", sorted(MIXED_GATE))
 def test_mixed_precision_error(kind):
     """Mixed mode (FP32 reconstruction and fluxes on perturbation variables,
-    FP64 update) stays within a stated distance of the FP64 oracle."""
+    FP64 update) stays within a stated distance of the FP64 oracle: about
+    ten times the error measured, so that an accuracy regression fails."""
     case, prim, s, o = _classified(kind, "mixed")
     n = case.steps
     s.advance(n)
@@ -213,8 +231,12 @@ def test_mixed_precision_error(kind):
     gp = s.to_prim().cpu().numpy()
     op = o.state_to_prim(q)
     errs = compare_fields(gp, op)
+    if case.scheme == "dual":
+        # p against rho U^2 rather than p_inf (its own norm is O(p_inf))
+        errs[case.ndim + 1] = compare_state(s.interior().cpu().numpy(), o.interior(q), case)[0]
+    record(f"mixed[{kind}]", errs)
     print(kind, "mixed rel L2 per primitive", errs)
-    assert errs.max() < 1e-4, errs
+    assert errs.max() < MIXED_GATE[kind], errs
 
 
 @pytest.mark.parametrize("kind", ["wedge", "naca", "tube-static", "naca-sdsn", "star-sdsn"])
@@ -244,9 +266,9 @@ def test_graph_replay_matches_eager(kind):
     a.check_status()
 
 
-def _full_prefix(case, steps, precision="fp64"):
+def _full_prefix(case, steps, precision="fp64", oracle_prec=None):
     prim = w.freestream_prim(case.ndim, case.ni, case.nj, case.nk, case.p_inf)
-    s, o = make_pair(case, prim, precision)
+    s, o = make_pair(case, prim, precision, oracle_prec)
     s.classify()
     o.classify()
     assert np.array_equal(s.classes(), o.classes())
@@ -262,19 +284,22 @@ def test_c2_full_size_prefix_fp64():
     case = w.case_c2()
     s, o, q = _full_prefix(case, 5)
     errs = compare_fields(s.interior().cpu().numpy(), o.interior(q))
+    record("C2 full-size 5 steps", errs)
     assert errs.max() < TOL64, errs
 
 
 def test_c3_full_size_prefix_fp64():
     """NACA 0012 at M = 0.001 at its full 2048x1024 size: classification
-    exact, one physical dual-time step of 20 pseudo-iterations."""
+    exact, one physical dual-time step of 20 pseudo-iterations; the state
+    (p', u, v, T') within 1e-12 of the oracle's long double build (its
+    __float128 build takes too long at this size; the long double floor, a
+    few 1e-14 of rho U^2, is still far below the tolerance)."""
     case = w.case_c3()
-    s, o, q = _full_prefix(case, 1)
-    gp = s.to_prim().cpu().numpy()
-    op = o.state_to_prim(q)
-    errs = compare_fields(gp, op)
-    assert errs.max() < tol64(case), errs
-    assert np.abs(gp[3] - op[3]).max() < 1e-6   # p' against rho U^2 = 1
+    s, o, q = _full_prefix(case, 1, oracle_prec="long")
+    errs = compare_state(s.interior().cpu().numpy(), o.interior(q), case)
+    record("C3 full-size 1 step", errs)
+    print("C3 FP64 rel L2 (p', u, v, T')", errs)
+    assert errs.max() < TOL64, errs
 
 
 def test_c4_full_size_prefix_fp64():
@@ -296,4 +321,5 @@ def test_c4_full_size_prefix_fp64():
     q = o.prim_to_state(prim)
     o.run(q, 1)
     errs = compare_fields(s.interior().cpu().numpy(), o.interior(q))
+    record("C4 full-size 1 step", errs)
     assert errs.max() < TOL64, errs
