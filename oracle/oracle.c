@@ -568,6 +568,17 @@ int orc_classify(orc *o)
     uint8_t *in = (uint8_t *)calloc(ncell, 1);
     i64 lo[3], hi[3];
     body_box(o, lo, hi);
+    /* the predicates multiply lattice differences inside the body's box in
+     * 64-bit integers: refuse a box too large for that */
+    if (o->nfacet > 0) {
+        double ext = 0.0;
+        for (int d = 0; d < o->ndim; d++)
+            ext = fmax(ext, (double)hi[d] - (double)lo[d]);
+        if (2.0 * ext * ext >= 0x1p62) {
+            free(in);
+            return -2;
+        }
+    }
 #pragma omp parallel for schedule(static)
     for (long c = 0; c < ncell; c++) {
         int i = (int)(c % o->ni), j = (int)((c / o->ni) % o->nj), k = (int)(c / ((long)o->ni * o->nj));

@@ -53,6 +53,7 @@ struct ibm_ctx {
     const double *batch_q;
     std::vector<char> h_args;
     long long rest_box_lat[6];
+    long long region_lat[6];  // lattice box of the IB region's node centres
     // stage timing (IBM_OPT_STAGE_TIMING): event pairs recorded at the start
     // and end of each stage launch, tev_used of tev_cap taken since the last
     // ibm_stage_timing
@@ -430,6 +431,41 @@ void body_normals(HostGeom &h, const std::vector<double> &v)
     h.nedge = ne;
 }
 
+// Lattice box of the node centres of the IB region (empty: nhi < nlo).
+void region_lattice(const HostGeom &h, long long *nlo, long long *nhi)
+{
+    for (int d = 0; d < 3; ++d) {
+        int i0 = h.region[2 * d], i1 = h.region[2 * d + 1];
+        if (d >= h.nd || i1 <= i0) {
+            nlo[d] = 1;
+            nhi[d] = 0;
+            continue;
+        }
+        nlo[d] = h.Xc[d][i0];
+        nhi[d] = h.Xc[d][i1 - 1];
+    }
+}
+
+// The exact crossing predicates (section 3.2) multiply a facet's edge
+// extent by a node-to-vertex distance in 64-bit integers on the 2^24
+// lattice (the 3D crossing sum then uses 128 bits).  Both factors are bounded
+// by the body's lattice box (vertices shifted by sh along each axis) and the
+// lattice box of the node centres the classification visits (nlo, nhi; empty
+// when nhi < nlo); the products, and the difference of two, must stay below
+// 2^63.  Checked in floating point, which has ample range.
+bool lattice_products_fit(int nd, const long long *vlo, const long long *vhi, const long long *sh,
+                          const long long *nlo, const long long *nhi)
+{
+    double eb = 0.0, er = 0.0;
+    for (int d = 0; d < nd; ++d) {
+        double lo = (double)vlo[d] + (double)sh[d], hi = (double)vhi[d] + (double)sh[d];
+        eb = std::max(eb, hi - lo);
+        if (nhi[d] >= nlo[d])
+            er = std::max(er, std::max(std::fabs((double)nhi[d] - lo), std::fabs(hi - (double)nlo[d])));
+    }
+    return 2.0 * eb * std::max(eb, er) < 0x1p62;
+}
+
 int host_geom(const ibm_case *c, HostGeom &h)
 {
     h.nd = c->ndim;
@@ -545,6 +581,19 @@ int host_geom(const ibm_case *c, HostGeom &h)
     int rw = h.region[1] - h.region[0], rh = h.region[3] - h.region[2], rd = h.region[5] - h.region[4];
     if (rw <= 0 || rh <= 0 || rd <= 0)
         rw = rh = rd = 0;
+    if (nf > 0) {
+        long long vlo[3], vhi[3], nlo[3], nhi[3], zero[3] = {0, 0, 0};
+        region_lattice(h, nlo, nhi);
+        for (int d = 0; d < nd; ++d) {
+            vlo[d] = vhi[d] = h.V0[d];
+            for (int m = 1; m < nv; ++m) {
+                vlo[d] = std::min(vlo[d], h.V0[(size_t)m * nd + d]);
+                vhi[d] = std::max(vhi[d], h.V0[(size_t)m * nd + d]);
+            }
+        }
+        if (!lattice_products_fit(nd, vlo, vhi, zero, nlo, nhi))
+            return IBM_EGEOM;
+    }
     h.cap = rw * rh * rd;
     h.wpr = (rw + 1 + 31) / 32;
     h.nblk = (h.cap + 255) / 256;
@@ -700,6 +749,19 @@ int do_classify(ibm_ctx *c, double t, hipStream_t s)
         double disp, vel, acc;
         motion_kin(c, t, disp, vel, acc);
         long long dl = std::llrint(disp * kLatScale);
+        {
+            long long vlo[3], vhi[3], nlo[3], nhi[3], sh[3];
+            for (int d = 0; d < 3; ++d) {
+                vlo[d] = c->rest_box_lat[2 * d];
+                vhi[d] = c->rest_box_lat[2 * d + 1];
+                nlo[d] = c->region_lat[2 * d];
+                nhi[d] = c->region_lat[2 * d + 1];
+                sh[d] = d == c->mo.axis ? dl : 0;
+            }
+            if (!std::isfinite(disp) || std::fabs(disp) > 1.0e6 ||
+                !lattice_products_fit(c->g.ndim, vlo, vhi, sh, nlo, nhi))
+                return set_err(c, IBM_EGEOM, "body pose beyond the range of the exact lattice predicates");
+        }
         for (int d = 0; d < 3; ++d) {
             long long sh = d == c->mo.axis ? dl : 0;
             c->b.disp[d] = (double)sh / kLatScale;
@@ -855,6 +917,14 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
         }
         x->rest_box_lat[2 * d] = b.lat_lo[d] = lo;
         x->rest_box_lat[2 * d + 1] = b.lat_hi[d] = hi;
+    }
+    {
+        long long nlo[3], nhi[3];
+        region_lattice(h, nlo, nhi);
+        for (int d = 0; d < 3; ++d) {
+            x->region_lat[2 * d] = nlo[d];
+            x->region_lat[2 * d + 1] = nhi[d];
+        }
     }
     if (e == hipSuccess) e = up(L.bin_start, h.bin_start);
     if (e == hipSuccess) e = up(L.bin_facet, h.bin_facet);

@@ -125,3 +125,26 @@ def test_product_path_has_no_cpu_fallback():
     src += open(os.path.join(ROOT, "paper_1912_11908_amd", "_lib.py")).read()
     assert "oracle" not in src.replace("oracle's", "")
     assert "import oracle" not in src
+
+
+def test_bodies_beyond_the_exact_predicates_rejected():
+    """The exact crossing predicates (section 3.2) multiply a facet's edge
+    extent by a node-to-vertex distance in 64-bit integers on the 2^24
+    lattice: a body and IB region too large for that is refused with
+    IBM_EGEOM by the host-only sizing call, before any device work.  A square
+    of side 60 in a box of side 64 fits (2 * (64 * 2^24)^2 < 2^62 with
+    room); one of side 200 does not."""
+    import paper_1912_11908_amd as P
+    from workloads.cases import Case
+    lib, L = _lib()
+    n = ctypes.c_size_t(0)
+    for side, want in ((60.0, 0), (200.0, -2)):
+        h = side / 2
+        v = w.snap(np.array([[-h, -h], [h, -h], [h, h], [-h, h]]))
+        s = np.array([[0, 1], [1, 2], [2, 3], [3, 0]], np.int32)
+        f = w.uniform_faces(64, -0.55 * side - 2, 0.55 * side + 2)
+        case = Case("square", 2, f, f.copy(), np.array([-0.5, 0.5]), ("farfield",) * 4 + ("periodic",) * 2,
+                    v, s, 0.3, 100.0, dt=1e-3)
+        c, keep = P.case_struct(case)
+        assert L.ibm_workspace_bytes(ctypes.byref(c), ctypes.byref(n)) == want, side
+        del keep
