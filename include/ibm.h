@@ -144,7 +144,11 @@ int ibm_workspace_bytes(const ibm_case *c, size_t *bytes);
 int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out);
 void ibm_destroy(ibm_ctx *ctx);
 
-/* Solution time used by the next ibm_classify / ibm_advance call. */
+/* Solution time used by the next ibm_classify / ibm_advance call: the pose
+ * of a moving body (the prescribed translation of section 8.2.2, at
+ * constant speed in section 8.2.3) and the body velocity and acceleration
+ * of the wall conditions (eqs 4-7, section 4.4) are evaluated at it.
+ * IBM_EINVAL for a non-finite t; no device work. */
 int ibm_set_time(ibm_ctx *ctx, double t);
 
 /* a1-a4: pose the body at the context time, classify every cell by ray
@@ -158,11 +162,15 @@ int ibm_classify(ibm_ctx *ctx, void *stream);
  * (three per side) as images of the filled interior. */
 int ibm_fill(ibm_ctx *ctx, double *d_q, double t, void *stream);
 
-/* a6-a9: residual R = (1/V) sum_faces (F_inv - F_visc) . S of d_q on FLUID
- * cells (zero elsewhere), in conserved form, interior layout [nv][nk][nj][ni].
- * d_q's IB nodes must already be filled (ibm_fill); its halo is not read:
- * stencils resolve domain ghost cells from the interior by the rules of the
- * boundary types. */
+/* a6-a9 (section 2: cell-centred finite volumes with fifth-order WENO face
+ * states, low-diffusion flux splitting, preconditioned in dual time, and
+ * second-order central viscous fluxes; the unknowns of section 4.4):
+ * residual R = (1/V) sum_faces (F_inv - F_visc) . S of d_q on FLUID cells
+ * (zero elsewhere), in conserved form, device interior layout
+ * [nv][nk][nj][ni] (caller-owned, nv * ncell doubles).  d_q's IB nodes must
+ * already be filled (ibm_fill); its halo is not read: stencils resolve
+ * domain ghost cells from the interior by the rules of the boundary types.
+ * IBM_EINVAL for null pointers; asynchronous on stream. */
 int ibm_residual(ibm_ctx *ctx, const double *d_q, double *d_r, void *stream);
 
 /* Section 6, eq.9: the force on the body, F_i = surface integral of
@@ -208,10 +216,14 @@ int ibm_forces_static(ibm_ctx *ctx, const double *d_q, double *d_force, double *
 int ibm_body_state(const ibm_ctx *ctx, double *out);
 
 /* a1-a10: advance nsteps SSP-RK3 steps (IBM_RK3) or physical dual-time steps
- * of n_inner pseudo-iterations each (IBM_DUAL), in place on d_q.  Moving
- * bodies are reclassified at the pose of each step's start time.  The
- * interior (IB nodes included) is advanced; d_q's halo is neither read nor
- * written (call ibm_fill for a filled halo). */
+ * of n_inner pseudo-iterations each (IBM_DUAL; section 2: three-point
+ * physical-time and two-point pseudo-time differencing), in place on d_q,
+ * each stage filling the IB nodes first (sections 4.4-5).  Moving bodies
+ * are reclassified at every step (sections 3.2 and 5), at the pose of the
+ * step's start time (RK3) or end time (dual time).  The interior (IB nodes
+ * included) is advanced; d_q's halo is neither read nor written (call
+ * ibm_fill for a filled halo).  IBM_EINVAL for a null state or nsteps < 0;
+ * device errors and non-finite states are reported by ibm_status. */
 int ibm_advance(ibm_ctx *ctx, double *d_q, int nsteps, void *stream);
 
 /* Serving (several independent solves, e.g. under continuous batching):
