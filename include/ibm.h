@@ -270,6 +270,12 @@ int ibm_info_get(const ibm_ctx *ctx, ibm_info *out);
  * are enqueued eagerly (no graph replay).  0 turns it off.  At most
  * IBM_STAGE_TIMING_MAX.  Changing it discards unread timings. */
 #define IBM_OPT_STAGE_TIMING 3
+/* IBM_OPT_PIPELINE (default 1): a prescribed-motion solve classifies the
+ * next step (pose, ray parity, tags, lists, records) on a stream of its own
+ * into a second set of buffers while the current step's stages run on the
+ * caller's stream (joined by events); 0 classifies each step on the
+ * caller's stream before its stages.  Both give bit-identical results. */
+#define IBM_OPT_PIPELINE 4
 #define IBM_STAGE_TIMING_MAX 100000
 #define IBM_BATCH_MAX 64
 int ibm_set_option(ibm_ctx *ctx, int option, int value);

@@ -54,6 +54,16 @@ struct ibm_ctx {
     std::vector<char> h_args;
     long long rest_box_lat[6];
     long long region_lat[6];  // lattice box of the IB region's node centres
+    // classification buffers: ib is ibb[cur], the one the stages read.  With
+    // two (prescribed motion), the next step's classification runs on a side
+    // stream into the other while the current step's stages run
+    IB ibb[2];
+    int nbuf, cur;
+    bool buf_ok[2], buf_side[2];
+    double buf_t[2];
+    bool pipeline;            // IBM_OPT_PIPELINE
+    hipStream_t side;
+    hipEvent_t ev_fork, ev_ready[2];
     // stage timing (IBM_OPT_STAGE_TIMING): event pairs recorded at the start
     // and end of each stage launch, tev_used of tev_cap taken since the last
     // ibm_stage_timing
@@ -625,6 +635,15 @@ struct Layout {
     double *fforce;          // surface force of a free body's step
     int32_t *rmap;
     int32_t *tile_slot, *slot_tile, *tg_cnt, *tg_t, *tg_rec, *tj_cnt, *tj_rec;
+    // a second set of the classification's outputs (prescribed motion: the
+    // next step is classified while the current one's stages run)
+    struct Out2 {
+        uint8_t *cls;
+        int32_t *counts, *listF, *listG, *rec_i, *plan_node, *plan_off, *plan_mode, *plan_frec, *rmap;
+        double *rec_d, *plan_w, *plan_geo, *plan_kappa;
+        int32_t *tg_cnt, *tg_t, *tg_rec, *tj_cnt, *tj_rec;
+    } out2;
+    bool has_out2;
     int32_t *tiles;
     char *args;
     double *q1, *q2, *wtmp, *qn, *qnm1;
@@ -707,6 +726,31 @@ size_t carve(const ibm_case *c, const HostGeom &h, char *base, Layout &L)
         L.qn = cv.take<double>((size_t)h.ncell * (nd + 2));
         L.qnm1 = cv.take<double>((size_t)h.ncell * (nd + 2));
     }
+    L.has_out2 = c->motion == 1 && c->nfacet > 0 && h.cap > 0;
+    L.out2 = {};
+    if (L.has_out2) {
+        Layout::Out2 &o = L.out2;
+        size_t nslot = h.tiles_near.size(), stride = (size_t)tile_load_cells(nd);
+        o.cls = cv.take<uint8_t>(h.ncell);
+        o.counts = cv.take<int32_t>(CNT_WORDS);
+        o.listF = cv.take<int32_t>(cap);
+        o.listG = cv.take<int32_t>(cap);
+        o.rec_i = cv.take<int32_t>(cap * kRecI);
+        o.rec_d = cv.take<double>(cap * kRecD);
+        o.plan_node = cv.take<int32_t>(cap);
+        o.plan_off = cv.take<int32_t>(16 * cap);
+        o.plan_w = cv.take<double>(16 * cap);
+        o.plan_geo = cv.take<double>(6 * cap);
+        o.plan_mode = cv.take<int32_t>(cap);
+        o.plan_frec = cv.take<int32_t>(16 * cap);
+        o.plan_kappa = cv.take<double>(cap);
+        o.rmap = cv.take<int32_t>(cap);
+        o.tg_cnt = cv.take<int32_t>(std::max<size_t>(nslot, 1));
+        o.tg_t = cv.take<int32_t>(std::max<size_t>(nslot * stride, 1));
+        o.tg_rec = cv.take<int32_t>(std::max<size_t>(nslot * stride, 1));
+        o.tj_cnt = cv.take<int32_t>(std::max<size_t>(nslot, 1));
+        o.tj_rec = cv.take<int32_t>(std::max<size_t>(nslot * stride, 1));
+    }
     return (cv.off + kAlign - 1) / kAlign * kAlign;
 }
 
@@ -742,8 +786,11 @@ void motion_kin(const ibm_ctx *c, double t, double &disp, double &vel, double &a
     acc = -w * w * c->mo.amp * std::cos(w * t + c->mo.phase);
 }
 
-int do_classify(ibm_ctx *c, double t, hipStream_t s)
+// Pose the body at t and classify into buffer k on stream s (ray parity,
+// tags, lists, records, near-tile lists).
+int classify_buf(ibm_ctx *c, int k, double t, hipStream_t s)
 {
+    IB &ib = c->ibb[k];
     hipError_t e = hipSuccess;
     if (c->mo.on && c->b.nvert > 0) {
         double disp, vel, acc;
@@ -772,22 +819,36 @@ int do_classify(ibm_ctx *c, double t, hipStream_t s)
         if (e != hipSuccess)
             return dev_err(c, e, "pose");
     }
-    if (c->b.nfacet == 0) {
-        c->classified = true;
-        return IBM_OK;
+    c->buf_ok[k] = false;
+    if (c->b.nfacet > 0) {
+        e = launch_classify(c->g, c->b, ib, s);
+        if (e != hipSuccess)
+            return dev_err(c, e, "classify");
+        e = launch_records(c->g, c->b, c->f, ib, s);
+        if (e != hipSuccess)
+            return dev_err(c, e, "records");
+        e = launch_ghost_lists(c->g, ib, c->f.family == IBM_IB_QUADRATIC, c->corner_lists, s);
+        if (e != hipSuccess)
+            return dev_err(c, e, "ghost lists");
     }
-    e = launch_classify(c->g, c->b, c->ib, s);
-    if (e != hipSuccess)
-        return dev_err(c, e, "classify");
-    e = launch_records(c->g, c->b, c->f, c->ib, s);
-    if (e != hipSuccess)
-        return dev_err(c, e, "records");
-    e = launch_ghost_lists(c->g, c->ib, c->f.family == IBM_IB_QUADRATIC, c->corner_lists, s);
-    if (e != hipSuccess)
-        return dev_err(c, e, "ghost lists");
+    c->buf_ok[k] = true;
+    c->buf_t[k] = t;
+    c->buf_side[k] = false;
+    return IBM_OK;
+}
+
+// Classify at t into the current buffer, on the caller's stream.
+int do_classify(ibm_ctx *c, double t, hipStream_t s)
+{
+    int rc = classify_buf(c, c->cur, t, s);
+    c->ib = c->ibb[c->cur];
+    if (rc)
+        return rc;
     c->classified = true;
     return IBM_OK;
 }
+
+
 
 int do_fill(ibm_ctx *c, double *q, double t, hipStream_t s)
 {
@@ -973,6 +1034,7 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
         f.uc2 = std::max(f.uinf2, std::max(bb * bb, cc * cc));
     }
     IB &ib = x->ib;
+    ib.counts_other = nullptr;
     for (int s = 0; s < 6; ++s)
         ib.region[s] = h.region[s];
     ib.rw = h.region[1] - h.region[0];
@@ -1010,6 +1072,15 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     ib.tj_rec = L.tj_rec;
     ib.nslot = (int)h.tiles_near.size();
     ib.tg_stride = tile_load_cells(nd);
+    x->nbuf = 1;
+    x->cur = 0;
+    x->pipeline = true;
+    x->side = nullptr;
+    x->ev_fork = x->ev_ready[0] = x->ev_ready[1] = nullptr;
+    for (int k = 0; k < 2; ++k) {
+        x->buf_ok[k] = x->buf_side[k] = false;
+        x->buf_t[k] = 0.0;
+    }
     {
         std::vector<int32_t> ts(h.tiles_far.size() + h.tiles_near.size(), -1);
         for (size_t m = 0; m < h.tiles_near.size(); ++m)
@@ -1043,6 +1114,37 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     if (e == hipSuccess) e = up(L.tiles, list);
     if (e == hipSuccess) e = hipMemset(L.cls, IBM_FLUID, (size_t)h.ncell);
     if (e == hipSuccess) e = hipMemset(L.counts, 0, sizeof(int32_t) * CNT_WORDS);
+    x->ibb[0] = x->ib;
+    if (L.has_out2) {
+        const Layout::Out2 &o = L.out2;
+        IB b2 = x->ib;
+        b2.cls = o.cls;
+        b2.counts = o.counts;
+        b2.listF = o.listF;
+        b2.listG = o.listG;
+        b2.rec_i = o.rec_i;
+        b2.rec_d = o.rec_d;
+        b2.plan_node = o.plan_node;
+        b2.plan_off = o.plan_off;
+        b2.plan_w = o.plan_w;
+        b2.plan_geo = o.plan_geo;
+        b2.plan_mode = o.plan_mode;
+        b2.plan_frec = o.plan_frec;
+        b2.plan_kappa = o.plan_kappa;
+        b2.rmap = o.rmap;
+        b2.tg_cnt = o.tg_cnt;
+        b2.tg_t = o.tg_t;
+        b2.tg_rec = o.tg_rec;
+        b2.tj_cnt = o.tj_cnt;
+        b2.tj_rec = o.tj_rec;
+        b2.counts_other = x->ib.counts;
+        x->ibb[1] = b2;
+        x->ibb[0].counts_other = o.counts;
+        x->ib = x->ibb[0];
+        x->nbuf = 2;
+        if (e == hipSuccess) e = hipMemset(o.cls, IBM_FLUID, (size_t)h.ncell);
+        if (e == hipSuccess) e = hipMemset(o.counts, 0, sizeof(int32_t) * CNT_WORDS);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     x->mo.on = c->motion != 0;
     x->mo.axis = c->motion ? (int)c->motion_par[0] : 0;
@@ -1121,6 +1223,15 @@ void ibm_destroy(ibm_ctx *c)
         return;
     drop_graph(c);
     drop_timing(c);
+    if (c->side) {
+        (void)hipStreamSynchronize(c->side);
+        (void)hipStreamDestroy(c->side);
+    }
+    if (c->ev_fork)
+        (void)hipEventDestroy(c->ev_fork);
+    for (int k = 0; k < 2; ++k)
+        if (c->ev_ready[k])
+            (void)hipEventDestroy(c->ev_ready[k]);
     if (c->cap_stream)
         (void)hipStreamDestroy(c->cap_stream);
     delete c;
@@ -1138,6 +1249,11 @@ int ibm_set_option(ibm_ctx *c, int option, int value)
     if (option == IBM_OPT_CORNER_LISTS) {
         c->corner_lists = value != 0;
         c->classified = false;  // the lists are rebuilt by the next classification
+        c->buf_ok[0] = c->buf_ok[1] = false;
+        return IBM_OK;
+    }
+    if (option == IBM_OPT_PIPELINE) {
+        c->pipeline = value != 0;
         return IBM_OK;
     }
     if (option == IBM_OPT_STAGE_TIMING) {
@@ -1163,6 +1279,7 @@ int ibm_set_time(ibm_ctx *c, double t)
     if (!c || !std::isfinite(t))
         return IBM_EINVAL;
     c->t = t;
+    c->buf_ok[0] = c->buf_ok[1] = false;
     return IBM_OK;
 }
 
@@ -1272,6 +1389,20 @@ void take_timing_pair(ibm_ctx *c, hipEvent_t &e0, hipEvent_t &e1)
     e0 = c->tev[2 * c->tev_used];
     e1 = c->tev[2 * c->tev_used + 1];
     ++c->tev_used;
+}
+
+// The side stream and events of the classification pipeline (created on
+// first use, on the context's device, default priority).
+int ensure_side(ibm_ctx *c)
+{
+    if (c->side)
+        return IBM_OK;
+    hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k)
+        e = hipEventCreateWithFlags(&c->ev_ready[k], hipEventDisableTiming);
+    return dev_err(c, e, "pipeline stream");
 }
 
 // One stage is one launch on the stream.  With a body it runs the tile list,
@@ -1557,9 +1688,44 @@ int ibm_advance(ibm_ctx *c, double *q, int nsteps, void *stream)
         bool rk = c->f.scheme == IBM_RK3;
         // moving bodies are posed at t^n (RK3) or t^{n+1} (dual time)
         double tpose = rk ? c->t : c->t + dt;
-        if (c->mo.on || !c->classified)
-            if ((rc = do_classify(c, tpose, s)))
+        int nxt = -1;
+        if (c->mo.on) {
+            // this step's classification: prefetched by the previous step on
+            // the side stream (wait for it), or done now on the stream
+            int k = c->cur;
+            if (c->buf_ok[k] && c->buf_t[k] == tpose) {
+                if (c->buf_side[k]) {
+                    if ((rc = dev_err(c, hipStreamWaitEvent(s, c->ev_ready[k], 0), "pipeline join")))
+                        return rc;
+                    c->buf_side[k] = false;
+                }
+                c->ib = c->ibb[k];
+                c->classified = true;
+            } else if ((rc = do_classify(c, tpose, s))) {
                 return rc;
+            }
+            // the next step's, into the other buffer, while this step's stages
+            // run: the side stream starts once this step's classification
+            // is ready (and with it the stages of the previous step, the last
+            // readers of the other buffer, are done)
+            if (c->nbuf == 2 && c->pipeline && n + 1 < nsteps) {
+                if ((rc = ensure_side(c)))
+                    return rc;
+                nxt = k ^ 1;
+                hipError_t e = hipEventRecord(c->ev_fork, s);
+                if (e == hipSuccess)
+                    e = hipStreamWaitEvent(c->side, c->ev_fork, 0);
+                if ((rc = dev_err(c, e, "pipeline fork")))
+                    return rc;
+                if ((rc = classify_buf(c, nxt, tpose + dt, c->side)))
+                    return rc;
+                if ((rc = dev_err(c, hipEventRecord(c->ev_ready[nxt], c->side), "pipeline event")))
+                    return rc;
+                c->buf_side[nxt] = true;
+            }
+        } else if (!c->classified && (rc = do_classify(c, tpose, s))) {
+            return rc;
+        }
         int first = !rk && c->step == 0;
         int k = 1;
         // stationary bodies: the shared batched path on prepared arguments
@@ -1593,6 +1759,8 @@ int ibm_advance(ibm_ctx *c, double *q, int nsteps, void *stream)
         c->t += k * dt;
         c->step += k;
         n += k;
+        if (nxt >= 0)
+            c->cur = nxt;
     }
     return IBM_OK;
 }

@@ -79,6 +79,9 @@ struct IB {
     uint8_t *inside;         // inside flag per region cell
     uint32_t *toggle;        // crossing toggles per region row
     int32_t *counts;         // CNT_* words
+    // the other classification buffer's counts (null with one buffer): the
+    // sticky status bits are set in both, so either buffer's word is whole
+    int32_t *counts_other;
     int32_t *blk;            // per-block counts for the compaction scan (2 * nblk)
     int nblk;
     int32_t *listF, *listG;
@@ -112,6 +115,14 @@ struct IB {
     int32_t *tj_rec;           // nslot * tg_stride
     int nslot, tg_stride;
 };
+
+// Set sticky status bits (ST_*) in the counts of every classification buffer.
+__device__ inline void raise_status(const IB &ib, int32_t *counts, int bits)
+{
+    atomicOr(&counts[CNT_STATUS], bits);
+    if (ib.counts_other)
+        atomicOr(&ib.counts_other[CNT_STATUS], bits);
+}
 
 // Tiles of the fused residual/update kernel: cells per block along x, y, z.
 constexpr int kTile2[3] = {16, 15, 1};  // 255 x-faces, 256 y-faces: one pass each

@@ -1088,7 +1088,7 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
                 bad |= !(qv > 0.0);
         }
         if (bad)
-            atomicOr(&A.counts[CNT_STATUS], ST_NONFINITE);
+            raise_status(A.ib, A.counts, ST_NONFINITE);
         return;
     }
     // MODE_DUAL: point-implicit preconditioned pseudo-time step, FP64
@@ -1218,7 +1218,7 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
             bad |= !isfinite(v);
         }
         if (bad)
-            atomicOr(&A.counts[CNT_STATUS], ST_NONFINITE);
+            raise_status(A.ib, A.counts, ST_NONFINITE);
     }
 }
 

@@ -339,7 +339,7 @@ __global__ __launch_bounds__(1024) void scan_kernel(IB ib)
         }
         ib.counts[t == 0 ? CNT_F : CNT_G] = run;
         if (run > ib.cap)
-            atomicOr(&ib.counts[CNT_STATUS], ST_CAPACITY);
+            raise_status(ib, ib.counts, ST_CAPACITY);
     }
     __syncthreads();
     for (int l = 0; l < 2; ++l) {
