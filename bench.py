@@ -80,7 +80,8 @@ COUNTERS = {
 }
 KERNEL_NAME = {
     (3, "rk3", "mixed"): "step_ghost_kernel_3f<RK3> (stage launch with inline IB fill)",
-    (3, "rk3", "fp64"): "step_ghost_kernel<3, double, RK3> (stage launch with inline IB fill)",
+    (3, "rk3", "fp64"): "step_dir_kernel_3d<RK3> over every tile, after forcing_fill_kernel<3> and "
+                        "ghost_fill_kernel<3> on the stage input (the stage time spans the three launches)",
     (2, "rk3", "mixed"): "step_batch_kernel_2f<RK3, true> (stage launch with inline IB fill)",
     (2, "rk3", "fp64"): "step_batch_kernel<2, double, RK3, true> (stage launch with inline IB fill)",
     (2, "dual", "mixed"): "step_batch_kernel_2f<DUAL, true> (pseudo-iteration with inline IB fill)",
@@ -231,6 +232,18 @@ def run_case(case, precision, steps, warmup, timed_stages=True):
         s.set_stage_timing(0)
         stages = {"avg_ms": tot / n, "launches": n, "min_ms": lo, "max_ms": hi,
                   "where": "timed region" if moving else "2 eager steps after the timed region"}
+        if moving:
+            # the same launches without the next step's classification
+            # running beside them (pipelining off for 4 steps)
+            s.set_pipeline(False)
+            s.set_stage_timing(4 * per)
+            s.advance(4)
+            tot, n, lo, hi = s.stage_timing()
+            s.set_stage_timing(0)
+            s.set_pipeline(True)
+            stages["isolated_avg_ms"] = tot / n
+            stages["isolated_note"] = ("4 steps after the timed region with the next step's classification "
+                                       "not overlapped; in the timed region it runs beside the stages")
     torch.cuda.synchronize()
     done = {"cell_updates_per_s": case.ncells * per * steps / wall, "ms_per_step": wall * 1e3 / steps,
             "event_ms_per_step": ev_ms / steps, "steps": steps, "warmup": warmup}
@@ -614,7 +627,9 @@ def main():
     for prec in [p for p in args.precisions.split(",") if p]:
         s, done, stages = run_case(case, prec, args.steps, args.warmup)
         roof, other = roofline(case, prec, stages["avg_ms"], "C4")
+        iso, _ = roofline(case, prec, stages["isolated_avg_ms"], "C4")
         done["stage_kernel"] = stages
+        done["roofline_isolated"] = {k: iso[k] for k in ("bound", "achieved", "peak", "unit", "frac", "kernel_avg_ms")}
         res[prec] = (done, roof, other)
         prims[prec] = s.to_prim()
         done["forces"] = surface_forces(s, 4.0)
@@ -632,12 +647,14 @@ def main():
                                "M=0.2, Re=185, SSP-RK3, IDW/image-point IB, reclassified every step",
                    "cells": ncell, "cell_updates_per_step": case.evals_per_step * ncell, "precision": head},
         "roofline": roof, "roofline_other": other,
+        "roofline_isolated": r["roofline_isolated"],
         "stage_kernel": r["stage_kernel"], "forces": r["forces"],
     }
     if "fp64" in res and "mixed" in res:
         f, froof, fother = res["fp64"]
         out["fp64"] = {"value": f["cell_updates_per_s"], "ms_per_step": f["ms_per_step"],
-                       "stage_kernel": f["stage_kernel"], "roofline": froof, "forces": f["forces"]}
+                       "stage_kernel": f["stage_kernel"], "roofline": froof,
+                       "roofline_isolated": f["roofline_isolated"], "forces": f["forces"]}
         out["mixed_speedup_vs_fp64"] = f["ms_per_step"] / r["ms_per_step"]
         out["mixed_vs_fp64_rel_l2"] = mixed_error(prims["mixed"], prims["fp64"], case.ndim, case.p_inf)
     del prims

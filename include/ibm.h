@@ -266,7 +266,9 @@ int ibm_info_get(const ibm_ctx *ctx, ibm_info *out);
 /* IBM_OPT_STAGE_TIMING (default 0): value n > 0 makes the next n stage
  * launches of ibm_advance (each RK3 stage or dual-time pseudo-iteration of
  * the fused residual-and-update kernel, section 2) record HIP events at
- * their start and end, read back by ibm_stage_timing; while it is on, steps
+ * their start and end (a 3D FP64 stage with a body: from the start of its
+ * two fill launches to the end of its stage kernel), read back by
+ * ibm_stage_timing; while it is on, steps
  * are enqueued eagerly (no graph replay).  0 turns it off.  At most
  * IBM_STAGE_TIMING_MAX.  Changing it discards unread timings. */
 #define IBM_OPT_STAGE_TIMING 3
@@ -294,10 +296,12 @@ int ibm_stage_timing(ibm_ctx *ctx, float *total_ms, int *launches, float *min_ms
  * one dual-time pseudo-iteration (stage 0, BDF2 coefficients), measured with
  * HIP events around nrep launches on stream.  It is the kernel a step
  * launches, on the same tiles: with a body, the tile list whose near tiles
- * fill the IB nodes they read (body at the context time).  d_q is the input;
- * the output goes to the context's scratch stage buffer, so neither d_q nor
- * the solve's dual-time history changes.  Dual time needs one advanced step
- * first (IBM_EINVAL otherwise).  Synchronises. */
+ * fill the IB nodes they read (body at the context time); for a 3D FP64
+ * solve with a body, the two fill launches on a copy of d_q in the
+ * context's scratch, then the kernel over every tile (the time spans the
+ * three).  d_q is the input; the output goes to the context's scratch stage
+ * buffer, so neither d_q nor the solve's dual-time history changes.  Dual
+ * time needs one advanced step first (IBM_EINVAL otherwise).  Synchronises. */
 int ibm_time_update_kernel(ibm_ctx *ctx, const double *d_q, int stage, int nrep, void *stream,
                            float *avg_ms);
 

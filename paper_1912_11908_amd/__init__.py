@@ -219,6 +219,12 @@ class Solver:
                    "ibm_read_counts", self.h)
         return out
 
+    def set_pipeline(self, on):
+        """Classify a prescribed-motion solve's next step on a side stream
+        during the current step's stages (default), or each step before its
+        stages."""
+        _lib.check(self.L.ibm_set_option(self.h, 4, 1 if on else 0), "ibm_set_option", self.h)
+
     def set_stage_timing(self, launches):
         """Time the next `launches` stage launches of advance() with HIP
         events (0: off; steps then replay as graphs again)."""

@@ -33,6 +33,12 @@ struct ibm_ctx {
     // chunks, near tiles spread over them first, padded with -1
     const int32_t *tiles;
     int ntiles;
+    // 3D FP64 with a body: each stage fills the IB nodes of its input in
+    // place (standalone fill kernels), then runs the kernel that stages one
+    // face direction at a time over every tile
+    bool prefill;
+    double *slot_qin[kSlots];  // stage input of each batched launch slot (prefill)
+    double *qfill;             // kernel timing of a prefill solve: filled copy of the input
     double *fpart;           // surface force block sums
     int32_t *fmissed;        // surface force: facets without a valid centre
     double *fforce;          // surface force of a free body's step (device, 3)
@@ -646,8 +652,17 @@ struct Layout {
     bool has_out2;
     int32_t *tiles;
     char *args;
-    double *q1, *q2, *wtmp, *qn, *qnm1;
+    double *q1, *q2, *wtmp, *qn, *qnm1, *qfill;
 };
+
+// 3D FP64 solves with a body fill the IB nodes of each stage input in place
+// with the standalone fill launches, then run the kernel that stages one
+// face direction at a time over every tile: its 72 KB of LDS leave room for
+// two blocks per CU, the 122 KB FP64 tile of the inline fill for one.
+bool prefill_solve(int nd, int precision, int nfacet, int cap)
+{
+    return nd == 3 && precision == IBM_FP64 && nfacet > 0 && cap > 0;
+}
 
 size_t carve(const ibm_case *c, const HostGeom &h, char *base, Layout &L)
 {
@@ -717,7 +732,7 @@ size_t carve(const ibm_case *c, const HostGeom &h, char *base, Layout &L)
     L.tiles = cv.take<int32_t>(h.tiles_far.size() + h.tiles_near.size() + 16);
     L.args = cv.take<char>(kSlots * stage_args_bytes());
     size_t st = (size_t)h.vs * (nd + 2);
-    L.q1 = L.q2 = L.wtmp = L.qn = L.qnm1 = nullptr;
+    L.q1 = L.q2 = L.wtmp = L.qn = L.qnm1 = L.qfill = nullptr;
     if (c->scheme == IBM_RK3) {
         L.q1 = cv.take<double>(st);
         L.q2 = cv.take<double>(st);
@@ -725,6 +740,8 @@ size_t carve(const ibm_case *c, const HostGeom &h, char *base, Layout &L)
         L.wtmp = cv.take<double>(st);
         L.qn = cv.take<double>((size_t)h.ncell * (nd + 2));
         L.qnm1 = cv.take<double>((size_t)h.ncell * (nd + 2));
+        if (prefill_solve(nd, c->precision, c->nfacet, h.cap))
+            L.qfill = cv.take<double>(st);
     }
     L.has_out2 = c->motion == 1 && c->nfacet > 0 && h.cap > 0;
     L.out2 = {};
@@ -1187,6 +1204,10 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
         x->slot_nblk[k] = 0;
     x->tiles = L.tiles;
     x->ntiles = (int)list.size();
+    x->prefill = prefill_solve(nd, x->f.precision, c->nfacet, h.cap);
+    x->qfill = x->prefill ? (x->f.scheme == IBM_RK3 ? L.q2 : L.qfill) : nullptr;
+    for (int k = 0; k < kSlots; ++k)
+        x->slot_qin[k] = nullptr;
     x->tev_used = 0;
     if (e != hipSuccess) {
         delete x;
@@ -1405,8 +1426,19 @@ int ensure_side(ibm_ctx *c)
     return dev_err(c, e, "pipeline stream");
 }
 
+// The tile lists of a stage launch with a body (the body moving along
+// `axis` at vel, acc; axis -1 when stationary).
+StagePart stage_part(const ibm_ctx *c, double vel, double acc, int axis)
+{
+    StagePart p{c->tiles, c->ntiles, vel, acc, axis};
+    p.prefill = c->prefill;
+    return p;
+}
+
 // One stage is one launch on the stream.  With a body it runs the tile list,
 // whose near tiles fill the IB nodes they read; without one, every tile.
+// (3D FP64 with a body: the two standalone fill launches on the stage input,
+// then every tile.)
 template <typename Launch> int enqueue_stage(ibm_ctx *c, double t, hipStream_t s, Launch launch)
 {
     if (c->b.nfacet == 0 || c->ib.cap == 0)
@@ -1417,7 +1449,7 @@ template <typename Launch> int enqueue_stage(ibm_ctx *c, double t, hipStream_t s
         motion_kin(c, t, disp, vel, acc);
         axis = c->mo.axis;
     }
-    StagePart p{c->tiles, c->ntiles, vel, acc, axis};
+    StagePart p = stage_part(c, vel, acc, axis);
     take_timing_pair(c, p.ev_start, p.ev_stop);
     return dev_err(c, launch(s, &p), "stage");
 }
@@ -1477,13 +1509,19 @@ int prepare_batch(ibm_ctx *c, double *q, hipStream_t s)
     size_t nb = stage_args_bytes();
     c->h_args.assign(kSlots * nb, 0);
     bool body = c->b.nfacet > 0 && c->ib.cap > 0;
-    StagePart p{c->tiles, c->ntiles, 0.0, 0.0, -1};
-    // launch 0 of a stage is the plain kernel (solves without a body), launch
-    // 1 the kernel with the inline IB fill (solves with one)
+    StagePart p = stage_part(c, 0.0, 0.0, -1);
+    if (c->prefill) {
+        p.tiles = nullptr;
+        p.ntiles = 0;
+    }
+    // launch 0 of a stage is the plain kernel (solves without a body, and
+    // 3D FP64 ones with a body after the fill of their input, c->slot_qin),
+    // launch 1 the kernel with the inline IB fill (other solves with a body)
     auto put = [&](int slot, int launch, double *qin, const double *qn, const double *qnm1, double *out,
                    double a, double b) {
         const StagePart *part = body ? &p : nullptr;
-        if (body != (launch == 1)) {
+        c->slot_qin[slot] = qin;
+        if ((body && !c->prefill) != (launch == 1)) {
             c->slot_nblk[slot] = 0;
             return;
         }
@@ -1523,28 +1561,42 @@ int enqueue_group_step(ibm_ctx *const *ctx, double *const *q, const std::vector<
     const ibm_ctx *c0 = ctx[gp[0]];
     int nd = c0->g.ndim, prec = c0->f.precision, scheme = c0->f.scheme;
     size_t nb = stage_args_bytes();
-    std::vector<const void *> args;
-    std::vector<int> nblk;
+    std::vector<const void *> args[2];
+    std::vector<int> nblk[2];
     auto run = [&](auto slot_of) -> int {
+        int tot[2] = {0, 0};
         for (int l = 0; l < 2; ++l) {
-            args.clear();
-            nblk.clear();
+            args[l].clear();
+            nblk[l].clear();
             for (int m : gp) {
                 int slot = slot_of(ctx[m]);
                 if (slot < 0)
                     continue;
-                args.push_back(static_cast<char *>(ctx[m]->d_args) + (slot + l) * nb);
-                nblk.push_back(ctx[m]->slot_nblk[slot + l]);
+                args[l].push_back(static_cast<char *>(ctx[m]->d_args) + (slot + l) * nb);
+                nblk[l].push_back(ctx[m]->slot_nblk[slot + l]);
+                tot[l] += std::max(ctx[m]->slot_nblk[slot + l], 0);
             }
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            int tot = 0;
-            for (int b : nblk)
-                tot += b > 0 ? b : 0;
-            // the stage timer of a single solve times its stage launches
-            if (gp.size() == 1 && tot > 0)
-                take_timing_pair(ctx[gp[0]], e0, e1);
-            hipError_t e = launch_stage_batch(nd, prec, scheme, l == 1, (int)args.size(), args.data(), nblk.data(), s,
-                                              e0, e1);
+        }
+        // the stage timer of a single solve times each stage: from the start
+        // of its first non-empty launch (a prefill solve's fill) to the end
+        // of its last
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (gp.size() == 1 && tot[0] + tot[1] > 0)
+            take_timing_pair(ctx[gp[0]], e0, e1);
+        int first = tot[0] > 0 ? 0 : 1, last = tot[1] > 0 ? 1 : 0;
+        for (int m : gp) {
+            const ibm_ctx *c = ctx[m];
+            int slot = slot_of(c);
+            if (slot < 0 || !c->prefill || c->slot_nblk[slot] <= 0)
+                continue;
+            hipError_t e = launch_ib_fill(c->g, c->f, c->ib, c->slot_qin[slot], 0.0, 0.0, -1, s, e0);
+            if (e != hipSuccess)
+                return dev_err(ctx[gp[0]], e, "stage fill");
+            e0 = nullptr;
+        }
+        for (int l = 0; l < 2; ++l) {
+            hipError_t e = launch_stage_batch(nd, prec, scheme, l == 1, (int)args[l].size(), args[l].data(),
+                                              nblk[l].data(), s, l == first ? e0 : nullptr, l == last ? e1 : nullptr);
             if (e != hipSuccess)
                 return dev_err(ctx[gp[0]], e, "batched stage");
         }
@@ -1922,6 +1974,8 @@ int ibm_time_update_kernel(ibm_ctx *c, const double *q, int stage, int nrep, voi
     // at the context time), else every tile.  d_q is only read; the output
     // goes to a scratch stage buffer (the filled FORCING corner values to
     // their scratch slots)
+    // (3D FP64 with a body: the fill launches on a copy of d_q, c->qfill,
+    // then the plain kernel over every tile, as in the step)
     size_t nb = stage_args_bytes();
     std::vector<char> h(nb);
     double *qm = const_cast<double *>(q);
@@ -1929,17 +1983,30 @@ int ibm_time_update_kernel(ibm_ctx *c, const double *q, int stage, int nrep, voi
     double disp = 0.0, vel = 0.0, acc = 0.0;
     if (c->mo.on)
         motion_kin(c, c->t, disp, vel, acc);
-    StagePart p{c->tiles, c->ntiles, vel, acc, c->mo.on ? c->mo.axis : -1};
+    int axis = c->mo.on ? c->mo.axis : -1;
+    StagePart p = stage_part(c, vel, acc, axis);
     const StagePart *part = body ? &p : nullptr;
+    if (c->prefill) {
+        p.tiles = nullptr;
+        p.ntiles = 0;
+        qm = c->qfill;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(qm, q, sizeof(double) * (size_t)c->g.vs * c->g.nv, hipMemcpyDeviceToDevice, s);
+    }
     int nblk = rk ? stage_args(c->g, c->f, c->ib, qm, q, nullptr, c->q1, A[stage], B[stage], part, h.data())
                   : stage_args(c->g, c->f, c->ib, qm, c->qn, c->qnm1, c->wtmp, 1.5, 0.5, part, h.data());
     const void *d = static_cast<char *>(c->d_args) + (kSlots - 1) * nb;
+    bool ghosts = body && !c->prefill;
     if (e == hipSuccess)
         e = hipMemcpyAsync(const_cast<void *>(d), h.data(), nb, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipEventRecord(e0, s);
-    for (int r = 0; r < nrep && e == hipSuccess; ++r)
-        e = launch_stage_batch(c->g.ndim, c->f.precision, c->f.scheme, body, 1, &d, &nblk, s);
+    for (int r = 0; r < nrep && e == hipSuccess; ++r) {
+        if (c->prefill)
+            e = launch_ib_fill(c->g, c->f, c->ib, qm, vel, acc, axis, s, nullptr);
+        if (e == hipSuccess)
+            e = launch_stage_batch(c->g.ndim, c->f.precision, c->f.scheme, ghosts, 1, &d, &nblk, s);
+    }
     if (e == hipSuccess)
         e = hipEventRecord(e1, s);
     if (e == hipSuccess)

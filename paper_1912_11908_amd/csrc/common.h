@@ -141,6 +141,10 @@ struct StagePart {
     // when set, the launch records these events at its start and end (stage
     // timing); null otherwise
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+    // 3D FP64: the stage fills the IB nodes of its input in place (the
+    // standalone fill launches), then runs the plain kernel over every tile;
+    // `tiles` is then unused
+    bool prefill = false;
 };
 
 struct Motion {
@@ -175,6 +179,11 @@ int tile_load_cells(int ndim);
 
 // flow.hip
 hipError_t launch_domain_bc(const Grid &g, const Flow &f, double *q, hipStream_t s);
+// The IB nodes of q filled in place: FORCING nodes, then the ghost layers
+// that read them (two launches; ev_start, when set, records the start of the
+// first).
+hipError_t launch_ib_fill(const Grid &g, const Flow &f, const IB &ib, double *q, double ub_axis, double ab_axis,
+                          int axis, hipStream_t s, hipEvent_t ev_start);
 hipError_t launch_bc_fill(const Grid &g, const Flow &f, const IB &ib, double *q, double ub_axis,
                           double ab_axis, int axis, hipStream_t s);
 hipError_t launch_residual(const Grid &g, const Flow &f, const IB &ib, const double *q, double *r,

@@ -531,6 +531,7 @@ __device__ inline void weno5_pair(R v0, R v1, R v2, R v3, R v4, R v5, R &wl, R &
 
 template <typename R> struct FlowR {
     R gamma, gm1inv, pinf, mu, kc, uc2, uinf2;
+    R rR;  // 1 / R (R = p_inf)
     bool precond;
     bool tvd;  // second-order TVD faces instead of WENO5
 };
@@ -658,7 +659,9 @@ template <typename Real> __device__ inline Real metric(const double *d64, const 
 // Flux through the face between tile-local cells L (LDS index `base`) and
 // L + e_D: WENO5 face states, LDFSS, minus the central viscous flux.
 // gc: global coordinates of L.
-template <int DIM, int D, typename Real, int LX, int LY, int LCELLS>
+// TDER: the staging holds (rho', u.., p') only and T' = (p' - R rho') /
+// (R (1 + rho')) is formed at the two cells of the face (p_inf = R).
+template <int DIM, int D, typename Real, int LX, int LY, int LCELLS, bool TDER = false>
 __device__ inline void face_flux(const Real *__restrict__ S, int base, const int *gc, const Grid &g,
                                  const FlowR<Real> &fp, Real *flux)
 {
@@ -681,7 +684,7 @@ __device__ inline void face_flux(const Real *__restrict__ S, int base, const int
     // normal derivatives from the two cells, tangential ones the mean of the
     // two cells' central differences, face velocity the mean of the cells
     const Real *SU = S + LCELLS;
-    const Real *ST = S + (DIM + 2) * LCELLS;
+    const Real *ST = S + (TDER ? 0 : (DIM + 2) * LCELLS);
     Real rdn = metric<Real>(g.rdxc[D], g.rdxc_f[D], gc[D] + 3);
     Real dudn[DIM], uf[DIM];
 #pragma unroll
@@ -690,7 +693,15 @@ __device__ inline void face_flux(const Real *__restrict__ S, int base, const int
         dudn[m] = (uR - uL) * rdn;
         uf[m] = Real(0.5) * (uL + uR);
     }
-    Real dTdn = (ST[base + SD] - ST[base]) * rdn;
+    Real dTdn;
+    if constexpr (TDER) {
+        const Real *SR = S, *SP = S + (DIM + 1) * LCELLS;
+        Real tL = (SP[base] - fp.pinf * SR[base]) * fp.rR * rcp_fast<Real>(Real(1) + SR[base]);
+        Real tR = (SP[base + SD] - fp.pinf * SR[base + SD]) * fp.rR * rcp_fast<Real>(Real(1) + SR[base + SD]);
+        dTdn = (tR - tL) * rdn;
+    } else {
+        dTdn = (ST[base + SD] - ST[base]) * rdn;
+    }
     Real div = dudn[D];
     Real tau[DIM];
 #pragma unroll
@@ -744,6 +755,194 @@ __device__ inline void face_pass(const Real *__restrict__ S, Real *__restrict__ 
 #pragma unroll
         for (int m = 0; m < NV; ++m)
             F[m * NFACE + off + fi] = flux[m];
+    }
+}
+
+// 3. per-cell residual and update, one thread per tile cell: FLUID cells
+// take the RK3 stage or the dual-time pseudo step (FP64), IB nodes keep
+// their filled value (written by the inline fill, or copied), SOLID cells
+// their state; residual mode writes R.
+template <int DIM, typename Real, int MODE, bool INLINE_GHOSTS>
+__device__ __forceinline__ void update_cell(const StepArgs &__restrict__ A, bool own, uint8_t cls, const double *qc,
+                                            const Real *racc, long long cell, long long s_own, int i, int j, int k)
+{
+    constexpr int NV = DIM + 2;
+    const Grid &g = A.g;
+    const Flow &f = A.f;
+    if (!own)
+        return;
+    long long s = s_own;
+    if (MODE != MODE_RESID) {
+        if (cls != IBM_FLUID) {  // IB nodes carry their filled value, solid cells their state
+            if (INLINE_GHOSTS && cls >= IBM_FORCING && cls <= IBM_G3)
+                return;  // written by the inline fill
+#pragma unroll
+            for (int m = 0; m < NV; ++m)
+                A.out[s + m * g.vs] = qc[m];
+            return;
+        }
+    } else if (cls != IBM_FLUID) {
+#pragma unroll
+        for (int m = 0; m < NV; ++m)
+            A.out[m * g.ncell + cell] = 0.0;
+        return;
+    }
+    double R[NV];
+#pragma unroll
+    for (int m = 0; m < NV; ++m)
+        R[m] = (double)racc[m];
+    R[NV - 1] += f.Hinf * R[0];
+
+    if (MODE == MODE_RESID) {
+#pragma unroll
+        for (int m = 0; m < NV; ++m)
+            A.out[m * g.ncell + cell] = R[m];
+        return;
+    }
+    if (MODE == MODE_RK3) {
+        bool bad = false;
+#pragma unroll
+        for (int m = 0; m < NV; ++m) {
+            double qv = A.b * (qc[m] - f.dt * R[m]);
+            if (A.a != 0.0)
+                qv += A.a * A.qn[s + m * g.vs];
+            A.out[s + m * g.vs] = qv;
+            bad |= !isfinite(qv);
+            if (m == 0)
+                bad |= !(qv > 0.0);
+        }
+        if (bad)
+            raise_status(A.ib, A.counts, ST_NONFINITE);
+        return;
+    }
+    // MODE_DUAL: point-implicit preconditioned pseudo-time step, FP64
+    {
+        constexpr int N = NV;
+        double pp = qc[0], tp = qc[DIM + 1];
+        double u[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+            u[d] = qc[1 + d];
+        double p = f.pinf + pp, T = 1.0 + tp;
+        // reciprocals instead of divides (within an ulp or so)
+        double rTi = rcp_fast<double>(T);
+        double rho = p * f.rR * rTi;
+        double rhop = (pp - f.R * tp) * f.rR * rTi;  // rho - 1
+        double rrho = rcp_fast<double>(rho);
+        double q2 = 0.0;
+        for (int d = 0; d < DIM; ++d)
+            q2 += u[d] * u[d];
+        double a2 = f.gamma * p * rrho;
+        double ur2 = fmin(a2, fmax(q2, f.uc2));
+        double eps = ur2 * rcp_fast<double>(a2);
+        double nuv = f.mu * rrho * fmax(4.0 / 3.0, f.gamma / f.pr);
+        double lam = 0.0;
+        for (int d = 0; d < DIM; ++d) {
+            double rdx = g.rdx[d][(d == 0 ? i : d == 1 ? j : k) + 3];
+            double ud = u[d];
+            double up = 0.5 * (1.0 + eps) * fabs(ud);
+            double cpr = 0.5 * sqrt_fast<double>((1.0 - eps) * (1.0 - eps) * ud * ud + 4.0 * eps * a2);
+            lam += (up + cpr) * rdx + 2.0 * nuv * rdx * rdx;
+        }
+        double rdt = rcp_fast<double>(f.dt);
+        double b0 = A.a, b2 = A.b;
+        double cdt = b0 * rdt, ctau = lam * rcp_fast<double>(f.cfl_tau);
+        double rp = f.rR * rTi, rT = -rho * rTi;
+        double th = rcp_fast<double>(ur2) + rcp_fast<double>(f.cp * T);
+        // perturbation conserved vector of the current state
+        double Qp[N];
+        Qp[0] = rhop;
+        for (int d = 0; d < DIM; ++d)
+            Qp[1 + d] = rhop * u[d] + (u[d] - f.uinf[d]);
+        Qp[N - 1] = pp * f.gm1inv + 0.5 * (rhop * q2 + q2 - f.uinf2);
+        double rhs[N];
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            double qn = A.qn[m * g.ncell + cell], qm = A.qnm1[m * g.ncell + cell];
+            rhs[m] = -((b0 * (Qp[m] - qn) - b2 * (qn - qm)) * rdt + R[m]);
+        }
+        // energy row minus H times the mass row: exact row operation that
+        // removes the O(H) terms (H' = c_p T' + (|u|^2 - 1) / 2)
+        double H = f.cp * T + 0.5 * q2;
+        double Hp = f.cp * tp + 0.5 * (q2 - f.uinf2);
+        {
+            double qn0 = A.qn[cell], qm0 = A.qnm1[cell];
+            double qnE = A.qn[(N - 1) * g.ncell + cell], qmE = A.qnm1[(N - 1) * g.ncell + cell];
+            double bdf0 = b0 * (Qp[0] - qn0) - b2 * (qn0 - qm0);
+            double bdfE = b0 * (Qp[N - 1] - qnE) - b2 * (qnE - qmE);
+            double Rrho = R[0], REp = R[N - 1] - f.Hinf * R[0];
+            rhs[N - 1] = -((bdfE - H * bdf0) * rdt + (REp - Hp * Rrho));
+        }
+        double M[N][N];
+        for (int r = 0; r < N; ++r)
+            for (int c = 0; c < N; ++c)
+                M[r][c] = 0.0;
+        double cc = ctau + cdt;
+        M[0][0] = th * ctau + rp * cdt;
+        M[0][N - 1] = rT * cc;
+        for (int d = 0; d < DIM; ++d) {
+            M[1 + d][0] = u[d] * (th * ctau + rp * cdt);
+            M[1 + d][1 + d] = rho * cc;
+            M[1 + d][N - 1] = u[d] * rT * cc;
+            M[N - 1][1 + d] = rho * u[d] * cc;
+        }
+        M[N - 1][0] = -cc;
+        M[N - 1][N - 1] = rho * f.cp * cc;
+        (void)H;
+        // Gaussian elimination with partial pivoting; every index is fixed
+        // at compile time (row swaps by selects), so that the matrix stays
+        // in registers, and each pivot is inverted once
+        double dinv[N];
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+            int piv = c;
+            double big = fabs(M[c][c]);
+#pragma unroll
+            for (int r = c + 1; r < N; ++r)
+                if (fabs(M[r][c]) > big) {
+                    big = fabs(M[r][c]);
+                    piv = r;
+                }
+#pragma unroll
+            for (int r = c + 1; r < N; ++r) {
+                if (r == piv) {
+#pragma unroll
+                    for (int m = 0; m < N; ++m) {
+                        double t = M[c][m];
+                        M[c][m] = M[r][m];
+                        M[r][m] = t;
+                    }
+                    double t = rhs[c];
+                    rhs[c] = rhs[r];
+                    rhs[r] = t;
+                }
+            }
+            dinv[c] = rcp_fast<double>(M[c][c]);
+#pragma unroll
+            for (int r = c + 1; r < N; ++r) {
+                double fct = M[r][c] * dinv[c];
+#pragma unroll
+                for (int m = c; m < N; ++m)
+                    M[r][m] -= fct * M[c][m];
+                rhs[r] -= fct * rhs[c];
+            }
+        }
+#pragma unroll
+        for (int r = N - 1; r >= 0; --r) {
+            double sum = rhs[r];
+#pragma unroll
+            for (int m = r + 1; m < N; ++m)
+                sum -= M[r][m] * rhs[m];
+            rhs[r] = sum * dinv[r];
+        }
+        bool bad = false;
+        for (int m = 0; m < N; ++m) {
+            double v = qc[m] + rhs[m];
+            A.out[s + m * g.vs] = v;
+            bad |= !isfinite(v);
+        }
+        if (bad)
+            raise_status(A.ib, A.counts, ST_NONFINITE);
     }
 }
 
@@ -986,6 +1185,7 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
     fp.kc = (Real)f.kc;
     fp.uc2 = (Real)f.uc2;
     fp.uinf2 = (Real)f.uinf2;
+    fp.rR = (Real)f.rR;
     fp.precond = f.scheme == IBM_DUAL;
     fp.tvd = f.recon == IBM_RECON_TVD2;
     // 2. face fluxes, one pass per direction (compile-time direction)
@@ -1044,183 +1244,221 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
         }
     }
 
-    // 3. per-cell residual and update
-    if (!own)
-        return;
-    long long s = s_own;
-    if (MODE != MODE_RESID) {
-        if (cls != IBM_FLUID) {  // IB nodes carry their filled value, solid cells their state
-            if (INLINE_GHOSTS && cls >= IBM_FORCING && cls <= IBM_G3)
-                return;  // written by the inline fill
+    update_cell<DIM, Real, MODE, INLINE_GHOSTS>(A, own, cls, qc, racc, cell, s_own, i, j, k);
+}
+
+// ----------------------------- 3D FP64 stages staged one direction at a time
+// For tiles whose stencils never reach an IB node (the far tiles of a
+// launch with a body, every tile without one): the tile's cells are staged
+// in LDS one face direction at a time -- along it the three-cell WENO5 halo,
+// across it the one cell the tangential derivatives read -- with
+// (rho', u, v, w, p') only (T' follows from rho' and p').  That is about
+// half the cells of the full halo'd tile and five of its six variables, so
+// two 512-thread FP64 blocks share a CU (72 KB of LDS each) instead of one.
+template <int D> struct DirBox {
+    static constexpr int OX = D == 0 ? 3 : 1, OY = D == 1 ? 3 : 1, OZ = D == 2 ? 3 : 1;
+    static constexpr int LX = kTile3[0] + 2 * OX, LY = kTile3[1] + 2 * OY, LZ = kTile3[2] + 2 * OZ;
+    static constexpr int LCELLS = LX * LY * LZ;
+};
+constexpr int dir_cells_max()
+{
+    int a = DirBox<0>::LCELLS, b = DirBox<1>::LCELLS, c = DirBox<2>::LCELLS;
+    return a > b ? (a > c ? a : c) : (b > c ? b : c);
+}
+constexpr int kDirCells = dir_cells_max();
+constexpr int kDirFaces = 512;  // the most faces of a direction of the 8x7x8 tile
+static_assert((kTile3[0] + 1) * kTile3[1] * kTile3[2] <= kDirFaces && kTile3[0] * (kTile3[1] + 1) * kTile3[2] <= kDirFaces &&
+                  kTile3[0] * kTile3[1] * (kTile3[2] + 1) <= kDirFaces,
+              "face buffer");
+
+// Stage the box of direction D: state -> (rho', u, v, w, p') in FP64, domain
+// ghost cells resolved on the fly, two rounds of loads in flight.
+template <int D>
+__device__ __forceinline__ void load_dir(const StepArgs &__restrict__ A, double *__restrict__ S, int i0, int j0,
+                                         int k0, int tid)
+{
+    using B = DirBox<D>;
+    constexpr int NV = 5, NT = kThreads3;
+    constexpr int NR = (B::LCELLS + NT - 1) / NT;
+    const Grid &g = A.g;
+    const Flow &f = A.f;
+    for (int r0 = 0; r0 < NR; r0 += 2) {
+        double qv[2][NV];
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+            int t = tid + (r0 + rr) * NT;
+            if (r0 + rr >= NR || t >= B::LCELLS)
+                continue;
+            int lx = t % B::LX, ly = (t / B::LX) % B::LY, lz = t / (B::LX * B::LY);
+            int c[3] = {i0 + lx - B::OX, j0 + ly - B::OY, k0 + lz - B::OZ};
+            bool ff = ghost_source<3>(g, c);
+            if (ff) {
+#pragma unroll
+                for (int m = 0; m < NV; ++m)
+                    qv[rr][m] = A.fs.v[m];
+            } else {
+                long long s = sidx(g, c[0], c[1], c[2]);
+#pragma unroll
+                for (int m = 0; m < NV; ++m)
+                    qv[rr][m] = A.qin[s + m * g.vs];
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+            int t = tid + (r0 + rr) * NT;
+            if (r0 + rr >= NR || t >= B::LCELLS)
+                continue;
+            const double *v = qv[rr];
+            double w[NV];
+            if (f.scheme == IBM_RK3) {
+                double rho = v[0];
+                double ri = rcp_fast<double>(rho);
+                double ke = 0.0;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    w[1 + d] = v[1 + d] * ri;
+                    ke += w[1 + d] * w[1 + d];
+                }
+                w[0] = rho - 1.0;
+                w[4] = (f.gamma - 1.0) * (v[4] - 0.5 * rho * ke) - f.pinf;
+            } else {
+                double pp = v[0], tp = v[4];
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    w[1 + d] = v[1 + d];
+                w[0] = (pp - f.R * tp) * f.rR * rcp_fast<double>(1.0 + tp);
+                w[4] = pp;
+            }
 #pragma unroll
             for (int m = 0; m < NV; ++m)
-                A.out[s + m * g.vs] = qc[m];
-            return;
+                S[m * B::LCELLS + t] = w[m];
         }
-    } else if (cls != IBM_FLUID) {
-#pragma unroll
-        for (int m = 0; m < NV; ++m)
-            A.out[m * g.ncell + cell] = 0.0;
-        return;
-    }
-    double R[NV];
-#pragma unroll
-    for (int m = 0; m < NV; ++m)
-        R[m] = (double)racc[m];
-    R[NV - 1] += f.Hinf * R[0];
-
-    if (MODE == MODE_RESID) {
-#pragma unroll
-        for (int m = 0; m < NV; ++m)
-            A.out[m * g.ncell + cell] = R[m];
-        return;
-    }
-    if (MODE == MODE_RK3) {
-        bool bad = false;
-#pragma unroll
-        for (int m = 0; m < NV; ++m) {
-            double qv = A.b * (qc[m] - f.dt * R[m]);
-            if (A.a != 0.0)
-                qv += A.a * A.qn[s + m * g.vs];
-            A.out[s + m * g.vs] = qv;
-            bad |= !isfinite(qv);
-            if (m == 0)
-                bad |= !(qv > 0.0);
-        }
-        if (bad)
-            raise_status(A.ib, A.counts, ST_NONFINITE);
-        return;
-    }
-    // MODE_DUAL: point-implicit preconditioned pseudo-time step, FP64
-    {
-        constexpr int N = NV;
-        double pp = qc[0], tp = qc[DIM + 1];
-        double u[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int d = 0; d < DIM; ++d)
-            u[d] = qc[1 + d];
-        double p = f.pinf + pp, T = 1.0 + tp;
-        // reciprocals instead of divides (within an ulp or so)
-        double rTi = rcp_fast<double>(T);
-        double rho = p * f.rR * rTi;
-        double rhop = (pp - f.R * tp) * f.rR * rTi;  // rho - 1
-        double rrho = rcp_fast<double>(rho);
-        double q2 = 0.0;
-        for (int d = 0; d < DIM; ++d)
-            q2 += u[d] * u[d];
-        double a2 = f.gamma * p * rrho;
-        double ur2 = fmin(a2, fmax(q2, f.uc2));
-        double eps = ur2 * rcp_fast<double>(a2);
-        double nuv = f.mu * rrho * fmax(4.0 / 3.0, f.gamma / f.pr);
-        double lam = 0.0;
-        for (int d = 0; d < DIM; ++d) {
-            double rdx = g.rdx[d][(d == 0 ? i : d == 1 ? j : k) + 3];
-            double ud = u[d];
-            double up = 0.5 * (1.0 + eps) * fabs(ud);
-            double cpr = 0.5 * sqrt_fast<double>((1.0 - eps) * (1.0 - eps) * ud * ud + 4.0 * eps * a2);
-            lam += (up + cpr) * rdx + 2.0 * nuv * rdx * rdx;
-        }
-        double rdt = rcp_fast<double>(f.dt);
-        double b0 = A.a, b2 = A.b;
-        double cdt = b0 * rdt, ctau = lam * rcp_fast<double>(f.cfl_tau);
-        double rp = f.rR * rTi, rT = -rho * rTi;
-        double th = rcp_fast<double>(ur2) + rcp_fast<double>(f.cp * T);
-        // perturbation conserved vector of the current state
-        double Qp[N];
-        Qp[0] = rhop;
-        for (int d = 0; d < DIM; ++d)
-            Qp[1 + d] = rhop * u[d] + (u[d] - f.uinf[d]);
-        Qp[N - 1] = pp * f.gm1inv + 0.5 * (rhop * q2 + q2 - f.uinf2);
-        double rhs[N];
-#pragma unroll
-        for (int m = 0; m < N; ++m) {
-            double qn = A.qn[m * g.ncell + cell], qm = A.qnm1[m * g.ncell + cell];
-            rhs[m] = -((b0 * (Qp[m] - qn) - b2 * (qn - qm)) * rdt + R[m]);
-        }
-        // energy row minus H times the mass row: exact row operation that
-        // removes the O(H) terms (H' = c_p T' + (|u|^2 - 1) / 2)
-        double H = f.cp * T + 0.5 * q2;
-        double Hp = f.cp * tp + 0.5 * (q2 - f.uinf2);
-        {
-            double qn0 = A.qn[cell], qm0 = A.qnm1[cell];
-            double qnE = A.qn[(N - 1) * g.ncell + cell], qmE = A.qnm1[(N - 1) * g.ncell + cell];
-            double bdf0 = b0 * (Qp[0] - qn0) - b2 * (qn0 - qm0);
-            double bdfE = b0 * (Qp[N - 1] - qnE) - b2 * (qnE - qmE);
-            double Rrho = R[0], REp = R[N - 1] - f.Hinf * R[0];
-            rhs[N - 1] = -((bdfE - H * bdf0) * rdt + (REp - Hp * Rrho));
-        }
-        double M[N][N];
-        for (int r = 0; r < N; ++r)
-            for (int c = 0; c < N; ++c)
-                M[r][c] = 0.0;
-        double cc = ctau + cdt;
-        M[0][0] = th * ctau + rp * cdt;
-        M[0][N - 1] = rT * cc;
-        for (int d = 0; d < DIM; ++d) {
-            M[1 + d][0] = u[d] * (th * ctau + rp * cdt);
-            M[1 + d][1 + d] = rho * cc;
-            M[1 + d][N - 1] = u[d] * rT * cc;
-            M[N - 1][1 + d] = rho * u[d] * cc;
-        }
-        M[N - 1][0] = -cc;
-        M[N - 1][N - 1] = rho * f.cp * cc;
-        (void)H;
-        // Gaussian elimination with partial pivoting; every index is fixed
-        // at compile time (row swaps by selects), so that the matrix stays
-        // in registers, and each pivot is inverted once
-        double dinv[N];
-#pragma unroll
-        for (int c = 0; c < N; ++c) {
-            int piv = c;
-            double big = fabs(M[c][c]);
-#pragma unroll
-            for (int r = c + 1; r < N; ++r)
-                if (fabs(M[r][c]) > big) {
-                    big = fabs(M[r][c]);
-                    piv = r;
-                }
-#pragma unroll
-            for (int r = c + 1; r < N; ++r) {
-                if (r == piv) {
-#pragma unroll
-                    for (int m = 0; m < N; ++m) {
-                        double t = M[c][m];
-                        M[c][m] = M[r][m];
-                        M[r][m] = t;
-                    }
-                    double t = rhs[c];
-                    rhs[c] = rhs[r];
-                    rhs[r] = t;
-                }
-            }
-            dinv[c] = rcp_fast<double>(M[c][c]);
-#pragma unroll
-            for (int r = c + 1; r < N; ++r) {
-                double fct = M[r][c] * dinv[c];
-#pragma unroll
-                for (int m = c; m < N; ++m)
-                    M[r][m] -= fct * M[c][m];
-                rhs[r] -= fct * rhs[c];
-            }
-        }
-#pragma unroll
-        for (int r = N - 1; r >= 0; --r) {
-            double sum = rhs[r];
-#pragma unroll
-            for (int m = r + 1; m < N; ++m)
-                sum -= M[r][m] * rhs[m];
-            rhs[r] = sum * dinv[r];
-        }
-        bool bad = false;
-        for (int m = 0; m < N; ++m) {
-            double v = qc[m] + rhs[m];
-            A.out[s + m * g.vs] = v;
-            bad |= !isfinite(v);
-        }
-        if (bad)
-            raise_status(A.ib, A.counts, ST_NONFINITE);
     }
 }
+
+// All faces of direction D of the tile, from the staging box of D.
+template <int D>
+__device__ __forceinline__ void face_pass_dir(const double *__restrict__ S, double *__restrict__ F, int i0, int j0,
+                                              int k0, const Grid &g, const FlowR<double> &fp, int tid)
+{
+    using B = DirBox<D>;
+    constexpr int TX = kTile3[0], TY = kTile3[1], TZ = kTile3[2];
+    constexpr int NV = 5, NT = kThreads3;
+    constexpr int FX = TX + (D == 0), FY = TY + (D == 1), FZ = TZ + (D == 2);
+    constexpr int NF = FX * FY * FZ;
+    for (int fi = tid; fi < NF; fi += NT) {
+        int fx = fi % FX, fy = (fi / FX) % FY, fz = fi / (FX * FY);
+        int lc[3] = {fx - (D == 0), fy - (D == 1), fz - (D == 2)};
+        int gc[3] = {i0 + lc[0], j0 + lc[1], k0 + lc[2]};
+        bool need;
+        if (D == 0) need = gc[0] >= -1 && gc[0] < g.ni && gc[1] < g.nj && gc[2] < g.nk;
+        if (D == 1) need = gc[1] >= -1 && gc[1] < g.nj && gc[0] < g.ni && gc[2] < g.nk;
+        if (D == 2) need = gc[2] >= -1 && gc[2] < g.nk && gc[0] < g.ni && gc[1] < g.nj;
+        if (!need)
+            continue;
+        int base = (lc[0] + B::OX) + (lc[1] + B::OY) * B::LX + (lc[2] + B::OZ) * B::LX * B::LY;
+        double flux[NV];
+        face_flux<3, D, double, B::LX, B::LY, B::LCELLS, true>(S, base, gc, g, fp, flux);
+#pragma unroll
+        for (int m = 0; m < NV; ++m)
+            F[m * kDirFaces + fi] = flux[m];
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ void step_body_dir3(const StepArgs &__restrict__ A, int bid)
+{
+    constexpr int TX = kTile3[0], TY = kTile3[1], TZ = kTile3[2], NT = kThreads3;
+    constexpr int NV = 5;
+    __shared__ double S[NV * kDirCells];
+    __shared__ double F[NV * kDirFaces];
+    const Grid &g = A.g;
+    const Flow &f = A.f;
+    const int32_t *list = A.tiles;
+    int nt = list ? A.ntiles : A.ntx * A.nty * A.ntz;
+    int b = bid;
+    int per = (nt + 7) / 8;
+    int pos = (b % 8) * per + b / 8;
+    if (pos >= nt)
+        return;
+    int tile = list ? list[pos] : pos;
+    if (tile < 0)
+        return;
+    int tx0 = tile % A.ntx, ty0 = (tile / A.ntx) % A.nty, tz0 = tile / (A.ntx * A.nty);
+    int i0 = tx0 * TX, j0 = ty0 * TY, k0 = tz0 * TZ;
+    int tid = threadIdx.x;
+    int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
+    int i = i0 + tx, j = j0 + ty, k = k0 + tz;
+    bool own = tid < TX * TY * TZ && i < g.ni && j < g.nj && k < g.nk;
+    long long cell = ((long long)k * g.nj + j) * g.ni + i;
+    long long s_own = sidx(g, i, j, k);
+    uint8_t cls = IBM_SOLID;
+    double qc[NV];
+#pragma unroll
+    for (int m = 0; m < NV; ++m)
+        qc[m] = 0.0;
+    if (own) {
+        cls = A.cls[cell];
+        if (MODE != MODE_RESID) {
+#pragma unroll
+            for (int m = 0; m < NV; ++m)
+                qc[m] = A.qin[s_own + m * g.vs];
+        }
+    }
+    FlowR<double> fp;
+    fp.gamma = f.gamma;
+    fp.gm1inv = f.gm1inv;
+    fp.pinf = f.pinf;
+    fp.mu = f.mu;
+    fp.kc = f.kc;
+    fp.uc2 = f.uc2;
+    fp.uinf2 = f.uinf2;
+    fp.rR = f.rR;
+    fp.precond = f.scheme == IBM_DUAL;
+    fp.tvd = f.recon == IBM_RECON_TVD2;
+    double rd[3] = {0.0, 0.0, 0.0};
+    if (own) {
+        rd[0] = g.rdx[0][i + 3];
+        rd[1] = g.rdx[1][j + 3];
+        rd[2] = g.rdx[2][k + 3];
+    }
+    int fl0 = (tz * TY + ty) * (TX + 1) + tx;  // x-face at i - 1/2
+    int fl1 = (tz * (TY + 1) + ty) * TX + tx;  // y-face at j - 1/2
+    int fl2 = (tz * TY + ty) * TX + tx;        // z-face at k - 1/2
+    double racc[NV];
+#pragma unroll
+    for (int m = 0; m < NV; ++m)
+        racc[m] = 0.0;
+    load_dir<0>(A, S, i0, j0, k0, tid);
+    __syncthreads();
+    face_pass_dir<0>(S, F, i0, j0, k0, g, fp, tid);
+    __syncthreads();
+    if (own) {
+#pragma unroll
+        for (int m = 0; m < NV; ++m)
+            racc[m] = (F[m * kDirFaces + fl0 + 1] - F[m * kDirFaces + fl0]) * rd[0];
+    }
+    load_dir<1>(A, S, i0, j0, k0, tid);
+    __syncthreads();
+    face_pass_dir<1>(S, F, i0, j0, k0, g, fp, tid);
+    __syncthreads();
+    if (own) {
+#pragma unroll
+        for (int m = 0; m < NV; ++m)
+            racc[m] += (F[m * kDirFaces + fl1 + TX] - F[m * kDirFaces + fl1]) * rd[1];
+    }
+    load_dir<2>(A, S, i0, j0, k0, tid);
+    __syncthreads();
+    face_pass_dir<2>(S, F, i0, j0, k0, g, fp, tid);
+    __syncthreads();
+    if (own) {
+#pragma unroll
+        for (int m = 0; m < NV; ++m)
+            racc[m] += (F[m * kDirFaces + fl2 + TX * TY] - F[m * kDirFaces + fl2]) * rd[2];
+    }
+    update_cell<3, double, MODE, false>(A, own, cls, qc, racc, cell, s_own, i, j, k);
+}
+
 
 template <int DIM, typename Real, int MODE>
 __global__ __launch_bounds__(TileCfg<DIM>::NT) void step_kernel(StepArgs A)
@@ -1242,7 +1480,7 @@ struct BatchArgs {
     const StepArgs *args[IBM_BATCH_MAX];
 };
 
-template <int DIM, typename Real, int MODE, bool GHOSTS>
+template <int DIM, typename Real, int MODE, bool GHOSTS, bool DIR = false>
 __device__ __forceinline__ void batch_body(const BatchArgs &B)
 {
     int b = blockIdx.x;
@@ -1265,7 +1503,10 @@ __device__ __forceinline__ void batch_body(const BatchArgs &B)
     using ConstArgs = __attribute__((address_space(4))) const StepArgs;
     const ConstArgs *ap = (const ConstArgs *)(((unsigned long long)phi << 32) | plo);
     int first = __builtin_amdgcn_readfirstlane(B.off[lo]);
-    step_body<DIM, Real, MODE, GHOSTS>(*(const StepArgs *)ap, b - first);
+    if constexpr (DIR)
+        step_body_dir3<MODE>(*(const StepArgs *)ap, b - first);
+    else
+        step_body<DIM, Real, MODE, GHOSTS>(*(const StepArgs *)ap, b - first);
 }
 
 template <int DIM, typename Real, int MODE, bool GHOSTS>
@@ -1293,6 +1534,20 @@ template <int MODE, bool GHOSTS>
 __global__ __launch_bounds__(kThreads3) __attribute__((amdgpu_num_vgpr(128))) void step_batch_kernel_3f(BatchArgs B)
 {
     batch_body<3, float, MODE, GHOSTS>(B);
+}
+
+// 3D FP64 staged one direction at a time (tiles without IB nodes in their
+// stencils): two blocks per CU, 128 registers per lane.
+template <int MODE>
+__global__ __launch_bounds__(kThreads3) __attribute__((amdgpu_num_vgpr(128))) void step_dir_kernel_3d(StepArgs A)
+{
+    step_body_dir3<MODE>(A, blockIdx.x);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads3) __attribute__((amdgpu_num_vgpr(128))) void step_batch_dir_kernel_3d(BatchArgs B)
+{
+    batch_body<3, double, MODE, false, true>(B);
 }
 
 // 2D FP32: the tile fits eight 256-thread blocks per CU in LDS; the
@@ -1326,6 +1581,8 @@ template <int DIM, typename Real, int MODE> constexpr auto plain_kernel()
 {
     if constexpr (DIM == 3 && sizeof(Real) == 4)
         return &step_kernel_3f<MODE>;
+    else if constexpr (DIM == 3)
+        return &step_dir_kernel_3d<MODE>;
     else if constexpr (DIM == 2 && sizeof(Real) == 4 && MODE != MODE_RESID)
         return &step_kernel_2f<MODE>;
     else
@@ -1344,6 +1601,8 @@ template <int DIM, typename Real, int MODE, bool GHOSTS> constexpr auto batch_ke
 {
     if constexpr (DIM == 3 && sizeof(Real) == 4)
         return &step_batch_kernel_3f<MODE, GHOSTS>;
+    else if constexpr (DIM == 3 && !GHOSTS)
+        return &step_batch_dir_kernel_3d<MODE>;
     else if constexpr (DIM == 2 && sizeof(Real) == 4)
         return &step_batch_kernel_2f<MODE, GHOSTS>;
     else
@@ -1558,6 +1817,25 @@ hipError_t run_step(const Grid &g, const Flow &f, const IB &ib, double *qin, con
     if (nblk == 0)
         return hipSuccess;
     hipEvent_t e0 = part ? part->ev_start : nullptr, e1 = part ? part->ev_stop : nullptr;
+    if constexpr (MODE != MODE_RESID && DIM == 3 && sizeof(Real) == 8) {
+        if (part && ib.cap > 0 && part->prefill) {
+            // the IB nodes of the stage input filled in place, then every
+            // tile with the kernel that stages one direction at a time
+            StagePart pa = *part;
+            pa.tiles = nullptr;
+            pa.ntiles = 0;
+            A = make_args<DIM>(g, f, ib, qin, qn, qnm1, out, a, b, &pa, &nblk);
+            hipError_t e = launch_ib_fill(g, f, ib, qin, part->ub, part->ab, part->axis, s, e0);
+            if (e != hipSuccess)
+                return e;
+            if (e1)
+                hipExtLaunchKernelGGL((plain_kernel<DIM, Real, MODE>()), dim3(nblk), dim3(TileCfg<DIM>::NT), 0, s,
+                                      nullptr, e1, 0, A);
+            else
+                hipLaunchKernelGGL((plain_kernel<DIM, Real, MODE>()), dim3(nblk), dim3(TileCfg<DIM>::NT), 0, s, A);
+            return hipGetLastError();
+        }
+    }
     if constexpr (MODE != MODE_RESID) {
         if (part && ib.cap > 0) {
             if (e0)
@@ -1599,29 +1877,39 @@ hipError_t launch_domain_bc(const Grid &g, const Flow &f, double *q, hipStream_t
     return hipGetLastError();
 }
 
+template <int DIM>
+hipError_t ib_fill(const Grid &g, const Flow &f, const IB &ib, double *q, double ub_axis, double ab_axis, int axis,
+                   hipStream_t s, hipEvent_t ev_start)
+{
+    int nbf = blocks_for((long long)ib.cap * (1 << DIM), kBlock);
+    nbf = nbf < 256 ? nbf : 256;
+    if (ev_start)
+        hipExtLaunchKernelGGL(forcing_fill_kernel<DIM>, dim3(nbf), dim3(kBlock), 0, s, ev_start, nullptr, 0, g, f,
+                              ib, q, ub_axis, ab_axis, axis);
+    else
+        hipLaunchKernelGGL(forcing_fill_kernel<DIM>, dim3(nbf), dim3(kBlock), 0, s, g, f, ib, q, ub_axis, ab_axis,
+                           axis);
+    hipLaunchKernelGGL(ghost_fill_kernel<DIM>, dim3(nbf), dim3(kBlock), 0, s, g, f, ib, q, ub_axis, ab_axis, axis);
+    return hipGetLastError();
+}
+
+hipError_t launch_ib_fill(const Grid &g, const Flow &f, const IB &ib, double *q, double ub_axis, double ab_axis,
+                          int axis, hipStream_t s, hipEvent_t ev_start)
+{
+    if (ib.cap <= 0)
+        return hipSuccess;
+    return g.ndim == 2 ? ib_fill<2>(g, f, ib, q, ub_axis, ab_axis, axis, s, ev_start)
+                       : ib_fill<3>(g, f, ib, q, ub_axis, ab_axis, axis, s, ev_start);
+}
+
 // IB nodes (FORCING, then the ghost layers that read them), then the domain
 // ghost layers as images of the filled interior.
 hipError_t launch_bc_fill(const Grid &g, const Flow &f, const IB &ib, double *q, double ub_axis,
                           double ab_axis, int axis, hipStream_t s)
 {
-    if (ib.cap > 0) {
-        int nbf = blocks_for((long long)ib.cap * (1 << g.ndim), kBlock);
-        nbf = nbf < 256 ? nbf : 256;
-        if (g.ndim == 2) {
-            hipLaunchKernelGGL(forcing_fill_kernel<2>, dim3(nbf), dim3(kBlock), 0, s, g, f, ib, q, ub_axis,
-                               ab_axis, axis);
-            hipLaunchKernelGGL(ghost_fill_kernel<2>, dim3(nbf), dim3(kBlock), 0, s, g, f, ib, q, ub_axis,
-                               ab_axis, axis);
-        } else {
-            hipLaunchKernelGGL(forcing_fill_kernel<3>, dim3(nbf), dim3(kBlock), 0, s, g, f, ib, q, ub_axis,
-                               ab_axis, axis);
-            hipLaunchKernelGGL(ghost_fill_kernel<3>, dim3(nbf), dim3(kBlock), 0, s, g, f, ib, q, ub_axis,
-                               ab_axis, axis);
-        }
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess)
-            return e;
-    }
+    hipError_t e = launch_ib_fill(g, f, ib, q, ub_axis, ab_axis, axis, s, nullptr);
+    if (e != hipSuccess)
+        return e;
     return launch_domain_bc(g, f, q, s);
 }
 
@@ -1687,7 +1975,7 @@ hipError_t batch_launch(const BatchArgs &B, bool ghosts, hipStream_t s, hipEvent
 {
     int nblk = B.off[B.n];
     auto k = ghosts ? batch_kernel<DIM, Real, MODE, true>() : batch_kernel<DIM, Real, MODE, false>();
-    if (e0)
+    if (e0 || e1)
         hipExtLaunchKernelGGL(k, dim3(nblk), dim3(TileCfg<DIM>::NT), 0, s, e0, e1, 0, B);
     else
         hipLaunchKernelGGL(k, dim3(nblk), dim3(TileCfg<DIM>::NT), 0, s, B);

@@ -42,7 +42,19 @@ SMALL = {
     "tube-static-sdsn": lambda: w.small_case("tube", 30, steps=2, nz=10, ntheta=48, nzt=5, moving=False,
                                              ib_framework="sdsn"),
     "tube-moving-sdsn": lambda: w.small_case("tube", 32, steps=3, nz=8, ntheta=64, nzt=4, ib_framework="sdsn"),
+    # 3D dual time (FP64: IB nodes filled by the standalone launches, every
+    # tile staged one direction at a time)
+    "tube-static-dual": lambda: _dual3d(False),
+    "tube-moving-dual": lambda: _dual3d(True),
 }
+
+
+def _dual3d(moving):
+    import dataclasses
+    from workloads.cases import dual_dt
+    c = w.small_case("tube", 24, steps=2, nz=8, ntheta=48, nzt=4, moving=moving)
+    return dataclasses.replace(c, mach=0.05, scheme="dual", ib_family="quadratic", n_inner=3,
+                               dt=dual_dt([c.xf, c.yf, c.zf]))
 
 
 def _octahedron_case():
@@ -132,11 +144,12 @@ def test_rk3_steps_fp64(kind):
     assert np.array_equal(s.classes(), o.classes())
 
 
-@pytest.mark.parametrize("kind", ["naca", "naca-sdsn", "naca-m0.01"])
+@pytest.mark.parametrize("kind", ["naca", "naca-sdsn", "naca-m0.01", "tube-static-dual", "tube-moving-dual"])
 def test_dual_time_fp64(kind):
-    """Dual time at M = 0.001 (and 0.01): the FP64 state (p', u, v, T')
-    against the oracle's __float128 build within 1e-12 relative L2, with p'
-    measured against rho_inf U_inf^2 and the velocities against U_inf."""
+    """Dual time at M = 0.001 (and 0.01; the 3D tube at 0.05, stationary
+    and moving): the FP64 state (p', u, v, T') against the oracle's
+    __float128 build within 1e-12 relative L2, with p' measured against
+    rho_inf U_inf^2 and the velocities against U_inf."""
     case, prim, s, o = _classified(kind)
     assert o.precision == "quad"
     n = case.steps
@@ -239,7 +252,7 @@ def test_mixed_precision_error(kind):
     assert errs.max() < MIXED_GATE[kind], errs
 
 
-@pytest.mark.parametrize("kind", ["wedge", "naca", "tube-static", "naca-sdsn", "star-sdsn"])
+@pytest.mark.parametrize("kind", ["wedge", "naca", "tube-static", "naca-sdsn", "star-sdsn", "tube-static-dual"])
 def test_graph_replay_matches_eager(kind):
     """Whole-step HIP graph replay (one-step and multi-step graphs) gives
     bit-identical states to eager launches, replay after replay, with eager
