@@ -75,8 +75,10 @@ BYTES_PER_CELL = {(2, "rk3"): (65 + 97 + 97) / 3.0, (2, "dual"): 129.0, (3, "rk3
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1912_11908_amd", "csrc", "flow.hip")
 COUNTERS = {
-    "C4": os.path.join(ROOT, "profiles", "step_ghost_kernel_3f_tube_384x256x64_hbm_counters.md"),
-    "C2": os.path.join(ROOT, "profiles", "step_batch_kernel_wedge_1024x512_hbm_counters.md"),
+    ("C4", "mixed"): os.path.join(ROOT, "profiles", "step_ghost_kernel_3f_tube_384x256x64_hbm_counters.md"),
+    ("C4", "fp64"): os.path.join(ROOT, "profiles", "step_dir_kernel_3d_tube_384x256x64_hbm_counters.md"),
+    ("C2", "mixed"): os.path.join(ROOT, "profiles", "step_batch_kernel_2f_wedge_1024x512_hbm_counters.md"),
+    ("C2", "fp64"): os.path.join(ROOT, "profiles", "step_batch_kernel_fp64_wedge_1024x512_hbm_counters.md"),
 }
 KERNEL_NAME = {
     (3, "rk3", "mixed"): "step_ghost_kernel_3f<RK3> (stage launch with inline IB fill)",
@@ -89,12 +91,12 @@ KERNEL_NAME = {
 }
 
 
-def measured_traffic(key):
-    """HBM bytes per launch of the stage kernel of workload `key` from the
+def measured_traffic(key, precision):
+    """HBM bytes per stage of workload `key` in `precision` from the
     committed counter summary, or None when there is none or the kernel
     source has changed since the counters were taken (the summary records
     the source's SHA-256)."""
-    path = COUNTERS.get(key)
+    path = COUNTERS.get((key, precision))
     try:
         text = open(path).read()
         sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
@@ -123,10 +125,10 @@ def roofline(case, precision, avg_ms, key=None):
            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4)}
     alu_bound = flops / (fpeak * 1e12) >= nbytes / (HBM_PEAK_GBS * 1e9)
     roof, other = (alu, hbm) if alu_bound else (hbm, alu)
-    roof["traffic"] = measured_traffic(key) if (key and precision == "mixed") else None
+    roof["traffic"] = measured_traffic(key, precision) if key else None
     roof["kernel"] = KERNEL_NAME.get((case.ndim, case.scheme, precision))
     roof["kernel_avg_ms"] = round(avg_ms, 5)
-    roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+    roof["traffic_unit"] = "HBM bytes per stage (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     roof["per_unit"] = {"flops_per_cell_update": flops, "bytes_per_cell_update": round(nbytes, 2),
                         "cells_per_launch": ncell}
     return roof, other
@@ -304,6 +306,17 @@ def other_configs(only=None, exclude=("tube",)):
                                                                               case.ndim, case.p_inf)
         del prims
     return out
+
+
+def calibration_copy():
+    """One plain device copy of 256 MiB (the reference of the HBM byte
+    counters); returns the bytes it moves."""
+    import torch
+    src = torch.ones(32 << 20, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    return 2 * src.numel() * 8
 
 
 def mixed_error(a, b, ndim, p_inf):
@@ -618,7 +631,10 @@ def main():
         print(json.dumps({"supersonic_pair": supersonic_pair(args.supersonic_t)}), flush=True)
         return
     if args.config_only:
-        print(json.dumps({"other_configs": other_configs(args.config_only)}), flush=True)
+        line = {"other_configs": other_configs(args.config_only)}
+        if args.calibration_copy:
+            line["calibration_copy_bytes"] = calibration_copy()
+        print(json.dumps(line), flush=True)
         return
 
     case = w.case_c4(steps=args.steps)
@@ -664,12 +680,7 @@ def main():
         out["appendix_a"] = preprocessing()
         out["frameworks"] = frameworks()
     if args.calibration_copy:
-        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda:0")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        out["calibration_copy_bytes"] = 2 * src.numel() * 8
-        del src, dst
+        out["calibration_copy_bytes"] = calibration_copy()
     if args.serving_requests > 0:
         sv = serving(args.serving_requests, args.serving_rate, "mixed")
         out["latency_p50_s"] = sv["p50_s"]
