@@ -134,6 +134,14 @@ def roofline(case, precision, avg_ms, key=None):
     return roof, other
 
 
+_T0 = time.perf_counter()
+
+
+def log(msg):
+    """Progress of the run on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
 def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -292,6 +300,7 @@ def other_configs(only=None, exclude=("tube",)):
         prims = {}
         for prec in precs:
             s, done, stages = run_case(case, prec, steps, 3)
+            log(f"{tag} [{prec}]: {done['ms_per_step']:.3f} ms per step")
             roof, _ = roofline(case, prec, stages["avg_ms"], tag)
             done["stage_kernel"] = stages
             done["roofline"] = roof
@@ -642,6 +651,7 @@ def main():
     res, prims = {}, {}
     for prec in [p for p in args.precisions.split(",") if p]:
         s, done, stages = run_case(case, prec, args.steps, args.warmup)
+        log(f"oscillating tube [{prec}]: {done['ms_per_step']:.3f} ms per step")
         roof, other = roofline(case, prec, stages["avg_ms"], "C4")
         iso, _ = roofline(case, prec, stages["isolated_avg_ms"], "C4")
         done["stage_kernel"] = stages
@@ -677,24 +687,31 @@ def main():
     if not args.no_other_configs:
         out["other_configs"] = other_configs()
         out["faces"] = face_schemes(200)
+        log("face schemes done")
         out["appendix_a"] = preprocessing()
+        log("appendix A preprocessing done")
         out["frameworks"] = frameworks()
+        log("IB frameworks done")
     if args.calibration_copy:
         out["calibration_copy_bytes"] = calibration_copy()
     if args.serving_requests > 0:
         sv = serving(args.serving_requests, args.serving_rate, "mixed")
+        log(f"serving [mixed]: p50 {sv['p50_s']:.4f} s, p99 {sv['p99_s']:.4f} s")
         out["latency_p50_s"] = sv["p50_s"]
         out["latency_p99_s"] = sv["p99_s"]
         out["serving"] = {"mixed": sv}
         if not args.no_serving_fp64:
             out["serving"]["fp64"] = serving(args.serving_requests, args.serving_rate, "fp64")
+            log("serving [fp64] done")
         if not args.no_saturation:
             sat = serving(args.serving_requests, 1.0e5, "mixed")
+            log("serving at saturation done")
             sat["note"] = "every request arrives within the first 0.03 s: throughput is the server's capacity"
             out["serving"]["saturated_mixed"] = sat
             out["serving_capacity_cell_updates_per_s"] = sat["cell_updates_per_s"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w.case_c4())
+        log("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 

@@ -489,21 +489,21 @@ template <int DIM> __device__ inline bool ghost_source(const Grid &g, int *c)
 // the left state's mirrored and negated), as are two of the three second
 // differences.  Per state, with d1..d4 its first differences and c its
 // central cell:
-//   12 (eps + beta_k) = 12 eps + 13 t_k^2 + 3 u_k^2,
+//   4 (eps + beta_k) = 4 eps + (13/3) t_k^2 + u_k^2,
 //   t = (d2 - d1, d3 - d2, d4 - d3), u = (3 d2 - d1, d2 + d3, d4 - 3 d3);
 // the candidate values are c + r_k / 6 with r = (5 d2 - 2 d1, d2 + 2 d3,
 // 4 d3 - d4), and the state is c + sum_k w_k r_k / 6 with
-// w_k ~ gamma_k / (12 (eps + beta_k))^2, formed with a single reciprocal
-// (the common factor 12 cancels in the normalised weights).
+// w_k ~ gamma_k / (4 (eps + beta_k))^2, formed with a single reciprocal
+// (the common factor 4 cancels in the normalised weights).
 template <typename R>
 __device__ inline R weno5_state(R c, R d1, R d2, R d3, R d4, R t0, R t1, R t2, R k0, R k1, R k2)
 {
-    // k = 13 t (shared with the other state of the face)
-    const R e12 = R(12.0e-6);
+    // k = (13/3) t (shared with the other state of the face)
+    const R e4 = R(4.0e-6);
     R u0 = R(3) * d2 - d1, u1 = d2 + d3, u2 = d4 - R(3) * d3;
-    R s0 = fma(t0, k0, fma(u0, R(3) * u0, e12));
-    R s1 = fma(t1, k1, fma(u1, R(3) * u1, e12));
-    R s2 = fma(t2, k2, fma(u2, R(3) * u2, e12));
+    R s0 = fma(t0, k0, fma(u0, u0, e4));
+    R s1 = fma(t1, k1, fma(u1, u1, e4));
+    R s2 = fma(t2, k2, fma(u2, u2, e4));
     s0 *= s0;
     s1 *= s1;
     s2 *= s2;
@@ -522,7 +522,7 @@ __device__ inline void weno5_pair(R v0, R v1, R v2, R v3, R v4, R v5, R &wl, R &
 {
     R D0 = v1 - v0, D1 = v2 - v1, D2 = v3 - v2, D3 = v4 - v3, D4 = v5 - v4;
     R T1 = D1 - D0, T2 = D2 - D1, T3 = D3 - D2, T4 = D4 - D3;
-    R K1 = R(13) * T1, K2 = R(13) * T2, K3 = R(13) * T3, K4 = R(13) * T4;
+    R K1 = R(13.0 / 3.0) * T1, K2 = R(13.0 / 3.0) * T2, K3 = R(13.0 / 3.0) * T3, K4 = R(13.0 / 3.0) * T4;
     // left: d = (D0, D1, D2, D3), t = (T1, T2, T3)
     wl = weno5_state<R>(v2, D0, D1, D2, D3, T1, T2, T3, K1, K2, K3);
     // right (v5, v4, v3, v2, v1): d = (-D4, -D3, -D2, -D1), t = (T4, T3, T2)
