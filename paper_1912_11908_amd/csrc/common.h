@@ -116,6 +116,21 @@ struct IB {
     int nslot, tg_stride;
 };
 
+// The by-value argument block of a kernel whose only argument it is, read in
+// place through a pointer into the constant kernel-argument segment: the
+// compiler then loads each field where it is used instead of holding the
+// whole block in scalar registers, which it would otherwise spill into
+// vector-register lanes (a VALU instruction per reload).
+template <typename T> __device__ __forceinline__ const T &kernarg_block()
+{
+    unsigned long long pa = reinterpret_cast<unsigned long long>(__builtin_amdgcn_kernarg_segment_ptr());
+    unsigned plo = __builtin_amdgcn_readfirstlane((unsigned)pa);
+    unsigned phi = __builtin_amdgcn_readfirstlane((unsigned)(pa >> 32));
+    using Const = __attribute__((address_space(4))) const T;
+    const Const *ap = (const Const *)(((unsigned long long)phi << 32) | plo);
+    return *(const T *)ap;
+}
+
 // Set sticky status bits (ST_*) in the counts of every classification buffer.
 __device__ inline void raise_status(const IB &ib, int32_t *counts, int bits)
 {

@@ -460,20 +460,6 @@ struct StepArgs {
     FreeStream fs;       // conserved or perturbation free-stream state
 };
 
-// A kernel's by-value StepArgs (its only argument, at the start of the
-// kernel argument segment) read in place through a pointer into that
-// constant segment: the compiler then loads each field where it is used
-// instead of holding the whole block in scalar registers, which it would
-// otherwise spill into vector-register lanes.
-__device__ __forceinline__ const StepArgs &kernel_args()
-{
-    unsigned long long pa = reinterpret_cast<unsigned long long>(__builtin_amdgcn_kernarg_segment_ptr());
-    unsigned plo = __builtin_amdgcn_readfirstlane((unsigned)pa);
-    unsigned phi = __builtin_amdgcn_readfirstlane((unsigned)(pa >> 32));
-    using ConstArgs = __attribute__((address_space(4))) const StepArgs;
-    const ConstArgs *ap = (const ConstArgs *)(((unsigned long long)phi << 32) | plo);
-    return *(const StepArgs *)ap;
-}
 
 // Domain ghost cell -> source cell, by the rules of the ghost-layer fill:
 // EXTRAP copies the nearest interior cell, PERIODIC wraps; a cell outside
@@ -1524,14 +1510,14 @@ template <int DIM, typename Real, int MODE>
 __global__ __launch_bounds__(TileCfg<DIM>::NT) void step_kernel(StepArgs A)
 {
     (void)A;
-    step_body<DIM, Real, MODE, false>(kernel_args(), blockIdx.x);
+    step_body<DIM, Real, MODE, false>(kernarg_block<StepArgs>(), blockIdx.x);
 }
 
 template <int DIM, typename Real, int MODE>
 __global__ __launch_bounds__(TileCfg<DIM>::NT) void step_ghost_kernel(StepArgs A)
 {
     (void)A;
-    step_body<DIM, Real, MODE, true>(kernel_args(), blockIdx.x);
+    step_body<DIM, Real, MODE, true>(kernarg_block<StepArgs>(), blockIdx.x);
 }
 
 
@@ -1585,14 +1571,14 @@ template <int MODE>
 __global__ __launch_bounds__(kThreads3) __attribute__((amdgpu_num_vgpr(128))) void step_kernel_3f(StepArgs A)
 {
     (void)A;
-    step_body<3, float, MODE, false>(kernel_args(), blockIdx.x);
+    step_body<3, float, MODE, false>(kernarg_block<StepArgs>(), blockIdx.x);
 }
 
 template <int MODE>
 __global__ __launch_bounds__(kThreads3) __attribute__((amdgpu_num_vgpr(128))) void step_ghost_kernel_3f(StepArgs A)
 {
     (void)A;
-    step_body<3, float, MODE, true>(kernel_args(), blockIdx.x);
+    step_body<3, float, MODE, true>(kernarg_block<StepArgs>(), blockIdx.x);
 }
 
 template <int MODE, bool GHOSTS>
@@ -1606,7 +1592,7 @@ __global__ __launch_bounds__(kThreads3) __attribute__((amdgpu_num_vgpr(128))) vo
 template <int MODE>
 __global__ __launch_bounds__(kThreads3) __attribute__((amdgpu_num_vgpr(128))) void step_dir_kernel_3d(StepArgs A)
 {
-    // (by value: measured faster for this kernel than kernel_args())
+    // (by value: measured faster for this kernel than kernarg_block())
     step_body_dir3<MODE>(A, blockIdx.x);
 }
 
@@ -1626,7 +1612,7 @@ __global__ __launch_bounds__(kThreads2) __attribute__((amdgpu_waves_per_eu(waves
 step_kernel_2f(StepArgs A)
 {
     (void)A;
-    step_body<2, float, MODE, false>(kernel_args(), blockIdx.x);
+    step_body<2, float, MODE, false>(kernarg_block<StepArgs>(), blockIdx.x);
 }
 
 template <int MODE>
@@ -1634,7 +1620,7 @@ __global__ __launch_bounds__(kThreads2) __attribute__((amdgpu_waves_per_eu(waves
 step_ghost_kernel_2f(StepArgs A)
 {
     (void)A;
-    step_body<2, float, MODE, true>(kernel_args(), blockIdx.x);
+    step_body<2, float, MODE, true>(kernarg_block<StepArgs>(), blockIdx.x);
 }
 
 template <int MODE, bool GHOSTS>

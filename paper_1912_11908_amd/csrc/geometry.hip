@@ -877,14 +877,26 @@ __device__ bool probe_setup(const Grid &g, const uint8_t *cls, const double *y, 
 // meets the surface; one wavefront per node (the facet searches are split
 // across the lanes; lane 0 writes).  probes_kernel: the probes along that
 // line and their stencils, one thread per record.
-__device__ void node_geometry(const Grid &g, const Body &b, const Flow &fl, IB &ib, int r, int nF, int lane,
+__device__ void node_geometry(const Grid &g, const Body &b, const Flow &fl, const IB &ib, int r, int nF, int lane,
                               int *nb, int *st);
+
+struct GeoArgs {
+    Grid g;
+    Body b;
+    Flow fl;
+    IB ib;
+};
 
 // four wavefronts per SIMD (at most 128 VGPRs): the searches are latency
 // bound, and the occupancy outweighs the few spills it costs
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void records_kernel(Grid g, Body b,
-                                                                                               Flow fl, IB ib)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void records_kernel(GeoArgs args)
 {
+    (void)args;
+    const GeoArgs &A = kernarg_block<GeoArgs>();
+    const Grid &g = A.g;
+    const Body &b = A.b;
+    const Flow &fl = A.fl;
+    const IB &ib = A.ib;
     __shared__ int lds[kBlock / kWave][2][kWave];
     int nF = min(ib.counts[CNT_F], ib.cap);
     int nG = min(ib.counts[CNT_G], ib.cap - nF);
@@ -909,7 +921,7 @@ __device__ inline void node_coords(const Grid &g, int c, int &i, int &j, int &k,
         h = fmin(h, g.xf[2][k + 4] - g.xf[2][k + 3]);
 }
 
-__device__ void node_geometry(const Grid &g, const Body &b, const Flow &fl, IB &ib, int r, int nF, int lane,
+__device__ void node_geometry(const Grid &g, const Body &b, const Flow &fl, const IB &ib, int r, int nF, int lane,
                               int *nb, int *st)
 {
     bool forcing = r < nF;
@@ -980,8 +992,13 @@ __device__ void node_geometry(const Grid &g, const Body &b, const Flow &fl, IB &
 // valid corners (flagged).  Fill plan: state offsets instead of cell ids,
 // unused corners aimed at the node itself with zero weight, so that the fill
 // loops are branch-free.
-__global__ __launch_bounds__(kBlock) void probes_kernel(Grid g, Flow fl, IB ib)
+__global__ __launch_bounds__(kBlock) void probes_kernel(GeoArgs args)
 {
+    (void)args;
+    const GeoArgs &A = kernarg_block<GeoArgs>();
+    const Grid &g = A.g;
+    const Flow &fl = A.fl;
+    const IB &ib = A.ib;
     int nF = min(ib.counts[CNT_F], ib.cap);
     int nG = min(ib.counts[CNT_G], ib.cap - nF);
     int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1182,8 +1199,9 @@ hipError_t launch_records(const Grid &g, const Body &b, const Flow &f, IB &ib, h
         return hipSuccess;
     int nb = blocks_for(ib.cap, kBlock / kWave);  // one wavefront per node
     nb = nb < 4096 ? nb : 4096;
-    hipLaunchKernelGGL(records_kernel, dim3(nb), dim3(kBlock), 0, s, g, b, f, ib);
-    hipLaunchKernelGGL(probes_kernel, dim3(blocks_for(ib.cap, kBlock)), dim3(kBlock), 0, s, g, f, ib);
+    GeoArgs a{g, b, f, ib};
+    hipLaunchKernelGGL(records_kernel, dim3(nb), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(probes_kernel, dim3(blocks_for(ib.cap, kBlock)), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
