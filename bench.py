@@ -19,7 +19,9 @@ Unless --no-other-configs: the cylinder (C1), the supersonic wedge (C2) and
 the low-Mach airfoil (C3), each with its throughput, its own stage-kernel
 roofline, its surface forces and (C2, C3) its mixed-vs-FP64 error; the wedge
 with WENO5 and with TVD-2 faces; the appendix A preprocessing of the
-1200-triangle sphere in both IB frameworks; the wedge in both IB frameworks.
+1200-triangle sphere in both IB frameworks; the wedge in both IB frameworks;
+the wedge's oblique shock developed on a 512^2 grid, its angle and plateau
+against the theta-beta-M relation and the Rankine-Hugoniot ratio.
 
 Then the serving workload: the seeded stream of 2000 independent 2D solves
 (grid side 64-512, cylinder / wedge / NACA 00tt, M 0.01-2, Re 40-1000, dual
@@ -37,6 +39,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -156,13 +159,14 @@ def _parse():
     ap.add_argument("--no-other-configs", action="store_true",
                     help="skip the cylinder, wedge and airfoil workloads and the side studies")
     ap.add_argument("--config-only", choices=("cylinder", "wedge", "airfoil", "tube", "supersonic", "shock",
-                                              "preprocessing", "faces", "frameworks"),
+                                              "preprocessing", "faces", "frameworks", "oblique"),
                     help="time only that one workload and print its line (for profiling); "
                          "supersonic: the moving / stationary cylinder pair of section 8.2.3; "
                          "shock: the shock-driven free cylinder of section 8.2.6; "
                          "preprocessing: the sphere-in-a-cube timing of appendix A; "
                          "faces: the wedge with WENO5 and with TVD-2 faces; "
-                         "frameworks: the wedge with ray tracing / local normals and signed distance / surface normals")
+                         "frameworks: the wedge with ray tracing / local normals and signed distance / surface normals; "
+                         "oblique: the wedge's shock angle, developed on a 512^2 grid")
     ap.add_argument("--supersonic-t", type=float, default=10.0,
                     help="convective times t* of the supersonic cylinder pair")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -510,6 +514,83 @@ def frameworks(steps=3000):
     return out
 
 
+def _beta_weak(mach, theta, gamma=1.4):
+    """Weak root of the theta-beta-M relation of an attached oblique shock
+    (bisection between the Mach angle and 64 degrees)."""
+    def f(b):
+        return math.tan(theta) - 2.0 / math.tan(b) * (mach ** 2 * math.sin(b) ** 2 - 1.0) / (
+            mach ** 2 * (gamma + math.cos(2.0 * b)) + 2.0)
+    lo, hi = math.asin(1.0 / mach) + 1e-12, math.radians(64.0)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (lo, mid) if f(lo) * f(mid) <= 0.0 else (mid, hi)
+    return 0.5 * (lo + hi)
+
+
+def oblique_shock(t_end=1.5):
+    """The shock of the C2 wedge shape measured where the flow has reached
+    it: the C2 run itself (2000 steps, t = 0.03) ends long before the shock
+    is steady, so the 15 degree wedge at M = 2, Re = 1e4 is run on [-1, 1]^2
+    at h = 1/256 (512^2 cells) from a uniform stream for t_end convective
+    times.  At 0.2-0.5 from the apex: the shock angle (where the pressure,
+    scanned down from the free stream, first reaches the mean of the free
+    stream and the exact plateau) against the weak root of the
+    theta-beta-M relation, and the plateau pressure ratio (median between
+    30 and 70 % of the way from the wall to the shock) against the
+    Rankine-Hugoniot ratio."""
+    import numpy as np
+    import torch
+    import workloads as w
+    from workloads.cases import Case, rk3_dt
+    import paper_1912_11908_amd as P
+    mach, theta, apex = 2.0, math.radians(15.0), (-0.5, 0.0)
+    beta = _beta_weak(mach, theta)
+    mn = mach * math.sin(beta)
+    p21 = 1.0 + 2.0 * 1.4 / 2.4 * (mn ** 2 - 1.0)
+    f = w.uniform_faces(512, -1.0, 1.0)
+    v, s_ = w.wedge_polygon(15.0, 1.0, apex)
+    bc = ("farfield", "extrap", "extrap", "extrap", "periodic", "periodic")
+    case = Case("oblique-wedge", 2, f, f.copy(), np.array([-0.5, 0.5]), bc, v, s_, mach, 1.0e4,
+                dt=rk3_dt(mach, 1.0e4, [f, f]))
+    steps = int(round(t_end / case.dt))
+    xc = 0.5 * (f[1:] + f[:-1])
+    h = float(xc[1] - xc[0])
+    out = {"workload": f"15 degree wedge, M = 2, Re = 1e4, 512^2 cells on [-1, 1]^2, {steps} RK3 steps "
+                       f"(t = {t_end:g}) from a uniform stream",
+           "beta_exact_deg": math.degrees(beta), "p2_over_p1_exact": p21}
+    for prec in ("mixed", "fp64"):
+        s = P.Solver(case, prec, "cuda:0")
+        s.init_prim(w.freestream_prim(2, case.ni, case.nj, 1, case.p_inf))
+        s.classify()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.advance(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        s.check_status()
+        p = s.to_prim().cpu().numpy()[3, 0] / case.p_inf
+        mid = 0.5 * (p21 + 1.0)
+        st = []
+        for d0 in (0.2, 0.3, 0.4, 0.5):
+            i = int(np.argmin(np.abs(xc - (apex[0] + d0))))
+            d = float(xc[i] - apex[0])
+            col = p[:, i]
+            ywall = apex[1] + math.tan(theta) * d
+            k = min(int(np.searchsorted(xc, apex[1] + 2.0 * math.tan(beta) * d)), case.nj - 2)
+            while k > 0 and col[k] < mid and xc[k] > ywall:
+                k -= 1
+            ysh = xc[k] + (col[k] - mid) / (col[k] - col[k + 1]) * h
+            sel = (xc > ywall + 0.3 * (ysh - ywall)) & (xc < ywall + 0.7 * (ysh - ywall))
+            st.append({"distance_from_apex": round(d, 4),
+                       "beta_deg": math.degrees(math.atan2(ysh - apex[1], d)),
+                       "p2_over_p1": float(np.median(col[sel]))})
+        out[prec] = {"stations": st, "ms_per_step": el * 1e3 / steps,
+                     "max_beta_error_deg": max(abs(e["beta_deg"] - math.degrees(beta)) for e in st),
+                     "max_p21_rel_error": max(abs(e["p2_over_p1"] / p21 - 1.0) for e in st)}
+        del s
+    return out
+
+
 def cpu_baseline_preprocessing(case, reps=3):
     """CPU baseline leg of the appendix A timing: the oracle's classification
     and records of the same case, on this host's cores."""
@@ -624,6 +705,9 @@ def main():
     import torch
     import workloads as w
 
+    if args.config_only == "oblique":
+        print(json.dumps({"oblique_shock": oblique_shock()}), flush=True)
+        return
     if args.config_only == "frameworks":
         print(json.dumps({"frameworks": frameworks()}), flush=True)
         return
@@ -692,6 +776,8 @@ def main():
         log("appendix A preprocessing done")
         out["frameworks"] = frameworks()
         log("IB frameworks done")
+        out["oblique_shock"] = oblique_shock()
+        log("oblique shock done")
     if args.calibration_copy:
         out["calibration_copy_bytes"] = calibration_copy()
     if args.serving_requests > 0:
