@@ -248,22 +248,28 @@ __global__ void tag_kernel(Grid g, IB ib)
                     cls = IBM_FORCING;
             }
     } else {
+        // the offsets of face-graph distance 1, then 2, then 3 (the shells
+        // |a| + |b| + |c| = dist), stopping at the first fluid neighbour
         int best = 4;
-        int rz = nd == 3 ? 3 : 0;
-        for (int c = -rz; c <= rz; ++c)
-            for (int b2 = -3; b2 <= 3; ++b2)
-                for (int a = -3; a <= 3; ++a) {
-                    int dist = abs(a) + abs(b2) + abs(c);
-                    if (dist == 0 || dist > 3 || dist >= best)
-                        continue;
-                    int ii, jj, kk = k;
-                    if (!nb_coord(g, 0, i + a, ii) || !nb_coord(g, 1, j + b2, jj))
-                        continue;
-                    if (nd == 3 && !nb_coord(g, 2, k + c, kk))
-                        continue;
-                    if (!inside_at(ib, ii, jj, kk))
-                        best = dist;
+        const int rz = nd == 3 ? 1 : 0;
+        for (int dist = 1; dist <= 3 && best == 4; ++dist)
+            for (int c = -dist * rz; c <= dist * rz && best == 4; ++c) {
+                int rb = dist - abs(c);
+                for (int b2 = -rb; b2 <= rb && best == 4; ++b2) {
+                    int ra = rb - abs(b2);
+                    for (int a = -ra; a <= ra; a += (ra > 0 ? 2 * ra : 1)) {
+                        int ii, jj, kk = k;
+                        if (!nb_coord(g, 0, i + a, ii) || !nb_coord(g, 1, j + b2, jj))
+                            continue;
+                        if (nd == 3 && !nb_coord(g, 2, k + c, kk))
+                            continue;
+                        if (!inside_at(ib, ii, jj, kk)) {
+                            best = dist;
+                            break;
+                        }
+                    }
                 }
+            }
         cls = best == 1 ? IBM_G1 : best == 2 ? IBM_G2 : best == 3 ? IBM_G3 : IBM_SOLID;
     }
     ib.cls[cell_index(g, i, j, k)] = cls;
