@@ -799,7 +799,8 @@ __device__ inline void face_pass(const Real *__restrict__ S, Real *__restrict__ 
 // their state; residual mode writes R.
 template <int DIM, typename Real, int MODE, bool INLINE_GHOSTS>
 __device__ __forceinline__ void update_cell(const StepArgs &__restrict__ A, bool own, uint8_t cls, const double *qc,
-                                            const Real *racc, long long cell, long long s_own, int i, int j, int k)
+                                            const Real *racc, long long cell, long long s_own, int i, int j, int k,
+                                            const double *qn_pre = nullptr)
 {
     constexpr int NV = DIM + 2;
     const Grid &g = A.g;
@@ -840,7 +841,7 @@ __device__ __forceinline__ void update_cell(const StepArgs &__restrict__ A, bool
         for (int m = 0; m < NV; ++m) {
             double qv = A.b * (qc[m] - f.dt * R[m]);
             if (A.a != 0.0)
-                qv += A.a * A.qn[s + m * g.vs];
+                qv += A.a * (qn_pre ? qn_pre[m] : A.qn[s + m * g.vs]);
             A.out[s + m * g.vs] = qv;
             bad |= !isfinite(qv);
             if (m == 0)
@@ -1205,15 +1206,26 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
     long long s_own = sidx(g, i, j, k);
     uint8_t cls = IBM_SOLID;
     double qc[NV];
+    // RK3 stages 2 and 3 also fetch Q^n here, so that its latency is
+    // covered by the face passes rather than exposed at the update (3D:
+    // stages 2-3 of the C4 tube 0.48 -> 0.45 ms; the 2D FP64 kernel would
+    // lose a wave per SIMD to the registers, and does not)
+    constexpr bool PRE_QN = MODE == MODE_RK3 && (DIM == 3 || sizeof(Real) == 4);
+    double qn_pre[NV];
 #pragma unroll
     for (int m = 0; m < NV; ++m)
-        qc[m] = 0.0;
+        qc[m] = qn_pre[m] = 0.0;
     if (own) {
         cls = A.cls[cell];
         if (MODE != MODE_RESID) {
 #pragma unroll
             for (int m = 0; m < NV; ++m)
                 qc[m] = A.qin[s_own + m * g.vs];
+        }
+        if (PRE_QN && A.a != 0.0) {
+#pragma unroll
+            for (int m = 0; m < NV; ++m)
+                qn_pre[m] = A.qn[s_own + m * g.vs];
         }
     }
     __syncthreads();
@@ -1285,7 +1297,8 @@ __device__ __forceinline__ void step_body(const StepArgs &__restrict__ A, int bi
         }
     }
 
-    update_cell<DIM, Real, MODE, INLINE_GHOSTS>(A, own, cls, qc, racc, cell, s_own, i, j, k);
+    update_cell<DIM, Real, MODE, INLINE_GHOSTS>(A, own, cls, qc, racc, cell, s_own, i, j, k,
+                                                PRE_QN ? qn_pre : nullptr);
 }
 
 // ----------------------------- 3D FP64 stages staged one direction at a time
@@ -1443,12 +1456,21 @@ __device__ __forceinline__ void step_body_dir3(const StepArgs &__restrict__ A, i
 #pragma unroll
     for (int m = 0; m < NV; ++m)
         qc[m] = 0.0;
+    double qn_pre[NV];
+#pragma unroll
+    for (int m = 0; m < NV; ++m)
+        qn_pre[m] = 0.0;
     if (own) {
         cls = A.cls[cell];
         if (MODE != MODE_RESID) {
 #pragma unroll
             for (int m = 0; m < NV; ++m)
                 qc[m] = A.qin[s_own + m * g.vs];
+        }
+        if (MODE == MODE_RK3 && A.a != 0.0) {
+#pragma unroll
+            for (int m = 0; m < NV; ++m)
+                qn_pre[m] = A.qn[s_own + m * g.vs];
         }
     }
     FlowR<double> fp;
@@ -1502,7 +1524,8 @@ __device__ __forceinline__ void step_body_dir3(const StepArgs &__restrict__ A, i
         for (int m = 0; m < NV; ++m)
             racc[m] += (F[m * kDirFaces + fl2 + TX * TY] - F[m * kDirFaces + fl2]) * rd[2];
     }
-    update_cell<3, double, MODE, false>(A, own, cls, qc, racc, cell, s_own, i, j, k);
+    update_cell<3, double, MODE, false>(A, own, cls, qc, racc, cell, s_own, i, j, k,
+                                        MODE == MODE_RK3 ? qn_pre : nullptr);
 }
 
 
