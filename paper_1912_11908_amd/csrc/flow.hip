@@ -477,8 +477,15 @@ template <int DIM> __device__ inline bool ghost_source(const Grid &g, int *c)
             ff = true;
         else if (type == IBM_BC_EXTRAP)
             c[ax] = c[ax] < 0 ? 0 : n[ax] - 1;
-        else
-            c[ax] = ((c[ax] % n[ax]) + n[ax]) % n[ax];
+        else {
+            // periodic: the stencils reach at most three cells beyond the
+            // grid, so a shift by n (repeated for grids narrower than the
+            // halo) wraps without an integer division
+            while (c[ax] < 0)
+                c[ax] += n[ax];
+            while (c[ax] >= n[ax])
+                c[ax] -= n[ax];
+        }
     }
     return ff;
 }
