@@ -202,7 +202,7 @@ struct HostGeom {
     double bin_o[3], bin_h;
     int bin_n[3], nbin;
     std::vector<int32_t> bin_start, bin_facet;
-    std::vector<double> fbox;
+    std::vector<float> fbox;
 };
 
 // Uniform bins over the rest-pose body box for the 3D closest-feature and
@@ -223,7 +223,7 @@ void facet_bins(HostGeom &h, const std::vector<double> &v)
     int nf = (int)(h.facet.size() / 3);
     if (h.nd != 3 || nf == 0)
         return;
-    h.fbox.assign((size_t)6 * nf, 0.0);
+    h.fbox.assign((size_t)6 * nf, 0.0f);
     for (int f = 0; f < nf; ++f)
         for (int d = 0; d < 3; ++d) {
             double fl = 1e300, fh = -1e300;
@@ -231,8 +231,14 @@ void facet_bins(HostGeom &h, const std::vector<double> &v)
                 fl = std::min(fl, v[3 * h.facet[3 * f + m] + d]);
                 fh = std::max(fh, v[3 * h.facet[3 * f + m] + d]);
             }
-            h.fbox[6 * f + d] = fl;
-            h.fbox[6 * f + 3 + d] = fh;
+            // rounded outward: the float box contains the exact one
+            float flf = (float)fl, fhf = (float)fh;
+            if ((double)flf > fl)
+                flf = std::nextafter(flf, -HUGE_VALF);
+            if ((double)fhf < fh)
+                fhf = std::nextafter(fhf, HUGE_VALF);
+            h.fbox[6 * f + d] = flf;
+            h.fbox[6 * f + 3 + d] = fhf;
         }
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (size_t m = 0; m < v.size() / 3; ++m)
@@ -628,7 +634,7 @@ struct Layout {
     double *fcurv, *vcurv;
     int *edge_of;
     int32_t *bin_start, *bin_facet;
-    double *fbox;
+    float *fbox;
     uint8_t *cls, *inside;
     uint32_t *toggle;
     int32_t *counts, *blk, *listF, *listG, *rec_i;
@@ -640,6 +646,7 @@ struct Layout {
     int32_t *fmissed;        // surface force: facets without a valid centre
     double *fforce;          // surface force of a free body's step
     int32_t *rmap;
+    int32_t *hint;
     int32_t *tile_slot, *slot_tile, *tg_cnt, *tg_t, *tg_rec, *tj_cnt, *tj_rec;
     // a second set of the classification's outputs (prescribed motion: the
     // next step is classified while the current one's stages run)
@@ -694,7 +701,7 @@ size_t carve(const ibm_case *c, const HostGeom &h, char *base, Layout &L)
     L.vcurv = cv.take<double>((size_t)std::max(c->nvert, 1));
     L.bin_start = cv.take<int32_t>(h.bin_start.size());
     L.bin_facet = cv.take<int32_t>(std::max<size_t>(h.bin_facet.size(), 1));
-    L.fbox = cv.take<double>(std::max<size_t>(h.fbox.size(), 1));
+    L.fbox = cv.take<float>(std::max<size_t>(h.fbox.size(), 1));
     size_t cap = (size_t)std::max(h.cap, 1);
     int rows = (h.region[3] - h.region[2]) * (h.region[5] - h.region[4]);
     L.cls = cv.take<uint8_t>(h.ncell);
@@ -718,6 +725,7 @@ size_t carve(const ibm_case *c, const HostGeom &h, char *base, Layout &L)
     L.fforce = cv.take<double>(3);
     L.fmissed = cv.take<int32_t>(1);
     L.rmap = cv.take<int32_t>(cap);
+    L.hint = cv.take<int32_t>(cap);
     {
         size_t ntile = h.tiles_far.size() + h.tiles_near.size(), nslot = h.tiles_near.size();
         size_t stride = (size_t)tile_load_cells(nd);
@@ -1080,6 +1088,7 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     ib.plan_kappa = L.plan_kappa;
     ib.fval = L.fval;
     ib.rmap = L.rmap;
+    ib.hint = L.hint;
     ib.tile_slot = L.tile_slot;
     ib.slot_tile = L.slot_tile;
     ib.tg_cnt = L.tg_cnt;
@@ -1131,6 +1140,7 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     if (e == hipSuccess) e = up(L.tiles, list);
     if (e == hipSuccess) e = hipMemset(L.cls, IBM_FLUID, (size_t)h.ncell);
     if (e == hipSuccess) e = hipMemset(L.counts, 0, sizeof(int32_t) * CNT_WORDS);
+    if (e == hipSuccess) e = hipMemset(L.hint, 0xff, sizeof(int32_t) * (size_t)std::max(h.cap, 1));  // no hints yet (-1)
     x->ibb[0] = x->ib;
     if (L.has_out2) {
         const Layout::Out2 &o = L.out2;

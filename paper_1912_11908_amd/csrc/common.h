@@ -52,7 +52,7 @@ struct Body {
     double bin_o[3], bin_h;
     int bin_n[3], nbin;
     const int *bin_start, *bin_facet;
-    const double *fbox;      // per facet: rest-frame bounding box lo[3], hi[3]
+    const float *fbox;       // per facet: rest-frame bounding box lo[3], hi[3], rounded outward
     double disp[3];          // current displacement of the pose (exact)
     // IBM_FRAME_*; for the signed-distance classification the posed lattice
     // box of the vertices (cells outside it are outside the body)
@@ -101,6 +101,11 @@ struct IB {
     double *plan_kappa;      // cap: surface curvature at the node's feature (2D, eq.7)
     double *fval;            // NV * cap: filled values of FORCING corners, by record
     int32_t *rmap;           // cap: record index per region cell (IB nodes only)
+    // cap: per region cell, the closest facet that the last 3D search from
+    // it found.  The next search starts from that facet's distance, which
+    // bounds the minimum from above whatever facet it is, so an entry only
+    // speeds the search up (out-of-range entries are ignored).
+    int32_t *hint;
     // per near tile ("slot", a tile whose stencils reach the region): the
     // IB nodes (FORCING and G1-G3) among the cells it loads, as (tile-local
     // cell, record); rebuilt after every classification

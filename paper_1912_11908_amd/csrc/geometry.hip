@@ -570,15 +570,18 @@ __device__ inline int bin_of(const Body &b, int d, double y) { return (int)floor
 // half-width shell around lo + shell), spread over the whole wavefront:
 // lane l reads the range of the box's bin l of each group of 64, a prefix
 // sum over the lanes numbers the group's entries, and every lane takes
-// every 64th entry, finding its bin by bisection over the sums in LDS.
-// A facet listed in several bins is visited once per listing.
+// every 64th entry, finding its bin in the sums in LDS by walking forward
+// from the bin of its previous entry (the sums grow with the entry).  With
+// PAIR the lane takes two entries 64 apart per round and hands both to
+// visit(fa, fb) (fb = -1 past the end), which can then issue the loads of
+// both at once.  A facet listed in several bins is visited once per listing.
 // With a finite cut2 (the same on every lane), a bin whose box lies farther
 // from the point y than sqrt(cut2) (by more than a margin far above
 // rounding) is skipped: a facet listed there that came closer than that
 // would also be listed in a bin that does not lie that far.
 // Wavefront-uniform control flow; `nb` (the sums) and `st` (the bin
 // starts) are this wavefront's 64-entry LDS slices.
-template <typename Visit>
+template <bool PAIR = false, typename Visit>
 __device__ inline void visit_bins(const Body &b, const int *lo, const int *ext, int shell, int lane, int *nb,
                                   int *st, const double *y, double cut2, Visit &&visit)
 {
@@ -625,24 +628,35 @@ __device__ inline void visit_bins(const Body &b, const int *lo, const int *ext, 
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int t = lane; t < total; t += kWave) {
-            int l0 = 0, l1 = kWave - 1;  // first lane whose sum exceeds t
-            while (l0 < l1) {
-                int mid = (l0 + l1) >> 1;
-                if (nb[mid] > t)
-                    l1 = mid;
-                else
-                    l0 = mid + 1;
+        // l0: the first lane whose sum exceeds the entry (nb[63] = total
+        // bounds every walk)
+        int l0 = 0;
+        if constexpr (PAIR) {
+            for (int t = lane; t < total; t += 2 * kWave) {
+                while (nb[l0] <= t)
+                    ++l0;
+                int fa = b.bin_facet[st[l0] + t], fb = -1;
+                int t2 = t + kWave;
+                if (t2 < total) {
+                    while (nb[l0] <= t2)
+                        ++l0;
+                    fb = b.bin_facet[st[l0] + t2];
+                }
+                visit(fa, fb);
             }
-            visit(b.bin_facet[st[l0] + t]);
+        } else {
+            for (int t = lane; t < total; t += kWave) {
+                while (nb[l0] <= t)
+                    ++l0;
+                visit(b.bin_facet[st[l0] + t]);
+            }
         }
     }
 }
 
-// squared distance from rest-frame point y to facet f's bounding box
-__device__ inline double box_dist2(const Body &b, const double *y, int f)
+// squared distance from rest-frame point y to the box bx = (lo, hi)
+__device__ inline double box_dist2v(const float *bx, const double *y)
 {
-    const double *bx = b.fbox + 6 * f;
     double s = 0.0;
     for (int d = 0; d < 3; ++d) {
         double u = fmax(fmax(bx[d] - y[d], y[d] - bx[3 + d]), 0.0);
@@ -661,7 +675,11 @@ __device__ inline double box_dist2(const Body &b, const double *y, int f)
 // than the lane's minimum so far (by the same margin) cannot win or tie and
 // is skipped.  Called by a whole wavefront for one node: lanes split the
 // facets of each shell, and every shell ends on the wavefront's minimum.
-__device__ Closest closest3d(const Body &b, const double *p, int lane, int *nb, int *st)
+// A valid facet id `hint` (the previous search's answer from the same cell)
+// is measured first: its distance bounds the minimum from above, so the
+// bins and facets farther than it are skipped from the first shell on; the
+// result is the same for any hint.
+__device__ Closest closest3d(const Body &b, const double *p, int lane, int *nb, int *st, int hint)
 {
     Closest best;
     best.d2 = __builtin_inf();
@@ -672,6 +690,8 @@ __device__ Closest closest3d(const Body &b, const double *p, int lane, int *nb, 
             keep(best, facet_closest(b, p, f));
         return wave_min(best);
     }
+    if (hint >= 0 && hint < b.nfacet)
+        keep(best, facet_closest(b, p, hint));
     double y[3];
     int ic[3], far = 0;
     for (int d = 0; d < 3; ++d) {
@@ -683,14 +703,27 @@ __device__ Closest closest3d(const Body &b, const double *p, int lane, int *nb, 
     for (int K = 0; K <= far; ++K) {
         int lo[3] = {ic[0] - K, ic[1] - K, ic[2] - K}, ext[3] = {2 * K + 1, 2 * K + 1, 2 * K + 1};
         double cut2 = best.d2;  // the wavefront's minimum after the inner shells
-        visit_bins(b, lo, ext, K, lane, nb, st, y, cut2, [&](int f) {
-            double bd2 = box_dist2(b, y, f);
-            if (bd2 > best.d2) {
-                double lb = sqrt(bd2) - margin;
-                if (lb > 0.0 && lb * lb > best.d2)
-                    return;
+        visit_bins<true>(b, lo, ext, K, lane, nb, st, y, cut2, [&](int fa, int fb) {
+            // both boxes in flight before either test
+            const float *ba = b.fbox + 6 * fa, *bb = b.fbox + 6 * (fb >= 0 ? fb : fa);
+            float xa[6], xb[6];
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+                xa[m] = ba[m];
+                xb[m] = bb[m];
             }
-            keep(best, facet_closest(b, p, f));
+            auto test = [&](int f, const float *bx) {
+                double bd2 = box_dist2v(bx, y);
+                if (bd2 > best.d2) {
+                    double lb = sqrt(bd2) - margin;
+                    if (lb > 0.0 && lb * lb > best.d2)
+                        return;
+                }
+                keep(best, facet_closest(b, p, f));
+            };
+            test(fa, xa);
+            if (fb >= 0)
+                test(fb, xb);
         });
         best = wave_min(best);
         double r = __builtin_inf();
@@ -936,7 +969,17 @@ __device__ void node_geometry(const Grid &g, const Body &b, const Flow &fl, cons
     int i, j, k;
     double X[3], h;
     node_coords(g, c, i, j, k, X, h);
-    Closest cl = nd == 2 ? closest2d(b, X, lane) : closest3d(b, X, lane, nb, st);
+    // region cell of the node (IB nodes lie in the region)
+    int li = i - ib.region[0], lj = j - ib.region[2], lk = k - ib.region[4];
+    int rc = li >= 0 && li < ib.rw && lj >= 0 && lj < ib.rh && lk >= 0 && lk < ib.rd ? (lk * ib.rh + lj) * ib.rw + li : -1;
+    Closest cl;
+    if (nd == 2) {
+        cl = closest2d(b, X, lane);
+    } else {
+        cl = closest3d(b, X, lane, nb, st, rc >= 0 ? ib.hint[rc] : -1);
+        if (lane == 0 && rc >= 0)
+            ib.hint[rc] = cl.facet;
+    }
     const double *src = cl.kind == FEAT_FACE ? b.fnrm + 3 * cl.id
                         : cl.kind == FEAT_VERTEX ? b.vnrm + 3 * cl.id
                                                  : b.enrm + 3 * cl.id;
@@ -1141,7 +1184,14 @@ __global__ __launch_bounds__(kBlock) void sd_inside_kernel(Grid g, Body b, IB ib
         int in = 0;
         if (inbox) {
             double X[3] = {g.xc[0][c[0] + 3], g.xc[1][c[1] + 3], nd == 3 ? g.xc[2][c[2] + 3] : 0.0};
-            Closest cl = nd == 2 ? closest2d(b, X, lane) : closest3d(b, X, lane, nb, st);
+            Closest cl;
+            if (nd == 2) {
+                cl = closest2d(b, X, lane);
+            } else {
+                cl = closest3d(b, X, lane, nb, st, ib.hint[rc]);
+                if (lane == 0)
+                    ib.hint[rc] = cl.facet;
+            }
             const double *n = b.fnrm + 3 * cl.facet;
             double sd = 0.0;
             for (int d = 0; d < nd; ++d)
