@@ -226,6 +226,104 @@ __device__ inline int inside_at(const IB &ib, int i, int j, int k)
     return ib.inside[((k - ib.region[4]) * ib.rh + (j - ib.region[2])) * ib.rw + (i - ib.region[0])];
 }
 
+// Is any cell at face-graph distance DIST (the offsets with |a|+|b|+|c| =
+// DIST) a fluid cell?  Every periodic axis has at least three cells here,
+// so one shift by n wraps an offset.  The shell's indices are formed first
+// (a cell beyond a non-periodic side, or outside the region, reads region
+// cell 0 and is masked), then all its flags are loaded at once.
+template <int ND, int DIST>
+__device__ inline bool shell_has_fluid(const Grid &g, const IB &ib, int i, int j, int k)
+{
+    constexpr int RZ = ND == 3 ? DIST : 0;
+    constexpr int N = ND == 3 ? 4 * DIST * DIST + 2 : 4 * DIST;
+    const int n3[3] = {g.ni, g.nj, g.nk};
+    const bool per[3] = {g.bc[0] == IBM_BC_PERIODIC, g.bc[2] == IBM_BC_PERIODIC, g.bc[4] == IBM_BC_PERIODIC};
+    const int c0[3] = {i, j, k};
+    int idx[N];
+    unsigned long long valid = 0;
+    int e = 0;
+#pragma unroll
+    for (int c = -RZ; c <= RZ; ++c) {
+        const int rb = DIST - (c < 0 ? -c : c);
+#pragma unroll
+        for (int b2 = -rb; b2 <= rb; ++b2) {
+            const int ra = rb - (b2 < 0 ? -b2 : b2);
+#pragma unroll
+            for (int sgn = 0; sgn < 2; ++sgn) {
+                if (sgn == 1 && ra == 0)
+                    continue;
+                const int off[3] = {sgn == 0 ? -ra : ra, b2, c};
+                bool ok = true;
+                int l[3];
+#pragma unroll
+                for (int d = 0; d < ND; ++d) {
+                    int x = c0[d] + off[d];
+                    bool in = x >= 0 && x < n3[d];
+                    ok = ok && (in || per[d]);
+                    x += x < 0 ? n3[d] : 0;
+                    x -= x >= n3[d] ? n3[d] : 0;
+                    l[d] = x - ib.region[2 * d];
+                }
+                if (ND == 2)
+                    l[2] = k - ib.region[4];
+                bool inreg = (unsigned)l[0] < (unsigned)ib.rw && (unsigned)l[1] < (unsigned)ib.rh &&
+                             (unsigned)l[2] < (unsigned)ib.rd;
+                // valid bit: the cell exists; idx: its region cell, or 0 (a
+                // cell outside the region is fluid: masked below)
+                idx[e] = ok && inreg ? (l[2] * ib.rh + l[1]) * ib.rw + l[0] : -1;
+                valid |= (unsigned long long)ok << e;
+                ++e;
+            }
+        }
+    }
+    uint8_t fl[N];
+#pragma unroll
+    for (int m = 0; m < N; ++m)
+        fl[m] = ib.inside[idx[m] >= 0 ? idx[m] : 0];
+    bool hit = false;
+#pragma unroll
+    for (int m = 0; m < N; ++m)
+        hit = hit | (((valid >> m) & 1ull) != 0 && (idx[m] < 0 || fl[m] == 0));
+    return hit;
+}
+
+template <int ND> __device__ inline int fluid_distance(const Grid &g, const IB &ib, int i, int j, int k)
+{
+    if (shell_has_fluid<ND, 1>(g, ib, i, j, k))
+        return 1;
+    if (shell_has_fluid<ND, 2>(g, ib, i, j, k))
+        return 2;
+    if (shell_has_fluid<ND, 3>(g, ib, i, j, k))
+        return 3;
+    return 4;
+}
+
+// The same distance, one neighbour at a time (any periodic axis length).
+__device__ inline int fluid_distance_any(const Grid &g, const IB &ib, int nd, int i, int j, int k)
+{
+    int best = 4;
+    const int rz = nd == 3 ? 1 : 0;
+    for (int dist = 1; dist <= 3 && best == 4; ++dist)
+        for (int c = -dist * rz; c <= dist * rz && best == 4; ++c) {
+            int rb = dist - abs(c);
+            for (int b2 = -rb; b2 <= rb && best == 4; ++b2) {
+                int ra = rb - abs(b2);
+                for (int a = -ra; a <= ra; a += (ra > 0 ? 2 * ra : 1)) {
+                    int ii, jj, kk = k;
+                    if (!nb_coord(g, 0, i + a, ii) || !nb_coord(g, 1, j + b2, jj))
+                        continue;
+                    if (nd == 3 && !nb_coord(g, 2, k + c, kk))
+                        continue;
+                    if (!inside_at(ib, ii, jj, kk)) {
+                        best = dist;
+                        break;
+                    }
+                }
+            }
+        }
+    return best;
+}
+
 __global__ void tag_kernel(Grid g, IB ib)
 {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -248,28 +346,14 @@ __global__ void tag_kernel(Grid g, IB ib)
                     cls = IBM_FORCING;
             }
     } else {
-        // the offsets of face-graph distance 1, then 2, then 3 (the shells
-        // |a| + |b| + |c| = dist), stopping at the first fluid neighbour
-        int best = 4;
-        const int rz = nd == 3 ? 1 : 0;
-        for (int dist = 1; dist <= 3 && best == 4; ++dist)
-            for (int c = -dist * rz; c <= dist * rz && best == 4; ++c) {
-                int rb = dist - abs(c);
-                for (int b2 = -rb; b2 <= rb && best == 4; ++b2) {
-                    int ra = rb - abs(b2);
-                    for (int a = -ra; a <= ra; a += (ra > 0 ? 2 * ra : 1)) {
-                        int ii, jj, kk = k;
-                        if (!nb_coord(g, 0, i + a, ii) || !nb_coord(g, 1, j + b2, jj))
-                            continue;
-                        if (nd == 3 && !nb_coord(g, 2, k + c, kk))
-                            continue;
-                        if (!inside_at(ib, ii, jj, kk)) {
-                            best = dist;
-                            break;
-                        }
-                    }
-                }
-            }
+        // the shells of face-graph distance 1, then 2, then 3, stopping at
+        // the first that holds a fluid cell
+        bool narrow = false;  // a periodic axis of fewer than three cells
+        for (int d = 0; d < nd; ++d)
+            narrow = narrow || (g.bc[2 * d] == IBM_BC_PERIODIC && (d == 0 ? g.ni : d == 1 ? g.nj : g.nk) < 3);
+        int best = narrow ? fluid_distance_any(g, ib, nd, i, j, k)
+                   : nd == 3 ? fluid_distance<3>(g, ib, i, j, k)
+                             : fluid_distance<2>(g, ib, i, j, k);
         cls = best == 1 ? IBM_G1 : best == 2 ? IBM_G2 : best == 3 ? IBM_G3 : IBM_SOLID;
     }
     ib.cls[cell_index(g, i, j, k)] = cls;
