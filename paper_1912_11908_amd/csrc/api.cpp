@@ -708,7 +708,7 @@ size_t carve(const ibm_case *c, const HostGeom &h, char *base, Layout &L)
     L.inside = cv.take<uint8_t>(cap);
     L.toggle = cv.take<uint32_t>((size_t)std::max(rows * h.wpr, 1));
     L.counts = cv.take<int32_t>(CNT_WORDS);
-    L.blk = cv.take<int32_t>((size_t)2 * std::max(h.nblk, 1));
+    L.blk = cv.take<int32_t>((size_t)5 * std::max(h.nblk, 1));
     L.listF = cv.take<int32_t>(cap);
     L.listG = cv.take<int32_t>(cap);
     L.rec_i = cv.take<int32_t>(cap * kRecI);

@@ -82,7 +82,7 @@ struct IB {
     // the other classification buffer's counts (null with one buffer): the
     // sticky status bits are set in both, so either buffer's word is whole
     int32_t *counts_other;
-    int32_t *blk;            // per-block counts for the compaction scan (2 * nblk)
+    int32_t *blk;            // per-block counts: FORCING, ghosts (scanned), G1, G2, G3 (5 * nblk)
     int nblk;
     int32_t *listF, *listG;
     int32_t *rec_i;          // cap * kRecI

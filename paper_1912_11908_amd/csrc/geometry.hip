@@ -372,75 +372,83 @@ __global__ void zero_counts_kernel(int32_t *counts)
         counts[threadIdx.x] = 0;
 }
 
+// per-block counts of FORCING, ghost (G1-G3), G1, G2 and G3 cells
 __global__ __launch_bounds__(kBlock) void count_kernel(Grid g, IB ib)
 {
-    __shared__ int sF[kBlock / kWave], sG[kBlock / kWave];
+    __shared__ int sc[5][kBlock / kWave];
     int n = ib.rw * ib.rh * ib.rd;
     int t = blockIdx.x * kBlock + threadIdx.x;
     uint8_t c = t < n ? ib.cls[region_cell(g, ib, t)] : (uint8_t)IBM_SOLID;
     bool f = c == IBM_FORCING, gh = c >= IBM_G1 && c <= IBM_G3;
-    unsigned long long bf = __ballot(f), bg = __ballot(gh);
-    unsigned long long b1 = __ballot(c == IBM_G1), b2 = __ballot(c == IBM_G2),
-                       b3 = __ballot(c == IBM_G3);
     int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-    if (lane == 0) {
-        sF[w] = __popcll(bf);
-        sG[w] = __popcll(bg);
-        if (b1) atomicAdd(&ib.counts[CNT_G1], __popcll(b1));
-        if (b2) atomicAdd(&ib.counts[CNT_G2], __popcll(b2));
-        if (b3) atomicAdd(&ib.counts[CNT_G3], __popcll(b3));
-    }
+    int cnt[5] = {(int)__popcll(__ballot(f)), (int)__popcll(__ballot(gh)), (int)__popcll(__ballot(c == IBM_G1)),
+                  (int)__popcll(__ballot(c == IBM_G2)), (int)__popcll(__ballot(c == IBM_G3))};
+    if (lane == 0)
+        for (int l = 0; l < 5; ++l)
+            sc[l][w] = cnt[l];
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int a = 0, b = 0;
-        for (int m = 0; m < kBlock / kWave; ++m) {
-            a += sF[m];
-            b += sG[m];
-        }
-        ib.blk[blockIdx.x] = a;
-        ib.blk[ib.nblk + blockIdx.x] = b;
+    if (threadIdx.x < 5) {
+        int a = 0;
+        for (int m = 0; m < kBlock / kWave; ++m)
+            a += sc[threadIdx.x][m];
+        ib.blk[threadIdx.x * ib.nblk + blockIdx.x] = a;
     }
 }
 
-// single block: exclusive scan of the per-block counts of both lists
+// single block: exclusive scan of the per-block counts of both lists (in
+// place), the list sizes and the G1-G3 totals into the count words.  Thread
+// t sums a run of `per` blocks; the 1024 run sums of a list are scanned
+// across each wavefront (shuffles), then across the 16 wavefront totals.
 __global__ __launch_bounds__(1024) void scan_kernel(IB ib)
 {
-    __shared__ int part[2][1024];
+    constexpr int NW = 1024 / kWave;
+    __shared__ int wsum[5][NW];
     int nb = ib.nblk;
     int per = (nb + 1023) / 1024;
-    int t = threadIdx.x;
-    for (int l = 0; l < 2; ++l) {
-        int *a = ib.blk + l * nb;
+    int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+    int run[2];  // exclusive scan of the run sums within the wavefront
+    for (int l = 0; l < 5; ++l) {
+        const int *a = ib.blk + l * nb;
         int s = 0;
         for (int m = 0; m < per; ++m) {
             int idx = t * per + m;
             if (idx < nb)
                 s += a[idx];
         }
-        part[l][t] = s;
+        int incl = s;
+        for (int o = 1; o < kWave; o <<= 1) {
+            int v = __shfl_up(incl, o, kWave);
+            if (lane >= o)
+                incl += v;
+        }
+        if (l < 2)
+            run[l] = incl - s;
+        if (lane == kWave - 1)
+            wsum[l][w] = incl;
     }
     __syncthreads();
-    if (t < 2) {
-        int run = 0;
-        for (int m = 0; m < 1024; ++m) {
-            int v = part[t][m];
-            part[t][m] = run;
-            run += v;
-        }
-        ib.counts[t == 0 ? CNT_F : CNT_G] = run;
-        if (run > ib.cap)
+    int offs[2] = {0, 0};
+    for (int l = 0; l < 2; ++l)
+        for (int m = 0; m < w; ++m)
+            offs[l] += wsum[l][m];
+    if (t < 5) {
+        int all = 0;
+        for (int m = 0; m < NW; ++m)
+            all += wsum[t][m];
+        const int word[5] = {CNT_F, CNT_G, CNT_G1, CNT_G2, CNT_G3};
+        ib.counts[word[t]] = all;
+        if (t < 2 && all > ib.cap)
             raise_status(ib, ib.counts, ST_CAPACITY);
     }
-    __syncthreads();
     for (int l = 0; l < 2; ++l) {
         int *a = ib.blk + l * nb;
-        int run = part[l][t];
+        int r = offs[l] + run[l];
         for (int m = 0; m < per; ++m) {
             int idx = t * per + m;
             if (idx < nb) {
                 int v = a[idx];
-                a[idx] = run;
-                run += v;
+                a[idx] = r;
+                r += v;
             }
         }
     }
@@ -923,7 +931,32 @@ __device__ inline bool locate(const double *c, int n, bool periodic, double y, i
     return true;
 }
 
-__device__ inline int wrap_idx(int i, int n) { return ((i % n) + n) % n; }
+// i in [-1, n]: the enclosing pair of a probe may straddle a periodic side
+__device__ inline int wrap_idx(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// quotient and remainder of 0 <= x < 2^31 by n > 0 through the FP64
+// reciprocal (a quotient off by at most one), then corrected exactly
+__device__ inline int divmod_rcp(int x, int n, double rn, int &r)
+{
+    int q = (int)((double)x * rn);
+    int rr = x - q * n;
+    if (rr < 0) {
+        --q;
+        rr += n;
+    } else if (rr >= n) {
+        ++q;
+        rr -= n;
+    }
+    r = rr;
+    return q;
+}
+
+// (i, j, k) of cell id c
+__device__ inline void split_cell(const Grid &g, int c, int &i, int &j, int &k)
+{
+    int q = divmod_rcp(c, g.ni, 1.0 / g.ni, i);
+    k = divmod_rcp(q, g.nj, 1.0 / g.nj, j);
+}
 
 // Probe stencil set-up: mode 0 multilinear (all corners valid), mode 1
 // inverse-distance 1/r^2 over the valid corners (a corner at r = 0 takes all
@@ -1033,9 +1066,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 
 __device__ inline void node_coords(const Grid &g, int c, int &i, int &j, int &k, double *X, double &h)
 {
-    i = c % g.ni;
-    j = (c / g.ni) % g.nj;
-    k = c / (g.ni * g.nj);
+    split_cell(g, c, i, j, k);
     X[0] = g.xc[0][i + 3];
     X[1] = g.xc[1][j + 3];
     X[2] = g.ndim == 3 ? g.xc[2][k + 3] : 0.0;
@@ -1224,7 +1255,8 @@ __global__ __launch_bounds__(kBlock) void probes_kernel(GeoArgs args)
         double wt = 0.0;
         int frec = -1;
         if (cc >= 0 && ws != 0.0) {
-            int ci = cc % g.ni, cj = (cc / g.ni) % g.nj, ck = cc / (g.ni * g.nj);
+            int ci, cj, ck;
+            split_cell(g, cc, ci, cj, ck);
             off = (int)(((long long)(ck + g.hz) * g.sy + (cj + 3)) * g.sx + (ci + 3));
             wt = ws;
             // a ghost's weighted FORCING corner: its record, so that a tile
