@@ -121,6 +121,30 @@ struct IB {
     int nslot, tg_stride;
 };
 
+// quotient and remainder of 0 <= x < 2^31 by n > 0 through the FP64
+// reciprocal (a quotient off by at most one), then corrected exactly
+__device__ inline int divmod_rcp(int x, int n, double rn, int &r)
+{
+    int q = (int)((double)x * rn);
+    int rr = x - q * n;
+    if (rr < 0) {
+        --q;
+        rr += n;
+    } else if (rr >= n) {
+        ++q;
+        rr -= n;
+    }
+    r = rr;
+    return q;
+}
+
+// (i, j, k) of cell id c = (k nj + j) ni + i
+__device__ inline void split_cell(const Grid &g, int c, int &i, int &j, int &k)
+{
+    int q = divmod_rcp(c, g.ni, 1.0 / g.ni, i);
+    k = divmod_rcp(q, g.nj, 1.0 / g.nj, j);
+}
+
 // The by-value argument block of a kernel whose only argument it is, read in
 // place through a pointer into the constant kernel-argument segment: the
 // compiler then loads each field where it is used instead of holding the

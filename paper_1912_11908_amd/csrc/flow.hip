@@ -1717,20 +1717,38 @@ __global__ __launch_bounds__(kBlock) void ghost_lists_kernel(Grid g, IB ib, int 
     int slot = blockIdx.x;
     int tile = ib.slot_tile[slot];
     int i0 = (tile % ntx) * TX, j0 = ((tile / ntx) % nty) * TY, k0 = (tile / (ntx * nty)) * TZ;
-    for (int t = threadIdx.x; t < LCELLS; t += kBlock) {
-        int lx = t % LX, ly = (t / LX) % LY, lz = t / (LX * LY);
-        int c[3] = {i0 + lx - 3, j0 + ly - 3, k0 + lz - HZ};
-        if (ghost_source<DIM>(g, c))
-            continue;
-        int li = c[0] - ib.region[0], lj = c[1] - ib.region[2], lk = c[2] - ib.region[4];
-        if (li < 0 || li >= ib.rw || lj < 0 || lj >= ib.rh || lk < 0 || lk >= ib.rd)
-            continue;
-        uint8_t kc = ib.cls[((long long)c[2] * g.nj + c[1]) * g.ni + c[0]];
-        if (kc < IBM_FORCING || kc > IBM_G3)
+    // every round's class loads in flight at once (cells outside the region
+    // or the grid read cell 0 and are skipped)
+    constexpr int NR = (LCELLS + kBlock - 1) / kBlock;
+    int rcs[NR];
+    uint8_t kcs[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        int t = threadIdx.x + r * kBlock;
+        int rc = -1;
+        long long cell = 0;
+        if (t < LCELLS) {
+            int lx = t % LX, ly = (t / LX) % LY, lz = t / (LX * LY);
+            int c[3] = {i0 + lx - 3, j0 + ly - 3, k0 + lz - HZ};
+            if (!ghost_source<DIM>(g, c)) {
+                int li = c[0] - ib.region[0], lj = c[1] - ib.region[2], lk = c[2] - ib.region[4];
+                if (li >= 0 && li < ib.rw && lj >= 0 && lj < ib.rh && lk >= 0 && lk < ib.rd) {
+                    rc = (lk * ib.rh + lj) * ib.rw + li;
+                    cell = ((long long)c[2] * g.nj + c[1]) * g.ni + c[0];
+                }
+            }
+        }
+        rcs[r] = rc;
+        kcs[r] = ib.cls[cell];
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        uint8_t kc = kcs[r];
+        if (rcs[r] < 0 || kc < IBM_FORCING || kc > IBM_G3)
             continue;
         int e = atomicAdd(&n, 1);
-        ib.tg_t[(long long)slot * ib.tg_stride + e] = t;
-        ib.tg_rec[(long long)slot * ib.tg_stride + e] = ib.rmap[(lk * ib.rh + lj) * ib.rw + li];
+        ib.tg_t[(long long)slot * ib.tg_stride + e] = threadIdx.x + r * kBlock;
+        ib.tg_rec[(long long)slot * ib.tg_stride + e] = ib.rmap[rcs[r]];
     }
     __syncthreads();
     int nl = n;
@@ -1754,7 +1772,8 @@ __global__ __launch_bounds__(kBlock) void ghost_lists_kernel(Grid g, IB ib, int 
             if (fr[k] < 0)
                 continue;
             int cc = ib.listF[fr[k]];
-            int ci = cc % g.ni, cj = (cc / g.ni) % g.nj, ck = cc / (g.ni * g.nj);
+            int ci, cj, ck;
+            split_cell(g, cc, ci, cj, ck);
             int lx = ci - i0 + 3, ly = cj - j0 + 3, lz = ck - k0 + HZ;
             if (lx >= 0 && lx < LX && ly >= 0 && ly < LY && lz >= 0 && lz < LZ)
                 continue;

@@ -934,30 +934,6 @@ __device__ inline bool locate(const double *c, int n, bool periodic, double y, i
 // i in [-1, n]: the enclosing pair of a probe may straddle a periodic side
 __device__ inline int wrap_idx(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// quotient and remainder of 0 <= x < 2^31 by n > 0 through the FP64
-// reciprocal (a quotient off by at most one), then corrected exactly
-__device__ inline int divmod_rcp(int x, int n, double rn, int &r)
-{
-    int q = (int)((double)x * rn);
-    int rr = x - q * n;
-    if (rr < 0) {
-        --q;
-        rr += n;
-    } else if (rr >= n) {
-        ++q;
-        rr -= n;
-    }
-    r = rr;
-    return q;
-}
-
-// (i, j, k) of cell id c
-__device__ inline void split_cell(const Grid &g, int c, int &i, int &j, int &k)
-{
-    int q = divmod_rcp(c, g.ni, 1.0 / g.ni, i);
-    k = divmod_rcp(q, g.nj, 1.0 / g.nj, j);
-}
-
 // Probe stencil set-up: mode 0 multilinear (all corners valid), mode 1
 // inverse-distance 1/r^2 over the valid corners (a corner at r = 0 takes all
 // the weight).  Valid corners: FLUID, plus FORCING for ghost nodes.
