@@ -202,7 +202,7 @@ struct HostGeom {
     double bin_o[3], bin_h;
     int bin_n[3], nbin;
     std::vector<int32_t> bin_start, bin_facet;
-    std::vector<float> fbox;
+    std::vector<float> fbox, bin_box;
 };
 
 // Uniform bins over the rest-pose body box for the 3D closest-feature and
@@ -220,6 +220,7 @@ void facet_bins(HostGeom &h, const std::vector<double> &v)
     h.bin_start.assign(1, 0);
     h.bin_facet.clear();
     h.fbox.clear();
+    h.bin_box.clear();
     int nf = (int)(h.facet.size() / 3);
     if (h.nd != 3 || nf == 0)
         return;
@@ -299,6 +300,10 @@ void facet_bins(HostGeom &h, const std::vector<double> &v)
                 for (int kx = a[0]; kx <= b[0]; ++kx)
                     h.bin_facet[fillp[(kz * h.bin_n[1] + ky) * h.bin_n[0] + kx]++] = f;
     }
+    h.bin_box.resize(h.bin_facet.size() * 6);
+    for (size_t m = 0; m < h.bin_facet.size(); ++m)
+        for (int q = 0; q < 6; ++q)
+            h.bin_box[6 * m + q] = h.fbox[6 * (size_t)h.bin_facet[m] + q];
 }
 
 // Does [lo, hi) meet [r0, r1), directly or through a periodic wrap of an
@@ -634,7 +639,7 @@ struct Layout {
     double *fcurv, *vcurv;
     int *edge_of;
     int32_t *bin_start, *bin_facet;
-    float *fbox;
+    float *bin_box;
     uint8_t *cls, *inside;
     uint32_t *toggle;
     int32_t *counts, *blk, *listF, *listG, *rec_i;
@@ -701,7 +706,7 @@ size_t carve(const ibm_case *c, const HostGeom &h, char *base, Layout &L)
     L.vcurv = cv.take<double>((size_t)std::max(c->nvert, 1));
     L.bin_start = cv.take<int32_t>(h.bin_start.size());
     L.bin_facet = cv.take<int32_t>(std::max<size_t>(h.bin_facet.size(), 1));
-    L.fbox = cv.take<float>(std::max<size_t>(h.fbox.size(), 1));
+    L.bin_box = cv.take<float>(std::max<size_t>(h.bin_box.size(), 1));
     size_t cap = (size_t)std::max(h.cap, 1);
     int rows = (h.region[3] - h.region[2]) * (h.region[5] - h.region[4]);
     L.cls = cv.take<uint8_t>(h.ncell);
@@ -992,7 +997,7 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     b.nbin = h.nbin;
     b.bin_start = L.bin_start;
     b.bin_facet = L.bin_facet;
-    b.fbox = L.fbox;
+    b.bin_box = L.bin_box;
     b.frame = c->ib_framework;
     for (int d = 0; d < 3; ++d) {
         long long lo = 0, hi = 0;
@@ -1014,7 +1019,7 @@ int ibm_create(const ibm_case *c, void *d_workspace, size_t bytes, ibm_ctx **out
     }
     if (e == hipSuccess) e = up(L.bin_start, h.bin_start);
     if (e == hipSuccess) e = up(L.bin_facet, h.bin_facet);
-    if (e == hipSuccess && !h.fbox.empty()) e = up(L.fbox, h.fbox);
+    if (e == hipSuccess && !h.bin_box.empty()) e = up(L.bin_box, h.bin_box);
     if (e == hipSuccess) e = up(L.V0, h.V0);
     if (e == hipSuccess) e = up(L.V, h.V0);
     if (e == hipSuccess) e = up(L.v, h.v0);

@@ -52,7 +52,9 @@ struct Body {
     double bin_o[3], bin_h;
     int bin_n[3], nbin;
     const int *bin_start, *bin_facet;
-    const float *fbox;       // per facet: rest-frame bounding box lo[3], hi[3], rounded outward
+    // per bin listing (beside bin_facet): the listed facet's rest-frame
+    // bounding box lo[3], hi[3], rounded outward to float
+    const float *bin_box;
     double disp[3];          // current displacement of the pose (exact)
     // IBM_FRAME_*; for the signed-distance classification the posed lattice
     // box of the vertices (cells outside it are outside the body)

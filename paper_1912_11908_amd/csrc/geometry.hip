@@ -664,9 +664,10 @@ __device__ inline int bin_of(const Body &b, int d, double y) { return (int)floor
 // sum over the lanes numbers the group's entries, and every lane takes
 // every 64th entry, finding its bin in the sums in LDS by walking forward
 // from the bin of its previous entry (the sums grow with the entry).  With
-// PAIR the lane takes two entries 64 apart per round and hands both to
-// visit(fa, fb) (fb = -1 past the end), which can then issue the loads of
-// both at once.  A facet listed in several bins is visited once per listing.
+// PAIR the lane takes two entries 64 apart per round and hands their
+// listing indices to visit(la, lb) (lb = -1 past the end), which can then
+// issue the loads of both at once; otherwise visit(facet).  A facet listed
+// in several bins is visited once per listing.
 // With a finite cut2 (the same on every lane), a bin whose box lies farther
 // from the point y than sqrt(cut2) (by more than a margin far above
 // rounding) is skipped: a facet listed there that came closer than that
@@ -727,14 +728,14 @@ __device__ inline void visit_bins(const Body &b, const int *lo, const int *ext, 
             for (int t = lane; t < total; t += 2 * kWave) {
                 while (nb[l0] <= t)
                     ++l0;
-                int fa = b.bin_facet[st[l0] + t], fb = -1;
+                int la = st[l0] + t, lb = -1;
                 int t2 = t + kWave;
                 if (t2 < total) {
                     while (nb[l0] <= t2)
                         ++l0;
-                    fb = b.bin_facet[st[l0] + t2];
+                    lb = st[l0] + t2;
                 }
-                visit(fa, fb);
+                visit(la, lb);
             }
         } else {
             for (int t = lane; t < total; t += kWave) {
@@ -795,9 +796,12 @@ __device__ Closest closest3d(const Body &b, const double *p, int lane, int *nb, 
     for (int K = 0; K <= far; ++K) {
         int lo[3] = {ic[0] - K, ic[1] - K, ic[2] - K}, ext[3] = {2 * K + 1, 2 * K + 1, 2 * K + 1};
         double cut2 = best.d2;  // the wavefront's minimum after the inner shells
-        visit_bins<true>(b, lo, ext, K, lane, nb, st, y, cut2, [&](int fa, int fb) {
-            // both boxes in flight before either test
-            const float *ba = b.fbox + 6 * fa, *bb = b.fbox + 6 * (fb >= 0 ? fb : fa);
+        visit_bins<true>(b, lo, ext, K, lane, nb, st, y, cut2, [&](int la, int lb) {
+            // both listings' facets and boxes in flight before either test
+            bool two = lb >= 0;
+            lb = two ? lb : la;
+            int fa = b.bin_facet[la], fb = b.bin_facet[lb];
+            const float *ba = b.bin_box + 6 * (long long)la, *bb = b.bin_box + 6 * (long long)lb;
             float xa[6], xb[6];
 #pragma unroll
             for (int m = 0; m < 6; ++m) {
@@ -814,7 +818,7 @@ __device__ Closest closest3d(const Body &b, const double *p, int lane, int *nb, 
                 keep(best, facet_closest(b, p, f));
             };
             test(fa, xa);
-            if (fb >= 0)
+            if (two)
                 test(fb, xb);
         });
         best = wave_min(best);
@@ -954,13 +958,22 @@ __device__ bool probe_setup(const Grid &g, const uint8_t *cls, const double *y, 
     if (nd == 3 && !locate(g.xc[2], g.nk, per[2], y[2], hint[2], i0[2], fr[2]))
         return false;
     int nvalid = 0, zero = -1;
-    for (int m = 0; m < ncorner; ++m) {
+    // the corners' classes, all loads in flight before any test
+    uint8_t tc[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        if (m >= ncorner)
+            break;
         int bx = m & 1, by = (m >> 1) & 1, bz = (m >> 2) & 1;
         int c = cell_index(g, wrap_idx(i0[0] + bx, g.ni), wrap_idx(i0[1] + by, g.nj),
                            nd == 3 ? wrap_idx(i0[2] + bz, g.nk) : 0);
-        uint8_t t = cls[c];
-        bool valid = t == IBM_FLUID || (allow_forcing && t == IBM_FORCING);
         ids[m] = c;
+        tc[m] = cls[c];
+    }
+    for (int m = 0; m < ncorner; ++m) {
+        int bx = m & 1, by = (m >> 1) & 1, bz = (m >> 2) & 1;
+        uint8_t t = tc[m];
+        bool valid = t == IBM_FLUID || (allow_forcing && t == IBM_FORCING);
         if (mode == 0) {
             if (!valid)
                 return false;
