@@ -179,6 +179,29 @@ def test_c1_full_fp64():
     assert errs.max() < TOL64, errs
 
 
+@pytest.mark.parametrize("kind", ["tube-moving", "tube-moving-sdsn", "tube-moving-dual"])
+def test_closest_search_independent_of_history(kind):
+    """The 3D closest-facet search starts from the facet each region cell's
+    previous search found.  Records of a pose must not depend on that
+    history: the first classification (no history) against the same pose
+    classified again after three other poses, bit for bit."""
+    case, prim, s, o = _classified(kind)
+    ir0, dr0 = [np.array(x, copy=True) for x in s.records()]
+    cls0 = np.array(s.classes(), copy=True)
+    t0 = 0.0
+    for t in (0.37, 1.9, 0.05):
+        s.set_time(t)
+        s.classify()
+    s.set_time(t0)
+    s.classify()
+    ir1, dr1 = s.records()
+    record(f"records after other poses [{kind}] (differing entries)", float((ir0 != ir1).sum() + (dr0 != dr1).sum()))
+    assert np.array_equal(cls0, s.classes())
+    assert np.array_equal(ir0, ir1)
+    assert np.array_equal(dr0.view(np.int64), dr1.view(np.int64))
+    s.check_status()
+
+
 def test_deterministic():
     case, prim, s, o = _classified("wedge")
     s.advance(3)
