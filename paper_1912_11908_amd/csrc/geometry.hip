@@ -1236,29 +1236,57 @@ __global__ __launch_bounds__(kBlock) void probes_kernel(GeoArgs args)
         dr[m] = 0.0;
     int cap = ib.cap;
     int node_off = ib.plan_node[r];
-    for (int pm = 0; pm < 16; ++pm) {
-        int p = pm / 8, m = pm % 8;
-        int cc = p ? ids2[m] : ids1[m];
-        double ws = p ? w2[m] : w1[m];
-        int off = node_off;
-        double wt = 0.0;
-        int frec = -1;
-        if (cc >= 0 && ws != 0.0) {
-            int ci, cj, ck;
-            split_cell(g, cc, ci, cj, ck);
-            off = (int)(((long long)(ck + g.hz) * g.sy + (cj + 3)) * g.sx + (ci + 3));
-            wt = ws;
-            // a ghost's weighted FORCING corner: its record, so that a tile
-            // can fill the corner before the ghost
-            if (!forcing && ib.cls[cc] == IBM_FORCING) {
+    // per probe: the eight corners' offsets first, then their classes and
+    // region-map entries, each round of loads in flight at once
+    for (int p = 0; p < (quad ? 2 : 1); ++p) {
+        int off8[8], rmi[8];
+        double wt8[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            int cc = p ? ids2[m] : ids1[m];
+            double ws = p ? w2[m] : w1[m];
+            off8[m] = node_off;
+            wt8[m] = 0.0;
+            rmi[m] = -1;
+            if (cc >= 0 && ws != 0.0) {
+                int ci, cj, ck;
+                split_cell(g, cc, ci, cj, ck);
+                off8[m] = (int)(((long long)(ck + g.hz) * g.sy + (cj + 3)) * g.sx + (ci + 3));
+                wt8[m] = ws;
                 int li = ci - ib.region[0], lj = cj - ib.region[2], lk = ck - ib.region[4];
                 if (li >= 0 && li < ib.rw && lj >= 0 && lj < ib.rh && lk >= 0 && lk < ib.rd)
-                    frec = ib.rmap[(lk * ib.rh + lj) * ib.rw + li];
+                    rmi[m] = (lk * ib.rh + lj) * ib.rw + li;
             }
         }
-        ib.plan_off[pm * cap + r] = off;
-        ib.plan_w[pm * cap + r] = wt;
-        ib.plan_frec[pm * cap + r] = frec;
+        // a ghost's weighted FORCING corner: its record, so that a tile can
+        // fill the corner before the ghost (a FORCING cell lies in the region)
+        uint8_t c8[8];
+        int fr8[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {  // unconditional loads (cell 0 when unused)
+            int cc = p ? ids2[m] : ids1[m];
+            uint8_t v = ib.cls[rmi[m] >= 0 ? cc : 0];
+            c8[m] = !forcing && rmi[m] >= 0 ? v : (uint8_t)IBM_SOLID;
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            int v = ib.rmap[rmi[m] >= 0 ? rmi[m] : 0];
+            fr8[m] = c8[m] == IBM_FORCING ? v : -1;
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            int pm = 8 * p + m;
+            ib.plan_off[pm * cap + r] = off8[m];
+            ib.plan_w[pm * cap + r] = wt8[m];
+            ib.plan_frec[pm * cap + r] = fr8[m];
+        }
+    }
+    if (!quad) {
+        for (int m = 8; m < 16; ++m) {
+            ib.plan_off[m * cap + r] = node_off;
+            ib.plan_w[m * cap + r] = 0.0;
+            ib.plan_frec[m * cap + r] = -1;
+        }
     }
     ib.plan_geo[4 * cap + r] = s1;
     ib.plan_geo[5 * cap + r] = s2;
