@@ -227,8 +227,8 @@ __device__ inline int inside_at(const IB &ib, int i, int j, int k)
 }
 
 // Is any cell at face-graph distance DIST (the offsets with |a|+|b|+|c| =
-// DIST) a fluid cell?  Every periodic axis has at least three cells here,
-// so one shift by n wraps an offset.  The shell's indices are formed first
+// DIST) a fluid cell?  Every axis has at least four cells (checked when a
+// solve is created), so one shift by n wraps an offset of up to three.  The shell's indices are formed first
 // (a cell beyond a non-periodic side, or outside the region, reads region
 // cell 0 and is masked), then all its flags are loaded at once.
 template <int ND, int DIST>
@@ -298,32 +298,6 @@ template <int ND> __device__ inline int fluid_distance(const Grid &g, const IB &
     return 4;
 }
 
-// The same distance, one neighbour at a time (any periodic axis length).
-__device__ inline int fluid_distance_any(const Grid &g, const IB &ib, int nd, int i, int j, int k)
-{
-    int best = 4;
-    const int rz = nd == 3 ? 1 : 0;
-    for (int dist = 1; dist <= 3 && best == 4; ++dist)
-        for (int c = -dist * rz; c <= dist * rz && best == 4; ++c) {
-            int rb = dist - abs(c);
-            for (int b2 = -rb; b2 <= rb && best == 4; ++b2) {
-                int ra = rb - abs(b2);
-                for (int a = -ra; a <= ra; a += (ra > 0 ? 2 * ra : 1)) {
-                    int ii, jj, kk = k;
-                    if (!nb_coord(g, 0, i + a, ii) || !nb_coord(g, 1, j + b2, jj))
-                        continue;
-                    if (nd == 3 && !nb_coord(g, 2, k + c, kk))
-                        continue;
-                    if (!inside_at(ib, ii, jj, kk)) {
-                        best = dist;
-                        break;
-                    }
-                }
-            }
-        }
-    return best;
-}
-
 __global__ void tag_kernel(Grid g, IB ib)
 {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -348,12 +322,7 @@ __global__ void tag_kernel(Grid g, IB ib)
     } else {
         // the shells of face-graph distance 1, then 2, then 3, stopping at
         // the first that holds a fluid cell
-        bool narrow = false;  // a periodic axis of fewer than three cells
-        for (int d = 0; d < nd; ++d)
-            narrow = narrow || (g.bc[2 * d] == IBM_BC_PERIODIC && (d == 0 ? g.ni : d == 1 ? g.nj : g.nk) < 3);
-        int best = narrow ? fluid_distance_any(g, ib, nd, i, j, k)
-                   : nd == 3 ? fluid_distance<3>(g, ib, i, j, k)
-                             : fluid_distance<2>(g, ib, i, j, k);
+        int best = nd == 3 ? fluid_distance<3>(g, ib, i, j, k) : fluid_distance<2>(g, ib, i, j, k);
         cls = best == 1 ? IBM_G1 : best == 2 ? IBM_G2 : best == 3 ? IBM_G3 : IBM_SOLID;
     }
     ib.cls[cell_index(g, i, j, k)] = cls;
