@@ -228,9 +228,10 @@ __device__ inline int inside_at(const IB &ib, int i, int j, int k)
 
 // Is any cell at face-graph distance DIST (the offsets with |a|+|b|+|c| =
 // DIST) a fluid cell?  Every axis has at least four cells (checked when a
-// solve is created), so one shift by n wraps an offset of up to three.  The shell's indices are formed first
-// (a cell beyond a non-periodic side, or outside the region, reads region
-// cell 0 and is masked), then all its flags are loaded at once.
+// solve is created), so one shift by n wraps an offset of up to three.  The
+// shell's indices are formed first (a cell beyond a non-periodic side, or
+// outside the region, reads region cell 0 and is masked), then all its
+// flags are loaded at once.
 template <int ND, int DIST>
 __device__ inline bool shell_has_fluid(const Grid &g, const IB &ib, int i, int j, int k)
 {
