@@ -251,9 +251,15 @@ def test_nonfinite_status_reported():
 # (largest per-primitive relative L2 after the case's steps, p' against
 # rho U^2 at low Mach): cylinder 2.2e-8, wedge 5.9e-8, naca 4.9e-8,
 # tube-moving 1.8e-8, supersonic-moving 6.4e-9, cylinder-tvd 2.0e-8,
-# star-sdsn 2.1e-8, tube-moving-sdsn 1.8e-8, tube-thin-z 1.2e-8.
+# star-sdsn 2.1e-8, tube-moving-sdsn 1.8e-8, tube-thin-z 1.2e-8, tube-static-dual 2.5e-8,
+# tube-moving-dual 2.5e-8, octahedron 1.1e-8, cylinder-quad 2.3e-8, naca-m0.01 7.0e-8,
+# moving-cylinder 3.1e-8, tube-static 1.2e-8, ragged 1.8e-8, supersonic-moving-eq7 6.5e-9,
+# star 2.1e-8.
 MIXED_GATE = {"cylinder": 3e-7, "wedge": 6e-7, "naca": 5e-7, "tube-moving": 2e-7, "supersonic-moving": 7e-8,
-              "cylinder-tvd": 2e-7, "star-sdsn": 3e-7, "tube-moving-sdsn": 2e-7, "tube-thin-z": 2e-7}
+              "cylinder-tvd": 2e-7, "star-sdsn": 3e-7, "tube-moving-sdsn": 2e-7, "tube-thin-z": 2e-7,
+              "tube-static-dual": 3e-7, "tube-moving-dual": 3e-7, "octahedron": 2e-7, "cylinder-quad": 3e-7,
+              "naca-m0.01": 8e-7, "moving-cylinder": 4e-7, "tube-static": 2e-7, "ragged": 2e-7,
+              "supersonic-moving-eq7": 7e-8, "star": 3e-7}
 
 
 @pytest.mark.parametrize("kind", sorted(MIXED_GATE))
