@@ -3,6 +3,8 @@ the same seeded inputs.  Classification, lists and record integers must be
 bit-exact; FP64 flow fields must agree to a relative L2 of 1e-12 per
 variable (low-Mach cases against the oracle's __float128 build, whose own
 rounding is far below that); every test records its achieved error."""
+import math
+
 import numpy as np
 import pytest
 
@@ -203,6 +205,40 @@ def test_closest_search_independent_of_history(kind):
     assert np.array_equal(ir0, ir1)
     assert np.array_equal(dr0.view(np.int64), dr1.view(np.int64))
     s.check_status()
+
+
+@pytest.mark.parametrize("nd", [2, 3])
+def test_box_no_body_fp64(nd):
+    """No body, a periodic box of fluid cells (ragged against the tiles):
+    FP64 fields against the oracle after RK3 steps, and the volume-weighted
+    totals of mass, momentum and energy kept to rounding (section 2's
+    finite volumes: on a periodic grid the face fluxes cancel in the sum)."""
+    case = w.small_case("box", 24, steps=3, ndim=nd, nz=8)
+    prim = w.random_periodic_prim(nd, case.xf, case.yf, case.zf, case.p_inf, seed=1)
+    s, o = make_pair(case, prim)
+    s.classify()
+    o.classify()
+    assert not s.classes().any()  # every cell FLUID
+    dz = np.diff(case.zf) if nd == 3 else np.array([1.0])
+    vol = dz[:, None, None] * np.diff(case.yf)[None, :, None] * np.diff(case.xf)[None, None, :]
+
+    def totals(I):
+        return [math.fsum((I[v] * vol).ravel()) for v in range(nd + 2)]
+
+    t0 = totals(s.interior().cpu().numpy())
+    s.advance(case.steps)
+    s.check_status()
+    got = s.interior().cpu().numpy()
+    q = o.prim_to_state(prim)
+    o.run(q, case.steps)
+    errs = compare_fields(got, o.interior(q))
+    record(f"rk3[box-{nd}d]", errs)
+    assert errs.max() < TOL64, errs
+    t1 = totals(got)
+    drift = [abs(t1[v] - t0[v]) / math.fsum(np.abs(got[v] * vol).ravel()) for v in range(nd + 2)]
+    record(f"conservation drift [box-{nd}d]", drift)
+    assert max(drift) <= 30 * case.steps * np.finfo(float).eps, drift
+    assert not np.allclose(got[0], o.interior(o.prim_to_state(prim))[0])  # the field evolved
 
 
 def test_deterministic():
