@@ -229,6 +229,29 @@ def test_freestream_preserved(nd, bc, scheme, precision):
     assert np.array_equal(s.interior().cpu().numpy(), q0)
 
 
+def test_weno5_order_on_gpu():
+    """WENO5 order through the GPU's FP64 residual, against the mathematics
+    rather than the oracle: rho = 1 + 0.2 sin(2 pi x), u and p constant, a
+    periodic box; the mass residual converges to the exact cell average of
+    d(rho u)/dx at about fifth order."""
+    from test_oracle_flow import _box
+    from paper_1912_11908_amd import Solver
+    errs, ns = [], [32, 64, 128, 256]
+    for n in ns:
+        c = _box(2, n, re=1e15)
+        c.yf = w.uniform_faces(4, 0.0, 4.0 / n)
+        s = Solver(c, "fp64", "cuda:0")
+        s.init_prim(w.entropy_wave_prim(2, c.xf, 4, 1, c.p_inf, amp=0.2, u=1.0))
+        s.classify()
+        r = s.residual().cpu().numpy()
+        xf = c.xf
+        exact = (0.2 * np.sin(2 * np.pi * xf[1:]) - 0.2 * np.sin(2 * np.pi * xf[:-1])) / np.diff(xf)
+        errs.append(np.mean(np.abs(r[0, 0, 1, :] - exact)))
+    slopes = [math.log(errs[k] / errs[k + 1], 2) for k in range(len(errs) - 1)]
+    record("weno5 order of the GPU residual (finest pair)", slopes[-1])
+    assert slopes[-1] > 4.7, (errs, slopes)
+
+
 @pytest.mark.parametrize("nd", [2, 3])
 def test_box_no_body_fp64(nd):
     """No body, a periodic box of fluid cells (ragged against the tiles):
