@@ -51,7 +51,7 @@ if ROOT not in sys.path:
 METRIC = "cell-updates/s (full residual+IBM step) mixed vs FP64; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-# FP32 vector peak without packed FP32 math (which this build leaves off):
+# FP32 vector peak without packed FP32 math (the kernels are compiled without it):
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.  The packed peak,
 # 157.3 TFLOP/s, is twice that.
 FP32_PEAK_TFLOPS = 78.6
@@ -698,7 +698,7 @@ def cpu_baseline(case):
 def main():
     args = _parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
